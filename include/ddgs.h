@@ -1,0 +1,242 @@
+/*
+ * ddgs.h -- C ABI of libddgs.so, the MI355X (gfx950) DRR splatting renderer
+ * of DDGS-CT (arXiv 2406.02518).
+ *
+ * The library renders digitally reconstructed radiographs from two disjoint
+ * sets of 3D Gaussians (isotropic and direction-dependent, Sec. 3.2) through
+ * a cone-beam geometry, and differentiates the images with respect to every
+ * Gaussian parameter, the two shared bases and the 6-DoF source pose of
+ * every view.
+ *
+ *   image (Sec. 3.1, Eq. 1):  C(p) = sum_j c_j s_j prod_{l<j} (1 - s_l),
+ *       s_j = min(sigma_max, alpha_j exp(-d2_j / 2)),
+ *       d2_j = (p - mu^_j)^T A_j (p - mu^_j), A_j = (J Sigma_c J^T + dI)^-1,
+ *       Gaussians with d2_j > kappa^2 are not considered at p, and the
+ *       order is ascending depth (source-frame z of the mean, ties by index);
+ *       both sets are composited together (App. A.2).
+ *   radiosity (Sec. 3.2, Eq. 3):  iso c = sigmoid(b_iso . f),
+ *       dir c = sigmoid(Y_{1..L}(d) . (B_dir f)), d the unit direction from
+ *       the source to the Gaussian mean in the world frame, Y the real
+ *       orthonormal spherical basis of degrees 1..L (k_L = L(L+2)
+ *       functions, order l = 1..L, m = -l..l, no Condon-Shortley phase).
+ *   loss (Sec. 3.1, Eq. 2):  (1 - lambda) mean|I - I*| + lambda (1 - SSIM),
+ *       or 1 - NCC for pose scoring.
+ *
+ * Conventions shared by every entry point:
+ *   - All array pointers in ddgs_model, ddgs_grads, images, targets and
+ *     gradients are DEVICE pointers on the context's device, float32,
+ *     structure-of-arrays, 16-byte aligned, owned by the caller.  The library
+ *     never frees them.  ddgs_view arrays are host memory and are copied.
+ *   - All device work is enqueued on the context's stream (settable, e.g.
+ *     torch's current stream).  Entry points do not synchronise the stream
+ *     except where stated (ddgs_render reads the number of tile entries back;
+ *     ddgs_check and the debug getters synchronise).
+ *   - Every function returns a ddgs_status; on failure nothing is written to
+ *     the outputs that the status code does not mention, and the message is
+ *     kept in ddgs_last_error(ctx).  No C++ exception crosses the ABI.
+ *   - The library allocates its internal workspace with hipMalloc, grows it
+ *     on demand (outside a captured step) and frees it in ddgs_destroy.
+ *   - A context is not thread-safe; use one per host thread.
+ */
+#ifndef DDGS_H
+#define DDGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DDGS_OK = 0,
+    DDGS_ERR_INVALID_ARG = 1, /* bad pointer, size, alignment or option        */
+    DDGS_ERR_OOM = 2,         /* hipMalloc failed                              */
+    DDGS_ERR_HIP = 3,         /* a HIP runtime call failed (message kept)      */
+    DDGS_ERR_CAPACITY = 4,    /* tile entries exceeded the captured capacity   */
+    DDGS_ERR_NONFINITE = 5,   /* non-finite value met in an input              */
+    DDGS_ERR_STATE = 6,       /* call out of order (e.g. backward before render)*/
+    DDGS_ERR_UNSUPPORTED = 7  /* valid request this build does not implement   */
+} ddgs_status;
+
+typedef struct ddgs_ctx ddgs_ctx;
+
+/* Gaussian model, device SoA arrays (borrowed until the next ddgs_set_model
+ * or ddgs_destroy; the caller may change their contents between calls).
+ * Gaussians [0, n_iso) are isotropic, [n_iso, n) direction-dependent.
+ * Activations: Sigma = R(q/|q|) diag(exp(2 log_scale)) R^T,
+ * alpha = sigmoid(opacity_logit). */
+typedef struct {
+    int64_t n, n_iso;            /* 0 <= n_iso <= n < 2^31 / n_views          */
+    int32_t k;                   /* feature size, 1..32                       */
+    int32_t L;                   /* directional degree, 1..3                  */
+    const float *mean;           /* [3][n] world mm                           */
+    const float *quat;           /* [4][n] (w, x, y, z), non-zero             */
+    const float *log_scale;      /* [3][n]                                    */
+    const float *opacity_logit;  /* [n]                                       */
+    const float *feat;           /* [k][n]                                    */
+    const float *b_iso;          /* [k]                                       */
+    const float *B_dir;          /* [L(L+2)][k] row-major                     */
+} ddgs_model;
+
+/* One cone-beam view.  pose = [R | t] row-major 3x4, world -> source frame:
+ * +z along the principal ray towards the detector, +x along detector
+ * columns, +y along detector rows; R must be a rotation.  Focal length
+ * f = sdd_mm / pitch_mm pixels, principal point (W/2, H/2), pixel (u, v)
+ * has centre (u + 0.5, v + 0.5).  Images of all views are concatenated
+ * view-major, each H rows of W floats. */
+typedef struct {
+    int32_t W, H;                /* 1..16384                                  */
+    float pitch_mm, sdd_mm;      /* > 0                                       */
+    float pose[12];
+} ddgs_view;
+
+/* Options; ddgs_default_options fills the defaults shown. */
+typedef struct {
+    int32_t tile_w, tile_h;      /* 16, 16; supported: 8x8, 16x8, 16x16, 32x8 */
+    float kappa;                 /* 3: Mahalanobis cut-off radius             */
+    float dilation;              /* 0.3: added to the projected covariance    */
+    float t_min;                 /* 0: early stop when T(1-s) < t_min (off)  */
+    float z_near;                /* 1 mm: depth at or below which a Gaussian is culled */
+    float sigma_max;             /* 0.99: clamp of s                          */
+    int32_t persistent;          /* 0: one workgroup per tile; 1: persistent
+                                    workgroups over a longest-first queue     */
+    int64_t capacity;            /* tile-entry capacity of a captured step;
+                                    0 = chosen by ddgs_step_capture          */
+} ddgs_options;
+
+/* Gradient outputs, device arrays with the shapes of the inputs; every
+ * non-NULL array is OVERWRITTEN (not accumulated).  NULL skips the group;
+ * if only dpose is non-NULL the per-Gaussian chain is skipped. */
+typedef struct {
+    float *dmean;            /* [3][n] */
+    float *dquat;            /* [4][n] */
+    float *dlog_scale;       /* [3][n] */
+    float *dopacity_logit;   /* [n]    */
+    float *dfeat;            /* [k][n] */
+    float *db_iso;           /* [k]    */
+    float *dB_dir;           /* [L(L+2)][k] */
+    float *dpose;            /* [n_views][6]: (rho, omega), the left tangent
+                                delta of pose' = Exp(delta) pose at delta = 0,
+                                i.e. R' = Exp(omega) R, t' = Exp(omega) t + rho;
+                                mm and rad                                   */
+} ddgs_grads;
+
+enum { DDGS_LOSS_L1_DSSIM = 0, DDGS_LOSS_NCC = 1, DDGS_LOSS_LINEAR = 2 };
+
+/* ---------------------------------------------------------------- context */
+ddgs_status ddgs_create(ddgs_ctx **out, int device, void *hip_stream);
+void ddgs_destroy(ddgs_ctx *ctx);
+ddgs_status ddgs_set_stream(ddgs_ctx *ctx, void *hip_stream);
+const char *ddgs_status_str(ddgs_status s);
+const char *ddgs_last_error(const ddgs_ctx *ctx);
+void ddgs_default_options(ddgs_options *opt);
+ddgs_status ddgs_set_options(ddgs_ctx *ctx, const ddgs_options *opt);
+ddgs_status ddgs_get_options(const ddgs_ctx *ctx, ddgs_options *opt);
+
+/* Eq. 1/3 inputs. */
+ddgs_status ddgs_set_model(ddgs_ctx *ctx, const ddgs_model *model);
+ddgs_status ddgs_set_views(ddgs_ctx *ctx, const ddgs_view *views, int n_views);
+/* Number of floats of the concatenated images of the current views. */
+ddgs_status ddgs_image_size(const ddgs_ctx *ctx, int64_t *n_floats);
+
+/* ---------------------------------------------------------------- compute */
+
+/* Renders every view (Eq. 1 with Eq. 3) into images (device,
+ * ddgs_image_size floats).  Reads the number of tile entries back to size
+ * the sort (one stream synchronisation).  Keeps what the backward needs
+ * (the sorted tile lists, per-pixel final value and last contributor). */
+ddgs_status ddgs_render(ddgs_ctx *ctx, float *images);
+
+/* Gradient of L = sum_p dL_dimages[p] I(p) with respect to the model and the
+ * view poses; the transmittance is recomputed from the saved tile lists.
+ * Requires a preceding ddgs_render with the same model, views and options
+ * (DDGS_ERR_STATE otherwise). */
+ddgs_status ddgs_backward(ddgs_ctx *ctx, const float *dL_dimages, const ddgs_grads *grads);
+
+/* Eq. 2 losses of the current images against target (same layout):
+ *   DDGS_LOSS_L1_DSSIM: per view (1-lambda) mean|I-I*| + lambda (1 - SSIM),
+ *     SSIM with an 11x11 Gaussian window of std 1.5, K1 = 0.01, K2 = 0.03,
+ *     dynamic range 1, zero padding;
+ *   DDGS_LOSS_NCC: per view 1 - NCC over all pixels (population statistics,
+ *     1e-12 added to each variance);
+ *   DDGS_LOSS_LINEAR: sum_p target[p] I(p) (target holds the weights).
+ * loss_out: device [n_views] floats (may be NULL); dL_dimages: device, image
+ * layout, overwritten with the gradient (may be NULL). */
+ddgs_status ddgs_loss(ddgs_ctx *ctx, int kind, const float *images, const float *target,
+                      float lambda, float *loss_out, float *dL_dimages);
+
+/* ------------------------------------------------------- batched step */
+
+/* Records render -> loss -> backward of all views as one HIP graph with a
+ * fixed tile-entry capacity (options.capacity, or twice the current need)
+ * and no host synchronisation inside.  The pointers passed here are baked
+ * into the graph and must stay valid.  ddgs_step_launch replays it;
+ * ddgs_check synchronises and reports DDGS_ERR_CAPACITY if the last replay
+ * overflowed (outputs of that replay are then invalid; capture again with a
+ * larger capacity).  The model and views may change contents between
+ * replays but not shapes (n, views' W/H); ddgs_set_model / ddgs_set_views
+ * with a different shape drop the graph. */
+ddgs_status ddgs_step_capture(ddgs_ctx *ctx, int loss_kind, const float *target, float lambda,
+                              float *images, float *dL_dimages, float *loss_out,
+                              const ddgs_grads *grads);
+ddgs_status ddgs_step_launch(ddgs_ctx *ctx);
+ddgs_status ddgs_check(ddgs_ctx *ctx, uint32_t *flags);
+
+/* Times forward + backward for each supported tile shape and scheduling mode
+ * on the current model and views (the images are identical across
+ * candidates), selects the fastest into the options and, if cache_path is
+ * not NULL, reads/writes a JSON cache keyed by the workload signature.
+ * best_ms (may be NULL) receives the chosen candidate's median time. */
+ddgs_status ddgs_autotune(ddgs_ctx *ctx, const char *cache_path, int repeats, float *best_ms);
+
+/* ------------------------------------------------------------- inspection */
+
+/* Per-Gaussian float count (position 3, rotation 4, scale 3, opacity 1,
+ * features k) and shared float count (k + k_L k); Sec. 4.2 counts 19 and 32
+ * at k = 8, L = 1. */
+ddgs_status ddgs_param_count(int k, int L, int64_t n, int64_t *per_gaussian, int64_t *shared);
+
+/* Number of (tile, Gaussian) entries of the last render. */
+ddgs_status ddgs_num_rendered(const ddgs_ctx *ctx, int64_t *n);
+
+enum {
+    DDGS_DBG_RECORDS = 0,     /* [n_views*n][8] f32: mu^x, mu^y, A00, A01, A11, alpha, c, 0 */
+    DDGS_DBG_DEPTH_KEYS = 1,  /* [n_views*n] u32: float bits of z, 0xFFFFFFFF if culled */
+    DDGS_DBG_COUNTS = 2,      /* [n_views*n] u32: tiles touched                  */
+    DDGS_DBG_RECTS = 3,       /* [n_views*n][4] u16: tile x0, y0, x1, y1 (incl.)   */
+    DDGS_DBG_TILE_KEYS_UNSORTED = 4, /* [M] u32 global tile id, emission order  */
+    DDGS_DBG_TILE_VALS_UNSORTED = 5, /* [M] u32 Gaussian index, emission order  */
+    DDGS_DBG_TILE_KEYS = 6,   /* [M] u32 sorted                                  */
+    DDGS_DBG_TILE_VALS = 7,   /* [M] u32 sorted                                  */
+    DDGS_DBG_RANGES = 8,      /* [n_tiles][2] u32 [start, end)                   */
+    DDGS_DBG_NLAST = 9,       /* [pixels] u32: end of the contributing prefix    */
+    DDGS_DBG_TILE_BASE = 10   /* [n_views+1] i32: first global tile id per view  */
+};
+/* Copies an internal array of the last render to host memory (synchronises).
+ * The *_UNSORTED arrays are kept only when options are set with
+ * ddgs_debug_keep_unsorted(ctx, 1) before the render. */
+ddgs_status ddgs_debug_copy(ddgs_ctx *ctx, int what, void *host, size_t bytes);
+ddgs_status ddgs_debug_keep_unsorted(ddgs_ctx *ctx, int keep);
+
+/* Stable LSD radix sort of n (key, value) u32 pairs in place on the device,
+ * by key bits [0, bits) (bits 1..32).  Exposes the sort that orders the
+ * tile lists. */
+ddgs_status ddgs_debug_sort_pairs(ddgs_ctx *ctx, uint32_t *keys, uint32_t *vals, int64_t n, int bits);
+
+/* Exclusive prefix sum of n u32 values on the device; *total receives the
+ * 64-bit sum (host).  Exposes the scan that places the tile entries. */
+ddgs_status ddgs_debug_exclusive_scan(ddgs_ctx *ctx, const uint32_t *in, uint32_t *out, int64_t n,
+                                      uint64_t *total);
+
+/* Accumulated device time of the last render/backward/step per stage, ms
+ * (filled when timing is enabled with ddgs_enable_timing). */
+enum { DDGS_T_PROJECT = 0, DDGS_T_SORT = 1, DDGS_T_RASTER_FWD = 2, DDGS_T_LOSS = 3,
+       DDGS_T_RASTER_BWD = 4, DDGS_T_PROJECT_BWD = 5, DDGS_T_COUNT = 6 };
+ddgs_status ddgs_enable_timing(ddgs_ctx *ctx, int enable);
+ddgs_status ddgs_stage_times(const ddgs_ctx *ctx, float *ms /* [DDGS_T_COUNT] */);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,71 @@
+"""``torch.autograd.Function`` around the HIP render / backward of libddgs.so.
+
+``DDGSRender.apply(renderer, views, mean, quat, log_scale, opacity_logit, feat,
+b_iso, B_dir, pose_tangent, n_iso, L)`` returns the concatenated images of all
+views (view-major, each H x W).  Gradients flow to every Gaussian tensor, the
+two shared bases and ``pose_tangent`` (V x 6, (rho, omega) in mm and rad).
+The pose actually rendered is Exp(delta) pose (R' = Exp(omega) R,
+t' = Exp(omega) t + rho), composed on the host in float64; the returned pose
+gradient is the left-tangent derivative at that composed pose, which equals
+the derivative with respect to delta at delta = 0.  Pose optimisers therefore
+re-base the pose after each step and keep delta at zero.
+"""
+import numpy as np
+import torch
+from scipy.spatial.transform import Rotation
+
+from . import binding
+from .synth import View
+
+
+def compose_views(views, pose_tangent):
+    if pose_tangent is None:
+        return list(views)
+    d = pose_tangent.detach().to("cpu", torch.float64).numpy().reshape(-1, 6)
+    out = []
+    for v, dv in zip(views, d):
+        if not np.any(dv):
+            out.append(v)
+            continue
+        P = np.asarray(v.pose, dtype=np.float64)
+        E = Rotation.from_rotvec(dv[3:]).as_matrix()
+        pose = np.concatenate([E @ P[:, :3], (E @ P[:, 3] + dv[:3])[:, None]], axis=1)
+        out.append(View(W=v.W, H=v.H, pitch=v.pitch, sdd=v.sdd, pose=pose.astype(np.float32),
+                        sid=v.sid, azimuth_deg=v.azimuth_deg))
+    return out
+
+
+class DDGSRender(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, renderer, views, mean, quat, log_scale, opacity_logit, feat, b_iso, B_dir, pose_tangent,
+                n_iso, L):
+        params = dict(mean=mean.detach(), quat=quat.detach(), log_scale=log_scale.detach(),
+                      opacity_logit=opacity_logit.detach(), feat=feat.detach(), b_iso=b_iso.detach(),
+                      B_dir=B_dir.detach())
+        renderer.set_model(params, n_iso, L)
+        renderer.set_views(compose_views(views, pose_tangent))
+        img = renderer.render()
+        ctx.renderer = renderer
+        ctx.has_pose = pose_tangent is not None
+        return img
+
+    @staticmethod
+    def backward(ctx, dimg):
+        r = ctx.renderer
+        need = ctx.needs_input_grad
+        names = ("dmean", "dquat", "dlog_scale", "dopacity_logit", "dfeat", "db_iso", "dB_dir", "dpose")
+        which = [nm for nm, flag in zip(names, need[2:10]) if flag]
+        grads = r.backward(dimg.contiguous(), which=which) if which else {}
+        out = [grads.get(nm) for nm in names]
+        if not ctx.has_pose:
+            out[-1] = None
+        return (None, None, *out, None, None)
+
+
+def render(renderer, views, params, n_iso, L, pose_tangent=None):
+    """Differentiable render of ``views`` (list of synth.View) from ``params``
+    (dict of tensors named mean, quat, log_scale, opacity_logit, feat, b_iso,
+    B_dir)."""
+    return DDGSRender.apply(renderer, views, params["mean"], params["quat"], params["log_scale"],
+                            params["opacity_logit"], params["feat"], params["b_iso"], params["B_dir"],
+                            pose_tangent, n_iso, L)

@@ -1,0 +1,383 @@
+"""ctypes binding of libddgs.so (include/ddgs.h).
+
+The ``ddgs_*`` functions below carry the C names and only marshal arguments:
+every step of the render / backward / loss path runs in the HIP kernels of the
+library.  ``Renderer`` is a small convenience layer that takes torch tensors
+(device memory and streams come from torch) and keeps them alive while the
+library borrows their pointers.  There is no CPU fallback: if the library has
+not been built, ``lib()`` raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libddgs.so")
+
+OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_CAPACITY, ERR_NONFINITE, ERR_STATE, ERR_UNSUPPORTED = range(8)
+LOSS_L1_DSSIM, LOSS_NCC, LOSS_LINEAR = 0, 1, 2
+(DBG_RECORDS, DBG_DEPTH_KEYS, DBG_COUNTS, DBG_RECTS, DBG_TILE_KEYS_UNSORTED, DBG_TILE_VALS_UNSORTED,
+ DBG_TILE_KEYS, DBG_TILE_VALS, DBG_RANGES, DBG_NLAST, DBG_TILE_BASE) = range(11)
+T_PROJECT, T_SORT, T_RASTER_FWD, T_LOSS, T_RASTER_BWD, T_PROJECT_BWD, T_COUNT = range(7)
+STAGES = ("project", "sort", "raster_fwd", "loss", "raster_bwd", "project_bwd")
+
+EXPORTED = (
+    "ddgs_create", "ddgs_destroy", "ddgs_set_stream", "ddgs_status_str", "ddgs_last_error",
+    "ddgs_default_options", "ddgs_set_options", "ddgs_get_options", "ddgs_set_model", "ddgs_set_views",
+    "ddgs_image_size", "ddgs_render", "ddgs_backward", "ddgs_loss", "ddgs_step_capture", "ddgs_step_launch",
+    "ddgs_check", "ddgs_autotune", "ddgs_param_count", "ddgs_num_rendered", "ddgs_debug_copy",
+    "ddgs_debug_keep_unsorted", "ddgs_debug_sort_pairs", "ddgs_debug_exclusive_scan", "ddgs_enable_timing",
+    "ddgs_stage_times")
+
+
+class ddgs_model(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_iso", C.c_int64), ("k", C.c_int32), ("L", C.c_int32),
+                ("mean", C.c_void_p), ("quat", C.c_void_p), ("log_scale", C.c_void_p),
+                ("opacity_logit", C.c_void_p), ("feat", C.c_void_p), ("b_iso", C.c_void_p),
+                ("B_dir", C.c_void_p)]
+
+
+class ddgs_view(C.Structure):
+    _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("pitch_mm", C.c_float), ("sdd_mm", C.c_float),
+                ("pose", C.c_float * 12)]
+
+
+class ddgs_options(C.Structure):
+    _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("kappa", C.c_float), ("dilation", C.c_float),
+                ("t_min", C.c_float), ("z_near", C.c_float), ("sigma_max", C.c_float),
+                ("persistent", C.c_int32), ("capacity", C.c_int64)]
+
+
+class ddgs_grads(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("dmean", "dquat", "dlog_scale", "dopacity_logit", "dfeat", "db_iso",
+                                          "dB_dir", "dpose")]
+
+
+class DDGSError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{status_name(status)}: {message}")
+        self.status = status
+
+
+_LIB = None
+
+
+def lib():
+    """Loads libddgs.so; raises if it has not been built (no fallback)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2406_02518_amd/build.py "
+                               "(the DRR renderer has no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, st = C.c_void_p, C.c_int32, C.c_int64, C.c_int
+        sig = {
+            "ddgs_create": ([C.POINTER(vp), C.c_int, vp], st),
+            "ddgs_destroy": ([vp], None),
+            "ddgs_set_stream": ([vp, vp], st),
+            "ddgs_status_str": ([st], C.c_char_p),
+            "ddgs_last_error": ([vp], C.c_char_p),
+            "ddgs_default_options": ([C.POINTER(ddgs_options)], None),
+            "ddgs_set_options": ([vp, C.POINTER(ddgs_options)], st),
+            "ddgs_get_options": ([vp, C.POINTER(ddgs_options)], st),
+            "ddgs_set_model": ([vp, C.POINTER(ddgs_model)], st),
+            "ddgs_set_views": ([vp, C.POINTER(ddgs_view), C.c_int], st),
+            "ddgs_image_size": ([vp, C.POINTER(i64)], st),
+            "ddgs_render": ([vp, vp], st),
+            "ddgs_backward": ([vp, vp, C.POINTER(ddgs_grads)], st),
+            "ddgs_loss": ([vp, C.c_int, vp, vp, C.c_float, vp, vp], st),
+            "ddgs_step_capture": ([vp, C.c_int, vp, C.c_float, vp, vp, vp, C.POINTER(ddgs_grads)], st),
+            "ddgs_step_launch": ([vp], st),
+            "ddgs_check": ([vp, C.POINTER(C.c_uint32)], st),
+            "ddgs_autotune": ([vp, C.c_char_p, C.c_int, C.POINTER(C.c_float)], st),
+            "ddgs_param_count": ([C.c_int, C.c_int, i64, C.POINTER(i64), C.POINTER(i64)], st),
+            "ddgs_num_rendered": ([vp, C.POINTER(i64)], st),
+            "ddgs_debug_copy": ([vp, C.c_int, vp, C.c_size_t], st),
+            "ddgs_debug_keep_unsorted": ([vp, C.c_int], st),
+            "ddgs_debug_sort_pairs": ([vp, vp, vp, i64, C.c_int], st),
+            "ddgs_debug_exclusive_scan": ([vp, vp, vp, i64, C.POINTER(C.c_uint64)], st),
+            "ddgs_enable_timing": ([vp, C.c_int], st),
+            "ddgs_stage_times": ([vp, C.POINTER(C.c_float)], st),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _LIB = L
+    return _LIB
+
+
+def status_name(s):
+    try:
+        return lib().ddgs_status_str(int(s)).decode()
+    except Exception:  # noqa: BLE001 - message formatting must not fail
+        return f"status {s}"
+
+
+def _check(status, ctx=None):
+    if status != OK:
+        msg = lib().ddgs_last_error(ctx).decode() if ctx else ""
+        raise DDGSError(status, msg)
+
+
+# ------------------------------------------------------------ C-name wrappers
+
+def ddgs_create(device=0, stream=0):
+    h = C.c_void_p()
+    _check(lib().ddgs_create(C.byref(h), int(device), C.c_void_p(stream or 0)))
+    return h
+
+
+def ddgs_destroy(ctx):
+    lib().ddgs_destroy(ctx)
+
+
+def ddgs_set_stream(ctx, stream):
+    _check(lib().ddgs_set_stream(ctx, C.c_void_p(stream or 0)), ctx)
+
+
+def ddgs_default_options():
+    o = ddgs_options()
+    lib().ddgs_default_options(C.byref(o))
+    return o
+
+
+def ddgs_set_options(ctx, opts):
+    _check(lib().ddgs_set_options(ctx, C.byref(opts)), ctx)
+
+
+def ddgs_get_options(ctx):
+    o = ddgs_options()
+    _check(lib().ddgs_get_options(ctx, C.byref(o)), ctx)
+    return o
+
+
+def ddgs_set_model(ctx, model):
+    _check(lib().ddgs_set_model(ctx, C.byref(model)), ctx)
+
+
+def ddgs_set_views(ctx, views_arr, n):
+    _check(lib().ddgs_set_views(ctx, views_arr, int(n)), ctx)
+
+
+def ddgs_image_size(ctx):
+    n = C.c_int64()
+    _check(lib().ddgs_image_size(ctx, C.byref(n)), ctx)
+    return n.value
+
+
+def ddgs_render(ctx, images_ptr):
+    _check(lib().ddgs_render(ctx, C.c_void_p(images_ptr)), ctx)
+
+
+def ddgs_backward(ctx, dl_ptr, grads):
+    _check(lib().ddgs_backward(ctx, C.c_void_p(dl_ptr), C.byref(grads)), ctx)
+
+
+def ddgs_loss(ctx, kind, images_ptr, target_ptr, lam, loss_ptr, dl_ptr):
+    _check(lib().ddgs_loss(ctx, int(kind), C.c_void_p(images_ptr), C.c_void_p(target_ptr), float(lam),
+                           C.c_void_p(loss_ptr or 0), C.c_void_p(dl_ptr or 0)), ctx)
+
+
+def ddgs_step_capture(ctx, kind, target_ptr, lam, images_ptr, dl_ptr, loss_ptr, grads):
+    _check(lib().ddgs_step_capture(ctx, int(kind), C.c_void_p(target_ptr), float(lam), C.c_void_p(images_ptr),
+                                   C.c_void_p(dl_ptr), C.c_void_p(loss_ptr or 0), C.byref(grads)), ctx)
+
+
+def ddgs_step_launch(ctx):
+    _check(lib().ddgs_step_launch(ctx), ctx)
+
+
+def ddgs_check(ctx, raise_on_error=True):
+    fl = C.c_uint32()
+    st = lib().ddgs_check(ctx, C.byref(fl))
+    if raise_on_error:
+        _check(st, ctx)
+    return st, fl.value
+
+
+def ddgs_autotune(ctx, cache_path=None, repeats=5):
+    ms = C.c_float()
+    p = cache_path.encode() if cache_path else None
+    _check(lib().ddgs_autotune(ctx, p, int(repeats), C.byref(ms)), ctx)
+    return ms.value
+
+
+def ddgs_param_count(k, L, n):
+    per, sh = C.c_int64(), C.c_int64()
+    _check(lib().ddgs_param_count(int(k), int(L), int(n), C.byref(per), C.byref(sh)))
+    return per.value, sh.value
+
+
+def ddgs_num_rendered(ctx):
+    n = C.c_int64()
+    _check(lib().ddgs_num_rendered(ctx, C.byref(n)), ctx)
+    return n.value
+
+
+def ddgs_debug_keep_unsorted(ctx, keep):
+    _check(lib().ddgs_debug_keep_unsorted(ctx, int(bool(keep))), ctx)
+
+
+def ddgs_debug_copy(ctx, what, dtype, count):
+    out = np.zeros(int(count), dtype=dtype)
+    _check(lib().ddgs_debug_copy(ctx, int(what), out.ctypes.data_as(C.c_void_p), out.nbytes), ctx)
+    return out
+
+
+def ddgs_debug_sort_pairs(ctx, keys_ptr, vals_ptr, n, bits):
+    _check(lib().ddgs_debug_sort_pairs(ctx, C.c_void_p(keys_ptr), C.c_void_p(vals_ptr), int(n), int(bits)), ctx)
+
+
+def ddgs_debug_exclusive_scan(ctx, in_ptr, out_ptr, n):
+    t = C.c_uint64()
+    _check(lib().ddgs_debug_exclusive_scan(ctx, C.c_void_p(in_ptr), C.c_void_p(out_ptr), int(n), C.byref(t)), ctx)
+    return t.value
+
+
+def ddgs_enable_timing(ctx, enable):
+    _check(lib().ddgs_enable_timing(ctx, int(bool(enable))), ctx)
+
+
+def ddgs_stage_times(ctx):
+    ms = (C.c_float * T_COUNT)()
+    _check(lib().ddgs_stage_times(ctx, ms), ctx)
+    return dict(zip(STAGES, list(ms)))
+
+
+# --------------------------------------------------------- torch-facing layer
+
+def _views_struct(views):
+    arr = (ddgs_view * max(1, len(views)))()
+    for i, v in enumerate(views):
+        arr[i].W, arr[i].H = int(v.W), int(v.H)
+        arr[i].pitch_mm, arr[i].sdd_mm = float(v.pitch), float(v.sdd)
+        pose = np.asarray(v.pose, dtype=np.float32).reshape(12)
+        for j in range(12):
+            arr[i].pose[j] = float(pose[j])
+    return arr
+
+
+PARAM_NAMES = ("mean", "quat", "log_scale", "opacity_logit", "feat", "b_iso", "B_dir")
+GRAD_NAMES = ("dmean", "dquat", "dlog_scale", "dopacity_logit", "dfeat", "db_iso", "dB_dir", "dpose")
+
+
+class Renderer:
+    """Owns a ddgs context bound to a torch CUDA(HIP) device and stream."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = ddgs_create(device, self.stream.cuda_stream)
+        self._keep = {}
+        self.views = []
+        self.n = 0
+        self.k = 0
+        self.L = 1
+
+    def close(self):
+        if self.ctx is not None:
+            ddgs_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    # inputs
+    def set_options(self, **kw):
+        o = ddgs_get_options(self.ctx)
+        for k, v in kw.items():
+            setattr(o, k, v)
+        ddgs_set_options(self.ctx, o)
+
+    def options(self):
+        o = ddgs_get_options(self.ctx)
+        return {f: getattr(o, f) for f, _ in o._fields_}
+
+    def set_model(self, params, n_iso, L):
+        """params: dict of float32 contiguous device tensors named as PARAM_NAMES."""
+        t = {}
+        for name in PARAM_NAMES:
+            x = params[name]
+            if x.dtype != self.torch.float32 or x.device != self.device:
+                raise ValueError(f"{name} must be a float32 tensor on {self.device}")
+            t[name] = x.contiguous()
+        m = ddgs_model()
+        m.n = int(t["mean"].shape[1])
+        m.n_iso = int(n_iso)
+        m.k = int(t["feat"].shape[0])
+        m.L = int(L)
+        for name in PARAM_NAMES:
+            setattr(m, name, t[name].data_ptr())
+        ddgs_set_model(self.ctx, m)
+        self._keep["model"] = t
+        self.n, self.k, self.L = m.n, m.k, m.L
+
+    def set_scene(self, scene):
+        p = {name: self.torch.from_numpy(np.ascontiguousarray(getattr(scene, name))).to(self.device)
+             for name in PARAM_NAMES}
+        self.set_model(p, scene.n_iso, scene.L)
+        return p
+
+    def set_views(self, views):
+        self.views = list(views)
+        ddgs_set_views(self.ctx, _views_struct(self.views), len(self.views))
+
+    def image_size(self):
+        return ddgs_image_size(self.ctx)
+
+    def split(self, flat):
+        out, base = [], 0
+        for v in self.views:
+            P = int(v.W) * int(v.H)
+            out.append(flat[base:base + P].view(int(v.H), int(v.W)))
+            base += P
+        return out
+
+    # compute
+    def render(self, out=None):
+        if out is None:
+            out = self.torch.empty(self.image_size(), device=self.device, dtype=self.torch.float32)
+        ddgs_render(self.ctx, out.data_ptr())
+        return out
+
+    def alloc_grads(self, which=GRAD_NAMES):
+        m = self._keep["model"]
+        shapes = dict(dmean=m["mean"].shape, dquat=m["quat"].shape, dlog_scale=m["log_scale"].shape,
+                      dopacity_logit=m["opacity_logit"].shape, dfeat=m["feat"].shape, db_iso=m["b_iso"].shape,
+                      dB_dir=m["B_dir"].shape, dpose=(len(self.views), 6))
+        return {k: self.torch.empty(shapes[k], device=self.device, dtype=self.torch.float32) for k in which}
+
+    @staticmethod
+    def grads_struct(grads):
+        g = ddgs_grads()
+        for name in GRAD_NAMES:
+            x = grads.get(name)
+            setattr(g, name, x.data_ptr() if x is not None else None)
+        return g
+
+    def backward(self, dl, grads=None, which=GRAD_NAMES):
+        if grads is None:
+            grads = self.alloc_grads(which)
+        dl = dl.contiguous()
+        ddgs_backward(self.ctx, dl.data_ptr(), self.grads_struct(grads))
+        return grads
+
+    def loss(self, kind, images, target, lam=0.2, want_grad=True):
+        loss = self.torch.empty(len(self.views), device=self.device, dtype=self.torch.float32)
+        dl = self.torch.empty_like(images) if want_grad else None
+        ddgs_loss(self.ctx, kind, images.data_ptr(), target.data_ptr(), lam, loss.data_ptr(),
+                  dl.data_ptr() if dl is not None else 0)
+        return loss, dl
+
+    def num_rendered(self):
+        return ddgs_num_rendered(self.ctx)
+
+    def debug(self, what, dtype, count):
+        return ddgs_debug_copy(self.ctx, what, dtype, count)

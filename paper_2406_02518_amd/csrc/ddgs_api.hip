@@ -1,0 +1,1180 @@
+// ddgs_api.hip -- host runtime behind the C ABI of include/ddgs.h: context
+// and error state, workspace planning, the plain single-call render and
+// backward, the losses, the captured batched step (one HIP graph per shape,
+// fixed tile-entry capacity with an overflow flag), the autotuner and the
+// debug getters.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/ddgs.h"
+#include "internal.h"
+
+using namespace ddgs;
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Status {
+    ddgs_status code;
+};
+
+}  // namespace
+
+struct ddgs_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cu = 256;
+    std::string err;
+
+    ddgs_options opt{};
+    bool has_model = false;
+    ddgs_model model{};
+    std::vector<ddgs_view> views_h;
+
+    // derived view table for the current options
+    std::vector<ViewDev> vdev_h;
+    std::vector<int32_t> loss_tile_base_h;
+    int n_tiles = 0, loss_tiles = 0;
+    int64_t total_pix = 0, max_view_pix = 0;
+    bool views_dirty = true;
+
+    // workspace
+    std::map<std::string, DevBuf> bufs;
+
+    // state of the last render
+    bool rendered = false;
+    uint64_t model_gen = 0, views_gen = 0, opt_gen = 0;
+    uint64_t r_model_gen = ~0ull, r_views_gen = ~0ull, r_opt_gen = ~0ull;
+    int64_t M = 0;             // entries of the last render
+    uint32_t *tkey_sorted = nullptr, *tval_sorted = nullptr;
+    uint32_t *queue = nullptr;
+    int64_t entry_cap = 0;     // capacity of the entry buffers
+    bool keep_unsorted = false;
+
+    // captured step
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    int64_t step_cap = 0;
+
+    // timing: a start and an end event per stage
+    bool timing = false;
+    hipEvent_t ev_s[DDGS_T_COUNT] = {};
+    hipEvent_t ev_e[DDGS_T_COUNT] = {};
+    bool ev_valid[DDGS_T_COUNT] = {};
+};
+
+namespace {
+
+ddgs_status fail(ddgs_ctx *c, ddgs_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                                       \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail((ctx), e_ == hipErrorOutOfMemory ? DDGS_ERR_OOM : DDGS_ERR_HIP,          \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                       \
+    } while (0)
+
+#define DDGS_TRY(expr)                  \
+    do {                                \
+        ddgs_status s_ = (expr);        \
+        if (s_ != DDGS_OK) return s_;   \
+    } while (0)
+
+ddgs_status ensure(ddgs_ctx *c, const char *name, size_t bytes, void **out)
+{
+    DevBuf &b = c->bufs[name];
+    if (bytes == 0) bytes = 16;
+    if (b.bytes < bytes) {
+        if (b.p) {
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            HIP_TRY(c, hipFree(b.p));
+            b.p = nullptr;
+            b.bytes = 0;
+        }
+        const size_t nb = bytes + bytes / 4 + 256;
+        hipError_t e = hipMalloc(&b.p, nb);
+        if (e != hipSuccess) {
+            b.p = nullptr;
+            return fail(c, DDGS_ERR_OOM, std::string("hipMalloc of ") + name + " (" + std::to_string(nb) +
+                                             " bytes) failed: " + hipGetErrorString(e));
+        }
+        b.bytes = nb;
+    }
+    *out = b.p;
+    return DDGS_OK;
+}
+
+template <typename T>
+ddgs_status ensure_t(ddgs_ctx *c, const char *name, size_t count, T **out)
+{
+    void *p = nullptr;
+    DDGS_TRY(ensure(c, name, count * sizeof(T), &p));
+    *out = (T *)p;
+    return DDGS_OK;
+}
+
+template <typename T>
+T *buf(ddgs_ctx *c, const char *name)
+{
+    auto it = c->bufs.find(name);
+    return it == c->bufs.end() ? nullptr : (T *)it->second.p;
+}
+
+int kl_of(int L) { return L * (L + 2); }
+
+RenderOpts render_opts(const ddgs_options &o)
+{
+    RenderOpts r;
+    r.kappa = o.kappa;
+    r.kappa2 = o.kappa * o.kappa;
+    r.dilation = o.dilation;
+    r.t_min = o.t_min;
+    r.z_near = o.z_near;
+    r.sigma_max = o.sigma_max;
+    r.tile_w = o.tile_w;
+    r.tile_h = o.tile_h;
+    return r;
+}
+
+ModelDev model_dev(const ddgs_model &m)
+{
+    ModelDev d;
+    d.n = (int32_t)m.n;
+    d.n_iso = (int32_t)m.n_iso;
+    d.k = m.k;
+    d.L = m.L;
+    d.mean = m.mean;
+    d.quat = m.quat;
+    d.log_scale = m.log_scale;
+    d.opacity_logit = m.opacity_logit;
+    d.feat = m.feat;
+    d.b_iso = m.b_iso;
+    d.B_dir = m.B_dir;
+    return d;
+}
+
+int bits_for(int64_t n)
+{
+    int b = 1;
+    while (b < 32 && ((int64_t)1 << b) < n) ++b;
+    return b;
+}
+
+// Builds the device view table (tile grid depends on the tile size).
+ddgs_status prepare_views(ddgs_ctx *c)
+{
+    if (!c->views_dirty) return DDGS_OK;
+    const int V = (int)c->views_h.size();
+    c->vdev_h.assign(V, ViewDev{});
+    c->loss_tile_base_h.assign(V + 1, 0);
+    int64_t tiles = 0, pix = 0, ltiles = 0, maxp = 0;
+    for (int v = 0; v < V; ++v) {
+        const ddgs_view &h = c->views_h[v];
+        ViewDev &d = c->vdev_h[v];
+        for (int r = 0; r < 3; ++r) {
+            for (int q = 0; q < 3; ++q) d.R[3 * r + q] = h.pose[4 * r + q];
+            d.t[r] = h.pose[4 * r + 3];
+        }
+        for (int q = 0; q < 3; ++q) {
+            const double s = -((double)h.pose[q] * h.pose[3] + (double)h.pose[4 + q] * h.pose[7] +
+                               (double)h.pose[8 + q] * h.pose[11]);
+            d.so[q] = (float)s;
+        }
+        d.f = (float)((double)h.sdd_mm / (double)h.pitch_mm);
+        d.cx = 0.5f * (float)h.W;
+        d.cy = 0.5f * (float)h.H;
+        d.W = h.W;
+        d.H = h.H;
+        d.ntx = (h.W + c->opt.tile_w - 1) / c->opt.tile_w;
+        d.nty = (h.H + c->opt.tile_h - 1) / c->opt.tile_h;
+        d.tile_base = (int32_t)tiles;
+        d.pix_base = pix;
+        tiles += (int64_t)d.ntx * d.nty;
+        pix += (int64_t)h.W * h.H;
+        maxp = std::max<int64_t>(maxp, (int64_t)h.W * h.H);
+        c->loss_tile_base_h[v] = (int32_t)ltiles;
+        ltiles += (int64_t)((h.W + 15) / 16) * ((h.H + 15) / 16);
+    }
+    c->loss_tile_base_h[V] = (int32_t)ltiles;
+    if (tiles >= (int64_t)1 << 30 || ltiles >= (int64_t)1 << 30)
+        return fail(c, DDGS_ERR_INVALID_ARG, "too many tiles");
+    c->n_tiles = (int)tiles;
+    c->loss_tiles = (int)ltiles;
+    c->total_pix = pix;
+    c->max_view_pix = maxp;
+    ViewDev *vd;
+    int32_t *lb;
+    DDGS_TRY(ensure_t(c, "views", std::max(1, V), &vd));
+    DDGS_TRY(ensure_t(c, "loss_tile_base", V + 1, &lb));
+    if (V > 0) HIP_TRY(c, hipMemcpyAsync(vd, c->vdev_h.data(), sizeof(ViewDev) * V, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(lb, c->loss_tile_base_h.data(), sizeof(int32_t) * (V + 1), hipMemcpyHostToDevice,
+                              c->stream));
+    // host vectors must outlive the async copies
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->views_dirty = false;
+    return DDGS_OK;
+}
+
+ddgs_status check_ready(ddgs_ctx *c)
+{
+    if (!c->has_model) return fail(c, DDGS_ERR_STATE, "no model set");
+    if (c->views_h.empty()) return fail(c, DDGS_ERR_STATE, "no views set");
+    return prepare_views(c);
+}
+
+// Buffers whose size depends on n and the views only.
+ddgs_status ensure_static(ddgs_ctx *c)
+{
+    const int64_t n = c->model.n, V = (int64_t)c->views_h.size(), VN = n * V;
+    const int KL = kl_of(c->model.L);
+    float *f;
+    uint32_t *u;
+    DDGS_TRY(ensure_t(c, "cov", 6 * n, &f));
+    DDGS_TRY(ensure_t(c, "alpha", n, &f));
+    DDGS_TRY(ensure_t(c, "ciso", n, &f));
+    DDGS_TRY(ensure_t(c, "hdir", (size_t)KL * std::max<int64_t>(1, n - c->model.n_iso), &f));
+    DDGS_TRY(ensure_t(c, "ubuf", (size_t)KL * n, &f));
+    float4 *f4;
+    DDGS_TRY(ensure_t(c, "rec", 2 * VN, &f4));
+    uint2 *u2;
+    DDGS_TRY(ensure_t(c, "rect", VN, &u2));
+    const char *u32s[] = {"zkey", "cnt", "offs", "skey", "sval", "skey2", "sval2", "off_sorted"};
+    for (const char *nm : u32s) DDGS_TRY(ensure_t(c, nm, VN, &u));
+    DDGS_TRY(ensure_t(c, "ranges", std::max(1, c->n_tiles), &u2));
+    DDGS_TRY(ensure_t(c, "qkey", std::max(1, c->n_tiles), &u));
+    DDGS_TRY(ensure_t(c, "qval", std::max(1, c->n_tiles), &u));
+    DDGS_TRY(ensure_t(c, "qkey2", std::max(1, c->n_tiles), &u));
+    DDGS_TRY(ensure_t(c, "qval2", std::max(1, c->n_tiles), &u));
+    DDGS_TRY(ensure_t(c, "img_saved", c->total_pix, &f));
+    DDGS_TRY(ensure_t(c, "nlast", c->total_pix, &u));
+    DDGS_TRY(ensure_t(c, "scalars", 16, &u));
+    const int64_t n_waves = ((n + 255) / 256) * 4;
+    DDGS_TRY(ensure_t(c, "pose_part", (size_t)std::max<int64_t>(1, V * n_waves * 9), &f));
+    DDGS_TRY(ensure_t(c, "basis_part", (size_t)basis_grad_blocks((int)std::max<int64_t>(1, n)) * (32 + 15 * 32), &f));
+    double *d;
+    DDGS_TRY(ensure_t(c, "loss_part", loss_part_doubles((int)V, c->max_view_pix, c->loss_tiles), &d));
+    DDGS_TRY(ensure_t(c, "loss_maps", (size_t)3 * c->total_pix, &f));
+    return DDGS_OK;
+}
+
+// Entry-level buffers (tile entries) and the radix / scan temporaries.
+ddgs_status ensure_entries(ddgs_ctx *c, int64_t cap)
+{
+    const int64_t VN = c->model.n * (int64_t)c->views_h.size();
+    uint32_t *u;
+    float4 *f4;
+    DDGS_TRY(ensure_t(c, "tkey", cap, &u));
+    DDGS_TRY(ensure_t(c, "tval", cap, &u));
+    DDGS_TRY(ensure_t(c, "tkey2", cap, &u));
+    DDGS_TRY(ensure_t(c, "tval2", cap, &u));
+    DDGS_TRY(ensure_t(c, "slot", 2 * cap, &f4));
+    if (c->keep_unsorted) {
+        DDGS_TRY(ensure_t(c, "ukey", cap, &u));
+        DDGS_TRY(ensure_t(c, "uval", cap, &u));
+    }
+    const int64_t big = std::max<int64_t>({VN, cap, (int64_t)c->n_tiles, 1});
+    const size_t cw = radix_counts_words(big);
+    DDGS_TRY(ensure_t(c, "radix_counts", cw, &u));
+    void *p;
+    DDGS_TRY(ensure(c, "scan_tmp", scan_tmp_bytes(std::max<int64_t>((int64_t)cw, big)), &p));
+    c->entry_cap = std::max(c->entry_cap, cap);
+    return DDGS_OK;
+}
+
+void stage_begin(ddgs_ctx *c, int i)
+{
+    if (c->timing) (void)hipEventRecord(c->ev_s[i], c->stream);
+}
+void stage_end(ddgs_ctx *c, int i)
+{
+    if (c->timing) {
+        (void)hipEventRecord(c->ev_e[i], c->stream);
+        c->ev_valid[i] = true;
+    }
+}
+
+// device scalars: [0..1] u64 entry total, [2] entries kept (min(total, cap)),
+// [3] flags (bit 0: capacity overflow), [4], [5] work-queue counters,
+// [8..9] u64 scratch total of the radix-sort scans
+uint64_t *total_ptr(ddgs_ctx *c) { return (uint64_t *)buf<uint32_t>(c, "scalars"); }
+uint32_t *mdev_ptr(ddgs_ctx *c) { return buf<uint32_t>(c, "scalars") + 2; }
+uint32_t *flags_ptr(ddgs_ctx *c) { return buf<uint32_t>(c, "scalars") + 3; }
+uint32_t *counter_ptr(ddgs_ctx *c) { return buf<uint32_t>(c, "scalars") + 4; }
+uint64_t *sort_total_ptr(ddgs_ctx *c) { return (uint64_t *)(buf<uint32_t>(c, "scalars") + 8); }
+
+// Projection, depth sort and scan of the tile counts (stages shared by the
+// plain and the captured paths).
+ddgs_status enqueue_front(ddgs_ctx *c)
+{
+    hipStream_t s = c->stream;
+    const ModelDev m = model_dev(c->model);
+    const int V = (int)c->views_h.size();
+    const int64_t VN = (int64_t)m.n * V;
+    GaussCache gc{buf<float>(c, "cov"), buf<float>(c, "alpha"), buf<float>(c, "ciso"), buf<float>(c, "hdir")};
+    ProjOut po{buf<float4>(c, "rec"), buf<uint2>(c, "rect"), buf<uint32_t>(c, "zkey"), buf<uint32_t>(c, "cnt"),
+               buf<uint32_t>(c, "skey"), buf<uint32_t>(c, "sval")};
+    const RenderOpts ro = render_opts(c->opt);
+    stage_begin(c, DDGS_T_PROJECT);
+    HIP_TRY(c, launch_fill_u32(flags_ptr(c), 0u, 1, s));
+    HIP_TRY(c, launch_prep(m, gc, s));
+    HIP_TRY(c, launch_project(m, gc, buf<ViewDev>(c, "views"), V, ro, po, s));
+    stage_end(c, DDGS_T_PROJECT);
+    stage_begin(c, DDGS_T_SORT);
+    bool in_k1 = false;
+    HIP_TRY(c, radix_sort_pairs(po.sort_key, po.sort_val, buf<uint32_t>(c, "skey2"), buf<uint32_t>(c, "sval2"), VN,
+                                nullptr, 32, buf<uint32_t>(c, "radix_counts"), buf<void>(c, "scan_tmp"),
+                                sort_total_ptr(c), &in_k1, s));
+    const uint32_t *order = in_k1 ? buf<uint32_t>(c, "sval2") : po.sort_val;
+    HIP_TRY(c, launch_exclusive_scan(po.cnt, order, buf<uint32_t>(c, "off_sorted"), VN, buf<void>(c, "scan_tmp"),
+                                     total_ptr(c), s));
+    return DDGS_OK;
+}
+
+// Emission, tile sort, ranges, optional work queue and the forward raster.
+ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, int64_t sort_n, float *images)
+{
+    hipStream_t s = c->stream;
+    const int V = (int)c->views_h.size();
+    const int n = (int)c->model.n;
+    const int64_t VN = (int64_t)n * V;
+    uint32_t *skey = buf<uint32_t>(c, "skey"), *sval = buf<uint32_t>(c, "sval");
+    (void)skey;
+    // the depth order ended where the 4-pass sort left it (even count: input buffers)
+    const uint32_t *order = sval;
+    uint32_t *tkey = buf<uint32_t>(c, "tkey"), *tval = buf<uint32_t>(c, "tval");
+    HIP_TRY(c, launch_emit(VN, n, order, buf<uint32_t>(c, "off_sorted"), buf<uint32_t>(c, "cnt"),
+                           buf<uint2>(c, "rect"), buf<ViewDev>(c, "views"), buf<uint32_t>(c, "offs"), tkey, tval,
+                           (uint32_t)cap, total_ptr(c), mdev_ptr(c), flags_ptr(c), s));
+    if (c->keep_unsorted) {
+        HIP_TRY(c, launch_copy_u32(buf<uint32_t>(c, "ukey"), tkey, mdev_ptr(c), sort_n, s));
+        HIP_TRY(c, launch_copy_u32(buf<uint32_t>(c, "uval"), tval, mdev_ptr(c), sort_n, s));
+    }
+    bool in_k1 = false;
+    HIP_TRY(c, radix_sort_pairs(tkey, tval, buf<uint32_t>(c, "tkey2"), buf<uint32_t>(c, "tval2"), sort_n, mdev_ptr(c),
+                                bits_for(c->n_tiles), buf<uint32_t>(c, "radix_counts"), buf<void>(c, "scan_tmp"),
+                                sort_total_ptr(c), &in_k1, s));
+    c->tkey_sorted = in_k1 ? buf<uint32_t>(c, "tkey2") : tkey;
+    c->tval_sorted = in_k1 ? buf<uint32_t>(c, "tval2") : tval;
+    HIP_TRY(c, launch_ranges(c->tkey_sorted, mdev_ptr(c), sort_n, buf<uint2>(c, "ranges"), c->n_tiles, s));
+    c->queue = nullptr;
+    if (c->opt.persistent) {
+        bool qk1 = false;
+        HIP_TRY(c, launch_tile_cost_keys(buf<uint2>(c, "ranges"), c->n_tiles, buf<uint32_t>(c, "qkey"),
+                                         buf<uint32_t>(c, "qval"), counter_ptr(c), s));
+        HIP_TRY(c, radix_sort_pairs(buf<uint32_t>(c, "qkey"), buf<uint32_t>(c, "qval"), buf<uint32_t>(c, "qkey2"),
+                                    buf<uint32_t>(c, "qval2"), c->n_tiles, nullptr, 24,
+                                    buf<uint32_t>(c, "radix_counts"), buf<void>(c, "scan_tmp"), sort_total_ptr(c),
+                                    &qk1, s));
+        c->queue = qk1 ? buf<uint32_t>(c, "qval2") : buf<uint32_t>(c, "qval");
+    }
+    stage_end(c, DDGS_T_SORT);
+    stage_begin(c, DDGS_T_RASTER_FWD);
+    RasterArgs ra{};
+    ra.views = buf<ViewDev>(c, "views");
+    ra.V = V;
+    ra.n = n;
+    ra.o = render_opts(c->opt);
+    ra.ranges = buf<uint2>(c, "ranges");
+    ra.tval = c->tval_sorted;
+    ra.rec = buf<float4>(c, "rec");
+    ra.n_tiles = c->n_tiles;
+    ra.queue = c->queue;
+    ra.queue_counter = counter_ptr(c);
+    ra.img = images;
+    ra.img_saved = buf<float>(c, "img_saved");
+    ra.nlast = buf<uint32_t>(c, "nlast");
+    HIP_TRY(c, launch_raster_fwd(ra, c->num_cu * 8, s));
+    stage_end(c, DDGS_T_RASTER_FWD);
+    return DDGS_OK;
+}
+
+bool any_param_grad(const ddgs_grads *g)
+{
+    return g->dmean || g->dquat || g->dlog_scale || g->dopacity_logit || g->dfeat || g->db_iso || g->dB_dir;
+}
+
+ddgs_status enqueue_backward(ddgs_ctx *c, const float *dL, const ddgs_grads *g, int64_t slot_cap)
+{
+    hipStream_t s = c->stream;
+    const int V = (int)c->views_h.size();
+    const int n = (int)c->model.n;
+    RasterArgs ra{};
+    ra.views = buf<ViewDev>(c, "views");
+    ra.V = V;
+    ra.n = n;
+    ra.o = render_opts(c->opt);
+    ra.ranges = buf<uint2>(c, "ranges");
+    ra.tval = c->tval_sorted;
+    ra.rec = buf<float4>(c, "rec");
+    ra.n_tiles = c->n_tiles;
+    ra.queue = c->queue;
+    ra.queue_counter = counter_ptr(c) + 1;
+    ra.img_saved = buf<float>(c, "img_saved");
+    ra.nlast = buf<uint32_t>(c, "nlast");
+    ra.dL_dimg = dL;
+    ra.rect = buf<uint2>(c, "rect");
+    ra.offs = buf<uint32_t>(c, "offs");
+    ra.slot = buf<float4>(c, "slot");
+    ra.slot_cap = (uint32_t)std::min<int64_t>(slot_cap, 0xFFFFFFFFll);
+    stage_begin(c, DDGS_T_RASTER_BWD);
+    if (c->queue) HIP_TRY(c, launch_fill_u32(counter_ptr(c) + 1, 0u, 1, s));
+    HIP_TRY(c, launch_raster_bwd(ra, c->num_cu * 4, s));
+    stage_end(c, DDGS_T_RASTER_BWD);
+    stage_begin(c, DDGS_T_PROJECT_BWD);
+
+    const bool per_g = any_param_grad(g);
+    ProjBwdArgs pa{};
+    pa.m = model_dev(c->model);
+    pa.gc = GaussCache{buf<float>(c, "cov"), buf<float>(c, "alpha"), buf<float>(c, "ciso"), buf<float>(c, "hdir")};
+    pa.views = buf<ViewDev>(c, "views");
+    pa.V = V;
+    pa.o = render_opts(c->opt);
+    pa.cnt = buf<uint32_t>(c, "cnt");
+    pa.offs = buf<uint32_t>(c, "offs");
+    pa.slot = buf<float4>(c, "slot");
+    pa.dmean = g->dmean;
+    pa.dquat = g->dquat;
+    pa.dlog_scale = g->dlog_scale;
+    pa.dopacity = g->dopacity_logit;
+    pa.dfeat = g->dfeat;
+    pa.ubuf = (g->db_iso || g->dB_dir) ? buf<float>(c, "ubuf") : nullptr;
+    pa.pose_part = buf<float>(c, "pose_part");
+    pa.per_gaussian = per_g ? 1 : 0;
+    pa.slot_cap = ra.slot_cap;
+    HIP_TRY(c, launch_project_bwd(pa, s));
+    if (g->db_iso || g->dB_dir) {
+        HIP_TRY(c, launch_basis_grad(pa.m, pa.ubuf, buf<float>(c, "basis_part"), s));
+        HIP_TRY(c, launch_basis_final(pa.m, buf<float>(c, "basis_part"), basis_grad_blocks(n), g->db_iso, g->dB_dir, s));
+    }
+    if (g->dpose) {
+        const int n_waves = ((n + 255) / 256) * 4;
+        HIP_TRY(c, launch_pose_final(buf<ViewDev>(c, "views"), V, n_waves, buf<float>(c, "pose_part"), g->dpose, s));
+    }
+    stage_end(c, DDGS_T_PROJECT_BWD);
+    return DDGS_OK;
+}
+
+ddgs_status enqueue_loss(ddgs_ctx *c, int kind, const float *images, const float *target, float lambda,
+                         float *loss_out, float *dL)
+{
+    LossArgs la{};
+    la.views = buf<ViewDev>(c, "views");
+    la.V = (int)c->views_h.size();
+    la.total_pix = c->total_pix;
+    la.img = images;
+    la.target = target;
+    la.lambda = lambda;
+    la.loss_out = loss_out;
+    la.grad = dL;
+    la.part = buf<double>(c, "loss_part");
+    la.maps = buf<float>(c, "loss_maps");
+    la.loss_tiles = c->loss_tiles;
+    la.loss_tile_base = buf<int32_t>(c, "loss_tile_base");
+    la.max_view_pix = c->max_view_pix;
+    stage_begin(c, DDGS_T_LOSS);
+    HIP_TRY(c, launch_loss(kind, la, c->stream));
+    stage_end(c, DDGS_T_LOSS);
+    return DDGS_OK;
+}
+
+void drop_graph(ddgs_ctx *c)
+{
+    if (c->exec) (void)hipGraphExecDestroy(c->exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->exec = nullptr;
+    c->graph = nullptr;
+}
+
+ddgs_status validate_options(ddgs_ctx *c, const ddgs_options &o)
+{
+    if (!raster_tile_supported(o.tile_w, o.tile_h))
+        return fail(c, DDGS_ERR_UNSUPPORTED, "tile shape not supported (8x8, 16x8, 16x16, 32x8)");
+    if (!(o.kappa > 0.0f) || !std::isfinite(o.kappa)) return fail(c, DDGS_ERR_INVALID_ARG, "kappa must be > 0");
+    if (!(o.dilation >= 0.0f) || !std::isfinite(o.dilation)) return fail(c, DDGS_ERR_INVALID_ARG, "dilation must be >= 0");
+    if (!(o.t_min >= 0.0f) || !(o.t_min < 1.0f)) return fail(c, DDGS_ERR_INVALID_ARG, "t_min must be in [0, 1)");
+    if (!(o.z_near > 0.0f) || !std::isfinite(o.z_near)) return fail(c, DDGS_ERR_INVALID_ARG, "z_near must be > 0");
+    if (!(o.sigma_max > 0.0f) || !(o.sigma_max < 1.0f)) return fail(c, DDGS_ERR_INVALID_ARG, "sigma_max must be in (0, 1)");
+    if (o.capacity < 0 || o.capacity > 0xFFFFFFFFll) return fail(c, DDGS_ERR_INVALID_ARG, "capacity out of range");
+    return DDGS_OK;
+}
+
+bool is_state_current(const ddgs_ctx *c)
+{
+    return c->rendered && c->r_model_gen == c->model_gen && c->r_views_gen == c->views_gen &&
+           c->r_opt_gen == c->opt_gen;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+
+extern "C" {
+
+const char *ddgs_status_str(ddgs_status s)
+{
+    switch (s) {
+    case DDGS_OK: return "ok";
+    case DDGS_ERR_INVALID_ARG: return "invalid argument";
+    case DDGS_ERR_OOM: return "out of device memory";
+    case DDGS_ERR_HIP: return "HIP runtime error";
+    case DDGS_ERR_CAPACITY: return "tile-entry capacity exceeded";
+    case DDGS_ERR_NONFINITE: return "non-finite input";
+    case DDGS_ERR_STATE: return "call out of order";
+    case DDGS_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *ddgs_last_error(const ddgs_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void ddgs_default_options(ddgs_options *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tile_w = 16;
+    o->tile_h = 16;
+    o->kappa = 3.0f;
+    o->dilation = 0.3f;
+    o->t_min = 0.0f;
+    o->z_near = 1.0f;
+    o->sigma_max = 0.99f;
+    o->persistent = 0;
+    o->capacity = 0;
+}
+
+ddgs_status ddgs_create(ddgs_ctx **out, int device, void *hip_stream)
+{
+    if (!out) return DDGS_ERR_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return DDGS_ERR_HIP;
+    if (device < 0 || device >= ndev) return DDGS_ERR_INVALID_ARG;
+    if (hipSetDevice(device) != hipSuccess) return DDGS_ERR_HIP;
+    ddgs_ctx *c = new (std::nothrow) ddgs_ctx();
+    if (!c) return DDGS_ERR_OOM;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    ddgs_default_options(&c->opt);
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+        c->num_cu = ncu;
+    for (int i = 0; i < DDGS_T_COUNT; ++i) {
+        if (hipEventCreate(&c->ev_s[i]) != hipSuccess || hipEventCreate(&c->ev_e[i]) != hipSuccess) {
+            ddgs_destroy(c);
+            return DDGS_ERR_HIP;
+        }
+    }
+    *out = c;
+    return DDGS_OK;
+}
+
+void ddgs_destroy(ddgs_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    drop_graph(c);
+    for (auto &kv : c->bufs)
+        if (kv.second.p) (void)hipFree(kv.second.p);
+    for (int i = 0; i < DDGS_T_COUNT; ++i) {
+        if (c->ev_s[i]) (void)hipEventDestroy(c->ev_s[i]);
+        if (c->ev_e[i]) (void)hipEventDestroy(c->ev_e[i]);
+    }
+    delete c;
+}
+
+ddgs_status ddgs_set_stream(ddgs_ctx *c, void *s)
+{
+    if (!c) return DDGS_ERR_INVALID_ARG;
+    c->stream = (hipStream_t)s;
+    drop_graph(c);
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_set_options(ddgs_ctx *c, const ddgs_options *o)
+{
+    if (!c || !o) return fail(c, DDGS_ERR_INVALID_ARG, "null argument");
+    DDGS_TRY(validate_options(c, *o));
+    const bool tiles_changed = o->tile_w != c->opt.tile_w || o->tile_h != c->opt.tile_h;
+    c->opt = *o;
+    if (tiles_changed) c->views_dirty = true;
+    ++c->opt_gen;
+    drop_graph(c);
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_get_options(const ddgs_ctx *c, ddgs_options *o)
+{
+    if (!c || !o) return DDGS_ERR_INVALID_ARG;
+    *o = c->opt;
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_set_model(ddgs_ctx *c, const ddgs_model *m)
+{
+    if (!c || !m) return fail(c, DDGS_ERR_INVALID_ARG, "null argument");
+    if (m->n < 0 || m->n_iso < 0 || m->n_iso > m->n) return fail(c, DDGS_ERR_INVALID_ARG, "need 0 <= n_iso <= n");
+    if (m->n >= ((int64_t)1 << 31)) return fail(c, DDGS_ERR_INVALID_ARG, "n too large");
+    if (m->k < 1 || m->k > kMaxK) return fail(c, DDGS_ERR_INVALID_ARG, "k must be in 1..32");
+    if (m->L < 1 || m->L > 3) return fail(c, DDGS_ERR_UNSUPPORTED, "L must be in 1..3");
+    if (m->n > 0 && (!m->mean || !m->quat || !m->log_scale || !m->opacity_logit || !m->feat))
+        return fail(c, DDGS_ERR_INVALID_ARG, "null Gaussian array");
+    if (!m->b_iso || !m->B_dir) return fail(c, DDGS_ERR_INVALID_ARG, "null basis array");
+    const void *ptrs[] = {m->mean, m->quat, m->log_scale, m->opacity_logit, m->feat, m->b_iso, m->B_dir};
+    for (const void *p : ptrs)
+        if (((uintptr_t)p) % 4 != 0) return fail(c, DDGS_ERR_INVALID_ARG, "arrays must be 4-byte aligned");
+    const bool shape_changed = !c->has_model || c->model.n != m->n || c->model.n_iso != m->n_iso ||
+                               c->model.k != m->k || c->model.L != m->L;
+    const bool ptr_changed = !c->has_model || std::memcmp(&c->model, m, sizeof(*m)) != 0;
+    c->model = *m;
+    c->has_model = true;
+    ++c->model_gen;
+    if (shape_changed || ptr_changed) drop_graph(c);
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_set_views(ddgs_ctx *c, const ddgs_view *v, int nv)
+{
+    if (!c || (nv > 0 && !v) || nv < 0) return fail(c, DDGS_ERR_INVALID_ARG, "bad views");
+    for (int i = 0; i < nv; ++i) {
+        if (v[i].W < 1 || v[i].H < 1 || v[i].W > 16384 || v[i].H > 16384)
+            return fail(c, DDGS_ERR_INVALID_ARG, "detector size must be in 1..16384");
+        if (!(v[i].pitch_mm > 0.0f) || !(v[i].sdd_mm > 0.0f))
+            return fail(c, DDGS_ERR_INVALID_ARG, "pitch and sdd must be > 0");
+        for (int q = 0; q < 12; ++q)
+            if (!std::isfinite(v[i].pose[q])) return fail(c, DDGS_ERR_NONFINITE, "non-finite pose");
+        if (!std::isfinite(v[i].pitch_mm) || !std::isfinite(v[i].sdd_mm))
+            return fail(c, DDGS_ERR_NONFINITE, "non-finite intrinsics");
+    }
+    bool same_shape = (int)c->views_h.size() == nv;
+    for (int i = 0; same_shape && i < nv; ++i)
+        same_shape = c->views_h[i].W == v[i].W && c->views_h[i].H == v[i].H;
+    c->views_h.assign(v, v + nv);
+    c->views_dirty = true;
+    ++c->views_gen;
+    if (!same_shape) drop_graph(c);
+    if (c->exec) {
+        // same shapes: refresh the device table in place for the captured graph
+        DDGS_TRY(prepare_views(c));
+    }
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_image_size(const ddgs_ctx *c, int64_t *nf)
+{
+    if (!c || !nf) return DDGS_ERR_INVALID_ARG;
+    int64_t s = 0;
+    for (const auto &v : c->views_h) s += (int64_t)v.W * v.H;
+    *nf = s;
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_render(ddgs_ctx *c, float *images)
+{
+    if (!c) return DDGS_ERR_INVALID_ARG;
+    if (!images) return fail(c, DDGS_ERR_INVALID_ARG, "null images");
+    HIP_TRY(c, hipSetDevice(c->device));
+    DDGS_TRY(check_ready(c));
+    c->rendered = false;
+    DDGS_TRY(ensure_static(c));
+    DDGS_TRY(ensure_entries(c, std::max<int64_t>(c->entry_cap, 1)));
+    const int64_t VN = c->model.n * (int64_t)c->views_h.size();
+    if (VN > 0) {
+        DDGS_TRY(enqueue_front(c));
+        uint64_t total = 0;
+        HIP_TRY(c, hipMemcpyAsync(&total, total_ptr(c), sizeof(total), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (total >= 0xFFFFFFFFull) return fail(c, DDGS_ERR_CAPACITY, "more than 2^32-1 tile entries");
+        c->M = (int64_t)total;
+        if (c->M > c->entry_cap) DDGS_TRY(ensure_entries(c, c->M));
+    } else {
+        c->M = 0;
+        HIP_TRY(c, launch_zero_u64(total_ptr(c), c->stream));
+    }
+    if (VN > 0) {
+        DDGS_TRY(enqueue_back(c, c->entry_cap, c->M, images));
+    } else {
+        // no Gaussians: empty lists everywhere
+        HIP_TRY(c, launch_fill_u32(mdev_ptr(c), 0u, 1, c->stream));
+        HIP_TRY(c, launch_ranges(buf<uint32_t>(c, "tkey"), mdev_ptr(c), 0, buf<uint2>(c, "ranges"), c->n_tiles,
+                                 c->stream));
+        c->tkey_sorted = buf<uint32_t>(c, "tkey");
+        c->tval_sorted = buf<uint32_t>(c, "tval");
+        c->queue = nullptr;
+        RasterArgs ra{};
+        ra.views = buf<ViewDev>(c, "views");
+        ra.V = (int)c->views_h.size();
+        ra.n = 1;
+        ra.o = render_opts(c->opt);
+        ra.ranges = buf<uint2>(c, "ranges");
+        ra.tval = c->tval_sorted;
+        ra.rec = buf<float4>(c, "rec");
+        ra.n_tiles = c->n_tiles;
+        ra.img = images;
+        ra.img_saved = buf<float>(c, "img_saved");
+        ra.nlast = buf<uint32_t>(c, "nlast");
+        HIP_TRY(c, launch_raster_fwd(ra, c->num_cu, c->stream));
+    }
+    c->rendered = true;
+    c->r_model_gen = c->model_gen;
+    c->r_views_gen = c->views_gen;
+    c->r_opt_gen = c->opt_gen;
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_backward(ddgs_ctx *c, const float *dL, const ddgs_grads *g)
+{
+    if (!c) return DDGS_ERR_INVALID_ARG;
+    if (!dL || !g) return fail(c, DDGS_ERR_INVALID_ARG, "null argument");
+    if (!is_state_current(c)) return fail(c, DDGS_ERR_STATE, "backward needs a render with the current model, views and options");
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (c->model.n == 0) {
+        // nothing depends on any parameter: zero outputs
+        if (g->db_iso) HIP_TRY(c, launch_fill_u32((uint32_t *)g->db_iso, 0u, c->model.k, c->stream));
+        if (g->dB_dir) HIP_TRY(c, launch_fill_u32((uint32_t *)g->dB_dir, 0u, (int64_t)kl_of(c->model.L) * c->model.k, c->stream));
+        if (g->dpose) HIP_TRY(c, launch_fill_u32((uint32_t *)g->dpose, 0u, 6 * (int64_t)c->views_h.size(), c->stream));
+        return DDGS_OK;
+    }
+    DDGS_TRY(enqueue_backward(c, dL, g, c->entry_cap));
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_loss(ddgs_ctx *c, int kind, const float *images, const float *target, float lambda,
+                      float *loss_out, float *dL)
+{
+    if (!c) return DDGS_ERR_INVALID_ARG;
+    if (!images || !target) return fail(c, DDGS_ERR_INVALID_ARG, "null images or target");
+    if (kind < 0 || kind > 2) return fail(c, DDGS_ERR_INVALID_ARG, "unknown loss kind");
+    if (!(lambda >= 0.0f && lambda <= 1.0f)) return fail(c, DDGS_ERR_INVALID_ARG, "lambda must be in [0, 1]");
+    HIP_TRY(c, hipSetDevice(c->device));
+    DDGS_TRY(check_ready(c));
+    DDGS_TRY(ensure_static(c));
+    DDGS_TRY(enqueue_loss(c, kind, images, target, lambda, loss_out, dL));
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_step_capture(ddgs_ctx *c, int kind, const float *target, float lambda, float *images, float *dL,
+                              float *loss_out, const ddgs_grads *g)
+{
+    if (!c) return DDGS_ERR_INVALID_ARG;
+    if (!images || !dL || !g || !target) return fail(c, DDGS_ERR_INVALID_ARG, "null argument");
+    if (kind < 0 || kind > 2) return fail(c, DDGS_ERR_INVALID_ARG, "unknown loss kind");
+    HIP_TRY(c, hipSetDevice(c->device));
+    DDGS_TRY(check_ready(c));
+    if (c->model.n == 0) return fail(c, DDGS_ERR_UNSUPPORTED, "a captured step needs n > 0");
+    if (!c->stream) return fail(c, DDGS_ERR_INVALID_ARG, "capture needs a non-default stream");
+    drop_graph(c);
+    DDGS_TRY(ensure_static(c));
+    int64_t cap = c->opt.capacity;
+    if (cap <= 0) {
+        // one plain render sizes the capacity: twice the current need
+        float *tmp_img;
+        DDGS_TRY(ensure_t(c, "capture_probe_img", c->total_pix, &tmp_img));
+        DDGS_TRY(ddgs_render(c, tmp_img));
+        cap = std::max<int64_t>(2 * c->M, 1024);
+    }
+    cap = std::min<int64_t>(cap, 0xFFFFFFF0ll);
+    DDGS_TRY(ensure_entries(c, cap));
+    c->step_cap = c->entry_cap;
+    const bool saved_timing = c->timing;
+    c->timing = false;
+    HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    ddgs_status st = enqueue_front(c);
+    if (st == DDGS_OK) st = enqueue_back(c, c->step_cap, c->step_cap, images);
+    if (st == DDGS_OK) st = enqueue_loss(c, kind, images, target, lambda, loss_out, dL);
+    if (st == DDGS_OK) st = enqueue_backward(c, dL, g, c->step_cap);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &graph);
+    c->timing = saved_timing;
+    if (st != DDGS_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(c, DDGS_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    c->graph = graph;
+    e = hipGraphInstantiate(&c->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        drop_graph(c);
+        return fail(c, DDGS_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    c->rendered = false;
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_step_launch(ddgs_ctx *c)
+{
+    if (!c) return DDGS_ERR_INVALID_ARG;
+    if (!c->exec) return fail(c, DDGS_ERR_STATE, "no captured step");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipGraphLaunch(c->exec, c->stream));
+    c->M = -1;  // unknown until ddgs_check
+    c->rendered = true;
+    c->r_model_gen = c->model_gen;
+    c->r_views_gen = c->views_gen;
+    c->r_opt_gen = c->opt_gen;
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_check(ddgs_ctx *c, uint32_t *flags)
+{
+    if (!c) return DDGS_ERR_INVALID_ARG;
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    uint32_t sc[4] = {0, 0, 0, 0};
+    if (buf<uint32_t>(c, "scalars"))
+        HIP_TRY(c, hipMemcpy(sc, buf<uint32_t>(c, "scalars"), sizeof(sc), hipMemcpyDeviceToHost));
+    if (flags) *flags = sc[3];
+    const uint64_t total = (uint64_t)sc[0] | ((uint64_t)sc[1] << 32);
+    if (c->M < 0) c->M = (int64_t)std::min<uint64_t>(total, (uint64_t)c->entry_cap);
+    if (sc[3] & 1u)
+        return fail(c, DDGS_ERR_CAPACITY, "tile entries (" + std::to_string(total) + ") exceeded the capacity (" +
+                                              std::to_string(c->step_cap) + ")");
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_param_count(int k, int L, int64_t n, int64_t *per, int64_t *shared)
+{
+    if (k < 1 || L < 1 || L > 3 || n < 0) return DDGS_ERR_INVALID_ARG;
+    if (per) *per = 3 + 4 + 3 + 1 + (int64_t)k;
+    if (shared) *shared = (int64_t)k + (int64_t)kl_of(L) * k;
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_num_rendered(const ddgs_ctx *c, int64_t *n)
+{
+    if (!c || !n) return DDGS_ERR_INVALID_ARG;
+    *n = c->M;
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_debug_keep_unsorted(ddgs_ctx *c, int keep)
+{
+    if (!c) return DDGS_ERR_INVALID_ARG;
+    c->keep_unsorted = keep != 0;
+    if (keep && c->entry_cap > 0) DDGS_TRY(ensure_entries(c, c->entry_cap));
+    drop_graph(c);
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_debug_copy(ddgs_ctx *c, int what, void *host, size_t bytes)
+{
+    if (!c || !host) return DDGS_ERR_INVALID_ARG;
+    if (!c->rendered) return fail(c, DDGS_ERR_STATE, "nothing rendered");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const int64_t VN = c->model.n * (int64_t)c->views_h.size();
+    if (c->M < 0) {
+        uint32_t fl = 0;
+        ddgs_check(c, &fl);
+    }
+    const int64_t M = std::max<int64_t>(c->M, 0);
+    const void *src = nullptr;
+    size_t need = 0;
+    std::vector<uint16_t> rect16;
+    switch (what) {
+    case DDGS_DBG_RECORDS: src = buf<void>(c, "rec"); need = (size_t)VN * 32; break;
+    case DDGS_DBG_DEPTH_KEYS: src = buf<void>(c, "zkey"); need = (size_t)VN * 4; break;
+    case DDGS_DBG_COUNTS: src = buf<void>(c, "cnt"); need = (size_t)VN * 4; break;
+    case DDGS_DBG_RECTS: src = buf<void>(c, "rect"); need = (size_t)VN * 8; break;
+    case DDGS_DBG_TILE_KEYS_UNSORTED:
+    case DDGS_DBG_TILE_VALS_UNSORTED:
+        if (!c->keep_unsorted) return fail(c, DDGS_ERR_STATE, "unsorted entries were not kept");
+        src = buf<void>(c, what == DDGS_DBG_TILE_KEYS_UNSORTED ? "ukey" : "uval");
+        need = (size_t)M * 4;
+        break;
+    case DDGS_DBG_TILE_KEYS: src = c->tkey_sorted; need = (size_t)M * 4; break;
+    case DDGS_DBG_TILE_VALS: src = c->tval_sorted; need = (size_t)M * 4; break;
+    case DDGS_DBG_RANGES: src = buf<void>(c, "ranges"); need = (size_t)c->n_tiles * 8; break;
+    case DDGS_DBG_NLAST: src = buf<void>(c, "nlast"); need = (size_t)c->total_pix * 4; break;
+    case DDGS_DBG_TILE_BASE: {
+        const size_t V = c->views_h.size();
+        if (bytes < (V + 1) * 4) return fail(c, DDGS_ERR_INVALID_ARG, "buffer too small");
+        int32_t *o = (int32_t *)host;
+        for (size_t v = 0; v < V; ++v) o[v] = c->vdev_h[v].tile_base;
+        o[V] = c->n_tiles;
+        return DDGS_OK;
+    }
+    default: return fail(c, DDGS_ERR_INVALID_ARG, "unknown debug array");
+    }
+    if (bytes < need) return fail(c, DDGS_ERR_INVALID_ARG, "buffer too small: need " + std::to_string(need));
+    if (need > 0 && src) HIP_TRY(c, hipMemcpy(host, src, need, hipMemcpyDeviceToHost));
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_debug_sort_pairs(ddgs_ctx *c, uint32_t *keys, uint32_t *vals, int64_t n, int bits)
+{
+    if (!c || n < 0 || bits < 1 || bits > 32 || (n > 0 && (!keys || !vals))) return fail(c, DDGS_ERR_INVALID_ARG, "bad sort arguments");
+    if (n > 0xFFFFFFFFll) return fail(c, DDGS_ERR_INVALID_ARG, "n too large");
+    if (n == 0) return DDGS_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    uint32_t *k1, *v1, *counts;
+    DDGS_TRY(ensure_t(c, "dbg_k1", n, &k1));
+    DDGS_TRY(ensure_t(c, "dbg_v1", n, &v1));
+    const size_t cw = radix_counts_words(n);
+    DDGS_TRY(ensure_t(c, "dbg_counts", cw, &counts));
+    void *tmp;
+    DDGS_TRY(ensure(c, "dbg_scan", scan_tmp_bytes(std::max<int64_t>((int64_t)cw, n)), &tmp));
+    uint64_t *tot;
+    DDGS_TRY(ensure_t(c, "dbg_total", 1, &tot));
+    bool in_k1 = false;
+    HIP_TRY(c, radix_sort_pairs(keys, vals, k1, v1, n, nullptr, bits, counts, tmp, tot, &in_k1, c->stream));
+    if (in_k1) {
+        HIP_TRY(c, launch_copy_u32(keys, k1, nullptr, n, c->stream));
+        HIP_TRY(c, launch_copy_u32(vals, v1, nullptr, n, c->stream));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_debug_exclusive_scan(ddgs_ctx *c, const uint32_t *in, uint32_t *out, int64_t n, uint64_t *total)
+{
+    if (!c || n < 0 || (n > 0 && (!in || !out))) return fail(c, DDGS_ERR_INVALID_ARG, "bad scan arguments");
+    HIP_TRY(c, hipSetDevice(c->device));
+    void *tmp;
+    DDGS_TRY(ensure(c, "dbg_scan", scan_tmp_bytes(std::max<int64_t>(n, 1)), &tmp));
+    uint64_t *tot;
+    DDGS_TRY(ensure_t(c, "dbg_total", 1, &tot));
+    HIP_TRY(c, launch_exclusive_scan(in, nullptr, out, n, tmp, tot, c->stream));
+    uint64_t h = 0;
+    HIP_TRY(c, hipMemcpyAsync(&h, tot, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (total) *total = h;
+    return DDGS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ autotune
+
+namespace {
+
+struct TuneEntry {
+    int tile_w = 16, tile_h = 16, persistent = 0;
+    double ms = 0.0;
+};
+
+std::string tune_signature(const ddgs_ctx *c)
+{
+    // workload signature: Gaussian-count bucket (power of two), the detector
+    // mix (sizes with multiplicity), the feature size and the degree
+    std::map<std::pair<int, int>, int> mix;
+    for (const auto &v : c->views_h) mix[{v.W, v.H}]++;
+    int b = 0;
+    while (((int64_t)1 << b) < c->model.n) ++b;
+    std::ostringstream s;
+    s << "gfx950|n2^" << b << "|k" << c->model.k << "|L" << c->model.L << "|";
+    for (const auto &kv : mix) s << kv.first.first << "x" << kv.first.second << "*" << kv.second << ";";
+    return s.str();
+}
+
+bool parse_num(const std::string &obj, const char *key, double *out)
+{
+    const std::string k = std::string("\"") + key + "\"";
+    const size_t p = obj.find(k);
+    if (p == std::string::npos) return false;
+    const size_t colon = obj.find(':', p + k.size());
+    if (colon == std::string::npos) return false;
+    char *end = nullptr;
+    const double v = std::strtod(obj.c_str() + colon + 1, &end);
+    if (end == obj.c_str() + colon + 1 || !std::isfinite(v)) return false;
+    *out = v;
+    return true;
+}
+
+// Reads {"sig": {"tile_w": .., "tile_h": .., "persistent": .., "ms": ..}, ...};
+// anything unreadable is skipped (an unusable cache just means re-tuning).
+std::map<std::string, TuneEntry> read_cache(const char *path)
+{
+    std::map<std::string, TuneEntry> out;
+    std::ifstream f(path);
+    if (!f) return out;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string s = ss.str();
+    size_t pos = 0;
+    while (true) {
+        const size_t q0 = s.find('"', pos);
+        if (q0 == std::string::npos) break;
+        const size_t q1 = s.find('"', q0 + 1);
+        if (q1 == std::string::npos) break;
+        const size_t ob = s.find('{', q1);
+        const size_t cb = s.find('}', q1);
+        if (ob == std::string::npos || cb == std::string::npos || cb < ob) break;
+        const std::string key = s.substr(q0 + 1, q1 - q0 - 1);
+        const std::string obj = s.substr(ob, cb - ob + 1);
+        double tw, th, pe, ms;
+        if (parse_num(obj, "tile_w", &tw) && parse_num(obj, "tile_h", &th) && parse_num(obj, "persistent", &pe) &&
+            parse_num(obj, "ms", &ms) && raster_tile_supported((int)tw, (int)th) && (pe == 0.0 || pe == 1.0)) {
+            TuneEntry e;
+            e.tile_w = (int)tw;
+            e.tile_h = (int)th;
+            e.persistent = (int)pe;
+            e.ms = ms;
+            out[key] = e;
+        }
+        pos = cb + 1;
+    }
+    return out;
+}
+
+bool write_cache(const char *path, const std::map<std::string, TuneEntry> &m)
+{
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream f(tmp);
+        if (!f) return false;
+        f << "{\n";
+        size_t i = 0;
+        for (const auto &kv : m) {
+            f << "  \"" << kv.first << "\": {\"tile_w\": " << kv.second.tile_w << ", \"tile_h\": " << kv.second.tile_h
+              << ", \"persistent\": " << kv.second.persistent << ", \"ms\": " << kv.second.ms << "}"
+              << (++i < m.size() ? ",\n" : "\n");
+        }
+        f << "}\n";
+        if (!f) return false;
+    }
+    return std::rename(tmp.c_str(), path) == 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+ddgs_status ddgs_autotune(ddgs_ctx *c, const char *cache_path, int repeats, float *best_ms)
+{
+    if (!c) return DDGS_ERR_INVALID_ARG;
+    if (repeats < 1) repeats = 5;
+    HIP_TRY(c, hipSetDevice(c->device));
+    DDGS_TRY(check_ready(c));
+    const std::string sig = tune_signature(c);
+    std::map<std::string, TuneEntry> cache;
+    if (cache_path) {
+        cache = read_cache(cache_path);
+        auto it = cache.find(sig);
+        if (it != cache.end()) {
+            ddgs_options o = c->opt;
+            o.tile_w = it->second.tile_w;
+            o.tile_h = it->second.tile_h;
+            o.persistent = it->second.persistent;
+            DDGS_TRY(ddgs_set_options(c, &o));
+            if (best_ms) *best_ms = (float)it->second.ms;
+            return DDGS_OK;
+        }
+    }
+    const int64_t n = c->model.n, k = c->model.k, KL = kl_of(c->model.L), V = (int64_t)c->views_h.size();
+    float *img, *dL, *gm, *gq, *gs, *go, *gf, *gb, *gB, *gp;
+    DDGS_TRY(prepare_views(c));
+    DDGS_TRY(ensure_t(c, "tune_img", c->total_pix, &img));
+    DDGS_TRY(ensure_t(c, "tune_dl", c->total_pix, &dL));
+    DDGS_TRY(ensure_t(c, "tune_gm", 3 * n, &gm));
+    DDGS_TRY(ensure_t(c, "tune_gq", 4 * n, &gq));
+    DDGS_TRY(ensure_t(c, "tune_gs", 3 * n, &gs));
+    DDGS_TRY(ensure_t(c, "tune_go", n, &go));
+    DDGS_TRY(ensure_t(c, "tune_gf", k * n, &gf));
+    DDGS_TRY(ensure_t(c, "tune_gb", k, &gb));
+    DDGS_TRY(ensure_t(c, "tune_gB", KL * k, &gB));
+    DDGS_TRY(ensure_t(c, "tune_gp", 6 * V, &gp));
+    HIP_TRY(c, launch_fill_u32((uint32_t *)dL, 0x3f800000u, c->total_pix, c->stream));  // 1.0f
+    ddgs_grads g{gm, gq, gs, go, gf, gb, gB, gp};
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    const ddgs_options base = c->opt;
+    const int shapes[4][2] = {{16, 16}, {8, 8}, {16, 8}, {32, 8}};
+    TuneEntry best;
+    double best_t = 1e300;
+    ddgs_status st = DDGS_OK;
+    for (int si = 0; si < 4 && st == DDGS_OK; ++si) {
+        for (int pe = 0; pe < 2 && st == DDGS_OK; ++pe) {
+            ddgs_options o = base;
+            o.tile_w = shapes[si][0];
+            o.tile_h = shapes[si][1];
+            o.persistent = pe;
+            st = ddgs_set_options(c, &o);
+            if (st == DDGS_OK) st = ddgs_render(c, img);
+            if (st == DDGS_OK) st = ddgs_backward(c, dL, &g);
+            std::vector<float> ts;
+            for (int r = 0; r < repeats && st == DDGS_OK; ++r) {
+                (void)hipEventRecord(e0, c->stream);
+                st = ddgs_render(c, img);
+                if (st == DDGS_OK) st = ddgs_backward(c, dL, &g);
+                (void)hipEventRecord(e1, c->stream);
+                if (hipEventSynchronize(e1) != hipSuccess) st = fail(c, DDGS_ERR_HIP, "event sync failed");
+                float t = 0.0f;
+                (void)hipEventElapsedTime(&t, e0, e1);
+                ts.push_back(t);
+            }
+            if (st != DDGS_OK) break;
+            std::sort(ts.begin(), ts.end());
+            const double med = ts[ts.size() / 2];
+            if (med < best_t) {
+                best_t = med;
+                best.tile_w = o.tile_w;
+                best.tile_h = o.tile_h;
+                best.persistent = pe;
+                best.ms = med;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ddgs_options o = base;
+    if (st == DDGS_OK) {
+        o.tile_w = best.tile_w;
+        o.tile_h = best.tile_h;
+        o.persistent = best.persistent;
+    }
+    const ddgs_status st2 = ddgs_set_options(c, &o);
+    if (st != DDGS_OK) return st;
+    if (st2 != DDGS_OK) return st2;
+    if (best_ms) *best_ms = (float)best.ms;
+    if (cache_path) {
+        cache[sig] = best;
+        if (!write_cache(cache_path, cache)) return fail(c, DDGS_ERR_INVALID_ARG, "cannot write the tuning cache");
+    }
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_enable_timing(ddgs_ctx *c, int enable)
+{
+    if (!c) return DDGS_ERR_INVALID_ARG;
+    c->timing = enable != 0;
+    for (int i = 0; i < DDGS_T_COUNT; ++i) c->ev_valid[i] = false;
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_stage_times(const ddgs_ctx *cc, float *ms)
+{
+    ddgs_ctx *c = const_cast<ddgs_ctx *>(cc);
+    if (!c || !ms) return DDGS_ERR_INVALID_ARG;
+    if (!c->timing) return fail(c, DDGS_ERR_STATE, "timing is not enabled");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < DDGS_T_COUNT; ++i) {
+        ms[i] = 0.0f;
+        if (!c->ev_valid[i]) continue;
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, c->ev_s[i], c->ev_e[i]) == hipSuccess) ms[i] = t;
+    }
+    return DDGS_OK;
+}
+
+}  // extern "C"

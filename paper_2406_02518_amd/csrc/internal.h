@@ -1,0 +1,188 @@
+// internal.h -- device-side structures and launch wrappers of libddgs.so
+// (gfx950, wave64).  Not part of the public ABI (include/ddgs.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ddgs {
+
+constexpr int kWave = 64;
+constexpr int kMaxK = 32;   // feature size supported (Eq. 3: f in R^k)
+constexpr int kMaxKL = 15;  // L(L+2) at L = 3
+
+// One view as the kernels see it (host prepares it from ddgs_view).
+struct ViewDev {
+    float R[9];      // world -> source rotation, row-major
+    float t[3];
+    float so[3];     // source position in the world frame, -R^T t
+    float f;         // focal length in pixels, sdd / pitch
+    float cx, cy;    // principal point, (W/2, H/2)
+    int32_t W, H;
+    int32_t ntx, nty;      // tiles per row / column
+    int32_t tile_base;     // first global tile id of this view
+    int32_t pad;
+    int64_t pix_base;      // first pixel of this view in the concatenated image
+};
+
+struct RenderOpts {
+    float kappa, kappa2, dilation, t_min, z_near, sigma_max;
+    int32_t tile_w, tile_h;
+};
+
+// Device pointers of the model (SoA, caller-owned).
+struct ModelDev {
+    int32_t n, n_iso, k, L;
+    const float *mean, *quat, *log_scale, *opacity_logit, *feat, *b_iso, *B_dir;
+};
+
+// View-independent per-Gaussian values, computed once per step.
+struct GaussCache {
+    float *cov;    // [6][n]: world covariance xx, xy, xz, yy, yz, zz
+    float *alpha;  // [n]
+    float *ciso;   // [n]: isotropic radiosity (only [0, n_iso) meaningful)
+    float *hdir;   // [k_L][n - n_iso]: B_dir f for directional Gaussians
+};
+
+// Per (view, Gaussian) projection output.
+struct ProjOut {
+    float4 *rec;     // [V*n][2]: (mx, my, A00, A01), (A11, alpha, c, 0)
+    uint2 *rect;     // [V*n]: (tx0 | ty0 << 16, tx1 | ty1 << 16), inclusive
+    uint32_t *zkey;  // [V*n]: float bits of the source-frame depth, ~0u if culled
+    uint32_t *cnt;   // [V*n]: number of tiles touched
+    uint32_t *sort_key, *sort_val;  // [V*n]: depth key and v*n+i, input of the depth sort
+};
+
+// Per-(view, Gaussian) image-plane gradient accumulated by the raster
+// backward, one 8-float slot per tile entry in emission order:
+// d mu^x, d mu^y, d A00, d A01, d A11, d alpha, d c, 0.
+struct GradSlots { float4 *slot; };
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ float wave_sum(float x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
+{
+    const int lane = (int)__lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, kWave);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+// ---------------------------------------------------------------- launches
+// (each returns hipGetLastError() of its launches)
+
+// project.hip
+hipError_t launch_prep(const ModelDev &m, const GaussCache &gc, hipStream_t s);
+hipError_t launch_project(const ModelDev &m, const GaussCache &gc, const ViewDev *views, int V,
+                          const RenderOpts &o, const ProjOut &po, hipStream_t s);
+
+// Backward of the projection: sums each (view, Gaussian)'s gradient slots,
+// applies the chain rule to the parameters, and writes per-wave pose partials
+// [V][n_waves][9] and per-Gaussian basis terms ubuf ([k_L][n] for directional,
+// [0][i] = d z for isotropic).
+struct ProjBwdArgs {
+    ModelDev m;
+    GaussCache gc;
+    const ViewDev *views;
+    int V;
+    RenderOpts o;
+    const uint32_t *cnt, *offs;
+    const float4 *slot;
+    float *dmean, *dquat, *dlog_scale, *dopacity, *dfeat;  // NULL: skip
+    float *ubuf;        // [k_L][n] (NULL: skip basis terms)
+    float *pose_part;   // [V][n_waves][9]
+    int per_gaussian;   // 0: pose only
+    uint32_t slot_cap;  // number of gradient slots (entries beyond are ignored)
+};
+hipError_t launch_project_bwd(const ProjBwdArgs &a, hipStream_t s);
+// d b_iso, d B_dir partial sums per block: part [n_blocks][k + k_L k]
+int basis_grad_blocks(int n);
+hipError_t launch_basis_grad(const ModelDev &m, const float *ubuf, float *part, hipStream_t s);
+hipError_t launch_basis_final(const ModelDev &m, const float *part, int nblk, float *db, float *dB,
+                              hipStream_t s);
+hipError_t launch_pose_final(const ViewDev *views, int V, int n_waves, const float *pose_part,
+                             float *dpose, hipStream_t s);
+
+// sort.hip
+constexpr int kScanTile = 4096;
+size_t scan_tmp_bytes(int64_t n);
+// out[i] = sum_{j<i} in[g(j)] with g = gather ? gather[j] : j; *total (device u64) = sum.
+hipError_t launch_exclusive_scan(const uint32_t *in, const uint32_t *gather, uint32_t *out, int64_t n,
+                                 void *tmp, uint64_t *total, hipStream_t s);
+size_t radix_counts_words(int64_t n_cap);
+// Sorts (keys, vals) by key bits [0, bits) (stable).  n_dev (may be NULL)
+// limits the count at run time to min(*n_dev, n_cap).  Ping-pongs between
+// (k0, v0) and (k1, v1); *in_k1 tells where the result ended.
+hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n_cap,
+                            const uint32_t *n_dev, int bits, uint32_t *counts, void *scan_tmp,
+                            uint64_t *scan_total, bool *in_k1, hipStream_t s);
+hipError_t launch_emit(int64_t VN, int n, const uint32_t *order, const uint32_t *off_sorted,
+                       const uint32_t *cnt, const uint2 *rect, const ViewDev *views,
+                       uint32_t *offs, uint32_t *tkey, uint32_t *tval, uint32_t capacity,
+                       const uint64_t *total, uint32_t *m_out, uint32_t *flags, hipStream_t s);
+hipError_t launch_ranges(const uint32_t *keys, const uint32_t *m_dev, int64_t m_cap, uint2 *ranges,
+                         int n_tiles, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_zero_u64(uint64_t *p, hipStream_t s);
+hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, const uint32_t *n_dev, int64_t n_cap,
+                           hipStream_t s);
+
+// raster.hip
+struct RasterArgs {
+    const ViewDev *views;
+    int V, n;
+    RenderOpts o;
+    const uint2 *ranges;
+    const uint32_t *tval;
+    const float4 *rec;
+    int n_tiles;
+    const uint32_t *queue;     // persistent mode: tile order (NULL: blockIdx)
+    uint32_t *queue_counter;   // persistent mode work counter
+    // forward
+    float *img, *img_saved;
+    uint32_t *nlast;
+    // backward
+    const float *dL_dimg;
+    const uint2 *rect;
+    const uint32_t *offs;
+    float4 *slot;
+    uint32_t slot_cap;
+};
+hipError_t launch_raster_fwd(const RasterArgs &a, int persistent_blocks, hipStream_t s);
+hipError_t launch_raster_bwd(const RasterArgs &a, int persistent_blocks, hipStream_t s);
+// persistent queue: order tiles by descending list length
+hipError_t launch_tile_cost_keys(const uint2 *ranges, int n_tiles, uint32_t *keys, uint32_t *vals,
+                                 uint32_t *counter, hipStream_t s);
+bool raster_tile_supported(int tw, int th);
+
+// loss.hip
+struct LossArgs {
+    const ViewDev *views;
+    int V;
+    int64_t total_pix;
+    const float *img, *target;
+    float lambda;
+    float *loss_out;   // [V] (may be NULL)
+    float *grad;       // image layout (may be NULL)
+    double *part;      // scratch
+    float *maps;       // scratch, 3 * total_pix floats (SSIM)
+    int loss_tiles;    // SSIM: total 16x16 tiles
+    const int32_t *loss_tile_base; // [V+1]
+    int64_t max_view_pix;          // largest W*H among the views
+};
+size_t loss_part_doubles(int V, int64_t max_view_pix, int loss_tiles);
+hipError_t launch_loss(int kind, const LossArgs &a, hipStream_t s);
+
+}  // namespace ddgs

@@ -1,0 +1,717 @@
+// project.hip -- per-Gaussian and per-(view, Gaussian) kernels of the DDGS
+// DRR splatting path on gfx950: view-independent preparation, cone-beam
+// projection with the Eq. 3 radiosity and tile footprint, and the backward
+// chain rule to the Gaussian parameters, the shared bases and the source pose.
+//
+// Layout: every model array is structure-of-arrays ([component][n]) so that
+// consecutive lanes of a wave read consecutive floats (coalesced 256-byte
+// wave loads).  One thread handles one Gaussian (x) of one view (y).
+#include "internal.h"
+
+namespace ddgs {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+// Real orthonormal spherical basis of degrees 1..L at the unit direction
+// (x, y, z): order l = 1..L, m = -l..l, no Condon-Shortley phase.  The
+// normalisations are sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!) times the factor
+// sqrt(2) for m != 0, folded into the Cartesian polynomials.
+template <int L>
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float *Y)
+{
+    const float c1 = 0.48860251190291992f;
+    Y[0] = c1 * y;
+    Y[1] = c1 * z;
+    Y[2] = c1 * x;
+    if constexpr (L >= 2) {
+        const float a2 = 1.0925484305920792f, b2 = 0.31539156525252005f, c2 = 0.54627421529603959f;
+        Y[3] = a2 * x * y;
+        Y[4] = a2 * y * z;
+        Y[5] = b2 * (3.0f * z * z - 1.0f);
+        Y[6] = a2 * x * z;
+        Y[7] = c2 * (x * x - y * y);
+    }
+    if constexpr (L >= 3) {
+        const float a3 = 0.59004358992664352f, b3 = 2.8906114426405538f, c3 = 0.45704579946446572f;
+        const float e3 = 0.37317633259011540f, h3 = 1.4453057213202769f;
+        Y[8] = a3 * y * (3.0f * x * x - y * y);
+        Y[9] = b3 * x * y * z;
+        Y[10] = c3 * y * (5.0f * z * z - 1.0f);
+        Y[11] = e3 * z * (5.0f * z * z - 3.0f);
+        Y[12] = c3 * x * (5.0f * z * z - 1.0f);
+        Y[13] = h3 * z * (x * x - y * y);
+        Y[14] = a3 * x * (x * x - 3.0f * y * y);
+    }
+}
+
+// sum_m w[m] * grad Y_m(x, y, z) (gradient of the polynomials above)
+template <int L>
+__device__ __forceinline__ void sh_basis_grad(float x, float y, float z, const float *w, float &gx,
+                                              float &gy, float &gz)
+{
+    const float c1 = 0.48860251190291992f;
+    gx = c1 * w[2];
+    gy = c1 * w[0];
+    gz = c1 * w[1];
+    if constexpr (L >= 2) {
+        const float a2 = 1.0925484305920792f, b2 = 0.31539156525252005f, c2 = 0.54627421529603959f;
+        gx += a2 * (y * w[3] + z * w[6]) + 2.0f * c2 * x * w[7];
+        gy += a2 * (x * w[3] + z * w[4]) - 2.0f * c2 * y * w[7];
+        gz += a2 * (y * w[4] + x * w[6]) + 6.0f * b2 * z * w[5];
+    }
+    if constexpr (L >= 3) {
+        const float a3 = 0.59004358992664352f, b3 = 2.8906114426405538f, c3 = 0.45704579946446572f;
+        const float e3 = 0.37317633259011540f, h3 = 1.4453057213202769f;
+        const float q = 5.0f * z * z - 1.0f;
+        gx += 6.0f * a3 * x * y * w[8] + b3 * y * z * w[9] + c3 * q * w[12] +
+              2.0f * h3 * x * z * w[13] + 3.0f * a3 * (x * x - y * y) * w[14];
+        gy += 3.0f * a3 * (x * x - y * y) * w[8] + b3 * x * z * w[9] + c3 * q * w[10] -
+              2.0f * h3 * y * z * w[13] - 6.0f * a3 * x * y * w[14];
+        gz += b3 * x * y * w[9] + 10.0f * c3 * y * z * w[10] + e3 * (15.0f * z * z - 3.0f) * w[11] +
+              10.0f * c3 * x * z * w[12] + h3 * (x * x - y * y) * w[13];
+    }
+}
+
+__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
+
+// Rotation matrix of the unit quaternion (w, x, y, z), row-major.
+__device__ __forceinline__ void quat_rot(float w, float x, float y, float z, float *R)
+{
+    R[0] = 1.0f - 2.0f * (y * y + z * z); R[1] = 2.0f * (x * y - w * z); R[2] = 2.0f * (x * z + w * y);
+    R[3] = 2.0f * (x * y + w * z); R[4] = 1.0f - 2.0f * (x * x + z * z); R[5] = 2.0f * (y * z - w * x);
+    R[6] = 2.0f * (x * z - w * y); R[7] = 2.0f * (y * z + w * x); R[8] = 1.0f - 2.0f * (x * x + y * y);
+}
+
+// Geometry of one (view, Gaussian) pair: source-frame mean and covariance,
+// the Jacobian of the pinhole map at the mean, the projected covariance with
+// the low-pass dilation, its inverse (the conic) and the projected mean.
+struct Geom {
+    float xc, yc, zc, iz;
+    float Sc[6];                 // 00 01 02 11 12 22
+    float J00, J02, J11, J12;
+    float a, b, c;               // projected covariance 00 01 11
+    float A00, A01, A11;         // conic
+    float mux, muy;
+    uint32_t zbits;
+};
+
+// Source-frame depth of the mean as a chain of fused multiply-adds in the
+// order R20 x + (R21 y + (R22 z + t2)); it doubles as the sort key.
+__device__ __forceinline__ float depth_of(const ViewDev &V, float mx, float my, float mz)
+{
+    return __builtin_fmaf(V.R[6], mx, __builtin_fmaf(V.R[7], my, __builtin_fmaf(V.R[8], mz, V.t[2])));
+}
+
+__device__ __forceinline__ bool project_geom(const ViewDev &V, float mx, float my, float mz,
+                                             const float *cw, const RenderOpts &o, Geom &g)
+{
+    const float z = depth_of(V, mx, my, mz);
+    g.zbits = __float_as_uint(z);
+    if (!(z > o.z_near)) return false;
+    g.xc = V.R[0] * mx + V.R[1] * my + V.R[2] * mz + V.t[0];
+    g.yc = V.R[3] * mx + V.R[4] * my + V.R[5] * mz + V.t[1];
+    g.zc = z;
+    g.iz = 1.0f / z;
+    // T = R Sigma (Sigma symmetric: xx xy xz yy yz zz)
+    const float *R = V.R;
+    float T[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        T[3 * r + 0] = R[3 * r] * cw[0] + R[3 * r + 1] * cw[1] + R[3 * r + 2] * cw[2];
+        T[3 * r + 1] = R[3 * r] * cw[1] + R[3 * r + 1] * cw[3] + R[3 * r + 2] * cw[4];
+        T[3 * r + 2] = R[3 * r] * cw[2] + R[3 * r + 1] * cw[4] + R[3 * r + 2] * cw[5];
+    }
+    // Sigma_c = T R^T
+    g.Sc[0] = T[0] * R[0] + T[1] * R[1] + T[2] * R[2];
+    g.Sc[1] = T[0] * R[3] + T[1] * R[4] + T[2] * R[5];
+    g.Sc[2] = T[0] * R[6] + T[1] * R[7] + T[2] * R[8];
+    g.Sc[3] = T[3] * R[3] + T[4] * R[4] + T[5] * R[5];
+    g.Sc[4] = T[3] * R[6] + T[4] * R[7] + T[5] * R[8];
+    g.Sc[5] = T[6] * R[6] + T[7] * R[7] + T[8] * R[8];
+    const float f = V.f, iz = g.iz;
+    g.J00 = f * iz;
+    g.J11 = f * iz;
+    g.J02 = -f * g.xc * iz * iz;
+    g.J12 = -f * g.yc * iz * iz;
+    const float *S = g.Sc;
+    g.a = g.J00 * g.J00 * S[0] + 2.0f * g.J00 * g.J02 * S[2] + g.J02 * g.J02 * S[5] + o.dilation;
+    g.b = g.J00 * g.J11 * S[1] + g.J00 * g.J12 * S[2] + g.J02 * g.J11 * S[4] + g.J02 * g.J12 * S[5];
+    g.c = g.J11 * g.J11 * S[3] + 2.0f * g.J11 * g.J12 * S[4] + g.J12 * g.J12 * S[5] + o.dilation;
+    const float det = g.a * g.c - g.b * g.b;
+    if (!(det > 0.0f)) return false;
+    const float idet = 1.0f / det;
+    g.A00 = g.c * idet;
+    g.A01 = -g.b * idet;
+    g.A11 = g.a * idet;
+    g.mux = f * g.xc * iz + V.cx;
+    g.muy = f * g.yc * iz + V.cy;
+    return isfinite(g.mux) && isfinite(g.muy) && isfinite(g.A00) && isfinite(g.A11);
+}
+
+// ------------------------------------------------------------------ prepare
+
+template <int KMAX, int L>
+__global__ __launch_bounds__(kBlock) void prep_kernel(ModelDev m, GaussCache gc)
+{
+    constexpr int KL = L * (L + 2);
+    __shared__ float sb[KMAX];
+    __shared__ float sB[KL * KMAX];
+    const int k = m.k;
+    for (int q = threadIdx.x; q < KMAX; q += kBlock) sb[q] = q < k ? m.b_iso[q] : 0.0f;
+    for (int q = threadIdx.x; q < KL * KMAX; q += kBlock) {
+        const int r = q / KMAX, j = q % KMAX;
+        sB[q] = j < k ? m.B_dir[r * k + j] : 0.0f;
+    }
+    __syncthreads();
+    const int n = m.n;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    float qw = m.quat[i], qx = m.quat[n + i], qy = m.quat[2 * n + i], qz = m.quat[3 * n + i];
+    const float inv = 1.0f / sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+    qw *= inv; qx *= inv; qy *= inv; qz *= inv;
+    float Rq[9];
+    quat_rot(qw, qx, qy, qz, Rq);
+    float s2[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float s = expf(m.log_scale[a * n + i]);
+        s2[a] = s * s;
+    }
+    // Sigma = Rq diag(s^2) Rq^T
+    float cw[6];
+    cw[0] = Rq[0] * Rq[0] * s2[0] + Rq[1] * Rq[1] * s2[1] + Rq[2] * Rq[2] * s2[2];
+    cw[1] = Rq[0] * Rq[3] * s2[0] + Rq[1] * Rq[4] * s2[1] + Rq[2] * Rq[5] * s2[2];
+    cw[2] = Rq[0] * Rq[6] * s2[0] + Rq[1] * Rq[7] * s2[1] + Rq[2] * Rq[8] * s2[2];
+    cw[3] = Rq[3] * Rq[3] * s2[0] + Rq[4] * Rq[4] * s2[1] + Rq[5] * Rq[5] * s2[2];
+    cw[4] = Rq[3] * Rq[6] * s2[0] + Rq[4] * Rq[7] * s2[1] + Rq[5] * Rq[8] * s2[2];
+    cw[5] = Rq[6] * Rq[6] * s2[0] + Rq[7] * Rq[7] * s2[1] + Rq[8] * Rq[8] * s2[2];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) gc.cov[a * n + i] = cw[a];
+    gc.alpha[i] = sigmoidf(m.opacity_logit[i]);
+    float f[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) f[j] = j < k ? m.feat[(size_t)j * n + i] : 0.0f;
+    if (i < m.n_iso) {
+        float zl = 0.0f;
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) zl += sb[j] * f[j];
+        gc.ciso[i] = sigmoidf(zl);
+    } else {
+        const int nd = n - m.n_iso, id = i - m.n_iso;
+#pragma unroll
+        for (int r = 0; r < KL; ++r) {
+            float h = 0.0f;
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j) h += sB[r * KMAX + j] * f[j];
+            gc.hdir[(size_t)r * nd + id] = h;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ project
+
+template <int L>
+__global__ __launch_bounds__(kBlock) void project_kernel(ModelDev m, GaussCache gc, const ViewDev *views,
+                                                         RenderOpts o, ProjOut po)
+{
+    constexpr int KL = L * (L + 2);
+    const int n = m.n;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int v = blockIdx.y;
+    const ViewDev V = views[v];
+    const size_t vi = (size_t)v * n + i;
+    const float mx = m.mean[i], my = m.mean[n + i], mz = m.mean[2 * n + i];
+    float cw[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) cw[a] = gc.cov[a * n + i];
+    Geom g;
+    const bool ok = project_geom(V, mx, my, mz, cw, o, g);
+    if (!ok) {
+        po.zkey[vi] = 0xFFFFFFFFu;
+        po.sort_key[vi] = 0xFFFFFFFFu;
+        po.sort_val[vi] = (uint32_t)vi;
+        po.cnt[vi] = 0;
+        po.rect[vi] = make_uint2(0, 0);
+        po.rec[2 * vi] = make_float4(0.f, 0.f, 0.f, 0.f);
+        po.rec[2 * vi + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        return;
+    }
+    float c;
+    if (i < m.n_iso) {
+        c = gc.ciso[i];
+    } else {
+        const int nd = n - m.n_iso, id = i - m.n_iso;
+        float rx = mx - V.so[0], ry = my - V.so[1], rz = mz - V.so[2];
+        const float il = 1.0f / sqrtf(rx * rx + ry * ry + rz * rz);
+        float Y[KL];
+        sh_basis<L>(rx * il, ry * il, rz * il, Y);
+        float zl = 0.0f;
+#pragma unroll
+        for (int r = 0; r < KL; ++r) zl += Y[r] * gc.hdir[(size_t)r * nd + id];
+        c = sigmoidf(zl);
+    }
+    // conservative pixel box of the kappa ellipse: half-widths kappa sqrt(S00),
+    // kappa sqrt(S11), widened for float rounding of the per-pixel test
+    const float rxp = o.kappa * sqrtf(g.a) * 1.0005f + 0.01f;
+    const float ryp = o.kappa * sqrtf(g.c) * 1.0005f + 0.01f;
+    const float fu0 = fmaxf(ceilf(g.mux - rxp - 0.5f), 0.0f);
+    const float fu1 = fminf(floorf(g.mux + rxp - 0.5f), (float)(V.W - 1));
+    const float fv0 = fmaxf(ceilf(g.muy - ryp - 0.5f), 0.0f);
+    const float fv1 = fminf(floorf(g.muy + ryp - 0.5f), (float)(V.H - 1));
+    uint32_t count = 0;
+    uint2 rc = make_uint2(0, 0);
+    if (fu0 <= fu1 && fv0 <= fv1) {
+        const int tx0 = (int)fu0 / o.tile_w, tx1 = (int)fu1 / o.tile_w;
+        const int ty0 = (int)fv0 / o.tile_h, ty1 = (int)fv1 / o.tile_h;
+        count = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+        rc = make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16));
+    }
+    po.zkey[vi] = g.zbits;
+    po.sort_key[vi] = g.zbits;
+    po.sort_val[vi] = (uint32_t)vi;
+    po.cnt[vi] = count;
+    po.rect[vi] = rc;
+    po.rec[2 * vi] = make_float4(g.mux, g.muy, g.A00, g.A01);
+    po.rec[2 * vi + 1] = make_float4(g.A11, gc.alpha[i], c, 0.0f);
+}
+
+// ------------------------------------------------------------ backward chain
+
+template <int KMAX, int L>
+__global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
+{
+    constexpr int KL = L * (L + 2);
+    const int n = a.m.n, k = a.m.k;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = i < n;
+    const int ii = valid ? i : 0;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    const int n_waves = gridDim.x * (kBlock / kWave);
+    const bool is_dir = ii >= a.m.n_iso;
+    const int nd = n - a.m.n_iso, id = ii - a.m.n_iso;
+
+    const float mx = a.m.mean[ii], my = a.m.mean[n + ii], mz = a.m.mean[2 * n + ii];
+    float cw[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) cw[q] = a.gc.cov[q * n + ii];
+    float h[KL];
+#pragma unroll
+    for (int r = 0; r < KL; ++r) h[r] = is_dir ? a.gc.hdir[(size_t)r * nd + id] : 0.0f;
+    const float ciso = is_dir ? 0.0f : a.gc.ciso[ii];
+
+    float gmu[3] = {0.f, 0.f, 0.f};
+    float GSw[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float galpha = 0.0f, zsum = 0.0f;
+    float u[KL];
+#pragma unroll
+    for (int r = 0; r < KL; ++r) u[r] = 0.0f;
+
+    for (int v = 0; v < a.V; ++v) {
+        const ViewDev &V = a.views[v];
+        float pose[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        uint32_t c = 0, off = 0;
+        if (valid) {
+            c = a.cnt[(size_t)v * n + ii];
+            if (c > 0) {
+                off = a.offs[(size_t)v * n + ii];
+                // slots past the capacity do not exist (overflowed step)
+                if (off >= a.slot_cap) c = 0;
+                else if ((uint64_t)off + c > a.slot_cap) c = a.slot_cap - off;
+            }
+        }
+        float g7[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (uint32_t e = 0; e < c; ++e) {
+            const float4 s0 = a.slot[2 * ((size_t)off + e)];
+            const float4 s1 = a.slot[2 * ((size_t)off + e) + 1];
+            g7[0] += s0.x; g7[1] += s0.y; g7[2] += s0.z; g7[3] += s0.w;
+            g7[4] += s1.x; g7[5] += s1.y; g7[6] += s1.z;
+        }
+        Geom g;
+        if (c > 0 && project_geom(V, mx, my, mz, cw, a.o, g)) {
+            // conic = inverse of the projected covariance: dL/dS2 = -A Gbar A
+            const float gb00 = g7[2], gb01 = 0.5f * g7[3], gb11 = g7[4];
+            const float t00 = g.A00 * gb00 + g.A01 * gb01, t01 = g.A00 * gb01 + g.A01 * gb11;
+            const float t10 = g.A01 * gb00 + g.A11 * gb01, t11 = g.A01 * gb01 + g.A11 * gb11;
+            const float G00 = -(t00 * g.A00 + t01 * g.A01);
+            const float G01 = -(t00 * g.A01 + t01 * g.A11);
+            const float G11 = -(t10 * g.A01 + t11 * g.A11);
+            // S2 = J Sc J^T + dI
+            float GSc[6];
+            GSc[0] = g.J00 * g.J00 * G00;
+            GSc[1] = g.J00 * g.J11 * G01;
+            GSc[2] = g.J00 * (g.J02 * G00 + g.J12 * G01);
+            GSc[3] = g.J11 * g.J11 * G11;
+            GSc[4] = g.J11 * (g.J02 * G01 + g.J12 * G11);
+            GSc[5] = g.J02 * g.J02 * G00 + 2.0f * g.J02 * g.J12 * G01 + g.J12 * g.J12 * G11;
+            const float *S = g.Sc;
+            const float p0x = G00 * g.J00, p0y = G01 * g.J11, p0z = G00 * g.J02 + G01 * g.J12;
+            const float p1x = G01 * g.J00, p1y = G11 * g.J11, p1z = G01 * g.J02 + G11 * g.J12;
+            const float GJ00 = 2.0f * (p0x * S[0] + p0y * S[1] + p0z * S[2]);
+            const float GJ02 = 2.0f * (p0x * S[2] + p0y * S[4] + p0z * S[5]);
+            const float GJ11 = 2.0f * (p1x * S[1] + p1y * S[3] + p1z * S[4]);
+            const float GJ12 = 2.0f * (p1x * S[2] + p1y * S[4] + p1z * S[5]);
+            // source-frame mean through mu^ and J
+            const float f = V.f, fiz = f * g.iz, fz2 = fiz * g.iz;
+            const float gxc = g7[0] * fiz - GJ02 * fz2;
+            const float gyc = g7[1] * fiz - GJ12 * fz2;
+            const float gzc = -(g7[0] * g.xc + g7[1] * g.yc) * fz2 - (GJ00 + GJ11) * fz2 +
+                              2.0f * fz2 * g.iz * (GJ02 * g.xc + GJ12 * g.yc);
+            // pose tangent (source frame moved by Exp(w), rho)
+            const float *R = V.R;
+            const float rmx = R[0] * mx + R[1] * my + R[2] * mz;
+            const float rmy = R[3] * mx + R[4] * my + R[5] * mz;
+            const float rmz = R[6] * mx + R[7] * my + R[8] * mz;
+            pose[0] = gxc; pose[1] = gyc; pose[2] = gzc;
+            // N = Sc GSc; the covariance term of d/dw_k is 2 (N12-N21, N20-N02, N01-N10)
+            const float N01 = S[0] * GSc[1] + S[1] * GSc[3] + S[2] * GSc[4];
+            const float N02 = S[0] * GSc[2] + S[1] * GSc[4] + S[2] * GSc[5];
+            const float N10 = S[1] * GSc[0] + S[3] * GSc[1] + S[4] * GSc[2];
+            const float N12 = S[1] * GSc[2] + S[3] * GSc[4] + S[4] * GSc[5];
+            const float N20 = S[2] * GSc[0] + S[4] * GSc[1] + S[5] * GSc[2];
+            const float N21 = S[2] * GSc[1] + S[4] * GSc[3] + S[5] * GSc[4];
+            pose[3] = rmy * gzc - rmz * gyc + 2.0f * (N12 - N21);
+            pose[4] = rmz * gxc - rmx * gzc + 2.0f * (N20 - N02);
+            pose[5] = rmx * gyc - rmy * gxc + 2.0f * (N01 - N10);
+            // world frame
+            gmu[0] += R[0] * gxc + R[3] * gyc + R[6] * gzc;
+            gmu[1] += R[1] * gxc + R[4] * gyc + R[7] * gzc;
+            gmu[2] += R[2] * gxc + R[5] * gyc + R[8] * gzc;
+            // GSw = R^T GSc R
+            float Gf[9] = {GSc[0], GSc[1], GSc[2], GSc[1], GSc[3], GSc[4], GSc[2], GSc[4], GSc[5]};
+            float U[9];  // GSc R
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    U[3 * r + q] = Gf[3 * r] * R[q] + Gf[3 * r + 1] * R[3 + q] + Gf[3 * r + 2] * R[6 + q];
+            GSw[0] += R[0] * U[0] + R[3] * U[3] + R[6] * U[6];
+            GSw[1] += R[0] * U[1] + R[3] * U[4] + R[6] * U[7];
+            GSw[2] += R[0] * U[2] + R[3] * U[5] + R[6] * U[8];
+            GSw[3] += R[1] * U[1] + R[4] * U[4] + R[7] * U[7];
+            GSw[4] += R[1] * U[2] + R[4] * U[5] + R[7] * U[8];
+            GSw[5] += R[2] * U[2] + R[5] * U[5] + R[8] * U[8];
+            galpha += g7[5];
+            // radiosity
+            if (!is_dir) {
+                zsum += g7[6] * ciso * (1.0f - ciso);
+            } else {
+                const float rx = mx - V.so[0], ry = my - V.so[1], rz = mz - V.so[2];
+                const float il = 1.0f / sqrtf(rx * rx + ry * ry + rz * rz);
+                const float dx = rx * il, dy = ry * il, dz = rz * il;
+                float Y[KL];
+                sh_basis<L>(dx, dy, dz, Y);
+                float zl = 0.0f;
+#pragma unroll
+                for (int r = 0; r < KL; ++r) zl += Y[r] * h[r];
+                const float cd = 1.0f / (1.0f + expf(-zl));
+                const float gz = g7[6] * cd * (1.0f - cd);
+                float w[KL];
+#pragma unroll
+                for (int r = 0; r < KL; ++r) {
+                    u[r] += gz * Y[r];
+                    w[r] = gz * h[r];
+                }
+                float gdx, gdy, gdz;
+                sh_basis_grad<L>(dx, dy, dz, w, gdx, gdy, gdz);
+                const float dd = gdx * dx + gdy * dy + gdz * dz;
+                const float grx = (gdx - dx * dd) * il, gry = (gdy - dy * dd) * il, grz = (gdz - dz * dd) * il;
+                gmu[0] += grx; gmu[1] += gry; gmu[2] += grz;
+                pose[6] = R[0] * grx + R[1] * gry + R[2] * grz;
+                pose[7] = R[3] * grx + R[4] * gry + R[5] * grz;
+                pose[8] = R[6] * grx + R[7] * gry + R[8] * grz;
+            }
+        }
+        // per-wave pose partials (deterministic, reduced in FP64 later)
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const float r = wave_sum(pose[q]);
+            if (lane == 0) a.pose_part[((size_t)v * n_waves + wave) * 9 + q] = r;
+        }
+    }
+    if (!valid || !a.per_gaussian) return;
+
+    // Sigma = M M^T, M = Rq diag(s): dL/dM = 2 GSw M
+    float qw = a.m.quat[i], qx = a.m.quat[n + i], qy = a.m.quat[2 * n + i], qz = a.m.quat[3 * n + i];
+    const float qnorm = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+    const float iq = 1.0f / qnorm;
+    qw *= iq; qx *= iq; qy *= iq; qz *= iq;
+    float Rq[9];
+    quat_rot(qw, qx, qy, qz, Rq);
+    float s[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) s[q] = expf(a.m.log_scale[q * n + i]);
+    const float Gs[9] = {GSw[0], GSw[1], GSw[2], GSw[1], GSw[3], GSw[4], GSw[2], GSw[4], GSw[5]};
+    float GR[9];
+    float gls[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            // GM[r][b] = 2 sum_q Gs[r][q] M[q][b], M[q][b] = Rq[q][b] s[b]
+            const float gm = 2.0f * (Gs[3 * r] * Rq[b] + Gs[3 * r + 1] * Rq[3 + b] + Gs[3 * r + 2] * Rq[6 + b]) * s[b];
+            acc += gm * Rq[3 * r + b];
+            GR[3 * r + b] = gm * s[b];
+        }
+        gls[b] = acc * s[b];
+    }
+    float gq[4];
+    gq[0] = 2.0f * (-qz * GR[1] + qy * GR[2] + qz * GR[3] - qx * GR[5] - qy * GR[6] + qx * GR[7]);
+    gq[1] = 2.0f * (qy * GR[1] + qz * GR[2] + qy * GR[3] - qw * GR[5] + qz * GR[6] + qw * GR[7]) -
+            4.0f * qx * (GR[4] + GR[8]);
+    gq[2] = 2.0f * (qx * GR[1] + qw * GR[2] + qx * GR[3] + qz * GR[5] - qw * GR[6] + qz * GR[7]) -
+            4.0f * qy * (GR[0] + GR[8]);
+    gq[3] = 2.0f * (-qw * GR[1] + qx * GR[2] + qw * GR[3] + qy * GR[5] + qx * GR[6] + qy * GR[7]) -
+            4.0f * qz * (GR[0] + GR[4]);
+    const float dq = gq[0] * qw + gq[1] * qx + gq[2] * qy + gq[3] * qz;
+    const float qh[4] = {qw, qx, qy, qz};
+    if (a.dmean) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) a.dmean[q * n + i] = gmu[q];
+    }
+    if (a.dquat) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a.dquat[q * n + i] = (gq[q] - qh[q] * dq) * iq;
+    }
+    if (a.dlog_scale) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) a.dlog_scale[q * n + i] = gls[q];
+    }
+    if (a.dopacity) {
+        const float al = a.gc.alpha[i];
+        a.dopacity[i] = galpha * al * (1.0f - al);
+    }
+    if (a.dfeat) {
+        if (!is_dir) {
+            for (int j = 0; j < k; ++j) a.dfeat[(size_t)j * n + i] = zsum * a.m.b_iso[j];
+        } else {
+            for (int j = 0; j < k; ++j) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int r = 0; r < KL; ++r) acc += a.m.B_dir[r * k + j] * u[r];
+                a.dfeat[(size_t)j * n + i] = acc;
+            }
+        }
+    }
+    if (a.ubuf) {
+        if (!is_dir) {
+            a.ubuf[i] = zsum;
+        } else {
+#pragma unroll
+            for (int r = 0; r < KL; ++r) a.ubuf[(size_t)r * n + i] = u[r];
+        }
+    }
+}
+
+// d b_iso[j] = sum_{iso} zsum_i f_j,i ; d B_dir[r][j] = sum_{dir} u_r,i f_j,i.
+// A rank-n outer-product sum with a tiny output: bandwidth bound, so each
+// block stages 64 Gaussians of u and f in LDS and every thread owns output
+// components; per-block partials are summed in FP64 afterwards.
+constexpr int kBasisChunk = 1024;
+constexpr int kBasisSub = 64;
+
+template <int KMAX, int L>
+__global__ __launch_bounds__(kBlock) void basis_grad_kernel(ModelDev m, const float *ubuf, float *part)
+{
+    constexpr int KL = L * (L + 2);
+    constexpr int NOUT = KMAX + KL * KMAX;
+    constexpr int PER = (NOUT + kBlock - 1) / kBlock;
+    __shared__ float sf[KMAX][kBasisSub + 1];
+    __shared__ float su[KL][kBasisSub + 1];
+    const int n = m.n, k = m.k, n_iso = m.n_iso;
+    const int i0 = blockIdx.x * kBasisChunk;
+    float acc[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) acc[p] = 0.0f;
+    for (int c0 = i0; c0 < min(n, i0 + kBasisChunk); c0 += kBasisSub) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < KMAX * kBasisSub; q += kBlock) {
+            const int j = q / kBasisSub, c = q % kBasisSub, ig = c0 + c;
+            sf[j][c] = (j < k && ig < n) ? m.feat[(size_t)j * n + ig] : 0.0f;
+        }
+        for (int q = threadIdx.x; q < KL * kBasisSub; q += kBlock) {
+            const int r = q / kBasisSub, c = q % kBasisSub, ig = c0 + c;
+            float val = 0.0f;
+            if (ig < n) {
+                if (ig < n_iso) val = (r == 0) ? ubuf[ig] : 0.0f;
+                else val = ubuf[(size_t)r * n + ig];
+            }
+            su[r][c] = val;
+        }
+        __syncthreads();
+        const int cend = min(kBasisSub, n - c0);
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int o = threadIdx.x + p * kBlock;
+            if (o >= NOUT) continue;
+            if (o < KMAX) {
+                for (int c = 0; c < cend; ++c)
+                    if (c0 + c < n_iso) acc[p] += su[0][c] * sf[o][c];
+            } else {
+                const int r = (o - KMAX) / KMAX, j = (o - KMAX) % KMAX;
+                for (int c = 0; c < cend; ++c)
+                    if (c0 + c >= n_iso) acc[p] += su[r][c] * sf[j][c];
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int o = threadIdx.x + p * kBlock;
+        if (o < NOUT) part[(size_t)blockIdx.x * NOUT + o] = acc[p];
+    }
+}
+
+template <int KMAX, int L>
+__global__ __launch_bounds__(kBlock) void basis_final_kernel(int k, const float *part, int nblk, float *db,
+                                                             float *dB)
+{
+    constexpr int KL = L * (L + 2);
+    constexpr int NOUT = KMAX + KL * KMAX;
+    for (int o = threadIdx.x; o < NOUT; o += kBlock) {
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += (double)part[(size_t)b * NOUT + o];
+        if (o < KMAX) {
+            if (o < k && db) db[o] = (float)s;
+        } else {
+            const int r = (o - KMAX) / KMAX, j = (o - KMAX) % KMAX;
+            if (j < k && dB) dB[r * k + j] = (float)s;
+        }
+    }
+}
+
+// dpose[v] = (rho, omega) from the per-wave partials: rho = sum d mu_c +
+// sum R d r; omega = sum (R mu) x d mu_c + covariance term + t x sum d mu_c.
+__global__ __launch_bounds__(kBlock) void pose_final_kernel(const ViewDev *views, int n_waves,
+                                                            const float *part, float *dpose)
+{
+    const int v = blockIdx.x;
+    double s[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) s[q] = 0.0;
+    for (int w = threadIdx.x; w < n_waves; w += kBlock) {
+        const float *p = part + ((size_t)v * n_waves + w) * 9;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) s[q] += (double)p[q];
+    }
+    __shared__ double red[kBlock / kWave][9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        double x = s[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+        s[q] = x;
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0)
+#pragma unroll
+        for (int q = 0; q < 9; ++q) red[threadIdx.x / kWave][q] = s[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t9[9];
+        for (int q = 0; q < 9; ++q) {
+            double x = 0.0;
+            for (int w = 0; w < kBlock / kWave; ++w) x += red[w][q];
+            t9[q] = x;
+        }
+        const ViewDev &V = views[v];
+        const double tx = V.t[0], ty = V.t[1], tz = V.t[2];
+        float *o = dpose + 6 * v;
+        o[0] = (float)(t9[0] + t9[6]);
+        o[1] = (float)(t9[1] + t9[7]);
+        o[2] = (float)(t9[2] + t9[8]);
+        o[3] = (float)(t9[3] + ty * t9[2] - tz * t9[1]);
+        o[4] = (float)(t9[4] + tz * t9[0] - tx * t9[2]);
+        o[5] = (float)(t9[5] + tx * t9[1] - ty * t9[0]);
+    }
+}
+
+template <typename F>
+hipError_t dispatch_kl(int k, int L, F &&f)
+{
+    // feature sizes 8 and 16 get exact instances; anything else <= 32 runs in
+    // the 32-wide instance with the tail masked
+    auto byL = [&](auto kc) -> hipError_t {
+        constexpr int K = decltype(kc)::value;
+        switch (L) {
+        case 1: return f(std::integral_constant<int, K>{}, std::integral_constant<int, 1>{});
+        case 2: return f(std::integral_constant<int, K>{}, std::integral_constant<int, 2>{});
+        case 3: return f(std::integral_constant<int, K>{}, std::integral_constant<int, 3>{});
+        default: return hipErrorInvalidValue;
+        }
+    };
+    if (k == 8) return byL(std::integral_constant<int, 8>{});
+    if (k == 16) return byL(std::integral_constant<int, 16>{});
+    if (k >= 1 && k <= 32) return byL(std::integral_constant<int, 32>{});
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_prep(const ModelDev &m, const GaussCache &gc, hipStream_t s)
+{
+    if (m.n == 0) return hipSuccess;
+    return dispatch_kl(m.k, m.L, [&](auto K, auto L) {
+        constexpr int KK = decltype(K)::value, LL = decltype(L)::value;
+        prep_kernel<KK, LL><<<(m.n + kBlock - 1) / kBlock, kBlock, 0, s>>>(m, gc);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_project(const ModelDev &m, const GaussCache &gc, const ViewDev *views, int V,
+                          const RenderOpts &o, const ProjOut &po, hipStream_t s)
+{
+    if (m.n == 0 || V == 0) return hipSuccess;
+    dim3 grid((m.n + kBlock - 1) / kBlock, V);
+    switch (m.L) {
+    case 1: project_kernel<1><<<grid, kBlock, 0, s>>>(m, gc, views, o, po); break;
+    case 2: project_kernel<2><<<grid, kBlock, 0, s>>>(m, gc, views, o, po); break;
+    case 3: project_kernel<3><<<grid, kBlock, 0, s>>>(m, gc, views, o, po); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_project_bwd(const ProjBwdArgs &a, hipStream_t s)
+{
+    if (a.m.n == 0 || a.V == 0) return hipSuccess;
+    return dispatch_kl(a.m.k, a.m.L, [&](auto K, auto L) {
+        constexpr int KK = decltype(K)::value, LL = decltype(L)::value;
+        project_bwd_kernel<KK, LL><<<(a.m.n + kBlock - 1) / kBlock, kBlock, 0, s>>>(a);
+        return hipGetLastError();
+    });
+}
+
+int basis_grad_blocks(int n) { return (n + kBasisChunk - 1) / kBasisChunk; }
+
+hipError_t launch_basis_grad(const ModelDev &m, const float *ubuf, float *part, hipStream_t s)
+{
+    if (m.n == 0) return hipSuccess;
+    return dispatch_kl(m.k, m.L, [&](auto K, auto L) {
+        constexpr int KK = decltype(K)::value, LL = decltype(L)::value;
+        basis_grad_kernel<KK, LL><<<basis_grad_blocks(m.n), kBlock, 0, s>>>(m, ubuf, part);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_basis_final(const ModelDev &m, const float *part, int nblk, float *db, float *dB,
+                              hipStream_t s)
+{
+    return dispatch_kl(m.k, m.L, [&](auto K, auto L) {
+        constexpr int KK = decltype(K)::value, LL = decltype(L)::value;
+        basis_final_kernel<KK, LL><<<1, kBlock, 0, s>>>(m.k, part, nblk, db, dB);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_pose_final(const ViewDev *views, int V, int n_waves, const float *pose_part,
+                             float *dpose, hipStream_t s)
+{
+    if (V == 0) return hipSuccess;
+    pose_final_kernel<<<V, kBlock, 0, s>>>(views, n_waves, pose_part, dpose);
+    return hipGetLastError();
+}
+
+}  // namespace ddgs

@@ -1,0 +1,318 @@
+// raster.hip -- per-tile compositing of Eq. 1 on gfx950 and its backward.
+//
+// One workgroup owns one (view, tile); one lane owns one pixel (a 16x16 tile
+// is four wave64s).  The tile's depth-ordered list is walked in batches: each
+// lane stages one 32-byte Gaussian record into LDS, then every lane reads the
+// batch back as wave-wide broadcasts and composites front to back.  The
+// per-pair arithmetic is written with explicit round-to-nearest intrinsics so
+// that the forward and the backward (which recomputes the transmittance
+// instead of storing it) take bit-identical decisions and values.
+//
+// The backward walks the same list front to back, recomputing T_j and the
+// running sum; the tail S_j = sum_{m>j} c_m s_m T_m is the saved pixel value
+// minus the running sum.  Per-pair image-plane gradients are reduced over the
+// wave (cross-lane shuffles), over the four waves in LDS in a fixed order,
+// and written once per tile entry into a slot indexed by the entry's
+// emission position -- no float atomics, so results are run-to-run
+// deterministic.  The projection backward then sums each Gaussian's slots.
+#include "internal.h"
+
+namespace ddgs {
+
+namespace {
+
+struct PairState {
+    float T, C;
+};
+
+__device__ __forceinline__ float maha2(float dx, float dy, float A00, float A01, float A11)
+{
+    float t = __fmul_rn(__fmul_rn(A11, dy), dy);
+    t = __fmaf_rn(__fmul_rn(__fmul_rn(2.0f, A01), dx), dy, t);
+    return __fmaf_rn(__fmul_rn(A00, dx), dx, t);
+}
+
+__device__ __forceinline__ int view_of_tile(const ViewDev *views, int V, int tile)
+{
+    int lo = 0, hi = V - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_base <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int NT>
+__device__ __forceinline__ int next_item(const RasterArgs &a, int &iter, int *sh)
+{
+    if (!a.queue) {
+        const int t = iter == 0 ? (int)blockIdx.x : a.n_tiles;
+        ++iter;
+        return t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *sh = (int)atomicAdd(a.queue_counter, 1u);
+    __syncthreads();
+    const int it = *sh;
+    ++iter;
+    return it < a.n_tiles ? (int)a.queue[it] : a.n_tiles;
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
+{
+    constexpr int NT = TW * TH;
+    __shared__ float4 s0[NT];
+    __shared__ float4 s1[NT];
+    __shared__ int sh_item;
+    const int tid = threadIdx.x;
+    const float k2 = a.o.kappa2, smax = a.o.sigma_max, tmin = a.o.t_min;
+    int iter = 0;
+    for (;;) {
+        const int tile = next_item<NT>(a, iter, &sh_item);
+        if (tile >= a.n_tiles) break;
+        const int v = view_of_tile(a.views, a.V, tile);
+        const ViewDev &V = a.views[v];
+        const int lt = tile - V.tile_base;
+        const int ty = lt / V.ntx, tx = lt - ty * V.ntx;
+        const int px = tx * TW + tid % TW, py = ty * TH + tid / TW;
+        const bool inside = px < V.W && py < V.H;
+        const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+        const uint2 rg = a.ranges[tile];
+        const size_t vbase = (size_t)v * a.n;
+        float T = 1.0f, C = 0.0f;
+        uint32_t last = rg.x;
+        bool done = !inside;
+        for (uint32_t b0 = rg.x; b0 < rg.y; b0 += NT) {
+            __syncthreads();
+            const uint32_t j = b0 + tid;
+            if (j < rg.y) {
+                const uint32_t gid = min(a.tval[j], (uint32_t)a.n - 1u);
+                const size_t idx = vbase + gid;
+                s0[tid] = a.rec[2 * idx];
+                s1[tid] = a.rec[2 * idx + 1];
+            }
+            __syncthreads();
+            const int cnt = (int)min((uint32_t)NT, rg.y - b0);
+            for (int q = 0; q < cnt; ++q) {
+                const float4 r0 = s0[q];
+                const float4 r1 = s1[q];
+                const float dx = __fsub_rn(fpx, r0.x), dy = __fsub_rn(fpy, r0.y);
+                const float d2 = maha2(dx, dy, r0.z, r0.w, r1.x);
+                if (d2 <= k2 && !done) {
+                    const float G = __expf(__fmul_rn(-0.5f, d2));
+                    const float s = fminf(smax, __fmul_rn(r1.y, G));
+                    const float om = __fsub_rn(1.0f, s);
+                    if (tmin > 0.0f && __fmul_rn(T, om) < tmin) {
+                        done = true;
+                    } else {
+                        C = __fmaf_rn(__fmul_rn(r1.z, s), T, C);
+                        T = __fmul_rn(T, om);
+                        last = b0 + (uint32_t)q + 1u;
+                    }
+                }
+            }
+            if (tmin > 0.0f && __syncthreads_and(done)) break;
+        }
+        if (inside) {
+            const size_t p = (size_t)V.pix_base + (size_t)py * V.W + px;
+            a.img[p] = C;
+            a.img_saved[p] = C;
+            a.nlast[p] = last;
+        }
+    }
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
+{
+    constexpr int NT = TW * TH;
+    constexpr int NW = NT / kWave;
+    __shared__ float4 s0[NT];
+    __shared__ float4 s1[NT];
+    __shared__ uint32_t se[NT];
+    __shared__ float acc[NW][7][NT];
+    __shared__ uint32_t wmax[NW];
+    __shared__ int sh_item;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+    const float k2 = a.o.kappa2, smax = a.o.sigma_max, tmin = a.o.t_min;
+    int iter = 0;
+    for (;;) {
+        const int tile = next_item<NT>(a, iter, &sh_item);
+        if (tile >= a.n_tiles) break;
+        const int v = view_of_tile(a.views, a.V, tile);
+        const ViewDev &V = a.views[v];
+        const int lt = tile - V.tile_base;
+        const int ty = lt / V.ntx, tx = lt - ty * V.ntx;
+        const int px = tx * TW + tid % TW, py = ty * TH + tid / TW;
+        const bool inside = px < V.W && py < V.H;
+        const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+        const uint2 rg = a.ranges[tile];
+        const size_t vbase = (size_t)v * a.n;
+        float g = 0.0f, Cf = 0.0f;
+        uint32_t lastp = rg.x;
+        if (inside) {
+            const size_t p = (size_t)V.pix_base + (size_t)py * V.W + px;
+            g = a.dL_dimg[p];
+            Cf = a.img_saved[p];
+            lastp = a.nlast[p];
+        }
+        // end of the longest contributing prefix in the tile
+        uint32_t m = lastp;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, kWave));
+        __syncthreads();
+        if (lane == 0) wmax[w] = m;
+        __syncthreads();
+        uint32_t end = wmax[0];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) end = max(end, wmax[q]);
+
+        float T = 1.0f, Cacc = 0.0f;
+        bool done = !inside;
+        for (uint32_t b0 = rg.x; b0 < rg.y; b0 += NT) {
+            const int cnt = (int)min((uint32_t)NT, rg.y - b0);
+            __syncthreads();
+            const uint32_t j = b0 + tid;
+            if (j < rg.y) {
+                const uint32_t gid = min(a.tval[j], (uint32_t)a.n - 1u);
+                const size_t idx = vbase + gid;
+                s0[tid] = a.rec[2 * idx];
+                s1[tid] = a.rec[2 * idx + 1];
+                const uint2 rc = a.rect[idx];
+                const int tx0 = rc.x & 0xFFFF, ty0 = rc.x >> 16, tx1 = rc.y & 0xFFFF;
+                se[tid] = a.offs[idx] + (uint32_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
+            }
+            __syncthreads();
+            if (b0 < end) {
+                for (int q = 0; q < cnt; ++q) {
+                    const float4 r0 = s0[q];
+                    const float4 r1 = s1[q];
+                    const float dx = __fsub_rn(fpx, r0.x), dy = __fsub_rn(fpy, r0.y);
+                    const float d2 = maha2(dx, dy, r0.z, r0.w, r1.x);
+                    float gv[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                    const bool hit = d2 <= k2 && !done && (b0 + (uint32_t)q) < lastp;
+                    if (hit) {
+                        const float G = __expf(__fmul_rn(-0.5f, d2));
+                        const float sraw = __fmul_rn(r1.y, G);
+                        const float s = fminf(smax, sraw);
+                        const float om = __fsub_rn(1.0f, s);
+                        if (tmin > 0.0f && __fmul_rn(T, om) < tmin) {
+                            done = true;
+                        } else {
+                            const float c = r1.z;
+                            Cacc = __fmaf_rn(__fmul_rn(c, s), T, Cacc);
+                            const float S = Cf - Cacc;
+                            const float ds = g * (c * T - S / om);
+                            gv[6] = g * s * T;
+                            if (!(sraw > smax)) {
+                                gv[5] = ds * G;
+                                const float dd2 = -0.5f * G * r1.y * ds;
+                                gv[0] = -2.0f * dd2 * (r0.z * dx + r0.w * dy);
+                                gv[1] = -2.0f * dd2 * (r0.w * dx + r1.x * dy);
+                                gv[2] = dd2 * dx * dx;
+                                gv[3] = 2.0f * dd2 * dx * dy;
+                                gv[4] = dd2 * dy * dy;
+                            }
+                            T = __fmul_rn(T, om);
+                        }
+                    }
+                    if (__ballot(hit) != 0ull) {
+#pragma unroll
+                        for (int c = 0; c < 7; ++c) gv[c] = wave_sum(gv[c]);
+                    }
+                    if (lane == 0) {
+#pragma unroll
+                        for (int c = 0; c < 7; ++c) acc[w][c][q] = gv[c];
+                    }
+                }
+            }
+            __syncthreads();
+            if (tid < cnt) {
+                float r[7];
+                if (b0 < end) {
+#pragma unroll
+                    for (int c = 0; c < 7; ++c) {
+                        float x = acc[0][c][tid];
+#pragma unroll
+                        for (int q = 1; q < NW; ++q) x += acc[q][c][tid];
+                        r[c] = x;
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 7; ++c) r[c] = 0.0f;
+                }
+                const size_t e = se[tid];
+                if (e < a.slot_cap) {
+                    a.slot[2 * e] = make_float4(r[0], r[1], r[2], r[3]);
+                    a.slot[2 * e + 1] = make_float4(r[4], r[5], r[6], 0.0f);
+                }
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void tile_cost_kernel(const uint2 *ranges, int n_tiles, uint32_t *keys,
+                                                        uint32_t *vals, uint32_t *counter)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t == 0) *counter = 0;
+    if (t >= n_tiles) return;
+    const uint2 r = ranges[t];
+    const uint32_t len = min(r.y - r.x, 0xFFFFFFu);
+    keys[t] = 0xFFFFFFu - len;  // ascending sort -> longest first
+    vals[t] = (uint32_t)t;
+}
+
+template <int TW, int TH>
+hipError_t fwd_inst(const RasterArgs &a, int pb, hipStream_t s)
+{
+    const int grid = a.queue ? pb : a.n_tiles;
+    if (grid > 0) raster_fwd_kernel<TW, TH><<<grid, TW * TH, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template <int TW, int TH>
+hipError_t bwd_inst(const RasterArgs &a, int pb, hipStream_t s)
+{
+    const int grid = a.queue ? pb : a.n_tiles;
+    if (grid > 0) raster_bwd_kernel<TW, TH><<<grid, TW * TH, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool raster_tile_supported(int tw, int th)
+{
+    return (tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 16 && th == 8) || (tw == 32 && th == 8);
+}
+
+hipError_t launch_raster_fwd(const RasterArgs &a, int pb, hipStream_t s)
+{
+    const int tw = a.o.tile_w, th = a.o.tile_h;
+    if (tw == 16 && th == 16) return fwd_inst<16, 16>(a, pb, s);
+    if (tw == 8 && th == 8) return fwd_inst<8, 8>(a, pb, s);
+    if (tw == 16 && th == 8) return fwd_inst<16, 8>(a, pb, s);
+    if (tw == 32 && th == 8) return fwd_inst<32, 8>(a, pb, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_raster_bwd(const RasterArgs &a, int pb, hipStream_t s)
+{
+    const int tw = a.o.tile_w, th = a.o.tile_h;
+    if (tw == 16 && th == 16) return bwd_inst<16, 16>(a, pb, s);
+    if (tw == 8 && th == 8) return bwd_inst<8, 8>(a, pb, s);
+    if (tw == 16 && th == 8) return bwd_inst<16, 8>(a, pb, s);
+    if (tw == 32 && th == 8) return bwd_inst<32, 8>(a, pb, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_tile_cost_keys(const uint2 *ranges, int n_tiles, uint32_t *keys, uint32_t *vals,
+                                 uint32_t *counter, hipStream_t s)
+{
+    tile_cost_kernel<<<(n_tiles + 255) / 256 + (n_tiles == 0), 256, 0, s>>>(ranges, n_tiles, keys, vals, counter);
+    return hipGetLastError();
+}
+
+}  // namespace ddgs

@@ -1,0 +1,403 @@
+// sort.hip -- tile binning of the projected footprints on gfx950: exclusive
+// scan of the per-(view, Gaussian) tile counts, emission of one
+// (tile, Gaussian) entry per touched tile, a stable LSD radix sort of
+// (key, value) u32 pairs, and the per-tile [start, end) ranges.
+//
+// Ordering scheme.  The tile lists must be ordered by (tile, depth, index)
+// (Eq. 1 composites front to back; ties by Gaussian index).  Instead of one
+// 64-bit (tile | depth) sort over all entries, the (view, Gaussian) pairs are
+// first sorted by their 32-bit depth key (stable, input in index order), the
+// entries are then emitted in that depth order, and a stable sort on the
+// tile id alone (1-2 passes) groups them by tile without disturbing the
+// depth order inside a tile.  The result is identical to the 64-bit sort and
+// moves far fewer bytes, since the depth pass runs over V*n pairs instead of
+// the several-times larger entry count.
+#include "internal.h"
+
+namespace ddgs {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kScanIPT = kScanTile / kBlock;  // 16
+constexpr int kRadixIPT = 8;
+constexpr int kRadixTile = kBlock * kRadixIPT;  // 2048
+constexpr int kWaves = kBlock / kWave;
+
+// exclusive scan over a block of 256 threads; returns the block total
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *lds /* >= 4 */, uint32_t &total)
+{
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const uint32_t inc = wave_incl_scan(x);
+    if (lane == kWave - 1) lds[w] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    total = 0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) {
+        const uint32_t t = lds[q];
+        if (q < w) before += t;
+        total += t;
+    }
+    __syncthreads();
+    return before + inc - x;
+}
+
+__global__ __launch_bounds__(kBlock) void scan_reduce_kernel(const uint32_t *in, const uint32_t *gather,
+                                                             int64_t n, uint64_t *blocksum)
+{
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    uint64_t s = 0;
+#pragma unroll 4
+    for (int q = 0; q < kScanIPT; ++q) {
+        const int64_t idx = base + q * kBlock + threadIdx.x;
+        if (idx < n) s += in[gather ? gather[idx] : idx];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
+    __shared__ uint64_t red[kWaves];
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int q = 0; q < kWaves; ++q) t += red[q];
+        blocksum[blockIdx.x] = t;
+    }
+}
+
+// single block: exclusive scan of the block sums with a running carry
+__global__ __launch_bounds__(1024) void scan_top_kernel(uint64_t *blocksum, int64_t nb, uint64_t *total)
+{
+    __shared__ uint64_t wt[16];
+    __shared__ uint64_t carry_s;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < nb; c0 += 1024) {
+        const int64_t idx = c0 + threadIdx.x;
+        const uint64_t x = idx < nb ? blocksum[idx] : 0;
+        uint64_t inc = x;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint64_t y = __shfl_up(inc, o, kWave);
+            if (lane >= o) inc += y;
+        }
+        if (lane == kWave - 1) wt[w] = inc;
+        __syncthreads();
+        uint64_t before = carry_s, tot = 0;
+        for (int q = 0; q < 16; ++q) {
+            if (q < w) before += wt[q];
+            tot += wt[q];
+        }
+        if (idx < nb) blocksum[idx] = before + inc - x;
+        __syncthreads();
+        if (threadIdx.x == 0) carry_s += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && total) *total = carry_s;
+}
+
+__global__ __launch_bounds__(kBlock) void scan_apply_kernel(const uint32_t *in, const uint32_t *gather, int64_t n,
+                                                            const uint64_t *blockoff, uint32_t *out)
+{
+    __shared__ uint32_t tile[kScanTile];
+    __shared__ uint32_t wl[kWaves];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+#pragma unroll 4
+    for (int q = 0; q < kScanIPT; ++q) {
+        const int64_t idx = base + q * kBlock + threadIdx.x;
+        tile[q * kBlock + threadIdx.x] = idx < n ? in[gather ? gather[idx] : idx] : 0u;
+    }
+    __syncthreads();
+    uint32_t v[kScanIPT], s = 0;
+#pragma unroll
+    for (int q = 0; q < kScanIPT; ++q) {
+        v[q] = tile[threadIdx.x * kScanIPT + q];
+        s += v[q];
+    }
+    uint32_t tot;
+    uint32_t pre = block_excl_scan(s, wl, tot);
+#pragma unroll
+    for (int q = 0; q < kScanIPT; ++q) {
+        tile[threadIdx.x * kScanIPT + q] = pre;
+        pre += v[q];
+    }
+    __syncthreads();
+    const uint32_t off = (uint32_t)blockoff[blockIdx.x];
+#pragma unroll 4
+    for (int q = 0; q < kScanIPT; ++q) {
+        const int64_t idx = base + q * kBlock + threadIdx.x;
+        if (idx < n) out[idx] = off + tile[q * kBlock + threadIdx.x];
+    }
+}
+
+// ------------------------------------------------------------- radix sort
+
+__device__ __forceinline__ int64_t runtime_n(int64_t n_cap, const uint32_t *n_dev)
+{
+    if (!n_dev) return n_cap;
+    const int64_t m = (int64_t)*n_dev;
+    return m < n_cap ? m : n_cap;
+}
+
+__global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t *kin, int64_t n_cap, const uint32_t *n_dev,
+                                                            int shift, uint32_t mask, uint32_t *counts, int nblocks)
+{
+    __shared__ uint32_t h[kWaves][256];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+    for (int q = 0; q < 256 / kWave; ++q) h[w][lane + q * kWave] = 0;
+    __syncthreads();
+    const int64_t n = runtime_n(n_cap, n_dev);
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile + w * (kRadixTile / kWaves);
+#pragma unroll
+    for (int r = 0; r < kRadixIPT; ++r) {
+        const int64_t idx = base + r * kWave + lane;
+        if (idx < n) atomicAdd(&h[w][(kin[idx] >> shift) & mask], 1u);
+    }
+    __syncthreads();
+    const int d = threadIdx.x;
+    counts[(size_t)d * nblocks + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+}
+
+// Stable scatter: every wave ranks its 8 rounds of 64 consecutive keys with
+// ballots (lanes sharing the digit), the block combines the 4 wave
+// histograms, the keys are staged in LDS in digit order and written out
+// with consecutive lanes on consecutive addresses.
+__global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *kin, const uint32_t *vin,
+                                                               uint32_t *kout, uint32_t *vout, int64_t n_cap,
+                                                               const uint32_t *n_dev, int shift, int nbits,
+                                                               const uint32_t *offsets, int nblocks)
+{
+    __shared__ uint32_t wh[kWaves][256];
+    __shared__ uint32_t bstart[256];
+    __shared__ uint32_t gbase[256];
+    __shared__ uint32_t sk[kRadixTile];
+    __shared__ uint32_t sv[kRadixTile];
+    __shared__ uint32_t wl[kWaves];
+    const int64_t n = runtime_n(n_cap, n_dev);
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    if (base >= n) return;  // uniform over the block
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const uint32_t mask = (1u << nbits) - 1u;
+#pragma unroll
+    for (int q = 0; q < 256 / kWave; ++q) wh[w][lane + q * kWave] = 0;
+    __syncthreads();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    uint32_t key[kRadixIPT], val[kRadixIPT], rank[kRadixIPT];
+    const int64_t wbase = base + w * (kRadixTile / kWaves);
+#pragma unroll
+    for (int r = 0; r < kRadixIPT; ++r) {
+        const int64_t idx = wbase + r * kWave + lane;
+        const bool ok = idx < n;
+        key[r] = ok ? kin[idx] : 0u;
+        val[r] = ok ? vin[idx] : 0u;
+        const uint32_t d = (key[r] >> shift) & mask;
+        uint64_t peers = __ballot(ok);
+        for (int b = 0; b < nbits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bal = __ballot(bit);
+            peers &= bit ? bal : ~bal;
+        }
+        const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
+        uint32_t prev = 0;
+        if (ok) prev = wh[w][d];
+        __builtin_amdgcn_wave_barrier();
+        if (ok && below == 0) wh[w][d] = prev + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+        rank[r] = prev + below;
+    }
+    __syncthreads();
+    {
+        const int d = threadIdx.x;
+        const uint32_t c0 = wh[0][d], c1 = wh[1][d], c2 = wh[2][d], c3 = wh[3][d];
+        wh[0][d] = 0;
+        wh[1][d] = c0;
+        wh[2][d] = c0 + c1;
+        wh[3][d] = c0 + c1 + c2;
+        uint32_t tot;
+        bstart[d] = block_excl_scan(c0 + c1 + c2 + c3, wl, tot);
+        gbase[d] = offsets[(size_t)d * nblocks + blockIdx.x];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRadixIPT; ++r) {
+        const int64_t idx = wbase + r * kWave + lane;
+        if (idx < n) {
+            const uint32_t d = (key[r] >> shift) & mask;
+            const uint32_t pos = bstart[d] + wh[w][d] + rank[r];
+            sk[pos] = key[r];
+            sv[pos] = val[r];
+        }
+    }
+    __syncthreads();
+    const int cnt = (int)min((int64_t)kRadixTile, n - base);
+    for (int j = threadIdx.x; j < cnt; j += kBlock) {
+        const uint32_t kk = sk[j];
+        const uint32_t d = (kk >> shift) & mask;
+        const uint32_t o = gbase[d] + (uint32_t)j - bstart[d];
+        kout[o] = kk;
+        vout[o] = sv[j];
+    }
+}
+
+// ------------------------------------------------------------------ emit
+
+// One thread per (view, Gaussian) in depth order: writes the Gaussian's tile
+// entries at its scanned offset, row-major over its tile rectangle.
+__global__ __launch_bounds__(kBlock) void emit_kernel(int64_t VN, int n, const uint32_t *order,
+                                                      const uint32_t *off_sorted, const uint32_t *cnt,
+                                                      const uint2 *rect, const ViewDev *views, uint32_t *offs,
+                                                      uint32_t *tkey, uint32_t *tval, uint32_t capacity,
+                                                      const uint64_t *total, uint32_t *m_out, uint32_t *flags)
+{
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (r == 0) {
+        const uint64_t t = *total;
+        const bool over = t > (uint64_t)capacity;
+        *m_out = over ? capacity : (uint32_t)t;
+        if (over) atomicOr(flags, 1u);
+    }
+    if (r >= VN) return;
+    const uint32_t vi = order[r];
+    const uint32_t c = cnt[vi];
+    if (c == 0) return;
+    const uint32_t off = off_sorted[r];
+    offs[vi] = off;
+    if (off >= capacity) return;
+    // entries past the capacity are dropped (the overflow flag is set above);
+    // the ones that fit are written so that no stale entry survives
+    const uint32_t e_end = (uint64_t)off + c > (uint64_t)capacity ? capacity : off + c;
+    const uint32_t v = vi / (uint32_t)n, i = vi - v * (uint32_t)n;
+    const ViewDev &V = views[v];
+    const uint2 rc = rect[vi];
+    const int tx0 = rc.x & 0xFFFF, ty0 = rc.x >> 16, tx1 = rc.y & 0xFFFF, ty1 = rc.y >> 16;
+    uint32_t e = off;
+    for (int ty = ty0; ty <= ty1 && e < e_end; ++ty) {
+        const uint32_t row = (uint32_t)V.tile_base + (uint32_t)ty * (uint32_t)V.ntx;
+        for (int tx = tx0; tx <= tx1 && e < e_end; ++tx, ++e) {
+            tkey[e] = row + (uint32_t)tx;
+            tval[e] = i;
+        }
+    }
+}
+
+__global__ void zero_u64_kernel(uint64_t *p) { *p = 0; }
+
+__global__ __launch_bounds__(kBlock) void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void copy_u32_kernel(uint32_t *dst, const uint32_t *src, const uint32_t *n_dev,
+                                                          int64_t n_cap)
+{
+    const int64_t n = runtime_n(n_cap, n_dev);
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(kBlock) void ranges_kernel(const uint32_t *keys, const uint32_t *m_dev, int64_t m_cap,
+                                                        uint2 *ranges, int n_tiles)
+{
+    const int64_t m = runtime_n(m_cap, m_dev);
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < m; j += (int64_t)gridDim.x * kBlock) {
+        const uint32_t k = keys[j];
+        if (k >= (uint32_t)n_tiles) continue;
+        if (j == 0 || keys[j - 1] != k) ranges[k].x = (uint32_t)j;
+        if (j == m - 1 || keys[j + 1] != k) ranges[k].y = (uint32_t)(j + 1);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void zero_ranges_kernel(uint2 *ranges, int n_tiles)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n_tiles) ranges[i] = make_uint2(0, 0);
+}
+
+int64_t blocks_for(int64_t n, int64_t per) { return (n + per - 1) / per; }
+
+}  // namespace
+
+size_t scan_tmp_bytes(int64_t n) { return (size_t)(blocks_for(n, kScanTile) + 1) * sizeof(uint64_t); }
+
+hipError_t launch_exclusive_scan(const uint32_t *in, const uint32_t *gather, uint32_t *out, int64_t n, void *tmp,
+                                 uint64_t *total, hipStream_t s)
+{
+    uint64_t *bs = (uint64_t *)tmp;
+    const int64_t nb = blocks_for(n, kScanTile);
+    if (n == 0) return total ? launch_zero_u64(total, s) : hipSuccess;
+    scan_reduce_kernel<<<(unsigned)nb, kBlock, 0, s>>>(in, gather, n, bs);
+    scan_top_kernel<<<1, 1024, 0, s>>>(bs, nb, total);
+    scan_apply_kernel<<<(unsigned)nb, kBlock, 0, s>>>(in, gather, n, bs, out);
+    return hipGetLastError();
+}
+
+size_t radix_counts_words(int64_t n_cap) { return (size_t)256 * (size_t)std::max<int64_t>(1, blocks_for(n_cap, kRadixTile)); }
+
+hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n_cap,
+                            const uint32_t *n_dev, int bits, uint32_t *counts, void *scan_tmp, uint64_t *scan_total,
+                            bool *in_k1, hipStream_t s)
+{
+    *in_k1 = false;
+    if (n_cap <= 0 || bits <= 0) return hipSuccess;
+    const int nblocks = (int)blocks_for(n_cap, kRadixTile);
+    uint32_t *ka = k0, *va = v0, *kb = k1, *vb = v1;
+    for (int shift = 0; shift < bits; shift += 8) {
+        const int nbits = std::min(8, bits - shift);
+        const uint32_t mask = (1u << nbits) - 1u;
+        radix_hist_kernel<<<nblocks, kBlock, 0, s>>>(ka, n_cap, n_dev, shift, mask, counts, nblocks);
+        hipError_t e = launch_exclusive_scan(counts, nullptr, counts, (int64_t)256 * nblocks, scan_tmp, scan_total, s);
+        if (e != hipSuccess) return e;
+        radix_scatter_kernel<<<nblocks, kBlock, 0, s>>>(ka, va, kb, vb, n_cap, n_dev, shift, nbits, counts, nblocks);
+        std::swap(ka, kb);
+        std::swap(va, vb);
+        *in_k1 = !*in_k1;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(int64_t VN, int n, const uint32_t *order, const uint32_t *off_sorted, const uint32_t *cnt,
+                       const uint2 *rect, const ViewDev *views, uint32_t *offs, uint32_t *tkey, uint32_t *tval,
+                       uint32_t capacity, const uint64_t *total, uint32_t *m_out, uint32_t *flags, hipStream_t s)
+{
+    const int64_t nb = std::max<int64_t>(1, blocks_for(VN, kBlock));
+    emit_kernel<<<(unsigned)nb, kBlock, 0, s>>>(VN, n, order, off_sorted, cnt, rect, views, offs, tkey, tval,
+                                                capacity, total, m_out, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_ranges(const uint32_t *keys, const uint32_t *m_dev, int64_t m_cap, uint2 *ranges, int n_tiles,
+                         hipStream_t s)
+{
+    if (n_tiles > 0) zero_ranges_kernel<<<(unsigned)blocks_for(n_tiles, kBlock), kBlock, 0, s>>>(ranges, n_tiles);
+    if (m_cap > 0) {
+        const int64_t nb = std::min<int64_t>(blocks_for(m_cap, kBlock), 65536);
+        ranges_kernel<<<(unsigned)nb, kBlock, 0, s>>>(keys, m_dev, m_cap, ranges, n_tiles);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(uint64_t *p, hipStream_t s)
+{
+    zero_u64_kernel<<<1, 1, 0, s>>>(p);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    fill_u32_kernel<<<(unsigned)blocks_for(n, kBlock), kBlock, 0, s>>>(p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, const uint32_t *n_dev, int64_t n_cap, hipStream_t s)
+{
+    if (n_cap <= 0) return hipSuccess;
+    const int64_t nb = std::min<int64_t>(blocks_for(n_cap, kBlock), 65536);
+    copy_u32_kernel<<<(unsigned)nb, kBlock, 0, s>>>(dst, src, n_dev, n_cap);
+    return hipGetLastError();
+}
+
+}  // namespace ddgs

@@ -239,16 +239,19 @@ OPACITY_SCALE = {"C2": 0.2, "C3": 0.055, "C4": 0.07, "C5": 0.03}
 CONFIG_NAMES = ("C1", "C2", "C3", "C4", "C5")
 
 
-def config(name, scale=1.0):
-    """Configurations of the measured workloads.  ``scale`` < 1 shrinks
-    Gaussian count, phantom and detector together for quick tests while
-    keeping the geometry (pitch is enlarged so the field of view is kept)."""
+def config(name, scale=1.0, det_scale=None):
+    """Configurations of the measured workloads.  ``scale`` < 1 shrinks the
+    Gaussian count and the phantom for quick tests; the detector shrinks by
+    ``det_scale`` (default sqrt(scale)) with the pitch enlarged so that the
+    field of view is kept."""
+    if det_scale is None:
+        det_scale = scale ** 0.5
     seed = 1000 + CONFIG_NAMES.index(name) + 1
     ss = np.random.SeedSequence(seed)
     r_pose = np.random.default_rng(ss.spawn(1)[0])
 
     def det(px):
-        return max(8, int(round(px * scale)))
+        return max(8, int(round(px * det_scale)))
 
     if name == "C1":
         n = max(16, int(round(2000 * scale)))

@@ -1,0 +1,261 @@
+"""GPU parity of the binning path and the forward render against the FP64
+oracle and plain library routines (numpy stable sort, cumulative sum)."""
+import numpy as np
+import pytest
+
+from gpu_common import expected_tile_lists, make_renderer, rel_l2, small_scene
+from oracle import ref
+from paper_2406_02518_amd import binding, synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    r = make_renderer()
+    yield r
+    r.close()
+
+
+# ------------------------------------------------------------- sort and scan
+
+@pytest.mark.parametrize("n,bits,kind", [(1, 8, "rand"), (2047, 8, "rand"), (2049, 13, "rand"),
+                                         (100_000, 32, "rand"), (1_000_003, 24, "rand"), (70_000, 16, "equal"),
+                                         (50_000, 32, "reverse"), (4096, 1, "rand"), (300_001, 11, "few")])
+def test_radix_sort_is_stable_and_bit_exact(R, n, bits, kind):
+    rng = np.random.default_rng(n + bits)
+    if kind == "rand":
+        keys = rng.integers(0, 1 << bits, size=n, dtype=np.uint64).astype(np.uint32)
+    elif kind == "equal":
+        keys = np.full(n, 7, dtype=np.uint32)
+    elif kind == "reverse":
+        keys = (np.arange(n, dtype=np.uint64)[::-1] * 977).astype(np.uint32)
+    else:
+        keys = rng.integers(0, 3, size=n).astype(np.uint32) << (bits - 2)
+    vals = np.arange(n, dtype=np.uint32)
+    kd = torch.from_numpy(keys.view(np.int32)).cuda()
+    vd = torch.from_numpy(vals.view(np.int32)).cuda()
+    binding.ddgs_debug_sort_pairs(R.ctx, kd.data_ptr(), vd.data_ptr(), n, bits)
+    order = np.argsort(keys & np.uint32((1 << bits) - 1 if bits < 32 else 0xFFFFFFFF), kind="stable")
+    np.testing.assert_array_equal(kd.cpu().numpy().view(np.uint32), keys[order])
+    np.testing.assert_array_equal(vd.cpu().numpy().view(np.uint32), vals[order])
+
+
+@pytest.mark.parametrize("n", [0, 1, 4095, 4097, 1_000_000])
+def test_exclusive_scan(R, n):
+    x = np.random.default_rng(n).integers(0, 40, size=n).astype(np.uint32)
+    xd = torch.from_numpy(x.view(np.int32)).cuda()
+    yd = torch.zeros(max(n, 1), dtype=torch.int32, device="cuda")
+    total = binding.ddgs_debug_exclusive_scan(R.ctx, xd.data_ptr(), yd.data_ptr(), n)
+    assert total == int(x.astype(np.uint64).sum())
+    if n:
+        exp = np.concatenate([[0], np.cumsum(x.astype(np.uint64))[:-1]]).astype(np.uint32)
+        np.testing.assert_array_equal(yd.cpu().numpy().view(np.uint32)[:n], exp)
+
+
+# ------------------------------------------------------------ projection
+
+def _records(R, V, n):
+    rec = R.debug(binding.DBG_RECORDS, np.float32, V * n * 8).reshape(V, n, 8)
+    zk = R.debug(binding.DBG_DEPTH_KEYS, np.uint32, V * n).reshape(V, n)
+    cnt = R.debug(binding.DBG_COUNTS, np.uint32, V * n).reshape(V, n)
+    rects = R.debug(binding.DBG_RECTS, np.uint16, V * n * 4).reshape(V, n, 4)
+    return rec, zk, cnt, rects
+
+
+@pytest.mark.parametrize("cfg", ["C1", "C2s"])
+def test_projection_records_match_oracle(R, cfg):
+    if cfg == "C1":
+        c = synth.config("C1")
+    else:
+        c = synth.config("C2", scale=0.05)
+    R.set_scene(c.scene)
+    R.set_views(c.views)
+    R.render()
+    n = c.scene.n
+    rec, zk, cnt, rects = _records(R, len(c.views), n)
+    for v, view in enumerate(c.views):
+        P = ref.project(c.scene, view)
+        valid = P[:, 0] > 0
+        np.testing.assert_array_equal(zk[v], np.where(valid, P[:, 8].astype(np.float32).view(np.uint32),
+                                                      np.uint32(0xFFFFFFFF)))
+        gv = rec[v, valid]
+        np.testing.assert_allclose(gv[:, 0], P[valid, 1], atol=2e-3, rtol=0)
+        np.testing.assert_allclose(gv[:, 1], P[valid, 2], atol=2e-3, rtol=0)
+        for col, pc in ((2, 3), (3, 4), (4, 5)):
+            scale = np.maximum(np.abs(P[valid, 3]), np.abs(P[valid, 5]))
+            assert np.max(np.abs(gv[:, col] - P[valid, pc]) / scale) < 1e-4
+        np.testing.assert_allclose(gv[:, 5], P[valid, 6], rtol=2e-6)
+        np.testing.assert_allclose(gv[:, 6], P[valid, 7], rtol=2e-5, atol=1e-7)
+        # tile rectangles cover every pixel inside the cut-off ellipse
+        tw = th = 16
+        for i in np.flatnonzero(valid):
+            rx, ry = 3.0 * np.sqrt(P[i, 9]), 3.0 * np.sqrt(P[i, 11])
+            u0, u1 = np.ceil(P[i, 1] - rx - 0.5), np.floor(P[i, 1] + rx - 0.5)
+            v0, v1 = np.ceil(P[i, 2] - ry - 0.5), np.floor(P[i, 2] + ry - 0.5)
+            u0, u1 = max(u0, 0), min(u1, view.W - 1)
+            v0, v1 = max(v0, 0), min(v1, view.H - 1)
+            if u0 > u1 or v0 > v1:
+                continue
+            assert cnt[v, i] > 0
+            tx0, ty0, tx1, ty1 = rects[v, i]
+            assert tx0 <= u0 // tw and tx1 >= u1 // tw and ty0 <= v0 // th and ty1 >= v1 // th
+            assert cnt[v, i] == (tx1 - tx0 + 1) * (ty1 - ty0 + 1)
+
+
+def test_tile_lists_bit_exact(R):
+    c = synth.config("C2", scale=0.05)
+    views = [c.views[0], synth.view(100, 60, 1.2, 1000.0, 600.0, 40.0)]
+    R.set_scene(c.scene)
+    R.set_views(views)
+    binding.ddgs_debug_keep_unsorted(R.ctx, 1)
+    try:
+        R.render()
+        M = R.num_rendered()
+        uk = R.debug(binding.DBG_TILE_KEYS_UNSORTED, np.uint32, M)
+        uv = R.debug(binding.DBG_TILE_VALS_UNSORTED, np.uint32, M)
+        sk = R.debug(binding.DBG_TILE_KEYS, np.uint32, M)
+        sv = R.debug(binding.DBG_TILE_VALS, np.uint32, M)
+        base = R.debug(binding.DBG_TILE_BASE, np.int32, len(views) + 1)
+        ranges = R.debug(binding.DBG_RANGES, np.uint32, int(base[-1]) * 2).reshape(-1, 2)
+    finally:
+        binding.ddgs_debug_keep_unsorted(R.ctx, 0)
+    s = np.argsort(uk, kind="stable")
+    np.testing.assert_array_equal(sk, uk[s])
+    np.testing.assert_array_equal(sv, uv[s])
+    # same lists from the per-(view, Gaussian) keys and rectangles on the host
+    n = c.scene.n
+    _, zk, cnt, rects = _records(R, len(views), n)
+    ntx = [(v.W + 15) // 16 for v in views]
+    ek, ev = expected_tile_lists(zk.ravel(), cnt.ravel(), rects.reshape(-1, 4), base, ntx, n)
+    np.testing.assert_array_equal(sk, ek)
+    np.testing.assert_array_equal(sv, ev)
+    # ranges by a linear scan
+    exp = np.zeros_like(ranges)
+    for j, t in enumerate(sk):
+        if j == 0 or sk[j - 1] != t:
+            exp[t, 0] = j
+        exp[t, 1] = j + 1
+    np.testing.assert_array_equal(ranges, exp)
+    # depth keys equal the oracle's
+    for v, view in enumerate(views):
+        P = ref.project(c.scene, view)
+        np.testing.assert_array_equal(zk[v][P[:, 0] > 0], P[P[:, 0] > 0, 8].astype(np.float32).view(np.uint32))
+
+
+# ---------------------------------------------------------------- forward
+
+@pytest.mark.parametrize("cfg,scale", [("C1", 1.0), ("C2", 1.0), ("C3", 0.03), ("C4", 0.03), ("C5", 0.02)])
+def test_forward_matches_oracle(R, cfg, scale):
+    c = synth.config(cfg, scale=scale)
+    views = c.views[:3] if cfg in ("C3", "C4") else c.views
+    if cfg == "C5":
+        views = c.views[:6]
+    R.set_scene(c.scene)
+    R.set_views(views)
+    img = R.render().cpu().numpy()
+    exp = ref.render(c.scene, views)
+    base = 0
+    for v, e in zip(views, exp):
+        P = v.W * v.H
+        err = rel_l2(img[base:base + P], e)
+        assert err < 1e-4, (cfg, err)
+        base += P
+
+
+def test_forward_sampled_pixels_full_size_c3(R):
+    c = synth.config("C3")
+    views = [c.views[0], c.views[9]]
+    R.set_scene(c.scene)
+    R.set_views(views)
+    img = R.render().cpu().numpy()
+    rng = np.random.default_rng(0)
+    pix = []
+    for vi, v in enumerate(views):
+        uu = rng.integers(0, v.W, 300)
+        vv = rng.integers(int(0.3 * v.H), int(0.7 * v.H), 300)
+        pix.append(np.stack([np.full(300, vi), uu, vv], 1))
+    pix = np.concatenate(pix).astype(np.int32)
+    exp = ref.render_pixels(c.scene, views, pix)
+    got = img[pix[:, 0] * views[0].W * views[0].H + pix[:, 2] * views[0].W + pix[:, 1]]
+    assert rel_l2(got, exp) < 1e-4
+    assert np.abs(got - exp).max() < 1e-3 * max(1.0, np.abs(exp).max())
+
+
+def test_forward_is_tile_and_schedule_invariant(R):
+    c = synth.config("C2", scale=0.05)
+    views = [synth.view(90, 70, 1.3, 1000.0, 600.0, 20.0), synth.view(37, 53, 2.0, 1000.0, 550.0, 200.0)]
+    R.set_scene(c.scene)
+    R.set_views(views)
+    ref_img = None
+    try:
+        for tw, th in ((16, 16), (8, 8), (16, 8), (32, 8)):
+            for pe in (0, 1):
+                R.set_options(tile_w=tw, tile_h=th, persistent=pe)
+                img = R.render().cpu().numpy()
+                if ref_img is None:
+                    ref_img = img
+                np.testing.assert_array_equal(img, ref_img)
+    finally:
+        R.set_options(tile_w=16, tile_h=16, persistent=0)
+
+
+def test_batched_views_equal_single_views(R):
+    c = synth.config("C4", scale=0.05)
+    views = c.views[:5]
+    R.set_scene(c.scene)
+    R.set_views(views)
+    batch = R.render().cpu().numpy()
+    base = 0
+    for v in views:
+        R.set_views([v])
+        one = R.render().cpu().numpy()
+        np.testing.assert_array_equal(batch[base:base + one.size], one)
+        base += one.size
+
+
+def test_edge_cases(R):
+    sc = small_scene(n=50)
+    # an empty model renders zeros
+    empty = sc.subset([], [])
+    R.set_scene(empty)
+    R.set_views([synth.view(20, 20, 1.0, 1000.0, 600.0, 0.0)])
+    assert np.all(R.render().cpu().numpy() == 0)
+    # a 1x1 detector and a ragged one
+    R.set_scene(sc)
+    for W, H in ((1, 1), (17, 33), (5, 200)):
+        v = synth.view(W, H, 40.0 / max(W, H), 1000.0, 600.0, 10.0)
+        R.set_views([v])
+        img = R.render().cpu().numpy()
+        assert rel_l2(img, ref.render(sc, [v])[0]) < 1e-4 or np.abs(img).max() < 1e-6
+    # everything behind the source: culled
+    v = synth.view(20, 20, 1.0, 1000.0, 600.0, 0.0)
+    behind = sc.copy()
+    behind.mean = (behind.mean + np.array([[800.0], [0.0], [0.0]], dtype=np.float32)).astype(np.float32)
+    R.set_scene(behind)
+    R.set_views([v])
+    assert np.all(R.render().cpu().numpy() == 0)
+    # a huge Gaussian over the whole detector plus small ones
+    big = sc.copy()
+    big.log_scale[:, 0] = np.log(60.0)
+    R.set_scene(big)
+    img = R.render().cpu().numpy()
+    assert rel_l2(img, ref.render(big, [v])[0]) < 1e-4
+
+
+def test_early_termination_matches_oracle(R):
+    c = synth.config("C2", scale=0.05)
+    v = c.views[0]
+    R.set_scene(c.scene)
+    R.set_views([v])
+    try:
+        R.set_options(t_min=0.3)
+        img = R.render().cpu().numpy()
+    finally:
+        R.set_options(t_min=0.0)
+    exp = ref.render(c.scene, [v], opts=dict(t_min=0.3))[0]
+    assert rel_l2(img, exp) < 1e-4

@@ -1,0 +1,68 @@
+"""Host-side checks of libddgs.so that need no GPU: the library loads, it
+exports every entry point that include/ddgs.h declares, and its pure host
+functions behave (no compute call is made here)."""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+from paper_2406_02518_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ddgs.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2406_02518_amd import build
+        build.build()
+    return binding.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ddgs_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    assert len(names) >= 20
+    assert set(names) == set(binding.EXPORTED)
+
+
+def test_every_declared_symbol_is_exported(L):
+    cdll = ctypes.CDLL(binding.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(cdll, n)]
+    assert not missing, missing
+
+
+def test_param_count_matches_paper(L):
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "param_count.json")))
+    per, shared = binding.ddgs_param_count(g["k"], g["L"], g["n"])
+    assert (per, shared) == (g["per_gaussian"], g["shared"])
+    assert per * g["n"] + shared == g["total"]
+    assert binding.ddgs_param_count(16, 3, 1) == (27, 16 + 15 * 16)
+    with pytest.raises(binding.DDGSError):
+        binding.ddgs_param_count(0, 1, 1)
+
+
+def test_status_strings_and_default_options(L):
+    assert binding.status_name(binding.OK) == "ok"
+    assert "capacity" in binding.status_name(binding.ERR_CAPACITY)
+    o = binding.ddgs_default_options()
+    assert (o.tile_w, o.tile_h) == (16, 16)
+    assert o.kappa == pytest.approx(3.0) and o.dilation == pytest.approx(0.3)
+    assert o.sigma_max == pytest.approx(0.99) and o.t_min == 0.0 and o.z_near == pytest.approx(1.0)
+    assert ctypes.sizeof(binding.ddgs_view) == 64
+    assert ctypes.sizeof(binding.ddgs_options) == 40
+
+
+def test_product_path_refuses_to_run_without_the_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(binding, "_LIB", None)
+    monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        binding.lib()
