@@ -99,8 +99,18 @@ typedef struct {
     float t_min;                 /* 0: early stop when T(1-s) < t_min (off)  */
     float z_near;                /* 1 mm: depth at or below which a Gaussian is culled */
     float sigma_max;             /* 0.99: clamp of s                          */
-    int32_t persistent;          /* 0: one workgroup per tile; 1: persistent
-                                    workgroups over a longest-first queue     */
+    int32_t persistent;          /* 0: one workgroup per work item; 1:
+                                    persistent workgroups taking work items
+                                    from a counter (longest tiles first when
+                                    split is 0)                               */
+    int32_t split;               /* 256: entries per work item -- a tile's
+                                    depth-ordered list is cut into chunks of
+                                    this many entries, composited in parallel
+                                    and merged exactly with the over operator
+                                    (images then differ from split 0 only by
+                                    rounding); 0: one work item per tile (the
+                                    image is bit-identical for every tile
+                                    shape).  Forced to 0 when t_min > 0.      */
     int64_t capacity;            /* tile-entry capacity of a captured step;
                                     0 = chosen by ddgs_step_capture          */
 } ddgs_options;
@@ -228,6 +238,13 @@ ddgs_status ddgs_debug_sort_pairs(ddgs_ctx *ctx, uint32_t *keys, uint32_t *vals,
  * 64-bit sum (host).  Exposes the scan that places the tile entries. */
 ddgs_status ddgs_debug_exclusive_scan(ddgs_ctx *ctx, const uint32_t *in, uint32_t *out, int64_t n,
                                       uint64_t *total);
+
+/* Pair statistics of the forward raster: once enabled, every render counts
+ * the (pixel, tile entry) pairs it evaluated and the pairs that contributed
+ * to Eq. 1 (inside the cut-off radius, before any early stop).  The counts
+ * of the last render are returned by ddgs_debug_pair_counts. */
+ddgs_status ddgs_debug_count_pairs(ddgs_ctx *ctx, int enable);
+ddgs_status ddgs_debug_pair_counts(ddgs_ctx *ctx, int64_t *evaluated, int64_t *contributing);
 
 /* Accumulated device time of the last render/backward/step per stage, ms
  * (filled when timing is enabled with ddgs_enable_timing). */

@@ -27,8 +27,8 @@ EXPORTED = (
     "ddgs_default_options", "ddgs_set_options", "ddgs_get_options", "ddgs_set_model", "ddgs_set_views",
     "ddgs_image_size", "ddgs_render", "ddgs_backward", "ddgs_loss", "ddgs_step_capture", "ddgs_step_launch",
     "ddgs_check", "ddgs_autotune", "ddgs_param_count", "ddgs_num_rendered", "ddgs_debug_copy",
-    "ddgs_debug_keep_unsorted", "ddgs_debug_sort_pairs", "ddgs_debug_exclusive_scan", "ddgs_enable_timing",
-    "ddgs_stage_times")
+    "ddgs_debug_keep_unsorted", "ddgs_debug_sort_pairs", "ddgs_debug_exclusive_scan", "ddgs_debug_count_pairs",
+    "ddgs_debug_pair_counts", "ddgs_enable_timing", "ddgs_stage_times")
 
 
 class ddgs_model(C.Structure):
@@ -46,7 +46,7 @@ class ddgs_view(C.Structure):
 class ddgs_options(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("kappa", C.c_float), ("dilation", C.c_float),
                 ("t_min", C.c_float), ("z_near", C.c_float), ("sigma_max", C.c_float),
-                ("persistent", C.c_int32), ("capacity", C.c_int64)]
+                ("persistent", C.c_int32), ("split", C.c_int32), ("capacity", C.c_int64)]
 
 
 class ddgs_grads(C.Structure):
@@ -97,6 +97,8 @@ def lib():
             "ddgs_debug_keep_unsorted": ([vp, C.c_int], st),
             "ddgs_debug_sort_pairs": ([vp, vp, vp, i64, C.c_int], st),
             "ddgs_debug_exclusive_scan": ([vp, vp, vp, i64, C.POINTER(C.c_uint64)], st),
+            "ddgs_debug_count_pairs": ([vp, C.c_int], st),
+            "ddgs_debug_pair_counts": ([vp, C.POINTER(i64), C.POINTER(i64)], st),
             "ddgs_enable_timing": ([vp, C.c_int], st),
             "ddgs_stage_times": ([vp, C.POINTER(C.c_float)], st),
         }
@@ -236,6 +238,16 @@ def ddgs_debug_exclusive_scan(ctx, in_ptr, out_ptr, n):
     return t.value
 
 
+def ddgs_debug_count_pairs(ctx, enable):
+    _check(lib().ddgs_debug_count_pairs(ctx, int(bool(enable))), ctx)
+
+
+def ddgs_debug_pair_counts(ctx):
+    e, c = C.c_int64(), C.c_int64()
+    _check(lib().ddgs_debug_pair_counts(ctx, C.byref(e), C.byref(c)), ctx)
+    return e.value, c.value
+
+
 def ddgs_enable_timing(ctx, enable):
     _check(lib().ddgs_enable_timing(ctx, int(bool(enable))), ctx)
 
@@ -341,10 +353,28 @@ class Renderer:
         return out
 
     # compute
+    # Work runs on self.stream.  It first waits for torch's current stream
+    # (where the inputs were produced), and the current stream then waits for
+    # it, so results are ordered for any later torch work.
+    def _begin(self):
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+        return cur
+
+    def _end(self, cur, *outs):
+        if cur != self.stream:
+            for t in outs:
+                if t is not None:
+                    t.record_stream(self.stream)
+            cur.wait_stream(self.stream)
+
     def render(self, out=None):
+        cur = self._begin()
         if out is None:
             out = self.torch.empty(self.image_size(), device=self.device, dtype=self.torch.float32)
         ddgs_render(self.ctx, out.data_ptr())
+        self._end(cur, out)
         return out
 
     def alloc_grads(self, which=GRAD_NAMES):
@@ -363,17 +393,21 @@ class Renderer:
         return g
 
     def backward(self, dl, grads=None, which=GRAD_NAMES):
+        cur = self._begin()
         if grads is None:
             grads = self.alloc_grads(which)
         dl = dl.contiguous()
         ddgs_backward(self.ctx, dl.data_ptr(), self.grads_struct(grads))
+        self._end(cur, dl, *grads.values())
         return grads
 
     def loss(self, kind, images, target, lam=0.2, want_grad=True):
+        cur = self._begin()
         loss = self.torch.empty(len(self.views), device=self.device, dtype=self.torch.float32)
         dl = self.torch.empty_like(images) if want_grad else None
         ddgs_loss(self.ctx, kind, images.data_ptr(), target.data_ptr(), lam, loss.data_ptr(),
                   dl.data_ptr() if dl is not None else 0)
+        self._end(cur, loss, dl, images, target)
         return loss, dl
 
     def num_rendered(self):

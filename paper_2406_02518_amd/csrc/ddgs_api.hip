@@ -63,11 +63,19 @@ struct ddgs_ctx {
     uint32_t *queue = nullptr;
     int64_t entry_cap = 0;     // capacity of the entry buffers
     bool keep_unsorted = false;
+    bool count_pairs = false;
 
     // captured step
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     int64_t step_cap = 0;
+    int max_items = 0;         // work items the raster grids are sized for
+
+    // pinned staging of the view table uploads
+    void *stage_host = nullptr;
+    size_t stage_bytes = 0;
+    hipEvent_t stage_event = nullptr;
+    bool stage_pending = false;
 
     // timing: a start and an end event per stage
     bool timing = false;
@@ -224,11 +232,28 @@ ddgs_status prepare_views(ddgs_ctx *c)
     int32_t *lb;
     DDGS_TRY(ensure_t(c, "views", std::max(1, V), &vd));
     DDGS_TRY(ensure_t(c, "loss_tile_base", V + 1, &lb));
-    if (V > 0) HIP_TRY(c, hipMemcpyAsync(vd, c->vdev_h.data(), sizeof(ViewDev) * V, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(lb, c->loss_tile_base_h.data(), sizeof(int32_t) * (V + 1), hipMemcpyHostToDevice,
+    // stage through pinned host memory so the copies stay asynchronous; the
+    // staging area is reused only after the previous upload has completed
+    const size_t need = sizeof(ViewDev) * V + sizeof(int32_t) * (V + 1);
+    if (c->stage_pending) {
+        HIP_TRY(c, hipEventSynchronize(c->stage_event));
+        c->stage_pending = false;
+    }
+    if (c->stage_bytes < need) {
+        if (c->stage_host) HIP_TRY(c, hipHostFree(c->stage_host));
+        c->stage_host = nullptr;
+        c->stage_bytes = 0;
+        HIP_TRY(c, hipHostMalloc(&c->stage_host, need + 1024, hipHostMallocDefault));
+        c->stage_bytes = need + 1024;
+    }
+    char *h = (char *)c->stage_host;
+    std::memcpy(h, c->vdev_h.data(), sizeof(ViewDev) * V);
+    std::memcpy(h + sizeof(ViewDev) * V, c->loss_tile_base_h.data(), sizeof(int32_t) * (V + 1));
+    if (V > 0) HIP_TRY(c, hipMemcpyAsync(vd, h, sizeof(ViewDev) * V, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(lb, h + sizeof(ViewDev) * V, sizeof(int32_t) * (V + 1), hipMemcpyHostToDevice,
                               c->stream));
-    // host vectors must outlive the async copies
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipEventRecord(c->stage_event, c->stream));
+    c->stage_pending = true;
     c->views_dirty = false;
     return DDGS_OK;
 }
@@ -251,7 +276,7 @@ ddgs_status ensure_static(ddgs_ctx *c)
     DDGS_TRY(ensure_t(c, "alpha", n, &f));
     DDGS_TRY(ensure_t(c, "ciso", n, &f));
     DDGS_TRY(ensure_t(c, "hdir", (size_t)KL * std::max<int64_t>(1, n - c->model.n_iso), &f));
-    DDGS_TRY(ensure_t(c, "ubuf", (size_t)KL * n, &f));
+    DDGS_TRY(ensure_t(c, "ubuf", (size_t)16 * n, &f));
     float4 *f4;
     DDGS_TRY(ensure_t(c, "rec", 2 * VN, &f4));
     uint2 *u2;
@@ -268,11 +293,21 @@ ddgs_status ensure_static(ddgs_ctx *c)
     DDGS_TRY(ensure_t(c, "scalars", 16, &u));
     const int64_t n_waves = ((n + 255) / 256) * 4;
     DDGS_TRY(ensure_t(c, "pose_part", (size_t)std::max<int64_t>(1, V * n_waves * 9), &f));
-    DDGS_TRY(ensure_t(c, "basis_part", (size_t)basis_grad_blocks((int)std::max<int64_t>(1, n)) * (32 + 15 * 32), &f));
+    DDGS_TRY(ensure_t(c, "basis_part", basis_part_floats((int)std::max<int64_t>(1, n)), &f));
     double *d;
     DDGS_TRY(ensure_t(c, "loss_part", loss_part_doubles((int)V, c->max_view_pix, c->loss_tiles), &d));
     DDGS_TRY(ensure_t(c, "loss_maps", (size_t)3 * c->total_pix, &f));
     return DDGS_OK;
+}
+
+// Chunked work items are exact for Eq. 1 without early termination; with
+// t_min > 0 each tile is walked by one workgroup.
+int effective_split(const ddgs_ctx *c) { return c->opt.t_min > 0.0f ? 0 : std::max(0, (int)c->opt.split); }
+
+int64_t max_items_for(const ddgs_ctx *c, int64_t cap)
+{
+    const int split = effective_split(c);
+    return split > 0 ? cap / split + c->n_tiles + 1 : c->n_tiles;
 }
 
 // Entry-level buffers (tile entries) and the radix / scan temporaries.
@@ -290,6 +325,15 @@ ddgs_status ensure_entries(ddgs_ctx *c, int64_t cap)
         DDGS_TRY(ensure_t(c, "ukey", cap, &u));
         DDGS_TRY(ensure_t(c, "uval", cap, &u));
     }
+    // work items of the chunked raster and their per-pixel (C, T) partials
+    const int split = effective_split(c);
+    const int64_t max_items = split > 0 ? cap / split + c->n_tiles + 1 : 1;
+    uint2 *u2;
+    float2 *f2;
+    DDGS_TRY(ensure_t(c, "items", max_items, &u2));
+    DDGS_TRY(ensure_t(c, "item_cnt", std::max(1, c->n_tiles), &u));
+    DDGS_TRY(ensure_t(c, "item_base", std::max(1, c->n_tiles), &u));
+    DDGS_TRY(ensure_t(c, "part", (size_t)(split > 0 ? max_items : 1) * c->opt.tile_w * c->opt.tile_h, &f2));
     const int64_t big = std::max<int64_t>({VN, cap, (int64_t)c->n_tiles, 1});
     const size_t cw = radix_counts_words(big);
     DDGS_TRY(ensure_t(c, "radix_counts", cw, &u));
@@ -319,6 +363,21 @@ uint32_t *mdev_ptr(ddgs_ctx *c) { return buf<uint32_t>(c, "scalars") + 2; }
 uint32_t *flags_ptr(ddgs_ctx *c) { return buf<uint32_t>(c, "scalars") + 3; }
 uint32_t *counter_ptr(ddgs_ctx *c) { return buf<uint32_t>(c, "scalars") + 4; }
 uint64_t *sort_total_ptr(ddgs_ctx *c) { return (uint64_t *)(buf<uint32_t>(c, "scalars") + 8); }
+uint32_t *n_items_ptr(ddgs_ctx *c) { return buf<uint32_t>(c, "scalars") + 6; }
+
+// Work-item fields shared by the forward and backward raster launches.
+void set_items(ddgs_ctx *c, RasterArgs &ra, bool backward)
+{
+    ra.split = effective_split(c);
+    ra.items = buf<uint2>(c, "items");
+    ra.n_items = n_items_ptr(c);
+    ra.max_items = c->max_items;
+    ra.item_base = buf<uint32_t>(c, "item_base");
+    ra.item_cnt = buf<uint32_t>(c, "item_cnt");
+    ra.part = buf<float2>(c, "part");
+    ra.queue = c->queue;
+    ra.queue_counter = c->opt.persistent ? counter_ptr(c) + (backward ? 1 : 0) : nullptr;
+}
 
 // Projection, depth sort and scan of the tile counts (stages shared by the
 // plain and the captured paths).
@@ -375,7 +434,13 @@ ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, int64_t sort_n, float *images
     c->tval_sorted = in_k1 ? buf<uint32_t>(c, "tval2") : tval;
     HIP_TRY(c, launch_ranges(c->tkey_sorted, mdev_ptr(c), sort_n, buf<uint2>(c, "ranges"), c->n_tiles, s));
     c->queue = nullptr;
-    if (c->opt.persistent) {
+    const int split = effective_split(c);
+    c->max_items = (int)max_items_for(c, cap);
+    if (split > 0) {
+        HIP_TRY(c, launch_items(buf<uint2>(c, "ranges"), c->n_tiles, split, buf<uint32_t>(c, "item_cnt"),
+                                buf<uint32_t>(c, "item_base"), buf<uint2>(c, "items"), (uint32_t)c->max_items,
+                                buf<void>(c, "scan_tmp"), sort_total_ptr(c), n_items_ptr(c), counter_ptr(c), s));
+    } else if (c->opt.persistent) {
         bool qk1 = false;
         HIP_TRY(c, launch_tile_cost_keys(buf<uint2>(c, "ranges"), c->n_tiles, buf<uint32_t>(c, "qkey"),
                                          buf<uint32_t>(c, "qval"), counter_ptr(c), s));
@@ -396,11 +461,15 @@ ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, int64_t sort_n, float *images
     ra.tval = c->tval_sorted;
     ra.rec = buf<float4>(c, "rec");
     ra.n_tiles = c->n_tiles;
-    ra.queue = c->queue;
-    ra.queue_counter = counter_ptr(c);
+    set_items(c, ra, false);
     ra.img = images;
     ra.img_saved = buf<float>(c, "img_saved");
     ra.nlast = buf<uint32_t>(c, "nlast");
+    ra.pair_counts = nullptr;
+    if (c->count_pairs) {
+        ra.pair_counts = (unsigned long long *)(buf<uint32_t>(c, "scalars") + 12);
+        HIP_TRY(c, launch_fill_u32(buf<uint32_t>(c, "scalars") + 12, 0u, 4, s));
+    }
     HIP_TRY(c, launch_raster_fwd(ra, c->num_cu * 8, s));
     stage_end(c, DDGS_T_RASTER_FWD);
     return DDGS_OK;
@@ -425,8 +494,7 @@ ddgs_status enqueue_backward(ddgs_ctx *c, const float *dL, const ddgs_grads *g, 
     ra.tval = c->tval_sorted;
     ra.rec = buf<float4>(c, "rec");
     ra.n_tiles = c->n_tiles;
-    ra.queue = c->queue;
-    ra.queue_counter = counter_ptr(c) + 1;
+    set_items(c, ra, true);
     ra.img_saved = buf<float>(c, "img_saved");
     ra.nlast = buf<uint32_t>(c, "nlast");
     ra.dL_dimg = dL;
@@ -435,7 +503,7 @@ ddgs_status enqueue_backward(ddgs_ctx *c, const float *dL, const ddgs_grads *g, 
     ra.slot = buf<float4>(c, "slot");
     ra.slot_cap = (uint32_t)std::min<int64_t>(slot_cap, 0xFFFFFFFFll);
     stage_begin(c, DDGS_T_RASTER_BWD);
-    if (c->queue) HIP_TRY(c, launch_fill_u32(counter_ptr(c) + 1, 0u, 1, s));
+    if (c->opt.persistent) HIP_TRY(c, launch_fill_u32(counter_ptr(c) + 1, 0u, 1, s));
     HIP_TRY(c, launch_raster_bwd(ra, c->num_cu * 4, s));
     stage_end(c, DDGS_T_RASTER_BWD);
     stage_begin(c, DDGS_T_PROJECT_BWD);
@@ -462,7 +530,7 @@ ddgs_status enqueue_backward(ddgs_ctx *c, const float *dL, const ddgs_grads *g, 
     HIP_TRY(c, launch_project_bwd(pa, s));
     if (g->db_iso || g->dB_dir) {
         HIP_TRY(c, launch_basis_grad(pa.m, pa.ubuf, buf<float>(c, "basis_part"), s));
-        HIP_TRY(c, launch_basis_final(pa.m, buf<float>(c, "basis_part"), basis_grad_blocks(n), g->db_iso, g->dB_dir, s));
+        HIP_TRY(c, launch_basis_final(pa.m, buf<float>(c, "basis_part"), g->db_iso, g->dB_dir, s));
     }
     if (g->dpose) {
         const int n_waves = ((n + 255) / 256) * 4;
@@ -513,6 +581,8 @@ ddgs_status validate_options(ddgs_ctx *c, const ddgs_options &o)
     if (!(o.z_near > 0.0f) || !std::isfinite(o.z_near)) return fail(c, DDGS_ERR_INVALID_ARG, "z_near must be > 0");
     if (!(o.sigma_max > 0.0f) || !(o.sigma_max < 1.0f)) return fail(c, DDGS_ERR_INVALID_ARG, "sigma_max must be in (0, 1)");
     if (o.capacity < 0 || o.capacity > 0xFFFFFFFFll) return fail(c, DDGS_ERR_INVALID_ARG, "capacity out of range");
+    if (o.split < 0 || o.split > (1 << 24)) return fail(c, DDGS_ERR_INVALID_ARG, "split must be in 0..2^24");
+    if (o.persistent != 0 && o.persistent != 1) return fail(c, DDGS_ERR_INVALID_ARG, "persistent must be 0 or 1");
     return DDGS_OK;
 }
 
@@ -557,6 +627,7 @@ void ddgs_default_options(ddgs_options *o)
     o->z_near = 1.0f;
     o->sigma_max = 0.99f;
     o->persistent = 0;
+    o->split = 256;
     o->capacity = 0;
 }
 
@@ -582,6 +653,10 @@ ddgs_status ddgs_create(ddgs_ctx **out, int device, void *hip_stream)
             return DDGS_ERR_HIP;
         }
     }
+    if (hipEventCreateWithFlags(&c->stage_event, hipEventDisableTiming) != hipSuccess) {
+        ddgs_destroy(c);
+        return DDGS_ERR_HIP;
+    }
     *out = c;
     return DDGS_OK;
 }
@@ -598,6 +673,8 @@ void ddgs_destroy(ddgs_ctx *c)
         if (c->ev_s[i]) (void)hipEventDestroy(c->ev_s[i]);
         if (c->ev_e[i]) (void)hipEventDestroy(c->ev_e[i]);
     }
+    if (c->stage_event) (void)hipEventDestroy(c->stage_event);
+    if (c->stage_host) (void)hipHostFree(c->stage_host);
     delete c;
 }
 
@@ -793,7 +870,7 @@ ddgs_status ddgs_step_capture(ddgs_ctx *c, int kind, const float *target, float 
     }
     cap = std::min<int64_t>(cap, 0xFFFFFFF0ll);
     DDGS_TRY(ensure_entries(c, cap));
-    c->step_cap = c->entry_cap;
+    c->step_cap = cap;
     const bool saved_timing = c->timing;
     c->timing = false;
     HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
@@ -843,7 +920,7 @@ ddgs_status ddgs_check(ddgs_ctx *c, uint32_t *flags)
         HIP_TRY(c, hipMemcpy(sc, buf<uint32_t>(c, "scalars"), sizeof(sc), hipMemcpyDeviceToHost));
     if (flags) *flags = sc[3];
     const uint64_t total = (uint64_t)sc[0] | ((uint64_t)sc[1] << 32);
-    if (c->M < 0) c->M = (int64_t)std::min<uint64_t>(total, (uint64_t)c->entry_cap);
+    if (c->M < 0) c->M = (int64_t)std::min<uint64_t>(total, (uint64_t)c->step_cap);
     if (sc[3] & 1u)
         return fail(c, DDGS_ERR_CAPACITY, "tile entries (" + std::to_string(total) + ") exceeded the capacity (" +
                                               std::to_string(c->step_cap) + ")");
@@ -862,6 +939,27 @@ ddgs_status ddgs_num_rendered(const ddgs_ctx *c, int64_t *n)
 {
     if (!c || !n) return DDGS_ERR_INVALID_ARG;
     *n = c->M;
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_debug_count_pairs(ddgs_ctx *c, int enable)
+{
+    if (!c) return DDGS_ERR_INVALID_ARG;
+    c->count_pairs = enable != 0;
+    drop_graph(c);
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_debug_pair_counts(ddgs_ctx *c, int64_t *evaluated, int64_t *contributing)
+{
+    if (!c) return DDGS_ERR_INVALID_ARG;
+    if (!c->count_pairs || !c->rendered) return fail(c, DDGS_ERR_STATE, "pair counting was off for the last render");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    unsigned long long h[2] = {0, 0};
+    HIP_TRY(c, hipMemcpy(h, buf<uint32_t>(c, "scalars") + 12, sizeof(h), hipMemcpyDeviceToHost));
+    if (evaluated) *evaluated = (int64_t)h[0];
+    if (contributing) *contributing = (int64_t)h[1];
     return DDGS_OK;
 }
 
@@ -967,7 +1065,7 @@ ddgs_status ddgs_debug_exclusive_scan(ddgs_ctx *c, const uint32_t *in, uint32_t 
 namespace {
 
 struct TuneEntry {
-    int tile_w = 16, tile_h = 16, persistent = 0;
+    int tile_w = 16, tile_h = 16, persistent = 0, split = 256;
     double ms = 0.0;
 };
 
@@ -1020,13 +1118,15 @@ std::map<std::string, TuneEntry> read_cache(const char *path)
         if (ob == std::string::npos || cb == std::string::npos || cb < ob) break;
         const std::string key = s.substr(q0 + 1, q1 - q0 - 1);
         const std::string obj = s.substr(ob, cb - ob + 1);
-        double tw, th, pe, ms;
+        double tw, th, pe, sp, ms;
         if (parse_num(obj, "tile_w", &tw) && parse_num(obj, "tile_h", &th) && parse_num(obj, "persistent", &pe) &&
-            parse_num(obj, "ms", &ms) && raster_tile_supported((int)tw, (int)th) && (pe == 0.0 || pe == 1.0)) {
+            parse_num(obj, "split", &sp) && parse_num(obj, "ms", &ms) && raster_tile_supported((int)tw, (int)th) &&
+            (pe == 0.0 || pe == 1.0) && sp >= 0.0 && sp <= (double)(1 << 24)) {
             TuneEntry e;
             e.tile_w = (int)tw;
             e.tile_h = (int)th;
             e.persistent = (int)pe;
+            e.split = (int)sp;
             e.ms = ms;
             out[key] = e;
         }
@@ -1045,7 +1145,8 @@ bool write_cache(const char *path, const std::map<std::string, TuneEntry> &m)
         size_t i = 0;
         for (const auto &kv : m) {
             f << "  \"" << kv.first << "\": {\"tile_w\": " << kv.second.tile_w << ", \"tile_h\": " << kv.second.tile_h
-              << ", \"persistent\": " << kv.second.persistent << ", \"ms\": " << kv.second.ms << "}"
+              << ", \"persistent\": " << kv.second.persistent << ", \"split\": " << kv.second.split
+              << ", \"ms\": " << kv.second.ms << "}"
               << (++i < m.size() ? ",\n" : "\n");
         }
         f << "}\n";
@@ -1074,6 +1175,7 @@ ddgs_status ddgs_autotune(ddgs_ctx *c, const char *cache_path, int repeats, floa
             o.tile_w = it->second.tile_w;
             o.tile_h = it->second.tile_h;
             o.persistent = it->second.persistent;
+            o.split = it->second.split;
             DDGS_TRY(ddgs_set_options(c, &o));
             if (best_ms) *best_ms = (float)it->second.ms;
             return DDGS_OK;
@@ -1102,12 +1204,15 @@ ddgs_status ddgs_autotune(ddgs_ctx *c, const char *cache_path, int repeats, floa
     TuneEntry best;
     double best_t = 1e300;
     ddgs_status st = DDGS_OK;
+    const int splits[3] = {256, 1024, 0};
     for (int si = 0; si < 4 && st == DDGS_OK; ++si) {
-        for (int pe = 0; pe < 2 && st == DDGS_OK; ++pe) {
+        for (int ci = 0; ci < 6 && st == DDGS_OK; ++ci) {
+            const int pe = ci & 1, sp = splits[ci >> 1];
             ddgs_options o = base;
             o.tile_w = shapes[si][0];
             o.tile_h = shapes[si][1];
             o.persistent = pe;
+            o.split = sp;
             st = ddgs_set_options(c, &o);
             if (st == DDGS_OK) st = ddgs_render(c, img);
             if (st == DDGS_OK) st = ddgs_backward(c, dL, &g);
@@ -1130,6 +1235,7 @@ ddgs_status ddgs_autotune(ddgs_ctx *c, const char *cache_path, int repeats, floa
                 best.tile_w = o.tile_w;
                 best.tile_h = o.tile_h;
                 best.persistent = pe;
+                best.split = sp;
                 best.ms = med;
             }
         }
@@ -1141,6 +1247,7 @@ ddgs_status ddgs_autotune(ddgs_ctx *c, const char *cache_path, int repeats, floa
         o.tile_w = best.tile_w;
         o.tile_h = best.tile_h;
         o.persistent = best.persistent;
+        o.split = best.split;
     }
     const ddgs_status st2 = ddgs_set_options(c, &o);
     if (st != DDGS_OK) return st;

@@ -69,6 +69,28 @@ __device__ __forceinline__ float wave_sum(float x)
     return x;
 }
 
+// DPP move with identity fill (rows outside ROW_MASK read 0)
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ float dpp_move(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+
+// Sum over the 64 lanes of a wave using only VALU data-parallel moves; the
+// total lands in lane 63.  Butterflies inside quads and rows of 16
+// (quad_perm, row_half_mirror, row_mirror), then row_bcast:15 and
+// row_bcast:31 fold the four rows into the last one.
+__device__ __forceinline__ float wave_sum_to_lane63(float x)
+{
+    x += dpp_move<0xB1>(x);        // quad_perm [1,0,3,2]
+    x += dpp_move<0x4E>(x);        // quad_perm [2,3,0,1]
+    x += dpp_move<0x141>(x);       // row_half_mirror
+    x += dpp_move<0x140>(x);       // row_mirror
+    x += dpp_move<0x142, 0xA>(x);  // row_bcast:15 into rows 1 and 3
+    x += dpp_move<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
 {
     const int lane = (int)__lane_id();
@@ -107,11 +129,11 @@ struct ProjBwdArgs {
     uint32_t slot_cap;  // number of gradient slots (entries beyond are ignored)
 };
 hipError_t launch_project_bwd(const ProjBwdArgs &a, hipStream_t s);
-// d b_iso, d B_dir partial sums per block: part [n_blocks][k + k_L k]
-int basis_grad_blocks(int n);
+// d b_iso, d B_dir: per-wave 16 x 32 MFMA tiles in part, then an FP64 sum
+int basis_grad_waves(int n);
+size_t basis_part_floats(int n);
 hipError_t launch_basis_grad(const ModelDev &m, const float *ubuf, float *part, hipStream_t s);
-hipError_t launch_basis_final(const ModelDev &m, const float *part, int nblk, float *db, float *dB,
-                              hipStream_t s);
+hipError_t launch_basis_final(const ModelDev &m, const float *part, float *db, float *dB, hipStream_t s);
 hipError_t launch_pose_final(const ViewDev *views, int V, int n_waves, const float *pose_part,
                              float *dpose, hipStream_t s);
 
@@ -148,11 +170,19 @@ struct RasterArgs {
     const uint32_t *tval;
     const float4 *rec;
     int n_tiles;
-    const uint32_t *queue;     // persistent mode: tile order (NULL: blockIdx)
-    uint32_t *queue_counter;   // persistent mode work counter
+    const uint32_t *queue;     // persistent mode, split 0: tile order (NULL: natural order)
+    uint32_t *queue_counter;   // persistent mode work counter (NULL: one item per block)
+    // work items: split = entries per item (0: one item per tile)
+    int split;
+    const uint2 *items;        // [max_items] (tile, chunk)
+    const uint32_t *n_items;   // device count of items
+    int max_items;
+    const uint32_t *item_base, *item_cnt;  // [n_tiles] first item and item count per tile
+    float2 *part;              // [max_items][tile pixels] chunk (C, T), then (C, T) in front of it
     // forward
     float *img, *img_saved;
     uint32_t *nlast;
+    unsigned long long *pair_counts;  // [2]: evaluated, contributing (NULL: off)
     // backward
     const float *dL_dimg;
     const uint2 *rect;
@@ -165,6 +195,11 @@ hipError_t launch_raster_bwd(const RasterArgs &a, int persistent_blocks, hipStre
 // persistent queue: order tiles by descending list length
 hipError_t launch_tile_cost_keys(const uint2 *ranges, int n_tiles, uint32_t *keys, uint32_t *vals,
                                  uint32_t *counter, hipStream_t s);
+// work items of `split` entries: per-tile counts and bases, the item list,
+// the device item count; also clears the two work-queue counters
+hipError_t launch_items(const uint2 *ranges, int n_tiles, int split, uint32_t *cnt, uint32_t *base, uint2 *items,
+                        uint32_t max_items, void *scan_tmp, uint64_t *scan_total, uint32_t *n_items,
+                        uint32_t *counter, hipStream_t s);
 bool raster_tile_supported(int tw, int th);
 
 // loss.hip

@@ -427,9 +427,10 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
         }
         // per-wave pose partials (deterministic, reduced in FP64 later)
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            const float r = wave_sum(pose[q]);
-            if (lane == 0) a.pose_part[((size_t)v * n_waves + wave) * 9 + q] = r;
+        for (int q = 0; q < 9; ++q) pose[q] = wave_sum_to_lane63(pose[q]);
+        if (lane == kWave - 1) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) a.pose_part[((size_t)v * n_waves + wave) * 9 + q] = pose[q];
         }
     }
     if (!valid || !a.per_gaussian) return;
@@ -498,88 +499,93 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
         }
     }
     if (a.ubuf) {
+        // Gaussian-major rows of 16: directional u in [0, k_L), isotropic z in 15
+        float row[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) row[r] = 0.0f;
         if (!is_dir) {
-            a.ubuf[i] = zsum;
+            row[15] = zsum;
         } else {
 #pragma unroll
-            for (int r = 0; r < KL; ++r) a.ubuf[(size_t)r * n + i] = u[r];
+            for (int r = 0; r < KL; ++r) row[r] = u[r];
         }
+        float4 *dst = reinterpret_cast<float4 *>(a.ubuf + (size_t)i * 16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[q] = make_float4(row[4 * q], row[4 * q + 1], row[4 * q + 2], row[4 * q + 3]);
     }
 }
 
-// d b_iso[j] = sum_{iso} zsum_i f_j,i ; d B_dir[r][j] = sum_{dir} u_r,i f_j,i.
-// A rank-n outer-product sum with a tiny output: bandwidth bound, so each
-// block stages 64 Gaussians of u and f in LDS and every thread owns output
-// components; per-block partials are summed in FP64 afterwards.
-constexpr int kBasisChunk = 1024;
-constexpr int kBasisSub = 64;
+// Gradients of the shared bases (Eq. 3): d B_dir[r][j] = sum_{dir} u_r,i f_j,i
+// and d b_iso[j] = sum_{iso} z_i f_j,i -- one dense contraction U F^T over
+// all Gaussians with a 16-row U (rows [0, k_L) directional u, row 15 the
+// isotropic z, the rest zero).  Each wave runs it on the matrix cores with
+// v_mfma_f32_16x16x4_f32 over a contiguous run of Gaussians (four per
+// instruction), keeping a 16 x 16 accumulator per 16 features; the per-wave
+// tiles are then summed in FP64 by basis_final_kernel.
+constexpr int kBasisWaves = 2048;
 
-template <int KMAX, int L>
-__global__ __launch_bounds__(kBlock) void basis_grad_kernel(ModelDev m, const float *ubuf, float *part)
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+template <int KMAX>
+__global__ __launch_bounds__(kBlock) void basis_grad_kernel(int n, int k, const float *ubuf, const float *feat,
+                                                            float *part)
 {
-    constexpr int KL = L * (L + 2);
-    constexpr int NOUT = KMAX + KL * KMAX;
-    constexpr int PER = (NOUT + kBlock - 1) / kBlock;
-    __shared__ float sf[KMAX][kBasisSub + 1];
-    __shared__ float su[KL][kBasisSub + 1];
-    const int n = m.n, k = m.k, n_iso = m.n_iso;
-    const int i0 = blockIdx.x * kBasisChunk;
-    float acc[PER];
+    constexpr int NTILE = (KMAX + 15) / 16;
+    constexpr int NCOL = NTILE * 16;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    const int nwaves = gridDim.x * (kBlock / kWave);
+    const int per = ((n + nwaves - 1) / nwaves + 3) & ~3;
+    const int g_begin = min(n, wave * per), g_end = min(n, g_begin + per);
+    // operand layout of the 16x16x4 f32 MFMA: lane l supplies A[l % 16][l / 16]
+    // and B[l / 16][l % 16]; D[i][j] comes back in lane j + 16 (i / 4), item i % 4
+    const int row = lane & 15, kk = lane >> 4;
+    floatx4 acc[NTILE];
 #pragma unroll
-    for (int p = 0; p < PER; ++p) acc[p] = 0.0f;
-    for (int c0 = i0; c0 < min(n, i0 + kBasisChunk); c0 += kBasisSub) {
-        __syncthreads();
-        for (int q = threadIdx.x; q < KMAX * kBasisSub; q += kBlock) {
-            const int j = q / kBasisSub, c = q % kBasisSub, ig = c0 + c;
-            sf[j][c] = (j < k && ig < n) ? m.feat[(size_t)j * n + ig] : 0.0f;
-        }
-        for (int q = threadIdx.x; q < KL * kBasisSub; q += kBlock) {
-            const int r = q / kBasisSub, c = q % kBasisSub, ig = c0 + c;
-            float val = 0.0f;
-            if (ig < n) {
-                if (ig < n_iso) val = (r == 0) ? ubuf[ig] : 0.0f;
-                else val = ubuf[(size_t)r * n + ig];
-            }
-            su[r][c] = val;
-        }
-        __syncthreads();
-        const int cend = min(kBasisSub, n - c0);
+    for (int t = 0; t < NTILE; ++t) acc[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int g0 = g_begin; g0 < g_end; g0 += 4) {
+        const int g = g0 + kk;
+        const bool ok = g < g_end;
+        const float a = ok ? ubuf[(size_t)g * 16 + row] : 0.0f;
 #pragma unroll
-        for (int p = 0; p < PER; ++p) {
-            const int o = threadIdx.x + p * kBlock;
-            if (o >= NOUT) continue;
-            if (o < KMAX) {
-                for (int c = 0; c < cend; ++c)
-                    if (c0 + c < n_iso) acc[p] += su[0][c] * sf[o][c];
-            } else {
-                const int r = (o - KMAX) / KMAX, j = (o - KMAX) % KMAX;
-                for (int c = 0; c < cend; ++c)
-                    if (c0 + c >= n_iso) acc[p] += su[r][c] * sf[j][c];
-            }
+        for (int t = 0; t < NTILE; ++t) {
+            const int j = t * 16 + row;
+            const float b = (ok && j < k) ? feat[(size_t)j * n + g] : 0.0f;
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
         }
     }
 #pragma unroll
-    for (int p = 0; p < PER; ++p) {
-        const int o = threadIdx.x + p * kBlock;
-        if (o < NOUT) part[(size_t)blockIdx.x * NOUT + o] = acc[p];
-    }
+    for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = 4 * kk + q, j = t * 16 + row;
+            part[((size_t)wave * 16 + i) * NCOL + j] = acc[t][q];
+        }
 }
 
+// one block per output element: FP64 sum of the per-wave tiles
 template <int KMAX, int L>
-__global__ __launch_bounds__(kBlock) void basis_final_kernel(int k, const float *part, int nblk, float *db,
+__global__ __launch_bounds__(kBlock) void basis_final_kernel(int k, const float *part, int nwaves, float *db,
                                                              float *dB)
 {
     constexpr int KL = L * (L + 2);
-    constexpr int NOUT = KMAX + KL * KMAX;
-    for (int o = threadIdx.x; o < NOUT; o += kBlock) {
-        double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += (double)part[(size_t)b * NOUT + o];
-        if (o < KMAX) {
-            if (o < k && db) db[o] = (float)s;
-        } else {
-            const int r = (o - KMAX) / KMAX, j = (o - KMAX) % KMAX;
-            if (j < k && dB) dB[r * k + j] = (float)s;
-        }
+    constexpr int NCOL = ((KMAX + 15) / 16) * 16;
+    const int o = blockIdx.x;  // (row, column) of the 16 x NCOL tile
+    const int i = o / NCOL, j = o % NCOL;
+    double s = 0.0;
+    for (int w = threadIdx.x; w < nwaves; w += kBlock) s += (double)part[((size_t)w * 16 + i) * NCOL + j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
+    __shared__ double red[kBlock / kWave];
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x != 0 || j >= k) return;
+    double t = 0.0;
+    for (int q = 0; q < kBlock / kWave; ++q) t += red[q];
+    if (i == 15) {
+        if (db) db[j] = (float)t;
+    } else if (i < KL) {
+        if (dB) dB[i * k + j] = (float)t;
     }
 }
 
@@ -684,24 +690,34 @@ hipError_t launch_project_bwd(const ProjBwdArgs &a, hipStream_t s)
     });
 }
 
-int basis_grad_blocks(int n) { return (n + kBasisChunk - 1) / kBasisChunk; }
+int basis_grad_waves(int n)
+{
+    // about 64 Gaussians per wave at least, at most kBasisWaves waves
+    const int w = (n + 63) / 64;
+    return std::max(4, std::min(kBasisWaves, (w + 3) & ~3));
+}
+
+size_t basis_part_floats(int n) { return (size_t)basis_grad_waves(n) * 16 * 32; }
 
 hipError_t launch_basis_grad(const ModelDev &m, const float *ubuf, float *part, hipStream_t s)
 {
     if (m.n == 0) return hipSuccess;
+    const int blocks = basis_grad_waves(m.n) / (kBlock / kWave);
     return dispatch_kl(m.k, m.L, [&](auto K, auto L) {
-        constexpr int KK = decltype(K)::value, LL = decltype(L)::value;
-        basis_grad_kernel<KK, LL><<<basis_grad_blocks(m.n), kBlock, 0, s>>>(m, ubuf, part);
+        constexpr int KK = decltype(K)::value;
+        (void)L;
+        basis_grad_kernel<KK><<<blocks, kBlock, 0, s>>>(m.n, m.k, ubuf, m.feat, part);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_basis_final(const ModelDev &m, const float *part, int nblk, float *db, float *dB,
-                              hipStream_t s)
+hipError_t launch_basis_final(const ModelDev &m, const float *part, float *db, float *dB, hipStream_t s)
 {
+    const int nwaves = basis_grad_waves(m.n);
     return dispatch_kl(m.k, m.L, [&](auto K, auto L) {
         constexpr int KK = decltype(K)::value, LL = decltype(L)::value;
-        basis_final_kernel<KK, LL><<<1, kBlock, 0, s>>>(m.k, part, nblk, db, dB);
+        constexpr int NCOL = ((KK + 15) / 16) * 16;
+        basis_final_kernel<KK, LL><<<16 * NCOL, kBlock, 0, s>>>(m.k, part, nwaves, db, dB);
         return hipGetLastError();
     });
 }

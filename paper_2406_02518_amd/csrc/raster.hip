@@ -1,29 +1,34 @@
 // raster.hip -- per-tile compositing of Eq. 1 on gfx950 and its backward.
 //
-// One workgroup owns one (view, tile); one lane owns one pixel (a 16x16 tile
-// is four wave64s).  The tile's depth-ordered list is walked in batches: each
-// lane stages one 32-byte Gaussian record into LDS, then every lane reads the
-// batch back as wave-wide broadcasts and composites front to back.  The
-// per-pair arithmetic is written with explicit round-to-nearest intrinsics so
-// that the forward and the backward (which recomputes the transmittance
-// instead of storing it) take bit-identical decisions and values.
+// Work items.  A work item is a (tile, depth chunk) pair: the tile's
+// depth-ordered list is cut into chunks of `split` entries (split = 0: one
+// item per tile).  Chunking bounds the serial walk of any one workgroup, so
+// tiles with very long lists no longer set the kernel's critical path, and
+// the 256 CUs get thousands of similar-sized items.  Eq. 1 is a left fold
+// of the "over" operator (C, T) o (C', T') = (C + T C', T T'), which is
+// associative, so chunk results are merged exactly in depth order by a
+// small merge kernel (which also stores, for every chunk, the (C, T) in
+// front of it for the backward).  With split = 0 the image is bit-identical
+// for every tile shape; with chunks it differs only by rounding.
 //
-// The backward walks the same list front to back, recomputing T_j and the
-// running sum; the tail S_j = sum_{m>j} c_m s_m T_m is the saved pixel value
-// minus the running sum.  Per-pair image-plane gradients are reduced over the
-// wave (cross-lane shuffles), over the four waves in LDS in a fixed order,
-// and written once per tile entry into a slot indexed by the entry's
-// emission position -- no float atomics, so results are run-to-run
-// deterministic.  The projection backward then sums each Gaussian's slots.
+// Inside an item one workgroup owns the tile and one lane owns one pixel.
+// The item's entries are staged in LDS in batches (one 32-byte record per
+// entry) and read back as wave-wide broadcasts.  The per-pair arithmetic is
+// written with explicit round-to-nearest intrinsics so that the forward and
+// the backward (which recomputes the transmittance instead of storing it)
+// take bit-identical decisions.
+//
+// Backward: the tail S_j = sum_{m>j} c_m s_m T_m is the saved pixel value
+// minus the running sum.  Per-pair image-plane gradients are summed over the
+// wave with DPP row operations (VALU only, no LDS round trip), over the
+// waves of the workgroup in LDS in a fixed order, and written once per tile
+// entry into a slot indexed by the entry's emission position -- no float
+// atomics, so the gradients are run-to-run deterministic.
 #include "internal.h"
 
 namespace ddgs {
 
 namespace {
-
-struct PairState {
-    float T, C;
-};
 
 __device__ __forceinline__ float maha2(float dx, float dy, float A00, float A01, float A11)
 {
@@ -43,20 +48,51 @@ __device__ __forceinline__ int view_of_tile(const ViewDev *views, int V, int til
     return lo;
 }
 
-template <int NT>
+struct Item {
+    int tile;
+    uint32_t b, e;    // entry range [b, e) of the item
+    int chunk;
+};
+
+// Resolves work item `it`; false when `it` is past the last item.
+__device__ __forceinline__ bool resolve_item(const RasterArgs &a, int it, Item &r)
+{
+    if (a.split == 0) {
+        if (it >= a.n_tiles) return false;
+        const uint2 rg = a.ranges[it];
+        r.tile = it;
+        r.b = rg.x;
+        r.e = rg.y;
+        r.chunk = 0;
+        return true;
+    }
+    if (it >= (int)*a.n_items) return false;
+    const uint2 q = a.items[it];
+    const uint2 rg = a.ranges[q.x];
+    r.tile = (int)q.x;
+    r.chunk = (int)q.y;
+    r.b = rg.x + q.y * (uint32_t)a.split;
+    r.e = min(rg.y, r.b + (uint32_t)a.split);
+    return true;
+}
+
+// Next work item of this workgroup: its block index once, or (persistent
+// mode) items taken from a shared counter until none are left.
 __device__ __forceinline__ int next_item(const RasterArgs &a, int &iter, int *sh)
 {
-    if (!a.queue) {
-        const int t = iter == 0 ? (int)blockIdx.x : a.n_tiles;
+    if (!a.queue_counter) {
+        const int t = iter == 0 ? (int)blockIdx.x : 0x7FFFFFFF;
         ++iter;
         return t;
     }
     __syncthreads();
     if (threadIdx.x == 0) *sh = (int)atomicAdd(a.queue_counter, 1u);
     __syncthreads();
-    const int it = *sh;
+    const int k = *sh;
     ++iter;
-    return it < a.n_tiles ? (int)a.queue[it] : a.n_tiles;
+    const int limit = a.split ? (int)*a.n_items : a.n_tiles;
+    if (k >= limit) return 0x7FFFFFFF;
+    return a.queue ? (int)a.queue[k] : k;
 }
 
 template <int TW, int TH>
@@ -70,31 +106,33 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
     const float k2 = a.o.kappa2, smax = a.o.sigma_max, tmin = a.o.t_min;
     int iter = 0;
     for (;;) {
-        const int tile = next_item<NT>(a, iter, &sh_item);
-        if (tile >= a.n_tiles) break;
-        const int v = view_of_tile(a.views, a.V, tile);
+        const int it = next_item(a, iter, &sh_item);
+        Item I;
+        if (it == 0x7FFFFFFF || !resolve_item(a, it, I)) break;
+        const int v = view_of_tile(a.views, a.V, I.tile);
         const ViewDev &V = a.views[v];
-        const int lt = tile - V.tile_base;
+        const int lt = I.tile - V.tile_base;
         const int ty = lt / V.ntx, tx = lt - ty * V.ntx;
         const int px = tx * TW + tid % TW, py = ty * TH + tid / TW;
         const bool inside = px < V.W && py < V.H;
         const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
-        const uint2 rg = a.ranges[tile];
         const size_t vbase = (size_t)v * a.n;
         float T = 1.0f, C = 0.0f;
-        uint32_t last = rg.x;
+        uint32_t last = I.b;
+        uint32_t n_eval = 0, n_contrib = 0;
         bool done = !inside;
-        for (uint32_t b0 = rg.x; b0 < rg.y; b0 += NT) {
+        for (uint32_t b0 = I.b; b0 < I.e; b0 += NT) {
             __syncthreads();
             const uint32_t j = b0 + tid;
-            if (j < rg.y) {
+            if (j < I.e) {
                 const uint32_t gid = min(a.tval[j], (uint32_t)a.n - 1u);
                 const size_t idx = vbase + gid;
                 s0[tid] = a.rec[2 * idx];
                 s1[tid] = a.rec[2 * idx + 1];
             }
             __syncthreads();
-            const int cnt = (int)min((uint32_t)NT, rg.y - b0);
+            const int cnt = (int)min((uint32_t)NT, I.e - b0);
+            if (a.pair_counts && !done) n_eval += (uint32_t)cnt;
             for (int q = 0; q < cnt; ++q) {
                 const float4 r0 = s0[q];
                 const float4 r1 = s1[q];
@@ -110,17 +148,63 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
                         C = __fmaf_rn(__fmul_rn(r1.z, s), T, C);
                         T = __fmul_rn(T, om);
                         last = b0 + (uint32_t)q + 1u;
+                        ++n_contrib;
                     }
                 }
             }
             if (tmin > 0.0f && __syncthreads_and(done)) break;
         }
-        if (inside) {
+        if (a.pair_counts) {
+            unsigned long long e = n_eval, c = n_contrib;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                e += __shfl_xor(e, o, kWave);
+                c += __shfl_xor(c, o, kWave);
+            }
+            if ((tid & (kWave - 1)) == 0) {
+                atomicAdd(&a.pair_counts[0], e);
+                atomicAdd(&a.pair_counts[1], c);
+            }
+        }
+        if (a.split) {
+            a.part[(size_t)it * NT + tid] = make_float2(C, T);
+        } else if (inside) {
             const size_t p = (size_t)V.pix_base + (size_t)py * V.W + px;
             a.img[p] = C;
             a.img_saved[p] = C;
             a.nlast[p] = last;
         }
+    }
+}
+
+// Split mode: folds each tile's chunk results in depth order with the over
+// operator, writes the images, and replaces every chunk's (C, T) by the
+// (C, T) accumulated in front of it (what the chunk's backward starts from).
+template <int TW, int TH>
+__global__ __launch_bounds__(TW *TH) void merge_kernel(RasterArgs a)
+{
+    constexpr int NT = TW * TH;
+    const int tile = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int v = view_of_tile(a.views, a.V, tile);
+    const ViewDev &V = a.views[v];
+    const int lt = tile - V.tile_base;
+    const int ty = lt / V.ntx, tx = lt - ty * V.ntx;
+    const int px = tx * TW + tid % TW, py = ty * TH + tid / TW;
+    const uint32_t base = a.item_base[tile], cnt = a.item_cnt[tile];
+    float C = 0.0f, T = 1.0f;
+    for (uint32_t k = 0; k < cnt && base + k < (uint32_t)a.max_items; ++k) {
+        float2 *slot = a.part + (size_t)(base + k) * NT + tid;
+        const float2 ck = *slot;
+        *slot = make_float2(C, T);
+        C = __fmaf_rn(T, ck.x, C);
+        T = __fmul_rn(T, ck.y);
+    }
+    if (px < V.W && py < V.H) {
+        const size_t p = (size_t)V.pix_base + (size_t)py * V.W + px;
+        a.img[p] = C;
+        a.img_saved[p] = C;
+        a.nlast[p] = a.ranges[tile].y;
     }
 }
 
@@ -139,26 +223,31 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
     const float k2 = a.o.kappa2, smax = a.o.sigma_max, tmin = a.o.t_min;
     int iter = 0;
     for (;;) {
-        const int tile = next_item<NT>(a, iter, &sh_item);
-        if (tile >= a.n_tiles) break;
-        const int v = view_of_tile(a.views, a.V, tile);
+        const int it = next_item(a, iter, &sh_item);
+        Item I;
+        if (it == 0x7FFFFFFF || !resolve_item(a, it, I)) break;
+        const int v = view_of_tile(a.views, a.V, I.tile);
         const ViewDev &V = a.views[v];
-        const int lt = tile - V.tile_base;
+        const int lt = I.tile - V.tile_base;
         const int ty = lt / V.ntx, tx = lt - ty * V.ntx;
         const int px = tx * TW + tid % TW, py = ty * TH + tid / TW;
         const bool inside = px < V.W && py < V.H;
         const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
-        const uint2 rg = a.ranges[tile];
         const size_t vbase = (size_t)v * a.n;
-        float g = 0.0f, Cf = 0.0f;
-        uint32_t lastp = rg.x;
+        float g = 0.0f, Cf = 0.0f, T = 1.0f, Cacc = 0.0f;
+        uint32_t lastp = I.b;
         if (inside) {
             const size_t p = (size_t)V.pix_base + (size_t)py * V.W + px;
             g = a.dL_dimg[p];
             Cf = a.img_saved[p];
-            lastp = a.nlast[p];
+            lastp = a.split ? I.e : a.nlast[p];
         }
-        // end of the longest contributing prefix in the tile
+        if (a.split) {
+            const float2 pre = a.part[(size_t)it * NT + tid];
+            Cacc = pre.x;
+            T = pre.y;
+        }
+        // end of the longest contributing prefix in the item
         uint32_t m = lastp;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, kWave));
@@ -169,13 +258,12 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
 #pragma unroll
         for (int q = 1; q < NW; ++q) end = max(end, wmax[q]);
 
-        float T = 1.0f, Cacc = 0.0f;
         bool done = !inside;
-        for (uint32_t b0 = rg.x; b0 < rg.y; b0 += NT) {
-            const int cnt = (int)min((uint32_t)NT, rg.y - b0);
+        for (uint32_t b0 = I.b; b0 < I.e; b0 += NT) {
+            const int cnt = (int)min((uint32_t)NT, I.e - b0);
             __syncthreads();
             const uint32_t j = b0 + tid;
-            if (j < rg.y) {
+            if (j < I.e) {
                 const uint32_t gid = min(a.tval[j], (uint32_t)a.n - 1u);
                 const size_t idx = vbase + gid;
                 s0[tid] = a.rec[2 * idx];
@@ -204,7 +292,7 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                             const float c = r1.z;
                             Cacc = __fmaf_rn(__fmul_rn(c, s), T, Cacc);
                             const float S = Cf - Cacc;
-                            const float ds = g * (c * T - S / om);
+                            const float ds = g * (c * T - __fdividef(S, om));
                             gv[6] = g * s * T;
                             if (!(sraw > smax)) {
                                 gv[5] = ds * G;
@@ -220,9 +308,9 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                     }
                     if (__ballot(hit) != 0ull) {
 #pragma unroll
-                        for (int c = 0; c < 7; ++c) gv[c] = wave_sum(gv[c]);
+                        for (int c = 0; c < 7; ++c) gv[c] = wave_sum_to_lane63(gv[c]);
                     }
-                    if (lane == 0) {
+                    if (lane == kWave - 1) {
 #pragma unroll
                         for (int c = 0; c < 7; ++c) acc[w][c][q] = gv[c];
                     }
@@ -265,18 +353,45 @@ __global__ __launch_bounds__(256) void tile_cost_kernel(const uint2 *ranges, int
     vals[t] = (uint32_t)t;
 }
 
+__global__ __launch_bounds__(256) void chunk_count_kernel(const uint2 *ranges, int n_tiles, int split,
+                                                          uint32_t *cnt)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= n_tiles) return;
+    const uint2 r = ranges[t];
+    const uint32_t L = r.y - r.x;
+    cnt[t] = (L + (uint32_t)split - 1u) / (uint32_t)split;
+}
+
+__global__ __launch_bounds__(256) void expand_items_kernel(const uint32_t *cnt, const uint32_t *base, int n_tiles,
+                                                           uint2 *items, uint32_t max_items, const uint64_t *total,
+                                                           uint32_t *n_items, uint32_t *counter)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t == 0) {
+        const uint64_t tot = *total;
+        *n_items = tot > (uint64_t)max_items ? max_items : (uint32_t)tot;
+        counter[0] = 0;
+        counter[1] = 0;
+    }
+    if (t >= n_tiles) return;
+    const uint32_t b = base[t], c = cnt[t];
+    for (uint32_t k = 0; k < c && b + k < max_items; ++k) items[b + k] = make_uint2((uint32_t)t, k);
+}
+
 template <int TW, int TH>
 hipError_t fwd_inst(const RasterArgs &a, int pb, hipStream_t s)
 {
-    const int grid = a.queue ? pb : a.n_tiles;
+    const int grid = a.queue_counter ? pb : (a.split ? a.max_items : a.n_tiles);
     if (grid > 0) raster_fwd_kernel<TW, TH><<<grid, TW * TH, 0, s>>>(a);
+    if (a.split && a.n_tiles > 0) merge_kernel<TW, TH><<<a.n_tiles, TW * TH, 0, s>>>(a);
     return hipGetLastError();
 }
 
 template <int TW, int TH>
 hipError_t bwd_inst(const RasterArgs &a, int pb, hipStream_t s)
 {
-    const int grid = a.queue ? pb : a.n_tiles;
+    const int grid = a.queue_counter ? pb : (a.split ? a.max_items : a.n_tiles);
     if (grid > 0) raster_bwd_kernel<TW, TH><<<grid, TW * TH, 0, s>>>(a);
     return hipGetLastError();
 }
@@ -312,6 +427,18 @@ hipError_t launch_tile_cost_keys(const uint2 *ranges, int n_tiles, uint32_t *key
                                  uint32_t *counter, hipStream_t s)
 {
     tile_cost_kernel<<<(n_tiles + 255) / 256 + (n_tiles == 0), 256, 0, s>>>(ranges, n_tiles, keys, vals, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_items(const uint2 *ranges, int n_tiles, int split, uint32_t *cnt, uint32_t *base, uint2 *items,
+                        uint32_t max_items, void *scan_tmp, uint64_t *scan_total, uint32_t *n_items,
+                        uint32_t *counter, hipStream_t s)
+{
+    const int nb = (n_tiles + 255) / 256 + (n_tiles == 0);
+    chunk_count_kernel<<<nb, 256, 0, s>>>(ranges, n_tiles, split, cnt);
+    hipError_t e = launch_exclusive_scan(cnt, nullptr, base, n_tiles, scan_tmp, scan_total, s);
+    if (e != hipSuccess) return e;
+    expand_items_kernel<<<nb, 256, 0, s>>>(cnt, base, n_tiles, items, max_items, scan_total, n_items, counter);
     return hipGetLastError();
 }
 

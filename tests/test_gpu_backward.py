@@ -94,11 +94,14 @@ def test_backward_is_deterministic_and_tile_invariant_in_value(R):
     for k in a:
         np.testing.assert_array_equal(a[k], b[k])
     try:
-        R.set_options(tile_w=8, tile_h=8, persistent=1)
+        R.set_options(tile_w=8, tile_h=8, persistent=1, split=0)
         t = _gpu_grads(R, c.scene, views, dl)
+        R.set_options(tile_w=16, tile_h=8, persistent=0, split=5)
+        t2 = _gpu_grads(R, c.scene, views, dl)
     finally:
-        R.set_options(tile_w=16, tile_h=16, persistent=0)
+        R.set_options(tile_w=16, tile_h=16, persistent=0, split=256)
     for k in a:
+        assert rel_l2(t2[k], a[k]) < 1e-5, k
         assert rel_l2(t[k], a[k]) < 1e-5, k
 
 

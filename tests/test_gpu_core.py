@@ -193,15 +193,25 @@ def test_forward_is_tile_and_schedule_invariant(R):
     R.set_views(views)
     ref_img = None
     try:
+        # one work item per tile: bit-identical for every tile shape and schedule
         for tw, th in ((16, 16), (8, 8), (16, 8), (32, 8)):
             for pe in (0, 1):
-                R.set_options(tile_w=tw, tile_h=th, persistent=pe)
+                R.set_options(tile_w=tw, tile_h=th, persistent=pe, split=0)
                 img = R.render().cpu().numpy()
                 if ref_img is None:
                     ref_img = img
                 np.testing.assert_array_equal(img, ref_img)
+        # depth chunks merged with the over operator: equal up to rounding
+        for tw, th in ((16, 16), (8, 8)):
+            for sp in (1, 7, 64, 256):
+                for pe in (0, 1):
+                    R.set_options(tile_w=tw, tile_h=th, persistent=pe, split=sp)
+                    img = R.render().cpu().numpy()
+                    assert rel_l2(img, ref_img) < 1e-6, (tw, th, sp, pe)
+                    again = R.render().cpu().numpy()
+                    np.testing.assert_array_equal(again, img)
     finally:
-        R.set_options(tile_w=16, tile_h=16, persistent=0)
+        R.set_options(tile_w=16, tile_h=16, persistent=0, split=256)
 
 
 def test_batched_views_equal_single_views(R):

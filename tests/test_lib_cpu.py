@@ -58,7 +58,8 @@ def test_status_strings_and_default_options(L):
     assert o.kappa == pytest.approx(3.0) and o.dilation == pytest.approx(0.3)
     assert o.sigma_max == pytest.approx(0.99) and o.t_min == 0.0 and o.z_near == pytest.approx(1.0)
     assert ctypes.sizeof(binding.ddgs_view) == 64
-    assert ctypes.sizeof(binding.ddgs_options) == 40
+    assert ctypes.sizeof(binding.ddgs_options) == 48
+    assert o.split == 256 and o.persistent == 0 and o.capacity == 0
 
 
 def test_product_path_refuses_to_run_without_the_library(monkeypatch, tmp_path):
