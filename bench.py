@@ -53,7 +53,22 @@ def parse():
     ap.add_argument("--batched-reps", type=int, default=5)
     ap.add_argument("--tile", default="auto", help="WxH, or auto: the built-in autotuner picks tile shape, "
                     "scheduling and chunk size on the live inputs")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy (4 times); used to scale the HBM "
+                         "byte counters of a profiler to known traffic")
     return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    n = 64 << 20  # floats: 256 MiB
+    src = torch.rand(n, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(4):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 4}), flush=True)
 
 
 def traffic_from_profiles(kernel, workload):
@@ -90,6 +105,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     fixed = None if args.tile == "auto" else tuple(int(x) for x in args.tile.split("x"))
     stream = torch.cuda.Stream()
 

@@ -467,8 +467,10 @@ ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, int64_t sort_n, float *images
     ra.nlast = buf<uint32_t>(c, "nlast");
     ra.pair_counts = nullptr;
     if (c->count_pairs) {
-        ra.pair_counts = (unsigned long long *)(buf<uint32_t>(c, "scalars") + 12);
-        HIP_TRY(c, launch_fill_u32(buf<uint32_t>(c, "scalars") + 12, 0u, 4, s));
+        unsigned long long *pc;
+        DDGS_TRY(ensure_t(c, "pair_counts", 128, &pc));
+        ra.pair_counts = pc;
+        HIP_TRY(c, launch_fill_u32((uint32_t *)pc, 0u, 256, s));
     }
     HIP_TRY(c, launch_raster_fwd(ra, c->num_cu * 8, s));
     stage_end(c, DDGS_T_RASTER_FWD);
@@ -956,10 +958,15 @@ ddgs_status ddgs_debug_pair_counts(ddgs_ctx *c, int64_t *evaluated, int64_t *con
     if (!c->count_pairs || !c->rendered) return fail(c, DDGS_ERR_STATE, "pair counting was off for the last render");
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    unsigned long long h[2] = {0, 0};
-    HIP_TRY(c, hipMemcpy(h, buf<uint32_t>(c, "scalars") + 12, sizeof(h), hipMemcpyDeviceToHost));
-    if (evaluated) *evaluated = (int64_t)h[0];
-    if (contributing) *contributing = (int64_t)h[1];
+    unsigned long long h[128];
+    HIP_TRY(c, hipMemcpy(h, buf<unsigned long long>(c, "pair_counts"), sizeof(h), hipMemcpyDeviceToHost));
+    int64_t e = 0, k = 0;
+    for (int i = 0; i < 64; ++i) {
+        e += (int64_t)h[2 * i];
+        k += (int64_t)h[2 * i + 1];
+    }
+    if (evaluated) *evaluated = e;
+    if (contributing) *contributing = k;
     return DDGS_OK;
 }
 

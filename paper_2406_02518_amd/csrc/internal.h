@@ -182,7 +182,7 @@ struct RasterArgs {
     // forward
     float *img, *img_saved;
     uint32_t *nlast;
-    unsigned long long *pair_counts;  // [2]: evaluated, contributing (NULL: off)
+    unsigned long long *pair_counts;  // [64][2]: evaluated, contributing per slot (NULL: off)
     // backward
     const float *dL_dimg;
     const uint2 *rect;

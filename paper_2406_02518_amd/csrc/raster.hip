@@ -162,8 +162,10 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
                 c += __shfl_xor(c, o, kWave);
             }
             if ((tid & (kWave - 1)) == 0) {
-                atomicAdd(&a.pair_counts[0], e);
-                atomicAdd(&a.pair_counts[1], c);
+                // 64 counter pairs, chosen by block, keep the atomics uncontended
+                const int slot = (int)(blockIdx.x & 63u);
+                atomicAdd(&a.pair_counts[2 * slot], e);
+                atomicAdd(&a.pair_counts[2 * slot + 1], c);
             }
         }
         if (a.split) {
