@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--cpu-row-stride", type=int, default=2,
                     help="oracle baseline: every n-th detector row of one view")
     ap.add_argument("--batched-reps", type=int, default=5)
@@ -281,6 +282,49 @@ def main():
         log("batched:", json.dumps(batched))
         R4.close()
 
+    # ------------------------------------ uneven batch (1M Gaussians, 16 views)
+    uneven = None
+    if not args.no_uneven:
+        log("uneven batch: 1M Gaussians, 16 views of 256^2 / 512^2 / 1024^2")
+        c5 = synth.config("C5")
+        R5 = binding.Renderer(0, stream=stream)
+        with torch.cuda.stream(stream):
+            R5.set_scene(c5.scene)
+            R5.set_views(c5.views)
+            if fixed:
+                R5.set_options(tile_w=fixed[0], tile_h=fixed[1])
+            else:
+                binding.ddgs_autotune(R5.ctx, None, 3)
+            tuned5 = R5.options()
+            log("uneven raster options:", json.dumps(tuned5))
+            P5 = R5.image_size()
+            w5 = torch.from_numpy(np.random.default_rng(c5.extra["dl_seed"]).normal(size=P5).astype(np.float32)).cuda()
+            img5 = torch.empty(P5, device="cuda")
+            dl5 = torch.empty(P5, device="cuda")
+            loss5 = torch.empty(len(c5.views), device="cuda")
+            g5 = R5.alloc_grads()
+            binding.ddgs_step_capture(R5.ctx, binding.LOSS_LINEAR, w5.data_ptr(), 0.0, img5.data_ptr(),
+                                      dl5.data_ptr(), loss5.data_ptr(), R5.grads_struct(g5))
+            for _ in range(2):
+                binding.ddgs_step_launch(R5.ctx)
+        binding.ddgs_check(R5.ctx)
+        ts = []
+        for _ in range(args.batched_reps):
+            stream.synchronize()
+            a = time.perf_counter()
+            binding.ddgs_step_launch(R5.ctx)
+            stream.synchronize()
+            ts.append((time.perf_counter() - a) * 1e3)
+        binding.ddgs_check(R5.ctx)
+        n5 = R5.num_rendered()
+        uneven = {"workload": "1M Gaussians (256^3 phantom), 16 views in one captured step: 6 x 256^2, 6 x 512^2, "
+                              "4 x 1024^2, pitch U(0.4, 1.5) mm, source-isocentre U(500, 700) mm; forward + "
+                              "linear loss with fixed random weights + backward to all parameters and poses",
+                  "ms_per_step": round(float(np.median(ts)), 3), "tile_entries": int(n5),
+                  "raster_options": {k: tuned5[k] for k in ("tile_w", "tile_h", "persistent", "split")}}
+        log("uneven:", json.dumps(uneven))
+        R5.close()
+
     # ---------------------------------------------------------- CPU oracle
     cpu = None
     if not args.no_cpu_baseline:
@@ -318,6 +362,7 @@ def main():
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "roofline": roofline,
         "batched": batched,
+        "uneven_batch": uneven,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -329,21 +329,26 @@ static uint64_t mix64(uint64_t z)
 static double render_pixel(const gfast *fast, int64_t nv, double px, double py,
                            const orc_opts *o, contrib *list, int64_t *nlist,
                            const int64_t *order, uint64_t pixel_id, int64_t n,
-                           uint64_t *hash, int64_t *count)
+                           uint64_t *hash, int64_t *count, double *margin)
 {
     const double k2 = o->kappa * o->kappa;
-    double T = 1.0, C = 0.0;
+    double T = 1.0, C = 0.0, mg = HUGE_VAL;
     int64_t nl = 0;
     for (int64_t j = 0; j < nv; ++j) {
         const gfast *g = &fast[j];
         const double dx = px - g->mx, dy = py - g->my;
         const double d2 = g->A0 * dx * dx + 2.0 * g->A1 * dx * dy + g->A2 * dy * dy;
+        if (margin) mg = fmin(mg, fabs(d2 - k2) / k2);
         if (d2 > k2) continue;
         const double G = exp(-0.5 * d2);
         double s = g->alpha * G;
+        if (margin) mg = fmin(mg, fabs(s - o->sigma_max) / o->sigma_max);
         int clamped = 0;
         if (s > o->sigma_max) { s = o->sigma_max; clamped = 1; }
-        if (o->t_min > 0.0 && T * (1.0 - s) < o->t_min) break;
+        if (o->t_min > 0.0) {
+            if (margin) mg = fmin(mg, fabs(T * (1.0 - s) - o->t_min) / o->t_min);
+            if (T * (1.0 - s) < o->t_min) break;
+        }
         if (list) {
             list[nl].j = j; list[nl].s = s; list[nl].T = T; list[nl].G = G;
             list[nl].dx = dx; list[nl].dy = dy; list[nl].clamped = clamped;
@@ -355,6 +360,7 @@ static double render_pixel(const gfast *fast, int64_t nv, double px, double py,
     }
     if (nlist) *nlist = nl;
     if (count) *count += nl;
+    if (margin) *margin = mg;
     return C;
 }
 
@@ -387,7 +393,7 @@ int orc_render(const orc_model *m, const orc_view *views, int V,
                 uint64_t h = 0; int64_t c = 0;
                 img[base + (int64_t)row * W + col] =
                     render_pixel(fast, nv, col + 0.5, row + 0.5, o, NULL, NULL, order,
-                                 (uint64_t)row * W + col, m->n, &h, &c);
+                                 (uint64_t)row * W + col, m->n, &h, &c, NULL);
                 hsum += h; csum += c;
             }
         }
@@ -399,11 +405,11 @@ int orc_render(const orc_model *m, const orc_view *views, int V,
     return 0;
 }
 
-int orc_render_pixels(const orc_model *m, const orc_view *views, int V,
-                      const orc_opts *o, int64_t npix, const int32_t *pix,
-                      double *out, int threads)
+static int render_pixels_impl(const orc_model *m, const orc_view *views, int V,
+                              const orc_opts *o, int64_t npix, const int32_t *pix,
+                              double *out, double *margin, int threads)
 {
-    if (check_args(m, views, V, o) || (npix > 0 && (!pix || !out))) return -1;
+    if (check_args(m, views, V, o) || (npix > 0 && (!pix || (!out && !margin)))) return -1;
     for (int64_t p = 0; p < npix; ++p) {
         const int32_t v = pix[3 * p];
         if (v < 0 || v >= V || pix[3 * p + 1] < 0 || pix[3 * p + 1] >= views[v].W ||
@@ -419,12 +425,28 @@ int orc_render_pixels(const orc_model *m, const orc_view *views, int V,
 #pragma omp parallel for schedule(dynamic, 16) num_threads(threads)
         for (int64_t p = 0; p < npix; ++p) {
             if (pix[3 * p] != v) continue;
-            out[p] = render_pixel(fast, nv, pix[3 * p + 1] + 0.5, pix[3 * p + 2] + 0.5, o,
-                                  NULL, NULL, order, 0, m->n, NULL, NULL);
+            const double c = render_pixel(fast, nv, pix[3 * p + 1] + 0.5, pix[3 * p + 2] + 0.5, o,
+                                          NULL, NULL, order, 0, m->n, NULL, NULL,
+                                          margin ? &margin[p] : NULL);
+            if (out) out[p] = c;
         }
         free(gp); free(order); free(fast);
     }
     return 0;
+}
+
+int orc_render_pixels(const orc_model *m, const orc_view *views, int V,
+                      const orc_opts *o, int64_t npix, const int32_t *pix,
+                      double *out, int threads)
+{
+    return render_pixels_impl(m, views, V, o, npix, pix, out, NULL, threads);
+}
+
+int orc_pixel_margins(const orc_model *m, const orc_view *views, int V,
+                      const orc_opts *o, int64_t npix, const int32_t *pix,
+                      double *margin, int threads)
+{
+    return render_pixels_impl(m, views, V, o, npix, pix, NULL, margin, threads);
 }
 
 /* ------------------------------------------------------------------ backward */
@@ -630,7 +652,7 @@ int orc_backward(const orc_model *m, const orc_view *views, int V,
                 if (gp_ == 0.0) continue;
                 int64_t nl = 0;
                 render_pixel(fast, nv, pix[3 * p + 1] + 0.5, pix[3 * p + 2] + 0.5, o, list, &nl,
-                             order, 0, n, NULL, NULL);
+                             order, 0, n, NULL, NULL, NULL);
                 double S = 0.0;
                 for (int64_t q = nl - 1; q >= 0; --q) {
                     const contrib *e = &list[q];

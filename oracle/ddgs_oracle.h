@@ -118,6 +118,16 @@ int orc_render_pixels(const orc_model *m, const orc_view *views, int V,
                       const orc_opts *o, int64_t npix, const int32_t *pix,
                       double *out, int threads);
 
+/* Distance of each listed pixel from the decisions Eq. 1 takes there, as
+ * the smallest relative gap over its Gaussians of: |d2 - kappa^2| / kappa^2
+ * (the cutoff), |alpha G - sigma_max| / sigma_max for considered Gaussians
+ * (the clamp) and, with t_min > 0, |T (1 - s) - t_min| / t_min (the early
+ * stop).  A pixel whose margin is within rounding of 0 has more than one
+ * correct set of contributors at a given working precision. */
+int orc_pixel_margins(const orc_model *m, const orc_view *views, int V,
+                      const orc_opts *o, int64_t npix, const int32_t *pix,
+                      double *margin, int threads);
+
 /* Analytic gradient of L = sum_p g_p I(p) over the listed pixels
  * (pix [npix][3] = (view, u, v), g [npix]).  Every non-NULL output is
  * overwritten. */

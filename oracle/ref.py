@@ -62,6 +62,8 @@ def lib():
         L.orc_render.restype = C.c_int
         L.orc_render_pixels.argtypes = [vp, vp, C.c_int, vp, i64, vp, vp, C.c_int]
         L.orc_render_pixels.restype = C.c_int
+        L.orc_pixel_margins.argtypes = [vp, vp, C.c_int, vp, i64, vp, vp, C.c_int]
+        L.orc_pixel_margins.restype = C.c_int
         L.orc_backward.argtypes = [vp, vp, C.c_int, vp, i64, vp, vp, vp, C.c_int]
         L.orc_backward.restype = C.c_int
         L.orc_loss_l1ssim.argtypes = [vp, vp, C.c_int, C.c_int, C.c_double, vp, vp, vp]
@@ -213,6 +215,21 @@ def render_pixels(scene, views, pix, opts=None, threads=None, c_override=None):
     rc = lib().orc_render_pixels(C.byref(m), vs, len(views), C.byref(o), pix.shape[0], _ptr(pix),
                                  _ptr(out), int(threads or default_threads()))
     _check(rc, "render_pixels")
+    return out
+
+
+def pixel_margins(scene, views, pix, opts=None, threads=None, c_override=None):
+    """Smallest relative gap of each pixel in pix (M, 3) to the cutoff, clamp
+    and early-stop decisions of Eq. 1 (orc_pixel_margins)."""
+    keep = _Keep()
+    m = _model(scene, keep)
+    vs = _views(views)
+    o = _opts(opts, keep, c_override)
+    pix = np.ascontiguousarray(np.asarray(pix, dtype=np.int32).reshape(-1, 3))
+    out = np.zeros(pix.shape[0])
+    rc = lib().orc_pixel_margins(C.byref(m), vs, len(views), C.byref(o), pix.shape[0], _ptr(pix),
+                                 _ptr(out), int(threads or default_threads()))
+    _check(rc, "pixel_margins")
     return out
 
 

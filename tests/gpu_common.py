@@ -11,6 +11,24 @@ def rel_l2(x, ref):
     return float(np.linalg.norm(x - ref) / (den if den > 0 else 1.0))
 
 
+# Pixels near a hit decision of Eq. 1 (the kappa cutoff, the sigma_max clamp,
+# the t_min stop) have two correct sets of contributors: the kernel decides in
+# FP32, the oracle in FP64, and the two projected means and conics differ by
+# rounding.  Worst case near the cutoff: the FP32 mean of a ~1000 px image is
+# off by up to ~5e-4 px after the projection's roundings, and d2 moves by
+# 2 sqrt(d2 lambda_max(A)) per pixel of mean, lambda_max <= 1 / 0.3 (the
+# dilation), so d2 / kappa^2 is uncertain to ~6e-4.  Sampled-pixel parity
+# compares only pixels whose decisions are unique at that band.
+DECISION_BAND = 1e-3
+
+
+def unique_pixels(scene, views, pix, opts=None, band=DECISION_BAND):
+    """Rows of pix (M, 3) whose relative margin to every hit decision exceeds band."""
+    from oracle import ref
+    m = ref.pixel_margins(scene, views, pix, opts=opts)
+    return pix[m > band]
+
+
 def make_renderer(**opts):
     from paper_2406_02518_amd import binding
     r = binding.Renderer(0)

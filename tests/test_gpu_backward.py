@@ -4,7 +4,7 @@ on the oracle's forward, exact identities and run-to-run determinism."""
 import numpy as np
 import pytest
 
-from gpu_common import make_renderer, rel_l2
+from gpu_common import make_renderer, rel_l2, unique_pixels
 from oracle import ref
 from paper_2406_02518_amd import binding, synth
 
@@ -67,16 +67,18 @@ def test_backward_full_c2(R):
 
 
 def test_backward_full_size_c3_sampled_pixels(R):
-    """Full 500k / 512^2 launch, upstream gradient non-zero on 400 sampled
-    pixels: the oracle computes exactly that gradient pixel by pixel."""
+    """Full 500k / 512^2 launch, upstream gradient non-zero on a few hundred
+    sampled pixels whose hit decisions are unique: the oracle computes exactly
+    that gradient pixel by pixel."""
     c = synth.config("C3")
     views = [c.views[3]]
     v = views[0]
     rng = np.random.default_rng(3)
-    uu = rng.integers(0, v.W, 400)
-    vv = rng.integers(int(0.25 * v.H), int(0.75 * v.H), 400)
-    pix = np.stack([np.zeros(400, int), uu, vv], 1).astype(np.int32)
-    w = rng.normal(size=400)
+    uu = rng.integers(0, v.W, 480)
+    vv = rng.integers(int(0.25 * v.H), int(0.75 * v.H), 480)
+    pix = unique_pixels(c.scene, views, np.stack([np.zeros(480, int), uu, vv], 1).astype(np.int32))[:400]
+    uu, vv = pix[:, 1], pix[:, 2]
+    w = rng.normal(size=len(pix))
     dl = np.zeros(v.W * v.H)
     np.add.at(dl, vv * v.W + uu, w)
     g = _gpu_grads(R, c.scene, views, dl)

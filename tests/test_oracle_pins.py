@@ -249,6 +249,35 @@ def test_single_gaussian_footprint_closed_form(seed):
     np.testing.assert_allclose(proj[3:6], [A[0, 0], A[0, 1], A[1, 1]], rtol=1e-7)
 
 
+@pytest.mark.parametrize("seed", [0, 1])
+def test_pixel_margins_closed_form(seed):
+    # one Gaussian: the margin is the relative gap of the closed-form d2 to
+    # kappa^2, or of alpha exp(-d2/2) to sigma_max where it is considered
+    rng = np.random.default_rng(seed)
+    sc = make_scene([rng.uniform(-10, 10, size=3)], [rng.uniform(0.8, 4.0, size=3)], [rng.normal(size=4)],
+                    [0.985], seed=seed)
+    v = synth.view(40, 36, 0.9, 1000.0, 600.0, float(rng.uniform(0, 360)))
+    _, _, _, d2 = _expected_single(sc, v)
+    alpha = 1.0 / (1.0 + np.exp(-np.float64(sc.opacity_logit[0])))
+    exp = np.abs(d2 - 9.0) / 9.0
+    hit = d2 <= 9.0
+    exp[hit] = np.minimum(exp[hit], np.abs(alpha * np.exp(-0.5 * d2[hit]) - 0.99) / 0.99)
+    got = ref.pixel_margins(sc, [v], ref.all_pixels([v])).reshape(v.H, v.W)
+    np.testing.assert_allclose(got, exp, atol=1e-7)
+    assert got.min() < 1e-2
+
+
+def test_pixel_margins_early_stop_steps():
+    # three co-located s = 0.5 steps: T (1 - s) runs 0.5, 0.25, 0.125; with
+    # t_min = 0.2 the closest is 0.25 (gap 0.25); without it, the clamp gap
+    sc = make_scene([[0, 0, 0]] * 3, [[1, 1, 1]] * 3, [[1, 0, 0, 0]] * 3, [0.5] * 3)
+    v = synth.view(33, 33, 0.5, 1000.0, 600.0, 0.0)
+    got = ref.pixel_margins(sc, [v], [[0, 16, 16]], opts=dict(t_min=0.2))[0]
+    assert got == pytest.approx(0.25, abs=1e-12)
+    got = ref.pixel_margins(sc, [v], [[0, 16, 16]])[0]
+    assert got == pytest.approx(0.49 / 0.99, abs=1e-12)
+
+
 def test_parallel_beam_limit_equals_ray_maximum():
     """SID, SDD -> infinity at fixed ratio: the local-affine projection becomes
     exact and the footprint equals the maximum of the 3D Gaussian along each
