@@ -91,6 +91,51 @@ __device__ __forceinline__ float wave_sum_to_lane63(float x)
     return x;
 }
 
+// Sums 64 per-lane values over the wave at once: afterwards v[0] of lane l
+// holds the wave total of v[l].  Transposing butterfly: every step pairs
+// values i and i + h, each half of the lane pairs keeps one of them and adds
+// the partner's copy, so the per-lane work halves every step (63 additions
+// in all, instead of 6 per value).  The cross-row steps swap register
+// halves with v_permlane32_swap / v_permlane16_swap; the in-row steps pair
+// lane bits 3, 2, 1, 0 through row_mirror, row_half_mirror and the two quad
+// permutations, each of which maps a lane to one whose bit differs.
+__device__ __forceinline__ void wave_transpose_sum64(float (&v)[64])
+{
+    const uint32_t lane = __lane_id();
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 32]),
+                                                        false, false);
+        v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 16]),
+                                                        false, false);
+        v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const float keep = b3 ? v[i + 8] : v[i], send = b3 ? v[i] : v[i + 8];
+        v[i] = keep + dpp_move<0x140>(send);  // row_mirror: l <-> 15 - l
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float keep = b2 ? v[i + 4] : v[i], send = b2 ? v[i] : v[i + 4];
+        v[i] = keep + dpp_move<0x141>(send);  // row_half_mirror: l <-> 7 - l
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const float keep = b1 ? v[i + 2] : v[i], send = b1 ? v[i] : v[i + 2];
+        v[i] = keep + dpp_move<0x4E>(send);   // quad_perm [2,3,0,1]: l <-> l ^ 2
+    }
+    {
+        const float keep = b0 ? v[1] : v[0], send = b0 ? v[0] : v[1];
+        v[0] = keep + dpp_move<0xB1>(send);   // quad_perm [1,0,3,2]: l <-> l ^ 1
+    }
+}
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
 {
     const int lane = (int)__lane_id();

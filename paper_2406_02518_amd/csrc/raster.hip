@@ -54,26 +54,32 @@ struct Item {
     int chunk;
 };
 
-// Resolves work item `it`; false when `it` is past the last item.
-__device__ __forceinline__ bool resolve_item(const RasterArgs &a, int it, Item &r)
+// Resolves work item `it`; tile < 0 when `it` is past the last item.  The
+// item is built in registers and returned whole (field-wise stores through
+// a reference were kept in scratch memory by the compiler).
+__device__ __forceinline__ Item resolve_item(const RasterArgs &a, int it)
 {
-    if (a.split == 0) {
-        if (it >= a.n_tiles) return false;
-        const uint2 rg = a.ranges[it];
-        r.tile = it;
-        r.b = rg.x;
-        r.e = rg.y;
-        r.chunk = 0;
-        return true;
+    int tile = -1, chunk = 0;
+    uint32_t b = 0, e = 0;
+    if (it != 0x7FFFFFFF) {
+        if (a.split == 0) {
+            if (it < a.n_tiles) {
+                const uint2 rg = a.ranges[it];
+                tile = it;
+                b = rg.x;
+                e = rg.y;
+            }
+        } else if (it < (int)*a.n_items) {
+            const uint2 q = a.items[it];
+            const uint2 rg = a.ranges[q.x];
+            tile = (int)q.x;
+            chunk = (int)q.y;
+            b = rg.x + q.y * (uint32_t)a.split;
+            e = min(rg.y, b + (uint32_t)a.split);
+        }
     }
-    if (it >= (int)*a.n_items) return false;
-    const uint2 q = a.items[it];
-    const uint2 rg = a.ranges[q.x];
-    r.tile = (int)q.x;
-    r.chunk = (int)q.y;
-    r.b = rg.x + q.y * (uint32_t)a.split;
-    r.e = min(rg.y, r.b + (uint32_t)a.split);
-    return true;
+    return Item{__builtin_amdgcn_readfirstlane(tile), (uint32_t)__builtin_amdgcn_readfirstlane((int)b),
+                (uint32_t)__builtin_amdgcn_readfirstlane((int)e), __builtin_amdgcn_readfirstlane(chunk)};
 }
 
 // Next work item of this workgroup: its block index once, or (persistent
@@ -107,8 +113,8 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
     int iter = 0;
     for (;;) {
         const int it = next_item(a, iter, &sh_item);
-        Item I;
-        if (it == 0x7FFFFFFF || !resolve_item(a, it, I)) break;
+        const Item I = resolve_item(a, it);
+        if (I.tile < 0) break;
         const int v = view_of_tile(a.views, a.V, I.tile);
         const ViewDev &V = a.views[v];
         const int lt = I.tile - V.tile_base;
@@ -215,19 +221,21 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
 {
     constexpr int NT = TW * TH;
     constexpr int NW = NT / kWave;
+    constexpr int NA = NW > 1 ? NW : 1, NTA = NW > 1 ? NT : 1;
     __shared__ float4 s0[NT];
     __shared__ float4 s1[NT];
     __shared__ uint32_t se[NT];
-    __shared__ float acc[NW][7][NT];
+    __shared__ __align__(16) float acc[NA][NTA][8];  // several waves: per-wave entry sums
     __shared__ uint32_t wmax[NW];
     __shared__ int sh_item;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
     const float k2 = a.o.kappa2, smax = a.o.sigma_max, tmin = a.o.t_min;
+    float *slotf = reinterpret_cast<float *>(a.slot);
     int iter = 0;
     for (;;) {
         const int it = next_item(a, iter, &sh_item);
-        Item I;
-        if (it == 0x7FFFFFFF || !resolve_item(a, it, I)) break;
+        const Item I = resolve_item(a, it);
+        if (I.tile < 0) break;
         const int v = view_of_tile(a.views, a.V, I.tile);
         const ViewDev &V = a.views[v];
         const int lt = I.tile - V.tile_base;
@@ -276,67 +284,95 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
             }
             __syncthreads();
             if (b0 < end) {
-                for (int q = 0; q < cnt; ++q) {
-                    const float4 r0 = s0[q];
-                    const float4 r1 = s1[q];
-                    const float dx = __fsub_rn(fpx, r0.x), dy = __fsub_rn(fpy, r0.y);
-                    const float d2 = maha2(dx, dy, r0.z, r0.w, r1.x);
-                    float gv[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                    const bool hit = d2 <= k2 && !done && (b0 + (uint32_t)q) < lastp;
-                    if (hit) {
-                        const float G = __expf(__fmul_rn(-0.5f, d2));
-                        const float sraw = __fmul_rn(r1.y, G);
-                        const float s = fminf(smax, sraw);
-                        const float om = __fsub_rn(1.0f, s);
-                        if (tmin > 0.0f && __fmul_rn(T, om) < tmin) {
-                            done = true;
-                        } else {
-                            const float c = r1.z;
-                            Cacc = __fmaf_rn(__fmul_rn(c, s), T, Cacc);
-                            const float S = Cf - Cacc;
-                            const float ds = g * (c * T - __fdividef(S, om));
-                            gv[6] = g * s * T;
-                            if (!(sraw > smax)) {
-                                gv[5] = ds * G;
-                                const float dd2 = -0.5f * G * r1.y * ds;
-                                gv[0] = -2.0f * dd2 * (r0.z * dx + r0.w * dy);
-                                gv[1] = -2.0f * dd2 * (r0.w * dx + r1.x * dy);
-                                gv[2] = dd2 * dx * dx;
-                                gv[3] = 2.0f * dd2 * dx * dy;
-                                gv[4] = dd2 * dy * dy;
+                // groups of 8 entries: 7 gradient terms + a zero pad each, one
+                // transposing wave sum per group; lane l ends with term l & 7
+                // of entry l >> 3
+                for (int q0 = 0; q0 < cnt; q0 += 8) {
+                    float gb[64];
+                    bool any = false;
+#pragma unroll
+                    for (int qq = 0; qq < 8; ++qq) {
+                        float gv[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                        const int q = q0 + qq;
+                        if (q < cnt) {
+                            const float4 r0 = s0[q];
+                            const float4 r1 = s1[q];
+                            const float dx = __fsub_rn(fpx, r0.x), dy = __fsub_rn(fpy, r0.y);
+                            const float d2 = maha2(dx, dy, r0.z, r0.w, r1.x);
+                            const bool hit = d2 <= k2 && !done && (b0 + (uint32_t)q) < lastp;
+                            if (hit) {
+                                const float G = __expf(__fmul_rn(-0.5f, d2));
+                                const float sraw = __fmul_rn(r1.y, G);
+                                const float s = fminf(smax, sraw);
+                                const float om = __fsub_rn(1.0f, s);
+                                if (tmin > 0.0f && __fmul_rn(T, om) < tmin) {
+                                    done = true;
+                                } else {
+                                    any = true;
+                                    const float c = r1.z;
+                                    Cacc = __fmaf_rn(__fmul_rn(c, s), T, Cacc);
+                                    const float S = Cf - Cacc;
+                                    const float ds = g * (c * T - __fdividef(S, om));
+                                    gv[6] = g * s * T;
+                                    if (!(sraw > smax)) {
+                                        gv[5] = ds * G;
+                                        const float dd2 = -0.5f * G * r1.y * ds;
+                                        gv[0] = -2.0f * dd2 * (r0.z * dx + r0.w * dy);
+                                        gv[1] = -2.0f * dd2 * (r0.w * dx + r1.x * dy);
+                                        gv[2] = dd2 * dx * dx;
+                                        gv[3] = 2.0f * dd2 * dx * dy;
+                                        gv[4] = dd2 * dy * dy;
+                                    }
+                                    T = __fmul_rn(T, om);
+                                }
                             }
-                            T = __fmul_rn(T, om);
                         }
-                    }
-                    if (__ballot(hit) != 0ull) {
 #pragma unroll
-                        for (int c = 0; c < 7; ++c) gv[c] = wave_sum_to_lane63(gv[c]);
+                        for (int c = 0; c < 7; ++c) gb[qq * 8 + c] = gv[c];
+                        gb[qq * 8 + 7] = 0.0f;
                     }
-                    if (lane == kWave - 1) {
-#pragma unroll
-                        for (int c = 0; c < 7; ++c) acc[w][c][q] = gv[c];
+                    float res = 0.0f;
+                    if (__ballot(any) != 0ull) {
+                        wave_transpose_sum64(gb);
+                        res = gb[0];
+                    }
+                    const int q = q0 + (lane >> 3);
+                    if (q < cnt) {
+                        if constexpr (NW == 1) {
+                            const size_t e = se[q];
+                            if (e < a.slot_cap) slotf[8 * e + (lane & 7)] = res;
+                        } else {
+                            acc[w][q][lane & 7] = res;
+                        }
                     }
                 }
             }
-            __syncthreads();
-            if (tid < cnt) {
-                float r[7];
-                if (b0 < end) {
+            if constexpr (NW > 1) {
+                __syncthreads();
+                if (tid < cnt) {
+                    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
+                    if (b0 < end) {
 #pragma unroll
-                    for (int c = 0; c < 7; ++c) {
-                        float x = acc[0][c][tid];
-#pragma unroll
-                        for (int q = 1; q < NW; ++q) x += acc[q][c][tid];
-                        r[c] = x;
+                        for (int q = 0; q < NW; ++q) {
+                            const float4 x0 = *reinterpret_cast<const float4 *>(&acc[q][tid][0]);
+                            const float4 x1 = *reinterpret_cast<const float4 *>(&acc[q][tid][4]);
+                            r0.x += x0.x; r0.y += x0.y; r0.z += x0.z; r0.w += x0.w;
+                            r1.x += x1.x; r1.y += x1.y; r1.z += x1.z;
+                        }
                     }
-                } else {
-#pragma unroll
-                    for (int c = 0; c < 7; ++c) r[c] = 0.0f;
+                    const size_t e = se[tid];
+                    if (e < a.slot_cap) {
+                        a.slot[2 * e] = r0;
+                        a.slot[2 * e + 1] = r1;
+                    }
                 }
-                const size_t e = se[tid];
-                if (e < a.slot_cap) {
-                    a.slot[2 * e] = make_float4(r[0], r[1], r[2], r[3]);
-                    a.slot[2 * e + 1] = make_float4(r[4], r[5], r[6], 0.0f);
+            } else {
+                if (b0 >= end && tid < cnt) {
+                    const size_t e = se[tid];
+                    if (e < a.slot_cap) {
+                        a.slot[2 * e] = make_float4(0.f, 0.f, 0.f, 0.f);
+                        a.slot[2 * e + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
                 }
             }
         }
