@@ -106,6 +106,8 @@ ddgs_status fail(ddgs_ctx *c, ddgs_status s, const std::string &msg)
         if (s_ != DDGS_OK) return s_;   \
     } while (0)
 
+// (Re)allocates a workspace buffer of at least `bytes` (contents undefined).
+// Never called while a stream capture is open.
 ddgs_status ensure(ddgs_ctx *c, const char *name, size_t bytes, void **out)
 {
     DevBuf &b = c->bufs[name];
@@ -335,10 +337,11 @@ ddgs_status ensure_entries(ddgs_ctx *c, int64_t cap)
     DDGS_TRY(ensure_t(c, "item_base", std::max(1, c->n_tiles), &u));
     DDGS_TRY(ensure_t(c, "part", (size_t)(split > 0 ? max_items : 1) * c->opt.tile_w * c->opt.tile_h, &f2));
     const int64_t big = std::max<int64_t>({VN, cap, (int64_t)c->n_tiles, 1});
-    const size_t cw = radix_counts_words(big);
-    DDGS_TRY(ensure_t(c, "radix_counts", cw, &u));
-    void *p;
-    DDGS_TRY(ensure(c, "scan_tmp", scan_tmp_bytes(std::max<int64_t>((int64_t)cw, big)), &p));
+    uint64_t *st;
+    DDGS_TRY(ensure_t(c, "sort_counts", sort_counts_words(big), &u));
+    DDGS_TRY(ensure_t(c, "sort_tot", 256, &u));
+    uint64_t *bs;
+    DDGS_TRY(ensure_t(c, "sort_bsum", sort_blocksum_words(big), &bs));
     c->entry_cap = std::max(c->entry_cap, cap);
     return DDGS_OK;
 }
@@ -357,13 +360,32 @@ void stage_end(ddgs_ctx *c, int i)
 
 // device scalars: [0..1] u64 entry total, [2] entries kept (min(total, cap)),
 // [3] flags (bit 0: capacity overflow), [4], [5] work-queue counters,
-// [8..9] u64 scratch total of the radix-sort scans
+// [6] work items, [8..9] u64 scratch total
 uint64_t *total_ptr(ddgs_ctx *c) { return (uint64_t *)buf<uint32_t>(c, "scalars"); }
 uint32_t *mdev_ptr(ddgs_ctx *c) { return buf<uint32_t>(c, "scalars") + 2; }
 uint32_t *flags_ptr(ddgs_ctx *c) { return buf<uint32_t>(c, "scalars") + 3; }
 uint32_t *counter_ptr(ddgs_ctx *c) { return buf<uint32_t>(c, "scalars") + 4; }
 uint64_t *sort_total_ptr(ddgs_ctx *c) { return (uint64_t *)(buf<uint32_t>(c, "scalars") + 8); }
 uint32_t *n_items_ptr(ddgs_ctx *c) { return buf<uint32_t>(c, "scalars") + 6; }
+SortWs sort_ws(ddgs_ctx *c)
+{
+    return SortWs{buf<uint32_t>(c, "sort_counts"), buf<uint32_t>(c, "sort_tot"), buf<uint64_t>(c, "sort_bsum"),
+                  c->bufs["sort_counts"].bytes / sizeof(uint32_t), c->bufs["sort_bsum"].bytes / sizeof(uint64_t)};
+}
+
+// Sort / scan temporaries of the debug entry points (own buffers, so a debug
+// call leaves the render state alone).
+ddgs_status debug_ws(ddgs_ctx *c, int64_t n, SortWs *ws)
+{
+    uint32_t *u;
+    uint64_t *bs;
+    DDGS_TRY(ensure_t(c, "dbg_counts", sort_counts_words(std::max<int64_t>(n, 1)), &u));
+    DDGS_TRY(ensure_t(c, "dbg_tot", 256, &u));
+    DDGS_TRY(ensure_t(c, "dbg_bsum", sort_blocksum_words(std::max<int64_t>(n, 1)), &bs));
+    *ws = SortWs{buf<uint32_t>(c, "dbg_counts"), buf<uint32_t>(c, "dbg_tot"), buf<uint64_t>(c, "dbg_bsum"),
+                 c->bufs["dbg_counts"].bytes / sizeof(uint32_t), c->bufs["dbg_bsum"].bytes / sizeof(uint64_t)};
+    return DDGS_OK;
+}
 
 // Work-item fields shared by the forward and backward raster launches.
 void set_items(ddgs_ctx *c, RasterArgs &ra, bool backward)
@@ -399,11 +421,9 @@ ddgs_status enqueue_front(ddgs_ctx *c)
     stage_begin(c, DDGS_T_SORT);
     bool in_k1 = false;
     HIP_TRY(c, radix_sort_pairs(po.sort_key, po.sort_val, buf<uint32_t>(c, "skey2"), buf<uint32_t>(c, "sval2"), VN,
-                                nullptr, 32, buf<uint32_t>(c, "radix_counts"), buf<void>(c, "scan_tmp"),
-                                sort_total_ptr(c), &in_k1, s));
+                                nullptr, 32, sort_ws(c), &in_k1, s));
     const uint32_t *order = in_k1 ? buf<uint32_t>(c, "sval2") : po.sort_val;
-    HIP_TRY(c, launch_exclusive_scan(po.cnt, order, buf<uint32_t>(c, "off_sorted"), VN, buf<void>(c, "scan_tmp"),
-                                     total_ptr(c), s));
+    HIP_TRY(c, launch_exclusive_scan(po.cnt, order, buf<uint32_t>(c, "off_sorted"), VN, sort_ws(c), total_ptr(c), s));
     return DDGS_OK;
 }
 
@@ -428,8 +448,7 @@ ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, int64_t sort_n, float *images
     }
     bool in_k1 = false;
     HIP_TRY(c, radix_sort_pairs(tkey, tval, buf<uint32_t>(c, "tkey2"), buf<uint32_t>(c, "tval2"), sort_n, mdev_ptr(c),
-                                bits_for(c->n_tiles), buf<uint32_t>(c, "radix_counts"), buf<void>(c, "scan_tmp"),
-                                sort_total_ptr(c), &in_k1, s));
+                                bits_for(c->n_tiles), sort_ws(c), &in_k1, s));
     c->tkey_sorted = in_k1 ? buf<uint32_t>(c, "tkey2") : tkey;
     c->tval_sorted = in_k1 ? buf<uint32_t>(c, "tval2") : tval;
     HIP_TRY(c, launch_ranges(c->tkey_sorted, mdev_ptr(c), sort_n, buf<uint2>(c, "ranges"), c->n_tiles, s));
@@ -439,15 +458,13 @@ ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, int64_t sort_n, float *images
     if (split > 0) {
         HIP_TRY(c, launch_items(buf<uint2>(c, "ranges"), c->n_tiles, split, buf<uint32_t>(c, "item_cnt"),
                                 buf<uint32_t>(c, "item_base"), buf<uint2>(c, "items"), (uint32_t)c->max_items,
-                                buf<void>(c, "scan_tmp"), sort_total_ptr(c), n_items_ptr(c), counter_ptr(c), s));
+                                sort_ws(c), sort_total_ptr(c), n_items_ptr(c), counter_ptr(c), s));
     } else if (c->opt.persistent) {
         bool qk1 = false;
         HIP_TRY(c, launch_tile_cost_keys(buf<uint2>(c, "ranges"), c->n_tiles, buf<uint32_t>(c, "qkey"),
                                          buf<uint32_t>(c, "qval"), counter_ptr(c), s));
         HIP_TRY(c, radix_sort_pairs(buf<uint32_t>(c, "qkey"), buf<uint32_t>(c, "qval"), buf<uint32_t>(c, "qkey2"),
-                                    buf<uint32_t>(c, "qval2"), c->n_tiles, nullptr, 24,
-                                    buf<uint32_t>(c, "radix_counts"), buf<void>(c, "scan_tmp"), sort_total_ptr(c),
-                                    &qk1, s));
+                                    buf<uint32_t>(c, "qval2"), c->n_tiles, nullptr, 24, sort_ws(c), &qk1, s));
         c->queue = qk1 ? buf<uint32_t>(c, "qval2") : buf<uint32_t>(c, "qval");
     }
     stage_end(c, DDGS_T_SORT);
@@ -778,9 +795,10 @@ ddgs_status ddgs_render(ddgs_ctx *c, float *images)
     const int64_t VN = c->model.n * (int64_t)c->views_h.size();
     if (VN > 0) {
         DDGS_TRY(enqueue_front(c));
-        uint64_t total = 0;
-        HIP_TRY(c, hipMemcpyAsync(&total, total_ptr(c), sizeof(total), hipMemcpyDeviceToHost, c->stream));
+        uint32_t sc[4] = {0, 0, 0, 0};
+        HIP_TRY(c, hipMemcpyAsync(sc, total_ptr(c), sizeof(sc), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
+        const uint64_t total = (uint64_t)sc[0] | ((uint64_t)sc[1] << 32);
         if (total >= 0xFFFFFFFFull) return fail(c, DDGS_ERR_CAPACITY, "more than 2^32-1 tile entries");
         c->M = (int64_t)total;
         if (c->M > c->entry_cap) DDGS_TRY(ensure_entries(c, c->M));
@@ -1030,17 +1048,13 @@ ddgs_status ddgs_debug_sort_pairs(ddgs_ctx *c, uint32_t *keys, uint32_t *vals, i
     if (n > 0xFFFFFFFFll) return fail(c, DDGS_ERR_INVALID_ARG, "n too large");
     if (n == 0) return DDGS_OK;
     HIP_TRY(c, hipSetDevice(c->device));
-    uint32_t *k1, *v1, *counts;
+    uint32_t *k1, *v1;
     DDGS_TRY(ensure_t(c, "dbg_k1", n, &k1));
     DDGS_TRY(ensure_t(c, "dbg_v1", n, &v1));
-    const size_t cw = radix_counts_words(n);
-    DDGS_TRY(ensure_t(c, "dbg_counts", cw, &counts));
-    void *tmp;
-    DDGS_TRY(ensure(c, "dbg_scan", scan_tmp_bytes(std::max<int64_t>((int64_t)cw, n)), &tmp));
-    uint64_t *tot;
-    DDGS_TRY(ensure_t(c, "dbg_total", 1, &tot));
+    SortWs ws{};
+    DDGS_TRY(debug_ws(c, n, &ws));
     bool in_k1 = false;
-    HIP_TRY(c, radix_sort_pairs(keys, vals, k1, v1, n, nullptr, bits, counts, tmp, tot, &in_k1, c->stream));
+    HIP_TRY(c, radix_sort_pairs(keys, vals, k1, v1, n, nullptr, bits, ws, &in_k1, c->stream));
     if (in_k1) {
         HIP_TRY(c, launch_copy_u32(keys, k1, nullptr, n, c->stream));
         HIP_TRY(c, launch_copy_u32(vals, v1, nullptr, n, c->stream));
@@ -1053,11 +1067,11 @@ ddgs_status ddgs_debug_exclusive_scan(ddgs_ctx *c, const uint32_t *in, uint32_t 
 {
     if (!c || n < 0 || (n > 0 && (!in || !out))) return fail(c, DDGS_ERR_INVALID_ARG, "bad scan arguments");
     HIP_TRY(c, hipSetDevice(c->device));
-    void *tmp;
-    DDGS_TRY(ensure(c, "dbg_scan", scan_tmp_bytes(std::max<int64_t>(n, 1)), &tmp));
+    SortWs ws{};
+    DDGS_TRY(debug_ws(c, n, &ws));
     uint64_t *tot;
     DDGS_TRY(ensure_t(c, "dbg_total", 1, &tot));
-    HIP_TRY(c, launch_exclusive_scan(in, nullptr, out, n, tmp, tot, c->stream));
+    HIP_TRY(c, launch_exclusive_scan(in, nullptr, out, n, ws, tot, c->stream));
     uint64_t h = 0;
     HIP_TRY(c, hipMemcpyAsync(&h, tot, sizeof(h), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));

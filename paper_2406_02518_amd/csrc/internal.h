@@ -157,8 +157,9 @@ hipError_t launch_project(const ModelDev &m, const GaussCache &gc, const ViewDev
 
 // Backward of the projection: sums each (view, Gaussian)'s gradient slots,
 // applies the chain rule to the parameters, and writes per-wave pose partials
-// [V][n_waves][9] and per-Gaussian basis terms ubuf ([k_L][n] for directional,
-// [0][i] = d z for isotropic).
+// [V][n_waves][9] and per-Gaussian basis terms ubuf ([n][16]: the k_L
+// direction terms of a directional Gaussian, or d z of an isotropic one in
+// column 15).
 struct ProjBwdArgs {
     ModelDev m;
     GaussCache gc;
@@ -168,7 +169,7 @@ struct ProjBwdArgs {
     const uint32_t *cnt, *offs;
     const float4 *slot;
     float *dmean, *dquat, *dlog_scale, *dopacity, *dfeat;  // NULL: skip
-    float *ubuf;        // [k_L][n] (NULL: skip basis terms)
+    float *ubuf;        // [n][16] (NULL: skip basis terms)
     float *pose_part;   // [V][n_waves][9]
     int per_gaussian;   // 0: pose only
     uint32_t slot_cap;  // number of gradient slots (entries beyond are ignored)
@@ -184,17 +185,25 @@ hipError_t launch_pose_final(const ViewDev *views, int V, int n_waves, const flo
 
 // sort.hip
 constexpr int kScanTile = 4096;
-size_t scan_tmp_bytes(int64_t n);
+
+// Temporaries of the scans and radix sorts (device memory).
+struct SortWs {
+    uint32_t *counts;      // [counts_words]: per-block digit counts, then offsets
+    uint32_t *tot;         // [256]: digit totals of the current pass
+    uint64_t *blocksum;    // [blocksum_words]: scan block sums
+    size_t counts_words, blocksum_words;
+};
+// words of SortWs::counts / ::blocksum for sorts and scans of up to n elements
+size_t sort_counts_words(int64_t n);
+size_t sort_blocksum_words(int64_t n);
 // out[i] = sum_{j<i} in[g(j)] with g = gather ? gather[j] : j; *total (device u64) = sum.
 hipError_t launch_exclusive_scan(const uint32_t *in, const uint32_t *gather, uint32_t *out, int64_t n,
-                                 void *tmp, uint64_t *total, hipStream_t s);
-size_t radix_counts_words(int64_t n_cap);
+                                 const SortWs &ws, uint64_t *total, hipStream_t s);
 // Sorts (keys, vals) by key bits [0, bits) (stable).  n_dev (may be NULL)
 // limits the count at run time to min(*n_dev, n_cap).  Ping-pongs between
 // (k0, v0) and (k1, v1); *in_k1 tells where the result ended.
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n_cap,
-                            const uint32_t *n_dev, int bits, uint32_t *counts, void *scan_tmp,
-                            uint64_t *scan_total, bool *in_k1, hipStream_t s);
+                            const uint32_t *n_dev, int bits, const SortWs &ws, bool *in_k1, hipStream_t s);
 hipError_t launch_emit(int64_t VN, int n, const uint32_t *order, const uint32_t *off_sorted,
                        const uint32_t *cnt, const uint2 *rect, const ViewDev *views,
                        uint32_t *offs, uint32_t *tkey, uint32_t *tval, uint32_t capacity,
@@ -243,7 +252,7 @@ hipError_t launch_tile_cost_keys(const uint2 *ranges, int n_tiles, uint32_t *key
 // work items of `split` entries: per-tile counts and bases, the item list,
 // the device item count; also clears the two work-queue counters
 hipError_t launch_items(const uint2 *ranges, int n_tiles, int split, uint32_t *cnt, uint32_t *base, uint2 *items,
-                        uint32_t max_items, void *scan_tmp, uint64_t *scan_total, uint32_t *n_items,
+                        uint32_t max_items, const SortWs &ws, uint64_t *scan_total, uint32_t *n_items,
                         uint32_t *counter, hipStream_t s);
 bool raster_tile_supported(int tw, int th);
 

@@ -469,12 +469,12 @@ hipError_t launch_tile_cost_keys(const uint2 *ranges, int n_tiles, uint32_t *key
 }
 
 hipError_t launch_items(const uint2 *ranges, int n_tiles, int split, uint32_t *cnt, uint32_t *base, uint2 *items,
-                        uint32_t max_items, void *scan_tmp, uint64_t *scan_total, uint32_t *n_items,
+                        uint32_t max_items, const SortWs &ws, uint64_t *scan_total, uint32_t *n_items,
                         uint32_t *counter, hipStream_t s)
 {
     const int nb = (n_tiles + 255) / 256 + (n_tiles == 0);
     chunk_count_kernel<<<nb, 256, 0, s>>>(ranges, n_tiles, split, cnt);
-    hipError_t e = launch_exclusive_scan(cnt, nullptr, base, n_tiles, scan_tmp, scan_total, s);
+    hipError_t e = launch_exclusive_scan(cnt, nullptr, base, n_tiles, ws, scan_total, s);
     if (e != hipSuccess) return e;
     expand_items_kernel<<<nb, 256, 0, s>>>(cnt, base, n_tiles, items, max_items, scan_total, n_items, counter);
     return hipGetLastError();

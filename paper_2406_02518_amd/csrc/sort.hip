@@ -20,8 +20,8 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kScanIPT = kScanTile / kBlock;  // 16
-constexpr int kRadixIPT = 8;
-constexpr int kRadixTile = kBlock * kRadixIPT;  // 2048
+constexpr int kRadixIPT = 16;
+constexpr int kRadixTile = kBlock * kRadixIPT;  // 4096
 constexpr int kWaves = kBlock / kWave;
 
 // exclusive scan over a block of 256 threads; returns the block total
@@ -42,6 +42,14 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *lds /*
     __syncthreads();
     return before + inc - x;
 }
+
+// ------------------------------------------------------------------- scan
+// Two launches: per-block sums, then every block adds the sums of the blocks
+// before it (read by the block itself, at most kScanSelfMax of them) to its
+// own in-block exclusive scan.  Longer inputs scan the block sums in a third
+// launch in between.  (Chained single-pass scans were measured slower here:
+// every look-back hop is a cross-die round trip.)
+constexpr int64_t kScanSelfMax = (int64_t)kBlock * 16;
 
 __global__ __launch_bounds__(kBlock) void scan_reduce_kernel(const uint32_t *in, const uint32_t *gather,
                                                              int64_t n, uint64_t *blocksum)
@@ -97,18 +105,39 @@ __global__ __launch_bounds__(1024) void scan_top_kernel(uint64_t *blocksum, int6
     if (threadIdx.x == 0 && total) *total = carry_s;
 }
 
+// prescanned: blocksum holds exclusive block offsets (scan_top ran);
+// otherwise the block sums the raw block sums before it, and the last block
+// writes the total.
 __global__ __launch_bounds__(kBlock) void scan_apply_kernel(const uint32_t *in, const uint32_t *gather, int64_t n,
-                                                            const uint64_t *blockoff, uint32_t *out)
+                                                            const uint64_t *blocksum, int prescanned, uint32_t *out,
+                                                            uint64_t *total)
 {
     __shared__ uint32_t tile[kScanTile];
     __shared__ uint32_t wl[kWaves];
+    __shared__ uint64_t red[kWaves];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
 #pragma unroll 4
     for (int q = 0; q < kScanIPT; ++q) {
         const int64_t idx = base + q * kBlock + threadIdx.x;
         tile[q * kBlock + threadIdx.x] = idx < n ? in[gather ? gather[idx] : idx] : 0u;
     }
+    uint64_t off;
+    if (prescanned) {
+        off = blocksum[blockIdx.x];
+    } else {
+        uint64_t s = 0;
+        for (int j = threadIdx.x; j < (int)blockIdx.x; j += kBlock) s += blocksum[j];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
+        if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
+    }
     __syncthreads();
+    if (!prescanned) {
+        off = 0;
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) off += red[q];
+        if (threadIdx.x == 0 && total && blockIdx.x == gridDim.x - 1) *total = off + blocksum[blockIdx.x];
+    }
     uint32_t v[kScanIPT], s = 0;
 #pragma unroll
     for (int q = 0; q < kScanIPT; ++q) {
@@ -123,15 +152,18 @@ __global__ __launch_bounds__(kBlock) void scan_apply_kernel(const uint32_t *in, 
         pre += v[q];
     }
     __syncthreads();
-    const uint32_t off = (uint32_t)blockoff[blockIdx.x];
+    const uint32_t off32 = (uint32_t)off;
 #pragma unroll 4
     for (int q = 0; q < kScanIPT; ++q) {
         const int64_t idx = base + q * kBlock + threadIdx.x;
-        if (idx < n) out[idx] = off + tile[q * kBlock + threadIdx.x];
+        if (idx < n) out[idx] = off32 + tile[q * kBlock + threadIdx.x];
     }
 }
 
 // ------------------------------------------------------------- radix sort
+// One pass = three launches: per-block digit counts (digit-major), one block
+// per digit turning its row into offsets across blocks plus the digit total,
+// and the stable scatter, which adds the digit's start to its own offset.
 
 __device__ __forceinline__ int64_t runtime_n(int64_t n_cap, const uint32_t *n_dev)
 {
@@ -140,8 +172,8 @@ __device__ __forceinline__ int64_t runtime_n(int64_t n_cap, const uint32_t *n_de
     return m < n_cap ? m : n_cap;
 }
 
-__global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t *kin, int64_t n_cap, const uint32_t *n_dev,
-                                                            int shift, uint32_t mask, uint32_t *counts, int nblocks)
+__global__ __launch_bounds__(kBlock) void radix_count_kernel(const uint32_t *kin, int64_t n_cap, const uint32_t *n_dev,
+                                                             int shift, uint32_t mask, uint32_t *counts, int nblocks)
 {
     __shared__ uint32_t h[kWaves][256];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -149,10 +181,10 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t *kin,
     for (int q = 0; q < 256 / kWave; ++q) h[w][lane + q * kWave] = 0;
     __syncthreads();
     const int64_t n = runtime_n(n_cap, n_dev);
-    const int64_t base = (int64_t)blockIdx.x * kRadixTile + w * (kRadixTile / kWaves);
-#pragma unroll
+    const int64_t wbase = (int64_t)blockIdx.x * kRadixTile + w * (kRadixTile / kWaves);
+#pragma unroll 4
     for (int r = 0; r < kRadixIPT; ++r) {
-        const int64_t idx = base + r * kWave + lane;
+        const int64_t idx = wbase + r * kWave + lane;
         if (idx < n) atomicAdd(&h[w][(kin[idx] >> shift) & mask], 1u);
     }
     __syncthreads();
@@ -160,14 +192,54 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t *kin,
     counts[(size_t)d * nblocks + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
 }
 
-// Stable scatter: every wave ranks its 8 rounds of 64 consecutive keys with
+// Block d: exclusive scan of counts[d][0, nblocks) in place; tot[d] = row sum.
+__global__ __launch_bounds__(kBlock) void radix_prefix_kernel(uint32_t *counts, int nblocks, uint32_t *tot)
+{
+    __shared__ uint32_t tile[kScanTile];
+    __shared__ uint32_t wl[kWaves];
+    uint32_t *row = counts + (size_t)blockIdx.x * nblocks;
+    uint32_t carry = 0;
+    for (int c0 = 0; c0 < nblocks; c0 += kScanTile) {
+        __syncthreads();
+#pragma unroll 4
+        for (int q = 0; q < kScanIPT; ++q) {
+            const int idx = c0 + q * kBlock + threadIdx.x;
+            tile[q * kBlock + threadIdx.x] = idx < nblocks ? row[idx] : 0u;
+        }
+        __syncthreads();
+        uint32_t v[kScanIPT], sum = 0;
+#pragma unroll
+        for (int q = 0; q < kScanIPT; ++q) {
+            v[q] = tile[threadIdx.x * kScanIPT + q];
+            sum += v[q];
+        }
+        uint32_t t;
+        uint32_t pre = carry + block_excl_scan(sum, wl, t);
+#pragma unroll
+        for (int q = 0; q < kScanIPT; ++q) {
+            tile[threadIdx.x * kScanIPT + q] = pre;
+            pre += v[q];
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int q = 0; q < kScanIPT; ++q) {
+            const int idx = c0 + q * kBlock + threadIdx.x;
+            if (idx < nblocks) row[idx] = tile[q * kBlock + threadIdx.x];
+        }
+        carry += t;
+    }
+    if (threadIdx.x == 0) tot[blockIdx.x] = carry;
+}
+
+// Stable scatter: every wave ranks its 16 rounds of 64 consecutive keys with
 // ballots (lanes sharing the digit), the block combines the 4 wave
 // histograms, the keys are staged in LDS in digit order and written out
 // with consecutive lanes on consecutive addresses.
 __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *kin, const uint32_t *vin,
                                                                uint32_t *kout, uint32_t *vout, int64_t n_cap,
                                                                const uint32_t *n_dev, int shift, int nbits,
-                                                               const uint32_t *offsets, int nblocks)
+                                                               const uint32_t *offsets, const uint32_t *tot,
+                                                               int nblocks)
 {
     __shared__ uint32_t wh[kWaves][256];
     __shared__ uint32_t bstart[256];
@@ -215,9 +287,10 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *k
         wh[1][d] = c0;
         wh[2][d] = c0 + c1;
         wh[3][d] = c0 + c1 + c2;
-        uint32_t tot;
-        bstart[d] = block_excl_scan(c0 + c1 + c2 + c3, wl, tot);
-        gbase[d] = offsets[(size_t)d * nblocks + blockIdx.x];
+        uint32_t t;
+        bstart[d] = block_excl_scan(c0 + c1 + c2 + c3, wl, t);
+        const uint32_t dstart = block_excl_scan(tot[d], wl, t);
+        gbase[d] = dstart + offsets[(size_t)d * nblocks + blockIdx.x];
     }
     __syncthreads();
 #pragma unroll
@@ -243,8 +316,12 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *k
 
 // ------------------------------------------------------------------ emit
 
-// One thread per (view, Gaussian) in depth order: writes the Gaussian's tile
-// entries at its scanned offset, row-major over its tile rectangle.
+// Entries of the (view, Gaussian) pairs in depth order.  The 64 pairs of a
+// wave own one contiguous output range [off(r0), off(r0 + 63) + cnt), so the
+// lanes walk that range together, consecutive lanes on consecutive entries,
+// and each finds the pair an entry belongs to by a binary search over the
+// wave's 64 offsets (read from the owning lanes by shuffles).  Within a pair
+// the entries run row-major over its tile rectangle.
 __global__ __launch_bounds__(kBlock) void emit_kernel(int64_t VN, int n, const uint32_t *order,
                                                       const uint32_t *off_sorted, const uint32_t *cnt,
                                                       const uint2 *rect, const ViewDev *views, uint32_t *offs,
@@ -252,32 +329,57 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(int64_t VN, int n, const u
                                                       const uint64_t *total, uint32_t *m_out, uint32_t *flags)
 {
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
     if (r == 0) {
         const uint64_t t = *total;
         const bool over = t > (uint64_t)capacity;
         *m_out = over ? capacity : (uint32_t)t;
         if (over) atomicOr(flags, 1u);
     }
-    if (r >= VN) return;
-    const uint32_t vi = order[r];
-    const uint32_t c = cnt[vi];
-    if (c == 0) return;
-    const uint32_t off = off_sorted[r];
-    offs[vi] = off;
-    if (off >= capacity) return;
-    // entries past the capacity are dropped (the overflow flag is set above);
-    // the ones that fit are written so that no stale entry survives
-    const uint32_t e_end = (uint64_t)off + c > (uint64_t)capacity ? capacity : off + c;
-    const uint32_t v = vi / (uint32_t)n, i = vi - v * (uint32_t)n;
-    const ViewDev &V = views[v];
-    const uint2 rc = rect[vi];
-    const int tx0 = rc.x & 0xFFFF, ty0 = rc.x >> 16, tx1 = rc.y & 0xFFFF, ty1 = rc.y >> 16;
-    uint32_t e = off;
-    for (int ty = ty0; ty <= ty1 && e < e_end; ++ty) {
-        const uint32_t row = (uint32_t)V.tile_base + (uint32_t)ty * (uint32_t)V.ntx;
-        for (int tx = tx0; tx <= tx1 && e < e_end; ++tx, ++e) {
-            tkey[e] = row + (uint32_t)tx;
-            tval[e] = i;
+    const bool valid = r < VN;
+    uint32_t c = 0, off = 0xFFFFFFFFu, i = 0, x0y0 = 0, span = 1, rowbase = 0, ntx = 0;
+    if (valid) {
+        const uint32_t vi = order[r];
+        c = cnt[vi];
+        off = off_sorted[r];
+        if (c) {
+            offs[vi] = off;
+            const uint32_t v = vi / (uint32_t)n;
+            i = vi - v * (uint32_t)n;
+            const uint2 rc = rect[vi];
+            x0y0 = rc.x;
+            span = (rc.y & 0xFFFF) - (rc.x & 0xFFFF) + 1u;
+            rowbase = (uint32_t)views[v].tile_base;
+            ntx = (uint32_t)views[v].ntx;
+        }
+    }
+    // the wave's range; lanes past VN hold off = ~0 and never match
+    const uint64_t my_end = valid ? (uint64_t)off + c : 0ull;
+    uint64_t wend = my_end;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wend = max(wend, (uint64_t)__shfl_xor((unsigned long long)wend, o, kWave));
+    if (wend > (uint64_t)capacity) wend = capacity;
+    const uint32_t wbeg = (uint32_t)__shfl((int)off, 0, kWave);
+    // (uniform loop: every lane takes part in the shuffles, since a shuffle
+    // from an inactive lane does not return that lane's value)
+    for (uint64_t e0 = (uint64_t)wbeg; e0 < wend; e0 += kWave) {
+        const uint64_t e = e0 + (uint64_t)lane;
+        int L = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1) {
+            const uint32_t o = (uint32_t)__shfl((int)off, L + step, kWave);
+            if (o != 0xFFFFFFFFu && (uint64_t)o <= e) L += step;
+        }
+        const uint32_t k = (uint32_t)(e - (uint64_t)(uint32_t)__shfl((int)off, L, kWave));
+        const uint32_t sp = (uint32_t)__shfl((int)span, L, kWave);
+        const uint32_t xy = (uint32_t)__shfl((int)x0y0, L, kWave);
+        const uint32_t rb = (uint32_t)__shfl((int)rowbase, L, kWave);
+        const uint32_t nt = (uint32_t)__shfl((int)ntx, L, kWave);
+        const uint32_t gi = (uint32_t)__shfl((int)i, L, kWave);
+        if (e < wend) {
+            const uint32_t dy = k / sp, dx = k - dy * sp;
+            tkey[e] = rb + ((xy >> 16) + dy) * nt + (xy & 0xFFFF) + dx;
+            tval[e] = gi;
         }
     }
 }
@@ -320,37 +422,39 @@ int64_t blocks_for(int64_t n, int64_t per) { return (n + per - 1) / per; }
 
 }  // namespace
 
-size_t scan_tmp_bytes(int64_t n) { return (size_t)(blocks_for(n, kScanTile) + 1) * sizeof(uint64_t); }
+size_t sort_counts_words(int64_t n) { return (size_t)256 * (size_t)std::max<int64_t>(1, blocks_for(n, kRadixTile)); }
+size_t sort_blocksum_words(int64_t n) { return (size_t)std::max<int64_t>(1, blocks_for(n, kScanTile)) + 1; }
 
-hipError_t launch_exclusive_scan(const uint32_t *in, const uint32_t *gather, uint32_t *out, int64_t n, void *tmp,
-                                 uint64_t *total, hipStream_t s)
+hipError_t launch_exclusive_scan(const uint32_t *in, const uint32_t *gather, uint32_t *out, int64_t n,
+                                 const SortWs &ws, uint64_t *total, hipStream_t s)
 {
-    uint64_t *bs = (uint64_t *)tmp;
-    const int64_t nb = blocks_for(n, kScanTile);
     if (n == 0) return total ? launch_zero_u64(total, s) : hipSuccess;
-    scan_reduce_kernel<<<(unsigned)nb, kBlock, 0, s>>>(in, gather, n, bs);
-    scan_top_kernel<<<1, 1024, 0, s>>>(bs, nb, total);
-    scan_apply_kernel<<<(unsigned)nb, kBlock, 0, s>>>(in, gather, n, bs, out);
+    const int64_t nb = blocks_for(n, kScanTile);
+    if (!ws.blocksum || (size_t)nb + 1 > ws.blocksum_words || nb > 0x7FFFFFFF) return hipErrorInvalidValue;
+    scan_reduce_kernel<<<(unsigned)nb, kBlock, 0, s>>>(in, gather, n, ws.blocksum);
+    const bool pre = nb > kScanSelfMax;
+    if (pre) scan_top_kernel<<<1, 1024, 0, s>>>(ws.blocksum, nb, total);
+    scan_apply_kernel<<<(unsigned)nb, kBlock, 0, s>>>(in, gather, n, ws.blocksum, pre ? 1 : 0, out, total);
     return hipGetLastError();
 }
 
-size_t radix_counts_words(int64_t n_cap) { return (size_t)256 * (size_t)std::max<int64_t>(1, blocks_for(n_cap, kRadixTile)); }
-
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n_cap,
-                            const uint32_t *n_dev, int bits, uint32_t *counts, void *scan_tmp, uint64_t *scan_total,
-                            bool *in_k1, hipStream_t s)
+                            const uint32_t *n_dev, int bits, const SortWs &ws, bool *in_k1, hipStream_t s)
 {
     *in_k1 = false;
     if (n_cap <= 0 || bits <= 0) return hipSuccess;
-    const int nblocks = (int)blocks_for(n_cap, kRadixTile);
+    if (bits > 32 || !ws.counts || !ws.tot || sort_counts_words(n_cap) > ws.counts_words) return hipErrorInvalidValue;
+    const int64_t nblocks = blocks_for(n_cap, kRadixTile);
+    if (nblocks > 0x7FFFFFFF) return hipErrorInvalidValue;
     uint32_t *ka = k0, *va = v0, *kb = k1, *vb = v1;
     for (int shift = 0; shift < bits; shift += 8) {
         const int nbits = std::min(8, bits - shift);
         const uint32_t mask = (1u << nbits) - 1u;
-        radix_hist_kernel<<<nblocks, kBlock, 0, s>>>(ka, n_cap, n_dev, shift, mask, counts, nblocks);
-        hipError_t e = launch_exclusive_scan(counts, nullptr, counts, (int64_t)256 * nblocks, scan_tmp, scan_total, s);
-        if (e != hipSuccess) return e;
-        radix_scatter_kernel<<<nblocks, kBlock, 0, s>>>(ka, va, kb, vb, n_cap, n_dev, shift, nbits, counts, nblocks);
+        radix_count_kernel<<<(unsigned)nblocks, kBlock, 0, s>>>(ka, n_cap, n_dev, shift, mask, ws.counts,
+                                                                 (int)nblocks);
+        radix_prefix_kernel<<<256, kBlock, 0, s>>>(ws.counts, (int)nblocks, ws.tot);
+        radix_scatter_kernel<<<(unsigned)nblocks, kBlock, 0, s>>>(ka, va, kb, vb, n_cap, n_dev, shift, nbits,
+                                                                   ws.counts, ws.tot, (int)nblocks);
         std::swap(ka, kb);
         std::swap(va, vb);
         *in_k1 = !*in_k1;

@@ -45,15 +45,17 @@ def test_radix_sort_is_stable_and_bit_exact(R, n, bits, kind):
     np.testing.assert_array_equal(vd.cpu().numpy().view(np.uint32), vals[order])
 
 
-@pytest.mark.parametrize("n", [0, 1, 4095, 4097, 1_000_000])
-def test_exclusive_scan(R, n):
-    x = np.random.default_rng(n).integers(0, 40, size=n).astype(np.uint32)
+@pytest.mark.parametrize("n,hi", [(0, 40), (1, 40), (4095, 40), (4097, 40), (1_000_000, 40), (12_289, 1 << 31)])
+def test_exclusive_scan(R, n, hi):
+    # (hi = 2^31: the total passes 2^32; prefixes wrap, the total stays exact)
+    x = np.random.default_rng(n).integers(0, hi, size=n).astype(np.uint32)
     xd = torch.from_numpy(x.view(np.int32)).cuda()
     yd = torch.zeros(max(n, 1), dtype=torch.int32, device="cuda")
     total = binding.ddgs_debug_exclusive_scan(R.ctx, xd.data_ptr(), yd.data_ptr(), n)
     assert total == int(x.astype(np.uint64).sum())
     if n:
-        exp = np.concatenate([[0], np.cumsum(x.astype(np.uint64))[:-1]]).astype(np.uint32)
+        inc = np.cumsum(x.astype(np.uint64))
+        exp = (np.concatenate([np.zeros(1, np.uint64), inc[:-1]]) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
         np.testing.assert_array_equal(yd.cpu().numpy().view(np.uint32)[:n], exp)
 
 
