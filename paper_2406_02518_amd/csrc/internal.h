@@ -53,9 +53,11 @@ struct ProjOut {
     uint32_t *sort_key, *sort_val;  // [V*n]: depth key and v*n+i, input of the depth sort
 };
 
-// Per-(view, Gaussian) image-plane gradient accumulated by the raster
-// backward, one 8-float slot per tile entry in emission order:
-// d mu^x, d mu^y, d A00, d A01, d A11, d alpha, d c, 0.
+// Per-(view, Gaussian) image-plane gradient terms accumulated by the raster
+// backward, one 8-float slot per tile entry in emission order: with
+// q = dL/ds G at each hit pixel (0 where sigma_max clamps) and (dx, dy) =
+// pixel - mean, the sums over the tile's pixels of q dx, q dy, q dx^2,
+// q dx dy, q dy^2, q, and dL/dc, then 0.
 struct GradSlots { float4 *slot; };
 
 // ---------------------------------------------------------------- helpers

@@ -332,6 +332,21 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
         }
         Geom g;
         if (c > 0 && project_geom(V, mx, my, mz, cw, a.o, g)) {
+            // the slots hold moments of q = dL/ds G over the pixels, with
+            // (dx, dy) = pixel - mean: (sum q dx, sum q dy, sum q dx^2,
+            // sum q dx dy, sum q dy^2, sum q, dL/dc).  With s = alpha G,
+            // G = exp(-d2 / 2), d2 = d^T A d: dL/dmu = alpha A sum q d,
+            // dL/dA00 = -alpha/2 sum q dx^2, dL/dA01 (both off-diagonal
+            // entries together) = -alpha sum q dx dy, dL/dA11 = -alpha/2 sum q dy^2.
+            {
+                const float al = a.gc.alpha[ii];
+                const float m1x = g7[0], m1y = g7[1];
+                g7[0] = al * (g.A00 * m1x + g.A01 * m1y);
+                g7[1] = al * (g.A01 * m1x + g.A11 * m1y);
+                g7[2] = -0.5f * al * g7[2];
+                g7[3] = -al * g7[3];
+                g7[4] = -0.5f * al * g7[4];
+            }
             // conic = inverse of the projected covariance: dL/dS2 = -A Gbar A
             const float gb00 = g7[2], gb01 = 0.5f * g7[3], gb11 = g7[4];
             const float t00 = g.A00 * gb00 + g.A01 * gb01, t01 = g.A00 * gb01 + g.A01 * gb11;

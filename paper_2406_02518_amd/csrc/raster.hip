@@ -315,13 +315,18 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                                     const float ds = g * (c * T - __fdividef(S, om));
                                     gv[6] = g * s * T;
                                     if (!(sraw > smax)) {
-                                        gv[5] = ds * G;
-                                        const float dd2 = -0.5f * G * r1.y * ds;
-                                        gv[0] = -2.0f * dd2 * (r0.z * dx + r0.w * dy);
-                                        gv[1] = -2.0f * dd2 * (r0.w * dx + r1.x * dy);
-                                        gv[2] = dd2 * dx * dx;
-                                        gv[3] = 2.0f * dd2 * dx * dy;
-                                        gv[4] = dd2 * dy * dy;
+                                        // moments of dL/ds G about the mean; the
+                                        // conic and alpha factors are applied once
+                                        // per (view, Gaussian) in the projection
+                                        // backward
+                                        const float gds = ds * G;
+                                        const float m1x = gds * dx, m1y = gds * dy;
+                                        gv[0] = m1x;
+                                        gv[1] = m1y;
+                                        gv[2] = m1x * dx;
+                                        gv[3] = m1x * dy;
+                                        gv[4] = m1y * dy;
+                                        gv[5] = gds;
                                     }
                                     T = __fmul_rn(T, om);
                                 }
