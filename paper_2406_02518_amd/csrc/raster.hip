@@ -37,6 +37,16 @@ __device__ __forceinline__ float maha2(float dx, float dy, float A00, float A01,
     return __fmaf_rn(__fmul_rn(A00, dx), dx, t);
 }
 
+// Gaussian falloff exp(-d2 / 2) as one multiply and v_exp_f32 (2^x):
+// -log2(e) / 2 in FP32 is exactly half of FP32 log2(e), so this equals the
+// two-multiply form bit for bit.  Shared by the forward and the backward so
+// both see the same G.
+__device__ __forceinline__ float falloff(float d2)
+{
+    constexpr float kNegHalfLog2e = -0.7213475108146667f;  // 0xBF38AA3B
+    return __builtin_amdgcn_exp2f(__fmul_rn(d2, kNegHalfLog2e));
+}
+
 __device__ __forceinline__ int view_of_tile(const ViewDev *views, int V, int tile)
 {
     int lo = 0, hi = V - 1;
@@ -109,7 +119,8 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
     __shared__ float4 s1[NT];
     __shared__ int sh_item;
     const int tid = threadIdx.x;
-    const float k2 = a.o.kappa2, smax = a.o.sigma_max, tmin = a.o.t_min;
+    const float k2 = a.o.kappa2, tmin = a.o.t_min;
+    const float smax = __builtin_canonicalizef(a.o.sigma_max);
     int iter = 0;
     for (;;) {
         const int it = next_item(a, iter, &sh_item);
@@ -139,23 +150,28 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
             __syncthreads();
             const int cnt = (int)min((uint32_t)NT, I.e - b0);
             if (a.pair_counts && !done) n_eval += (uint32_t)cnt;
+#pragma unroll 4
             for (int q = 0; q < cnt; ++q) {
                 const float4 r0 = s0[q];
                 const float4 r1 = s1[q];
                 const float dx = __fsub_rn(fpx, r0.x), dy = __fsub_rn(fpy, r0.y);
                 const float d2 = maha2(dx, dy, r0.z, r0.w, r1.x);
-                if (d2 <= k2 && !done) {
-                    const float G = __expf(__fmul_rn(-0.5f, d2));
+                bool hit = d2 <= k2 && !done;
+                // when any lane hits, the whole wave runs the entry without
+                // branches; lanes that miss keep their state
+                if (__ballot(hit) != 0ull) {
+                    const float G = falloff(d2);
                     const float s = fminf(smax, __fmul_rn(r1.y, G));
                     const float om = __fsub_rn(1.0f, s);
-                    if (tmin > 0.0f && __fmul_rn(T, om) < tmin) {
-                        done = true;
-                    } else {
-                        C = __fmaf_rn(__fmul_rn(r1.z, s), T, C);
-                        T = __fmul_rn(T, om);
-                        last = b0 + (uint32_t)q + 1u;
-                        ++n_contrib;
-                    }
+                    // early termination (t_min > 0): mask arithmetic, no branch
+                    const bool stop = (tmin > 0.0f) & hit & (__fmul_rn(T, om) < tmin);
+                    done = done | stop;
+                    hit = hit & !stop;
+                    const float Cn = __fmaf_rn(__fmul_rn(r1.z, s), T, C);
+                    C = hit ? Cn : C;
+                    T = hit ? __fmul_rn(T, om) : T;
+                    last = hit ? b0 + (uint32_t)q + 1u : last;
+                    n_contrib += hit ? 1u : 0u;
                 }
             }
             if (tmin > 0.0f && __syncthreads_and(done)) break;
@@ -229,7 +245,8 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
     __shared__ uint32_t wmax[NW];
     __shared__ int sh_item;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-    const float k2 = a.o.kappa2, smax = a.o.sigma_max, tmin = a.o.t_min;
+    const float k2 = a.o.kappa2, tmin = a.o.t_min;
+    const float smax = __builtin_canonicalizef(a.o.sigma_max);
     float *slotf = reinterpret_cast<float *>(a.slot);
     int iter = 0;
     for (;;) {
@@ -299,37 +316,37 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                             const float4 r1 = s1[q];
                             const float dx = __fsub_rn(fpx, r0.x), dy = __fsub_rn(fpy, r0.y);
                             const float d2 = maha2(dx, dy, r0.z, r0.w, r1.x);
-                            const bool hit = d2 <= k2 && !done && (b0 + (uint32_t)q) < lastp;
-                            if (hit) {
-                                const float G = __expf(__fmul_rn(-0.5f, d2));
+                            bool hit = d2 <= k2 && !done && (b0 + (uint32_t)q) < lastp;
+                            // when any lane hits, the whole wave runs the entry:
+                            // computed without branches, lanes that miss keep
+                            // their state and contribute zeros
+                            if (__ballot(hit) != 0ull) {
+                                const float G = falloff(d2);
                                 const float sraw = __fmul_rn(r1.y, G);
                                 const float s = fminf(smax, sraw);
                                 const float om = __fsub_rn(1.0f, s);
-                                if (tmin > 0.0f && __fmul_rn(T, om) < tmin) {
-                                    done = true;
-                                } else {
-                                    any = true;
-                                    const float c = r1.z;
-                                    Cacc = __fmaf_rn(__fmul_rn(c, s), T, Cacc);
-                                    const float S = Cf - Cacc;
-                                    const float ds = g * (c * T - __fdividef(S, om));
-                                    gv[6] = g * s * T;
-                                    if (!(sraw > smax)) {
-                                        // moments of dL/ds G about the mean; the
-                                        // conic and alpha factors are applied once
-                                        // per (view, Gaussian) in the projection
-                                        // backward
-                                        const float gds = ds * G;
-                                        const float m1x = gds * dx, m1y = gds * dy;
-                                        gv[0] = m1x;
-                                        gv[1] = m1y;
-                                        gv[2] = m1x * dx;
-                                        gv[3] = m1x * dy;
-                                        gv[4] = m1y * dy;
-                                        gv[5] = gds;
-                                    }
-                                    T = __fmul_rn(T, om);
-                                }
+                                const bool stop = (tmin > 0.0f) & hit & (__fmul_rn(T, om) < tmin);
+                                done = done | stop;
+                                hit = hit & !stop;
+                                const float c = r1.z;
+                                const float Cn = __fmaf_rn(__fmul_rn(c, s), T, Cacc);
+                                Cacc = hit ? Cn : Cacc;
+                                const float S = Cf - Cacc;
+                                const float ds = g * (c * T - S * __builtin_amdgcn_rcpf(om));
+                                // moments of dL/ds G about the mean; the conic and
+                                // alpha factors are applied once per (view,
+                                // Gaussian) in the projection backward
+                                const float gds = (hit && !(sraw > smax)) ? ds * G : 0.0f;
+                                const float m1x = gds * dx, m1y = gds * dy;
+                                gv[0] = m1x;
+                                gv[1] = m1y;
+                                gv[2] = m1x * dx;
+                                gv[3] = m1x * dy;
+                                gv[4] = m1y * dy;
+                                gv[5] = gds;
+                                gv[6] = hit ? g * s * T : 0.0f;
+                                T = hit ? __fmul_rn(T, om) : T;
+                                any = any || hit;
                             }
                         }
 #pragma unroll
