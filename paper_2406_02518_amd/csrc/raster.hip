@@ -111,7 +111,9 @@ __device__ __forceinline__ int next_item(const RasterArgs &a, int &iter, int *sh
     return a.queue ? (int)a.queue[k] : k;
 }
 
-template <int TW, int TH>
+// SPLIT: work items are chunks (a.split > 0), so no per-pixel last index is
+// kept; COUNT: pair counters on.
+template <int TW, int TH, bool SPLIT, bool COUNT>
 __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
 {
     constexpr int NT = TW * TH;
@@ -149,7 +151,7 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
             }
             __syncthreads();
             const int cnt = (int)min((uint32_t)NT, I.e - b0);
-            if (a.pair_counts && !done) n_eval += (uint32_t)cnt;
+            if (COUNT && !done) n_eval += (uint32_t)cnt;
 #pragma unroll 4
             for (int q = 0; q < cnt; ++q) {
                 const float4 r0 = s0[q];
@@ -170,13 +172,13 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
                     const float Cn = __fmaf_rn(__fmul_rn(r1.z, s), T, C);
                     C = hit ? Cn : C;
                     T = hit ? __fmul_rn(T, om) : T;
-                    last = hit ? b0 + (uint32_t)q + 1u : last;
-                    n_contrib += hit ? 1u : 0u;
+                    if constexpr (!SPLIT) last = hit ? b0 + (uint32_t)q + 1u : last;
+                    if constexpr (COUNT) n_contrib += hit ? 1u : 0u;
                 }
             }
             if (tmin > 0.0f && __syncthreads_and(done)) break;
         }
-        if (a.pair_counts) {
+        if constexpr (COUNT) {
             unsigned long long e = n_eval, c = n_contrib;
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) {
@@ -190,7 +192,7 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
                 atomicAdd(&a.pair_counts[2 * slot + 1], c);
             }
         }
-        if (a.split) {
+        if constexpr (SPLIT) {
             a.part[(size_t)it * NT + tid] = make_float2(C, T);
         } else if (inside) {
             const size_t p = (size_t)V.pix_base + (size_t)py * V.W + px;
@@ -232,7 +234,9 @@ __global__ __launch_bounds__(TW *TH) void merge_kernel(RasterArgs a)
     }
 }
 
-template <int TW, int TH>
+// SPLIT: work items are chunks (every entry of an item lies before the
+// pixel's last contribution).
+template <int TW, int TH, bool SPLIT>
 __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
 {
     constexpr int NT = TW * TH;
@@ -316,7 +320,7 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                             const float4 r1 = s1[q];
                             const float dx = __fsub_rn(fpx, r0.x), dy = __fsub_rn(fpy, r0.y);
                             const float d2 = maha2(dx, dy, r0.z, r0.w, r1.x);
-                            bool hit = d2 <= k2 && !done && (b0 + (uint32_t)q) < lastp;
+                            bool hit = d2 <= k2 && !done && (SPLIT || (b0 + (uint32_t)q) < lastp);
                             // when any lane hits, the whole wave runs the entry:
                             // computed without branches, lanes that miss keep
                             // their state and contribute zeros
@@ -443,7 +447,13 @@ template <int TW, int TH>
 hipError_t fwd_inst(const RasterArgs &a, int pb, hipStream_t s)
 {
     const int grid = a.queue_counter ? pb : (a.split ? a.max_items : a.n_tiles);
-    if (grid > 0) raster_fwd_kernel<TW, TH><<<grid, TW * TH, 0, s>>>(a);
+    if (grid > 0) {
+        const bool cnt = a.pair_counts != nullptr;
+        if (a.split && cnt) raster_fwd_kernel<TW, TH, true, true><<<grid, TW * TH, 0, s>>>(a);
+        else if (a.split) raster_fwd_kernel<TW, TH, true, false><<<grid, TW * TH, 0, s>>>(a);
+        else if (cnt) raster_fwd_kernel<TW, TH, false, true><<<grid, TW * TH, 0, s>>>(a);
+        else raster_fwd_kernel<TW, TH, false, false><<<grid, TW * TH, 0, s>>>(a);
+    }
     if (a.split && a.n_tiles > 0) merge_kernel<TW, TH><<<a.n_tiles, TW * TH, 0, s>>>(a);
     return hipGetLastError();
 }
@@ -452,7 +462,12 @@ template <int TW, int TH>
 hipError_t bwd_inst(const RasterArgs &a, int pb, hipStream_t s)
 {
     const int grid = a.queue_counter ? pb : (a.split ? a.max_items : a.n_tiles);
-    if (grid > 0) raster_bwd_kernel<TW, TH><<<grid, TW * TH, 0, s>>>(a);
+    if (grid > 0) {
+        if (a.split)
+            raster_bwd_kernel<TW, TH, true><<<grid, TW * TH, 0, s>>>(a);
+        else
+            raster_bwd_kernel<TW, TH, false><<<grid, TW * TH, 0, s>>>(a);
+    }
     return hipGetLastError();
 }
 
