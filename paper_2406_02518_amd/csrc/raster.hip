@@ -30,12 +30,21 @@ namespace ddgs {
 
 namespace {
 
-__device__ __forceinline__ float maha2(float dx, float dy, float A00, float A01, float A11)
+// d2 = d^T A d for d = (dx, dy), A = [[A00, A01], [A01, A11]], evaluated as
+// dx (A00 dx + B dy) + A11 dy dy with B = 2 A01 (staged doubled in LDS);
+// five rounded operations, the same in the forward and the backward.
+__device__ __forceinline__ float maha2(float dx, float dy, float A00, float B, float A11)
 {
-    float t = __fmul_rn(__fmul_rn(A11, dy), dy);
-    t = __fmaf_rn(__fmul_rn(__fmul_rn(2.0f, A01), dx), dy, t);
-    return __fmaf_rn(__fmul_rn(A00, dx), dx, t);
+    const float u = __fmaf_rn(B, dy, __fmul_rn(A00, dx));
+    return __fmaf_rn(dx, u, __fmul_rn(__fmul_rn(A11, dy), dy));
 }
+
+// min(s, sigma_max) for s = alpha G >= 0 as one v_med3_f32 (median of s,
+// 0 and sigma_max), without the NaN canonicalisation fminf brings.
+__device__ __forceinline__ float clamp_opacity(float s, float smax) { return __builtin_amdgcn_fmed3f(s, 0.0f, smax); }
+
+// Wave-wide OR of a predicate as a lane mask (the compare mask itself).
+__device__ __forceinline__ uint64_t wave_any_mask(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 // Gaussian falloff exp(-d2 / 2) as one multiply and v_exp_f32 (2^x):
 // -log2(e) / 2 in FP32 is exactly half of FP32 log2(e), so this equals the
@@ -122,7 +131,7 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
     __shared__ int sh_item;
     const int tid = threadIdx.x;
     const float k2 = a.o.kappa2, tmin = a.o.t_min;
-    const float smax = __builtin_canonicalizef(a.o.sigma_max);
+    const float smax = a.o.sigma_max;
     int iter = 0;
     for (;;) {
         const int it = next_item(a, iter, &sh_item);
@@ -146,7 +155,9 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
             if (j < I.e) {
                 const uint32_t gid = min(a.tval[j], (uint32_t)a.n - 1u);
                 const size_t idx = vbase + gid;
-                s0[tid] = a.rec[2 * idx];
+                float4 r0 = a.rec[2 * idx];
+                r0.w = 2.0f * r0.w;  // 2 A01, as the Mahalanobis form uses it
+                s0[tid] = r0;
                 s1[tid] = a.rec[2 * idx + 1];
             }
             __syncthreads();
@@ -161,9 +172,9 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
                 bool hit = d2 <= k2 && !done;
                 // when any lane hits, the whole wave runs the entry without
                 // branches; lanes that miss keep their state
-                if (__ballot(hit) != 0ull) {
+                if (wave_any_mask(hit) != 0ull) {
                     const float G = falloff(d2);
-                    const float s = fminf(smax, __fmul_rn(r1.y, G));
+                    const float s = clamp_opacity(__fmul_rn(r1.y, G), smax);
                     const float om = __fsub_rn(1.0f, s);
                     // early termination (t_min > 0): mask arithmetic, no branch
                     const bool stop = (tmin > 0.0f) & hit & (__fmul_rn(T, om) < tmin);
@@ -250,7 +261,7 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
     __shared__ int sh_item;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
     const float k2 = a.o.kappa2, tmin = a.o.t_min;
-    const float smax = __builtin_canonicalizef(a.o.sigma_max);
+    const float smax = a.o.sigma_max;
     float *slotf = reinterpret_cast<float *>(a.slot);
     int iter = 0;
     for (;;) {
@@ -297,7 +308,9 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
             if (j < I.e) {
                 const uint32_t gid = min(a.tval[j], (uint32_t)a.n - 1u);
                 const size_t idx = vbase + gid;
-                s0[tid] = a.rec[2 * idx];
+                float4 r0 = a.rec[2 * idx];
+                r0.w = 2.0f * r0.w;  // 2 A01, as the Mahalanobis form uses it
+                s0[tid] = r0;
                 s1[tid] = a.rec[2 * idx + 1];
                 const uint2 rc = a.rect[idx];
                 const int tx0 = rc.x & 0xFFFF, ty0 = rc.x >> 16, tx1 = rc.y & 0xFFFF;
@@ -324,10 +337,10 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                             // when any lane hits, the whole wave runs the entry:
                             // computed without branches, lanes that miss keep
                             // their state and contribute zeros
-                            if (__ballot(hit) != 0ull) {
+                            if (wave_any_mask(hit) != 0ull) {
                                 const float G = falloff(d2);
                                 const float sraw = __fmul_rn(r1.y, G);
-                                const float s = fminf(smax, sraw);
+                                const float s = clamp_opacity(sraw, smax);
                                 const float om = __fsub_rn(1.0f, s);
                                 const bool stop = (tmin > 0.0f) & hit & (__fmul_rn(T, om) < tmin);
                                 done = done | stop;
@@ -358,7 +371,7 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                         gb[qq * 8 + 7] = 0.0f;
                     }
                     float res = 0.0f;
-                    if (__ballot(any) != 0ull) {
+                    if (wave_any_mask(any) != 0ull) {
                         wave_transpose_sum64(gb);
                         res = gb[0];
                     }
