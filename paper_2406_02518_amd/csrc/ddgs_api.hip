@@ -280,7 +280,7 @@ ddgs_status ensure_static(ddgs_ctx *c)
     DDGS_TRY(ensure_t(c, "hdir", (size_t)KL * std::max<int64_t>(1, n - c->model.n_iso), &f));
     DDGS_TRY(ensure_t(c, "ubuf", (size_t)16 * n, &f));
     float4 *f4;
-    DDGS_TRY(ensure_t(c, "rec", 2 * VN, &f4));
+    DDGS_TRY(ensure_t(c, "rec", 4 * VN, &f4));
     uint2 *u2;
     DDGS_TRY(ensure_t(c, "rect", VN, &u2));
     const char *u32s[] = {"zkey", "cnt", "offs", "skey", "sval", "skey2", "sval2", "off_sorted"};
@@ -440,8 +440,9 @@ ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, int64_t sort_n, float *images
     const uint32_t *order = sval;
     uint32_t *tkey = buf<uint32_t>(c, "tkey"), *tval = buf<uint32_t>(c, "tval");
     HIP_TRY(c, launch_emit(VN, n, order, buf<uint32_t>(c, "off_sorted"), buf<uint32_t>(c, "cnt"),
-                           buf<uint2>(c, "rect"), buf<ViewDev>(c, "views"), buf<uint32_t>(c, "offs"), tkey, tval,
-                           (uint32_t)cap, total_ptr(c), mdev_ptr(c), flags_ptr(c), s));
+                           buf<uint2>(c, "rect"), buf<ViewDev>(c, "views"), buf<uint32_t>(c, "offs"),
+                           buf<float4>(c, "rec"), tkey, tval, (uint32_t)cap, total_ptr(c), mdev_ptr(c),
+                           flags_ptr(c), s));
     if (c->keep_unsorted) {
         HIP_TRY(c, launch_copy_u32(buf<uint32_t>(c, "ukey"), tkey, mdev_ptr(c), sort_n, s));
         HIP_TRY(c, launch_copy_u32(buf<uint32_t>(c, "uval"), tval, mdev_ptr(c), sort_n, s));
@@ -1013,7 +1014,14 @@ ddgs_status ddgs_debug_copy(ddgs_ctx *c, int what, void *host, size_t bytes)
     size_t need = 0;
     std::vector<uint16_t> rect16;
     switch (what) {
-    case DDGS_DBG_RECORDS: src = buf<void>(c, "rec"); need = (size_t)VN * 32; break;
+    case DDGS_DBG_RECORDS: {
+        // the first 32 bytes of every 64-byte pair record
+        need = (size_t)VN * 32;
+        if (bytes < need) return fail(c, DDGS_ERR_INVALID_ARG, "buffer too small: need " + std::to_string(need));
+        if (VN > 0)
+            HIP_TRY(c, hipMemcpy2D(host, 32, buf<void>(c, "rec"), 64, 32, (size_t)VN, hipMemcpyDeviceToHost));
+        return DDGS_OK;
+    }
     case DDGS_DBG_DEPTH_KEYS: src = buf<void>(c, "zkey"); need = (size_t)VN * 4; break;
     case DDGS_DBG_COUNTS: src = buf<void>(c, "cnt"); need = (size_t)VN * 4; break;
     case DDGS_DBG_RECTS: src = buf<void>(c, "rect"); need = (size_t)VN * 8; break;

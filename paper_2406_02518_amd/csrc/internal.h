@@ -46,7 +46,9 @@ struct GaussCache {
 
 // Per (view, Gaussian) projection output.
 struct ProjOut {
-    float4 *rec;     // [V*n][2]: (mx, my, A00, A01), (A11, alpha, c, 0)
+    float4 *rec;     // [V*n][4], 64 B (one cache line) per pair: (mx, my, A00, A01),
+                     // (A11, alpha, c, bits of the first entry index, written at
+                     // emission), (bits of rect.x, rect.y, 0, 0), unused
     uint2 *rect;     // [V*n]: (tx0 | ty0 << 16, tx1 | ty1 << 16), inclusive
     uint32_t *zkey;  // [V*n]: float bits of the source-frame depth, ~0u if culled
     uint32_t *cnt;   // [V*n]: number of tiles touched
@@ -206,9 +208,10 @@ hipError_t launch_exclusive_scan(const uint32_t *in, const uint32_t *gather, uin
 // (k0, v0) and (k1, v1); *in_k1 tells where the result ended.
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n_cap,
                             const uint32_t *n_dev, int bits, const SortWs &ws, bool *in_k1, hipStream_t s);
+// (also stores each pair's first entry index into its record, rec[4 i + 1].w)
 hipError_t launch_emit(int64_t VN, int n, const uint32_t *order, const uint32_t *off_sorted,
                        const uint32_t *cnt, const uint2 *rect, const ViewDev *views,
-                       uint32_t *offs, uint32_t *tkey, uint32_t *tval, uint32_t capacity,
+                       uint32_t *offs, float4 *rec, uint32_t *tkey, uint32_t *tval, uint32_t capacity,
                        const uint64_t *total, uint32_t *m_out, uint32_t *flags, hipStream_t s);
 hipError_t launch_ranges(const uint32_t *keys, const uint32_t *m_dev, int64_t m_cap, uint2 *ranges,
                          int n_tiles, hipStream_t s);

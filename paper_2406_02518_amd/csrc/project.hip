@@ -235,8 +235,9 @@ __global__ __launch_bounds__(kBlock) void project_kernel(ModelDev m, GaussCache 
         po.sort_val[vi] = (uint32_t)vi;
         po.cnt[vi] = 0;
         po.rect[vi] = make_uint2(0, 0);
-        po.rec[2 * vi] = make_float4(0.f, 0.f, 0.f, 0.f);
-        po.rec[2 * vi + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        po.rec[4 * vi] = make_float4(0.f, 0.f, 0.f, 0.f);
+        po.rec[4 * vi + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        po.rec[4 * vi + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
         return;
     }
     float c;
@@ -274,8 +275,9 @@ __global__ __launch_bounds__(kBlock) void project_kernel(ModelDev m, GaussCache 
     po.sort_val[vi] = (uint32_t)vi;
     po.cnt[vi] = count;
     po.rect[vi] = rc;
-    po.rec[2 * vi] = make_float4(g.mux, g.muy, g.A00, g.A01);
-    po.rec[2 * vi + 1] = make_float4(g.A11, gc.alpha[i], c, 0.0f);
+    po.rec[4 * vi] = make_float4(g.mux, g.muy, g.A00, g.A01);
+    po.rec[4 * vi + 1] = make_float4(g.A11, gc.alpha[i], c, 0.0f);
+    po.rec[4 * vi + 2] = make_float4(__uint_as_float(rc.x), __uint_as_float(rc.y), 0.0f, 0.0f);
 }
 
 // ------------------------------------------------------------ backward chain

@@ -155,10 +155,10 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
             if (j < I.e) {
                 const uint32_t gid = min(a.tval[j], (uint32_t)a.n - 1u);
                 const size_t idx = vbase + gid;
-                float4 r0 = a.rec[2 * idx];
+                float4 r0 = a.rec[4 * idx];
                 r0.w = 2.0f * r0.w;  // 2 A01, as the Mahalanobis form uses it
                 s0[tid] = r0;
-                s1[tid] = a.rec[2 * idx + 1];
+                s1[tid] = a.rec[4 * idx + 1];
             }
             __syncthreads();
             const int cnt = (int)min((uint32_t)NT, I.e - b0);
@@ -308,13 +308,16 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
             if (j < I.e) {
                 const uint32_t gid = min(a.tval[j], (uint32_t)a.n - 1u);
                 const size_t idx = vbase + gid;
-                float4 r0 = a.rec[2 * idx];
+                // one 64-byte line per pair: record, first entry index, rectangle
+                float4 r0 = a.rec[4 * idx];
+                const float4 r1 = a.rec[4 * idx + 1];
+                const float4 r2 = a.rec[4 * idx + 2];
                 r0.w = 2.0f * r0.w;  // 2 A01, as the Mahalanobis form uses it
                 s0[tid] = r0;
-                s1[tid] = a.rec[2 * idx + 1];
-                const uint2 rc = a.rect[idx];
-                const int tx0 = rc.x & 0xFFFF, ty0 = rc.x >> 16, tx1 = rc.y & 0xFFFF;
-                se[tid] = a.offs[idx] + (uint32_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
+                s1[tid] = r1;
+                const uint32_t rx = __float_as_uint(r2.x), ry = __float_as_uint(r2.y);
+                const int tx0 = rx & 0xFFFF, ty0 = rx >> 16, tx1 = ry & 0xFFFF;
+                se[tid] = __float_as_uint(r1.w) + (uint32_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
             }
             __syncthreads();
             if (b0 < end) {

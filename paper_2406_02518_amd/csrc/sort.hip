@@ -325,8 +325,9 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *k
 __global__ __launch_bounds__(kBlock) void emit_kernel(int64_t VN, int n, const uint32_t *order,
                                                       const uint32_t *off_sorted, const uint32_t *cnt,
                                                       const uint2 *rect, const ViewDev *views, uint32_t *offs,
-                                                      uint32_t *tkey, uint32_t *tval, uint32_t capacity,
-                                                      const uint64_t *total, uint32_t *m_out, uint32_t *flags)
+                                                      float4 *rec, uint32_t *tkey, uint32_t *tval,
+                                                      uint32_t capacity, const uint64_t *total, uint32_t *m_out,
+                                                      uint32_t *flags)
 {
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & (kWave - 1);
@@ -344,6 +345,7 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(int64_t VN, int n, const u
         off = off_sorted[r];
         if (c) {
             offs[vi] = off;
+            reinterpret_cast<float *>(rec)[16 * (size_t)vi + 7] = __uint_as_float(off);
             const uint32_t v = vi / (uint32_t)n;
             i = vi - v * (uint32_t)n;
             const uint2 rc = rect[vi];
@@ -463,11 +465,12 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
 }
 
 hipError_t launch_emit(int64_t VN, int n, const uint32_t *order, const uint32_t *off_sorted, const uint32_t *cnt,
-                       const uint2 *rect, const ViewDev *views, uint32_t *offs, uint32_t *tkey, uint32_t *tval,
-                       uint32_t capacity, const uint64_t *total, uint32_t *m_out, uint32_t *flags, hipStream_t s)
+                       const uint2 *rect, const ViewDev *views, uint32_t *offs, float4 *rec, uint32_t *tkey,
+                       uint32_t *tval, uint32_t capacity, const uint64_t *total, uint32_t *m_out, uint32_t *flags,
+                       hipStream_t s)
 {
     const int64_t nb = std::max<int64_t>(1, blocks_for(VN, kBlock));
-    emit_kernel<<<(unsigned)nb, kBlock, 0, s>>>(VN, n, order, off_sorted, cnt, rect, views, offs, tkey, tval,
+    emit_kernel<<<(unsigned)nb, kBlock, 0, s>>>(VN, n, order, off_sorted, cnt, rect, views, offs, rec, tkey, tval,
                                                 capacity, total, m_out, flags);
     return hipGetLastError();
 }
