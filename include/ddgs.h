@@ -25,7 +25,8 @@
  * Conventions shared by every entry point:
  *   - All array pointers in ddgs_model, ddgs_grads, images, targets and
  *     gradients are DEVICE pointers on the context's device, float32,
- *     structure-of-arrays, 16-byte aligned, owned by the caller.  The library
+ *     structure-of-arrays, at least 4-byte aligned (ddgs_set_model rejects
+ *     others with DDGS_ERR_INVALID_ARG), owned by the caller.  The library
  *     never frees them.  ddgs_view arrays are host memory and are copied.
  *   - All device work is enqueued on the context's stream (settable, e.g.
  *     torch's current stream).  Entry points do not synchronise the stream
