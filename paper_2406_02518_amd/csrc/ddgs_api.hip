@@ -283,7 +283,7 @@ ddgs_status ensure_static(ddgs_ctx *c)
     DDGS_TRY(ensure_t(c, "rec", 4 * VN, &f4));
     uint2 *u2;
     DDGS_TRY(ensure_t(c, "rect", VN, &u2));
-    const char *u32s[] = {"zkey", "cnt", "offs", "skey", "sval", "skey2", "sval2", "off_sorted"};
+    const char *u32s[] = {"zkey", "cnt", "offs", "skey", "sval", "skey2", "sval2", "off_sorted", "cnt_sorted"};
     for (const char *nm : u32s) DDGS_TRY(ensure_t(c, nm, VN, &u));
     DDGS_TRY(ensure_t(c, "ranges", std::max(1, c->n_tiles), &u2));
     DDGS_TRY(ensure_t(c, "qkey", std::max(1, c->n_tiles), &u));
@@ -421,9 +421,10 @@ ddgs_status enqueue_front(ddgs_ctx *c)
     stage_begin(c, DDGS_T_SORT);
     bool in_k1 = false;
     HIP_TRY(c, radix_sort_pairs(po.sort_key, po.sort_val, buf<uint32_t>(c, "skey2"), buf<uint32_t>(c, "sval2"), VN,
-                                nullptr, 32, sort_ws(c), &in_k1, s));
-    const uint32_t *order = in_k1 ? buf<uint32_t>(c, "sval2") : po.sort_val;
-    HIP_TRY(c, launch_exclusive_scan(po.cnt, order, buf<uint32_t>(c, "off_sorted"), VN, sort_ws(c), total_ptr(c), s));
+                                nullptr, 32, sort_ws(c), &in_k1, s, po.cnt, buf<uint32_t>(c, "cnt_sorted")));
+    // (the last depth pass also wrote the tile counts in depth order)
+    HIP_TRY(c, launch_exclusive_scan(buf<uint32_t>(c, "cnt_sorted"), nullptr, buf<uint32_t>(c, "off_sorted"), VN,
+                                     sort_ws(c), total_ptr(c), s));
     return DDGS_OK;
 }
 
@@ -439,10 +440,10 @@ ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, int64_t sort_n, float *images
     // the depth order ended where the 4-pass sort left it (even count: input buffers)
     const uint32_t *order = sval;
     uint32_t *tkey = buf<uint32_t>(c, "tkey"), *tval = buf<uint32_t>(c, "tval");
-    HIP_TRY(c, launch_emit(VN, n, order, buf<uint32_t>(c, "off_sorted"), buf<uint32_t>(c, "cnt"),
+    HIP_TRY(c, launch_emit(VN, n, order, buf<uint32_t>(c, "off_sorted"), buf<uint32_t>(c, "cnt_sorted"),
                            buf<uint2>(c, "rect"), buf<ViewDev>(c, "views"), buf<uint32_t>(c, "offs"),
                            buf<float4>(c, "rec"), tkey, tval, (uint32_t)cap, total_ptr(c), mdev_ptr(c),
-                           flags_ptr(c), s));
+                           flags_ptr(c), buf<uint2>(c, "ranges"), c->n_tiles, s));
     if (c->keep_unsorted) {
         HIP_TRY(c, launch_copy_u32(buf<uint32_t>(c, "ukey"), tkey, mdev_ptr(c), sort_n, s));
         HIP_TRY(c, launch_copy_u32(buf<uint32_t>(c, "uval"), tval, mdev_ptr(c), sort_n, s));
@@ -452,7 +453,7 @@ ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, int64_t sort_n, float *images
                                 bits_for(c->n_tiles), sort_ws(c), &in_k1, s));
     c->tkey_sorted = in_k1 ? buf<uint32_t>(c, "tkey2") : tkey;
     c->tval_sorted = in_k1 ? buf<uint32_t>(c, "tval2") : tval;
-    HIP_TRY(c, launch_ranges(c->tkey_sorted, mdev_ptr(c), sort_n, buf<uint2>(c, "ranges"), c->n_tiles, s));
+    HIP_TRY(c, launch_ranges(c->tkey_sorted, mdev_ptr(c), sort_n, buf<uint2>(c, "ranges"), c->n_tiles, false, s));
     c->queue = nullptr;
     const int split = effective_split(c);
     c->max_items = (int)max_items_for(c, cap);
@@ -813,7 +814,7 @@ ddgs_status ddgs_render(ddgs_ctx *c, float *images)
         // no Gaussians: empty lists everywhere
         HIP_TRY(c, launch_fill_u32(mdev_ptr(c), 0u, 1, c->stream));
         HIP_TRY(c, launch_ranges(buf<uint32_t>(c, "tkey"), mdev_ptr(c), 0, buf<uint2>(c, "ranges"), c->n_tiles,
-                                 c->stream));
+                                 true, c->stream));
         c->tkey_sorted = buf<uint32_t>(c, "tkey");
         c->tval_sorted = buf<uint32_t>(c, "tval");
         c->queue = nullptr;

@@ -206,15 +206,20 @@ hipError_t launch_exclusive_scan(const uint32_t *in, const uint32_t *gather, uin
 // Sorts (keys, vals) by key bits [0, bits) (stable).  n_dev (may be NULL)
 // limits the count at run time to min(*n_dev, n_cap).  Ping-pongs between
 // (k0, v0) and (k1, v1); *in_k1 tells where the result ended.
+// gsrc / gdst (optional): the last pass also writes gdst[i] = gsrc[value i].
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n_cap,
-                            const uint32_t *n_dev, int bits, const SortWs &ws, bool *in_k1, hipStream_t s);
-// (also stores each pair's first entry index into its record, rec[4 i + 1].w)
+                            const uint32_t *n_dev, int bits, const SortWs &ws, bool *in_k1, hipStream_t s,
+                            const uint32_t *gsrc = nullptr, uint32_t *gdst = nullptr);
+// (also stores each pair's first entry index into its record, rec[4 i + 1].w,
+// and clears the n_tiles tile ranges; cnt_sorted: tile counts in depth order)
 hipError_t launch_emit(int64_t VN, int n, const uint32_t *order, const uint32_t *off_sorted,
-                       const uint32_t *cnt, const uint2 *rect, const ViewDev *views,
+                       const uint32_t *cnt_sorted, const uint2 *rect, const ViewDev *views,
                        uint32_t *offs, float4 *rec, uint32_t *tkey, uint32_t *tval, uint32_t capacity,
-                       const uint64_t *total, uint32_t *m_out, uint32_t *flags, hipStream_t s);
+                       const uint64_t *total, uint32_t *m_out, uint32_t *flags, uint2 *ranges, int n_tiles,
+                       hipStream_t s);
+// zero: clear the ranges first (else they must already be clear)
 hipError_t launch_ranges(const uint32_t *keys, const uint32_t *m_dev, int64_t m_cap, uint2 *ranges,
-                         int n_tiles, hipStream_t s);
+                         int n_tiles, bool zero, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_zero_u64(uint64_t *p, hipStream_t s);
 hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, const uint32_t *n_dev, int64_t n_cap,
@@ -254,8 +259,8 @@ hipError_t launch_raster_bwd(const RasterArgs &a, int persistent_blocks, hipStre
 // persistent queue: order tiles by descending list length
 hipError_t launch_tile_cost_keys(const uint2 *ranges, int n_tiles, uint32_t *keys, uint32_t *vals,
                                  uint32_t *counter, hipStream_t s);
-// work items of `split` entries: per-tile counts and bases, the item list,
-// the device item count; also clears the two work-queue counters
+// work items of `split` entries (sort.hip): per-tile counts and bases, the
+// item list, the device item count; also clears the two work-queue counters
 hipError_t launch_items(const uint2 *ranges, int n_tiles, int split, uint32_t *cnt, uint32_t *base, uint2 *items,
                         uint32_t max_items, const SortWs &ws, uint64_t *scan_total, uint32_t *n_items,
                         uint32_t *counter, hipStream_t s);

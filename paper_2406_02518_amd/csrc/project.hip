@@ -326,7 +326,23 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
             }
         }
         float g7[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        for (uint32_t e = 0; e < c; ++e) {
+        // the pair's slots in emission order; four entries' loads in flight
+        // at once (the sums keep the same order)
+        uint32_t e = 0;
+        for (; e + 4u <= c; e += 4u) {
+            float4 s0[4], s1[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                s0[u] = a.slot[2 * ((size_t)off + e + u)];
+                s1[u] = a.slot[2 * ((size_t)off + e + u) + 1];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                g7[0] += s0[u].x; g7[1] += s0[u].y; g7[2] += s0[u].z; g7[3] += s0[u].w;
+                g7[4] += s1[u].x; g7[5] += s1[u].y; g7[6] += s1[u].z;
+            }
+        }
+        for (; e < c; ++e) {
             const float4 s0 = a.slot[2 * ((size_t)off + e)];
             const float4 s1 = a.slot[2 * ((size_t)off + e) + 1];
             g7[0] += s0.x; g7[1] += s0.y; g7[2] += s0.z; g7[3] += s0.w;
@@ -557,26 +573,38 @@ __global__ __launch_bounds__(kBlock) void basis_grad_kernel(int n, int k, const 
     // operand layout of the 16x16x4 f32 MFMA: lane l supplies A[l % 16][l / 16]
     // and B[l / 16][l % 16]; D[i][j] comes back in lane j + 16 (i / 4), item i % 4
     const int row = lane & 15, kk = lane >> 4;
-    floatx4 acc[NTILE];
+    // two accumulator chains; the operands of four MFMA steps are loaded
+    // before any of them is issued
+    floatx4 acc[2][NTILE];
 #pragma unroll
-    for (int t = 0; t < NTILE; ++t) acc[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int g0 = g_begin; g0 < g_end; g0 += 4) {
-        const int g = g0 + kk;
-        const bool ok = g < g_end;
-        const float a = ok ? ubuf[(size_t)g * 16 + row] : 0.0f;
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int t = 0; t < NTILE; ++t) {
-            const int j = t * 16 + row;
-            const float b = (ok && j < k) ? feat[(size_t)j * n + g] : 0.0f;
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+        for (int t = 0; t < NTILE; ++t) acc[h][t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int g0 = g_begin; g0 < g_end; g0 += 16) {
+        float av[4], bv[4][NTILE];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int g = g0 + 4 * u + kk;
+            const bool ok = g < g_end;
+            av[u] = ok ? ubuf[(size_t)g * 16 + row] : 0.0f;
+#pragma unroll
+            for (int t = 0; t < NTILE; ++t) {
+                const int j = t * 16 + row;
+                bv[u][t] = (ok && j < k) ? feat[(size_t)j * n + g] : 0.0f;
+            }
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t = 0; t < NTILE; ++t)
+                acc[u & 1][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[u][t], acc[u & 1][t], 0, 0, 0);
     }
 #pragma unroll
     for (int t = 0; t < NTILE; ++t)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int i = 4 * kk + q, j = t * 16 + row;
-            part[((size_t)wave * 16 + i) * NCOL + j] = acc[t][q];
+            part[((size_t)wave * 16 + i) * NCOL + j] = acc[0][t][q] + acc[1][t][q];
         }
 }
 
@@ -608,19 +636,34 @@ __global__ __launch_bounds__(kBlock) void basis_final_kernel(int k, const float 
 
 // dpose[v] = (rho, omega) from the per-wave partials: rho = sum d mu_c +
 // sum R d r; omega = sum (R mu) x d mu_c + covariance term + t x sum d mu_c.
-__global__ __launch_bounds__(kBlock) void pose_final_kernel(const ViewDev *views, int n_waves,
-                                                            const float *part, float *dpose)
+constexpr int kPoseBlock = 512;
+__global__ __launch_bounds__(kPoseBlock) void pose_final_kernel(const ViewDev *views, int n_waves,
+                                                                const float *part, float *dpose)
 {
     const int v = blockIdx.x;
     double s[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) s[q] = 0.0;
-    for (int w = threadIdx.x; w < n_waves; w += kBlock) {
+    // two partials' loads in flight per thread
+    int w = threadIdx.x;
+    for (; w + kPoseBlock < n_waves; w += 2 * kPoseBlock) {
+        const float *p0 = part + ((size_t)v * n_waves + w) * 9;
+        const float *p1 = p0 + (size_t)kPoseBlock * 9;
+        float x0[9], x1[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            x0[q] = p0[q];
+            x1[q] = p1[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) s[q] += (double)x0[q] + (double)x1[q];
+    }
+    if (w < n_waves) {
         const float *p = part + ((size_t)v * n_waves + w) * 9;
 #pragma unroll
         for (int q = 0; q < 9; ++q) s[q] += (double)p[q];
     }
-    __shared__ double red[kBlock / kWave][9];
+    __shared__ double red[kPoseBlock / kWave][9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         double x = s[q];
@@ -634,9 +677,10 @@ __global__ __launch_bounds__(kBlock) void pose_final_kernel(const ViewDev *views
     __syncthreads();
     if (threadIdx.x == 0) {
         double t9[9];
+#pragma unroll
         for (int q = 0; q < 9; ++q) {
             double x = 0.0;
-            for (int w = 0; w < kBlock / kWave; ++w) x += red[w][q];
+            for (int r = 0; r < kPoseBlock / kWave; ++r) x += red[r][q];
             t9[q] = x;
         }
         const ViewDev &V = views[v];
@@ -743,7 +787,7 @@ hipError_t launch_pose_final(const ViewDev *views, int V, int n_waves, const flo
                              float *dpose, hipStream_t s)
 {
     if (V == 0) return hipSuccess;
-    pose_final_kernel<<<V, kBlock, 0, s>>>(views, n_waves, pose_part, dpose);
+    pose_final_kernel<<<V, kPoseBlock, 0, s>>>(views, n_waves, pose_part, dpose);
     return hipGetLastError();
 }
 

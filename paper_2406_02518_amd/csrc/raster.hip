@@ -433,32 +433,6 @@ __global__ __launch_bounds__(256) void tile_cost_kernel(const uint2 *ranges, int
     vals[t] = (uint32_t)t;
 }
 
-__global__ __launch_bounds__(256) void chunk_count_kernel(const uint2 *ranges, int n_tiles, int split,
-                                                          uint32_t *cnt)
-{
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= n_tiles) return;
-    const uint2 r = ranges[t];
-    const uint32_t L = r.y - r.x;
-    cnt[t] = (L + (uint32_t)split - 1u) / (uint32_t)split;
-}
-
-__global__ __launch_bounds__(256) void expand_items_kernel(const uint32_t *cnt, const uint32_t *base, int n_tiles,
-                                                           uint2 *items, uint32_t max_items, const uint64_t *total,
-                                                           uint32_t *n_items, uint32_t *counter)
-{
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t == 0) {
-        const uint64_t tot = *total;
-        *n_items = tot > (uint64_t)max_items ? max_items : (uint32_t)tot;
-        counter[0] = 0;
-        counter[1] = 0;
-    }
-    if (t >= n_tiles) return;
-    const uint32_t b = base[t], c = cnt[t];
-    for (uint32_t k = 0; k < c && b + k < max_items; ++k) items[b + k] = make_uint2((uint32_t)t, k);
-}
-
 template <int TW, int TH>
 hipError_t fwd_inst(const RasterArgs &a, int pb, hipStream_t s)
 {
@@ -518,18 +492,6 @@ hipError_t launch_tile_cost_keys(const uint2 *ranges, int n_tiles, uint32_t *key
                                  uint32_t *counter, hipStream_t s)
 {
     tile_cost_kernel<<<(n_tiles + 255) / 256 + (n_tiles == 0), 256, 0, s>>>(ranges, n_tiles, keys, vals, counter);
-    return hipGetLastError();
-}
-
-hipError_t launch_items(const uint2 *ranges, int n_tiles, int split, uint32_t *cnt, uint32_t *base, uint2 *items,
-                        uint32_t max_items, const SortWs &ws, uint64_t *scan_total, uint32_t *n_items,
-                        uint32_t *counter, hipStream_t s)
-{
-    const int nb = (n_tiles + 255) / 256 + (n_tiles == 0);
-    chunk_count_kernel<<<nb, 256, 0, s>>>(ranges, n_tiles, split, cnt);
-    hipError_t e = launch_exclusive_scan(cnt, nullptr, base, n_tiles, ws, scan_total, s);
-    if (e != hipSuccess) return e;
-    expand_items_kernel<<<nb, 256, 0, s>>>(cnt, base, n_tiles, items, max_items, scan_total, n_items, counter);
     return hipGetLastError();
 }
 

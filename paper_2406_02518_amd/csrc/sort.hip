@@ -51,15 +51,31 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *lds /*
 // every look-back hop is a cross-die round trip.)
 constexpr int64_t kScanSelfMax = (int64_t)kBlock * 16;
 
-__global__ __launch_bounds__(kBlock) void scan_reduce_kernel(const uint32_t *in, const uint32_t *gather,
-                                                             int64_t n, uint64_t *blocksum)
+// Scan inputs: a plain (optionally gathered) array, or the number of
+// `split`-entry work items of each tile range.
+struct PlainIn {
+    const uint32_t *in, *gather;
+    __device__ uint32_t operator()(int64_t i) const { return in[gather ? gather[i] : i]; }
+};
+struct ChunkIn {
+    const uint2 *ranges;
+    uint32_t split;
+    __device__ uint32_t operator()(int64_t t) const
+    {
+        const uint2 r = ranges[t];
+        return (r.y - r.x + split - 1u) / split;
+    }
+};
+
+template <class In>
+__global__ __launch_bounds__(kBlock) void scan_reduce_kernel(In f, int64_t n, uint64_t *blocksum)
 {
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     uint64_t s = 0;
 #pragma unroll 4
     for (int q = 0; q < kScanIPT; ++q) {
         const int64_t idx = base + q * kBlock + threadIdx.x;
-        if (idx < n) s += in[gather ? gather[idx] : idx];
+        if (idx < n) s += f(idx);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
@@ -105,21 +121,51 @@ __global__ __launch_bounds__(1024) void scan_top_kernel(uint64_t *blocksum, int6
     if (threadIdx.x == 0 && total) *total = carry_s;
 }
 
-// prescanned: blocksum holds exclusive block offsets (scan_top ran);
-// otherwise the block sums the raw block sums before it, and the last block
-// writes the total.
-__global__ __launch_bounds__(kBlock) void scan_apply_kernel(const uint32_t *in, const uint32_t *gather, int64_t n,
-                                                            const uint64_t *blocksum, int prescanned, uint32_t *out,
-                                                            uint64_t *total)
+// Scan outputs: the exclusive prefix, or the work items of each tile (its
+// item count, first item, and the (tile, chunk) list; finish() stores the
+// item count and clears the two work-queue counters).
+struct PlainOut {
+    uint32_t *out;
+    __device__ void operator()(int64_t i, uint32_t pre, uint32_t) const { out[i] = pre; }
+    __device__ void finish(uint64_t) const {}
+};
+struct ItemsOut {
+    uint32_t *cnt, *base;
+    uint2 *items;
+    uint32_t max_items;
+    uint32_t *n_items, *counter;
+    __device__ void operator()(int64_t t, uint32_t pre, uint32_t v) const
+    {
+        cnt[t] = v;
+        base[t] = pre;
+        for (uint32_t k = 0; k < v && pre + k < max_items; ++k) items[pre + k] = make_uint2((uint32_t)t, k);
+    }
+    __device__ void finish(uint64_t total) const
+    {
+        *n_items = total > (uint64_t)max_items ? max_items : (uint32_t)total;
+        counter[0] = 0;
+        counter[1] = 0;
+    }
+};
+
+// prescanned: blocksum holds exclusive block offsets (scan_top ran and wrote
+// *total); otherwise the block sums the raw block sums before it, and the
+// last block writes the total.
+template <class In, class Out>
+__global__ __launch_bounds__(kBlock) void scan_apply_kernel(In f, int64_t n, const uint64_t *blocksum, int prescanned,
+                                                            Out o, uint64_t *total)
 {
     __shared__ uint32_t tile[kScanTile];
+    __shared__ uint32_t vals[kScanTile];
     __shared__ uint32_t wl[kWaves];
     __shared__ uint64_t red[kWaves];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
 #pragma unroll 4
     for (int q = 0; q < kScanIPT; ++q) {
         const int64_t idx = base + q * kBlock + threadIdx.x;
-        tile[q * kBlock + threadIdx.x] = idx < n ? in[gather ? gather[idx] : idx] : 0u;
+        const uint32_t x = idx < n ? f(idx) : 0u;
+        tile[q * kBlock + threadIdx.x] = x;
+        vals[q * kBlock + threadIdx.x] = x;
     }
     uint64_t off;
     if (prescanned) {
@@ -128,7 +174,7 @@ __global__ __launch_bounds__(kBlock) void scan_apply_kernel(const uint32_t *in, 
         uint64_t s = 0;
         for (int j = threadIdx.x; j < (int)blockIdx.x; j += kBlock) s += blocksum[j];
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
+        for (int k = 32; k > 0; k >>= 1) s += __shfl_xor(s, k, kWave);
         if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
     }
     __syncthreads();
@@ -136,7 +182,11 @@ __global__ __launch_bounds__(kBlock) void scan_apply_kernel(const uint32_t *in, 
         off = 0;
 #pragma unroll
         for (int q = 0; q < kWaves; ++q) off += red[q];
-        if (threadIdx.x == 0 && total && blockIdx.x == gridDim.x - 1) *total = off + blocksum[blockIdx.x];
+    }
+    if (threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) {
+        const uint64_t t = prescanned ? *total : off + blocksum[blockIdx.x];
+        if (!prescanned && total) *total = t;
+        o.finish(t);
     }
     uint32_t v[kScanIPT], s = 0;
 #pragma unroll
@@ -156,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void scan_apply_kernel(const uint32_t *in, 
 #pragma unroll 4
     for (int q = 0; q < kScanIPT; ++q) {
         const int64_t idx = base + q * kBlock + threadIdx.x;
-        if (idx < n) out[idx] = off32 + tile[q * kBlock + threadIdx.x];
+        if (idx < n) o(idx, off32 + tile[q * kBlock + threadIdx.x], vals[q * kBlock + threadIdx.x]);
     }
 }
 
@@ -239,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *k
                                                                uint32_t *kout, uint32_t *vout, int64_t n_cap,
                                                                const uint32_t *n_dev, int shift, int nbits,
                                                                const uint32_t *offsets, const uint32_t *tot,
-                                                               int nblocks)
+                                                               int nblocks, const uint32_t *gsrc, uint32_t *gdst)
 {
     __shared__ uint32_t wh[kWaves][256];
     __shared__ uint32_t bstart[256];
@@ -311,6 +361,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *k
         const uint32_t o = gbase[d] + (uint32_t)j - bstart[d];
         kout[o] = kk;
         vout[o] = sv[j];
+        if (gsrc) gdst[o] = gsrc[sv[j]];
     }
 }
 
@@ -323,14 +374,16 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *k
 // wave's 64 offsets (read from the owning lanes by shuffles).  Within a pair
 // the entries run row-major over its tile rectangle.
 __global__ __launch_bounds__(kBlock) void emit_kernel(int64_t VN, int n, const uint32_t *order,
-                                                      const uint32_t *off_sorted, const uint32_t *cnt,
+                                                      const uint32_t *off_sorted, const uint32_t *cnt_sorted,
                                                       const uint2 *rect, const ViewDev *views, uint32_t *offs,
                                                       float4 *rec, uint32_t *tkey, uint32_t *tval,
                                                       uint32_t capacity, const uint64_t *total, uint32_t *m_out,
-                                                      uint32_t *flags)
+                                                      uint32_t *flags, uint2 *ranges, int n_tiles)
 {
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & (kWave - 1);
+    // clear the tile ranges for the ranges kernel after the sort
+    for (int64_t t = r; t < n_tiles; t += (int64_t)gridDim.x * kBlock) ranges[t] = make_uint2(0u, 0u);
     if (r == 0) {
         const uint64_t t = *total;
         const bool over = t > (uint64_t)capacity;
@@ -341,7 +394,7 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(int64_t VN, int n, const u
     uint32_t c = 0, off = 0xFFFFFFFFu, i = 0, x0y0 = 0, span = 1, rowbase = 0, ntx = 0;
     if (valid) {
         const uint32_t vi = order[r];
-        c = cnt[vi];
+        c = cnt_sorted[r];
         off = off_sorted[r];
         if (c) {
             offs[vi] = off;
@@ -427,21 +480,53 @@ int64_t blocks_for(int64_t n, int64_t per) { return (n + per - 1) / per; }
 size_t sort_counts_words(int64_t n) { return (size_t)256 * (size_t)std::max<int64_t>(1, blocks_for(n, kRadixTile)); }
 size_t sort_blocksum_words(int64_t n) { return (size_t)std::max<int64_t>(1, blocks_for(n, kScanTile)) + 1; }
 
+namespace {
+
+template <class In, class Out>
+hipError_t scan_launch(In f, int64_t n, Out o, const SortWs &ws, uint64_t *total, hipStream_t s)
+{
+    const int64_t nb = blocks_for(n, kScanTile);
+    if (!ws.blocksum || (size_t)nb + 1 > ws.blocksum_words || nb > 0x7FFFFFFF) return hipErrorInvalidValue;
+    scan_reduce_kernel<In><<<(unsigned)nb, kBlock, 0, s>>>(f, n, ws.blocksum);
+    const bool pre = nb > kScanSelfMax;
+    if (pre) scan_top_kernel<<<1, 1024, 0, s>>>(ws.blocksum, nb, total);
+    scan_apply_kernel<In, Out><<<(unsigned)nb, kBlock, 0, s>>>(f, n, ws.blocksum, pre ? 1 : 0, o, total);
+    return hipGetLastError();
+}
+
+__global__ void items_empty_kernel(uint32_t *n_items, uint32_t *counter)
+{
+    *n_items = 0;
+    counter[0] = 0;
+    counter[1] = 0;
+}
+
+}  // namespace
+
 hipError_t launch_exclusive_scan(const uint32_t *in, const uint32_t *gather, uint32_t *out, int64_t n,
                                  const SortWs &ws, uint64_t *total, hipStream_t s)
 {
     if (n == 0) return total ? launch_zero_u64(total, s) : hipSuccess;
-    const int64_t nb = blocks_for(n, kScanTile);
-    if (!ws.blocksum || (size_t)nb + 1 > ws.blocksum_words || nb > 0x7FFFFFFF) return hipErrorInvalidValue;
-    scan_reduce_kernel<<<(unsigned)nb, kBlock, 0, s>>>(in, gather, n, ws.blocksum);
-    const bool pre = nb > kScanSelfMax;
-    if (pre) scan_top_kernel<<<1, 1024, 0, s>>>(ws.blocksum, nb, total);
-    scan_apply_kernel<<<(unsigned)nb, kBlock, 0, s>>>(in, gather, n, ws.blocksum, pre ? 1 : 0, out, total);
-    return hipGetLastError();
+    if (!total) return hipErrorInvalidValue;
+    return scan_launch(PlainIn{in, gather}, n, PlainOut{out}, ws, total, s);
+}
+
+hipError_t launch_items(const uint2 *ranges, int n_tiles, int split, uint32_t *cnt, uint32_t *base, uint2 *items,
+                        uint32_t max_items, const SortWs &ws, uint64_t *scan_total, uint32_t *n_items,
+                        uint32_t *counter, hipStream_t s)
+{
+    if (split <= 0) return hipErrorInvalidValue;
+    if (n_tiles == 0) {
+        items_empty_kernel<<<1, 1, 0, s>>>(n_items, counter);
+        return hipGetLastError();
+    }
+    return scan_launch(ChunkIn{ranges, (uint32_t)split}, n_tiles,
+                       ItemsOut{cnt, base, items, max_items, n_items, counter}, ws, scan_total, s);
 }
 
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n_cap,
-                            const uint32_t *n_dev, int bits, const SortWs &ws, bool *in_k1, hipStream_t s)
+                            const uint32_t *n_dev, int bits, const SortWs &ws, bool *in_k1, hipStream_t s,
+                            const uint32_t *gsrc, uint32_t *gdst)
 {
     *in_k1 = false;
     if (n_cap <= 0 || bits <= 0) return hipSuccess;
@@ -455,8 +540,10 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
         radix_count_kernel<<<(unsigned)nblocks, kBlock, 0, s>>>(ka, n_cap, n_dev, shift, mask, ws.counts,
                                                                  (int)nblocks);
         radix_prefix_kernel<<<256, kBlock, 0, s>>>(ws.counts, (int)nblocks, ws.tot);
+        const bool last = shift + 8 >= bits;
         radix_scatter_kernel<<<(unsigned)nblocks, kBlock, 0, s>>>(ka, va, kb, vb, n_cap, n_dev, shift, nbits,
-                                                                   ws.counts, ws.tot, (int)nblocks);
+                                                                   ws.counts, ws.tot, (int)nblocks,
+                                                                   last ? gsrc : nullptr, last ? gdst : nullptr);
         std::swap(ka, kb);
         std::swap(va, vb);
         *in_k1 = !*in_k1;
@@ -464,21 +551,21 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
     return hipGetLastError();
 }
 
-hipError_t launch_emit(int64_t VN, int n, const uint32_t *order, const uint32_t *off_sorted, const uint32_t *cnt,
-                       const uint2 *rect, const ViewDev *views, uint32_t *offs, float4 *rec, uint32_t *tkey,
-                       uint32_t *tval, uint32_t capacity, const uint64_t *total, uint32_t *m_out, uint32_t *flags,
-                       hipStream_t s)
+hipError_t launch_emit(int64_t VN, int n, const uint32_t *order, const uint32_t *off_sorted,
+                       const uint32_t *cnt_sorted, const uint2 *rect, const ViewDev *views, uint32_t *offs,
+                       float4 *rec, uint32_t *tkey, uint32_t *tval, uint32_t capacity, const uint64_t *total,
+                       uint32_t *m_out, uint32_t *flags, uint2 *ranges, int n_tiles, hipStream_t s)
 {
     const int64_t nb = std::max<int64_t>(1, blocks_for(VN, kBlock));
-    emit_kernel<<<(unsigned)nb, kBlock, 0, s>>>(VN, n, order, off_sorted, cnt, rect, views, offs, rec, tkey, tval,
-                                                capacity, total, m_out, flags);
+    emit_kernel<<<(unsigned)nb, kBlock, 0, s>>>(VN, n, order, off_sorted, cnt_sorted, rect, views, offs, rec, tkey,
+                                                tval, capacity, total, m_out, flags, ranges, n_tiles);
     return hipGetLastError();
 }
 
 hipError_t launch_ranges(const uint32_t *keys, const uint32_t *m_dev, int64_t m_cap, uint2 *ranges, int n_tiles,
-                         hipStream_t s)
+                         bool zero, hipStream_t s)
 {
-    if (n_tiles > 0) zero_ranges_kernel<<<(unsigned)blocks_for(n_tiles, kBlock), kBlock, 0, s>>>(ranges, n_tiles);
+    if (zero && n_tiles > 0) zero_ranges_kernel<<<(unsigned)blocks_for(n_tiles, kBlock), kBlock, 0, s>>>(ranges, n_tiles);
     if (m_cap > 0) {
         const int64_t nb = std::min<int64_t>(blocks_for(m_cap, kBlock), 65536);
         ranges_kernel<<<(unsigned)nb, kBlock, 0, s>>>(keys, m_dev, m_cap, ranges, n_tiles);
