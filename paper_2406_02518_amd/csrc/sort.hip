@@ -20,8 +20,11 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kScanIPT = kScanTile / kBlock;  // 16
-constexpr int kRadixIPT = 16;
-constexpr int kRadixTile = kBlock * kRadixIPT;  // 4096
+// keys per thread of a radix block: 16 (4096 keys per block) for large sorts,
+// 4 (1024 keys) below kRadixSmallN keys so that a pass still spreads over
+// every compute unit
+constexpr int kRadixIPTLarge = 16, kRadixIPTSmall = 4;
+constexpr int64_t kRadixSmallN = (int64_t)2 << 20;
 constexpr int kWaves = kBlock / kWave;
 
 // exclusive scan over a block of 256 threads; returns the block total
@@ -222,9 +225,11 @@ __device__ __forceinline__ int64_t runtime_n(int64_t n_cap, const uint32_t *n_de
     return m < n_cap ? m : n_cap;
 }
 
+template <int IPT>
 __global__ __launch_bounds__(kBlock) void radix_count_kernel(const uint32_t *kin, int64_t n_cap, const uint32_t *n_dev,
                                                              int shift, uint32_t mask, uint32_t *counts, int nblocks)
 {
+    constexpr int kRadixTile = kBlock * IPT;
     __shared__ uint32_t h[kWaves][256];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
@@ -233,7 +238,7 @@ __global__ __launch_bounds__(kBlock) void radix_count_kernel(const uint32_t *kin
     const int64_t n = runtime_n(n_cap, n_dev);
     const int64_t wbase = (int64_t)blockIdx.x * kRadixTile + w * (kRadixTile / kWaves);
 #pragma unroll 4
-    for (int r = 0; r < kRadixIPT; ++r) {
+    for (int r = 0; r < IPT; ++r) {
         const int64_t idx = wbase + r * kWave + lane;
         if (idx < n) atomicAdd(&h[w][(kin[idx] >> shift) & mask], 1u);
     }
@@ -281,16 +286,18 @@ __global__ __launch_bounds__(kBlock) void radix_prefix_kernel(uint32_t *counts, 
     if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
-// Stable scatter: every wave ranks its 16 rounds of 64 consecutive keys with
+// Stable scatter: every wave ranks its IPT rounds of 64 consecutive keys with
 // ballots (lanes sharing the digit), the block combines the 4 wave
 // histograms, the keys are staged in LDS in digit order and written out
 // with consecutive lanes on consecutive addresses.
+template <int IPT>
 __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *kin, const uint32_t *vin,
                                                                uint32_t *kout, uint32_t *vout, int64_t n_cap,
                                                                const uint32_t *n_dev, int shift, int nbits,
                                                                const uint32_t *offsets, const uint32_t *tot,
                                                                int nblocks, const uint32_t *gsrc, uint32_t *gdst)
 {
+    constexpr int kRadixTile = kBlock * IPT;
     __shared__ uint32_t wh[kWaves][256];
     __shared__ uint32_t bstart[256];
     __shared__ uint32_t gbase[256];
@@ -306,10 +313,10 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *k
     for (int q = 0; q < 256 / kWave; ++q) wh[w][lane + q * kWave] = 0;
     __syncthreads();
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-    uint32_t key[kRadixIPT], val[kRadixIPT], rank[kRadixIPT];
+    uint32_t key[IPT], val[IPT], rank[IPT];
     const int64_t wbase = base + w * (kRadixTile / kWaves);
 #pragma unroll
-    for (int r = 0; r < kRadixIPT; ++r) {
+    for (int r = 0; r < IPT; ++r) {
         const int64_t idx = wbase + r * kWave + lane;
         const bool ok = idx < n;
         key[r] = ok ? kin[idx] : 0u;
@@ -344,7 +351,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *k
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kRadixIPT; ++r) {
+    for (int r = 0; r < IPT; ++r) {
         const int64_t idx = wbase + r * kWave + lane;
         if (idx < n) {
             const uint32_t d = (key[r] >> shift) & mask;
@@ -477,7 +484,15 @@ int64_t blocks_for(int64_t n, int64_t per) { return (n + per - 1) / per; }
 
 }  // namespace
 
-size_t sort_counts_words(int64_t n) { return (size_t)256 * (size_t)std::max<int64_t>(1, blocks_for(n, kRadixTile)); }
+int radix_ipt(int64_t n) { return n < kRadixSmallN ? kRadixIPTSmall : kRadixIPTLarge; }
+
+// (monotone in n, so a workspace sized for n also serves every smaller sort)
+size_t sort_counts_words(int64_t n)
+{
+    const int64_t small = blocks_for(std::min(n, kRadixSmallN), (int64_t)kBlock * kRadixIPTSmall);
+    const int64_t large = blocks_for(n, (int64_t)kBlock * kRadixIPTLarge);
+    return (size_t)256 * (size_t)std::max<int64_t>({1, small, large});
+}
 size_t sort_blocksum_words(int64_t n) { return (size_t)std::max<int64_t>(1, blocks_for(n, kScanTile)) + 1; }
 
 namespace {
@@ -531,19 +546,31 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
     *in_k1 = false;
     if (n_cap <= 0 || bits <= 0) return hipSuccess;
     if (bits > 32 || !ws.counts || !ws.tot || sort_counts_words(n_cap) > ws.counts_words) return hipErrorInvalidValue;
-    const int64_t nblocks = blocks_for(n_cap, kRadixTile);
+    const int ipt = radix_ipt(n_cap);
+    const int64_t nblocks = blocks_for(n_cap, (int64_t)kBlock * ipt);
     if (nblocks > 0x7FFFFFFF) return hipErrorInvalidValue;
     uint32_t *ka = k0, *va = v0, *kb = k1, *vb = v1;
     for (int shift = 0; shift < bits; shift += 8) {
         const int nbits = std::min(8, bits - shift);
         const uint32_t mask = (1u << nbits) - 1u;
-        radix_count_kernel<<<(unsigned)nblocks, kBlock, 0, s>>>(ka, n_cap, n_dev, shift, mask, ws.counts,
-                                                                 (int)nblocks);
-        radix_prefix_kernel<<<256, kBlock, 0, s>>>(ws.counts, (int)nblocks, ws.tot);
         const bool last = shift + 8 >= bits;
-        radix_scatter_kernel<<<(unsigned)nblocks, kBlock, 0, s>>>(ka, va, kb, vb, n_cap, n_dev, shift, nbits,
-                                                                   ws.counts, ws.tot, (int)nblocks,
-                                                                   last ? gsrc : nullptr, last ? gdst : nullptr);
+        const uint32_t *gs = last ? gsrc : nullptr;
+        uint32_t *gd = last ? gdst : nullptr;
+        if (ipt == kRadixIPTSmall) {
+            radix_count_kernel<kRadixIPTSmall><<<(unsigned)nblocks, kBlock, 0, s>>>(ka, n_cap, n_dev, shift, mask,
+                                                                                     ws.counts, (int)nblocks);
+        } else {
+            radix_count_kernel<kRadixIPTLarge><<<(unsigned)nblocks, kBlock, 0, s>>>(ka, n_cap, n_dev, shift, mask,
+                                                                                     ws.counts, (int)nblocks);
+        }
+        radix_prefix_kernel<<<256, kBlock, 0, s>>>(ws.counts, (int)nblocks, ws.tot);
+        if (ipt == kRadixIPTSmall) {
+            radix_scatter_kernel<kRadixIPTSmall><<<(unsigned)nblocks, kBlock, 0, s>>>(
+                ka, va, kb, vb, n_cap, n_dev, shift, nbits, ws.counts, ws.tot, (int)nblocks, gs, gd);
+        } else {
+            radix_scatter_kernel<kRadixIPTLarge><<<(unsigned)nblocks, kBlock, 0, s>>>(
+                ka, va, kb, vb, n_cap, n_dev, shift, nbits, ws.counts, ws.tot, (int)nblocks, gs, gd);
+        }
         std::swap(ka, kb);
         std::swap(va, vb);
         *in_k1 = !*in_k1;
