@@ -549,14 +549,10 @@ ddgs_status enqueue_backward(ddgs_ctx *c, const float *dL, const ddgs_grads *g, 
     pa.per_gaussian = per_g ? 1 : 0;
     pa.slot_cap = ra.slot_cap;
     HIP_TRY(c, launch_project_bwd(pa, s));
-    if (g->db_iso || g->dB_dir) {
-        HIP_TRY(c, launch_basis_grad(pa.m, pa.ubuf, buf<float>(c, "basis_part"), s));
-        HIP_TRY(c, launch_basis_final(pa.m, buf<float>(c, "basis_part"), g->db_iso, g->dB_dir, s));
-    }
-    if (g->dpose) {
-        const int n_waves = ((n + 255) / 256) * 4;
-        HIP_TRY(c, launch_pose_final(buf<ViewDev>(c, "views"), V, n_waves, buf<float>(c, "pose_part"), g->dpose, s));
-    }
+    if (g->db_iso || g->dB_dir) HIP_TRY(c, launch_basis_grad(pa.m, pa.ubuf, buf<float>(c, "basis_part"), s));
+    const int n_waves = ((n + 255) / 256) * 4;
+    HIP_TRY(c, launch_grad_final(pa.m, buf<float>(c, "basis_part"), g->db_iso, g->dB_dir, buf<ViewDev>(c, "views"), V,
+                                 n_waves, buf<float>(c, "pose_part"), g->dpose, s));
     stage_end(c, DDGS_T_PROJECT_BWD);
     return DDGS_OK;
 }

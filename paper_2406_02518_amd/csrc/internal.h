@@ -183,9 +183,10 @@ hipError_t launch_project_bwd(const ProjBwdArgs &a, hipStream_t s);
 int basis_grad_waves(int n);
 size_t basis_part_floats(int n);
 hipError_t launch_basis_grad(const ModelDev &m, const float *ubuf, float *part, hipStream_t s);
-hipError_t launch_basis_final(const ModelDev &m, const float *part, float *db, float *dB, hipStream_t s);
-hipError_t launch_pose_final(const ViewDev *views, int V, int n_waves, const float *pose_part,
-                             float *dpose, hipStream_t s);
+// FP64 sums of the basis tiles (when db or dB) and of the pose partials (when
+// dpose), in one launch
+hipError_t launch_grad_final(const ModelDev &m, const float *bpart, float *db, float *dB, const ViewDev *views,
+                             int V, int n_waves, const float *ppart, float *dpose, hipStream_t s);
 
 // sort.hip
 constexpr int kScanTile = 4096;

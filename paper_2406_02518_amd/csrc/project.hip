@@ -554,7 +554,7 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
 // isotropic z, the rest zero).  Each wave runs it on the matrix cores with
 // v_mfma_f32_16x16x4_f32 over a contiguous run of Gaussians (four per
 // instruction), keeping a 16 x 16 accumulator per 16 features; the per-wave
-// tiles are then summed in FP64 by basis_final_kernel.
+// tiles are then summed in FP64 by grad_final_kernel.
 constexpr int kBasisWaves = 2048;
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -608,47 +608,64 @@ __global__ __launch_bounds__(kBlock) void basis_grad_kernel(int n, int k, const 
         }
 }
 
-// one block per output element: FP64 sum of the per-wave tiles
+// FP64 reductions after the projection backward, in one launch of
+// kFinalBlock-thread blocks: blocks [0, 16 NCOL) each sum one element of the
+// per-wave basis tiles (when basis gradients are wanted), the next V blocks
+// each turn one view's per-wave pose partials into (rho, omega).
+constexpr int kFinalBlock = 512;
+
+template <int N>
+__device__ __forceinline__ void block_sum_f64(double (&x)[N], double (*red)[N])
+{
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        double y = x[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) y += __shfl_xor(y, o, kWave);
+        x[q] = y;
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0)
+#pragma unroll
+        for (int q = 0; q < N; ++q) red[threadIdx.x / kWave][q] = x[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        double t = 0.0;
+        for (int w = 0; w < kFinalBlock / kWave; ++w) t += red[w][q];
+        x[q] = t;
+    }
+}
+
 template <int KMAX, int L>
-__global__ __launch_bounds__(kBlock) void basis_final_kernel(int k, const float *part, int nwaves, float *db,
-                                                             float *dB)
+__device__ void basis_final_block(int o, int k, const float *part, int nwaves, float *db, float *dB)
 {
     constexpr int KL = L * (L + 2);
     constexpr int NCOL = ((KMAX + 15) / 16) * 16;
-    const int o = blockIdx.x;  // (row, column) of the 16 x NCOL tile
-    const int i = o / NCOL, j = o % NCOL;
-    double s = 0.0;
-    for (int w = threadIdx.x; w < nwaves; w += kBlock) s += (double)part[((size_t)w * 16 + i) * NCOL + j];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
-    __shared__ double red[kBlock / kWave];
-    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
-    __syncthreads();
+    const int i = o / NCOL, j = o % NCOL;  // (row, column) of the 16 x NCOL tile
+    double s[1] = {0.0};
+    for (int w = threadIdx.x; w < nwaves; w += kFinalBlock) s[0] += (double)part[((size_t)w * 16 + i) * NCOL + j];
+    __shared__ double red[kFinalBlock / kWave][1];
+    block_sum_f64<1>(s, red);
     if (threadIdx.x != 0 || j >= k) return;
-    double t = 0.0;
-    for (int q = 0; q < kBlock / kWave; ++q) t += red[q];
     if (i == 15) {
-        if (db) db[j] = (float)t;
+        if (db) db[j] = (float)s[0];
     } else if (i < KL) {
-        if (dB) dB[i * k + j] = (float)t;
+        if (dB) dB[i * k + j] = (float)s[0];
     }
 }
 
 // dpose[v] = (rho, omega) from the per-wave partials: rho = sum d mu_c +
 // sum R d r; omega = sum (R mu) x d mu_c + covariance term + t x sum d mu_c.
-constexpr int kPoseBlock = 512;
-__global__ __launch_bounds__(kPoseBlock) void pose_final_kernel(const ViewDev *views, int n_waves,
-                                                                const float *part, float *dpose)
+__device__ void pose_final_block(int v, const ViewDev *views, int n_waves, const float *part, float *dpose)
 {
-    const int v = blockIdx.x;
     double s[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) s[q] = 0.0;
     // two partials' loads in flight per thread
     int w = threadIdx.x;
-    for (; w + kPoseBlock < n_waves; w += 2 * kPoseBlock) {
+    for (; w + kFinalBlock < n_waves; w += 2 * kFinalBlock) {
         const float *p0 = part + ((size_t)v * n_waves + w) * 9;
-        const float *p1 = p0 + (size_t)kPoseBlock * 9;
+        const float *p1 = p0 + (size_t)kFinalBlock * 9;
         float x0[9], x1[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
@@ -663,36 +680,29 @@ __global__ __launch_bounds__(kPoseBlock) void pose_final_kernel(const ViewDev *v
 #pragma unroll
         for (int q = 0; q < 9; ++q) s[q] += (double)p[q];
     }
-    __shared__ double red[kPoseBlock / kWave][9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        double x = s[q];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
-        s[q] = x;
-    }
-    if ((threadIdx.x & (kWave - 1)) == 0)
-#pragma unroll
-        for (int q = 0; q < 9; ++q) red[threadIdx.x / kWave][q] = s[q];
-    __syncthreads();
+    __shared__ double red[kFinalBlock / kWave][9];
+    block_sum_f64<9>(s, red);
     if (threadIdx.x == 0) {
-        double t9[9];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            double x = 0.0;
-            for (int r = 0; r < kPoseBlock / kWave; ++r) x += red[r][q];
-            t9[q] = x;
-        }
         const ViewDev &V = views[v];
         const double tx = V.t[0], ty = V.t[1], tz = V.t[2];
         float *o = dpose + 6 * v;
-        o[0] = (float)(t9[0] + t9[6]);
-        o[1] = (float)(t9[1] + t9[7]);
-        o[2] = (float)(t9[2] + t9[8]);
-        o[3] = (float)(t9[3] + ty * t9[2] - tz * t9[1]);
-        o[4] = (float)(t9[4] + tz * t9[0] - tx * t9[2]);
-        o[5] = (float)(t9[5] + tx * t9[1] - ty * t9[0]);
+        o[0] = (float)(s[0] + s[6]);
+        o[1] = (float)(s[1] + s[7]);
+        o[2] = (float)(s[2] + s[8]);
+        o[3] = (float)(s[3] + ty * s[2] - tz * s[1]);
+        o[4] = (float)(s[4] + tz * s[0] - tx * s[2]);
+        o[5] = (float)(s[5] + tx * s[1] - ty * s[0]);
     }
+}
+
+template <int KMAX, int L>
+__global__ __launch_bounds__(kFinalBlock) void grad_final_kernel(int k, const float *bpart, int bwaves, int nbasis,
+                                                                 float *db, float *dB, const ViewDev *views,
+                                                                 int n_waves, const float *ppart, float *dpose)
+{
+    const int o = blockIdx.x;
+    if (o < nbasis) basis_final_block<KMAX, L>(o, k, bpart, bwaves, db, dB);
+    else pose_final_block(o - nbasis, views, n_waves, ppart, dpose);
 }
 
 template <typename F>
@@ -772,23 +782,21 @@ hipError_t launch_basis_grad(const ModelDev &m, const float *ubuf, float *part, 
     });
 }
 
-hipError_t launch_basis_final(const ModelDev &m, const float *part, float *db, float *dB, hipStream_t s)
+hipError_t launch_grad_final(const ModelDev &m, const float *bpart, float *db, float *dB, const ViewDev *views,
+                             int V, int n_waves, const float *ppart, float *dpose, hipStream_t s)
 {
-    const int nwaves = basis_grad_waves(m.n);
+    const bool basis = (db || dB) && m.n > 0;
+    const int nview = dpose ? V : 0;
+    const int bwaves = basis_grad_waves(std::max(m.n, 1));
     return dispatch_kl(m.k, m.L, [&](auto K, auto L) {
         constexpr int KK = decltype(K)::value, LL = decltype(L)::value;
         constexpr int NCOL = ((KK + 15) / 16) * 16;
-        basis_final_kernel<KK, LL><<<16 * NCOL, kBlock, 0, s>>>(m.k, part, nwaves, db, dB);
+        const int nbasis = basis ? 16 * NCOL : 0;
+        if (nbasis + nview > 0)
+            grad_final_kernel<KK, LL><<<nbasis + nview, kFinalBlock, 0, s>>>(m.k, bpart, bwaves, nbasis, db, dB,
+                                                                            views, n_waves, ppart, dpose);
         return hipGetLastError();
     });
-}
-
-hipError_t launch_pose_final(const ViewDev *views, int V, int n_waves, const float *pose_part,
-                             float *dpose, hipStream_t s)
-{
-    if (V == 0) return hipSuccess;
-    pose_final_kernel<<<V, kPoseBlock, 0, s>>>(views, n_waves, pose_part, dpose);
-    return hipGetLastError();
 }
 
 }  // namespace ddgs

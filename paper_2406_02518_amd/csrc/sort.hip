@@ -70,13 +70,13 @@ struct ChunkIn {
     }
 };
 
-template <class In>
+template <class In, int IPT>
 __global__ __launch_bounds__(kBlock) void scan_reduce_kernel(In f, int64_t n, uint64_t *blocksum)
 {
-    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    const int64_t base = (int64_t)blockIdx.x * (kBlock * IPT);
     uint64_t s = 0;
 #pragma unroll 4
-    for (int q = 0; q < kScanIPT; ++q) {
+    for (int q = 0; q < IPT; ++q) {
         const int64_t idx = base + q * kBlock + threadIdx.x;
         if (idx < n) s += f(idx);
     }
@@ -154,17 +154,18 @@ struct ItemsOut {
 // prescanned: blocksum holds exclusive block offsets (scan_top ran and wrote
 // *total); otherwise the block sums the raw block sums before it, and the
 // last block writes the total.
-template <class In, class Out>
+template <class In, class Out, int IPT>
 __global__ __launch_bounds__(kBlock) void scan_apply_kernel(In f, int64_t n, const uint64_t *blocksum, int prescanned,
                                                             Out o, uint64_t *total)
 {
-    __shared__ uint32_t tile[kScanTile];
-    __shared__ uint32_t vals[kScanTile];
+    constexpr int TILE = kBlock * IPT;
+    __shared__ uint32_t tile[TILE];
+    __shared__ uint32_t vals[TILE];
     __shared__ uint32_t wl[kWaves];
     __shared__ uint64_t red[kWaves];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    const int64_t base = (int64_t)blockIdx.x * TILE;
 #pragma unroll 4
-    for (int q = 0; q < kScanIPT; ++q) {
+    for (int q = 0; q < IPT; ++q) {
         const int64_t idx = base + q * kBlock + threadIdx.x;
         const uint32_t x = idx < n ? f(idx) : 0u;
         tile[q * kBlock + threadIdx.x] = x;
@@ -191,23 +192,23 @@ __global__ __launch_bounds__(kBlock) void scan_apply_kernel(In f, int64_t n, con
         if (!prescanned && total) *total = t;
         o.finish(t);
     }
-    uint32_t v[kScanIPT], s = 0;
+    uint32_t v[IPT], s = 0;
 #pragma unroll
-    for (int q = 0; q < kScanIPT; ++q) {
-        v[q] = tile[threadIdx.x * kScanIPT + q];
+    for (int q = 0; q < IPT; ++q) {
+        v[q] = tile[threadIdx.x * IPT + q];
         s += v[q];
     }
     uint32_t tot;
     uint32_t pre = block_excl_scan(s, wl, tot);
 #pragma unroll
-    for (int q = 0; q < kScanIPT; ++q) {
-        tile[threadIdx.x * kScanIPT + q] = pre;
+    for (int q = 0; q < IPT; ++q) {
+        tile[threadIdx.x * IPT + q] = pre;
         pre += v[q];
     }
     __syncthreads();
     const uint32_t off32 = (uint32_t)off;
 #pragma unroll 4
-    for (int q = 0; q < kScanIPT; ++q) {
+    for (int q = 0; q < IPT; ++q) {
         const int64_t idx = base + q * kBlock + threadIdx.x;
         if (idx < n) o(idx, off32 + tile[q * kBlock + threadIdx.x], vals[q * kBlock + threadIdx.x]);
     }
@@ -493,19 +494,22 @@ size_t sort_counts_words(int64_t n)
     const int64_t large = blocks_for(n, (int64_t)kBlock * kRadixIPTLarge);
     return (size_t)256 * (size_t)std::max<int64_t>({1, small, large});
 }
-size_t sort_blocksum_words(int64_t n) { return (size_t)std::max<int64_t>(1, blocks_for(n, kScanTile)) + 1; }
+// (enough for the 256-per-block item scans too: their inputs are tile counts)
+size_t sort_blocksum_words(int64_t n) { return (size_t)std::max<int64_t>(1, blocks_for(n, kBlock)) + 1; }
 
 namespace {
 
-template <class In, class Out>
+// IPT values per thread: kScanIPT (4096 per block) for long inputs, 1 (256
+// per block) where per-element output work dominates (the item lists)
+template <int IPT, class In, class Out>
 hipError_t scan_launch(In f, int64_t n, Out o, const SortWs &ws, uint64_t *total, hipStream_t s)
 {
-    const int64_t nb = blocks_for(n, kScanTile);
+    const int64_t nb = blocks_for(n, (int64_t)kBlock * IPT);
     if (!ws.blocksum || (size_t)nb + 1 > ws.blocksum_words || nb > 0x7FFFFFFF) return hipErrorInvalidValue;
-    scan_reduce_kernel<In><<<(unsigned)nb, kBlock, 0, s>>>(f, n, ws.blocksum);
+    scan_reduce_kernel<In, IPT><<<(unsigned)nb, kBlock, 0, s>>>(f, n, ws.blocksum);
     const bool pre = nb > kScanSelfMax;
     if (pre) scan_top_kernel<<<1, 1024, 0, s>>>(ws.blocksum, nb, total);
-    scan_apply_kernel<In, Out><<<(unsigned)nb, kBlock, 0, s>>>(f, n, ws.blocksum, pre ? 1 : 0, o, total);
+    scan_apply_kernel<In, Out, IPT><<<(unsigned)nb, kBlock, 0, s>>>(f, n, ws.blocksum, pre ? 1 : 0, o, total);
     return hipGetLastError();
 }
 
@@ -523,7 +527,7 @@ hipError_t launch_exclusive_scan(const uint32_t *in, const uint32_t *gather, uin
 {
     if (n == 0) return total ? launch_zero_u64(total, s) : hipSuccess;
     if (!total) return hipErrorInvalidValue;
-    return scan_launch(PlainIn{in, gather}, n, PlainOut{out}, ws, total, s);
+    return scan_launch<kScanIPT>(PlainIn{in, gather}, n, PlainOut{out}, ws, total, s);
 }
 
 hipError_t launch_items(const uint2 *ranges, int n_tiles, int split, uint32_t *cnt, uint32_t *base, uint2 *items,
@@ -535,7 +539,7 @@ hipError_t launch_items(const uint2 *ranges, int n_tiles, int split, uint32_t *c
         items_empty_kernel<<<1, 1, 0, s>>>(n_items, counter);
         return hipGetLastError();
     }
-    return scan_launch(ChunkIn{ranges, (uint32_t)split}, n_tiles,
+    return scan_launch<1>(ChunkIn{ranges, (uint32_t)split}, n_tiles,
                        ItemsOut{cnt, base, items, max_items, n_items, counter}, ws, scan_total, s);
 }
 
