@@ -148,8 +148,30 @@ ddgs_status ddgs_get_options(const ddgs_ctx *ctx, ddgs_options *opt);
 /* Eq. 1/3 inputs. */
 ddgs_status ddgs_set_model(ddgs_ctx *ctx, const ddgs_model *model);
 ddgs_status ddgs_set_views(ddgs_ctx *ctx, const ddgs_view *views, int n_views);
+/* Test hook: radiosity c per (view, Gaussian), device [n_views][n] floats,
+ * used instead of Eq. 3 (NULL restores Eq. 3).  With it the image is linear
+ * in c (Eq. 1), and the backward leaves the features and bases out of the
+ * chain (their gradients are zero).  Borrowed like the model arrays; the
+ * caller keeps it sized for the current views.  Drops a captured step. */
+ddgs_status ddgs_set_radiosity_override(ddgs_ctx *ctx, const float *c);
 /* Number of floats of the concatenated images of the current views. */
 ddgs_status ddgs_image_size(const ddgs_ctx *ctx, int64_t *n_floats);
+
+/* Device workspace.  By default the library allocates its workspace (tile
+ * lists, records, sort temporaries, gradient slots, ...) with hipMalloc and
+ * grows it on demand.  ddgs_set_workspace hands it a caller-owned device
+ * region instead (e.g. a torch byte tensor; 256-byte aligned; the caller
+ * keeps it alive and unchanged until the next ddgs_set_workspace or
+ * ddgs_destroy): every workspace buffer is then carved from that region, and
+ * a call that needs more than is left fails with DDGS_ERR_OOM and leaves the
+ * device untouched.  NULL returns to library-owned allocation.  Either way
+ * the previous workspace, any captured step and the last render are
+ * dropped.  ddgs_workspace_size reports the bytes needed for the current
+ * model, views and options with room for `capacity` tile entries (<= 0: the
+ * option's capacity, else the last render's count); ddgs_autotune and the
+ * debug getters need more for their own trial buffers. */
+ddgs_status ddgs_set_workspace(ddgs_ctx *ctx, void *dev, size_t bytes);
+ddgs_status ddgs_workspace_size(ddgs_ctx *ctx, int64_t capacity, size_t *bytes);
 
 /* ---------------------------------------------------------------- compute */
 

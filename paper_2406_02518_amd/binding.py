@@ -25,6 +25,7 @@ STAGES = ("project", "sort", "raster_fwd", "loss", "raster_bwd", "project_bwd")
 EXPORTED = (
     "ddgs_create", "ddgs_destroy", "ddgs_set_stream", "ddgs_status_str", "ddgs_last_error",
     "ddgs_default_options", "ddgs_set_options", "ddgs_get_options", "ddgs_set_model", "ddgs_set_views",
+    "ddgs_set_radiosity_override", "ddgs_set_workspace", "ddgs_workspace_size",
     "ddgs_image_size", "ddgs_render", "ddgs_backward", "ddgs_loss", "ddgs_step_capture", "ddgs_step_launch",
     "ddgs_check", "ddgs_autotune", "ddgs_param_count", "ddgs_num_rendered", "ddgs_debug_copy",
     "ddgs_debug_keep_unsorted", "ddgs_debug_sort_pairs", "ddgs_debug_exclusive_scan", "ddgs_debug_count_pairs",
@@ -83,6 +84,9 @@ def lib():
             "ddgs_get_options": ([vp, C.POINTER(ddgs_options)], st),
             "ddgs_set_model": ([vp, C.POINTER(ddgs_model)], st),
             "ddgs_set_views": ([vp, C.POINTER(ddgs_view), C.c_int], st),
+            "ddgs_set_radiosity_override": ([vp, vp], st),
+            "ddgs_set_workspace": ([vp, vp, C.c_size_t], st),
+            "ddgs_workspace_size": ([vp, i64, C.POINTER(C.c_size_t)], st),
             "ddgs_image_size": ([vp, C.POINTER(i64)], st),
             "ddgs_render": ([vp, vp], st),
             "ddgs_backward": ([vp, vp, C.POINTER(ddgs_grads)], st),
@@ -161,6 +165,20 @@ def ddgs_set_model(ctx, model):
 
 def ddgs_set_views(ctx, views_arr, n):
     _check(lib().ddgs_set_views(ctx, views_arr, int(n)), ctx)
+
+
+def ddgs_set_radiosity_override(ctx, ptr):
+    _check(lib().ddgs_set_radiosity_override(ctx, ptr), ctx)
+
+
+def ddgs_set_workspace(ctx, ptr, nbytes):
+    _check(lib().ddgs_set_workspace(ctx, ptr, int(nbytes)), ctx)
+
+
+def ddgs_workspace_size(ctx, capacity=0):
+    n = C.c_size_t()
+    _check(lib().ddgs_workspace_size(ctx, int(capacity), C.byref(n)), ctx)
+    return n.value
 
 
 def ddgs_image_size(ctx):
@@ -340,6 +358,33 @@ class Renderer:
     def set_views(self, views):
         self.views = list(views)
         ddgs_set_views(self.ctx, _views_struct(self.views), len(self.views))
+
+    def set_radiosity_override(self, c):
+        """c: float32 device tensor [n_views][n] used as the radiosity instead of
+        Eq. 3, or None to restore Eq. 3 (the tensor is kept alive here)."""
+        if c is None:
+            self._c_override = None
+            ddgs_set_radiosity_override(self.ctx, None)
+            return
+        if c.dtype != self.torch.float32 or c.device != self.device:
+            raise ValueError(f"override must be a float32 tensor on {self.device}")
+        self._c_override = c.contiguous()
+        ddgs_set_radiosity_override(self.ctx, self._c_override.data_ptr())
+
+    def workspace_size(self, capacity=0):
+        return ddgs_workspace_size(self.ctx, capacity)
+
+    def set_workspace(self, ws):
+        """ws: a uint8 device tensor the library carves its workspace from
+        (kept alive here), or None for library-owned allocation."""
+        if ws is None:
+            self._ws = None
+            ddgs_set_workspace(self.ctx, None, 0)
+            return
+        if ws.dtype != self.torch.uint8 or ws.device != self.device or not ws.is_contiguous():
+            raise ValueError(f"workspace must be a contiguous uint8 tensor on {self.device}")
+        self._ws = ws
+        ddgs_set_workspace(self.ctx, ws.data_ptr(), ws.numel())
 
     def image_size(self):
         return ddgs_image_size(self.ctx)

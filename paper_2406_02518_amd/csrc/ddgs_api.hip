@@ -42,6 +42,7 @@ struct ddgs_ctx {
     ddgs_options opt{};
     bool has_model = false;
     ddgs_model model{};
+    const float *c_override = nullptr;  // test hook: [V][n] radiosity instead of Eq. 3
     std::vector<ddgs_view> views_h;
 
     // derived view table for the current options
@@ -51,8 +52,12 @@ struct ddgs_ctx {
     int64_t total_pix = 0, max_view_pix = 0;
     bool views_dirty = true;
 
-    // workspace
+    // workspace: library-owned buffers, or carved from a caller region
     std::map<std::string, DevBuf> bufs;
+    char *ws_base = nullptr;      // caller workspace (NULL: hipMalloc per buffer)
+    size_t ws_size = 0, ws_used = 0;
+    bool dry_run = false;         // ensure() only adds up sizes (ddgs_workspace_size)
+    size_t dry_total = 0;
 
     // state of the last render
     bool rendered = false;
@@ -106,30 +111,63 @@ ddgs_status fail(ddgs_ctx *c, ddgs_status s, const std::string &msg)
         if (s_ != DDGS_OK) return s_;   \
     } while (0)
 
-// (Re)allocates a workspace buffer of at least `bytes` (contents undefined).
-// Never called while a stream capture is open.
+constexpr size_t kWsAlign = 256;
+size_t ws_round(size_t x) { return (x + kWsAlign - 1) / kWsAlign * kWsAlign; }
+
+// (Re)allocates a workspace buffer of at least `bytes` (contents undefined),
+// with room to grow by a quarter.  With a caller workspace the buffer is
+// carved from it (a grown buffer takes new space; the region is never
+// reused before ddgs_set_workspace is called again).  In a dry run only the
+// sizes of fresh buffers are added up.  Never called while a stream capture
+// is open.
 ddgs_status ensure(ddgs_ctx *c, const char *name, size_t bytes, void **out)
 {
-    DevBuf &b = c->bufs[name];
     if (bytes == 0) bytes = 16;
+    const size_t nb = ws_round(bytes + bytes / 4 + 256);
+    if (c->dry_run) {
+        c->dry_total += nb;
+        *out = nullptr;
+        return DDGS_OK;
+    }
+    DevBuf &b = c->bufs[name];
     if (b.bytes < bytes) {
-        if (b.p) {
-            HIP_TRY(c, hipStreamSynchronize(c->stream));
-            HIP_TRY(c, hipFree(b.p));
-            b.p = nullptr;
-            b.bytes = 0;
-        }
-        const size_t nb = bytes + bytes / 4 + 256;
-        hipError_t e = hipMalloc(&b.p, nb);
-        if (e != hipSuccess) {
-            b.p = nullptr;
-            return fail(c, DDGS_ERR_OOM, std::string("hipMalloc of ") + name + " (" + std::to_string(nb) +
-                                             " bytes) failed: " + hipGetErrorString(e));
+        if (c->ws_base) {
+            if (c->ws_used + nb > c->ws_size)
+                return fail(c, DDGS_ERR_OOM, std::string("workspace too small: ") + name + " needs " +
+                                                 std::to_string(nb) + " more bytes beyond " +
+                                                 std::to_string(c->ws_used) + " of " + std::to_string(c->ws_size) +
+                                                 " (see ddgs_workspace_size)");
+            b.p = c->ws_base + c->ws_used;
+            c->ws_used += nb;
+        } else {
+            if (b.p) {
+                HIP_TRY(c, hipStreamSynchronize(c->stream));
+                HIP_TRY(c, hipFree(b.p));
+                b.p = nullptr;
+                b.bytes = 0;
+            }
+            hipError_t e = hipMalloc(&b.p, nb);
+            if (e != hipSuccess) {
+                b.p = nullptr;
+                return fail(c, DDGS_ERR_OOM, std::string("hipMalloc of ") + name + " (" + std::to_string(nb) +
+                                                 " bytes) failed: " + hipGetErrorString(e));
+            }
         }
         b.bytes = nb;
     }
     *out = b.p;
     return DDGS_OK;
+}
+
+// Releases every workspace buffer (library-owned ones are freed).
+void release_buffers(ddgs_ctx *c)
+{
+    (void)hipStreamSynchronize(c->stream);
+    if (!c->ws_base)
+        for (auto &kv : c->bufs)
+            if (kv.second.p) (void)hipFree(kv.second.p);
+    c->bufs.clear();
+    c->ws_used = 0;
 }
 
 template <typename T>
@@ -164,9 +202,10 @@ RenderOpts render_opts(const ddgs_options &o)
     return r;
 }
 
-ModelDev model_dev(const ddgs_model &m)
+ModelDev model_dev(const ddgs_model &m, const float *c_override)
 {
     ModelDev d;
+    d.c_override = c_override;
     d.n = (int32_t)m.n;
     d.n_iso = (int32_t)m.n_iso;
     d.k = m.k;
@@ -342,7 +381,7 @@ ddgs_status ensure_entries(ddgs_ctx *c, int64_t cap)
     DDGS_TRY(ensure_t(c, "sort_tot", 256, &u));
     uint64_t *bs;
     DDGS_TRY(ensure_t(c, "sort_bsum", sort_blocksum_words(big), &bs));
-    c->entry_cap = std::max(c->entry_cap, cap);
+    if (!c->dry_run) c->entry_cap = std::max(c->entry_cap, cap);
     return DDGS_OK;
 }
 
@@ -406,7 +445,7 @@ void set_items(ddgs_ctx *c, RasterArgs &ra, bool backward)
 ddgs_status enqueue_front(ddgs_ctx *c)
 {
     hipStream_t s = c->stream;
-    const ModelDev m = model_dev(c->model);
+    const ModelDev m = model_dev(c->model, c->c_override);
     const int V = (int)c->views_h.size();
     const int64_t VN = (int64_t)m.n * V;
     GaussCache gc{buf<float>(c, "cov"), buf<float>(c, "alpha"), buf<float>(c, "ciso"), buf<float>(c, "hdir")};
@@ -531,7 +570,7 @@ ddgs_status enqueue_backward(ddgs_ctx *c, const float *dL, const ddgs_grads *g, 
 
     const bool per_g = any_param_grad(g);
     ProjBwdArgs pa{};
-    pa.m = model_dev(c->model);
+    pa.m = model_dev(c->model, c->c_override);
     pa.gc = GaussCache{buf<float>(c, "cov"), buf<float>(c, "alpha"), buf<float>(c, "ciso"), buf<float>(c, "hdir")};
     pa.views = buf<ViewDev>(c, "views");
     pa.V = V;
@@ -684,8 +723,7 @@ void ddgs_destroy(ddgs_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     drop_graph(c);
-    for (auto &kv : c->bufs)
-        if (kv.second.p) (void)hipFree(kv.second.p);
+    release_buffers(c);
     for (int i = 0; i < DDGS_T_COUNT; ++i) {
         if (c->ev_s[i]) (void)hipEventDestroy(c->ev_s[i]);
         if (c->ev_e[i]) (void)hipEventDestroy(c->ev_e[i]);
@@ -742,6 +780,58 @@ ddgs_status ddgs_set_model(ddgs_ctx *c, const ddgs_model *m)
     c->has_model = true;
     ++c->model_gen;
     if (shape_changed || ptr_changed) drop_graph(c);
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_set_workspace(ddgs_ctx *c, void *dev, size_t bytes)
+{
+    if (!c) return DDGS_ERR_INVALID_ARG;
+    if (dev && (((uintptr_t)dev) % kWsAlign != 0 || bytes == 0))
+        return fail(c, DDGS_ERR_INVALID_ARG, "workspace must be non-empty and 256-byte aligned");
+    HIP_TRY(c, hipSetDevice(c->device));
+    drop_graph(c);
+    release_buffers(c);
+    c->ws_base = (char *)dev;
+    c->ws_size = dev ? bytes : 0;
+    c->ws_used = 0;
+    // everything lived in the released buffers
+    c->views_dirty = true;
+    c->entry_cap = 0;
+    c->rendered = false;
+    c->tkey_sorted = c->tval_sorted = nullptr;
+    c->queue = nullptr;
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_workspace_size(ddgs_ctx *c, int64_t capacity, size_t *bytes)
+{
+    if (!c || !bytes) return DDGS_ERR_INVALID_ARG;
+    DDGS_TRY(check_ready(c));
+    int64_t cap = capacity > 0 ? capacity : (c->opt.capacity > 0 ? c->opt.capacity : std::max<int64_t>(c->entry_cap, c->M));
+    if (cap <= 0) return fail(c, DDGS_ERR_STATE, "no entry capacity known: pass one, set options.capacity or render once");
+    c->dry_run = true;
+    c->dry_total = 0;
+    const int V = (int)c->views_h.size();
+    void *p;
+    ddgs_status st = ensure(c, "views", sizeof(ViewDev) * (size_t)std::max(1, V), &p);
+    if (st == DDGS_OK) st = ensure(c, "loss_tile_base", sizeof(int32_t) * (size_t)(V + 1), &p);
+    if (st == DDGS_OK) st = ensure_static(c);
+    if (st == DDGS_OK) st = ensure_entries(c, cap);
+    c->dry_run = false;
+    if (st != DDGS_OK) return st;
+    *bytes = c->dry_total;
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_set_radiosity_override(ddgs_ctx *c, const float *cv)
+{
+    if (!c) return DDGS_ERR_INVALID_ARG;
+    if (((uintptr_t)cv) % 4 != 0) return fail(c, DDGS_ERR_INVALID_ARG, "arrays must be 4-byte aligned");
+    if (cv != c->c_override) {
+        c->c_override = cv;
+        ++c->model_gen;
+        drop_graph(c);
+    }
     return DDGS_OK;
 }
 

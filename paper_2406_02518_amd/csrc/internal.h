@@ -34,6 +34,7 @@ struct RenderOpts {
 struct ModelDev {
     int32_t n, n_iso, k, L;
     const float *mean, *quat, *log_scale, *opacity_logit, *feat, *b_iso, *B_dir;
+    const float *c_override;  // [V][n] radiosity used instead of Eq. 3 (NULL: Eq. 3)
 };
 
 // View-independent per-Gaussian values, computed once per step.

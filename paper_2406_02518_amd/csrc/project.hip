@@ -241,7 +241,9 @@ __global__ __launch_bounds__(kBlock) void project_kernel(ModelDev m, GaussCache 
         return;
     }
     float c;
-    if (i < m.n_iso) {
+    if (m.c_override) {
+        c = m.c_override[vi];
+    } else if (i < m.n_iso) {
         c = gc.ciso[i];
     } else {
         const int nd = n - m.n_iso, id = i - m.n_iso;
@@ -428,8 +430,9 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
             GSw[4] += R[1] * U[2] + R[4] * U[5] + R[7] * U[8];
             GSw[5] += R[2] * U[2] + R[5] * U[5] + R[8] * U[8];
             galpha += g7[5];
-            // radiosity
-            if (!is_dir) {
+            // radiosity (none when it is overridden)
+            if (a.m.c_override) {
+            } else if (!is_dir) {
                 zsum += g7[6] * ciso * (1.0f - ciso);
             } else {
                 const float rx = mx - V.so[0], ry = my - V.so[1], rz = mz - V.so[2];

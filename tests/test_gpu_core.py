@@ -150,6 +150,46 @@ def test_tile_lists_bit_exact(R):
         np.testing.assert_array_equal(zk[v][P[:, 0] > 0], P[P[:, 0] > 0, 8].astype(np.float32).view(np.uint32))
 
 
+# ---------------------------------------------------- radiosity override
+
+def test_radiosity_override_is_linear_and_matches_oracle(R):
+    # the test hook replaces Eq. 3: the image is linear in c (Eq. 1), equals the
+    # oracle's own override path, and the backward leaves features and bases out
+    c = synth.config("C1")
+    views = c.views
+    R.set_scene(c.scene)
+    R.set_views(views)
+    rng = np.random.default_rng(9)
+    n, V = c.scene.n, len(views)
+    c1 = rng.uniform(0.0, 1.0, size=(V, n)).astype(np.float32)
+    c2 = rng.uniform(0.0, 1.0, size=(V, n)).astype(np.float32)
+    try:
+        imgs = []
+        for cv in (c1, c2, c1 + c2):
+            R.set_radiosity_override(torch.from_numpy(cv).cuda())
+            imgs.append(R.render().cpu().numpy().astype(np.float64))
+        assert rel_l2(imgs[2], imgs[0] + imgs[1]) < 1e-6
+        R.set_radiosity_override(torch.from_numpy(c1).cuda())
+        img = R.render()
+        exp = np.concatenate([x.ravel() for x in ref.render(c.scene, views, c_override=c1.astype(np.float64))])
+        assert rel_l2(img.cpu().numpy(), exp) < 1e-4
+        w = rng.normal(size=img.numel())
+        g = R.backward(torch.from_numpy(w.astype(np.float32)).cuda())
+        torch.cuda.synchronize()
+        o = ref.backward(c.scene, views, ref.all_pixels(views), w, c_override=c1.astype(np.float64))
+        for k in ("dmean", "dquat", "dlog_scale", "dopacity_logit"):
+            assert rel_l2(g[k].cpu().numpy(), o[k]) < 1e-4, k
+        assert rel_l2(g["dpose"].cpu().numpy(), o["dpose"]) < 1e-4
+        for k in ("dfeat", "db_iso", "dB_dir"):
+            assert not g[k].cpu().numpy().any(), k
+    finally:
+        R.set_radiosity_override(None)
+    # Eq. 3 is back
+    img = R.render().cpu().numpy()
+    exp = np.concatenate([x.ravel() for x in ref.render(c.scene, views)])
+    assert rel_l2(img, exp) < 1e-4
+
+
 # ---------------------------------------------------------------- forward
 
 @pytest.mark.parametrize("cfg,scale", [("C1", 1.0), ("C2", 1.0), ("C3", 0.03), ("C4", 0.03), ("C5", 0.02)])

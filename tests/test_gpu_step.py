@@ -203,3 +203,39 @@ def test_pair_counts_are_consistent_with_oracle(R):
     _, _, n_contrib = ref.render(c.scene, c.views, stats=True)
     assert abs(co - int(n_contrib[0])) <= max(2, 1e-4 * co)
     assert ev >= co > 0
+
+
+def test_caller_workspace_matches_library_allocation(R):
+    c = synth.config("C2", scale=0.1)
+    views = c.views[:1] + [synth.view(96, 80, 1.2, 1000.0, 600.0, 75.0)]
+    R.set_scene(c.scene)
+    R.set_views(views)
+    img_ref = R.render().clone()
+    M = R.num_rendered()
+    dl = torch.from_numpy(np.random.default_rng(2).normal(size=img_ref.numel()).astype(np.float32)).cuda()
+    g_ref = {k: v.clone() for k, v in R.backward(dl).items()}
+    torch.cuda.synchronize()
+
+    W = make_renderer()
+    try:
+        W.set_scene(c.scene)
+        W.set_views(views)
+        nbytes = W.workspace_size(2 * M)
+        assert nbytes > 0
+        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        W.set_workspace(ws)
+        for _ in range(2):
+            img = W.render()
+            g = W.backward(dl)
+            torch.cuda.synchronize()
+            assert torch.equal(img, img_ref)
+            for k in g_ref:
+                assert torch.equal(g[k], g_ref[k]), k
+        # a workspace that is too small fails cleanly, and can be replaced
+        W.set_workspace(torch.empty(nbytes // 8 // 256 * 256, dtype=torch.uint8, device="cuda"))
+        with pytest.raises(binding.DDGSError):
+            W.render()
+        W.set_workspace(None)
+        assert torch.equal(W.render(), img_ref)
+    finally:
+        W.close()
