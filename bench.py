@@ -90,6 +90,25 @@ def traffic_from_profiles(kernel, workload):
         return None
 
 
+def valu_from_profiles(kernel, workload):
+    """VALU instructions per launch and the issue fraction from the committed
+    SQ counter summary, valid only while the kernel sources are unchanged."""
+    path = os.path.join(ROOT, "profiles", f"valu_raster_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        src = hashlib.sha256()
+        for f in d["sources"]:
+            src.update(open(os.path.join(ROOT, f), "rb").read())
+        if src.hexdigest() != d["sources_sha256"]:
+            return None
+        k = d["kernels"][kernel]
+        return {"valu_insts_per_launch": int(k["valu_insts"]), "issue_frac": round(k["valu_issue_frac"], 3)}
+    except Exception:  # noqa: BLE001 - a stale or unreadable summary means "not measured"
+        return None
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -169,11 +188,33 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / max(1, args.steps)
     log(f"captured fitting step: {ms_per_step:.3f} ms")
 
+    # per-step distribution: event-timed replays, `reps` per pose
+    reps = 20
+    marks = []
+    with torch.cuda.stream(stream):
+        for j in range(len(views)):
+            for _ in range(reps):
+                tgt.copy_(targets[j], non_blocking=True)
+                R.set_views([views[j]])
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                binding.ddgs_step_launch(R.ctx)
+                e1.record(stream)
+                marks.append((j, e0, e1))
+    stream.synchronize()
+    binding.ddgs_check(R.ctx)
+    per = np.array([a.elapsed_time(b) for _, a, b in marks])
+    pose_med = [float(np.median(per[[i for i, (j, _, _) in enumerate(marks) if j == p]])) for p in range(len(views))]
+    step_dist = {"repeats_per_pose": reps, "poses": len(views), "median_ms": round(float(np.median(per)), 4),
+                 "p10_ms": round(float(np.percentile(per, 10)), 4), "p90_ms": round(float(np.percentile(per, 90)), 4),
+                 "pose_median_min_ms": round(min(pose_med), 4), "pose_median_max_ms": round(max(pose_med), 4)}
+    log("step distribution:", json.dumps(step_dist))
+
     # ------------------------------ per-stage HIP-event timing + pair counts
     binding.ddgs_enable_timing(R.ctx, 1)
     R.set_options(capacity=0)
     stages = {k: 0.0 for k in binding.STAGES}
-    ev_pairs = co_pairs = 0
+    ev_pairs = co_pairs = entries = 0
     plain_ms = []
     nst = min(len(views), max(1, args.steps))
     with torch.cuda.stream(stream):
@@ -199,6 +240,7 @@ def main():
             e, c = binding.ddgs_debug_pair_counts(R.ctx)
             ev_pairs += e / nst
             co_pairs += c / nst
+            entries += R.num_rendered() / nst
         binding.ddgs_debug_count_pairs(R.ctx, 0)
     dominant = max(("raster_fwd", "raster_bwd"), key=lambda k: stages[k])
     flops = co_pairs * (FLOPS_BWD if dominant == "raster_bwd" else FLOPS_FWD)
@@ -208,7 +250,27 @@ def main():
                 "traffic": traffic_from_profiles(dominant, "C3"),
                 "kernel_ms": round(stages[dominant], 4),
                 "contributing_pairs_per_launch": int(co_pairs), "evaluated_pairs_per_launch": int(ev_pairs),
-                "flops_per_contributing_pair": FLOPS_BWD if dominant == "raster_bwd" else FLOPS_FWD}
+                "flops_per_contributing_pair": FLOPS_BWD if dominant == "raster_bwd" else FLOPS_FWD,
+                "valu_issue": valu_from_profiles(dominant, "C3")}
+    # every stage against its own bound, from algorithmic work per launch:
+    # parameters 4 (11 + k) B per Gaussian, a 28 B record or gradient slot per
+    # (view, Gaussian) / tile entry, 8 B keys + values, 12 B per pixel
+    n3, k3, P3 = cfg.scene.n, cfg.scene.k, int(views[0].W) * int(views[0].H)
+    pbytes = 4 * (11 + k3)
+    algo = {"project": ("hbm", (pbytes + 28) * n3), "sort": ("hbm", 16 * n3 + 16 * entries),
+            "raster_fwd": ("alu", FLOPS_FWD * co_pairs), "loss": ("hbm", 12 * P3),
+            "raster_bwd": ("alu", FLOPS_BWD * co_pairs), "project_bwd": ("hbm", 2 * pbytes * n3 + 28 * entries)}
+    stage_roofline = []
+    for k, (bound, work) in algo.items():
+        t = stages[k] * 1e-3
+        if bound == "alu":
+            a = work / t / 1e12
+            stage_roofline.append({"stage": k, "bound": "alu", "achieved": round(a, 3), "peak": PEAK_ALU_TFLOPS,
+                                   "unit": "TFLOP/s", "frac": round(a / PEAK_ALU_TFLOPS, 4), "ms": round(stages[k], 4)})
+        else:
+            a = work / t / 1e9
+            stage_roofline.append({"stage": k, "bound": "hbm", "achieved": round(a, 1), "peak": PEAK_HBM_GBS,
+                                   "unit": "GB/s", "frac": round(a / PEAK_HBM_GBS, 4), "ms": round(stages[k], 4)})
     log("stages (ms):", json.dumps({k: round(v, 4) for k, v in stages.items()}))
     R.close()
 
@@ -361,6 +423,8 @@ def main():
                    "plain_path_ms_per_step": round(float(np.median(plain_ms)), 4)},
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "roofline": roofline,
+        "stage_roofline": stage_roofline,
+        "step_distribution": step_dist,
         "batched": batched,
         "uneven_batch": uneven,
         "cpu_baseline": cpu,
