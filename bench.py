@@ -408,6 +408,30 @@ def main():
                          f"({len(rows)} of {v.H} rows = {len(pix)} pixels x 500k Gaussians), forward at those "
                          f"pixels + analytic FP64 backward of a linear loss on them; {dt:.1f} s measured, "
                          f"scaled by {scale:g} to one full 512x512 fwd+bwd"}
+        # more oracle timings: pair tests per second (every pixel is tested
+        # against every valid Gaussian), one thread on a smaller sample, and
+        # the two small workloads in full
+        pair_tests = len(pix) * cfg.scene.n
+        cpu["pair_tests_per_s"] = round(pair_tests / dt, 1)
+        rows1 = np.arange(0, v.H, 64)
+        u1, v1 = np.meshgrid(np.arange(v.W), rows1)
+        pix1 = np.stack([np.zeros(u1.size, int), u1.ravel(), v1.ravel()], 1).astype(np.int32)
+        a = time.perf_counter()
+        ref.render_pixels(cfg.scene, [v], pix1, threads=1)
+        ref.backward(cfg.scene, [v], pix1, np.ones(len(pix1)), threads=1)
+        dt1 = time.perf_counter() - a
+        cpu["single_thread_pair_tests_per_s"] = round(len(pix1) * cfg.scene.n / dt1, 1)
+        for name in ("C1", "C2"):
+            cs = synth.config(name)
+            a = time.perf_counter()
+            ref.render(cs.scene, cs.views, threads=threads)
+            t_f = time.perf_counter() - a
+            allp = ref.all_pixels(cs.views)
+            a = time.perf_counter()
+            ref.backward(cs.scene, cs.views, allp, np.ones(len(allp)), threads=threads)
+            t_b = time.perf_counter() - a
+            cpu[f"{name}_full_fwd_ms"] = round(t_f * 1e3, 1)
+            cpu[f"{name}_full_fwd_bwd_ms"] = round((t_f + t_b) * 1e3, 1)
         log("cpu:", json.dumps(cpu))
 
     out = {
