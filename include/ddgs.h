@@ -148,6 +148,23 @@ ddgs_status ddgs_get_options(const ddgs_ctx *ctx, ddgs_options *opt);
 /* Eq. 1/3 inputs. */
 ddgs_status ddgs_set_model(ddgs_ctx *ctx, const ddgs_model *model);
 ddgs_status ddgs_set_views(ddgs_ctx *ctx, const ddgs_view *views, int n_views);
+/* Pose registration (Sec. 4.4).  With an optimiser set, ddgs_step_capture
+ * appends one Adam step per view on the pose-tangent gradient the step just
+ * computed (grads->dpose must be non-NULL; up to 256 views) and re-bases the
+ * device view table with it: (rho, omega) = -lr * mhat / (sqrt(vhat) + eps)
+ * per component (lr_trans for rho in mm, lr_rot for omega in rad), then
+ * R <- Exp(omega) R, t <- Exp(omega) t + rho, so every replay is one
+ * registration iteration.  The moments restart from zero at the first
+ * replay after ddgs_set_pose_optimizer or ddgs_set_views.  NULL turns the
+ * optimiser off.  Either call drops a captured step.  ddgs_get_views
+ * synchronises and returns the current views, with the poses the optimiser
+ * has reached (they also replace the host copy the library keeps). */
+typedef struct ddgs_adam {
+    float lr_trans, lr_rot, beta1, beta2, eps;
+} ddgs_adam;
+ddgs_status ddgs_set_pose_optimizer(ddgs_ctx *ctx, const ddgs_adam *adam);
+ddgs_status ddgs_get_views(ddgs_ctx *ctx, ddgs_view *views, int n_views);
+
 /* Test hook: radiosity c per (view, Gaussian), device [n_views][n] floats,
  * used instead of Eq. 3 (NULL restores Eq. 3).  With it the image is linear
  * in c (Eq. 1), and the backward leaves the features and bases out of the

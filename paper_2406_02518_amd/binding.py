@@ -25,7 +25,8 @@ STAGES = ("project", "sort", "raster_fwd", "loss", "raster_bwd", "project_bwd")
 EXPORTED = (
     "ddgs_create", "ddgs_destroy", "ddgs_set_stream", "ddgs_status_str", "ddgs_last_error",
     "ddgs_default_options", "ddgs_set_options", "ddgs_get_options", "ddgs_set_model", "ddgs_set_views",
-    "ddgs_set_radiosity_override", "ddgs_set_workspace", "ddgs_workspace_size",
+    "ddgs_set_radiosity_override", "ddgs_set_workspace", "ddgs_workspace_size", "ddgs_set_pose_optimizer",
+    "ddgs_get_views",
     "ddgs_image_size", "ddgs_render", "ddgs_backward", "ddgs_loss", "ddgs_step_capture", "ddgs_step_launch",
     "ddgs_check", "ddgs_autotune", "ddgs_param_count", "ddgs_num_rendered", "ddgs_debug_copy",
     "ddgs_debug_keep_unsorted", "ddgs_debug_sort_pairs", "ddgs_debug_exclusive_scan", "ddgs_debug_count_pairs",
@@ -42,6 +43,11 @@ class ddgs_model(C.Structure):
 class ddgs_view(C.Structure):
     _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("pitch_mm", C.c_float), ("sdd_mm", C.c_float),
                 ("pose", C.c_float * 12)]
+
+
+class ddgs_adam(C.Structure):
+    _fields_ = [("lr_trans", C.c_float), ("lr_rot", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float)]
 
 
 class ddgs_options(C.Structure):
@@ -85,6 +91,8 @@ def lib():
             "ddgs_set_model": ([vp, C.POINTER(ddgs_model)], st),
             "ddgs_set_views": ([vp, C.POINTER(ddgs_view), C.c_int], st),
             "ddgs_set_radiosity_override": ([vp, vp], st),
+            "ddgs_set_pose_optimizer": ([vp, C.POINTER(ddgs_adam)], st),
+            "ddgs_get_views": ([vp, C.POINTER(ddgs_view), C.c_int], st),
             "ddgs_set_workspace": ([vp, vp, C.c_size_t], st),
             "ddgs_workspace_size": ([vp, i64, C.POINTER(C.c_size_t)], st),
             "ddgs_image_size": ([vp, C.POINTER(i64)], st),
@@ -169,6 +177,16 @@ def ddgs_set_views(ctx, views_arr, n):
 
 def ddgs_set_radiosity_override(ctx, ptr):
     _check(lib().ddgs_set_radiosity_override(ctx, ptr), ctx)
+
+
+def ddgs_set_pose_optimizer(ctx, adam):
+    _check(lib().ddgs_set_pose_optimizer(ctx, None if adam is None else C.byref(adam)), ctx)
+
+
+def ddgs_get_views(ctx, n):
+    arr = (ddgs_view * max(1, n))()
+    _check(lib().ddgs_get_views(ctx, arr, int(n)), ctx)
+    return arr
 
 
 def ddgs_set_workspace(ctx, ptr, nbytes):
@@ -370,6 +388,21 @@ class Renderer:
             raise ValueError(f"override must be a float32 tensor on {self.device}")
         self._c_override = c.contiguous()
         ddgs_set_radiosity_override(self.ctx, self._c_override.data_ptr())
+
+    def set_pose_optimizer(self, lr_trans=None, lr_rot=None, beta1=0.9, beta2=0.999, eps=1e-8):
+        """Adam on every view's pose tangent inside captured steps (None: off)."""
+        if lr_trans is None and lr_rot is None:
+            ddgs_set_pose_optimizer(self.ctx, None)
+            return
+        a = ddgs_adam()
+        a.lr_trans, a.lr_rot = float(lr_trans or 0.0), float(lr_rot or 0.0)
+        a.beta1, a.beta2, a.eps = float(beta1), float(beta2), float(eps)
+        ddgs_set_pose_optimizer(self.ctx, a)
+
+    def get_poses(self):
+        """Current (3, 4) float32 world -> source poses of the views."""
+        arr = ddgs_get_views(self.ctx, len(self.views))
+        return [np.array(arr[i].pose[:], dtype=np.float32).reshape(3, 4) for i in range(len(self.views))]
 
     def workspace_size(self, capacity=0):
         return ddgs_workspace_size(self.ctx, capacity)

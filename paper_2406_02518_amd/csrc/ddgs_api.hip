@@ -43,6 +43,11 @@ struct ddgs_ctx {
     bool has_model = false;
     ddgs_model model{};
     const float *c_override = nullptr;  // test hook: [V][n] radiosity instead of Eq. 3
+
+    // pose optimiser appended to captured steps (registration)
+    bool adam_on = false;
+    AdamCfg adam{};
+    bool adam_reset = true;   // zero the moments before the next replay
     std::vector<ddgs_view> views_h;
 
     // derived view table for the current options
@@ -823,6 +828,45 @@ ddgs_status ddgs_workspace_size(ddgs_ctx *c, int64_t capacity, size_t *bytes)
     return DDGS_OK;
 }
 
+ddgs_status ddgs_set_pose_optimizer(ddgs_ctx *c, const ddgs_adam *a)
+{
+    if (!c) return DDGS_ERR_INVALID_ARG;
+    if (a) {
+        const bool ok = a->lr_trans >= 0.0f && a->lr_rot >= 0.0f && a->beta1 >= 0.0f && a->beta1 < 1.0f &&
+                        a->beta2 >= 0.0f && a->beta2 < 1.0f && a->eps > 0.0f && std::isfinite(a->lr_trans) &&
+                        std::isfinite(a->lr_rot) && std::isfinite(a->eps);
+        if (!ok) return fail(c, DDGS_ERR_INVALID_ARG, "need lr >= 0, 0 <= beta < 1, eps > 0");
+        c->adam = AdamCfg{a->lr_trans, a->lr_rot, a->beta1, a->beta2, a->eps};
+    }
+    c->adam_on = a != nullptr;
+    c->adam_reset = true;
+    drop_graph(c);
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_get_views(ddgs_ctx *c, ddgs_view *out, int nv)
+{
+    if (!c || (nv > 0 && !out)) return DDGS_ERR_INVALID_ARG;
+    if (nv != (int)c->views_h.size()) return fail(c, DDGS_ERR_INVALID_ARG, "n_views differs from the views set");
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (nv == 0) return DDGS_OK;
+    if (!c->views_dirty && buf<ViewDev>(c, "views")) {
+        std::vector<ViewDev> d(nv);
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        HIP_TRY(c, hipMemcpy(d.data(), buf<ViewDev>(c, "views"), sizeof(ViewDev) * nv, hipMemcpyDeviceToHost));
+        for (int v = 0; v < nv; ++v) {
+            ddgs_view &h = c->views_h[v];
+            for (int r = 0; r < 3; ++r) {
+                for (int q = 0; q < 3; ++q) h.pose[4 * r + q] = d[v].R[3 * r + q];
+                h.pose[4 * r + 3] = d[v].t[r];
+            }
+            c->vdev_h[v] = d[v];
+        }
+    }
+    std::copy(c->views_h.begin(), c->views_h.end(), out);
+    return DDGS_OK;
+}
+
 ddgs_status ddgs_set_radiosity_override(ddgs_ctx *c, const float *cv)
 {
     if (!c) return DDGS_ERR_INVALID_ARG;
@@ -853,6 +897,7 @@ ddgs_status ddgs_set_views(ddgs_ctx *c, const ddgs_view *v, int nv)
         same_shape = c->views_h[i].W == v[i].W && c->views_h[i].H == v[i].H;
     c->views_h.assign(v, v + nv);
     c->views_dirty = true;
+    c->adam_reset = true;
     ++c->views_gen;
     if (!same_shape) drop_graph(c);
     if (c->exec) {
@@ -966,8 +1011,17 @@ ddgs_status ddgs_step_capture(ddgs_ctx *c, int kind, const float *target, float 
     DDGS_TRY(check_ready(c));
     if (c->model.n == 0) return fail(c, DDGS_ERR_UNSUPPORTED, "a captured step needs n > 0");
     if (!c->stream) return fail(c, DDGS_ERR_INVALID_ARG, "capture needs a non-default stream");
+    if (c->adam_on && !g->dpose) return fail(c, DDGS_ERR_INVALID_ARG, "the pose optimiser needs grads->dpose");
+    if (c->adam_on && c->views_h.size() > 256) return fail(c, DDGS_ERR_UNSUPPORTED, "the pose optimiser takes up to 256 views");
     drop_graph(c);
     DDGS_TRY(ensure_static(c));
+    if (c->adam_on) {
+        float *st_;
+        uint32_t *sp_;
+        DDGS_TRY(ensure_t(c, "adam_state", (size_t)12 * c->views_h.size(), &st_));
+        DDGS_TRY(ensure_t(c, "adam_step", 1, &sp_));
+        c->adam_reset = true;
+    }
     int64_t cap = c->opt.capacity;
     if (cap <= 0) {
         // one plain render sizes the capacity: twice the current need
@@ -986,6 +1040,11 @@ ddgs_status ddgs_step_capture(ddgs_ctx *c, int kind, const float *target, float 
     if (st == DDGS_OK) st = enqueue_back(c, c->step_cap, c->step_cap, images);
     if (st == DDGS_OK) st = enqueue_loss(c, kind, images, target, lambda, loss_out, dL);
     if (st == DDGS_OK) st = enqueue_backward(c, dL, g, c->step_cap);
+    if (st == DDGS_OK && c->adam_on) {
+        hipError_t ea = launch_pose_adam(buf<ViewDev>(c, "views"), (int)c->views_h.size(), g->dpose,
+                                         buf<float>(c, "adam_state"), buf<uint32_t>(c, "adam_step"), c->adam, c->stream);
+        if (ea != hipSuccess) st = fail(c, DDGS_ERR_HIP, std::string("pose optimiser: ") + hipGetErrorString(ea));
+    }
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(c->stream, &graph);
     c->timing = saved_timing;
@@ -1009,6 +1068,12 @@ ddgs_status ddgs_step_launch(ddgs_ctx *c)
     if (!c) return DDGS_ERR_INVALID_ARG;
     if (!c->exec) return fail(c, DDGS_ERR_STATE, "no captured step");
     HIP_TRY(c, hipSetDevice(c->device));
+    if (c->adam_on && c->adam_reset) {
+        // fresh moments (outside the graph: no memset nodes are captured)
+        HIP_TRY(c, hipMemsetAsync(buf<float>(c, "adam_state"), 0, sizeof(float) * 12 * c->views_h.size(), c->stream));
+        HIP_TRY(c, hipMemsetAsync(buf<uint32_t>(c, "adam_step"), 0, sizeof(uint32_t), c->stream));
+        c->adam_reset = false;
+    }
     HIP_TRY(c, hipGraphLaunch(c->exec, c->stream));
     c->M = -1;  // unknown until ddgs_check
     c->rendered = true;

@@ -268,6 +268,14 @@ hipError_t launch_items(const uint2 *ranges, int n_tiles, int split, uint32_t *c
                         uint32_t *counter, hipStream_t s);
 bool raster_tile_supported(int tw, int th);
 
+// pose.hip: one Adam step per view on its pose tangent gradient, then the
+// device view table is re-based (R <- Exp(w) R, t <- Exp(w) t + rho).
+struct AdamCfg {
+    float lr_trans, lr_rot, beta1, beta2, eps;
+};
+hipError_t launch_pose_adam(ViewDev *views, int V, const float *dpose, float *state, uint32_t *step,
+                            const AdamCfg &cfg, hipStream_t s);
+
 // loss.hip
 struct LossArgs {
     const ViewDev *views;

@@ -493,3 +493,48 @@ def test_ncc_matches_corrcoef_and_affine_invariance():
     loss2, g2 = ref.loss_ncc(2.5 * y + 0.3, y, eps=0.0)
     assert loss2 == pytest.approx(0.0, abs=1e-14)
     assert np.abs(g2).max() < 1e-14
+
+
+# ------------------------------------------------------ pose optimiser step
+
+def test_pose_step_reference_pins():
+    from oracle import pose_opt
+    rng = np.random.default_rng(4)
+    # Exp equals scipy's rotation of the same rotation vector, small and large
+    for w in (rng.normal(size=3) * 1e-7, rng.normal(size=3) * 0.3, np.array([0.0, 2.5, -1.0])):
+        np.testing.assert_allclose(pose_opt.exp_so3(w), Rotation.from_rotvec(w).as_matrix(), atol=1e-12)
+    # Adam's first bias-corrected step moves every component by lr against the
+    # gradient's sign (|mhat| / sqrt(vhat) = 1 at t = 1 up to eps)
+    g = rng.normal(size=6)
+    lr = np.array([1.0, 1.0, 1.0, 0.01, 0.01, 0.01])
+    d, m, s = pose_opt.adam_step(g, np.zeros(6), np.zeros(6), 1, lr, 0.9, 0.999, 1e-12)
+    np.testing.assert_allclose(d, -lr * np.sign(g), rtol=1e-9)
+    # a constant gradient keeps the step at lr (bias correction exact)
+    for t in range(2, 6):
+        d, m, s = pose_opt.adam_step(g, m, s, t, lr, 0.9, 0.999, 1e-12)
+        np.testing.assert_allclose(d, -lr * np.sign(g), rtol=1e-9)
+    # re-basing is the left action: source position moves by -R'^T rho rotated, and
+    # a pure translation tangent shifts t only
+    P = synth.azimuth_pose(30.0, 600.0)
+    Q = pose_opt.rebase(P, np.array([1.0, -2.0, 3.0, 0.0, 0.0, 0.0]))
+    np.testing.assert_allclose(Q[:, :3], P[:, :3], atol=1e-15)
+    np.testing.assert_allclose(Q[:, 3], P[:, 3] + [1.0, -2.0, 3.0], atol=1e-12)
+    # errors: a rotation by 5 degrees about the isocentre gives 5 degrees and a
+    # source displacement of 2 SID sin(2.5 deg)
+    w = np.array([0.0, 0.0, np.radians(5.0)])
+    P2 = synth.perturbed_pose(P, w, np.zeros(3))
+    ang, dso = pose_opt.pose_errors(P2, P)
+    assert ang == pytest.approx(5.0, abs=1e-9)
+    assert dso == pytest.approx(2 * 600.0 * np.sin(np.radians(2.5)), rel=1e-9)
+    # projection distance: points at one camera depth z shifted sideways by d
+    # move by f d / z pixels; a rotation about the optical axis by a moves a
+    # point at image radius r by 2 r sin(a / 2)
+    I = np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1)
+    pts = np.concatenate([rng.uniform(-50, 50, size=(20, 2)), np.full((20, 1), 700.0)], axis=1)
+    T = I.copy()
+    T[:, 3] = [3.0, -4.0, 0.0]
+    assert pose_opt.projection_distance(T, I, 2000.0, pts) == pytest.approx(2000.0 * 5.0 / 700.0, rel=1e-12)
+    assert pose_opt.projection_distance(I, I, 2000.0, pts) == 0.0
+    Rz = np.concatenate([Rotation.from_rotvec([0, 0, 0.1]).as_matrix(), np.zeros((3, 1))], axis=1)
+    r = 2000.0 * np.linalg.norm(pts[:, :2], axis=1) / 700.0
+    assert pose_opt.projection_distance(Rz, I, 2000.0, pts) == pytest.approx(np.mean(2 * r * np.sin(0.05)), rel=1e-12)
