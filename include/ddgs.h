@@ -152,15 +152,29 @@ ddgs_status ddgs_set_views(ddgs_ctx *ctx, const ddgs_view *views, int n_views);
  * appends one Adam step per view on the pose-tangent gradient the step just
  * computed (grads->dpose must be non-NULL; up to 256 views) and re-bases the
  * device view table with it: (rho, omega) = -lr * mhat / (sqrt(vhat) + eps)
- * per component (lr_trans for rho in mm, lr_rot for omega in rad), then
- * R <- Exp(omega) R, t <- Exp(omega) t + rho, so every replay is one
- * registration iteration.  The moments restart from zero at the first
- * replay after ddgs_set_pose_optimizer or ddgs_set_views.  NULL turns the
- * optimiser off.  Either call drops a captured step.  ddgs_get_views
- * synchronises and returns the current views, with the poses the optimiser
- * has reached (they also replace the host copy the library keeps). */
+ * per component (lr_trans for rho in mm, lr_rot for omega in rad), then the
+ * view is re-based, so every replay is one registration iteration.
+ *   pivot_mode DDGS_PIVOT_SOURCE: the left tangent the backward
+ *     differentiates, R <- Exp(omega) R, t <- Exp(omega) t + rho (rotation
+ *     about the source point).
+ *   pivot_mode DDGS_PIVOT_POINT: rotation about the world point pivot[3]
+ *     (mm; the isocentre is the world origin), with p = R pivot + t its
+ *     source-frame position: R <- Exp(omega) R, t <- Exp(omega)(t - p) + p
+ *     + rho.  The tangent gradient is mapped first, g_omega += g_rho x p,
+ *     and Adam runs on the mapped gradient.  Rotating about the source moves
+ *     the image almost as a sideways shift does, which makes the two nearly
+ *     interchangeable for the optimiser; a pivot inside the object avoids it.
+ * The moments restart from zero at the first replay after
+ * ddgs_set_pose_optimizer or ddgs_set_views.  NULL turns the optimiser off.
+ * Either call drops a captured step.  ddgs_get_views synchronises and
+ * returns the current views, with the poses the optimiser has reached (they
+ * also replace the host copy the library keeps).  The dpose output keeps the
+ * left-tangent gradient in both modes. */
+enum { DDGS_PIVOT_SOURCE = 0, DDGS_PIVOT_POINT = 1 };
 typedef struct ddgs_adam {
     float lr_trans, lr_rot, beta1, beta2, eps;
+    int32_t pivot_mode;
+    float pivot[3];
 } ddgs_adam;
 ddgs_status ddgs_set_pose_optimizer(ddgs_ctx *ctx, const ddgs_adam *adam);
 ddgs_status ddgs_get_views(ddgs_ctx *ctx, ddgs_view *views, int n_views);

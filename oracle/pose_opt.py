@@ -34,6 +34,26 @@ def rebase(pose, delta):
     return np.concatenate([E @ P[:, :3], (E @ P[:, 3] + np.asarray(delta[:3]))[:, None]], axis=1)
 
 
+def rebase_about(pose, delta, pivot):
+    """Rotation by Exp(w) about the world point ``pivot`` and a shift rho in
+    the source frame: with p = R pivot + t, [Exp(w) R | Exp(w)(t - p) + p + rho]."""
+    P = np.asarray(pose, dtype=np.float64)
+    E = exp_so3(delta[3:])
+    p = P[:, :3] @ np.asarray(pivot, np.float64) + P[:, 3]
+    return np.concatenate([E @ P[:, :3], (E @ (P[:, 3] - p) + p + np.asarray(delta[:3]))[:, None]], axis=1)
+
+
+def pivot_gradient(g, pose, pivot):
+    """Gradient for the tangent of ``rebase_about`` from the left-tangent
+    gradient g = (g_rho, g_omega): a camera point x moves by
+    omega x (x - p) + rho, the left tangent (rho - omega x p, omega), so the
+    chain rule gives (g_rho, g_omega + g_rho x p)."""
+    g = np.asarray(g, np.float64)
+    P = np.asarray(pose, np.float64)
+    p = P[:, :3] @ np.asarray(pivot, np.float64) + P[:, 3]
+    return np.concatenate([g[:3], g[3:] + np.cross(g[:3], p)])
+
+
 def pose_errors(pose, pose_gt):
     """Rotation error (degrees, angle of R R_gt^T) and source-position error (mm)."""
     P, G = np.asarray(pose, np.float64), np.asarray(pose_gt, np.float64)

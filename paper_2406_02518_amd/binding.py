@@ -47,7 +47,10 @@ class ddgs_view(C.Structure):
 
 class ddgs_adam(C.Structure):
     _fields_ = [("lr_trans", C.c_float), ("lr_rot", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
-                ("eps", C.c_float)]
+                ("eps", C.c_float), ("pivot_mode", C.c_int32), ("pivot", C.c_float * 3)]
+
+
+PIVOT_SOURCE, PIVOT_POINT = 0, 1
 
 
 class ddgs_options(C.Structure):
@@ -389,14 +392,21 @@ class Renderer:
         self._c_override = c.contiguous()
         ddgs_set_radiosity_override(self.ctx, self._c_override.data_ptr())
 
-    def set_pose_optimizer(self, lr_trans=None, lr_rot=None, beta1=0.9, beta2=0.999, eps=1e-8):
-        """Adam on every view's pose tangent inside captured steps (None: off)."""
+    def set_pose_optimizer(self, lr_trans=None, lr_rot=None, beta1=0.9, beta2=0.999, eps=1e-8, pivot=None):
+        """Adam on every view's pose tangent inside captured steps (None: off).
+        ``pivot``: world point (mm) the rotation turns about; None turns it
+        about the source (the left tangent)."""
         if lr_trans is None and lr_rot is None:
             ddgs_set_pose_optimizer(self.ctx, None)
             return
         a = ddgs_adam()
         a.lr_trans, a.lr_rot = float(lr_trans or 0.0), float(lr_rot or 0.0)
         a.beta1, a.beta2, a.eps = float(beta1), float(beta2), float(eps)
+        if pivot is None:
+            a.pivot_mode = PIVOT_SOURCE
+        else:
+            a.pivot_mode = PIVOT_POINT
+            a.pivot[:] = [float(x) for x in pivot]
         ddgs_set_pose_optimizer(self.ctx, a)
 
     def get_poses(self):

@@ -834,9 +834,14 @@ ddgs_status ddgs_set_pose_optimizer(ddgs_ctx *c, const ddgs_adam *a)
     if (a) {
         const bool ok = a->lr_trans >= 0.0f && a->lr_rot >= 0.0f && a->beta1 >= 0.0f && a->beta1 < 1.0f &&
                         a->beta2 >= 0.0f && a->beta2 < 1.0f && a->eps > 0.0f && std::isfinite(a->lr_trans) &&
-                        std::isfinite(a->lr_rot) && std::isfinite(a->eps);
-        if (!ok) return fail(c, DDGS_ERR_INVALID_ARG, "need lr >= 0, 0 <= beta < 1, eps > 0");
-        c->adam = AdamCfg{a->lr_trans, a->lr_rot, a->beta1, a->beta2, a->eps};
+                        std::isfinite(a->lr_rot) && std::isfinite(a->eps) &&
+                        (a->pivot_mode == DDGS_PIVOT_SOURCE || a->pivot_mode == DDGS_PIVOT_POINT) &&
+                        std::isfinite(a->pivot[0]) && std::isfinite(a->pivot[1]) && std::isfinite(a->pivot[2]);
+        if (!ok)
+            return fail(c, DDGS_ERR_INVALID_ARG,
+                        "need lr >= 0, 0 <= beta < 1, eps > 0, a known pivot mode and a finite pivot");
+        c->adam = AdamCfg{a->lr_trans, a->lr_rot, a->beta1, a->beta2, a->eps, a->pivot_mode,
+                          {a->pivot[0], a->pivot[1], a->pivot[2]}};
     }
     c->adam_on = a != nullptr;
     c->adam_reset = true;

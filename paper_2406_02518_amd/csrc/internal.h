@@ -272,6 +272,8 @@ bool raster_tile_supported(int tw, int th);
 // device view table is re-based (R <- Exp(w) R, t <- Exp(w) t + rho).
 struct AdamCfg {
     float lr_trans, lr_rot, beta1, beta2, eps;
+    int pivot_mode;  // 0: rotate about the source, 1: about the world point pivot
+    float pivot[3];
 };
 hipError_t launch_pose_adam(ViewDev *views, int V, const float *dpose, float *state, uint32_t *step,
                             const AdamCfg &cfg, hipStream_t s);

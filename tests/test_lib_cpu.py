@@ -67,3 +67,33 @@ def test_product_path_refuses_to_run_without_the_library(monkeypatch, tmp_path):
     monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         binding.lib()
+
+
+def test_registration_metrics():
+    """The registration driver's error measures against the FP64 reference on
+    random poses, and the target registration error against closed forms."""
+    import numpy as np
+    from scipy.spatial.transform import Rotation
+
+    from oracle import pose_opt
+    from paper_2406_02518_amd import register, synth
+
+    rng = np.random.default_rng(21)
+    pts = rng.normal(size=(50, 3)) * 30.0
+    P = synth.azimuth_pose(40.0, 600.0)
+    for _ in range(5):
+        Q = synth.perturbed_pose(P, rng.normal(size=3) * 0.1, rng.normal(size=3) * 10.0)
+        ang, dso = pose_opt.pose_errors(Q, P)
+        assert register.rotation_error_deg(Q, P) == pytest.approx(ang, abs=1e-9)
+        assert register.source_error_mm(Q, P) == pytest.approx(dso, rel=1e-12)
+        assert register.projection_distance(Q, P, 800.0, pts) == pytest.approx(
+            pose_opt.projection_distance(Q, P, 800.0, pts), rel=1e-12)
+    # a shift by tau moves every point by |tau|; a rotation by a about an axis
+    # through the origin moves a point at distance r from the axis by 2 r sin(a/2)
+    T = P.copy()
+    T[:, 3] += [3.0, 4.0, 12.0]
+    assert register.target_registration_error(T, P, pts) == pytest.approx(13.0, rel=1e-12)
+    Rz = P.copy()
+    Rz[:, :3] = P[:, :3] @ Rotation.from_rotvec([0.0, 0.0, 0.3]).as_matrix()
+    r = np.linalg.norm(pts[:, :2], axis=1)
+    assert register.target_registration_error(Rz, P, pts) == pytest.approx(np.mean(2 * r * np.sin(0.15)), rel=1e-12)

@@ -538,3 +538,31 @@ def test_pose_step_reference_pins():
     Rz = np.concatenate([Rotation.from_rotvec([0, 0, 0.1]).as_matrix(), np.zeros((3, 1))], axis=1)
     r = 2000.0 * np.linalg.norm(pts[:, :2], axis=1) / 700.0
     assert pose_opt.projection_distance(Rz, I, 2000.0, pts) == pytest.approx(np.mean(2 * r * np.sin(0.05)), rel=1e-12)
+    # rotation about a pivot: the pivot's image stays put under a pure rotation,
+    # and pivot_gradient matches central differences of a smooth function of
+    # the projected points through rebase_about, given the left-tangent
+    # gradient from central differences through rebase
+    piv = np.array([5.0, -8.0, 12.0])
+    Q = pose_opt.rebase_about(P, np.array([0.0, 0.0, 0.0, 0.1, -0.2, 0.05]), piv)
+    np.testing.assert_allclose(Q[:, :3] @ piv + Q[:, 3], P[:, :3] @ piv + P[:, 3], atol=1e-9)
+    wpts = rng.normal(size=(30, 3)) * 40.0
+
+    def lossf(pose):
+        x = wpts @ pose[:, :3].T + pose[:, 3]
+        u = 1000.0 * x[:, :2] / x[:, 2:3]
+        return float(np.sum(np.sin(u / 37.0)) + np.sum(u[:, 0] * u[:, 1]) * 1e-4)
+
+    def fd(step_fn):
+        out = np.zeros(6)
+        for q in range(6):
+            e = np.zeros(6)
+            e[q] = 1e-6
+            out[q] = (lossf(step_fn(e)) - lossf(step_fn(-e))) / 2e-6
+        return out
+
+    g_left = fd(lambda e: pose_opt.rebase(P, e))
+    g_piv = fd(lambda e: pose_opt.rebase_about(P, e, piv))
+    np.testing.assert_allclose(pose_opt.pivot_gradient(g_left, P, piv), g_piv, rtol=1e-5, atol=1e-6 * np.abs(g_piv).max())
+    # the world origin is the source-frame point t
+    np.testing.assert_allclose(pose_opt.rebase_about(P, np.array([1.0, 2.0, 3.0, 0.1, 0.0, 0.0]), np.zeros(3))[:, 3],
+                               P[:, 3] + [1.0, 2.0, 3.0], atol=1e-9)
