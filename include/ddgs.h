@@ -66,7 +66,16 @@ typedef struct ddgs_ctx ddgs_ctx;
  * or ddgs_destroy; the caller may change their contents between calls).
  * Gaussians [0, n_iso) are isotropic, [n_iso, n) direction-dependent.
  * Activations: Sigma = R(q/|q|) diag(exp(2 log_scale)) R^T,
- * alpha = sigmoid(opacity_logit). */
+ * alpha = sigmoid(opacity_logit).
+ * Radiosity (Sec. 3.2, Eq. 3): DDGS_RADIOSITY_DISENTANGLED gives
+ * c = sigmoid(b_iso . f) to the isotropic set and
+ * c = sigmoid(Y_{1..L}(dir) . (B_dir f)) to the directional one, dir being
+ * the unit ray from the source to the mean.  DDGS_RADIOSITY_ENTANGLED is
+ * the co-located ablation of Sec. 4 ("direct-entangled"): every Gaussian
+ * carries both terms under one sigmoid, c = sigmoid(b_iso . f +
+ * Y_{1..L}(dir) . (B_dir f)), and n_iso must be 0.  Iso-only and dir-only
+ * models are n_iso = n and n_iso = 0 of the disentangled form. */
+enum { DDGS_RADIOSITY_DISENTANGLED = 0, DDGS_RADIOSITY_ENTANGLED = 1 };
 typedef struct {
     int64_t n, n_iso;            /* 0 <= n_iso <= n < 2^31 / n_views          */
     int32_t k;                   /* feature size, 1..32                       */
@@ -78,6 +87,8 @@ typedef struct {
     const float *feat;           /* [k][n]                                    */
     const float *b_iso;          /* [k]                                       */
     const float *B_dir;          /* [L(L+2)][k] row-major                     */
+    int32_t radiosity;           /* DDGS_RADIOSITY_*, 0 = Eq. 3 as printed     */
+    int32_t reserved;            /* must be 0                                 */
 } ddgs_model;
 
 /* One cone-beam view.  pose = [R | t] row-major 3x4, world -> source frame:

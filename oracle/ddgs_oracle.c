@@ -219,29 +219,29 @@ static void project_one(const orc_model *m, const orc_view *v, int vi,
     g->m2[1] = f * y / z + 0.5 * v->H;
     g->alpha = sigmoid(m->opacity_logit[i]);
 
-    /* Eq. 3 radiosity */
+    /* Eq. 3 radiosity: the isotropic logit b_iso . f, the directional logit
+     * Y(dir) . (B_dir f), or (co-located ablation) their sum */
     const int k = m->k, kl = orc_kl(m->L);
     if (o->c_override) {
         g->c = o->c_override[(int64_t)vi * n + i];
-    } else if (i < m->n_iso) {
-        double s = 0.0;
-        for (int j = 0; j < k; ++j) s += m->b_iso[j] * m->feat[(int64_t)j * n + i];
-        g->zl = s;
-        g->c = sigmoid(s);
     } else {
-        /* source position s_o = -R^T t; ray direction source -> mean, world frame */
-        double so[3];
-        for (int r = 0; r < 3; ++r) so[r] = -(R[r] * t[0] + R[3 + r] * t[1] + R[6 + r] * t[2]);
-        double rv[3] = {mu[0] - so[0], mu[1] - so[1], mu[2] - so[2]};
-        g->rlen = sqrt(rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2]);
-        for (int r = 0; r < 3; ++r) g->dir[r] = rv[r] / g->rlen;
-        orc_sh(m->L, g->dir, g->Y, NULL);
         double s = 0.0;
-        for (int a = 0; a < kl; ++a) {
-            double hv = 0.0;
-            for (int j = 0; j < k; ++j) hv += m->B_dir[a * k + j] * m->feat[(int64_t)j * n + i];
-            g->h[a] = hv;
-            s += g->Y[a] * hv;
+        if (m->entangled || i < m->n_iso)
+            for (int j = 0; j < k; ++j) s += m->b_iso[j] * m->feat[(int64_t)j * n + i];
+        if (m->entangled || i >= m->n_iso) {
+            /* source position s_o = -R^T t; ray direction source -> mean, world frame */
+            double so[3];
+            for (int r = 0; r < 3; ++r) so[r] = -(R[r] * t[0] + R[3 + r] * t[1] + R[6 + r] * t[2]);
+            double rv[3] = {mu[0] - so[0], mu[1] - so[1], mu[2] - so[2]};
+            g->rlen = sqrt(rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2]);
+            for (int r = 0; r < 3; ++r) g->dir[r] = rv[r] / g->rlen;
+            orc_sh(m->L, g->dir, g->Y, NULL);
+            for (int a = 0; a < kl; ++a) {
+                double hv = 0.0;
+                for (int j = 0; j < k; ++j) hv += m->B_dir[a * k + j] * m->feat[(int64_t)j * n + i];
+                g->h[a] = hv;
+                s += g->Y[a] * hv;
+            }
         }
         g->zl = s;
         g->c = sigmoid(s);
@@ -368,6 +368,7 @@ static int check_args(const orc_model *m, const orc_view *views, int V, const or
 {
     if (!m || !views || !o || V < 0 || m->n < 0) return -1;
     if (m->n_iso < 0 || m->n_iso > m->n) return -1;
+    if (m->entangled != 0 && (m->entangled != 1 || m->n_iso != 0)) return -1;
     if (m->L < 1 || m->L > 3 || m->k < 1) return -1;
     for (int v = 0; v < V; ++v)
         if (views[v].W <= 0 || views[v].H <= 0 || !(views[v].pitch_mm > 0.0) || !(views[v].sdd_mm > 0.0))
@@ -571,12 +572,13 @@ static void chain_one(const orc_model *m, const orc_view *v, const orc_opts *o,
     if (o->c_override) return;
     const int k = m->k, kl = orc_kl(m->L);
     const double gz = g7[6] * g->c * (1.0 - g->c);
-    if (i < m->n_iso) {
+    if (m->entangled || i < m->n_iso) {
         for (int j = 0; j < k; ++j) {
             gf[j] += gz * m->b_iso[j];
             gb[j] += gz * m->feat[(int64_t)j * n + i];
         }
-    } else {
+    }
+    if (m->entangled || i >= m->n_iso) {
         double Y[ORC_MAXKL], dY[3 * ORC_MAXKL];
         orc_sh(m->L, g->dir, Y, dY);
         double gd[3] = {0.0, 0.0, 0.0};

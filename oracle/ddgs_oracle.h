@@ -17,7 +17,8 @@
  *   - Sec. 3.2, Eq. 3: radiosity c = sigmoid(b_iso . f) for the isotropic
  *     set and c = sigmoid(Y_{1..L}(dir) . (B_dir f)) for the
  *     direction-dependent set, with k_L = L(L+2) basis functions and no
- *     degree-0 term.
+ *     degree-0 term; or, for the co-located ablation, the sigmoid of the sum
+ *     of both logits on every Gaussian.
  *   - App. A.2: both sets are composited jointly in one depth order.
  *   - App. A.1: transmittance is the running product of (1 - s).
  *   - Sec. 3.1, Eq. 2: the (1-lambda) L1 + lambda D-SSIM fitting loss, and a
@@ -41,7 +42,10 @@ extern "C" {
 
 /* Gaussian set, structure of arrays.  Values are float32 numbers widened to
  * double (the depth key re-reads them as float, which is exact then).
- * Gaussians [0, n_iso) are isotropic, [n_iso, n) direction-dependent. */
+ * Gaussians [0, n_iso) are isotropic, [n_iso, n) direction-dependent.
+ * entangled = 1 is the co-located ablation of Sec. 4 ("direct-entangled"):
+ * every Gaussian carries both terms under one sigmoid,
+ * c = sigmoid(b_iso . f + Y_{1..L}(dir) . (B_dir f)); it needs n_iso = 0. */
 typedef struct {
     int64_t n, n_iso;
     int32_t k, L;
@@ -52,6 +56,7 @@ typedef struct {
     const double *feat;          /* [k][n]                                   */
     const double *b_iso;         /* [k]                                      */
     const double *B_dir;         /* [k_L][k] row-major                       */
+    int32_t entangled;           /* 0: Eq. 3 as printed; 1: co-located        */
 } orc_model;
 
 /* Cone-beam view.  pose = [R | t] row-major 3x4, world -> source frame:

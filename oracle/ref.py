@@ -25,7 +25,7 @@ class _Model(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_iso", C.c_int64), ("k", C.c_int32), ("L", C.c_int32),
                 ("mean", C.c_void_p), ("quat", C.c_void_p), ("log_scale", C.c_void_p),
                 ("opacity_logit", C.c_void_p), ("feat", C.c_void_p), ("b_iso", C.c_void_p),
-                ("B_dir", C.c_void_p)]
+                ("B_dir", C.c_void_p), ("entangled", C.c_int32)]
 
 
 class _View(C.Structure):
@@ -105,6 +105,7 @@ def _model(scene, keep):
     m.L = int(scene.L)
     for name in ("mean", "quat", "log_scale", "opacity_logit", "feat", "b_iso", "B_dir"):
         setattr(m, name, _ptr(keep.add(_f64(getattr(scene, name)))))
+    m.entangled = 1 if getattr(scene, "entangled", False) else 0
     return m
 
 

@@ -1,7 +1,7 @@
 """``torch.autograd.Function`` around the HIP render / backward of libddgs.so.
 
 ``DDGSRender.apply(renderer, views, mean, quat, log_scale, opacity_logit, feat,
-b_iso, B_dir, pose_tangent, n_iso, L)`` returns the concatenated images of all
+b_iso, B_dir, pose_tangent, n_iso, L, entangled)`` returns the concatenated images of all
 views (view-major, each H x W).  Gradients flow to every Gaussian tensor, the
 two shared bases and ``pose_tangent`` (V x 6, (rho, omega) in mm and rad).
 The pose actually rendered is Exp(delta) pose (R' = Exp(omega) R,
@@ -38,11 +38,11 @@ def compose_views(views, pose_tangent):
 class DDGSRender(torch.autograd.Function):
     @staticmethod
     def forward(ctx, renderer, views, mean, quat, log_scale, opacity_logit, feat, b_iso, B_dir, pose_tangent,
-                n_iso, L):
+                n_iso, L, entangled=False):
         params = dict(mean=mean.detach(), quat=quat.detach(), log_scale=log_scale.detach(),
                       opacity_logit=opacity_logit.detach(), feat=feat.detach(), b_iso=b_iso.detach(),
                       B_dir=B_dir.detach())
-        renderer.set_model(params, n_iso, L)
+        renderer.set_model(params, n_iso, L, entangled)
         renderer.set_views(compose_views(views, pose_tangent))
         img = renderer.render()
         ctx.renderer = renderer
@@ -59,13 +59,13 @@ class DDGSRender(torch.autograd.Function):
         out = [grads.get(nm) for nm in names]
         if not ctx.has_pose:
             out[-1] = None
-        return (None, None, *out, None, None)
+        return (None, None, *out, None, None, None)
 
 
-def render(renderer, views, params, n_iso, L, pose_tangent=None):
+def render(renderer, views, params, n_iso, L, pose_tangent=None, entangled=False):
     """Differentiable render of ``views`` (list of synth.View) from ``params``
     (dict of tensors named mean, quat, log_scale, opacity_logit, feat, b_iso,
     B_dir)."""
     return DDGSRender.apply(renderer, views, params["mean"], params["quat"], params["log_scale"],
                             params["opacity_logit"], params["feat"], params["b_iso"], params["B_dir"],
-                            pose_tangent, n_iso, L)
+                            pose_tangent, n_iso, L, entangled)

@@ -37,7 +37,10 @@ class ddgs_model(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_iso", C.c_int64), ("k", C.c_int32), ("L", C.c_int32),
                 ("mean", C.c_void_p), ("quat", C.c_void_p), ("log_scale", C.c_void_p),
                 ("opacity_logit", C.c_void_p), ("feat", C.c_void_p), ("b_iso", C.c_void_p),
-                ("B_dir", C.c_void_p)]
+                ("B_dir", C.c_void_p), ("radiosity", C.c_int32), ("reserved", C.c_int32)]
+
+
+RADIOSITY_DISENTANGLED, RADIOSITY_ENTANGLED = 0, 1
 
 
 class ddgs_view(C.Structure):
@@ -351,8 +354,9 @@ class Renderer:
         o = ddgs_get_options(self.ctx)
         return {f: getattr(o, f) for f, _ in o._fields_}
 
-    def set_model(self, params, n_iso, L):
-        """params: dict of float32 contiguous device tensors named as PARAM_NAMES."""
+    def set_model(self, params, n_iso, L, entangled=False):
+        """params: dict of float32 contiguous device tensors named as PARAM_NAMES.
+        ``entangled``: both radiosity terms on every Gaussian (needs n_iso = 0)."""
         t = {}
         for name in PARAM_NAMES:
             x = params[name]
@@ -364,6 +368,7 @@ class Renderer:
         m.n_iso = int(n_iso)
         m.k = int(t["feat"].shape[0])
         m.L = int(L)
+        m.radiosity = RADIOSITY_ENTANGLED if entangled else RADIOSITY_DISENTANGLED
         for name in PARAM_NAMES:
             setattr(m, name, t[name].data_ptr())
         ddgs_set_model(self.ctx, m)
@@ -373,7 +378,7 @@ class Renderer:
     def set_scene(self, scene):
         p = {name: self.torch.from_numpy(np.ascontiguousarray(getattr(scene, name))).to(self.device)
              for name in PARAM_NAMES}
-        self.set_model(p, scene.n_iso, scene.L)
+        self.set_model(p, scene.n_iso, scene.L, getattr(scene, "entangled", False))
         return p
 
     def set_views(self, views):

@@ -215,6 +215,7 @@ ModelDev model_dev(const ddgs_model &m, const float *c_override)
     d.n_iso = (int32_t)m.n_iso;
     d.k = m.k;
     d.L = m.L;
+    d.entangled = m.radiosity == DDGS_RADIOSITY_ENTANGLED ? 1 : 0;
     d.mean = m.mean;
     d.quat = m.quat;
     d.log_scale = m.log_scale;
@@ -772,6 +773,11 @@ ddgs_status ddgs_set_model(ddgs_ctx *c, const ddgs_model *m)
     if (m->n >= ((int64_t)1 << 31)) return fail(c, DDGS_ERR_INVALID_ARG, "n too large");
     if (m->k < 1 || m->k > kMaxK) return fail(c, DDGS_ERR_INVALID_ARG, "k must be in 1..32");
     if (m->L < 1 || m->L > 3) return fail(c, DDGS_ERR_UNSUPPORTED, "L must be in 1..3");
+    if (m->reserved != 0) return fail(c, DDGS_ERR_INVALID_ARG, "reserved must be 0");
+    if (m->radiosity != DDGS_RADIOSITY_DISENTANGLED && m->radiosity != DDGS_RADIOSITY_ENTANGLED)
+        return fail(c, DDGS_ERR_INVALID_ARG, "unknown radiosity form");
+    if (m->radiosity == DDGS_RADIOSITY_ENTANGLED && m->n_iso != 0)
+        return fail(c, DDGS_ERR_INVALID_ARG, "an entangled model has no separate isotropic set (n_iso must be 0)");
     if (m->n > 0 && (!m->mean || !m->quat || !m->log_scale || !m->opacity_logit || !m->feat))
         return fail(c, DDGS_ERR_INVALID_ARG, "null Gaussian array");
     if (!m->b_iso || !m->B_dir) return fail(c, DDGS_ERR_INVALID_ARG, "null basis array");
@@ -779,7 +785,7 @@ ddgs_status ddgs_set_model(ddgs_ctx *c, const ddgs_model *m)
     for (const void *p : ptrs)
         if (((uintptr_t)p) % 4 != 0) return fail(c, DDGS_ERR_INVALID_ARG, "arrays must be 4-byte aligned");
     const bool shape_changed = !c->has_model || c->model.n != m->n || c->model.n_iso != m->n_iso ||
-                               c->model.k != m->k || c->model.L != m->L;
+                               c->model.k != m->k || c->model.L != m->L || c->model.radiosity != m->radiosity;
     const bool ptr_changed = !c->has_model || std::memcmp(&c->model, m, sizeof(*m)) != 0;
     c->model = *m;
     c->has_model = true;

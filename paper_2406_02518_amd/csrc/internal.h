@@ -33,6 +33,7 @@ struct RenderOpts {
 // Device pointers of the model (SoA, caller-owned).
 struct ModelDev {
     int32_t n, n_iso, k, L;
+    int32_t entangled;  // 1: both radiosity terms under one sigmoid on every Gaussian (n_iso = 0)
     const float *mean, *quat, *log_scale, *opacity_logit, *feat, *b_iso, *B_dir;
     const float *c_override;  // [V][n] radiosity used instead of Eq. 3 (NULL: Eq. 3)
 };
@@ -41,7 +42,8 @@ struct ModelDev {
 struct GaussCache {
     float *cov;    // [6][n]: world covariance xx, xy, xz, yy, yz, zz
     float *alpha;  // [n]
-    float *ciso;   // [n]: isotropic radiosity (only [0, n_iso) meaningful)
+    float *ciso;   // [n]: isotropic radiosity (only [0, n_iso) meaningful); entangled
+                   // models hold the isotropic logit b_iso . f of every Gaussian
     float *hdir;   // [k_L][n - n_iso]: B_dir f for directional Gaussians
 };
 

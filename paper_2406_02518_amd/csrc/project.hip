@@ -193,12 +193,13 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(ModelDev m, GaussCache gc)
     float f[KMAX];
 #pragma unroll
     for (int j = 0; j < KMAX; ++j) f[j] = j < k ? m.feat[(size_t)j * n + i] : 0.0f;
-    if (i < m.n_iso) {
+    if (i < m.n_iso || m.entangled) {
         float zl = 0.0f;
 #pragma unroll
         for (int j = 0; j < KMAX; ++j) zl += sb[j] * f[j];
-        gc.ciso[i] = sigmoidf(zl);
-    } else {
+        gc.ciso[i] = m.entangled ? zl : sigmoidf(zl);
+    }
+    if (i >= m.n_iso) {
         const int nd = n - m.n_iso, id = i - m.n_iso;
 #pragma unroll
         for (int r = 0; r < KL; ++r) {
@@ -251,7 +252,7 @@ __global__ __launch_bounds__(kBlock) void project_kernel(ModelDev m, GaussCache 
         const float il = 1.0f / sqrtf(rx * rx + ry * ry + rz * rz);
         float Y[KL];
         sh_basis<L>(rx * il, ry * il, rz * il, Y);
-        float zl = 0.0f;
+        float zl = m.entangled ? gc.ciso[i] : 0.0f;
 #pragma unroll
         for (int r = 0; r < KL; ++r) zl += Y[r] * gc.hdir[(size_t)r * nd + id];
         c = sigmoidf(zl);
@@ -305,7 +306,9 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
     float h[KL];
 #pragma unroll
     for (int r = 0; r < KL; ++r) h[r] = is_dir ? a.gc.hdir[(size_t)r * nd + id] : 0.0f;
-    const float ciso = is_dir ? 0.0f : a.gc.ciso[ii];
+    // isotropic radiosity, or for entangled models the isotropic logit
+    const float ciso = (is_dir && !a.m.entangled) ? 0.0f : a.gc.ciso[ii];
+    const float zl0 = a.m.entangled ? ciso : 0.0f;
 
     float gmu[3] = {0.f, 0.f, 0.f};
     float GSw[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -440,11 +443,12 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
                 const float dx = rx * il, dy = ry * il, dz = rz * il;
                 float Y[KL];
                 sh_basis<L>(dx, dy, dz, Y);
-                float zl = 0.0f;
+                float zl = zl0;
 #pragma unroll
                 for (int r = 0; r < KL; ++r) zl += Y[r] * h[r];
                 const float cd = 1.0f / (1.0f + expf(-zl));
                 const float gz = g7[6] * cd * (1.0f - cd);
+                if (a.m.entangled) zsum += gz;
                 float w[KL];
 #pragma unroll
                 for (int r = 0; r < KL; ++r) {
@@ -527,7 +531,7 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
             for (int j = 0; j < k; ++j) a.dfeat[(size_t)j * n + i] = zsum * a.m.b_iso[j];
         } else {
             for (int j = 0; j < k; ++j) {
-                float acc = 0.0f;
+                float acc = a.m.entangled ? zsum * a.m.b_iso[j] : 0.0f;
 #pragma unroll
                 for (int r = 0; r < KL; ++r) acc += a.m.B_dir[r * k + j] * u[r];
                 a.dfeat[(size_t)j * n + i] = acc;
@@ -539,9 +543,8 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
         float row[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) row[r] = 0.0f;
-        if (!is_dir) {
-            row[15] = zsum;
-        } else {
+        if (!is_dir || a.m.entangled) row[15] = zsum;
+        if (is_dir) {
 #pragma unroll
             for (int r = 0; r < KL; ++r) row[r] = u[r];
         }

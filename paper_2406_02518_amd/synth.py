@@ -32,6 +32,7 @@ class Scene:
     B_dir: np.ndarray          # (k_L, k)
     n_iso: int
     L: int
+    entangled: bool = False    # co-located ablation: both radiosity terms on every Gaussian (n_iso = 0)
 
     @property
     def n(self):

@@ -77,6 +77,27 @@ def test_parameter_gradients_by_central_differences(seed):
         assert np.linalg.norm(an) > 0, name
 
 
+@pytest.mark.parametrize("seed,L,k", [(33, 3, 8), (34, 1, 4)])
+def test_entangled_gradients_by_central_differences(seed, L, k):
+    """The co-located ablation (both radiosity terms under one sigmoid on every
+    Gaussian): every parameter group, both bases included, by central
+    differences."""
+    from dataclasses import replace
+    sc = replace(_scene64(seed, k=k, L=L), n_iso=0, entangled=True)
+    v = _view(theta=11.0 * seed)
+    g = np.random.default_rng(seed).normal(size=v.W * v.H)
+    _, base_hash = _loss(sc, v, g)
+    grads = ref.backward(sc, [v], ref.all_pixels([v]), g)
+    for name, gname, h in GROUPS:
+        fd, skipped = _fd_group(sc, v, g, name, h, base_hash)
+        an = grads[gname].reshape(-1)
+        ok = ~np.isnan(fd)
+        assert ok.sum() >= 0.9 * fd.size, (name, skipped)
+        err = np.linalg.norm(fd[ok] - an[ok]) / max(1e-300, np.linalg.norm(an[ok]))
+        assert err < 1e-6, (name, err)
+        assert np.linalg.norm(an) > 0, name
+
+
 def _exp_pose(v, delta):
     """pose' = Exp(delta) pose with delta = (rho, omega): R' = Exp(w) R,
     t' = Exp(w) t + rho."""

@@ -566,3 +566,40 @@ def test_pose_step_reference_pins():
     # the world origin is the source-frame point t
     np.testing.assert_allclose(pose_opt.rebase_about(P, np.array([1.0, 2.0, 3.0, 0.1, 0.0, 0.0]), np.zeros(3))[:, 3],
                                P[:, 3] + [1.0, 2.0, 3.0], atol=1e-9)
+
+
+def test_entangled_radiosity_reductions_and_logit_sum():
+    """Co-located ablation: with B_dir = 0 it is the all-isotropic model, with
+    b_iso = 0 the all-directional one (same images), and in general each
+    Gaussian's radiosity logit is the isotropic logit plus the directional one
+    (read from the per-Gaussian projection records of the three models)."""
+    from dataclasses import replace
+    base = synth.random_scene(5, 40, k=8, L=2, iso_fraction=0.0, extent=8.0, std_range=(1.0, 2.5),
+                              alpha_range=(0.1, 0.6))
+    ent = replace(base, n_iso=0, entangled=True)
+    v = synth.view(32, 28, 0.6, 1000.0, 600.0, 25.0)
+    iso_only = replace(base, n_iso=base.n)
+    dir_only = replace(base, n_iso=0)
+    zero_B = replace(ent, B_dir=np.zeros_like(base.B_dir))
+    zero_b = replace(ent, b_iso=np.zeros_like(base.b_iso))
+    np.testing.assert_allclose(ref.render(zero_B, [v])[0], ref.render(replace(iso_only, B_dir=zero_B.B_dir), [v])[0],
+                               rtol=0, atol=1e-15)
+    np.testing.assert_allclose(ref.render(zero_b, [v])[0], ref.render(replace(dir_only, b_iso=zero_b.b_iso), [v])[0],
+                               rtol=0, atol=1e-15)
+    ci = ref.project(iso_only, v)[:, ref.PROJ_FIELDS.index("c")]
+    cd = ref.project(dir_only, v)[:, ref.PROJ_FIELDS.index("c")]
+    ce = ref.project(ent, v)[:, ref.PROJ_FIELDS.index("c")]
+    ok = ref.project(ent, v)[:, 0] > 0
+    assert ok.sum() > 20
+
+    def logit(c):
+        return np.log(c) - np.log1p(-c)
+
+    np.testing.assert_allclose(logit(ce[ok]), logit(ci[ok]) + logit(cd[ok]), rtol=1e-9, atol=1e-9)
+    # the entangled image differs from both single-term models
+    img_e = ref.render(ent, [v])[0]
+    assert np.abs(img_e - ref.render(iso_only, [v])[0]).max() > 1e-3
+    assert np.abs(img_e - ref.render(dir_only, [v])[0]).max() > 1e-3
+    # an entangled model must have no separate isotropic set
+    with pytest.raises(Exception):
+        ref.render(replace(ent, n_iso=3), [v])
