@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-row-stride", type=int, default=2,
                     help="oracle baseline: every n-th detector row of one view")
     ap.add_argument("--batched-reps", type=int, default=5)
@@ -275,6 +276,41 @@ def main():
             stage_roofline.append({"stage": k, "bound": "hbm", "achieved": round(a, 1), "peak": PEAK_HBM_GBS,
                                    "unit": "GB/s", "frac": round(a / PEAK_HBM_GBS, 4), "ms": round(stages[k], 4)})
     log("stages (ms):", json.dumps({k: round(v, 4) for k, v in stages.items()}))
+
+    # ---------------- model variants of the ablations on the same geometry
+    # (same Gaussians, poses, targets and raster options; new seeded features
+    # and bases of each size), one captured fitting step per pose
+    variants = None
+    if not args.no_variants:
+        variants = []
+        R.set_options(capacity=int(maxM * 1.25) + 1024)
+        for name, k_v, L_v, kind in (("disentangled L=3 k=16", 16, 3, "disentangled"),
+                                     ("disentangled L=1 k=8", 8, 1, "disentangled"),
+                                     ("disentangled L=3 k=8", 8, 3, "disentangled"),
+                                     ("disentangled L=3 k=32", 32, 3, "disentangled"),
+                                     ("disentangled L=3 k=1", 1, 3, "disentangled"),
+                                     ("iso-only k=16", 16, 3, "iso_only"),
+                                     ("dir-only L=3 k=16", 16, 3, "dir_only"),
+                                     ("entangled L=3 k=16", 16, 3, "entangled")):
+            sc_v = synth.with_features(cfg.scene, 5150 + len(variants), k_v, L_v, kind)
+            with torch.cuda.stream(stream):
+                R.set_scene(sc_v)
+                R.set_views([views[0]])
+            g_v = R.alloc_grads()
+            binding.ddgs_step_capture(R.ctx, binding.LOSS_L1_DSSIM, tgt.data_ptr(), 0.2, img.data_ptr(),
+                                      dl.data_ptr(), loss.data_ptr(), R.grads_struct(g_v))
+            for j in range(3):
+                step(j)
+            binding.ddgs_check(R.ctx)
+            stream.synchronize()
+            a = time.perf_counter()
+            for j in range(len(views)):
+                step(j)
+            stream.synchronize()
+            t_v = (time.perf_counter() - a) * 1e3 / len(views)
+            binding.ddgs_check(R.ctx)
+            variants.append({"model": name, "n_iso": int(sc_v.n_iso), "ms_per_step": round(t_v, 4)})
+            log("variant:", json.dumps(variants[-1]))
     R.close()
 
     # ------------------------------------------- C4 batched vs plain speed-up
@@ -490,6 +526,7 @@ def main():
         "roofline": roofline,
         "stage_roofline": stage_roofline,
         "step_distribution": step_dist,
+        "variants": variants,
         "batched": batched,
         "uneven_batch": uneven,
         "cpu_baseline": cpu,

@@ -154,6 +154,20 @@ def random_scene(seed, n, k=K_DEFAULT, L=L_DEFAULT, iso_fraction=0.8, extent=32.
                  n_iso=n_iso, L=L)
 
 
+def with_features(scene, seed, k, L, variant="disentangled"):
+    """The geometry of ``scene`` with new seeded features and bases of size k
+    and degree L, for the model variants of the ablations: "disentangled"
+    keeps the isotropic / directional split, "iso_only" and "dir_only" make
+    every Gaussian one kind, "entangled" gives every Gaussian both terms.
+    Features ~N(0, 0.5^2), b_iso ~N(0, 1), B_dir ~N(0, 0.3^2)."""
+    rng = np.random.default_rng(seed)
+    n, kl = scene.n, L * (L + 2)
+    n_iso = {"disentangled": scene.n_iso, "iso_only": n, "dir_only": 0, "entangled": 0}[variant]
+    return replace(scene, feat=_f32(rng.normal(0.0, 0.5, size=(k, n))), b_iso=_f32(rng.normal(size=k)),
+                   B_dir=_f32(rng.normal(0.0, 0.3, size=(kl, k))), n_iso=n_iso, L=L,
+                   entangled=variant == "entangled")
+
+
 def phantom(n, rng):
     """n^3 HU volume at 1 mm: air -1000, a soft-tissue body ellipsoid (0..80),
     three organ ellipsoids, two air-filled lungs, a spine cylinder with cortex
