@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--fit-iters", type=int, default=720,
+                    help="iterations of the fitting run on the 500k-Gaussian workload (0: skip)")
     ap.add_argument("--cpu-row-stride", type=int, default=2,
                     help="oracle baseline: every n-th detector row of one view")
     ap.add_argument("--batched-reps", type=int, default=5)
@@ -124,7 +126,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2406_02518_amd import binding, register, synth
+    from paper_2406_02518_amd import binding, fit, register, synth
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -311,6 +313,32 @@ def main():
             binding.ddgs_check(R.ctx)
             variants.append({"model": name, "n_iso": int(sc_v.n_iso), "ms_per_step": round(t_v, 4)})
             log("variant:", json.dumps(variants[-1]))
+
+    # ------------- fitting run: captured step + Adam, densification between
+    fitting = None
+    if args.fit_iters > 0:
+        R.set_options(capacity=0)  # every capture sizes itself (the model grows)
+        with torch.cuda.stream(stream):
+            p_fit = R.set_scene(cfg.scene)
+        extent = float(np.abs(cfg.scene.mean).max())
+        sched = fit.FitSchedule(densify_from=100, densify_until=600, densify_every=100, opacity_reset_every=0)
+        stream.synchronize()
+        a = time.perf_counter()
+        _, _, hist = fit.fit(R, p_fit, cfg.scene.n_iso, cfg.scene.L, views, targets, iters=args.fit_iters,
+                             extent=extent, schedule=sched, log_every=72)
+        stream.synchronize()
+        t_fit = time.perf_counter() - a
+        n_dens = len([i for i in range(1, args.fit_iters + 1)
+                      if sched.densify_from <= i <= sched.densify_until and i % sched.densify_every == 0])
+        fitting = {"workload": "fitting run on the same 500k-Gaussian model, poses and targets: one captured step "
+                               "(render, (1-0.2) L1 + 0.2 D-SSIM, backward, Adam on every group) per iteration, "
+                               "one pose per iteration in shuffled epochs, densification every 100 iterations "
+                               "from 100 to 600 followed by a new capture",
+                   "iterations": args.fit_iters, "seconds": round(t_fit, 3),
+                   "ms_per_iteration": round(t_fit * 1e3 / args.fit_iters, 4), "densifications": n_dens,
+                   "gaussians": [int(cfg.scene.n), int(hist[-1][1]) if hist else int(cfg.scene.n)],
+                   "loss_first_last_72": [round(hist[0][2], 7), round(hist[-1][2], 7)] if hist else None}
+        log("fitting:", json.dumps(fitting))
     R.close()
 
     # ------------------------------------------- C4 batched vs plain speed-up
@@ -527,6 +555,7 @@ def main():
         "stage_roofline": stage_roofline,
         "step_distribution": step_dist,
         "variants": variants,
+        "fitting": fitting,
         "batched": batched,
         "uneven_batch": uneven,
         "cpu_baseline": cpu,

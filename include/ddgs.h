@@ -190,6 +190,81 @@ typedef struct ddgs_adam {
 ddgs_status ddgs_set_pose_optimizer(ddgs_ctx *ctx, const ddgs_adam *adam);
 ddgs_status ddgs_get_views(ddgs_ctx *ctx, ddgs_view *views, int n_views);
 
+/* Fitting (Sec. 4.1, implementation paragraph; App., Gaussians that move,
+ * split and drop).
+ *
+ * ddgs_set_fit_optimizer: with options set, ddgs_step_capture appends one
+ * Adam step over every parameter group (grads must hold all seven
+ * parameter gradients) that updates the model arrays IN PLACE -- the caller
+ * enables it only for writable device memory.  Per element:
+ * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr m / (1 - b1^t) / (sqrt(v / (1 - b2^t)) + eps), t = 1, 2, ... the
+ * step count kept on the device.  The position rate decays log-linearly from
+ * lr_mean_init to lr_mean_final over lr_mean_steps steps and is held after.
+ * Defaults (ddgs_default_fit_options): the paper's 1.25e-4 for both bases
+ * and 2.5e-3 for the features; 3D Gaussian splatting's 5e-3 log-scales,
+ * 1e-3 rotations, 5e-2 opacity logits, beta (0.9, 0.999), eps 1e-15 and
+ * position 1.6e-4 -> 1.6e-6 times the scene extent over 30000 steps (the
+ * extent argument, mm).  Moments and step count restart at the next replay
+ * after this call and after ddgs_set_model, except that a model set with the
+ * shape a ddgs_densify_apply produced keeps the moments it re-laid out.
+ * NULL turns the optimiser off.  Either call drops a captured step. */
+typedef struct ddgs_fit_opts {
+    float lr_mean_init, lr_mean_final;   /* mm per step                       */
+    int32_t lr_mean_steps;               /* >= 1                              */
+    float lr_quat, lr_log_scale, lr_opacity, lr_feat, lr_b_iso, lr_B_dir;
+    float beta1, beta2, eps;
+} ddgs_fit_opts;
+void ddgs_default_fit_options(ddgs_fit_opts *opts, float scene_extent_mm);
+ddgs_status ddgs_set_fit_optimizer(ddgs_ctx *ctx, const ddgs_fit_opts *opts);
+
+/* Densification statistics: device [n] floats owned by the caller
+ * (borrowed; zero them to start).  Every backward, plain or captured, adds
+ * for each Gaussian visible in a view (non-empty tile rectangle) the norm of
+ * its 2D-mean gradient in normalised device units (pixel gradient times W/2
+ * and H/2) to grad_accum and 1 to count, and raises max_radius to its
+ * projected radius kappa sqrt(lambda_max(Sigma^)) in pixels.  NULL arrays
+ * turn the accumulation off.  Drops a captured step. */
+ddgs_status ddgs_set_densify_stats(ddgs_ctx *ctx, float *grad_accum, float *count, float *max_radius);
+
+/* Densification of the current model from the statistics, in two calls.
+ * ddgs_densify_plan decides on the device, for every Gaussian: mean
+ * gradient a = grad_accum / count (0 if count is 0), s = largest log-scale;
+ * a >= grad_threshold and s <= log(dense_scale): clone (exact copy added);
+ * a >= grad_threshold and s > log(dense_scale): split (the parent is replaced
+ * by two children at mu + R(q) diag(exp(log_scale)) eps_c, eps_c = noise[i][c]
+ * (device [n][2][3], N(0, 1) draws supplied by the caller, read by
+ * ddgs_densify_apply), log-scales lowered by log(split_factor)).  Then every
+ * resulting Gaussian is dropped if sigmoid(opacity_logit) < min_opacity, or
+ * if max_world_scale > 0 and its largest scale exceeds it, or -- originals
+ * only -- if max_screen_radius > 0 and max_radius exceeds it.  Thresholds
+ * are compared in float32 against float32 images of log(dense_scale),
+ * logit(min_opacity), log(max_world_scale) and log(split_factor) formed in
+ * double.  It synchronises and returns the new counts.
+ * ddgs_densify_apply writes the new model into caller-allocated device
+ * arrays of n_new Gaussians (out; b_iso and B_dir are copied), ordered per
+ * set -- isotropic then directional -- as kept originals, clones, children,
+ * each in parent order, and re-lays out the optimiser moments (zero for new
+ * Gaussians).  The caller then sets the new model with ddgs_set_model. */
+typedef struct ddgs_densify_opts {
+    float grad_threshold;      /* 2e-4 (normalised device units)             */
+    float dense_scale;         /* mm; 3DGS: 0.01 x scene extent              */
+    float min_opacity;         /* 0.005                                      */
+    float max_world_scale;     /* mm; 3DGS: 0.1 x scene extent; <= 0: off    */
+    float max_screen_radius;   /* px; 3DGS: 20 after the first opacity reset */
+    float split_factor;        /* 1.6                                        */
+} ddgs_densify_opts;
+typedef struct ddgs_params {
+    float *mean, *quat, *log_scale, *opacity_logit, *feat, *b_iso, *B_dir;
+} ddgs_params;
+ddgs_status ddgs_densify_plan(ddgs_ctx *ctx, const ddgs_densify_opts *opts, const float *noise,
+                              int64_t *n_new, int64_t *n_iso_new);
+ddgs_status ddgs_densify_apply(ddgs_ctx *ctx, const ddgs_params *out);
+
+/* Opacity reset: opacity_logit = min(opacity_logit, logit(max_alpha)) in
+ * place, and the opacity moments are zeroed. */
+ddgs_status ddgs_fit_reset_opacity(ddgs_ctx *ctx, float max_alpha);
+
 /* Test hook: radiosity c per (view, Gaussian), device [n_views][n] floats,
  * used instead of Eq. 3 (NULL restores Eq. 3).  With it the image is linear
  * in c (Eq. 1), and the backward leaves the features and bases out of the
@@ -286,7 +361,9 @@ enum {
     DDGS_DBG_TILE_VALS = 7,   /* [M] u32 sorted                                  */
     DDGS_DBG_RANGES = 8,      /* [n_tiles][2] u32 [start, end)                   */
     DDGS_DBG_NLAST = 9,       /* [pixels] u32: end of the contributing prefix    */
-    DDGS_DBG_TILE_BASE = 10   /* [n_views+1] i32: first global tile id per view  */
+    DDGS_DBG_TILE_BASE = 10,  /* [n_views+1] i32: first global tile id per view  */
+    DDGS_DBG_FIT_MOMENTS = 11 /* [2][n(11+k) + k + k_L k] f32: Adam first, then
+                                 second moments, groups in model order       */
 };
 /* Copies an internal array of the last render to host memory (synchronises).
  * The *_UNSORTED arrays are kept only when options are set with

@@ -59,51 +59,57 @@ def adam(params, grads, m, v, t, lrs, beta1=0.9, beta2=0.999, eps=1e-15):
     return out_p, out_m, out_v
 
 
-def visible_boxes(scene, view, kappa=3.0, opts=None):
+def visible_boxes(scene, view, kappa=3.0, opts=None, band=0.05):
     """Visibility of every Gaussian in a view: projected (not culled) and its
     kappa box [mu -+ kappa sqrt(S_aa)] overlaps a pixel centre of the image.
-    Returns (visible bool [n], margin [n]: pixel distance of the box edges to
-    the nearest decision, for tests that skip ambiguous cases), and the
-    radius kappa sqrt(lambda_max) in pixels."""
+    Returns (visible bool [n], stable bool [n]: the decision is the same when
+    the box centre and half-widths move by -+(band + 1e-3 half-width) pixels,
+    for tests that skip cases within rounding of the decision, radius
+    kappa sqrt(lambda_max) in pixels)."""
     P = ref.project(scene, view, opts=opts)
     f = {name: P[:, i] for i, name in enumerate(ref.PROJ_FIELDS)}
     ok = f["valid"] > 0
     rx = kappa * np.sqrt(np.maximum(f["S00"], 0.0))
     ry = kappa * np.sqrt(np.maximum(f["S11"], 0.0))
-    # pixel centres u + 0.5 inside [mx - rx, mx + rx], clipped to the image
-    u0 = np.maximum(np.ceil(f["mx"] - rx - 0.5), 0)
-    u1 = np.minimum(np.floor(f["mx"] + rx - 0.5), view.W - 1)
-    v0 = np.maximum(np.ceil(f["my"] - ry - 0.5), 0)
-    v1 = np.minimum(np.floor(f["my"] + ry - 0.5), view.H - 1)
-    vis = ok & (u0 <= u1) & (v0 <= v1)
 
-    def frac_gap(x):
-        return np.abs(x - np.round(x))
+    def decide(mx, my, hx, hy):
+        # pixel centres u + 0.5 inside [mx - hx, mx + hx], clipped to the image
+        u0 = np.maximum(np.ceil(mx - hx - 0.5), 0)
+        u1 = np.minimum(np.floor(mx + hx - 0.5), view.W - 1)
+        v0 = np.maximum(np.ceil(my - hy - 0.5), 0)
+        v1 = np.minimum(np.floor(my + hy - 0.5), view.H - 1)
+        return ok & (u0 <= u1) & (v0 <= v1)
 
-    margin = np.minimum.reduce([frac_gap(f["mx"] - rx - 0.5), frac_gap(f["mx"] + rx - 0.5),
-                                frac_gap(f["my"] - ry - 0.5), frac_gap(f["my"] + ry - 0.5)])
+    vis = decide(f["mx"], f["my"], rx, ry)
+    stable = np.ones_like(vis)
+    dx, dy = band + 1e-3 * rx, band + 1e-3 * ry
+    for sx in (-1, 1):
+        for sy in (-1, 1):
+            for sw in (-1, 1):
+                stable &= decide(f["mx"] + sx * dx, f["my"] + sy * dy, rx + sw * dx, ry + sw * dy) == vis
     mid = 0.5 * (f["S00"] + f["S11"])
     lam = mid + np.sqrt(np.maximum(mid * mid - (f["S00"] * f["S11"] - f["S01"] ** 2), 0.0))
     radius = kappa * np.sqrt(np.maximum(lam, 0.0))
-    return vis, np.where(ok, margin, np.inf), np.where(ok, radius, 0.0)
+    return vis, stable | ~ok, np.where(ok, radius, 0.0)
 
 
 def densify_stats(scene, views, g2d, opts=None):
     """Statistics accumulated over one backward of ``views`` from the oracle's
     per-view image-plane gradients g2d [V][n][7] (d mu^x, d mu^y first).
-    Returns (grad_accum, denom, max_radius, margin)."""
+    Returns (grad_accum, denom, max_radius, stable) with stable as in
+    visible_boxes, over all views."""
     n = scene.n
     acc, den, rad = np.zeros(n), np.zeros(n), np.zeros(n)
-    margin = np.full(n, np.inf)
+    stable = np.ones(n, bool)
     for vi, v in enumerate(views):
-        vis, mg, r = visible_boxes(scene, v, opts=opts)
+        vis, st, r = visible_boxes(scene, v, opts=opts)
         gx = g2d[vi, :, 0] * (0.5 * v.W)
         gy = g2d[vi, :, 1] * (0.5 * v.H)
         acc += np.where(vis, np.sqrt(gx * gx + gy * gy), 0.0)
         den += vis
         rad = np.maximum(rad, np.where(vis, r, 0.0))
-        margin = np.minimum(margin, mg)
-    return acc, den, rad, margin
+        stable &= st
+    return acc, den, rad, stable
 
 
 def thresholds(grad_threshold, dense_scale, min_opacity, max_world_scale, max_screen_radius, split_factor=1.6):

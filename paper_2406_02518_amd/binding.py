@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libddgs.so")
 OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_CAPACITY, ERR_NONFINITE, ERR_STATE, ERR_UNSUPPORTED = range(8)
 LOSS_L1_DSSIM, LOSS_NCC, LOSS_LINEAR = 0, 1, 2
 (DBG_RECORDS, DBG_DEPTH_KEYS, DBG_COUNTS, DBG_RECTS, DBG_TILE_KEYS_UNSORTED, DBG_TILE_VALS_UNSORTED,
- DBG_TILE_KEYS, DBG_TILE_VALS, DBG_RANGES, DBG_NLAST, DBG_TILE_BASE) = range(11)
+ DBG_TILE_KEYS, DBG_TILE_VALS, DBG_RANGES, DBG_NLAST, DBG_TILE_BASE, DBG_FIT_MOMENTS) = range(12)
 T_PROJECT, T_SORT, T_RASTER_FWD, T_LOSS, T_RASTER_BWD, T_PROJECT_BWD, T_COUNT = range(7)
 STAGES = ("project", "sort", "raster_fwd", "loss", "raster_bwd", "project_bwd")
 
@@ -30,7 +30,9 @@ EXPORTED = (
     "ddgs_image_size", "ddgs_render", "ddgs_backward", "ddgs_loss", "ddgs_step_capture", "ddgs_step_launch",
     "ddgs_check", "ddgs_autotune", "ddgs_param_count", "ddgs_num_rendered", "ddgs_debug_copy",
     "ddgs_debug_keep_unsorted", "ddgs_debug_sort_pairs", "ddgs_debug_exclusive_scan", "ddgs_debug_count_pairs",
-    "ddgs_debug_pair_counts", "ddgs_enable_timing", "ddgs_stage_times")
+    "ddgs_debug_pair_counts", "ddgs_enable_timing", "ddgs_stage_times", "ddgs_default_fit_options",
+    "ddgs_set_fit_optimizer", "ddgs_set_densify_stats", "ddgs_densify_plan", "ddgs_densify_apply",
+    "ddgs_fit_reset_opacity")
 
 
 class ddgs_model(C.Structure):
@@ -65,6 +67,22 @@ class ddgs_options(C.Structure):
 class ddgs_grads(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("dmean", "dquat", "dlog_scale", "dopacity_logit", "dfeat", "db_iso",
                                           "dB_dir", "dpose")]
+
+
+class ddgs_fit_opts(C.Structure):
+    _fields_ = [("lr_mean_init", C.c_float), ("lr_mean_final", C.c_float), ("lr_mean_steps", C.c_int32),
+                ("lr_quat", C.c_float), ("lr_log_scale", C.c_float), ("lr_opacity", C.c_float),
+                ("lr_feat", C.c_float), ("lr_b_iso", C.c_float), ("lr_B_dir", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
+
+
+class ddgs_densify_opts(C.Structure):
+    _fields_ = [(n, C.c_float) for n in ("grad_threshold", "dense_scale", "min_opacity", "max_world_scale",
+                                         "max_screen_radius", "split_factor")]
+
+
+class ddgs_params(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("mean", "quat", "log_scale", "opacity_logit", "feat", "b_iso", "B_dir")]
 
 
 class DDGSError(RuntimeError):
@@ -119,6 +137,12 @@ def lib():
             "ddgs_debug_pair_counts": ([vp, C.POINTER(i64), C.POINTER(i64)], st),
             "ddgs_enable_timing": ([vp, C.c_int], st),
             "ddgs_stage_times": ([vp, C.POINTER(C.c_float)], st),
+            "ddgs_default_fit_options": ([C.POINTER(ddgs_fit_opts), C.c_float], None),
+            "ddgs_set_fit_optimizer": ([vp, C.POINTER(ddgs_fit_opts)], st),
+            "ddgs_set_densify_stats": ([vp, vp, vp, vp], st),
+            "ddgs_densify_plan": ([vp, C.POINTER(ddgs_densify_opts), vp, C.POINTER(i64), C.POINTER(i64)], st),
+            "ddgs_densify_apply": ([vp, C.POINTER(ddgs_params)], st),
+            "ddgs_fit_reset_opacity": ([vp, C.c_float], st),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -187,6 +211,34 @@ def ddgs_set_radiosity_override(ctx, ptr):
 
 def ddgs_set_pose_optimizer(ctx, adam):
     _check(lib().ddgs_set_pose_optimizer(ctx, None if adam is None else C.byref(adam)), ctx)
+
+
+def ddgs_default_fit_options(extent):
+    o = ddgs_fit_opts()
+    lib().ddgs_default_fit_options(C.byref(o), float(extent))
+    return o
+
+
+def ddgs_set_fit_optimizer(ctx, opts):
+    _check(lib().ddgs_set_fit_optimizer(ctx, None if opts is None else C.byref(opts)), ctx)
+
+
+def ddgs_set_densify_stats(ctx, grad_ptr, cnt_ptr, rad_ptr):
+    _check(lib().ddgs_set_densify_stats(ctx, grad_ptr, cnt_ptr, rad_ptr), ctx)
+
+
+def ddgs_densify_plan(ctx, opts, noise_ptr):
+    n_new, n_iso = C.c_int64(), C.c_int64()
+    _check(lib().ddgs_densify_plan(ctx, C.byref(opts), noise_ptr, C.byref(n_new), C.byref(n_iso)), ctx)
+    return n_new.value, n_iso.value
+
+
+def ddgs_densify_apply(ctx, params):
+    _check(lib().ddgs_densify_apply(ctx, C.byref(params)), ctx)
+
+
+def ddgs_fit_reset_opacity(ctx, max_alpha):
+    _check(lib().ddgs_fit_reset_opacity(ctx, float(max_alpha)), ctx)
 
 
 def ddgs_get_views(ctx, n):
@@ -413,6 +465,62 @@ class Renderer:
             a.pivot_mode = PIVOT_POINT
             a.pivot[:] = [float(x) for x in pivot]
         ddgs_set_pose_optimizer(self.ctx, a)
+
+    # ------------------------------------------------------------ fitting
+    def set_fit_optimizer(self, extent=None, **rates):
+        """Adam on every parameter group inside captured steps, updating the
+        model tensors in place; defaults from ddgs_default_fit_options(extent)
+        with any field overridden by keyword.  extent None turns it off."""
+        if extent is None:
+            ddgs_set_fit_optimizer(self.ctx, None)
+            return
+        o = ddgs_default_fit_options(extent)
+        for k, v in rates.items():
+            setattr(o, k, v)
+        ddgs_set_fit_optimizer(self.ctx, o)
+
+    def set_densify_stats(self, stats):
+        """stats: dict of float32 [n] device tensors grad, count, radius (None: off)."""
+        if stats is None:
+            ddgs_set_densify_stats(self.ctx, None, None, None)
+            self._keep.pop("stats", None)
+            return
+        ddgs_set_densify_stats(self.ctx, stats["grad"].data_ptr(), stats["count"].data_ptr(),
+                               stats["radius"].data_ptr())
+        self._keep["stats"] = stats
+
+    def new_densify_stats(self):
+        z = self.torch.zeros(self.n, device=self.device, dtype=self.torch.float32)
+        return {"grad": z, "count": z.clone(), "radius": z.clone()}
+
+    def densify(self, noise, grad_threshold=2e-4, dense_scale=1.0, min_opacity=0.005, max_world_scale=0.0,
+                max_screen_radius=0.0, split_factor=1.6):
+        """Plans and applies one densification; returns (params dict of new
+        tensors, n_iso).  The caller sets the new model (set_model)."""
+        o = ddgs_densify_opts(float(grad_threshold), float(dense_scale), float(min_opacity), float(max_world_scale),
+                              float(max_screen_radius), float(split_factor))
+        noise = noise.contiguous()
+        cur = self._begin()
+        n_new, n_iso = ddgs_densify_plan(self.ctx, o, noise.data_ptr())
+        m = self._keep["model"]
+        t = self.torch
+        out = {"mean": t.empty((3, n_new), device=self.device), "quat": t.empty((4, n_new), device=self.device),
+               "log_scale": t.empty((3, n_new), device=self.device), "opacity_logit": t.empty(n_new, device=self.device),
+               "feat": t.empty((self.k, n_new), device=self.device), "b_iso": t.empty_like(m["b_iso"]),
+               "B_dir": t.empty_like(m["B_dir"])}
+        p = ddgs_params(*[out[name].data_ptr() if out[name].numel() else None for name in PARAM_NAMES])
+        ddgs_densify_apply(self.ctx, p)
+        self._end(cur, noise, *out.values())
+        return out, n_iso
+
+    def reset_opacity(self, max_alpha=0.01):
+        ddgs_fit_reset_opacity(self.ctx, max_alpha)
+
+    def fit_moments(self):
+        """Adam moments (m, v) as flat float32 host arrays."""
+        P = self.n * (11 + self.k) + self.k + self.L * (self.L + 2) * self.k
+        out = ddgs_debug_copy(self.ctx, DBG_FIT_MOMENTS, np.float32, 2 * P)
+        return out[:P], out[P:]
 
     def get_poses(self):
         """Current (3, 4) float32 world -> source poses of the views."""

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <limits>
 #include <map>
 #include <sstream>
 #include <string>
@@ -48,6 +49,20 @@ struct ddgs_ctx {
     bool adam_on = false;
     AdamCfg adam{};
     bool adam_reset = true;   // zero the moments before the next replay
+
+    // fitting optimiser appended to captured steps; densification
+    bool fit_on = false;
+    FitCfg fit{};
+    bool fit_reset = true;          // zero moments and step count before the next replay
+    bool fit_live = false;          // "fit_mv" holds moments of the current model
+    int64_t fit_pending_n = -1, fit_pending_iso = -1;  // shape the last densify re-laid them out for
+    float *st_grad = nullptr, *st_cnt = nullptr, *st_rad = nullptr;
+    bool plan_ok = false;
+    uint64_t plan_model_gen = 0;
+    int64_t plan_n_new = 0, plan_iso_new = 0;
+    uint32_t plan_pref[5] = {};     // keep, clone, child prefixes at n_iso; keep, clone totals
+    const float *plan_noise = nullptr;
+    float plan_log_split = 0.0f;
     std::vector<ddgs_view> views_h;
 
     // derived view table for the current options
@@ -541,6 +556,16 @@ ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, int64_t sort_n, float *images
     return DDGS_OK;
 }
 
+// Writable pointers of the model groups in flat order: the fitting optimiser
+// and the opacity reset update the caller's arrays in place (the caller
+// enables them only for writable memory).
+void fit_groups(ddgs_ctx *c, float **p)
+{
+    const ddgs_model &m = c->model;
+    const float *q[kGroups] = {m.mean, m.quat, m.log_scale, m.opacity_logit, m.feat, m.b_iso, m.B_dir};
+    for (int g = 0; g < kGroups; ++g) p[g] = const_cast<float *>(q[g]);
+}
+
 bool any_param_grad(const ddgs_grads *g)
 {
     return g->dmean || g->dquat || g->dlog_scale || g->dopacity_logit || g->dfeat || g->db_iso || g->dB_dir;
@@ -593,6 +618,9 @@ ddgs_status enqueue_backward(ddgs_ctx *c, const float *dL, const ddgs_grads *g, 
     pa.pose_part = buf<float>(c, "pose_part");
     pa.per_gaussian = per_g ? 1 : 0;
     pa.slot_cap = ra.slot_cap;
+    pa.st_grad = c->st_grad;
+    pa.st_cnt = c->st_cnt;
+    pa.st_rad = c->st_rad;
     HIP_TRY(c, launch_project_bwd(pa, s));
     if (g->db_iso || g->dB_dir) HIP_TRY(c, launch_basis_grad(pa.m, pa.ubuf, buf<float>(c, "basis_part"), s));
     const int n_waves = ((n + 255) / 256) * 4;
@@ -787,6 +815,15 @@ ddgs_status ddgs_set_model(ddgs_ctx *c, const ddgs_model *m)
     const bool shape_changed = !c->has_model || c->model.n != m->n || c->model.n_iso != m->n_iso ||
                                c->model.k != m->k || c->model.L != m->L || c->model.radiosity != m->radiosity;
     const bool ptr_changed = !c->has_model || std::memcmp(&c->model, m, sizeof(*m)) != 0;
+    // the fitting moments survive only the model a densification produced
+    const bool adopt = c->fit_live && c->fit_pending_n == m->n && c->fit_pending_iso == m->n_iso &&
+                       c->has_model && c->model.k == m->k && c->model.L == m->L;
+    if (!adopt) {
+        c->fit_reset = true;
+        c->fit_live = false;
+    }
+    c->fit_pending_n = c->fit_pending_iso = -1;
+    c->plan_ok = false;
     c->model = *m;
     c->has_model = true;
     ++c->model_gen;
@@ -875,6 +912,222 @@ ddgs_status ddgs_get_views(ddgs_ctx *c, ddgs_view *out, int nv)
         }
     }
     std::copy(c->views_h.begin(), c->views_h.end(), out);
+    return DDGS_OK;
+}
+
+void ddgs_default_fit_options(ddgs_fit_opts *o, float extent)
+{
+    if (!o) return;
+    *o = ddgs_fit_opts{};
+    o->lr_mean_init = 1.6e-4f * extent;
+    o->lr_mean_final = 1.6e-6f * extent;
+    o->lr_mean_steps = 30000;
+    o->lr_quat = 1e-3f;
+    o->lr_log_scale = 5e-3f;
+    o->lr_opacity = 5e-2f;
+    o->lr_feat = 2.5e-3f;
+    o->lr_b_iso = 1.25e-4f;
+    o->lr_B_dir = 1.25e-4f;
+    o->beta1 = 0.9f;
+    o->beta2 = 0.999f;
+    o->eps = 1e-15f;
+}
+
+ddgs_status ddgs_set_fit_optimizer(ddgs_ctx *c, const ddgs_fit_opts *o)
+{
+    if (!c) return DDGS_ERR_INVALID_ARG;
+    if (o) {
+        const float rates[] = {o->lr_mean_init, o->lr_mean_final, o->lr_quat, o->lr_log_scale, o->lr_opacity,
+                               o->lr_feat, o->lr_b_iso, o->lr_B_dir};
+        bool ok = o->lr_mean_steps >= 1 && o->beta1 >= 0.0f && o->beta1 < 1.0f && o->beta2 >= 0.0f &&
+                  o->beta2 < 1.0f && o->eps > 0.0f && std::isfinite(o->eps) && o->lr_mean_init > 0.0f &&
+                  o->lr_mean_final > 0.0f;
+        for (float r : rates) ok = ok && r >= 0.0f && std::isfinite(r);
+        if (!ok)
+            return fail(c, DDGS_ERR_INVALID_ARG,
+                        "need finite rates >= 0 (position rates > 0), steps >= 1, 0 <= beta < 1, eps > 0");
+        FitCfg f{};
+        f.lr_mean0 = o->lr_mean_init;
+        f.lr_mean1 = o->lr_mean_final;
+        f.lr_steps = o->lr_mean_steps;
+        const float lr[kGroups] = {0.0f, o->lr_quat, o->lr_log_scale, o->lr_opacity, o->lr_feat, o->lr_b_iso, o->lr_B_dir};
+        for (int g = 0; g < kGroups; ++g) f.lr[g] = lr[g];
+        f.beta1 = o->beta1;
+        f.beta2 = o->beta2;
+        f.eps = o->eps;
+        c->fit = f;
+    }
+    c->fit_on = o != nullptr;
+    c->fit_reset = true;
+    c->fit_live = false;
+    drop_graph(c);
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_set_densify_stats(ddgs_ctx *c, float *grad_accum, float *count, float *max_radius)
+{
+    if (!c) return DDGS_ERR_INVALID_ARG;
+    const bool any = grad_accum || count || max_radius;
+    if (any && !(grad_accum && count && max_radius))
+        return fail(c, DDGS_ERR_INVALID_ARG, "pass all three statistics arrays or none");
+    c->st_grad = grad_accum;
+    c->st_cnt = count;
+    c->st_rad = max_radius;
+    c->plan_ok = false;
+    drop_graph(c);
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_densify_plan(ddgs_ctx *c, const ddgs_densify_opts *o, const float *noise, int64_t *n_new,
+                              int64_t *n_iso_new)
+{
+    if (!c || !o || !n_new || !n_iso_new) return DDGS_ERR_INVALID_ARG;
+    if (!c->has_model) return fail(c, DDGS_ERR_STATE, "no model");
+    if (!c->st_grad) return fail(c, DDGS_ERR_STATE, "no densification statistics (ddgs_set_densify_stats)");
+    const int n = (int)c->model.n, n_iso = (int)c->model.n_iso;
+    if (n > 0 && !noise) return fail(c, DDGS_ERR_INVALID_ARG, "null noise");
+    if (!(o->grad_threshold >= 0.0f && std::isfinite(o->grad_threshold) && o->dense_scale > 0.0f &&
+          std::isfinite(o->dense_scale) && o->min_opacity > 0.0f && o->min_opacity < 1.0f &&
+          std::isfinite(o->max_world_scale) && std::isfinite(o->max_screen_radius) && o->split_factor > 1.0f &&
+          std::isfinite(o->split_factor)))
+        return fail(c, DDGS_ERR_INVALID_ARG,
+                    "need grad_threshold >= 0, dense_scale > 0, 0 < min_opacity < 1, split_factor > 1, finite bounds");
+    if (c->model.radiosity == DDGS_RADIOSITY_ENTANGLED && n_iso != 0)
+        return fail(c, DDGS_ERR_STATE, "entangled model with an isotropic set");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const float inf = std::numeric_limits<float>::infinity();
+    DensifyTh th;
+    th.grad = o->grad_threshold;
+    th.log_dense = (float)std::log((double)o->dense_scale);
+    th.logit_min_op = (float)(std::log((double)o->min_opacity) - std::log1p(-(double)o->min_opacity));
+    th.log_world = o->max_world_scale > 0.0f ? (float)std::log((double)o->max_world_scale) : inf;
+    th.screen = o->max_screen_radius > 0.0f ? o->max_screen_radius : inf;
+    th.log_split = (float)std::log((double)o->split_factor);
+    uint32_t *keep, *clone, *child, *keep_ex, *clone_ex, *child_ex;
+    uint64_t *tot;
+    const size_t nn = (size_t)std::max(n, 1);
+    DDGS_TRY(ensure_t(c, "dn_keep", nn, &keep));
+    DDGS_TRY(ensure_t(c, "dn_clone", nn, &clone));
+    DDGS_TRY(ensure_t(c, "dn_child", nn, &child));
+    DDGS_TRY(ensure_t(c, "dn_keep_ex", nn, &keep_ex));
+    DDGS_TRY(ensure_t(c, "dn_clone_ex", nn, &clone_ex));
+    DDGS_TRY(ensure_t(c, "dn_child_ex", nn, &child_ex));
+    DDGS_TRY(ensure_t(c, "dn_tot", 4, &tot));
+    SortWs ws;
+    DDGS_TRY(debug_ws(c, n, &ws));
+    hipStream_t s = c->stream;
+    HIP_TRY(c, launch_densify_plan(n, c->model.log_scale, c->model.opacity_logit, c->st_grad, c->st_cnt, c->st_rad,
+                                   th, keep, clone, child, s));
+    HIP_TRY(c, launch_exclusive_scan(keep, nullptr, keep_ex, n, ws, tot, s));
+    HIP_TRY(c, launch_exclusive_scan(clone, nullptr, clone_ex, n, ws, tot + 1, s));
+    HIP_TRY(c, launch_exclusive_scan(child, nullptr, child_ex, n, ws, tot + 2, s));
+    uint64_t t_h[3] = {0, 0, 0};
+    uint32_t at_iso[3] = {0, 0, 0};
+    HIP_TRY(c, hipMemcpyAsync(t_h, tot, sizeof(t_h), hipMemcpyDeviceToHost, s));
+    if (n_iso < n) {
+        HIP_TRY(c, hipMemcpyAsync(&at_iso[0], keep_ex + n_iso, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipMemcpyAsync(&at_iso[1], clone_ex + n_iso, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipMemcpyAsync(&at_iso[2], child_ex + n_iso, 4, hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(c, hipStreamSynchronize(s));
+    if (n_iso == n)
+        for (int q = 0; q < 3; ++q) at_iso[q] = (uint32_t)t_h[q];
+    const int64_t total = (int64_t)(t_h[0] + t_h[1] + t_h[2]);
+    if (total >= ((int64_t)1 << 31)) return fail(c, DDGS_ERR_UNSUPPORTED, "densified model too large");
+    c->plan_pref[0] = at_iso[0];
+    c->plan_pref[1] = at_iso[1];
+    c->plan_pref[2] = at_iso[2];
+    c->plan_pref[3] = (uint32_t)t_h[0];
+    c->plan_pref[4] = (uint32_t)t_h[1];
+    c->plan_n_new = total;
+    c->plan_iso_new = (int64_t)at_iso[0] + at_iso[1] + at_iso[2];
+    c->plan_noise = noise;
+    c->plan_log_split = th.log_split;
+    c->plan_model_gen = c->model_gen;
+    c->plan_ok = true;
+    *n_new = c->plan_n_new;
+    *n_iso_new = c->plan_iso_new;
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_densify_apply(ddgs_ctx *c, const ddgs_params *out)
+{
+    if (!c || !out) return DDGS_ERR_INVALID_ARG;
+    if (!c->plan_ok || c->plan_model_gen != c->model_gen)
+        return fail(c, DDGS_ERR_STATE, "ddgs_densify_apply needs a ddgs_densify_plan of the current model");
+    float *dst[kGroups] = {out->mean, out->quat, out->log_scale, out->opacity_logit, out->feat, out->b_iso, out->B_dir};
+    for (int g = 0; g < kGroups; ++g) {
+        if (!dst[g] && (g >= 5 || c->plan_n_new > 0)) return fail(c, DDGS_ERR_INVALID_ARG, "null output array");
+        if (((uintptr_t)dst[g]) % 4 != 0) return fail(c, DDGS_ERR_INVALID_ARG, "arrays must be 4-byte aligned");
+    }
+    HIP_TRY(c, hipSetDevice(c->device));
+    drop_graph(c);
+    const ddgs_model &m = c->model;
+    const int kl = kl_of(m.L);
+    DensifyApplyArgs a{};
+    a.n = (int)m.n;
+    a.n_iso = (int)m.n_iso;
+    a.k = m.k;
+    a.kl = kl;
+    a.n_new = c->plan_n_new;
+    const float *src[5] = {m.mean, m.quat, m.log_scale, m.opacity_logit, m.feat};
+    for (int g = 0; g < 5; ++g) {
+        a.src[g] = src[g];
+        a.dst[g] = dst[g];
+    }
+    a.keep = buf<uint32_t>(c, "dn_keep");
+    a.clone = buf<uint32_t>(c, "dn_clone");
+    a.child = buf<uint32_t>(c, "dn_child");
+    a.keep_ex = buf<uint32_t>(c, "dn_keep_ex");
+    a.clone_ex = buf<uint32_t>(c, "dn_clone_ex");
+    a.child_ex = buf<uint32_t>(c, "dn_child_ex");
+    a.k_iso = c->plan_pref[0];
+    a.c_iso = c->plan_pref[1];
+    a.h_iso = c->plan_pref[2];
+    a.k_tot = c->plan_pref[3];
+    a.c_tot = c->plan_pref[4];
+    a.noise = c->plan_noise;
+    a.log_split = c->plan_log_split;
+    const bool moments = c->fit_live && buf<float>(c, "fit_mv") != nullptr;
+    if (moments) {
+        const int64_t P_old = fit_param_count(m.n, m.k, kl), P_new = fit_param_count(c->plan_n_new, m.k, kl);
+        float *mv2;
+        DDGS_TRY(ensure_t(c, "fit_mv_next", (size_t)2 * P_new, &mv2));
+        a.m_old = buf<float>(c, "fit_mv");
+        a.v_old = a.m_old + P_old;
+        a.m_new = mv2;
+        a.v_new = mv2 + P_new;
+    }
+    HIP_TRY(c, launch_densify_apply(a, c->stream));
+    const size_t nb = sizeof(float) * m.k, nB = sizeof(float) * kl * m.k;
+    if (out->b_iso != m.b_iso) HIP_TRY(c, hipMemcpyAsync(out->b_iso, m.b_iso, nb, hipMemcpyDeviceToDevice, c->stream));
+    if (out->B_dir != m.B_dir) HIP_TRY(c, hipMemcpyAsync(out->B_dir, m.B_dir, nB, hipMemcpyDeviceToDevice, c->stream));
+    if (moments) {
+        std::swap(c->bufs["fit_mv"], c->bufs["fit_mv_next"]);
+        c->fit_pending_n = c->plan_n_new;
+        c->fit_pending_iso = c->plan_iso_new;
+    }
+    c->plan_ok = false;
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_fit_reset_opacity(ddgs_ctx *c, float max_alpha)
+{
+    if (!c) return DDGS_ERR_INVALID_ARG;
+    if (!c->has_model) return fail(c, DDGS_ERR_STATE, "no model");
+    if (!(max_alpha > 0.0f && max_alpha < 1.0f)) return fail(c, DDGS_ERR_INVALID_ARG, "need 0 < max_alpha < 1");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const float cap = (float)(std::log((double)max_alpha) - std::log1p(-(double)max_alpha));
+    float *p[kGroups];
+    fit_groups(c, p);
+    float *mm = nullptr, *vv = nullptr;
+    if (c->fit_live && buf<float>(c, "fit_mv")) {
+        int64_t off[kGroups + 1];
+        fit_offsets(c->model.n, c->model.k, kl_of(c->model.L), off);
+        mm = buf<float>(c, "fit_mv") + off[3];
+        vv = buf<float>(c, "fit_mv") + off[kGroups] + off[3];
+    }
+    HIP_TRY(c, launch_opacity_reset(p[3], (int)c->model.n, cap, mm, vv, c->stream));
     return DDGS_OK;
 }
 
@@ -1024,6 +1277,8 @@ ddgs_status ddgs_step_capture(ddgs_ctx *c, int kind, const float *target, float 
     if (!c->stream) return fail(c, DDGS_ERR_INVALID_ARG, "capture needs a non-default stream");
     if (c->adam_on && !g->dpose) return fail(c, DDGS_ERR_INVALID_ARG, "the pose optimiser needs grads->dpose");
     if (c->adam_on && c->views_h.size() > 256) return fail(c, DDGS_ERR_UNSUPPORTED, "the pose optimiser takes up to 256 views");
+    if (c->fit_on && !(g->dmean && g->dquat && g->dlog_scale && g->dopacity_logit && g->dfeat && g->db_iso && g->dB_dir))
+        return fail(c, DDGS_ERR_INVALID_ARG, "the fitting optimiser needs every parameter gradient");
     drop_graph(c);
     DDGS_TRY(ensure_static(c));
     if (c->adam_on) {
@@ -1032,6 +1287,15 @@ ddgs_status ddgs_step_capture(ddgs_ctx *c, int kind, const float *target, float 
         DDGS_TRY(ensure_t(c, "adam_state", (size_t)12 * c->views_h.size(), &st_));
         DDGS_TRY(ensure_t(c, "adam_step", 1, &sp_));
         c->adam_reset = true;
+    }
+    if (c->fit_on) {
+        float *mv_;
+        uint32_t *fs_;
+        const int64_t P = fit_param_count(c->model.n, c->model.k, kl_of(c->model.L));
+        const bool had = buf<float>(c, "fit_mv") != nullptr;
+        DDGS_TRY(ensure_t(c, "fit_mv", (size_t)2 * P, &mv_));
+        DDGS_TRY(ensure_t(c, "fit_step", 1, &fs_));
+        if (!had || !c->fit_live) c->fit_reset = true;
     }
     int64_t cap = c->opt.capacity;
     if (cap <= 0) {
@@ -1055,6 +1319,19 @@ ddgs_status ddgs_step_capture(ddgs_ctx *c, int kind, const float *target, float 
         hipError_t ea = launch_pose_adam(buf<ViewDev>(c, "views"), (int)c->views_h.size(), g->dpose,
                                          buf<float>(c, "adam_state"), buf<uint32_t>(c, "adam_step"), c->adam, c->stream);
         if (ea != hipSuccess) st = fail(c, DDGS_ERR_HIP, std::string("pose optimiser: ") + hipGetErrorString(ea));
+    }
+    if (st == DDGS_OK && c->fit_on) {
+        FitArgs fa{};
+        const float *gs[kGroups] = {g->dmean, g->dquat, g->dlog_scale, g->dopacity_logit, g->dfeat, g->db_iso, g->dB_dir};
+        fit_groups(c, fa.p);
+        for (int q = 0; q < kGroups; ++q) fa.g[q] = gs[q];
+        fit_offsets(c->model.n, c->model.k, kl_of(c->model.L), fa.off);
+        fa.m = buf<float>(c, "fit_mv");
+        fa.v = fa.m + fa.off[kGroups];
+        fa.step = buf<uint32_t>(c, "fit_step");
+        fa.cfg = c->fit;
+        hipError_t ea = launch_fit_adam(fa, c->num_cu, c->stream);
+        if (ea != hipSuccess) st = fail(c, DDGS_ERR_HIP, std::string("fitting optimiser: ") + hipGetErrorString(ea));
     }
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(c->stream, &graph);
@@ -1084,6 +1361,13 @@ ddgs_status ddgs_step_launch(ddgs_ctx *c)
         HIP_TRY(c, hipMemsetAsync(buf<float>(c, "adam_state"), 0, sizeof(float) * 12 * c->views_h.size(), c->stream));
         HIP_TRY(c, hipMemsetAsync(buf<uint32_t>(c, "adam_step"), 0, sizeof(uint32_t), c->stream));
         c->adam_reset = false;
+    }
+    if (c->fit_on && c->fit_reset) {
+        const int64_t P = fit_param_count(c->model.n, c->model.k, kl_of(c->model.L));
+        HIP_TRY(c, hipMemsetAsync(buf<float>(c, "fit_mv"), 0, sizeof(float) * 2 * P, c->stream));
+        HIP_TRY(c, hipMemsetAsync(buf<uint32_t>(c, "fit_step"), 0, sizeof(uint32_t), c->stream));
+        c->fit_reset = false;
+        c->fit_live = true;
     }
     HIP_TRY(c, hipGraphLaunch(c->exec, c->stream));
     c->M = -1;  // unknown until ddgs_check
@@ -1164,6 +1448,15 @@ ddgs_status ddgs_debug_keep_unsorted(ddgs_ctx *c, int keep)
 ddgs_status ddgs_debug_copy(ddgs_ctx *c, int what, void *host, size_t bytes)
 {
     if (!c || !host) return DDGS_ERR_INVALID_ARG;
+    if (what == DDGS_DBG_FIT_MOMENTS) {
+        if (!c->fit_live) return fail(c, DDGS_ERR_STATE, "no fitting moments for the current model");
+        const size_t need = sizeof(float) * 2 * fit_param_count(c->model.n, c->model.k, kl_of(c->model.L));
+        if (bytes < need) return fail(c, DDGS_ERR_INVALID_ARG, "buffer too small: need " + std::to_string(need));
+        HIP_TRY(c, hipSetDevice(c->device));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        HIP_TRY(c, hipMemcpy(host, buf<void>(c, "fit_mv"), need, hipMemcpyDeviceToHost));
+        return DDGS_OK;
+    }
     if (!c->rendered) return fail(c, DDGS_ERR_STATE, "nothing rendered");
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, hipStreamSynchronize(c->stream));

@@ -25,6 +25,14 @@ struct ViewDev {
     int64_t pix_base;      // first pixel of this view in the concatenated image
 };
 
+// Rotation matrix of the unit quaternion (w, x, y, z), row-major.
+__device__ __forceinline__ void quat_rot(float w, float x, float y, float z, float *R)
+{
+    R[0] = 1.0f - 2.0f * (y * y + z * z); R[1] = 2.0f * (x * y - w * z); R[2] = 2.0f * (x * z + w * y);
+    R[3] = 2.0f * (x * y + w * z); R[4] = 1.0f - 2.0f * (x * x + z * z); R[5] = 2.0f * (y * z - w * x);
+    R[6] = 2.0f * (x * z - w * y); R[7] = 2.0f * (y * z + w * x); R[8] = 1.0f - 2.0f * (x * x + y * y);
+}
+
 struct RenderOpts {
     float kappa, kappa2, dilation, t_min, z_near, sigma_max;
     int32_t tile_w, tile_h;
@@ -180,6 +188,9 @@ struct ProjBwdArgs {
     float *pose_part;   // [V][n_waves][9]
     int per_gaussian;   // 0: pose only
     uint32_t slot_cap;  // number of gradient slots (entries beyond are ignored)
+    // densification statistics, [n] each (NULL: off): norm of the 2D-mean
+    // gradient in normalised device units, visible views, largest radius (px)
+    float *st_grad, *st_cnt, *st_rad;
 };
 hipError_t launch_project_bwd(const ProjBwdArgs &a, hipStream_t s);
 // d b_iso, d B_dir: per-wave 16 x 32 MFMA tiles in part, then an FP64 sum
@@ -279,6 +290,54 @@ struct AdamCfg {
 };
 hipError_t launch_pose_adam(ViewDev *views, int V, const float *dpose, float *state, uint32_t *step,
                             const AdamCfg &cfg, hipStream_t s);
+
+// fit.hip -- the fitting loop: fused Adam over every parameter group,
+// densification and the opacity reset.  The flat parameter index runs over
+// the groups in model order: mean [3][n], quat [4][n], log_scale [3][n],
+// opacity_logit [n], feat [k][n], b_iso [k], B_dir [k_L][k].
+constexpr int kGroups = 7;
+struct FitCfg {
+    float lr_mean0, lr_mean1;  // position rate, log-linear decay over lr_steps steps
+    int lr_steps;
+    float lr[kGroups];         // rates of the other groups (lr[0] unused)
+    float beta1, beta2, eps;
+};
+struct FitArgs {
+    float *p[kGroups];
+    const float *g[kGroups];
+    int64_t off[kGroups + 1];  // flat offsets of the groups
+    float *m, *v;              // moments [off[7]] each
+    uint32_t *step;            // completed steps
+    FitCfg cfg;
+};
+int64_t fit_param_count(int64_t n, int k, int kl);
+void fit_offsets(int64_t n, int k, int kl, int64_t *off);
+// one Adam step, then the step count is raised (two launches)
+hipError_t launch_fit_adam(const FitArgs &a, int num_cu, hipStream_t s);
+
+struct DensifyTh {
+    float grad, log_dense, logit_min_op, log_world, screen, log_split;  // +inf: bound off
+};
+// per Gaussian: keep (0/1), kept clone (0/1), kept children (0/2)
+hipError_t launch_densify_plan(int n, const float *log_scale, const float *opacity, const float *acc,
+                               const float *cnt, const float *rad, const DensifyTh &th, uint32_t *keep,
+                               uint32_t *clone, uint32_t *child, hipStream_t s);
+struct DensifyApplyArgs {
+    int n, n_iso, k, kl;
+    int64_t n_new;
+    const float *src[5];   // mean, quat, log_scale, opacity_logit, feat of the current model
+    float *dst[5];         // the same groups of the new model
+    const uint32_t *keep, *clone, *child;           // plan
+    const uint32_t *keep_ex, *clone_ex, *child_ex;  // their exclusive prefix sums
+    uint32_t k_iso, c_iso, h_iso, k_tot, c_tot;     // prefixes at n_iso and totals
+    const float *noise;    // [n][2][3]
+    float log_split;
+    const float *m_old, *v_old;  // moments of the current model (NULL: none)
+    float *m_new, *v_new;
+};
+hipError_t launch_densify_apply(const DensifyApplyArgs &a, hipStream_t s);
+// opacity_logit = min(opacity_logit, cap), opacity moments zeroed (m, v may be NULL)
+hipError_t launch_opacity_reset(float *opacity, int n, float cap, float *m, float *v, hipStream_t s);
 
 // loss.hip
 struct LossArgs {

@@ -76,14 +76,6 @@ __device__ __forceinline__ void sh_basis_grad(float x, float y, float z, const f
 
 __device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
 
-// Rotation matrix of the unit quaternion (w, x, y, z), row-major.
-__device__ __forceinline__ void quat_rot(float w, float x, float y, float z, float *R)
-{
-    R[0] = 1.0f - 2.0f * (y * y + z * z); R[1] = 2.0f * (x * y - w * z); R[2] = 2.0f * (x * z + w * y);
-    R[3] = 2.0f * (x * y + w * z); R[4] = 1.0f - 2.0f * (x * x + z * z); R[5] = 2.0f * (y * z - w * x);
-    R[6] = 2.0f * (x * z - w * y); R[7] = 2.0f * (y * z + w * x); R[8] = 1.0f - 2.0f * (x * x + y * y);
-}
-
 // Geometry of one (view, Gaussian) pair: source-frame mean and covariance,
 // the Jacobian of the pinhole map at the mean, the projected covariance with
 // the low-pass dilation, its inverse (the conic) and the projected mean.
@@ -313,6 +305,7 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
     float gmu[3] = {0.f, 0.f, 0.f};
     float GSw[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float galpha = 0.0f, zsum = 0.0f;
+    float st_grad = 0.0f, st_cnt = 0.0f, st_rad = 0.0f;  // densification statistics
     float u[KL];
 #pragma unroll
     for (int r = 0; r < KL; ++r) u[r] = 0.0f;
@@ -369,6 +362,16 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
                 g7[2] = -0.5f * al * g7[2];
                 g7[3] = -al * g7[3];
                 g7[4] = -0.5f * al * g7[4];
+            }
+            if (a.st_grad) {
+                // visible in this view: 2D-mean gradient in normalised device
+                // units and the projected radius kappa sqrt(lambda_max)
+                const float gx = g7[0] * (0.5f * (float)V.W), gy = g7[1] * (0.5f * (float)V.H);
+                st_grad += sqrtf(gx * gx + gy * gy);
+                st_cnt += 1.0f;
+                const float mid = 0.5f * (g.a + g.c);
+                const float lam = mid + sqrtf(fmaxf(mid * mid - (g.a * g.c - g.b * g.b), 0.0f));
+                st_rad = fmaxf(st_rad, a.o.kappa * sqrtf(lam));
             }
             // conic = inverse of the projected covariance: dL/dS2 = -A Gbar A
             const float gb00 = g7[2], gb01 = 0.5f * g7[3], gb11 = g7[4];
@@ -472,6 +475,11 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
 #pragma unroll
             for (int q = 0; q < 9; ++q) a.pose_part[((size_t)v * n_waves + wave) * 9 + q] = pose[q];
         }
+    }
+    if (valid && a.st_grad) {
+        a.st_grad[i] += st_grad;
+        a.st_cnt[i] += st_cnt;
+        a.st_rad[i] = fmaxf(a.st_rad[i], st_rad);
     }
     if (!valid || !a.per_gaussian) return;
 

@@ -50,9 +50,9 @@ def test_radius_and_visibility_of_an_isotropic_gaussian():
     sigma = np.float32(2.0)
     sc.log_scale[:] = np.log(sigma)
     v = synth.view(64, 64, 1.0, 1000.0, 600.0, 0.0)
-    vis, margin, radius = fit_ref.visible_boxes(sc, v)
+    vis, stable, radius = fit_ref.visible_boxes(sc, v)
     f = 1000.0 / 1.0
-    assert vis[0] and not vis[1]
+    assert vis[0] and not vis[1] and stable.all()
     assert radius[0] == pytest.approx(3.0 * np.sqrt((f * float(sigma) / 600.0) ** 2 + 0.3), rel=1e-6)
 
 
