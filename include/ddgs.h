@@ -265,6 +265,42 @@ ddgs_status ddgs_densify_apply(ddgs_ctx *ctx, const ddgs_params *out);
  * place, and the opacity moments are zeroed. */
 ddgs_status ddgs_fit_reset_opacity(ddgs_ctx *ctx, float max_alpha);
 
+/* Initialisation by radiodensity-aware dual sampling (Sec. 3.3; level and
+ * set sizes of Sec. 4.1), in two calls.
+ * ddgs_rads_prepare reads a CT volume and finds (synchronising):
+ *   - the interface level (min + max) / 2 of the volume (*level);
+ *   - every point where that level crosses an edge between neighbouring
+ *     voxel centres, linearly interpolated -- the vertex set marching cubes
+ *     places -- in edge order ((z ny + y) nx + x) 3 + axis, axes x, y, z
+ *     (*n_crossings = M); an edge crosses when exactly one end is below the
+ *     level;
+ *   - the voxel weights floor((hu - min) / (max - min) * 65535) (float32
+ *     arithmetic) and their total (*total_weight = W).
+ * The volume may be freed after it returns.
+ * ddgs_rads_sample writes N = min(n1, M) + n2 points, device [3][N]:
+ *   - P^mc: the min(n1, M) crossings with the smallest mc_keys (device [M]
+ *     u32, random keys supplied by the caller; ties by edge order), in key
+ *     order;
+ *   - P^dw: n2 voxel centres, draw j picking the first voxel whose inclusive
+ *     weight sum exceeds dw_draws[j] (device [n2] u64, uniform in [0, W)
+ *     supplied by the caller; a draw >= W picks the last voxel).
+ * P^mc and the first n2 / 2 draws form the isotropic set, the rest the
+ * directional one: *n_iso = min(n1, M) + n2 / 2.  log_scale (device [3][N],
+ * may be NULL) receives log sqrt(mean squared distance to the three nearest
+ * other points) on every axis, the mean clamped below at 1e-7 mm^2 (the
+ * initial scales of 3D Gaussian splatting). */
+typedef struct ddgs_volume {
+    int32_t nx, ny, nz;          /* voxels; nx ny nz < 2^30                   */
+    float spacing[3];            /* voxel size along x, y, z, mm (> 0)         */
+    float origin[3];             /* world position of the centre of voxel
+                                    (0, 0, 0), mm                             */
+    const float *hu;             /* device [nz][ny][nx] radiodensity, HU      */
+} ddgs_volume;
+ddgs_status ddgs_rads_prepare(ddgs_ctx *ctx, const ddgs_volume *vol, float *level, int64_t *n_crossings,
+                              uint64_t *total_weight);
+ddgs_status ddgs_rads_sample(ddgs_ctx *ctx, int64_t n1, const uint32_t *mc_keys, int64_t n2, const uint64_t *dw_draws,
+                             float *points, float *log_scale, int64_t *n_iso);
+
 /* Test hook: radiosity c per (view, Gaussian), device [n_views][n] floats,
  * used instead of Eq. 3 (NULL restores Eq. 3).  With it the image is linear
  * in c (Eq. 1), and the backward leaves the features and bases out of the

@@ -75,15 +75,17 @@ def weighted_draws(hu, draws, spacing, origin):
     return np.asarray(origin, np.float64) + g * np.asarray(spacing, np.float64), idx
 
 
-def knn_log_scale(points, k=3):
-    """log sqrt(mean squared distance to the k nearest other points), by brute force."""
+def knn_log_scale(points, k=3, rows=None):
+    """log sqrt(mean squared distance to the k nearest other points), by brute
+    force, for every point or the given rows."""
     P = np.asarray(points, np.float64)
     n = P.shape[0]
-    out = np.empty(n)
-    for lo in range(0, n, 512):
-        d2 = ((P[lo:lo + 512, None, :] - P[None, :, :]) ** 2).sum(axis=2)
-        for r in range(d2.shape[0]):
-            d2[r, lo + r] = np.inf
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    out = np.empty(len(rows))
+    for lo in range(0, len(rows), 512):
+        rr = rows[lo:lo + 512]
+        d2 = ((P[rr, None, :] - P[None, :, :]) ** 2).sum(axis=2)
+        d2[np.arange(len(rr)), rr] = np.inf
         kk = min(k, n - 1)
         near = np.sort(d2, axis=1)[:, :kk] if kk > 0 else np.zeros((d2.shape[0], 0))
         mean = near.mean(axis=1) if kk > 0 else np.zeros(d2.shape[0])

@@ -32,7 +32,7 @@ EXPORTED = (
     "ddgs_debug_keep_unsorted", "ddgs_debug_sort_pairs", "ddgs_debug_exclusive_scan", "ddgs_debug_count_pairs",
     "ddgs_debug_pair_counts", "ddgs_enable_timing", "ddgs_stage_times", "ddgs_default_fit_options",
     "ddgs_set_fit_optimizer", "ddgs_set_densify_stats", "ddgs_densify_plan", "ddgs_densify_apply",
-    "ddgs_fit_reset_opacity")
+    "ddgs_fit_reset_opacity", "ddgs_rads_prepare", "ddgs_rads_sample")
 
 
 class ddgs_model(C.Structure):
@@ -83,6 +83,11 @@ class ddgs_densify_opts(C.Structure):
 
 class ddgs_params(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("mean", "quat", "log_scale", "opacity_logit", "feat", "b_iso", "B_dir")]
+
+
+class ddgs_volume(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("spacing", C.c_float * 3),
+                ("origin", C.c_float * 3), ("hu", C.c_void_p)]
 
 
 class DDGSError(RuntimeError):
@@ -143,6 +148,9 @@ def lib():
             "ddgs_densify_plan": ([vp, C.POINTER(ddgs_densify_opts), vp, C.POINTER(i64), C.POINTER(i64)], st),
             "ddgs_densify_apply": ([vp, C.POINTER(ddgs_params)], st),
             "ddgs_fit_reset_opacity": ([vp, C.c_float], st),
+            "ddgs_rads_prepare": ([vp, C.POINTER(ddgs_volume), C.POINTER(C.c_float), C.POINTER(i64),
+                                   C.POINTER(C.c_uint64)], st),
+            "ddgs_rads_sample": ([vp, i64, vp, i64, vp, vp, vp, C.POINTER(i64)], st),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -239,6 +247,19 @@ def ddgs_densify_apply(ctx, params):
 
 def ddgs_fit_reset_opacity(ctx, max_alpha):
     _check(lib().ddgs_fit_reset_opacity(ctx, float(max_alpha)), ctx)
+
+
+def ddgs_rads_prepare(ctx, vol):
+    level, m, w = C.c_float(), C.c_int64(), C.c_uint64()
+    _check(lib().ddgs_rads_prepare(ctx, C.byref(vol), C.byref(level), C.byref(m), C.byref(w)), ctx)
+    return level.value, m.value, w.value
+
+
+def ddgs_rads_sample(ctx, n1, keys_ptr, n2, draws_ptr, points_ptr, log_scale_ptr):
+    n_iso = C.c_int64()
+    _check(lib().ddgs_rads_sample(ctx, int(n1), keys_ptr, int(n2), draws_ptr, points_ptr, log_scale_ptr,
+                                  C.byref(n_iso)), ctx)
+    return n_iso.value
 
 
 def ddgs_get_views(ctx, n):

@@ -63,6 +63,12 @@ struct ddgs_ctx {
     uint32_t plan_pref[5] = {};     // keep, clone, child prefixes at n_iso; keep, clone totals
     const float *plan_noise = nullptr;
     float plan_log_split = 0.0f;
+
+    // radiodensity-aware dual sampling between prepare and sample
+    bool rads_ok = false;
+    RadsVol rads_vol{};
+    int64_t rads_m = 0;
+    uint64_t rads_w = 0;
     std::vector<ddgs_view> views_h;
 
     // derived view table for the current options
@@ -1128,6 +1134,94 @@ ddgs_status ddgs_fit_reset_opacity(ddgs_ctx *c, float max_alpha)
         vv = buf<float>(c, "fit_mv") + off[kGroups] + off[3];
     }
     HIP_TRY(c, launch_opacity_reset(p[3], (int)c->model.n, cap, mm, vv, c->stream));
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_rads_prepare(ddgs_ctx *c, const ddgs_volume *vol, float *level, int64_t *n_crossings,
+                              uint64_t *total_weight)
+{
+    if (!c || !vol || !level || !n_crossings || !total_weight) return DDGS_ERR_INVALID_ARG;
+    c->rads_ok = false;
+    const int64_t n = (int64_t)vol->nx * vol->ny * vol->nz;
+    if (vol->nx < 1 || vol->ny < 1 || vol->nz < 1 || n >= ((int64_t)1 << 30))
+        return fail(c, DDGS_ERR_INVALID_ARG, "need 1 <= nx, ny, nz and nx ny nz < 2^30");
+    for (int a = 0; a < 3; ++a)
+        if (!(vol->spacing[a] > 0.0f) || !std::isfinite(vol->spacing[a]) || !std::isfinite(vol->origin[a]))
+            return fail(c, DDGS_ERR_INVALID_ARG, "need finite spacing > 0 and a finite origin");
+    if (!vol->hu || ((uintptr_t)vol->hu) % 4 != 0) return fail(c, DDGS_ERR_INVALID_ARG, "null or unaligned volume");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    RadsVol v{vol->nx, vol->ny, vol->nz, vol->spacing[0], vol->spacing[1], vol->spacing[2],
+              vol->origin[0], vol->origin[1], vol->origin[2], vol->hu};
+    const int64_t nb = rads_minmax_blocks(n, c->num_cu), nb64 = rads_scan64_blocks(n);
+    float2 *part;
+    float *mm;
+    uint32_t *cnt, *off;
+    uint64_t *tot, *bsum, *cdf;
+    DDGS_TRY(ensure_t(c, "rads_part", (size_t)nb, &part));
+    DDGS_TRY(ensure_t(c, "rads_mm", 4, &mm));
+    DDGS_TRY(ensure_t(c, "rads_cnt", (size_t)n, &cnt));
+    DDGS_TRY(ensure_t(c, "rads_off", (size_t)n, &off));
+    DDGS_TRY(ensure_t(c, "rads_tot", 1, &tot));
+    DDGS_TRY(ensure_t(c, "rads_bsum", (size_t)nb64 + 1, &bsum));
+    DDGS_TRY(ensure_t(c, "rads_cdf", (size_t)n, &cdf));
+    SortWs ws;
+    DDGS_TRY(debug_ws(c, n, &ws));
+    HIP_TRY(c, launch_rads_level(v, part, nb, mm, s));
+    HIP_TRY(c, launch_mc_count(v, mm, cnt, s));
+    HIP_TRY(c, launch_exclusive_scan(cnt, nullptr, off, n, ws, tot, s));
+    HIP_TRY(c, launch_rads_cdf(v, mm, bsum, cdf, s));
+    uint64_t m_h = 0, w_h = 0;
+    float mm_h[3] = {0.0f, 0.0f, 0.0f};
+    HIP_TRY(c, hipMemcpyAsync(&m_h, tot, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(&w_h, bsum + nb64, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(mm_h, mm, sizeof(mm_h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    float *pts;
+    DDGS_TRY(ensure_t(c, "rads_pts", (size_t)std::max<uint64_t>(3 * m_h, 1), &pts));
+    HIP_TRY(c, launch_mc_emit(v, mm, off, pts, (int64_t)m_h, s));
+    v.hu = nullptr;  // not read after this call
+    c->rads_vol = v;
+    c->rads_m = (int64_t)m_h;
+    c->rads_w = w_h;
+    c->rads_ok = true;
+    *level = mm_h[2];
+    *n_crossings = (int64_t)m_h;
+    *total_weight = w_h;
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_rads_sample(ddgs_ctx *c, int64_t n1, const uint32_t *mc_keys, int64_t n2, const uint64_t *dw_draws,
+                             float *points, float *log_scale, int64_t *n_iso)
+{
+    if (!c || !n_iso) return DDGS_ERR_INVALID_ARG;
+    if (!c->rads_ok) return fail(c, DDGS_ERR_STATE, "ddgs_rads_sample needs ddgs_rads_prepare");
+    if (n1 < 0 || n2 < 0) return fail(c, DDGS_ERR_INVALID_ARG, "need n1, n2 >= 0");
+    const int64_t M = c->rads_m, n1e = std::min(n1, M), N = n1e + n2;
+    if (N >= ((int64_t)1 << 31)) return fail(c, DDGS_ERR_INVALID_ARG, "too many points");
+    if (N > 0 && !points) return fail(c, DDGS_ERR_INVALID_ARG, "null points");
+    if (n1e > 0 && !mc_keys) return fail(c, DDGS_ERR_INVALID_ARG, "null mc_keys");
+    if (n2 > 0 && !dw_draws) return fail(c, DDGS_ERR_INVALID_ARG, "null dw_draws");
+    if (n2 > 0 && c->rads_w == 0) return fail(c, DDGS_ERR_STATE, "the volume has no weight (constant radiodensity)");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    if (n1e > 0) {
+        uint32_t *k0, *k1, *v0, *v1;
+        DDGS_TRY(ensure_t(c, "rads_k0", (size_t)M, &k0));
+        DDGS_TRY(ensure_t(c, "rads_k1", (size_t)M, &k1));
+        DDGS_TRY(ensure_t(c, "rads_v0", (size_t)M, &v0));
+        DDGS_TRY(ensure_t(c, "rads_v1", (size_t)M, &v1));
+        SortWs ws;
+        DDGS_TRY(debug_ws(c, M, &ws));
+        HIP_TRY(c, hipMemcpyAsync(k0, mc_keys, sizeof(uint32_t) * M, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(c, launch_iota(v0, M, s));
+        bool in_k1 = false;
+        HIP_TRY(c, radix_sort_pairs(k0, v0, k1, v1, M, nullptr, 32, ws, &in_k1, s));
+        HIP_TRY(c, launch_rads_gather(buf<float>(c, "rads_pts"), M, in_k1 ? v1 : v0, n1e, points, N, s));
+    }
+    HIP_TRY(c, launch_rads_draws(c->rads_vol, buf<uint64_t>(c, "rads_cdf"), dw_draws, n2, points, N, n1e, s));
+    if (log_scale) HIP_TRY(c, launch_knn3(points, N, log_scale, s));
+    *n_iso = n1e + n2 / 2;
     return DDGS_OK;
 }
 

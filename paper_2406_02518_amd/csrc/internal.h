@@ -339,6 +339,28 @@ hipError_t launch_densify_apply(const DensifyApplyArgs &a, hipStream_t s);
 // opacity_logit = min(opacity_logit, cap), opacity moments zeroed (m, v may be NULL)
 hipError_t launch_opacity_reset(float *opacity, int n, float cap, float *m, float *v, hipStream_t s);
 
+// rads.hip -- radiodensity-aware dual sampling
+struct RadsVol {
+    int nx, ny, nz;
+    float sx, sy, sz;  // voxel size, mm
+    float ox, oy, oz;  // centre of voxel (0, 0, 0), mm
+    const float *hu;   // [nz][ny][nx]
+};
+int64_t rads_minmax_blocks(int64_t n, int num_cu);
+int64_t rads_scan64_blocks(int64_t n);
+// mm[0..2] = min, max, level (min + max) / 2
+hipError_t launch_rads_level(const RadsVol &v, float2 *part, int64_t nb, float *mm, hipStream_t s);
+hipError_t launch_mc_count(const RadsVol &v, const float *mm, uint32_t *cnt, hipStream_t s);
+hipError_t launch_mc_emit(const RadsVol &v, const float *mm, const uint32_t *off, float *pts, int64_t M, hipStream_t s);
+// cdf[i]: inclusive sum of the 16-bit weights; bsum [blocks + 1], bsum[blocks] = total
+hipError_t launch_rads_cdf(const RadsVol &v, const float *mm, uint64_t *bsum, uint64_t *cdf, hipStream_t s);
+hipError_t launch_iota(uint32_t *p, int64_t n, hipStream_t s);
+hipError_t launch_rads_gather(const float *src, int64_t M, const uint32_t *idx, int64_t n1, float *out, int64_t N,
+                              hipStream_t s);
+hipError_t launch_rads_draws(const RadsVol &v, const uint64_t *cdf, const uint64_t *draws, int64_t n2, float *out,
+                             int64_t N, int64_t first, hipStream_t s);
+hipError_t launch_knn3(const float *pts, int64_t N, float *ls, hipStream_t s);
+
 // loss.hip
 struct LossArgs {
     const ViewDev *views;
