@@ -148,7 +148,36 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
         float T = 1.0f, C = 0.0f;
         uint32_t last = I.b;
         uint32_t n_eval = 0, n_contrib = 0;
-        bool done = !inside;
+        // the cut-off test with the lane's state folded in: -1 once the lane
+        // has stopped (or lies outside the image), so that a hit is one
+        // compare and its wave ballot costs no vector instruction
+        float k2e = inside ? k2 : -1.0f;
+        // one entry: when any lane hits, the whole wave runs it without
+        // branches; lanes that miss keep their state
+        auto entry = [&](const float4 r0, const float4 r1, uint32_t pos) {
+            const float dx = __fsub_rn(fpx, r0.x), dy = __fsub_rn(fpy, r0.y);
+            const float d2 = maha2(dx, dy, r0.z, r0.w, r1.x);
+            bool hit = d2 <= k2e;
+            if (wave_any_mask(hit) != 0ull) {
+                const float G = falloff(d2);
+                const float s = clamp_opacity(__fmul_rn(r1.y, G), smax);
+                const float om = __fsub_rn(1.0f, s);
+                if constexpr (!SPLIT) {
+                    // early termination (t_min > 0 runs unsplit): the lane
+                    // stops before this entry
+                    if (tmin > 0.0f) {
+                        const bool stop = hit & (__fmul_rn(T, om) < tmin);
+                        k2e = stop ? -1.0f : k2e;
+                        hit = hit & !stop;
+                    }
+                }
+                const float Cn = __fmaf_rn(__fmul_rn(r1.z, s), T, C);
+                C = hit ? Cn : C;
+                T = hit ? __fmul_rn(T, om) : T;
+                if constexpr (!SPLIT) last = hit ? pos + 1u : last;
+                if constexpr (COUNT) n_contrib += hit ? 1u : 0u;
+            }
+        };
         for (uint32_t b0 = I.b; b0 < I.e; b0 += NT) {
             __syncthreads();
             const uint32_t j = b0 + tid;
@@ -162,32 +191,22 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
             }
             __syncthreads();
             const int cnt = (int)min((uint32_t)NT, I.e - b0);
-            if (COUNT && !done) n_eval += (uint32_t)cnt;
-#pragma unroll 4
-            for (int q = 0; q < cnt; ++q) {
-                const float4 r0 = s0[q];
-                const float4 r1 = s1[q];
-                const float dx = __fsub_rn(fpx, r0.x), dy = __fsub_rn(fpy, r0.y);
-                const float d2 = maha2(dx, dy, r0.z, r0.w, r1.x);
-                bool hit = d2 <= k2 && !done;
-                // when any lane hits, the whole wave runs the entry without
-                // branches; lanes that miss keep their state
-                if (wave_any_mask(hit) != 0ull) {
-                    const float G = falloff(d2);
-                    const float s = clamp_opacity(__fmul_rn(r1.y, G), smax);
-                    const float om = __fsub_rn(1.0f, s);
-                    // early termination (t_min > 0): mask arithmetic, no branch
-                    const bool stop = (tmin > 0.0f) & hit & (__fmul_rn(T, om) < tmin);
-                    done = done | stop;
-                    hit = hit & !stop;
-                    const float Cn = __fmaf_rn(__fmul_rn(r1.z, s), T, C);
-                    C = hit ? Cn : C;
-                    T = hit ? __fmul_rn(T, om) : T;
-                    if constexpr (!SPLIT) last = hit ? b0 + (uint32_t)q + 1u : last;
-                    if constexpr (COUNT) n_contrib += hit ? 1u : 0u;
+            if (COUNT && k2e >= 0.0f) n_eval += (uint32_t)cnt;
+            // four entries' records read together (one LDS address, immediate
+            // offsets), then run in order
+            int q = 0;
+            for (; q + 4 <= cnt; q += 4) {
+                float4 r0[4], r1[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    r0[u] = s0[q + u];
+                    r1[u] = s1[q + u];
                 }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) entry(r0[u], r1[u], b0 + (uint32_t)(q + u));
             }
-            if (tmin > 0.0f && __syncthreads_and(done)) break;
+            for (; q < cnt; ++q) entry(s0[q], s1[q], b0 + (uint32_t)q);
+            if (tmin > 0.0f && __syncthreads_and(k2e < 0.0f)) break;
         }
         if constexpr (COUNT) {
             unsigned long long e = n_eval, c = n_contrib;
@@ -300,7 +319,9 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
 #pragma unroll
         for (int q = 1; q < NW; ++q) end = max(end, wmax[q]);
 
-        bool done = !inside;
+        // the cut-off test with the lane's state folded in (-1 once stopped or
+        // outside the image): a hit is one compare, its ballot is free
+        float k2e = inside ? k2 : -1.0f;
         for (uint32_t b0 = I.b; b0 < I.e; b0 += NT) {
             const int cnt = (int)min((uint32_t)NT, I.e - b0);
             __syncthreads();
@@ -336,7 +357,8 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                             const float4 r1 = s1[q];
                             const float dx = __fsub_rn(fpx, r0.x), dy = __fsub_rn(fpy, r0.y);
                             const float d2 = maha2(dx, dy, r0.z, r0.w, r1.x);
-                            bool hit = d2 <= k2 && !done && (SPLIT || (b0 + (uint32_t)q) < lastp);
+                            bool hit = d2 <= k2e;
+                            if constexpr (!SPLIT) hit = hit && (b0 + (uint32_t)q) < lastp;
                             // when any lane hits, the whole wave runs the entry:
                             // computed without branches, lanes that miss keep
                             // their state and contribute zeros
@@ -345,9 +367,14 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                                 const float sraw = __fmul_rn(r1.y, G);
                                 const float s = clamp_opacity(sraw, smax);
                                 const float om = __fsub_rn(1.0f, s);
-                                const bool stop = (tmin > 0.0f) & hit & (__fmul_rn(T, om) < tmin);
-                                done = done | stop;
-                                hit = hit & !stop;
+                                if constexpr (!SPLIT) {
+                                    // t_min > 0 runs unsplit
+                                    if (tmin > 0.0f) {
+                                        const bool stop = hit & (__fmul_rn(T, om) < tmin);
+                                        k2e = stop ? -1.0f : k2e;
+                                        hit = hit & !stop;
+                                    }
+                                }
                                 const float c = r1.z;
                                 const float Cn = __fmaf_rn(__fmul_rn(c, s), T, Cacc);
                                 Cacc = hit ? Cn : Cacc;
