@@ -22,7 +22,8 @@ constexpr int kBlock = 256;
 constexpr int kScanIPT = kScanTile / kBlock;  // 16
 // keys per thread of a radix block: 16 (4096 keys per block) for large sorts,
 // 4 (1024 keys) below kRadixSmallN keys so that a pass still spreads over
-// every compute unit
+// every compute unit.  (32 per thread, for longer write runs per digit, was
+// measured slower on 64M keys: the scatter's 215 VGPRs halve occupancy.)
 constexpr int kRadixIPTLarge = 16, kRadixIPTSmall = 4;
 constexpr int64_t kRadixSmallN = (int64_t)2 << 20;
 constexpr int kWaves = kBlock / kWave;
@@ -560,21 +561,16 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
         const bool last = shift + 8 >= bits;
         const uint32_t *gs = last ? gsrc : nullptr;
         uint32_t *gd = last ? gdst : nullptr;
-        if (ipt == kRadixIPTSmall) {
-            radix_count_kernel<kRadixIPTSmall><<<(unsigned)nblocks, kBlock, 0, s>>>(ka, n_cap, n_dev, shift, mask,
-                                                                                     ws.counts, (int)nblocks);
-        } else {
-            radix_count_kernel<kRadixIPTLarge><<<(unsigned)nblocks, kBlock, 0, s>>>(ka, n_cap, n_dev, shift, mask,
-                                                                                     ws.counts, (int)nblocks);
-        }
-        radix_prefix_kernel<<<256, kBlock, 0, s>>>(ws.counts, (int)nblocks, ws.tot);
-        if (ipt == kRadixIPTSmall) {
-            radix_scatter_kernel<kRadixIPTSmall><<<(unsigned)nblocks, kBlock, 0, s>>>(
-                ka, va, kb, vb, n_cap, n_dev, shift, nbits, ws.counts, ws.tot, (int)nblocks, gs, gd);
-        } else {
-            radix_scatter_kernel<kRadixIPTLarge><<<(unsigned)nblocks, kBlock, 0, s>>>(
-                ka, va, kb, vb, n_cap, n_dev, shift, nbits, ws.counts, ws.tot, (int)nblocks, gs, gd);
-        }
+        auto pass = [&](auto ipt_c) {
+            constexpr int IPT = decltype(ipt_c)::value;
+            radix_count_kernel<IPT><<<(unsigned)nblocks, kBlock, 0, s>>>(ka, n_cap, n_dev, shift, mask, ws.counts,
+                                                                        (int)nblocks);
+            radix_prefix_kernel<<<256, kBlock, 0, s>>>(ws.counts, (int)nblocks, ws.tot);
+            radix_scatter_kernel<IPT><<<(unsigned)nblocks, kBlock, 0, s>>>(ka, va, kb, vb, n_cap, n_dev, shift, nbits,
+                                                                          ws.counts, ws.tot, (int)nblocks, gs, gd);
+        };
+        if (ipt == kRadixIPTSmall) pass(std::integral_constant<int, kRadixIPTSmall>{});
+        else pass(std::integral_constant<int, kRadixIPTLarge>{});
         std::swap(ka, kb);
         std::swap(va, vb);
         *in_k1 = !*in_k1;
