@@ -159,9 +159,11 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
             const float d2 = maha2(dx, dy, r0.z, r0.w, r1.x);
             bool hit = d2 <= k2e;
             if (wave_any_mask(hit) != 0ull) {
-                const float G = falloff(d2);
-                const float s = clamp_opacity(__fmul_rn(r1.y, G), smax);
-                const float om = __fsub_rn(1.0f, s);
+                // lanes that miss run the same arithmetic with G = 0: s = 0,
+                // 1 - s = 1, so C and T stay exactly as they are
+                float G = hit ? falloff(d2) : 0.0f;
+                float s = clamp_opacity(__fmul_rn(r1.y, G), smax);
+                float om = __fsub_rn(1.0f, s);
                 if constexpr (!SPLIT) {
                     // early termination (t_min > 0 runs unsplit): the lane
                     // stops before this entry
@@ -169,11 +171,12 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
                         const bool stop = hit & (__fmul_rn(T, om) < tmin);
                         k2e = stop ? -1.0f : k2e;
                         hit = hit & !stop;
+                        s = stop ? 0.0f : s;
+                        om = stop ? 1.0f : om;
                     }
                 }
-                const float Cn = __fmaf_rn(__fmul_rn(r1.z, s), T, C);
-                C = hit ? Cn : C;
-                T = hit ? __fmul_rn(T, om) : T;
+                C = __fmaf_rn(__fmul_rn(r1.z, s), T, C);
+                T = __fmul_rn(T, om);
                 if constexpr (!SPLIT) last = hit ? pos + 1u : last;
                 if constexpr (COUNT) n_contrib += hit ? 1u : 0u;
             }
@@ -363,27 +366,34 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                             // computed without branches, lanes that miss keep
                             // their state and contribute zeros
                             if (wave_any_mask(hit) != 0ull) {
-                                const float G = falloff(d2);
-                                const float sraw = __fmul_rn(r1.y, G);
-                                const float s = clamp_opacity(sraw, smax);
-                                const float om = __fsub_rn(1.0f, s);
+                                // lanes that miss run the same arithmetic with
+                                // G = 0: s = 0, 1 - s = 1, so the running colour
+                                // and T stay exactly as they are and every term
+                                // below is zero
+                                float G = hit ? falloff(d2) : 0.0f;
+                                float sraw = __fmul_rn(r1.y, G);
+                                float s = clamp_opacity(sraw, smax);
+                                float om = __fsub_rn(1.0f, s);
                                 if constexpr (!SPLIT) {
                                     // t_min > 0 runs unsplit
                                     if (tmin > 0.0f) {
                                         const bool stop = hit & (__fmul_rn(T, om) < tmin);
                                         k2e = stop ? -1.0f : k2e;
                                         hit = hit & !stop;
+                                        G = stop ? 0.0f : G;
+                                        sraw = stop ? 0.0f : sraw;
+                                        s = stop ? 0.0f : s;
+                                        om = stop ? 1.0f : om;
                                     }
                                 }
                                 const float c = r1.z;
-                                const float Cn = __fmaf_rn(__fmul_rn(c, s), T, Cacc);
-                                Cacc = hit ? Cn : Cacc;
+                                Cacc = __fmaf_rn(__fmul_rn(c, s), T, Cacc);
                                 const float S = Cf - Cacc;
                                 const float ds = g * (c * T - S * __builtin_amdgcn_rcpf(om));
                                 // moments of dL/ds G about the mean; the conic and
                                 // alpha factors are applied once per (view,
                                 // Gaussian) in the projection backward
-                                const float gds = (hit && !(sraw > smax)) ? ds * G : 0.0f;
+                                const float gds = (sraw > smax) ? 0.0f : ds * G;
                                 const float m1x = gds * dx, m1y = gds * dy;
                                 gv[0] = m1x;
                                 gv[1] = m1y;
@@ -391,9 +401,9 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                                 gv[3] = m1x * dy;
                                 gv[4] = m1y * dy;
                                 gv[5] = gds;
-                                gv[6] = hit ? g * s * T : 0.0f;
-                                T = hit ? __fmul_rn(T, om) : T;
-                                any = any || hit;
+                                gv[6] = g * s * T;
+                                T = __fmul_rn(T, om);
+                                any = true;
                             }
                         }
 #pragma unroll
