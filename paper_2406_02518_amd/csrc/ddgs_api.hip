@@ -439,17 +439,18 @@ SortWs sort_ws(ddgs_ctx *c)
                   c->bufs["sort_counts"].bytes / sizeof(uint32_t), c->bufs["sort_bsum"].bytes / sizeof(uint64_t)};
 }
 
-// Sort / scan temporaries of the debug entry points (own buffers, so a debug
-// call leaves the render state alone).
-ddgs_status debug_ws(ddgs_ctx *c, int64_t n, SortWs *ws)
+// Sort / scan temporaries of the calls outside the render path (the debug
+// entry points, densification, dual sampling): buffers of their own, so such a
+// call leaves the render state alone.
+ddgs_status aux_sort_ws(ddgs_ctx *c, int64_t n, SortWs *ws)
 {
     uint32_t *u;
     uint64_t *bs;
-    DDGS_TRY(ensure_t(c, "dbg_counts", sort_counts_words(std::max<int64_t>(n, 1)), &u));
-    DDGS_TRY(ensure_t(c, "dbg_tot", 256, &u));
-    DDGS_TRY(ensure_t(c, "dbg_bsum", sort_blocksum_words(std::max<int64_t>(n, 1)), &bs));
-    *ws = SortWs{buf<uint32_t>(c, "dbg_counts"), buf<uint32_t>(c, "dbg_tot"), buf<uint64_t>(c, "dbg_bsum"),
-                 c->bufs["dbg_counts"].bytes / sizeof(uint32_t), c->bufs["dbg_bsum"].bytes / sizeof(uint64_t)};
+    DDGS_TRY(ensure_t(c, "aux_counts", sort_counts_words(std::max<int64_t>(n, 1)), &u));
+    DDGS_TRY(ensure_t(c, "aux_tot", 256, &u));
+    DDGS_TRY(ensure_t(c, "aux_bsum", sort_blocksum_words(std::max<int64_t>(n, 1)), &bs));
+    *ws = SortWs{buf<uint32_t>(c, "aux_counts"), buf<uint32_t>(c, "aux_tot"), buf<uint64_t>(c, "aux_bsum"),
+                 c->bufs["aux_counts"].bytes / sizeof(uint32_t), c->bufs["aux_bsum"].bytes / sizeof(uint64_t)};
     return DDGS_OK;
 }
 
@@ -1020,7 +1021,7 @@ ddgs_status ddgs_densify_plan(ddgs_ctx *c, const ddgs_densify_opts *o, const flo
     DDGS_TRY(ensure_t(c, "dn_child_ex", nn, &child_ex));
     DDGS_TRY(ensure_t(c, "dn_tot", 4, &tot));
     SortWs ws;
-    DDGS_TRY(debug_ws(c, n, &ws));
+    DDGS_TRY(aux_sort_ws(c, n, &ws));
     hipStream_t s = c->stream;
     HIP_TRY(c, launch_densify_plan(n, c->model.log_scale, c->model.opacity_logit, c->st_grad, c->st_cnt, c->st_rad,
                                    th, keep, clone, child, s));
@@ -1166,7 +1167,7 @@ ddgs_status ddgs_rads_prepare(ddgs_ctx *c, const ddgs_volume *vol, float *level,
     DDGS_TRY(ensure_t(c, "rads_bsum", (size_t)nb64 + 1, &bsum));
     DDGS_TRY(ensure_t(c, "rads_cdf", (size_t)n, &cdf));
     SortWs ws;
-    DDGS_TRY(debug_ws(c, n, &ws));
+    DDGS_TRY(aux_sort_ws(c, n, &ws));
     HIP_TRY(c, launch_rads_level(v, part, nb, mm, s));
     HIP_TRY(c, launch_mc_count(v, mm, cnt, s));
     HIP_TRY(c, launch_exclusive_scan(cnt, nullptr, off, n, ws, tot, s));
@@ -1212,7 +1213,7 @@ ddgs_status ddgs_rads_sample(ddgs_ctx *c, int64_t n1, const uint32_t *mc_keys, i
         DDGS_TRY(ensure_t(c, "rads_v0", (size_t)M, &v0));
         DDGS_TRY(ensure_t(c, "rads_v1", (size_t)M, &v1));
         SortWs ws;
-        DDGS_TRY(debug_ws(c, M, &ws));
+        DDGS_TRY(aux_sort_ws(c, M, &ws));
         HIP_TRY(c, hipMemcpyAsync(k0, mc_keys, sizeof(uint32_t) * M, hipMemcpyDeviceToDevice, s));
         HIP_TRY(c, launch_iota(v0, M, s));
         bool in_k1 = false;
@@ -1610,7 +1611,7 @@ ddgs_status ddgs_debug_sort_pairs(ddgs_ctx *c, uint32_t *keys, uint32_t *vals, i
     DDGS_TRY(ensure_t(c, "dbg_k1", n, &k1));
     DDGS_TRY(ensure_t(c, "dbg_v1", n, &v1));
     SortWs ws{};
-    DDGS_TRY(debug_ws(c, n, &ws));
+    DDGS_TRY(aux_sort_ws(c, n, &ws));
     bool in_k1 = false;
     HIP_TRY(c, radix_sort_pairs(keys, vals, k1, v1, n, nullptr, bits, ws, &in_k1, c->stream));
     if (in_k1) {
@@ -1626,7 +1627,7 @@ ddgs_status ddgs_debug_exclusive_scan(ddgs_ctx *c, const uint32_t *in, uint32_t 
     if (!c || n < 0 || (n > 0 && (!in || !out))) return fail(c, DDGS_ERR_INVALID_ARG, "bad scan arguments");
     HIP_TRY(c, hipSetDevice(c->device));
     SortWs ws{};
-    DDGS_TRY(debug_ws(c, n, &ws));
+    DDGS_TRY(aux_sort_ws(c, n, &ws));
     uint64_t *tot;
     DDGS_TRY(ensure_t(c, "dbg_total", 1, &tot));
     HIP_TRY(c, launch_exclusive_scan(in, nullptr, out, n, ws, tot, c->stream));
