@@ -67,6 +67,20 @@ def parse():
     return ap.parse_args()
 
 
+def host_cpu():
+    """Model name and logical CPU count of the host the oracle runs on."""
+    name = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": name, "logical_cpus": os.cpu_count()}
+
+
 def copy_calibration():
     import torch
     n = 64 << 20  # floats: 256 MiB
@@ -528,7 +542,7 @@ def main():
         ref.backward(cfg.scene, [v], pix, gw, threads=threads)
         dt = time.perf_counter() - a
         scale = v.H / len(rows)
-        cpu = {"value": round(dt * scale * 1e3, 1), "unit": "ms", "cores": threads, "kind": "oracle",
+        cpu = {"value": round(dt * scale * 1e3, 1), "unit": "ms", "cores": threads, "kind": "oracle", "host": host_cpu(),
                "sample": f"view 0 of the fitting workload, every {args.cpu_row_stride}th detector row "
                          f"({len(rows)} of {v.H} rows = {len(pix)} pixels x 500k Gaussians), forward at those "
                          f"pixels + analytic FP64 backward of a linear loss on them; {dt:.1f} s measured, "
