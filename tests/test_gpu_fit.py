@@ -226,3 +226,31 @@ def test_fitting_loop_lowers_the_loss(R):
     assert params["mean"].shape[1] == hist[-1][1]
     assert any(h[1] != c.scene.n for h in hist)
     assert all(torch.isfinite(t).all() for t in params.values())
+
+
+def test_training_from_dual_sampling(R):
+    """The paper's path end to end on a small phantom: dual-sampling
+    initialisation from the volume, then fitting to targets rendered by the
+    oracle from a model of the same phantom, with densification.  The loss
+    falls and densification adds Gaussians to both sets."""
+    from paper_2406_02518_amd import rads
+    seed = 61
+    ss = np.random.SeedSequence(seed)
+    ph = synth.phantom(40, np.random.default_rng(ss.spawn(1)[0]))
+    true = synth.scene_from_phantom(seed, 40, 3000, 0.15, k=8, L=1)
+    views = [synth.view(48, 48, 1.2, 1000.0, 600.0, 30.0 * j) for j in range(12)]
+    targets = [torch.from_numpy(t.astype(np.float32).ravel()).cuda() for t in ref.render(true, views)]
+    hu = torch.from_numpy(np.ascontiguousarray(ph.transpose(2, 1, 0))).cuda()
+    pts, ls, n_iso, _ = rads.sample(R, hu, (1.0, 1.0, 1.0), (-19.5, -19.5, -19.5), n1=1500, n2=1000, seed=2)
+    g = torch.Generator().manual_seed(3)
+    p = rads.initial_model(pts, ls, 8, 1, b_iso=torch.randn(8, generator=g).cuda(),
+                           B_dir=0.1 * torch.randn((3, 8), generator=g).cuda())
+    n0 = p["mean"].shape[1]
+    sched = fit.FitSchedule(densify_from=50, densify_until=250, densify_every=50, opacity_reset_every=0,
+                            grad_threshold=1e-5)
+    params, n_iso_end, hist = fit.fit(R, p, n_iso, 1, views, targets, iters=300, extent=20.0, schedule=sched,
+                                      log_every=50)
+    print("history", hist, "n_iso", n_iso, "->", n_iso_end)
+    assert hist[-1][2] < 0.7 * hist[0][2]
+    assert params["mean"].shape[1] > n0 and n_iso_end > n_iso and params["mean"].shape[1] - n_iso_end > n0 - n_iso
+    assert all(torch.isfinite(t).all() for t in params.values())
