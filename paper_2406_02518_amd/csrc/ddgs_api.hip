@@ -405,7 +405,7 @@ ddgs_status ensure_entries(ddgs_ctx *c, int64_t cap)
     const int64_t big = std::max<int64_t>({VN, cap, (int64_t)c->n_tiles, 1});
     uint64_t *st;
     DDGS_TRY(ensure_t(c, "sort_counts", sort_counts_words(big), &u));
-    DDGS_TRY(ensure_t(c, "sort_tot", 256, &u));
+    DDGS_TRY(ensure_t(c, "sort_tot", kSortTotWords, &u));
     uint64_t *bs;
     DDGS_TRY(ensure_t(c, "sort_bsum", sort_blocksum_words(big), &bs));
     if (!c->dry_run) c->entry_cap = std::max(c->entry_cap, cap);
@@ -447,7 +447,7 @@ ddgs_status aux_sort_ws(ddgs_ctx *c, int64_t n, SortWs *ws)
     uint32_t *u;
     uint64_t *bs;
     DDGS_TRY(ensure_t(c, "aux_counts", sort_counts_words(std::max<int64_t>(n, 1)), &u));
-    DDGS_TRY(ensure_t(c, "aux_tot", 256, &u));
+    DDGS_TRY(ensure_t(c, "aux_tot", kSortTotWords, &u));
     DDGS_TRY(ensure_t(c, "aux_bsum", sort_blocksum_words(std::max<int64_t>(n, 1)), &bs));
     *ws = SortWs{buf<uint32_t>(c, "aux_counts"), buf<uint32_t>(c, "aux_tot"), buf<uint64_t>(c, "aux_bsum"),
                  c->bufs["aux_counts"].bytes / sizeof(uint32_t), c->bufs["aux_bsum"].bytes / sizeof(uint64_t)};

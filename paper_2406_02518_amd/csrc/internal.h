@@ -206,9 +206,10 @@ hipError_t launch_grad_final(const ModelDev &m, const float *bpart, float *db, f
 constexpr int kScanTile = 4096;
 
 // Temporaries of the scans and radix sorts (device memory).
+constexpr int kSortTotWords = 512;  // digit totals of the widest radix pass (9-bit digits)
 struct SortWs {
     uint32_t *counts;      // [counts_words]: per-block digit counts, then offsets
-    uint32_t *tot;         // [256]: digit totals of the current pass
+    uint32_t *tot;         // [kSortTotWords]: digit totals of the current pass
     uint64_t *blocksum;    // [blocksum_words]: scan block sums
     size_t counts_words, blocksum_words;
 };

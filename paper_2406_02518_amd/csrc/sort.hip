@@ -26,6 +26,7 @@ constexpr int kScanIPT = kScanTile / kBlock;  // 16
 // measured slower on 64M keys: the scatter's 215 VGPRs halve occupancy.)
 constexpr int kRadixIPTLarge = 16, kRadixIPTSmall = 4;
 constexpr int64_t kRadixSmallN = (int64_t)2 << 20;
+constexpr int kRadixMaxDigits = kSortTotWords;  // digit values of the widest (9-bit) pass
 constexpr int kWaves = kBlock / kWave;
 
 // exclusive scan over a block of 256 threads; returns the block total
@@ -227,15 +228,16 @@ __device__ __forceinline__ int64_t runtime_n(int64_t n_cap, const uint32_t *n_de
     return m < n_cap ? m : n_cap;
 }
 
-template <int IPT>
+// NB: digit values of a pass (256, or 512 where 9-bit digits save a pass)
+template <int IPT, int NB>
 __global__ __launch_bounds__(kBlock) void radix_count_kernel(const uint32_t *kin, int64_t n_cap, const uint32_t *n_dev,
                                                              int shift, uint32_t mask, uint32_t *counts, int nblocks)
 {
     constexpr int kRadixTile = kBlock * IPT;
-    __shared__ uint32_t h[kWaves][256];
+    __shared__ uint32_t h[kWaves][NB];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
-    for (int q = 0; q < 256 / kWave; ++q) h[w][lane + q * kWave] = 0;
+    for (int q = 0; q < NB / kWave; ++q) h[w][lane + q * kWave] = 0;
     __syncthreads();
     const int64_t n = runtime_n(n_cap, n_dev);
     const int64_t wbase = (int64_t)blockIdx.x * kRadixTile + w * (kRadixTile / kWaves);
@@ -245,8 +247,8 @@ __global__ __launch_bounds__(kBlock) void radix_count_kernel(const uint32_t *kin
         if (idx < n) atomicAdd(&h[w][(kin[idx] >> shift) & mask], 1u);
     }
     __syncthreads();
-    const int d = threadIdx.x;
-    counts[(size_t)d * nblocks + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+    for (int d = threadIdx.x; d < NB; d += kBlock)
+        counts[(size_t)d * nblocks + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
 }
 
 // Block d: exclusive scan of counts[d][0, nblocks) in place; tot[d] = row sum.
@@ -292,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void radix_prefix_kernel(uint32_t *counts, 
 // ballots (lanes sharing the digit), the block combines the 4 wave
 // histograms, the keys are staged in LDS in digit order and written out
 // with consecutive lanes on consecutive addresses.
-template <int IPT>
+template <int IPT, int NB>
 __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *kin, const uint32_t *vin,
                                                                uint32_t *kout, uint32_t *vout, int64_t n_cap,
                                                                const uint32_t *n_dev, int shift, int nbits,
@@ -300,9 +302,10 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *k
                                                                int nblocks, const uint32_t *gsrc, uint32_t *gdst)
 {
     constexpr int kRadixTile = kBlock * IPT;
-    __shared__ uint32_t wh[kWaves][256];
-    __shared__ uint32_t bstart[256];
-    __shared__ uint32_t gbase[256];
+    constexpr int DPT = NB / kBlock;  // digits per thread in the block-wide steps
+    __shared__ uint32_t wh[kWaves][NB];
+    __shared__ uint32_t bstart[NB];
+    __shared__ uint32_t gbase[NB];
     __shared__ uint32_t sk[kRadixTile];
     __shared__ uint32_t sv[kRadixTile];
     __shared__ uint32_t wl[kWaves];
@@ -312,7 +315,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *k
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const uint32_t mask = (1u << nbits) - 1u;
 #pragma unroll
-    for (int q = 0; q < 256 / kWave; ++q) wh[w][lane + q * kWave] = 0;
+    for (int q = 0; q < NB / kWave; ++q) wh[w][lane + q * kWave] = 0;
     __syncthreads();
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     uint32_t key[IPT], val[IPT], rank[IPT];
@@ -340,16 +343,32 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *k
     }
     __syncthreads();
     {
-        const int d = threadIdx.x;
-        const uint32_t c0 = wh[0][d], c1 = wh[1][d], c2 = wh[2][d], c3 = wh[3][d];
-        wh[0][d] = 0;
-        wh[1][d] = c0;
-        wh[2][d] = c0 + c1;
-        wh[3][d] = c0 + c1 + c2;
+        // thread t owns digits t DPT .. t DPT + DPT - 1, so the block scans
+        // over threads run in digit order
+        uint32_t csum[DPT], cs = 0, ts = 0;
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            const int d = threadIdx.x * DPT + j;
+            const uint32_t c0 = wh[0][d], c1 = wh[1][d], c2 = wh[2][d], c3 = wh[3][d];
+            wh[0][d] = 0;
+            wh[1][d] = c0;
+            wh[2][d] = c0 + c1;
+            wh[3][d] = c0 + c1 + c2;
+            csum[j] = c0 + c1 + c2 + c3;
+            cs += csum[j];
+            ts += tot[d];
+        }
         uint32_t t;
-        bstart[d] = block_excl_scan(c0 + c1 + c2 + c3, wl, t);
-        const uint32_t dstart = block_excl_scan(tot[d], wl, t);
-        gbase[d] = dstart + offsets[(size_t)d * nblocks + blockIdx.x];
+        uint32_t bs = block_excl_scan(cs, wl, t);
+        uint32_t ds = block_excl_scan(ts, wl, t);
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            const int d = threadIdx.x * DPT + j;
+            bstart[d] = bs;
+            gbase[d] = ds + offsets[(size_t)d * nblocks + blockIdx.x];
+            bs += csum[j];
+            ds += tot[d];
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -493,7 +512,7 @@ size_t sort_counts_words(int64_t n)
 {
     const int64_t small = blocks_for(std::min(n, kRadixSmallN), (int64_t)kBlock * kRadixIPTSmall);
     const int64_t large = blocks_for(n, (int64_t)kBlock * kRadixIPTLarge);
-    return (size_t)256 * (size_t)std::max<int64_t>({1, small, large});
+    return (size_t)kRadixMaxDigits * (size_t)std::max<int64_t>({1, small, large});
 }
 // (enough for the 256-per-block item scans too: their inputs are tile counts)
 size_t sort_blocksum_words(int64_t n) { return (size_t)std::max<int64_t>(1, blocks_for(n, kBlock)) + 1; }
@@ -554,23 +573,39 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
     const int ipt = radix_ipt(n_cap);
     const int64_t nblocks = blocks_for(n_cap, (int64_t)kBlock * ipt);
     if (nblocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    // passes of 8-bit digits, or of up to 9 bits (512 digit values) where that
+    // takes fewer passes (9, 17 or 25 key bits), the bits then spread evenly
+    const int passes8 = (bits + 7) / 8, passes9 = (bits + 8) / 9;
+    const bool wide = passes9 < passes8;
+    const int passes = wide ? passes9 : passes8;
     uint32_t *ka = k0, *va = v0, *kb = k1, *vb = v1;
-    for (int shift = 0; shift < bits; shift += 8) {
-        const int nbits = std::min(8, bits - shift);
+    int shift = 0;
+    for (int p = 0; p < passes; ++p) {
+        const int nbits = wide ? bits / passes + (p < bits % passes ? 1 : 0) : std::min(8, bits - shift);
         const uint32_t mask = (1u << nbits) - 1u;
-        const bool last = shift + 8 >= bits;
+        const bool last = p == passes - 1;
         const uint32_t *gs = last ? gsrc : nullptr;
         uint32_t *gd = last ? gdst : nullptr;
-        auto pass = [&](auto ipt_c) {
-            constexpr int IPT = decltype(ipt_c)::value;
-            radix_count_kernel<IPT><<<(unsigned)nblocks, kBlock, 0, s>>>(ka, n_cap, n_dev, shift, mask, ws.counts,
-                                                                        (int)nblocks);
-            radix_prefix_kernel<<<256, kBlock, 0, s>>>(ws.counts, (int)nblocks, ws.tot);
-            radix_scatter_kernel<IPT><<<(unsigned)nblocks, kBlock, 0, s>>>(ka, va, kb, vb, n_cap, n_dev, shift, nbits,
-                                                                          ws.counts, ws.tot, (int)nblocks, gs, gd);
+        auto pass = [&](auto ipt_c, auto nb_c) {
+            constexpr int IPT = decltype(ipt_c)::value, NB = decltype(nb_c)::value;
+            radix_count_kernel<IPT, NB><<<(unsigned)nblocks, kBlock, 0, s>>>(ka, n_cap, n_dev, shift, mask,
+                                                                            ws.counts, (int)nblocks);
+            radix_prefix_kernel<<<NB, kBlock, 0, s>>>(ws.counts, (int)nblocks, ws.tot);
+            radix_scatter_kernel<IPT, NB><<<(unsigned)nblocks, kBlock, 0, s>>>(
+                ka, va, kb, vb, n_cap, n_dev, shift, nbits, ws.counts, ws.tot, (int)nblocks, gs, gd);
         };
-        if (ipt == kRadixIPTSmall) pass(std::integral_constant<int, kRadixIPTSmall>{});
-        else pass(std::integral_constant<int, kRadixIPTLarge>{});
+        using Small = std::integral_constant<int, kRadixIPTSmall>;
+        using Large = std::integral_constant<int, kRadixIPTLarge>;
+        using D8 = std::integral_constant<int, 256>;
+        using D9 = std::integral_constant<int, kRadixMaxDigits>;
+        if (ipt == kRadixIPTSmall) {
+            if (wide) pass(Small{}, D9{});
+            else pass(Small{}, D8{});
+        } else {
+            if (wide) pass(Large{}, D9{});
+            else pass(Large{}, D8{});
+        }
+        shift += nbits;
         std::swap(ka, kb);
         std::swap(va, vb);
         *in_k1 = !*in_k1;

@@ -26,7 +26,9 @@ def R():
 @pytest.mark.parametrize("n,bits,kind", [(1, 8, "rand"), (2047, 8, "rand"), (2049, 13, "rand"),
                                          (100_000, 32, "rand"), (1_000_003, 24, "rand"), (70_000, 16, "equal"),
                                          (50_000, 32, "reverse"), (4096, 1, "rand"), (300_001, 11, "few"),
-                                         (2_500_001, 13, "rand"), (16_777_217, 32, "rand")])
+                                         (2_500_001, 13, "rand"), (16_777_217, 32, "rand"),
+                                         (100_003, 9, "rand"), (2_500_003, 17, "rand"), (1_000_003, 25, "rand"),
+                                         (3_000, 17, "few")])
 def test_radix_sort_is_stable_and_bit_exact(R, n, bits, kind):
     rng = np.random.default_rng(n + bits)
     if kind == "rand":
