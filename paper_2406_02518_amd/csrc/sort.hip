@@ -72,16 +72,41 @@ struct ChunkIn {
     }
 };
 
+// The IPT inputs of a thread at base + q * kBlock + threadIdx.x, all read
+// before any is used so that the loads overlap; indices are clamped to the
+// last element (n > base), callers zero what lies past the end.
+template <int IPT, class In>
+__device__ __forceinline__ void load_inputs(const In &f, int64_t base, int64_t n, uint32_t (&x)[IPT])
+{
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) x[q] = f(min(base + q * kBlock + threadIdx.x, n - 1));
+}
+// (gathered input: every index first, then every value)
+template <int IPT>
+__device__ __forceinline__ void load_inputs(const PlainIn &f, int64_t base, int64_t n, uint32_t (&x)[IPT])
+{
+    if (f.gather) {
+        uint32_t g[IPT];
+#pragma unroll
+        for (int q = 0; q < IPT; ++q) g[q] = f.gather[min(base + q * kBlock + threadIdx.x, n - 1)];
+#pragma unroll
+        for (int q = 0; q < IPT; ++q) x[q] = f.in[g[q]];
+    } else {
+#pragma unroll
+        for (int q = 0; q < IPT; ++q) x[q] = f.in[min(base + q * kBlock + threadIdx.x, n - 1)];
+    }
+}
+
 template <class In, int IPT>
 __global__ __launch_bounds__(kBlock) void scan_reduce_kernel(In f, int64_t n, uint64_t *blocksum)
 {
     const int64_t base = (int64_t)blockIdx.x * (kBlock * IPT);
+    uint32_t x[IPT];
+    load_inputs(f, base, n, x);
     uint64_t s = 0;
-#pragma unroll 4
-    for (int q = 0; q < IPT; ++q) {
-        const int64_t idx = base + q * kBlock + threadIdx.x;
-        if (idx < n) s += f(idx);
-    }
+#pragma unroll
+    for (int q = 0; q < IPT; ++q)
+        if (base + q * kBlock + threadIdx.x < n) s += x[q];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
     __shared__ uint64_t red[kWaves];
@@ -166,12 +191,15 @@ __global__ __launch_bounds__(kBlock) void scan_apply_kernel(In f, int64_t n, con
     __shared__ uint32_t wl[kWaves];
     __shared__ uint64_t red[kWaves];
     const int64_t base = (int64_t)blockIdx.x * TILE;
-#pragma unroll 4
-    for (int q = 0; q < IPT; ++q) {
-        const int64_t idx = base + q * kBlock + threadIdx.x;
-        const uint32_t x = idx < n ? f(idx) : 0u;
-        tile[q * kBlock + threadIdx.x] = x;
-        vals[q * kBlock + threadIdx.x] = x;
+    {
+        uint32_t xs[IPT];
+        load_inputs(f, base, n, xs);
+#pragma unroll
+        for (int q = 0; q < IPT; ++q) {
+            const uint32_t x = base + q * kBlock + threadIdx.x < n ? xs[q] : 0u;
+            tile[q * kBlock + threadIdx.x] = x;
+            vals[q * kBlock + threadIdx.x] = x;
+        }
     }
     uint64_t off;
     if (prescanned) {
@@ -241,10 +269,16 @@ __global__ __launch_bounds__(kBlock) void radix_count_kernel(const uint32_t *kin
     __syncthreads();
     const int64_t n = runtime_n(n_cap, n_dev);
     const int64_t wbase = (int64_t)blockIdx.x * kRadixTile + w * (kRadixTile / kWaves);
-#pragma unroll 4
+    // every round's key is loaded before the first is counted, so the loads
+    // overlap (lanes past the end read the last key and count nothing)
+    const int64_t last = n > 0 ? n - 1 : 0;
+    uint32_t kk[IPT];
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) kk[r] = kin[min(wbase + r * kWave + lane, last)];
+#pragma unroll
     for (int r = 0; r < IPT; ++r) {
         const int64_t idx = wbase + r * kWave + lane;
-        if (idx < n) atomicAdd(&h[w][(kin[idx] >> shift) & mask], 1u);
+        if (idx < n) atomicAdd(&h[w][(kk[r] >> shift) & mask], 1u);
     }
     __syncthreads();
     for (int d = threadIdx.x; d < NB; d += kBlock)
@@ -320,12 +354,18 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *k
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     uint32_t key[IPT], val[IPT], rank[IPT];
     const int64_t wbase = base + w * (kRadixTile / kWaves);
+    // all rounds' keys and values are loaded before the first is ranked, so
+    // the loads overlap (lanes past the end read the last pair, n > base)
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const int64_t li = min(wbase + r * kWave + lane, n - 1);
+        key[r] = kin[li];
+        val[r] = vin[li];
+    }
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
         const int64_t idx = wbase + r * kWave + lane;
         const bool ok = idx < n;
-        key[r] = ok ? kin[idx] : 0u;
-        val[r] = ok ? vin[idx] : 0u;
         const uint32_t d = (key[r] >> shift) & mask;
         uint64_t peers = __ballot(ok);
         for (int b = 0; b < nbits; ++b) {
