@@ -290,6 +290,17 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
     const int n_waves = gridDim.x * (kBlock / kWave);
     const bool is_dir = ii >= a.m.n_iso;
     const int nd = n - a.m.n_iso, id = ii - a.m.n_iso;
+    // the next view's slot count and first slot, read one view ahead (the
+    // first view's before the parameters, since its slot reads wait on them)
+    uint32_t c_next = 0, off_next = 0;
+    if (valid && a.V > 0) {
+        c_next = a.cnt[ii];
+        off_next = a.offs[ii];
+    }
+    // isotropic radiosity, or for entangled models the isotropic logit (read
+    // early too: values derived from it are computed before the view loop)
+    const float ciso = (is_dir && !a.m.entangled) ? 0.0f : a.gc.ciso[ii];
+    const float zl0 = a.m.entangled ? ciso : 0.0f;
 
     const float mx = a.m.mean[ii], my = a.m.mean[n + ii], mz = a.m.mean[2 * n + ii];
     float cw[6];
@@ -297,10 +308,14 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
     for (int q = 0; q < 6; ++q) cw[q] = a.gc.cov[q * n + ii];
     float h[KL];
 #pragma unroll
-    for (int r = 0; r < KL; ++r) h[r] = is_dir ? a.gc.hdir[(size_t)r * nd + id] : 0.0f;
-    // isotropic radiosity, or for entangled models the isotropic logit
-    const float ciso = (is_dir && !a.m.entangled) ? 0.0f : a.gc.ciso[ii];
-    const float zl0 = a.m.entangled ? ciso : 0.0f;
+    for (int r = 0; r < KL; ++r) h[r] = 0.0f;
+    if (nd > 0) {
+        // read by every lane so that the loads are not split by per-lane
+        // branches: isotropic lanes read a clamped index and never use it
+        const int idc = min(max(id, 0), nd - 1);
+#pragma unroll
+        for (int r = 0; r < KL; ++r) h[r] = a.gc.hdir[(size_t)r * nd + idc];
+    }
 
     float gmu[3] = {0.f, 0.f, 0.f};
     float GSw[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -313,15 +328,16 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
     for (int v = 0; v < a.V; ++v) {
         const ViewDev &V = a.views[v];
         float pose[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        uint32_t c = 0, off = 0;
-        if (valid) {
-            c = a.cnt[(size_t)v * n + ii];
-            if (c > 0) {
-                off = a.offs[(size_t)v * n + ii];
-                // slots past the capacity do not exist (overflowed step)
-                if (off >= a.slot_cap) c = 0;
-                else if ((uint64_t)off + c > a.slot_cap) c = a.slot_cap - off;
-            }
+        // (the offset is only used when the count is non-zero)
+        uint32_t c = c_next, off = off_next;
+        if (valid && v + 1 < a.V) {
+            c_next = a.cnt[(size_t)(v + 1) * n + ii];
+            off_next = a.offs[(size_t)(v + 1) * n + ii];
+        }
+        // slots past the capacity do not exist (overflowed step)
+        if (c > 0) {
+            if (off >= a.slot_cap) c = 0;
+            else if ((uint64_t)off + c > a.slot_cap) c = a.slot_cap - off;
         }
         float g7[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         // the pair's slots in emission order; four entries' loads in flight
@@ -340,11 +356,24 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
                 g7[4] += s1[u].x; g7[5] += s1[u].y; g7[6] += s1[u].z;
             }
         }
-        for (; e < c; ++e) {
-            const float4 s0 = a.slot[2 * ((size_t)off + e)];
-            const float4 s1 = a.slot[2 * ((size_t)off + e) + 1];
-            g7[0] += s0.x; g7[1] += s0.y; g7[2] += s0.z; g7[3] += s0.w;
-            g7[4] += s1.x; g7[5] += s1.y; g7[6] += s1.z;
+        if (e < c) {
+            // the last one to three entries, loaded together (addresses past
+            // the pair's last slot repeat it and are not added)
+            const uint32_t rem = c - e;
+            float4 s0[3], s1[3];
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const size_t q = (size_t)off + e + min((uint32_t)u, rem - 1u);
+                s0[u] = a.slot[2 * q];
+                s1[u] = a.slot[2 * q + 1];
+            }
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                if ((uint32_t)u < rem) {
+                    g7[0] += s0[u].x; g7[1] += s0[u].y; g7[2] += s0[u].z; g7[3] += s0[u].w;
+                    g7[4] += s1[u].x; g7[5] += s1[u].y; g7[6] += s1[u].z;
+                }
+            }
         }
         Geom g;
         if (c > 0 && project_geom(V, mx, my, mz, cw, a.o, g)) {
