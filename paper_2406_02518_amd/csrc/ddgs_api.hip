@@ -349,8 +349,9 @@ ddgs_status ensure_static(ddgs_ctx *c)
     DDGS_TRY(ensure_t(c, "rec", 4 * VN, &f4));
     uint2 *u2;
     DDGS_TRY(ensure_t(c, "rect", VN, &u2));
-    const char *u32s[] = {"zkey", "cnt", "offs", "skey", "sval", "skey2", "sval2", "off_sorted", "cnt_sorted"};
+    const char *u32s[] = {"zkey", "cnt", "skey", "sval", "skey2", "sval2", "off_sorted", "cnt_sorted", "slot_lp"};
     for (const char *nm : u32s) DDGS_TRY(ensure_t(c, nm, VN, &u));
+    DDGS_TRY(ensure_t(c, "slot_btot", std::max<int64_t>(1, (int64_t)c->views_h.size() * slot_blocks(n)), &u));
     DDGS_TRY(ensure_t(c, "ranges", std::max(1, c->n_tiles), &u2));
     DDGS_TRY(ensure_t(c, "qkey", std::max(1, c->n_tiles), &u));
     DDGS_TRY(ensure_t(c, "qval", std::max(1, c->n_tiles), &u));
@@ -403,7 +404,6 @@ ddgs_status ensure_entries(ddgs_ctx *c, int64_t cap)
     DDGS_TRY(ensure_t(c, "item_base", std::max(1, c->n_tiles), &u));
     DDGS_TRY(ensure_t(c, "part", (size_t)(split > 0 ? max_items : 1) * c->opt.tile_w * c->opt.tile_h, &f2));
     const int64_t big = std::max<int64_t>({VN, cap, (int64_t)c->n_tiles, 1});
-    uint64_t *st;
     DDGS_TRY(ensure_t(c, "sort_counts", sort_counts_words(big), &u));
     DDGS_TRY(ensure_t(c, "sort_tot", kSortTotWords, &u));
     uint64_t *bs;
@@ -477,13 +477,15 @@ ddgs_status enqueue_front(ddgs_ctx *c)
     const int V = (int)c->views_h.size();
     const int64_t VN = (int64_t)m.n * V;
     GaussCache gc{buf<float>(c, "cov"), buf<float>(c, "alpha"), buf<float>(c, "ciso"), buf<float>(c, "hdir")};
-    ProjOut po{buf<float4>(c, "rec"), buf<uint2>(c, "rect"), buf<uint32_t>(c, "zkey"), buf<uint32_t>(c, "cnt"),
-               buf<uint32_t>(c, "skey"), buf<uint32_t>(c, "sval")};
+    ProjOut po{buf<float4>(c, "rec"),      buf<uint2>(c, "rect"),     buf<uint32_t>(c, "zkey"),
+               buf<uint32_t>(c, "cnt"),    buf<uint32_t>(c, "skey"),  buf<uint32_t>(c, "sval"),
+               buf<uint32_t>(c, "slot_lp"), buf<uint32_t>(c, "slot_btot")};
     const RenderOpts ro = render_opts(c->opt);
     stage_begin(c, DDGS_T_PROJECT);
     HIP_TRY(c, launch_fill_u32(flags_ptr(c), 0u, 1, s));
     HIP_TRY(c, launch_prep(m, gc, s));
     HIP_TRY(c, launch_project(m, gc, buf<ViewDev>(c, "views"), V, ro, po, s));
+    HIP_TRY(c, launch_slot_base(po.slot_btot, (int64_t)V * slot_blocks(m.n), s));
     stage_end(c, DDGS_T_PROJECT);
     stage_begin(c, DDGS_T_SORT);
     bool in_k1 = false;
@@ -508,8 +510,7 @@ ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, int64_t sort_n, float *images
     const uint32_t *order = sval;
     uint32_t *tkey = buf<uint32_t>(c, "tkey"), *tval = buf<uint32_t>(c, "tval");
     HIP_TRY(c, launch_emit(VN, n, order, buf<uint32_t>(c, "off_sorted"), buf<uint32_t>(c, "cnt_sorted"),
-                           buf<uint2>(c, "rect"), buf<ViewDev>(c, "views"), buf<uint32_t>(c, "offs"),
-                           buf<float4>(c, "rec"), tkey, tval, (uint32_t)cap, total_ptr(c), mdev_ptr(c),
+                           buf<uint2>(c, "rect"), buf<ViewDev>(c, "views"), tkey, tval, (uint32_t)cap, total_ptr(c), mdev_ptr(c),
                            flags_ptr(c), buf<uint2>(c, "ranges"), c->n_tiles, s));
     if (c->keep_unsorted) {
         HIP_TRY(c, launch_copy_u32(buf<uint32_t>(c, "ukey"), tkey, mdev_ptr(c), sort_n, s));
@@ -597,7 +598,8 @@ ddgs_status enqueue_backward(ddgs_ctx *c, const float *dL, const ddgs_grads *g, 
     ra.nlast = buf<uint32_t>(c, "nlast");
     ra.dL_dimg = dL;
     ra.rect = buf<uint2>(c, "rect");
-    ra.offs = buf<uint32_t>(c, "offs");
+    ra.slot_bofs = buf<uint32_t>(c, "slot_btot");
+    ra.slot_nblk = (int)slot_blocks(n);
     ra.slot = buf<float4>(c, "slot");
     ra.slot_cap = (uint32_t)std::min<int64_t>(slot_cap, 0xFFFFFFFFll);
     stage_begin(c, DDGS_T_RASTER_BWD);
@@ -614,7 +616,9 @@ ddgs_status enqueue_backward(ddgs_ctx *c, const float *dL, const ddgs_grads *g, 
     pa.V = V;
     pa.o = render_opts(c->opt);
     pa.cnt = buf<uint32_t>(c, "cnt");
-    pa.offs = buf<uint32_t>(c, "offs");
+    pa.slot_lp = buf<uint32_t>(c, "slot_lp");
+    pa.slot_bofs = buf<uint32_t>(c, "slot_btot");
+    pa.slot_nblk = (int)slot_blocks(n);
     pa.slot = buf<float4>(c, "slot");
     pa.dmean = g->dmean;
     pa.dquat = g->dquat;

@@ -55,19 +55,39 @@ struct GaussCache {
     float *hdir;   // [k_L][n - n_iso]: B_dir f for directional Gaussians
 };
 
+// Gaussians per block of the projection (and of the slot numbering).
+constexpr int kSlotBlock = 256;
+inline int64_t slot_blocks(int64_t n) { return (n + kSlotBlock - 1) / kSlotBlock; }
+
 // Per (view, Gaussian) projection output.
 struct ProjOut {
     float4 *rec;     // [V*n][4], 64 B (one cache line) per pair: (mx, my, A00, A01),
-                     // (A11, alpha, c, bits of the first entry index, written at
-                     // emission), (bits of rect.x, rect.y, 0, 0), unused
+                     // (A11, alpha, c, bits of the pair's place in its block's
+                     // slot numbering), (bits of rect.x, rect.y, 0, 0), unused
     uint2 *rect;     // [V*n]: (tx0 | ty0 << 16, tx1 | ty1 << 16), inclusive
     uint32_t *zkey;  // [V*n]: float bits of the source-frame depth, ~0u if culled
     uint32_t *cnt;   // [V*n]: number of tiles touched
     uint32_t *sort_key, *sort_val;  // [V*n]: depth key and v*n+i, input of the depth sort
+    // gradient-slot numbering in (view, Gaussian) order: each block of
+    // kSlotBlock Gaussians of a view stores its exclusive scan of the tile
+    // counts (slot_lp, [V*n]) and its total (slot_btot, [V * slot_blocks(n)]),
+    // which launch_slot_base turns into the blocks' first slots
+    uint32_t *slot_lp, *slot_btot;
 };
 
+// First gradient slot of pair (v, i): its block's first slot (bofs, from
+// launch_slot_base) plus its place in the block (lp, the projection's
+// block scan).  The slots of one Gaussian are consecutive, row-major over
+// its tile rectangle, and the pairs' slot ranges follow (view, Gaussian)
+// order, so the projection backward reads them with neighbouring lanes on
+// neighbouring ranges.
+__device__ __forceinline__ uint32_t first_slot(const uint32_t *bofs, int nblk, int v, int i, uint32_t lp)
+{
+    return bofs[(size_t)v * nblk + i / kSlotBlock] + lp;
+}
+
 // Per-(view, Gaussian) image-plane gradient terms accumulated by the raster
-// backward, one 8-float slot per tile entry in emission order: with
+// backward, one 8-float slot per tile entry (numbered by first_slot): with
 // q = dL/ds G at each hit pixel (0 where sigma_max clamps) and (dx, dy) =
 // pixel - mean, the sums over the tile's pixels of q dx, q dy, q dx^2,
 // q dx dy, q dy^2, q, and dL/dc, then 0.
@@ -181,7 +201,9 @@ struct ProjBwdArgs {
     const ViewDev *views;
     int V;
     RenderOpts o;
-    const uint32_t *cnt, *offs;
+    const uint32_t *cnt;
+    const uint32_t *slot_lp, *slot_bofs;  // slot numbering (first_slot)
+    int slot_nblk;
     const float4 *slot;
     float *dmean, *dquat, *dlog_scale, *dopacity, *dfeat;  // NULL: skip
     float *ubuf;        // [n][16] (NULL: skip basis terms)
@@ -217,6 +239,9 @@ struct SortWs {
 size_t sort_counts_words(int64_t n);
 size_t sort_blocksum_words(int64_t n);
 // out[i] = sum_{j<i} in[g(j)] with g = gather ? gather[j] : j; *total (device u64) = sum.
+// In-place exclusive scan of the nb block totals of the slot numbering (one
+// workgroup; the sum wraps at 2^32 like the slot indices themselves).
+hipError_t launch_slot_base(uint32_t *btot, int64_t nb, hipStream_t s);
 hipError_t launch_exclusive_scan(const uint32_t *in, const uint32_t *gather, uint32_t *out, int64_t n,
                                  const SortWs &ws, uint64_t *total, hipStream_t s);
 // Sorts (keys, vals) by key bits [0, bits) (stable).  n_dev (may be NULL)
@@ -226,11 +251,9 @@ hipError_t launch_exclusive_scan(const uint32_t *in, const uint32_t *gather, uin
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n_cap,
                             const uint32_t *n_dev, int bits, const SortWs &ws, bool *in_k1, hipStream_t s,
                             const uint32_t *gsrc = nullptr, uint32_t *gdst = nullptr);
-// (also stores each pair's first entry index into its record, rec[4 i + 1].w,
-// and clears the n_tiles tile ranges; cnt_sorted: tile counts in depth order)
+// (also clears the n_tiles tile ranges; cnt_sorted: tile counts in depth order)
 hipError_t launch_emit(int64_t VN, int n, const uint32_t *order, const uint32_t *off_sorted,
-                       const uint32_t *cnt_sorted, const uint2 *rect, const ViewDev *views,
-                       uint32_t *offs, float4 *rec, uint32_t *tkey, uint32_t *tval, uint32_t capacity,
+                       const uint32_t *cnt_sorted, const uint2 *rect, const ViewDev *views, uint32_t *tkey, uint32_t *tval, uint32_t capacity,
                        const uint64_t *total, uint32_t *m_out, uint32_t *flags, uint2 *ranges, int n_tiles,
                        hipStream_t s);
 // zero: clear the ranges first (else they must already be clear)
@@ -266,7 +289,8 @@ struct RasterArgs {
     // backward
     const float *dL_dimg;
     const uint2 *rect;
-    const uint32_t *offs;
+    const uint32_t *slot_bofs;  // slot numbering (first_slot; the place in the block is in the record)
+    int slot_nblk;
     float4 *slot;
     uint32_t slot_cap;
 };

@@ -209,70 +209,93 @@ template <int L>
 __global__ __launch_bounds__(kBlock) void project_kernel(ModelDev m, GaussCache gc, const ViewDev *views,
                                                          RenderOpts o, ProjOut po)
 {
+    static_assert(kBlock == kSlotBlock, "one projection block per block of the slot numbering");
     constexpr int KL = L * (L + 2);
     const int n = m.n;
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
     const int v = blockIdx.y;
-    const ViewDev V = views[v];
     const size_t vi = (size_t)v * n + i;
-    const float mx = m.mean[i], my = m.mean[n + i], mz = m.mean[2 * n + i];
-    float cw[6];
-#pragma unroll
-    for (int a = 0; a < 6; ++a) cw[a] = gc.cov[a * n + i];
-    Geom g;
-    const bool ok = project_geom(V, mx, my, mz, cw, o, g);
-    if (!ok) {
-        po.zkey[vi] = 0xFFFFFFFFu;
-        po.sort_key[vi] = 0xFFFFFFFFu;
-        po.sort_val[vi] = (uint32_t)vi;
-        po.cnt[vi] = 0;
-        po.rect[vi] = make_uint2(0, 0);
-        po.rec[4 * vi] = make_float4(0.f, 0.f, 0.f, 0.f);
-        po.rec[4 * vi + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
-        po.rec[4 * vi + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
-        return;
-    }
-    float c;
-    if (m.c_override) {
-        c = m.c_override[vi];
-    } else if (i < m.n_iso) {
-        c = gc.ciso[i];
-    } else {
-        const int nd = n - m.n_iso, id = i - m.n_iso;
-        float rx = mx - V.so[0], ry = my - V.so[1], rz = mz - V.so[2];
-        const float il = 1.0f / sqrtf(rx * rx + ry * ry + rz * rz);
-        float Y[KL];
-        sh_basis<L>(rx * il, ry * il, rz * il, Y);
-        float zl = m.entangled ? gc.ciso[i] : 0.0f;
-#pragma unroll
-        for (int r = 0; r < KL; ++r) zl += Y[r] * gc.hdir[(size_t)r * nd + id];
-        c = sigmoidf(zl);
-    }
-    // conservative pixel box of the kappa ellipse: half-widths kappa sqrt(S00),
-    // kappa sqrt(S11), widened for float rounding of the per-pixel test
-    const float rxp = o.kappa * sqrtf(g.a) * 1.0005f + 0.01f;
-    const float ryp = o.kappa * sqrtf(g.c) * 1.0005f + 0.01f;
-    const float fu0 = fmaxf(ceilf(g.mux - rxp - 0.5f), 0.0f);
-    const float fu1 = fminf(floorf(g.mux + rxp - 0.5f), (float)(V.W - 1));
-    const float fv0 = fmaxf(ceilf(g.muy - ryp - 0.5f), 0.0f);
-    const float fv1 = fminf(floorf(g.muy + ryp - 0.5f), (float)(V.H - 1));
     uint32_t count = 0;
-    uint2 rc = make_uint2(0, 0);
-    if (fu0 <= fu1 && fv0 <= fv1) {
-        const int tx0 = (int)fu0 / o.tile_w, tx1 = (int)fu1 / o.tile_w;
-        const int ty0 = (int)fv0 / o.tile_h, ty1 = (int)fv1 / o.tile_h;
-        count = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-        rc = make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16));
+    float4 r1 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (i < n) {
+        const ViewDev V = views[v];
+        const float mx = m.mean[i], my = m.mean[n + i], mz = m.mean[2 * n + i];
+        float cw[6];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) cw[a] = gc.cov[a * n + i];
+        Geom g;
+        const bool ok = project_geom(V, mx, my, mz, cw, o, g);
+        if (!ok) {
+            po.zkey[vi] = 0xFFFFFFFFu;
+            po.sort_key[vi] = 0xFFFFFFFFu;
+            po.sort_val[vi] = (uint32_t)vi;
+            po.cnt[vi] = 0;
+            po.rect[vi] = make_uint2(0, 0);
+            po.rec[4 * vi] = make_float4(0.f, 0.f, 0.f, 0.f);
+            po.rec[4 * vi + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
+        } else {
+            float c;
+            if (m.c_override) {
+                c = m.c_override[vi];
+            } else if (i < m.n_iso) {
+                c = gc.ciso[i];
+            } else {
+                const int nd = n - m.n_iso, id = i - m.n_iso;
+                float rx = mx - V.so[0], ry = my - V.so[1], rz = mz - V.so[2];
+                const float il = 1.0f / sqrtf(rx * rx + ry * ry + rz * rz);
+                float Y[KL];
+                sh_basis<L>(rx * il, ry * il, rz * il, Y);
+                float zl = m.entangled ? gc.ciso[i] : 0.0f;
+#pragma unroll
+                for (int r = 0; r < KL; ++r) zl += Y[r] * gc.hdir[(size_t)r * nd + id];
+                c = sigmoidf(zl);
+            }
+            // conservative pixel box of the kappa ellipse: half-widths kappa sqrt(S00),
+            // kappa sqrt(S11), widened for float rounding of the per-pixel test
+            const float rxp = o.kappa * sqrtf(g.a) * 1.0005f + 0.01f;
+            const float ryp = o.kappa * sqrtf(g.c) * 1.0005f + 0.01f;
+            const float fu0 = fmaxf(ceilf(g.mux - rxp - 0.5f), 0.0f);
+            const float fu1 = fminf(floorf(g.mux + rxp - 0.5f), (float)(V.W - 1));
+            const float fv0 = fmaxf(ceilf(g.muy - ryp - 0.5f), 0.0f);
+            const float fv1 = fminf(floorf(g.muy + ryp - 0.5f), (float)(V.H - 1));
+            uint2 rc = make_uint2(0, 0);
+            if (fu0 <= fu1 && fv0 <= fv1) {
+                const int tx0 = (int)fu0 / o.tile_w, tx1 = (int)fu1 / o.tile_w;
+                const int ty0 = (int)fv0 / o.tile_h, ty1 = (int)fv1 / o.tile_h;
+                count = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+                rc = make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16));
+            }
+            po.zkey[vi] = g.zbits;
+            po.sort_key[vi] = g.zbits;
+            po.sort_val[vi] = (uint32_t)vi;
+            po.cnt[vi] = count;
+            po.rect[vi] = rc;
+            po.rec[4 * vi] = make_float4(g.mux, g.muy, g.A00, g.A01);
+            r1 = make_float4(g.A11, gc.alpha[i], c, 0.0f);
+            po.rec[4 * vi + 2] = make_float4(__uint_as_float(rc.x), __uint_as_float(rc.y), 0.0f, 0.0f);
+        }
     }
-    po.zkey[vi] = g.zbits;
-    po.sort_key[vi] = g.zbits;
-    po.sort_val[vi] = (uint32_t)vi;
-    po.cnt[vi] = count;
-    po.rect[vi] = rc;
-    po.rec[4 * vi] = make_float4(g.mux, g.muy, g.A00, g.A01);
-    po.rec[4 * vi + 1] = make_float4(g.A11, gc.alpha[i], c, 0.0f);
-    po.rec[4 * vi + 2] = make_float4(__uint_as_float(rc.x), __uint_as_float(rc.y), 0.0f, 0.0f);
+    // the pair's place in its block's slot numbering (exclusive scan of the
+    // counts over the block's Gaussians, in index order) and the block total
+    __shared__ uint32_t wsum[kBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const uint32_t inc = wave_incl_scan(count);
+    if (lane == kWave - 1) wsum[w] = inc;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int q = 0; q < kBlock / kWave; ++q) {
+        const uint32_t t = wsum[q];
+        if (q < w) before += t;
+        total += t;
+    }
+    const uint32_t lp = before + inc - count;
+    if (i < n) {
+        r1.w = __uint_as_float(lp);
+        po.rec[4 * vi + 1] = r1;
+        po.slot_lp[vi] = lp;
+    }
+    if (threadIdx.x == 0) po.slot_btot[(size_t)v * gridDim.x + blockIdx.x] = total;
 }
 
 // ------------------------------------------------------------ backward chain
@@ -295,7 +318,7 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
     uint32_t c_next = 0, off_next = 0;
     if (valid && a.V > 0) {
         c_next = a.cnt[ii];
-        off_next = a.offs[ii];
+        off_next = first_slot(a.slot_bofs, a.slot_nblk, 0, ii, a.slot_lp[ii]);
     }
     // isotropic radiosity, or for entangled models the isotropic logit (read
     // early too: values derived from it are computed before the view loop)
@@ -332,7 +355,7 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
         uint32_t c = c_next, off = off_next;
         if (valid && v + 1 < a.V) {
             c_next = a.cnt[(size_t)(v + 1) * n + ii];
-            off_next = a.offs[(size_t)(v + 1) * n + ii];
+            off_next = first_slot(a.slot_bofs, a.slot_nblk, v + 1, ii, a.slot_lp[(size_t)(v + 1) * n + ii]);
         }
         // slots past the capacity do not exist (overflowed step)
         if (c > 0) {
@@ -340,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
             else if ((uint64_t)off + c > a.slot_cap) c = a.slot_cap - off;
         }
         float g7[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        // the pair's slots in emission order; four entries' loads in flight
+        // the pair's slots in rectangle order; four entries' loads in flight
         // at once (the sums keep the same order)
         uint32_t e = 0;
         for (; e + 4u <= c; e += 4u) {

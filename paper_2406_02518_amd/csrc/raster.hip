@@ -22,8 +22,9 @@
 // minus the running sum.  Per-pair image-plane gradients are summed over the
 // wave with DPP row operations (VALU only, no LDS round trip), over the
 // waves of the workgroup in LDS in a fixed order, and written once per tile
-// entry into a slot indexed by the entry's emission position -- no float
-// atomics, so the gradients are run-to-run deterministic.
+// entry into its own slot (the pair's first slot plus the tile's row-major
+// place in the pair's rectangle) -- no float atomics, so the gradients are
+// run-to-run deterministic.
 #include "internal.h"
 
 namespace ddgs {
@@ -332,7 +333,8 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
             if (j < I.e) {
                 const uint32_t gid = min(a.tval[j], (uint32_t)a.n - 1u);
                 const size_t idx = vbase + gid;
-                // one 64-byte line per pair: record, first entry index, rectangle
+                // one 64-byte line per pair: record, place in the slot
+                // numbering, rectangle
                 float4 r0 = a.rec[4 * idx];
                 const float4 r1 = a.rec[4 * idx + 1];
                 const float4 r2 = a.rec[4 * idx + 2];
@@ -341,7 +343,8 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                 s1[tid] = r1;
                 const uint32_t rx = __float_as_uint(r2.x), ry = __float_as_uint(r2.y);
                 const int tx0 = rx & 0xFFFF, ty0 = rx >> 16, tx1 = ry & 0xFFFF;
-                se[tid] = __float_as_uint(r1.w) + (uint32_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
+                se[tid] = first_slot(a.slot_bofs, a.slot_nblk, v, (int)gid, __float_as_uint(r1.w)) +
+                          (uint32_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
             }
             __syncthreads();
             if (b0 < end) {
