@@ -358,9 +358,10 @@ ddgs_status ddgs_loss(ddgs_ctx *ctx, int kind, const float *images, const float 
  * fixed tile-entry capacity (options.capacity, or twice the current need)
  * and no host synchronisation inside.  The pointers passed here are baked
  * into the graph and must stay valid.  ddgs_step_launch replays it;
- * ddgs_check synchronises and reports DDGS_ERR_CAPACITY if the last replay
- * overflowed (outputs of that replay are then invalid; capture again with a
- * larger capacity).  The model and views may change contents between
+ * ddgs_check synchronises and reports DDGS_ERR_CAPACITY if any replay (or
+ * render) since the previous ddgs_check overflowed, and clears that flag
+ * (outputs of an overflowed replay are invalid; capture again with a larger
+ * capacity).  The model and views may change contents between
  * replays but not shapes (n, views' W/H); ddgs_set_model / ddgs_set_views
  * with a different shape drop the graph. */
 ddgs_status ddgs_step_capture(ddgs_ctx *ctx, int loss_kind, const float *target, float lambda,

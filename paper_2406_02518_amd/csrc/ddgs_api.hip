@@ -254,6 +254,16 @@ int bits_for(int64_t n)
     return b;
 }
 
+// The "views" buffer holds the device views (at least one slot) followed by
+// the V + 1 first loss tiles per view.
+size_t loss_base_offset(int V) { return sizeof(ViewDev) * (size_t)std::max(1, V); }
+size_t views_bytes(int V) { return loss_base_offset(V) + sizeof(int32_t) * (size_t)(V + 1); }
+int32_t *loss_tile_base_ptr(ddgs_ctx *c)
+{
+    char *p = buf<char>(c, "views");
+    return p ? reinterpret_cast<int32_t *>(p + loss_base_offset((int)c->views_h.size())) : nullptr;
+}
+
 // Builds the device view table (tile grid depends on the tile size).
 ddgs_status prepare_views(ddgs_ctx *c)
 {
@@ -296,13 +306,12 @@ ddgs_status prepare_views(ddgs_ctx *c)
     c->loss_tiles = (int)ltiles;
     c->total_pix = pix;
     c->max_view_pix = maxp;
-    ViewDev *vd;
-    int32_t *lb;
-    DDGS_TRY(ensure_t(c, "views", std::max(1, V), &vd));
-    DDGS_TRY(ensure_t(c, "loss_tile_base", V + 1, &lb));
-    // stage through pinned host memory so the copies stay asynchronous; the
+    // one buffer, one upload: the views, then the loss tiles' bases
+    void *vp;
+    DDGS_TRY(ensure(c, "views", views_bytes(V), &vp));
+    // stage through pinned host memory so the copy stays asynchronous; the
     // staging area is reused only after the previous upload has completed
-    const size_t need = sizeof(ViewDev) * V + sizeof(int32_t) * (V + 1);
+    const size_t need = views_bytes(V);
     if (c->stage_pending) {
         HIP_TRY(c, hipEventSynchronize(c->stage_event));
         c->stage_pending = false;
@@ -315,11 +324,9 @@ ddgs_status prepare_views(ddgs_ctx *c)
         c->stage_bytes = need + 1024;
     }
     char *h = (char *)c->stage_host;
-    std::memcpy(h, c->vdev_h.data(), sizeof(ViewDev) * V);
-    std::memcpy(h + sizeof(ViewDev) * V, c->loss_tile_base_h.data(), sizeof(int32_t) * (V + 1));
-    if (V > 0) HIP_TRY(c, hipMemcpyAsync(vd, h, sizeof(ViewDev) * V, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(lb, h + sizeof(ViewDev) * V, sizeof(int32_t) * (V + 1), hipMemcpyHostToDevice,
-                              c->stream));
+    if (V > 0) std::memcpy(h, c->vdev_h.data(), sizeof(ViewDev) * V);
+    std::memcpy(h + loss_base_offset(V), c->loss_tile_base_h.data(), sizeof(int32_t) * (V + 1));
+    HIP_TRY(c, hipMemcpyAsync(vp, h, need, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipEventRecord(c->stage_event, c->stream));
     c->stage_pending = true;
     c->views_dirty = false;
@@ -359,7 +366,13 @@ ddgs_status ensure_static(ddgs_ctx *c)
     DDGS_TRY(ensure_t(c, "qval2", std::max(1, c->n_tiles), &u));
     DDGS_TRY(ensure_t(c, "img_saved", c->total_pix, &f));
     DDGS_TRY(ensure_t(c, "nlast", c->total_pix, &u));
-    DDGS_TRY(ensure_t(c, "scalars", 16, &u));
+    {
+        // the flags word is sticky (cleared by ddgs_check), so a new buffer
+        // starts cleared
+        uint32_t *prev = buf<uint32_t>(c, "scalars");
+        DDGS_TRY(ensure_t(c, "scalars", 16, &u));
+        if (u && u != prev) HIP_TRY(c, hipMemsetAsync(u, 0, sizeof(uint32_t) * 16, c->stream));
+    }
     const int64_t n_waves = ((n + 255) / 256) * 4;
     DDGS_TRY(ensure_t(c, "pose_part", (size_t)std::max<int64_t>(1, V * n_waves * 9), &f));
     DDGS_TRY(ensure_t(c, "basis_part", basis_part_floats((int)std::max<int64_t>(1, n)), &f));
@@ -425,7 +438,8 @@ void stage_end(ddgs_ctx *c, int i)
 }
 
 // device scalars: [0..1] u64 entry total, [2] entries kept (min(total, cap)),
-// [3] flags (bit 0: capacity overflow), [4], [5] work-queue counters,
+// [3] flags (bit 0: capacity overflow in some step since the last
+// ddgs_check, which clears them), [4], [5] work-queue counters,
 // [6] work items, [8..9] u64 scratch total
 uint64_t *total_ptr(ddgs_ctx *c) { return (uint64_t *)buf<uint32_t>(c, "scalars"); }
 uint32_t *mdev_ptr(ddgs_ctx *c) { return buf<uint32_t>(c, "scalars") + 2; }
@@ -482,10 +496,8 @@ ddgs_status enqueue_front(ddgs_ctx *c)
                buf<uint32_t>(c, "slot_lp"), buf<uint32_t>(c, "slot_btot")};
     const RenderOpts ro = render_opts(c->opt);
     stage_begin(c, DDGS_T_PROJECT);
-    HIP_TRY(c, launch_fill_u32(flags_ptr(c), 0u, 1, s));
     HIP_TRY(c, launch_prep(m, gc, s));
     HIP_TRY(c, launch_project(m, gc, buf<ViewDev>(c, "views"), V, ro, po, s));
-    HIP_TRY(c, launch_slot_base(po.slot_btot, (int64_t)V * slot_blocks(m.n), s));
     stage_end(c, DDGS_T_PROJECT);
     stage_begin(c, DDGS_T_SORT);
     bool in_k1 = false;
@@ -510,7 +522,8 @@ ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, int64_t sort_n, float *images
     const uint32_t *order = sval;
     uint32_t *tkey = buf<uint32_t>(c, "tkey"), *tval = buf<uint32_t>(c, "tval");
     HIP_TRY(c, launch_emit(VN, n, order, buf<uint32_t>(c, "off_sorted"), buf<uint32_t>(c, "cnt_sorted"),
-                           buf<uint2>(c, "rect"), buf<ViewDev>(c, "views"), tkey, tval, (uint32_t)cap, total_ptr(c), mdev_ptr(c),
+                           buf<uint2>(c, "rect"), buf<ViewDev>(c, "views"), tkey, tval, buf<uint32_t>(c, "slot_btot"),
+                           (int64_t)c->views_h.size() * slot_blocks(n), (uint32_t)cap, total_ptr(c), mdev_ptr(c),
                            flags_ptr(c), buf<uint2>(c, "ranges"), c->n_tiles, s));
     if (c->keep_unsorted) {
         HIP_TRY(c, launch_copy_u32(buf<uint32_t>(c, "ukey"), tkey, mdev_ptr(c), sort_n, s));
@@ -656,7 +669,7 @@ ddgs_status enqueue_loss(ddgs_ctx *c, int kind, const float *images, const float
     la.part = buf<double>(c, "loss_part");
     la.maps = buf<float>(c, "loss_maps");
     la.loss_tiles = c->loss_tiles;
-    la.loss_tile_base = buf<int32_t>(c, "loss_tile_base");
+    la.loss_tile_base = loss_tile_base_ptr(c);
     la.max_view_pix = c->max_view_pix;
     stage_begin(c, DDGS_T_LOSS);
     HIP_TRY(c, launch_loss(kind, la, c->stream));
@@ -872,8 +885,7 @@ ddgs_status ddgs_workspace_size(ddgs_ctx *c, int64_t capacity, size_t *bytes)
     c->dry_total = 0;
     const int V = (int)c->views_h.size();
     void *p;
-    ddgs_status st = ensure(c, "views", sizeof(ViewDev) * (size_t)std::max(1, V), &p);
-    if (st == DDGS_OK) st = ensure(c, "loss_tile_base", sizeof(int32_t) * (size_t)(V + 1), &p);
+    ddgs_status st = ensure(c, "views", views_bytes(V), &p);
     if (st == DDGS_OK) st = ensure_static(c);
     if (st == DDGS_OK) st = ensure_entries(c, cap);
     c->dry_run = false;
@@ -1486,6 +1498,8 @@ ddgs_status ddgs_check(ddgs_ctx *c, uint32_t *flags)
     if (buf<uint32_t>(c, "scalars"))
         HIP_TRY(c, hipMemcpy(sc, buf<uint32_t>(c, "scalars"), sizeof(sc), hipMemcpyDeviceToHost));
     if (flags) *flags = sc[3];
+    // the flags accumulate over steps until read here
+    if (sc[3]) HIP_TRY(c, hipMemsetAsync(flags_ptr(c), 0, sizeof(uint32_t), c->stream));
     const uint64_t total = (uint64_t)sc[0] | ((uint64_t)sc[1] << 32);
     if (c->M < 0) c->M = (int64_t)std::min<uint64_t>(total, (uint64_t)c->step_cap);
     if (sc[3] & 1u)

@@ -71,12 +71,12 @@ struct ProjOut {
     // gradient-slot numbering in (view, Gaussian) order: each block of
     // kSlotBlock Gaussians of a view stores its exclusive scan of the tile
     // counts (slot_lp, [V*n]) and its total (slot_btot, [V * slot_blocks(n)]),
-    // which launch_slot_base turns into the blocks' first slots
+    // which the emission turns into the blocks' first slots
     uint32_t *slot_lp, *slot_btot;
 };
 
 // First gradient slot of pair (v, i): its block's first slot (bofs, from
-// launch_slot_base) plus its place in the block (lp, the projection's
+// the emission) plus its place in the block (lp, the projection's
 // block scan).  The slots of one Gaussian are consecutive, row-major over
 // its tile rectangle, and the pairs' slot ranges follow (view, Gaussian)
 // order, so the projection backward reads them with neighbouring lanes on
@@ -239,9 +239,6 @@ struct SortWs {
 size_t sort_counts_words(int64_t n);
 size_t sort_blocksum_words(int64_t n);
 // out[i] = sum_{j<i} in[g(j)] with g = gather ? gather[j] : j; *total (device u64) = sum.
-// In-place exclusive scan of the nb block totals of the slot numbering (one
-// workgroup; the sum wraps at 2^32 like the slot indices themselves).
-hipError_t launch_slot_base(uint32_t *btot, int64_t nb, hipStream_t s);
 hipError_t launch_exclusive_scan(const uint32_t *in, const uint32_t *gather, uint32_t *out, int64_t n,
                                  const SortWs &ws, uint64_t *total, hipStream_t s);
 // Sorts (keys, vals) by key bits [0, bits) (stable).  n_dev (may be NULL)
@@ -251,9 +248,12 @@ hipError_t launch_exclusive_scan(const uint32_t *in, const uint32_t *gather, uin
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n_cap,
                             const uint32_t *n_dev, int bits, const SortWs &ws, bool *in_k1, hipStream_t s,
                             const uint32_t *gsrc = nullptr, uint32_t *gdst = nullptr);
-// (also clears the n_tiles tile ranges; cnt_sorted: tile counts in depth order)
+// (also clears the n_tiles tile ranges and turns the slot_nb block totals of
+// the slot numbering into the blocks' first slots, in place; cnt_sorted: tile
+// counts in depth order)
 hipError_t launch_emit(int64_t VN, int n, const uint32_t *order, const uint32_t *off_sorted,
-                       const uint32_t *cnt_sorted, const uint2 *rect, const ViewDev *views, uint32_t *tkey, uint32_t *tval, uint32_t capacity,
+                       const uint32_t *cnt_sorted, const uint2 *rect, const ViewDev *views, uint32_t *tkey,
+                       uint32_t *tval, uint32_t *slot_btot, int64_t slot_nb, uint32_t capacity,
                        const uint64_t *total, uint32_t *m_out, uint32_t *flags, uint2 *ranges, int n_tiles,
                        hipStream_t s);
 // zero: clear the ranges first (else they must already be clear)

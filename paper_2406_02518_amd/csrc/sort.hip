@@ -444,12 +444,36 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *k
 __global__ __launch_bounds__(kBlock) void emit_kernel(int64_t VN, int n, const uint32_t *order,
                                                       const uint32_t *off_sorted, const uint32_t *cnt_sorted,
                                                       const uint2 *rect, const ViewDev *views, uint32_t *tkey,
-                                                      uint32_t *tval,
+                                                      uint32_t *tval, uint32_t *slot_btot, int64_t slot_nb,
                                                       uint32_t capacity, const uint64_t *total, uint32_t *m_out,
                                                       uint32_t *flags, uint2 *ranges, int n_tiles)
 {
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & (kWave - 1);
+    if (blockIdx.x == 0) {
+        // block 0 also turns the slot numbering's block totals into the
+        // blocks' first slots (in-place exclusive scan, wrapping at 2^32
+        // like the slot indices)
+        __shared__ uint32_t wl[kWaves];
+        uint32_t carry = 0;
+        for (int64_t c0 = 0; c0 < slot_nb; c0 += 4 * kBlock) {
+            const int64_t b = c0 + 4 * (int64_t)threadIdx.x;
+            uint32_t x[4], s = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                x[q] = b + q < slot_nb ? slot_btot[b + q] : 0u;
+                s += x[q];
+            }
+            uint32_t tot;
+            uint32_t pre = carry + block_excl_scan(s, wl, tot);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (b + q < slot_nb) slot_btot[b + q] = pre;
+                pre += x[q];
+            }
+            carry += tot;
+        }
+    }
     // clear the tile ranges for the ranges kernel after the sort
     for (int64_t t = r; t < n_tiles; t += (int64_t)gridDim.x * kBlock) ranges[t] = make_uint2(0u, 0u);
     if (r == 0) {
@@ -580,54 +604,6 @@ __global__ void items_empty_kernel(uint32_t *n_items, uint32_t *counter)
 
 }  // namespace
 
-namespace {
-
-// One workgroup of 1024 threads scans the nb block totals in chunks of
-// 1024 x 4, carrying the running sum (u32, wrapping like the slot indices).
-__global__ __launch_bounds__(1024) void slot_base_kernel(uint32_t *btot, int64_t nb)
-{
-    constexpr int IPT = 4, CH = 1024 * IPT;
-    __shared__ uint32_t wt[16];
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    uint32_t carry = 0;
-    for (int64_t c0 = 0; c0 < nb; c0 += CH) {
-        const int64_t b = c0 + (int64_t)threadIdx.x * IPT;
-        uint32_t x[IPT], s = 0;
-#pragma unroll
-        for (int q = 0; q < IPT; ++q) {
-            x[q] = b + q < nb ? btot[b + q] : 0u;
-            s += x[q];
-        }
-        const uint32_t inc = wave_incl_scan(s);
-        if (lane == kWave - 1) wt[w] = inc;
-        __syncthreads();
-        uint32_t before = carry, tot = 0;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const uint32_t t = wt[q];
-            if (q < w) before += t;
-            tot += t;
-        }
-        uint32_t pre = before + inc - s;
-#pragma unroll
-        for (int q = 0; q < IPT; ++q) {
-            if (b + q < nb) btot[b + q] = pre;
-            pre += x[q];
-        }
-        carry += tot;
-        __syncthreads();
-    }
-}
-
-}  // namespace
-
-hipError_t launch_slot_base(uint32_t *btot, int64_t nb, hipStream_t s)
-{
-    if (nb <= 0) return hipSuccess;
-    slot_base_kernel<<<1, 1024, 0, s>>>(btot, nb);
-    return hipGetLastError();
-}
-
 hipError_t launch_exclusive_scan(const uint32_t *in, const uint32_t *gather, uint32_t *out, int64_t n,
                                  const SortWs &ws, uint64_t *total, hipStream_t s)
 {
@@ -700,12 +676,14 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
 }
 
 hipError_t launch_emit(int64_t VN, int n, const uint32_t *order, const uint32_t *off_sorted,
-                       const uint32_t *cnt_sorted, const uint2 *rect, const ViewDev *views, uint32_t *tkey, uint32_t *tval, uint32_t capacity, const uint64_t *total,
-                       uint32_t *m_out, uint32_t *flags, uint2 *ranges, int n_tiles, hipStream_t s)
+                       const uint32_t *cnt_sorted, const uint2 *rect, const ViewDev *views, uint32_t *tkey,
+                       uint32_t *tval, uint32_t *slot_btot, int64_t slot_nb, uint32_t capacity,
+                       const uint64_t *total, uint32_t *m_out, uint32_t *flags, uint2 *ranges, int n_tiles,
+                       hipStream_t s)
 {
     const int64_t nb = std::max<int64_t>(1, blocks_for(VN, kBlock));
-    emit_kernel<<<(unsigned)nb, kBlock, 0, s>>>(VN, n, order, off_sorted, cnt_sorted, rect, views, tkey,
-                                                tval, capacity, total, m_out, flags, ranges, n_tiles);
+    emit_kernel<<<(unsigned)nb, kBlock, 0, s>>>(VN, n, order, off_sorted, cnt_sorted, rect, views, tkey, tval,
+                                                slot_btot, slot_nb, capacity, total, m_out, flags, ranges, n_tiles);
     return hipGetLastError();
 }
 

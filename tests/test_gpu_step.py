@@ -132,6 +132,35 @@ def test_capacity_overflow_is_reported_not_faulted(R):
     _same(_launch(R, bufs), plain)
 
 
+def test_capacity_overflow_flag_persists_until_checked(R):
+    """An overflowed replay followed by one that fits is still reported, once:
+    the flag accumulates over replays and ddgs_check clears it."""
+    c = synth.config("C4", scale=0.05)
+    R.set_scene(c.scene)
+    counts = []
+    for v in c.views[:8]:
+        R.set_views([v])
+        R.render()
+        counts.append(R.num_rendered())
+    lo, hi = int(np.argmin(counts)), int(np.argmax(counts))
+    assert counts[hi] >= counts[lo] + 2, counts
+    target = torch.zeros(R.image_size(), device="cuda")
+    R.set_views([c.views[lo]])
+    R.set_options(capacity=(counts[lo] + counts[hi]) // 2)
+    _capture(R, binding.LOSS_LINEAR, target, 0.0, binding.GRAD_NAMES)
+    assert binding.ddgs_check(R.ctx, raise_on_error=False) == (binding.OK, 0)
+    R.set_views([c.views[hi]])
+    binding.ddgs_step_launch(R.ctx)  # needs more entries than the capacity
+    R.set_views([c.views[lo]])
+    binding.ddgs_step_launch(R.ctx)  # fits
+    st, flags = binding.ddgs_check(R.ctx, raise_on_error=False)
+    assert st == binding.ERR_CAPACITY and flags & 1
+    assert binding.ddgs_check(R.ctx, raise_on_error=False) == (binding.OK, 0)
+    binding.ddgs_step_launch(R.ctx)
+    assert binding.ddgs_check(R.ctx, raise_on_error=False) == (binding.OK, 0)
+    R.set_options(capacity=0)
+
+
 def test_backward_before_render_is_a_state_error(R):
     c = synth.config("C1")
     R.set_scene(c.scene)
