@@ -117,11 +117,33 @@ __global__ __launch_bounds__(kBlock) void ssim_fwd_kernel(LossArgs a, Window win
     }
 }
 
+// Loss of view v from the per-tile partial sums of the forward (one block of
+// 256 threads; FP64 sums in a fixed order).
+__device__ void ssim_final_view(const LossArgs &a, int v)
+{
+    const int t0 = a.loss_tile_base[v], t1 = a.loss_tile_base[v + 1];
+    double x[2] = {0.0, 0.0};
+    for (int t = t0 + threadIdx.x; t < t1; t += 256) {
+        x[0] += a.part[2 * (size_t)t];
+        x[1] += a.part[2 * (size_t)t + 1];
+    }
+    __shared__ double red[4 * 2];
+    block_sum_d<2>(x, red);
+    if (threadIdx.x == 0 && a.loss_out) {
+        const ViewDev &V = a.views[v];
+        const double P = (double)V.W * (double)V.H;
+        a.loss_out[v] = (float)((1.0 - a.lambda) * x[1] / P + a.lambda * (1.0 - x[0] / P));
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void ssim_bwd_kernel(LossArgs a, Window win)
 {
     __shared__ float sm[3][kHalo][kHalo + 1];
     __shared__ float hs[3][kHalo][kTS + 1];
     const int t = blockIdx.x;
+    // the forward's partial sums are complete: the first V blocks also
+    // finish the views' loss values (every view has at least one tile)
+    if (t < a.V) ssim_final_view(a, t);
     const int v = tile_view(a.loss_tile_base, a.V, t);
     const ViewDev &V = a.views[v];
     const int ntx = (V.W + kTS - 1) / kTS;
@@ -167,23 +189,7 @@ __global__ __launch_bounds__(kBlock) void ssim_bwd_kernel(LossArgs a, Window win
     a.grad[p] = ((1.0f - a.lambda) * sg - a.lambda * (f0 + 2.0f * xv * f1 + yv * f2)) / P;
 }
 
-__global__ __launch_bounds__(256) void ssim_final_kernel(LossArgs a)
-{
-    const int v = blockIdx.x;
-    const int t0 = a.loss_tile_base[v], t1 = a.loss_tile_base[v + 1];
-    double x[2] = {0.0, 0.0};
-    for (int t = t0 + threadIdx.x; t < t1; t += 256) {
-        x[0] += a.part[2 * (size_t)t];
-        x[1] += a.part[2 * (size_t)t + 1];
-    }
-    __shared__ double red[4 * 2];
-    block_sum_d<2>(x, red);
-    if (threadIdx.x == 0 && a.loss_out) {
-        const ViewDev &V = a.views[v];
-        const double P = (double)V.W * (double)V.H;
-        a.loss_out[v] = (float)((1.0 - a.lambda) * x[1] / P + a.lambda * (1.0 - x[0] / P));
-    }
-}
+__global__ __launch_bounds__(256) void ssim_final_kernel(LossArgs a) { ssim_final_view(a, blockIdx.x); }
 
 // ------------------------------------------------------------------- NCC
 
@@ -303,7 +309,7 @@ hipError_t launch_loss(int kind, const LossArgs &a, hipStream_t s)
         const Window w = make_window();
         ssim_fwd_kernel<<<a.loss_tiles, kBlock, 0, s>>>(a, w);
         if (a.grad) ssim_bwd_kernel<<<a.loss_tiles, kBlock, 0, s>>>(a, w);
-        ssim_final_kernel<<<a.V, 256, 0, s>>>(a);
+        else ssim_final_kernel<<<a.V, 256, 0, s>>>(a);
         return hipGetLastError();
     }
     const int nchunks = (int)((maxP + kChunk - 1) / kChunk);

@@ -545,15 +545,38 @@ __global__ __launch_bounds__(kBlock) void copy_u32_kernel(uint32_t *dst, const u
         dst[i] = src[i];
 }
 
+// Each thread takes kRangesIPT consecutive sorted keys (one 16-byte load
+// where all four exist, plus the key before and the key after) and marks
+// where a tile's run starts and ends.
+constexpr int kRangesIPT = 4;
+
 __global__ __launch_bounds__(kBlock) void ranges_kernel(const uint32_t *keys, const uint32_t *m_dev, int64_t m_cap,
                                                         uint2 *ranges, int n_tiles)
 {
     const int64_t m = runtime_n(m_cap, m_dev);
-    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < m; j += (int64_t)gridDim.x * kBlock) {
-        const uint32_t k = keys[j];
-        if (k >= (uint32_t)n_tiles) continue;
-        if (j == 0 || keys[j - 1] != k) ranges[k].x = (uint32_t)j;
-        if (j == m - 1 || keys[j + 1] != k) ranges[k].y = (uint32_t)(j + 1);
+    const int64_t stride = (int64_t)gridDim.x * kBlock * kRangesIPT;
+    for (int64_t j0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * kRangesIPT; j0 < m; j0 += stride) {
+        // k[q + 1] = keys[j0 + q]; k[0], k[kRangesIPT + 1]: the neighbours
+        // (indices clamped into [0, m); the ends are tested by position)
+        uint32_t k[kRangesIPT + 2];
+        k[0] = keys[j0 > 0 ? j0 - 1 : 0];
+        k[kRangesIPT + 1] = keys[j0 + kRangesIPT < m ? j0 + kRangesIPT : m - 1];
+        if (j0 + kRangesIPT <= m) {
+            const uint4 x = *reinterpret_cast<const uint4 *>(keys + j0);
+            k[1] = x.x; k[2] = x.y; k[3] = x.z; k[4] = x.w;
+        } else {
+#pragma unroll
+            for (int q = 1; q <= kRangesIPT; ++q) k[q] = keys[j0 - 1 + q < m ? j0 - 1 + q : m - 1];
+        }
+#pragma unroll
+        for (int q = 0; q < kRangesIPT; ++q) {
+            const int64_t j = j0 + q;
+            const uint32_t kk = k[q + 1];
+            if (j < m && kk < (uint32_t)n_tiles) {
+                if (j == 0 || k[q] != kk) ranges[kk].x = (uint32_t)j;
+                if (j == m - 1 || k[q + 2] != kk) ranges[kk].y = (uint32_t)(j + 1);
+            }
+        }
     }
 }
 
@@ -595,6 +618,32 @@ hipError_t scan_launch(In f, int64_t n, Out o, const SortWs &ws, uint64_t *total
     return hipGetLastError();
 }
 
+// Work items in one launch for up to kItemsSelfMax tiles: block b (one tile
+// per thread) first sums the item counts of the tiles before its own, read
+// directly from the ranges, then scans its own; the last block stores the
+// total.
+constexpr int64_t kItemsSelfMax = 16384;
+
+__global__ __launch_bounds__(kBlock) void items_self_kernel(ChunkIn f, int n, ItemsOut o, uint64_t *total)
+{
+    __shared__ uint32_t wl[kWaves];
+    const int base = blockIdx.x * kBlock;
+    uint32_t c = 0;
+#pragma unroll 4
+    for (int t = threadIdx.x; t < base; t += kBlock) c += f(t);
+    uint32_t carry;
+    (void)block_excl_scan(c, wl, carry);
+    const int t = base + threadIdx.x;
+    const uint32_t v = t < n ? f(t) : 0u;
+    uint32_t tot;
+    const uint32_t pre = carry + block_excl_scan(v, wl, tot);
+    if (t < n) o(t, pre, v);
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        if (total) *total = carry + tot;
+        o.finish(carry + tot);
+    }
+}
+
 __global__ void items_empty_kernel(uint32_t *n_items, uint32_t *counter)
 {
     *n_items = 0;
@@ -621,8 +670,13 @@ hipError_t launch_items(const uint2 *ranges, int n_tiles, int split, uint32_t *c
         items_empty_kernel<<<1, 1, 0, s>>>(n_items, counter);
         return hipGetLastError();
     }
-    return scan_launch<1>(ChunkIn{ranges, (uint32_t)split}, n_tiles,
-                       ItemsOut{cnt, base, items, max_items, n_items, counter}, ws, scan_total, s);
+    const ChunkIn f{ranges, (uint32_t)split};
+    const ItemsOut o{cnt, base, items, max_items, n_items, counter};
+    if (n_tiles <= kItemsSelfMax) {
+        items_self_kernel<<<(unsigned)blocks_for(n_tiles, kBlock), kBlock, 0, s>>>(f, n_tiles, o, scan_total);
+        return hipGetLastError();
+    }
+    return scan_launch<1>(f, n_tiles, o, ws, scan_total, s);
 }
 
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n_cap,
@@ -692,7 +746,7 @@ hipError_t launch_ranges(const uint32_t *keys, const uint32_t *m_dev, int64_t m_
 {
     if (zero && n_tiles > 0) zero_ranges_kernel<<<(unsigned)blocks_for(n_tiles, kBlock), kBlock, 0, s>>>(ranges, n_tiles);
     if (m_cap > 0) {
-        const int64_t nb = std::min<int64_t>(blocks_for(m_cap, kBlock), 65536);
+        const int64_t nb = std::min<int64_t>(blocks_for(m_cap, (int64_t)kBlock * kRangesIPT), 65536);
         ranges_kernel<<<(unsigned)nb, kBlock, 0, s>>>(keys, m_dev, m_cap, ranges, n_tiles);
     }
     return hipGetLastError();
