@@ -351,7 +351,6 @@ ddgs_status ensure_static(ddgs_ctx *c)
     DDGS_TRY(ensure_t(c, "alpha", n, &f));
     DDGS_TRY(ensure_t(c, "ciso", n, &f));
     DDGS_TRY(ensure_t(c, "hdir", (size_t)KL * std::max<int64_t>(1, n - c->model.n_iso), &f));
-    DDGS_TRY(ensure_t(c, "ubuf", (size_t)16 * n, &f));
     float4 *f4;
     DDGS_TRY(ensure_t(c, "rec", 4 * VN, &f4));
     uint2 *u2;
@@ -638,7 +637,7 @@ ddgs_status enqueue_backward(ddgs_ctx *c, const float *dL, const ddgs_grads *g, 
     pa.dlog_scale = g->dlog_scale;
     pa.dopacity = g->dopacity_logit;
     pa.dfeat = g->dfeat;
-    pa.ubuf = (g->db_iso || g->dB_dir) ? buf<float>(c, "ubuf") : nullptr;
+    pa.bpart = (g->db_iso || g->dB_dir) ? buf<float>(c, "basis_part") : nullptr;
     pa.pose_part = buf<float>(c, "pose_part");
     pa.per_gaussian = per_g ? 1 : 0;
     pa.slot_cap = ra.slot_cap;
@@ -646,7 +645,6 @@ ddgs_status enqueue_backward(ddgs_ctx *c, const float *dL, const ddgs_grads *g, 
     pa.st_cnt = c->st_cnt;
     pa.st_rad = c->st_rad;
     HIP_TRY(c, launch_project_bwd(pa, s));
-    if (g->db_iso || g->dB_dir) HIP_TRY(c, launch_basis_grad(pa.m, pa.ubuf, buf<float>(c, "basis_part"), s));
     const int n_waves = ((n + 255) / 256) * 4;
     HIP_TRY(c, launch_grad_final(pa.m, buf<float>(c, "basis_part"), g->db_iso, g->dB_dir, buf<ViewDev>(c, "views"), V,
                                  n_waves, buf<float>(c, "pose_part"), g->dpose, s));

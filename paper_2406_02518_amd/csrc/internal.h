@@ -192,9 +192,10 @@ hipError_t launch_project(const ModelDev &m, const GaussCache &gc, const ViewDev
 
 // Backward of the projection: sums each (view, Gaussian)'s gradient slots,
 // applies the chain rule to the parameters, and writes per-wave pose partials
-// [V][n_waves][9] and per-Gaussian basis terms ubuf ([n][16]: the k_L
-// direction terms of a directional Gaussian, or d z of an isotropic one in
-// column 15).
+// [V][n_waves][9] and, per block of kSlotBlock Gaussians, its share of the
+// basis gradients: the 16 x NCOL tile U F^T over the block's Gaussians, with
+// row r < k_L of U the direction terms of a directional Gaussian and row 15
+// the isotropic logit's gradient (NCOL = 16 or 32 columns of features).
 struct ProjBwdArgs {
     ModelDev m;
     GaussCache gc;
@@ -206,7 +207,7 @@ struct ProjBwdArgs {
     int slot_nblk;
     const float4 *slot;
     float *dmean, *dquat, *dlog_scale, *dopacity, *dfeat;  // NULL: skip
-    float *ubuf;        // [n][16] (NULL: skip basis terms)
+    float *bpart;       // [blocks][16][NCOL] basis tiles (NULL: skip)
     float *pose_part;   // [V][n_waves][9]
     int per_gaussian;   // 0: pose only
     uint32_t slot_cap;  // number of gradient slots (entries beyond are ignored)
@@ -215,10 +216,8 @@ struct ProjBwdArgs {
     float *st_grad, *st_cnt, *st_rad;
 };
 hipError_t launch_project_bwd(const ProjBwdArgs &a, hipStream_t s);
-// d b_iso, d B_dir: per-wave 16 x 32 MFMA tiles in part, then an FP64 sum
-int basis_grad_waves(int n);
+// floats of the basis tiles of the projection backward (one per block)
 size_t basis_part_floats(int n);
-hipError_t launch_basis_grad(const ModelDev &m, const float *ubuf, float *part, hipStream_t s);
 // FP64 sums of the basis tiles (when db or dB) and of the pose partials (when
 // dpose), in one launch
 hipError_t launch_grad_final(const ModelDev &m, const float *bpart, float *db, float *dB, const ViewDev *views,

@@ -14,6 +14,8 @@ namespace {
 
 constexpr int kBlock = 256;
 
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
 // Real orthonormal spherical basis of degrees 1..L at the unit direction
 // (x, y, z): order l = 1..L, m = -l..l, no Condon-Shortley phase.  The
 // normalisations are sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!) times the factor
@@ -329,6 +331,35 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
     float cw[6];
 #pragma unroll
     for (int q = 0; q < 6; ++q) cw[q] = a.gc.cov[q * n + ii];
+    // basis-gradient operands staged in LDS (used at the end): the features
+    // are read here, with the other parameters, so that their latency overlaps
+    // (the B operands of the basis contraction -- features in the matrix
+    // cores' layout, lane l holding feature t 16 + l % 16 of the wave's
+    // Gaussian 4 s + l / 16 for step s -- are read here, with the other
+    // parameters, and used at the end; sU holds each wave's U rows and then
+    // its tile, s_done counts the block's finished waves)
+    constexpr int NTILE = (KMAX + 15) / 16, NCOL = NTILE * 16;
+    constexpr int NW = kBlock / kWave;
+    static_assert(16 * NCOL <= kWave * 17, "a wave tile fits in the wave's U rows");
+    __shared__ float sU[NW][kWave][17];
+    __shared__ uint32_t s_done;
+    const int w = threadIdx.x / kWave;
+    const int ri = lane & 15, kk = lane >> 4;
+    float fb[kWave / 4][NTILE];
+    if (a.bpart) {
+        if (threadIdx.x == 0) s_done = 0;
+        __syncthreads();
+        const int g0 = blockIdx.x * kBlock + w * kWave;  // the wave's first Gaussian
+#pragma unroll
+        for (int st = 0; st < kWave / 4; ++st)
+#pragma unroll
+            for (int t = 0; t < NTILE; ++t) {
+                const int g = g0 + 4 * st + kk, j = t * 16 + ri;
+                // (a clamped index for lanes past the end or past k; masked below)
+                const float x = a.m.feat[(size_t)min(j, k - 1) * n + min(g, n - 1)];
+                fb[st][t] = (g < n && j < k && a.per_gaussian) ? x : 0.0f;
+            }
+    }
     float h[KL];
 #pragma unroll
     for (int r = 0; r < KL; ++r) h[r] = 0.0f;
@@ -533,145 +564,131 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
         a.st_cnt[i] += st_cnt;
         a.st_rad[i] = fmaxf(a.st_rad[i], st_rad);
     }
-    if (!valid || !a.per_gaussian) return;
-
-    // Sigma = M M^T, M = Rq diag(s): dL/dM = 2 GSw M
-    float qw = a.m.quat[i], qx = a.m.quat[n + i], qy = a.m.quat[2 * n + i], qz = a.m.quat[3 * n + i];
-    const float qnorm = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
-    const float iq = 1.0f / qnorm;
-    qw *= iq; qx *= iq; qy *= iq; qz *= iq;
-    float Rq[9];
-    quat_rot(qw, qx, qy, qz, Rq);
-    float s[3];
+    if (valid && a.per_gaussian) {
+        // Sigma = M M^T, M = Rq diag(s): dL/dM = 2 GSw M
+        float qw = a.m.quat[i], qx = a.m.quat[n + i], qy = a.m.quat[2 * n + i], qz = a.m.quat[3 * n + i];
+        const float qnorm = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+        const float iq = 1.0f / qnorm;
+        qw *= iq; qx *= iq; qy *= iq; qz *= iq;
+        float Rq[9];
+        quat_rot(qw, qx, qy, qz, Rq);
+        float s[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) s[q] = expf(a.m.log_scale[q * n + i]);
-    const float Gs[9] = {GSw[0], GSw[1], GSw[2], GSw[1], GSw[3], GSw[4], GSw[2], GSw[4], GSw[5]};
-    float GR[9];
-    float gls[3];
+        for (int q = 0; q < 3; ++q) s[q] = expf(a.m.log_scale[q * n + i]);
+        const float Gs[9] = {GSw[0], GSw[1], GSw[2], GSw[1], GSw[3], GSw[4], GSw[2], GSw[4], GSw[5]};
+        float GR[9];
+        float gls[3];
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-        float acc = 0.0f;
+        for (int b = 0; b < 3; ++b) {
+            float acc = 0.0f;
 #pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            // GM[r][b] = 2 sum_q Gs[r][q] M[q][b], M[q][b] = Rq[q][b] s[b]
-            const float gm = 2.0f * (Gs[3 * r] * Rq[b] + Gs[3 * r + 1] * Rq[3 + b] + Gs[3 * r + 2] * Rq[6 + b]) * s[b];
-            acc += gm * Rq[3 * r + b];
-            GR[3 * r + b] = gm * s[b];
+            for (int r = 0; r < 3; ++r) {
+                // GM[r][b] = 2 sum_q Gs[r][q] M[q][b], M[q][b] = Rq[q][b] s[b]
+                const float gm =
+                    2.0f * (Gs[3 * r] * Rq[b] + Gs[3 * r + 1] * Rq[3 + b] + Gs[3 * r + 2] * Rq[6 + b]) * s[b];
+                acc += gm * Rq[3 * r + b];
+                GR[3 * r + b] = gm * s[b];
+            }
+            gls[b] = acc * s[b];
         }
-        gls[b] = acc * s[b];
-    }
-    float gq[4];
-    gq[0] = 2.0f * (-qz * GR[1] + qy * GR[2] + qz * GR[3] - qx * GR[5] - qy * GR[6] + qx * GR[7]);
-    gq[1] = 2.0f * (qy * GR[1] + qz * GR[2] + qy * GR[3] - qw * GR[5] + qz * GR[6] + qw * GR[7]) -
-            4.0f * qx * (GR[4] + GR[8]);
-    gq[2] = 2.0f * (qx * GR[1] + qw * GR[2] + qx * GR[3] + qz * GR[5] - qw * GR[6] + qz * GR[7]) -
-            4.0f * qy * (GR[0] + GR[8]);
-    gq[3] = 2.0f * (-qw * GR[1] + qx * GR[2] + qw * GR[3] + qy * GR[5] + qx * GR[6] + qy * GR[7]) -
-            4.0f * qz * (GR[0] + GR[4]);
-    const float dq = gq[0] * qw + gq[1] * qx + gq[2] * qy + gq[3] * qz;
-    const float qh[4] = {qw, qx, qy, qz};
-    if (a.dmean) {
+        float gq[4];
+        gq[0] = 2.0f * (-qz * GR[1] + qy * GR[2] + qz * GR[3] - qx * GR[5] - qy * GR[6] + qx * GR[7]);
+        gq[1] = 2.0f * (qy * GR[1] + qz * GR[2] + qy * GR[3] - qw * GR[5] + qz * GR[6] + qw * GR[7]) -
+                4.0f * qx * (GR[4] + GR[8]);
+        gq[2] = 2.0f * (qx * GR[1] + qw * GR[2] + qx * GR[3] + qz * GR[5] - qw * GR[6] + qz * GR[7]) -
+                4.0f * qy * (GR[0] + GR[8]);
+        gq[3] = 2.0f * (-qw * GR[1] + qx * GR[2] + qw * GR[3] + qy * GR[5] + qx * GR[6] + qy * GR[7]) -
+                4.0f * qz * (GR[0] + GR[4]);
+        const float dq = gq[0] * qw + gq[1] * qx + gq[2] * qy + gq[3] * qz;
+        const float qh[4] = {qw, qx, qy, qz};
+        if (a.dmean) {
 #pragma unroll
-        for (int q = 0; q < 3; ++q) a.dmean[q * n + i] = gmu[q];
-    }
-    if (a.dquat) {
+            for (int q = 0; q < 3; ++q) a.dmean[q * n + i] = gmu[q];
+        }
+        if (a.dquat) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a.dquat[q * n + i] = (gq[q] - qh[q] * dq) * iq;
-    }
-    if (a.dlog_scale) {
+            for (int q = 0; q < 4; ++q) a.dquat[q * n + i] = (gq[q] - qh[q] * dq) * iq;
+        }
+        if (a.dlog_scale) {
 #pragma unroll
-        for (int q = 0; q < 3; ++q) a.dlog_scale[q * n + i] = gls[q];
-    }
-    if (a.dopacity) {
-        const float al = a.gc.alpha[i];
-        a.dopacity[i] = galpha * al * (1.0f - al);
-    }
-    if (a.dfeat) {
-        if (!is_dir) {
-            for (int j = 0; j < k; ++j) a.dfeat[(size_t)j * n + i] = zsum * a.m.b_iso[j];
-        } else {
-            for (int j = 0; j < k; ++j) {
-                float acc = a.m.entangled ? zsum * a.m.b_iso[j] : 0.0f;
+            for (int q = 0; q < 3; ++q) a.dlog_scale[q * n + i] = gls[q];
+        }
+        if (a.dopacity) {
+            const float al = a.gc.alpha[i];
+            a.dopacity[i] = galpha * al * (1.0f - al);
+        }
+        if (a.dfeat) {
+            if (!is_dir) {
+                for (int j = 0; j < k; ++j) a.dfeat[(size_t)j * n + i] = zsum * a.m.b_iso[j];
+            } else {
+                for (int j = 0; j < k; ++j) {
+                    float acc = a.m.entangled ? zsum * a.m.b_iso[j] : 0.0f;
 #pragma unroll
-                for (int r = 0; r < KL; ++r) acc += a.m.B_dir[r * k + j] * u[r];
-                a.dfeat[(size_t)j * n + i] = acc;
+                    for (int r = 0; r < KL; ++r) acc += a.m.B_dir[r * k + j] * u[r];
+                    a.dfeat[(size_t)j * n + i] = acc;
+                }
             }
         }
     }
-    if (a.ubuf) {
-        // Gaussian-major rows of 16: directional u in [0, k_L), isotropic z in 15
+
+    if (a.bpart) {
+        // the shared bases (Eq. 3): d B_dir[r][j] = sum over directional
+        // Gaussians of u_r f_j, d b_iso[j] = sum over isotropic ones (and
+        // every Gaussian of an entangled model) of z f_j -- this block's share
+        // of the dense contraction U F^T, on the matrix cores with
+        // v_mfma_f32_16x16x4_f32: each wave stages its 64 Gaussians' U rows
+        // in its own LDS rows, runs 16 steps of four Gaussians
+        // and leaves its tile there; the block's last wave to finish adds the
+        // four tiles in a fixed order (no workgroup barrier: waves do not
+        // wait for each other)
+        const bool own = valid && a.per_gaussian;
         float row[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) row[r] = 0.0f;
-        if (!is_dir || a.m.entangled) row[15] = zsum;
-        if (is_dir) {
+        if (own && (!is_dir || a.m.entangled)) row[15] = zsum;
+        if (own && is_dir) {
 #pragma unroll
             for (int r = 0; r < KL; ++r) row[r] = u[r];
         }
-        float4 *dst = reinterpret_cast<float4 *>(a.ubuf + (size_t)i * 16);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) dst[q] = make_float4(row[4 * q], row[4 * q + 1], row[4 * q + 2], row[4 * q + 3]);
-    }
-}
-
-// Gradients of the shared bases (Eq. 3): d B_dir[r][j] = sum_{dir} u_r,i f_j,i
-// and d b_iso[j] = sum_{iso} z_i f_j,i -- one dense contraction U F^T over
-// all Gaussians with a 16-row U (rows [0, k_L) directional u, row 15 the
-// isotropic z, the rest zero).  Each wave runs it on the matrix cores with
-// v_mfma_f32_16x16x4_f32 over a contiguous run of Gaussians (four per
-// instruction), keeping a 16 x 16 accumulator per 16 features; the per-wave
-// tiles are then summed in FP64 by grad_final_kernel.
-constexpr int kBasisWaves = 2048;
-
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-template <int KMAX>
-__global__ __launch_bounds__(kBlock) void basis_grad_kernel(int n, int k, const float *ubuf, const float *feat,
-                                                            float *part)
-{
-    constexpr int NTILE = (KMAX + 15) / 16;
-    constexpr int NCOL = NTILE * 16;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    const int nwaves = gridDim.x * (kBlock / kWave);
-    const int per = ((n + nwaves - 1) / nwaves + 3) & ~3;
-    const int g_begin = min(n, wave * per), g_end = min(n, g_begin + per);
-    // operand layout of the 16x16x4 f32 MFMA: lane l supplies A[l % 16][l / 16]
-    // and B[l / 16][l % 16]; D[i][j] comes back in lane j + 16 (i / 4), item i % 4
-    const int row = lane & 15, kk = lane >> 4;
-    // two accumulator chains; the operands of four MFMA steps are loaded
-    // before any of them is issued
-    floatx4 acc[2][NTILE];
+        for (int r = 0; r < 16; ++r) sU[w][lane][r] = row[r];
+        // (other lanes of this wave read these rows next)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // operand layout: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
+        // D[r][j] comes back in lane j + 16 (r / 4), item r % 4
+        floatx4 acc[NTILE];
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+        for (int t = 0; t < NTILE; ++t) acc[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int t = 0; t < NTILE; ++t) acc[h][t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int g0 = g_begin; g0 < g_end; g0 += 16) {
-        float av[4], bv[4][NTILE];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int g = g0 + 4 * u + kk;
-            const bool ok = g < g_end;
-            av[u] = ok ? ubuf[(size_t)g * 16 + row] : 0.0f;
-#pragma unroll
-            for (int t = 0; t < NTILE; ++t) {
-                const int j = t * 16 + row;
-                bv[u][t] = (ok && j < k) ? feat[(size_t)j * n + g] : 0.0f;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int st = 0; st < kWave / 4; ++st) {
+            const int g = 4 * st + kk;
+            const float av = sU[w][g][ri];
 #pragma unroll
             for (int t = 0; t < NTILE; ++t)
-                acc[u & 1][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[u][t], acc[u & 1][t], 0, 0, 0);
-    }
-#pragma unroll
-    for (int t = 0; t < NTILE; ++t)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int i = 4 * kk + q, j = t * 16 + row;
-            part[((size_t)wave * 16 + i) * NCOL + j] = acc[0][t][q] + acc[1][t][q];
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, fb[st][t], acc[t], 0, 0, 0);
         }
+        // the wave's tile replaces its U rows (all its operand reads are done)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        float *tile = &sU[w][0][0];
+#pragma unroll
+        for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) tile[(4 * kk + q) * NCOL + t * 16 + ri] = acc[t][q];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        uint32_t before = 0;
+        if (lane == 0) before = atomicAdd(&s_done, 1u);
+        before = (uint32_t)__shfl((int)before, 0, kWave);
+        if (before == NW - 1) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            const float *t0 = &sU[0][0][0], *t1 = &sU[1][0][0], *t2 = &sU[2][0][0], *t3 = &sU[3][0][0];
+            for (int e = lane; e < 16 * NCOL; e += kWave)
+                a.bpart[(size_t)blockIdx.x * 16 * NCOL + e] = ((t0[e] + t1[e]) + t2[e]) + t3[e];
+        }
+    }
 }
 
 // FP64 reductions after the projection backward, in one launch of
@@ -827,33 +844,14 @@ hipError_t launch_project_bwd(const ProjBwdArgs &a, hipStream_t s)
     });
 }
 
-int basis_grad_waves(int n)
-{
-    // about 64 Gaussians per wave at least, at most kBasisWaves waves
-    const int w = (n + 63) / 64;
-    return std::max(4, std::min(kBasisWaves, (w + 3) & ~3));
-}
-
-size_t basis_part_floats(int n) { return (size_t)basis_grad_waves(n) * 16 * 32; }
-
-hipError_t launch_basis_grad(const ModelDev &m, const float *ubuf, float *part, hipStream_t s)
-{
-    if (m.n == 0) return hipSuccess;
-    const int blocks = basis_grad_waves(m.n) / (kBlock / kWave);
-    return dispatch_kl(m.k, m.L, [&](auto K, auto L) {
-        constexpr int KK = decltype(K)::value;
-        (void)L;
-        basis_grad_kernel<KK><<<blocks, kBlock, 0, s>>>(m.n, m.k, ubuf, m.feat, part);
-        return hipGetLastError();
-    });
-}
+size_t basis_part_floats(int n) { return (size_t)std::max<int64_t>(1, slot_blocks(n)) * 16 * 32; }
 
 hipError_t launch_grad_final(const ModelDev &m, const float *bpart, float *db, float *dB, const ViewDev *views,
                              int V, int n_waves, const float *ppart, float *dpose, hipStream_t s)
 {
     const bool basis = (db || dB) && m.n > 0;
     const int nview = dpose ? V : 0;
-    const int bwaves = basis_grad_waves(std::max(m.n, 1));
+    const int bwaves = (int)slot_blocks(m.n);  // one basis tile per projection-backward block
     return dispatch_kl(m.k, m.L, [&](auto K, auto L) {
         constexpr int KK = decltype(K)::value, LL = decltype(L)::value;
         constexpr int NCOL = ((KK + 15) / 16) * 16;
