@@ -94,6 +94,7 @@ struct ddgs_ctx {
     uint32_t *queue = nullptr;
     int64_t entry_cap = 0;     // capacity of the entry buffers
     bool keep_unsorted = false;
+    bool depth_in_k1 = false;  // the depth order ended in (skey2, sval2)
     bool count_pairs = false;
 
     // captured step
@@ -502,6 +503,7 @@ ddgs_status enqueue_front(ddgs_ctx *c)
     bool in_k1 = false;
     HIP_TRY(c, radix_sort_pairs(po.sort_key, po.sort_val, buf<uint32_t>(c, "skey2"), buf<uint32_t>(c, "sval2"), VN,
                                 nullptr, 32, sort_ws(c), &in_k1, s, po.cnt, buf<uint32_t>(c, "cnt_sorted")));
+    c->depth_in_k1 = in_k1;
     // (the last depth pass also wrote the tile counts in depth order)
     HIP_TRY(c, launch_exclusive_scan(buf<uint32_t>(c, "cnt_sorted"), nullptr, buf<uint32_t>(c, "off_sorted"), VN,
                                      sort_ws(c), total_ptr(c), s));
@@ -515,10 +517,9 @@ ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, int64_t sort_n, float *images
     const int V = (int)c->views_h.size();
     const int n = (int)c->model.n;
     const int64_t VN = (int64_t)n * V;
-    uint32_t *skey = buf<uint32_t>(c, "skey"), *sval = buf<uint32_t>(c, "sval");
-    (void)skey;
-    // the depth order ended where the 4-pass sort left it (even count: input buffers)
-    const uint32_t *order = sval;
+    // the depth order: the values of the depth sort, in whichever buffer its
+    // last pass wrote
+    const uint32_t *order = c->depth_in_k1 ? buf<uint32_t>(c, "sval2") : buf<uint32_t>(c, "sval");
     uint32_t *tkey = buf<uint32_t>(c, "tkey"), *tval = buf<uint32_t>(c, "tval");
     HIP_TRY(c, launch_emit(VN, n, order, buf<uint32_t>(c, "off_sorted"), buf<uint32_t>(c, "cnt_sorted"),
                            buf<uint2>(c, "rect"), buf<ViewDev>(c, "views"), tkey, tval, buf<uint32_t>(c, "slot_btot"),

@@ -28,7 +28,7 @@ def R():
                                          (50_000, 32, "reverse"), (4096, 1, "rand"), (300_001, 11, "few"),
                                          (2_500_001, 13, "rand"), (16_777_217, 32, "rand"),
                                          (100_003, 9, "rand"), (2_500_003, 17, "rand"), (1_000_003, 25, "rand"),
-                                         (3_000, 17, "few")])
+                                         (3_000, 17, "few"), (2_000_003, 28, "few"), (1_500_001, 30, "rand")])
 def test_radix_sort_is_stable_and_bit_exact(R, n, bits, kind):
     rng = np.random.default_rng(n + bits)
     if kind == "rand":
