@@ -176,7 +176,8 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
                         om = stop ? 1.0f : om;
                     }
                 }
-                C = __fmaf_rn(__fmul_rn(r1.z, s), T, C);
+                // C += c (s T), the same rounded operations as the backward
+                C = __fmaf_rn(r1.z, __fmul_rn(s, T), C);
                 T = __fmul_rn(T, om);
                 if constexpr (!SPLIT) last = hit ? pos + 1u : last;
                 if constexpr (COUNT) n_contrib += hit ? 1u : 0u;
@@ -276,8 +277,12 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
     constexpr int NT = TW * TH;
     constexpr int NW = NT / kWave;
     constexpr int NA = NW > 1 ? NW : 1, NTA = NW > 1 ? NT : 1;
-    __shared__ float4 s0[NT];
-    __shared__ float4 s1[NT];
+    // one array, s1 first: the paired 4-byte reads of alpha and c then reach
+    // it with in-range immediate offsets from the same register as the
+    // 16-byte reads of s0
+    __shared__ float4 s10[2 * NT];
+    float4 *const s1 = s10;
+    float4 *const s0 = s10 + NT;
     __shared__ uint32_t se[NT];
     __shared__ __align__(16) float acc[NA][NTA][8];  // several waves: per-wave entry sums
     __shared__ uint32_t wmax[NW];
@@ -354,13 +359,19 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                 for (int q0 = 0; q0 < cnt; q0 += 8) {
                     float gb[64];
                     bool any = false;
+                    // the group's first entry index, held in one vector
+                    // register (an empty asm makes it opaque) so that the 8
+                    // entries' LDS reads use it with immediate offsets instead
+                    // of rebuilding an address for each entry
+                    int qv = q0;
+                    asm volatile("" : "+v"(qv));
 #pragma unroll
                     for (int qq = 0; qq < 8; ++qq) {
                         float gv[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                         const int q = q0 + qq;
                         if (q < cnt) {
-                            const float4 r0 = s0[q];
-                            const float4 r1 = s1[q];
+                            const float4 r0 = s0[qv + qq];
+                            const float4 r1 = s1[qv + qq];
                             const float dx = __fsub_rn(fpx, r0.x), dy = __fsub_rn(fpy, r0.y);
                             const float d2 = maha2(dx, dy, r0.z, r0.w, r1.x);
                             bool hit = d2 <= k2e;
@@ -390,7 +401,8 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                                     }
                                 }
                                 const float c = r1.z;
-                                Cacc = __fmaf_rn(__fmul_rn(c, s), T, Cacc);
+                                const float sT = __fmul_rn(s, T);
+                                Cacc = __fmaf_rn(c, sT, Cacc);
                                 const float S = Cf - Cacc;
                                 const float ds = g * (c * T - S * __builtin_amdgcn_rcpf(om));
                                 // moments of dL/ds G about the mean; the conic and
@@ -404,7 +416,7 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                                 gv[3] = m1x * dy;
                                 gv[4] = m1y * dy;
                                 gv[5] = gds;
-                                gv[6] = g * s * T;
+                                gv[6] = g * sT;
                                 T = __fmul_rn(T, om);
                                 any = true;
                             }
