@@ -31,14 +31,29 @@ namespace ddgs {
 
 namespace {
 
-// d2 = d^T A d for d = (dx, dy), A = [[A00, A01], [A01, A11]], evaluated as
-// dx (A00 dx + B dy) + A11 dy dy with B = 2 A01 (staged doubled in LDS);
-// five rounded operations, the same in the forward and the backward.
-__device__ __forceinline__ float maha2(float dx, float dy, float A00, float B, float A11)
+// The falloff exponent.  The conic is staged in LDS pre-multiplied by
+// kExpScale = -log2(e) / 2 (A00 k, 2 A01 k, A11 k), so that
+// e = dx (A00' dx + B' dy) + A11' dy dy -- five rounded operations, the same
+// in the forward and the backward -- is -d2 / 2 in base-2 units: the falloff
+// exp(-d2 / 2) is v_exp_f32(e), and the cut-off d2 <= kappa^2 becomes
+// e >= kappa^2 k (both sides scaled by the same negative factor).
+constexpr float kExpScale = -0.7213475108146667f;  // 0xBF38AA3B, -log2(e) / 2
+__device__ __forceinline__ float falloff_exponent(float dx, float dy, float A00, float B, float A11)
 {
     const float u = __fmaf_rn(B, dy, __fmul_rn(A00, dx));
     return __fmaf_rn(dx, u, __fmul_rn(__fmul_rn(A11, dy), dy));
 }
+// The staged conic of a record: (mx, my, A00 k, 2 A01 k) and (A11 k, alpha, c, .)
+__device__ __forceinline__ void scale_conic(float4 &r0, float4 &r1)
+{
+    r0.z = __fmul_rn(r0.z, kExpScale);
+    r0.w = __fmul_rn(2.0f * r0.w, kExpScale);
+    r1.x = __fmul_rn(r1.x, kExpScale);
+}
+// Cut-off value of a lane: kappa^2 k (< 0) while it composites, +infinity
+// (which no exponent of a finite record reaches) once it has stopped or lies
+// outside the image.
+constexpr float kLaneOff = __builtin_huge_valf();
 
 // min(s, sigma_max) for s = alpha G >= 0 as one v_med3_f32 (median of s,
 // 0 and sigma_max), without the NaN canonicalisation fminf brings.
@@ -47,15 +62,6 @@ __device__ __forceinline__ float clamp_opacity(float s, float smax) { return __b
 // Wave-wide OR of a predicate as a lane mask (the compare mask itself).
 __device__ __forceinline__ uint64_t wave_any_mask(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
-// Gaussian falloff exp(-d2 / 2) as one multiply and v_exp_f32 (2^x):
-// -log2(e) / 2 in FP32 is exactly half of FP32 log2(e), so this equals the
-// two-multiply form bit for bit.  Shared by the forward and the backward so
-// both see the same G.
-__device__ __forceinline__ float falloff(float d2)
-{
-    constexpr float kNegHalfLog2e = -0.7213475108146667f;  // 0xBF38AA3B
-    return __builtin_amdgcn_exp2f(__fmul_rn(d2, kNegHalfLog2e));
-}
 
 __device__ __forceinline__ int view_of_tile(const ViewDev *views, int V, int tile)
 {
@@ -131,7 +137,7 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
     __shared__ float4 s1[NT];
     __shared__ int sh_item;
     const int tid = threadIdx.x;
-    const float k2 = a.o.kappa2, tmin = a.o.t_min;
+    const float k2s = __fmul_rn(a.o.kappa2, kExpScale), tmin = a.o.t_min;
     const float smax = a.o.sigma_max;
     int iter = 0;
     for (;;) {
@@ -149,20 +155,20 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
         float T = 1.0f, C = 0.0f;
         uint32_t last = I.b;
         uint32_t n_eval = 0, n_contrib = 0;
-        // the cut-off test with the lane's state folded in: -1 once the lane
-        // has stopped (or lies outside the image), so that a hit is one
+        // the cut-off test with the lane's state folded in (kLaneOff once the
+        // lane has stopped or lies outside the image), so that a hit is one
         // compare and its wave ballot costs no vector instruction
-        float k2e = inside ? k2 : -1.0f;
+        float k2e = inside ? k2s : kLaneOff;
         // one entry: when any lane hits, the whole wave runs it without
         // branches; lanes that miss keep their state
         auto entry = [&](const float4 r0, const float4 r1, uint32_t pos) {
             const float dx = __fsub_rn(fpx, r0.x), dy = __fsub_rn(fpy, r0.y);
-            const float d2 = maha2(dx, dy, r0.z, r0.w, r1.x);
-            bool hit = d2 <= k2e;
+            const float ex = falloff_exponent(dx, dy, r0.z, r0.w, r1.x);
+            bool hit = ex >= k2e;
             if (wave_any_mask(hit) != 0ull) {
                 // lanes that miss run the same arithmetic with G = 0: s = 0,
                 // 1 - s = 1, so C and T stay exactly as they are
-                float G = hit ? falloff(d2) : 0.0f;
+                float G = hit ? __builtin_amdgcn_exp2f(ex) : 0.0f;
                 float s = clamp_opacity(__fmul_rn(r1.y, G), smax);
                 float om = __fsub_rn(1.0f, s);
                 if constexpr (!SPLIT) {
@@ -170,7 +176,7 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
                     // stops before this entry
                     if (tmin > 0.0f) {
                         const bool stop = hit & (__fmul_rn(T, om) < tmin);
-                        k2e = stop ? -1.0f : k2e;
+                        k2e = stop ? kLaneOff : k2e;
                         hit = hit & !stop;
                         s = stop ? 0.0f : s;
                         om = stop ? 1.0f : om;
@@ -189,14 +195,14 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
             if (j < I.e) {
                 const uint32_t gid = min(a.tval[j], (uint32_t)a.n - 1u);
                 const size_t idx = vbase + gid;
-                float4 r0 = a.rec[4 * idx];
-                r0.w = 2.0f * r0.w;  // 2 A01, as the Mahalanobis form uses it
+                float4 r0 = a.rec[4 * idx], r1 = a.rec[4 * idx + 1];
+                scale_conic(r0, r1);
                 s0[tid] = r0;
-                s1[tid] = a.rec[4 * idx + 1];
+                s1[tid] = r1;
             }
             __syncthreads();
             const int cnt = (int)min((uint32_t)NT, I.e - b0);
-            if (COUNT && k2e >= 0.0f) n_eval += (uint32_t)cnt;
+            if (COUNT && k2e < 0.0f) n_eval += (uint32_t)cnt;
             // four entries' records read together (one LDS address, immediate
             // offsets), then run in order
             int q = 0;
@@ -211,7 +217,7 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
                 for (int u = 0; u < 4; ++u) entry(r0[u], r1[u], b0 + (uint32_t)(q + u));
             }
             for (; q < cnt; ++q) entry(s0[q], s1[q], b0 + (uint32_t)q);
-            if (tmin > 0.0f && __syncthreads_and(k2e < 0.0f)) break;
+            if (tmin > 0.0f && __syncthreads_and(k2e == kLaneOff)) break;
         }
         if constexpr (COUNT) {
             unsigned long long e = n_eval, c = n_contrib;
@@ -271,8 +277,10 @@ __global__ __launch_bounds__(TW *TH) void merge_kernel(RasterArgs a)
 
 // SPLIT: work items are chunks (every entry of an item lies before the
 // pixel's last contribution).
+// (one-wave tiles: at least six waves per SIMD, i.e. at most 80 VGPRs)
 template <int TW, int TH, bool SPLIT>
-__global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
+__global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TW * TH == 64 ? 6 : 1)))
+void raster_bwd_kernel(RasterArgs a)
 {
     constexpr int NT = TW * TH;
     constexpr int NW = NT / kWave;
@@ -288,7 +296,7 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
     __shared__ uint32_t wmax[NW];
     __shared__ int sh_item;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-    const float k2 = a.o.kappa2, tmin = a.o.t_min;
+    const float k2s = __fmul_rn(a.o.kappa2, kExpScale), tmin = a.o.t_min;
     const float smax = a.o.sigma_max;
     float *slotf = reinterpret_cast<float *>(a.slot);
     int iter = 0;
@@ -328,9 +336,9 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
 #pragma unroll
         for (int q = 1; q < NW; ++q) end = max(end, wmax[q]);
 
-        // the cut-off test with the lane's state folded in (-1 once stopped or
-        // outside the image): a hit is one compare, its ballot is free
-        float k2e = inside ? k2 : -1.0f;
+        // the cut-off test with the lane's state folded in (kLaneOff once
+        // stopped or outside the image): a hit is one compare, its ballot is free
+        float k2e = inside ? k2s : kLaneOff;
         for (uint32_t b0 = I.b; b0 < I.e; b0 += NT) {
             const int cnt = (int)min((uint32_t)NT, I.e - b0);
             __syncthreads();
@@ -340,15 +348,15 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                 const size_t idx = vbase + gid;
                 // one 64-byte line per pair: record, place in the slot
                 // numbering, rectangle
-                float4 r0 = a.rec[4 * idx];
-                const float4 r1 = a.rec[4 * idx + 1];
+                float4 r0 = a.rec[4 * idx], r1 = a.rec[4 * idx + 1];
                 const float4 r2 = a.rec[4 * idx + 2];
-                r0.w = 2.0f * r0.w;  // 2 A01, as the Mahalanobis form uses it
+                const uint32_t place = __float_as_uint(r1.w);
+                scale_conic(r0, r1);
                 s0[tid] = r0;
                 s1[tid] = r1;
                 const uint32_t rx = __float_as_uint(r2.x), ry = __float_as_uint(r2.y);
                 const int tx0 = rx & 0xFFFF, ty0 = rx >> 16, tx1 = ry & 0xFFFF;
-                se[tid] = first_slot(a.slot_bofs, a.slot_nblk, v, (int)gid, __float_as_uint(r1.w)) +
+                se[tid] = first_slot(a.slot_bofs, a.slot_nblk, v, (int)gid, place) +
                           (uint32_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
             }
             __syncthreads();
@@ -373,8 +381,8 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                             const float4 r0 = s0[qv + qq];
                             const float4 r1 = s1[qv + qq];
                             const float dx = __fsub_rn(fpx, r0.x), dy = __fsub_rn(fpy, r0.y);
-                            const float d2 = maha2(dx, dy, r0.z, r0.w, r1.x);
-                            bool hit = d2 <= k2e;
+                            const float ex = falloff_exponent(dx, dy, r0.z, r0.w, r1.x);
+                            bool hit = ex >= k2e;
                             if constexpr (!SPLIT) hit = hit && (b0 + (uint32_t)q) < lastp;
                             // when any lane hits, the whole wave runs the entry:
                             // computed without branches, lanes that miss keep
@@ -384,7 +392,7 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                                 // G = 0: s = 0, 1 - s = 1, so the running colour
                                 // and T stay exactly as they are and every term
                                 // below is zero
-                                float G = hit ? falloff(d2) : 0.0f;
+                                float G = hit ? __builtin_amdgcn_exp2f(ex) : 0.0f;
                                 float sraw = __fmul_rn(r1.y, G);
                                 float s = clamp_opacity(sraw, smax);
                                 float om = __fsub_rn(1.0f, s);
@@ -392,7 +400,7 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                                     // t_min > 0 runs unsplit
                                     if (tmin > 0.0f) {
                                         const bool stop = hit & (__fmul_rn(T, om) < tmin);
-                                        k2e = stop ? -1.0f : k2e;
+                                        k2e = stop ? kLaneOff : k2e;
                                         hit = hit & !stop;
                                         G = stop ? 0.0f : G;
                                         sraw = stop ? 0.0f : sraw;
