@@ -126,6 +126,35 @@ __device__ __forceinline__ float wave_sum_to_lane63(float x)
     return x;
 }
 
+// One in-row step of the transposing sum for lane bit 3 (row_mirror pairs
+// lane l of a row with 15 - l) or bit 2 (row_half_mirror: l with 7 - l):
+// lanes whose bit is 0 get x + x[partner], the others y + y[partner].  Two
+// DPP additions with complementary bank masks write the same register (a
+// lane outside the bank mask is not written), instead of two selects and an
+// addition.  The leading s_nop 1 gives the two wait states a DPP read needs
+// after a VALU write of its source; r is early-clobber so that it never
+// shares a register with y, which the second addition still reads.
+__device__ __forceinline__ float pair_sum_bit3(float x, float y)
+{
+    float r;
+    asm volatile("s_nop 1\n\t"
+                 "v_add_f32_dpp %0, %1, %1 row_mirror row_mask:0xf bank_mask:0x3\n\t"
+                 "v_add_f32_dpp %0, %2, %2 row_mirror row_mask:0xf bank_mask:0xc"
+                 : "=&v"(r)
+                 : "v"(x), "v"(y));
+    return r;
+}
+__device__ __forceinline__ float pair_sum_bit2(float x, float y)
+{
+    float r;
+    asm volatile("s_nop 1\n\t"
+                 "v_add_f32_dpp %0, %1, %1 row_half_mirror row_mask:0xf bank_mask:0x5\n\t"
+                 "v_add_f32_dpp %0, %2, %2 row_half_mirror row_mask:0xf bank_mask:0xa"
+                 : "=&v"(r)
+                 : "v"(x), "v"(y));
+    return r;
+}
+
 // Sums 64 per-lane values over the wave at once: afterwards v[0] of lane l
 // holds the wave total of v[l].  Transposing butterfly: every step pairs
 // values i and i + h, each half of the lane pairs keeps one of them and adds
@@ -149,17 +178,11 @@ __device__ __forceinline__ void wave_transpose_sum64(float (&v)[64])
                                                         false, false);
         v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
-    const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
+    const bool b1 = lane & 2, b0 = lane & 1;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const float keep = b3 ? v[i + 8] : v[i], send = b3 ? v[i] : v[i + 8];
-        v[i] = keep + dpp_move<0x140>(send);  // row_mirror: l <-> 15 - l
-    }
+    for (int i = 0; i < 8; ++i) v[i] = pair_sum_bit3(v[i], v[i + 8]);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const float keep = b2 ? v[i + 4] : v[i], send = b2 ? v[i] : v[i + 4];
-        v[i] = keep + dpp_move<0x141>(send);  // row_half_mirror: l <-> 7 - l
-    }
+    for (int i = 0; i < 4; ++i) v[i] = pair_sum_bit2(v[i], v[i + 4]);
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const float keep = b1 ? v[i + 2] : v[i], send = b1 ? v[i] : v[i + 2];
