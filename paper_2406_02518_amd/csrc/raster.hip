@@ -277,10 +277,8 @@ __global__ __launch_bounds__(TW *TH) void merge_kernel(RasterArgs a)
 
 // SPLIT: work items are chunks (every entry of an item lies before the
 // pixel's last contribution).
-// (one-wave tiles: at least six waves per SIMD, i.e. at most 80 VGPRs)
 template <int TW, int TH, bool SPLIT>
-__global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TW * TH == 64 ? 6 : 1)))
-void raster_bwd_kernel(RasterArgs a)
+__global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
 {
     constexpr int NT = TW * TH;
     constexpr int NW = NT / kWave;
@@ -296,6 +294,13 @@ void raster_bwd_kernel(RasterArgs a)
     __shared__ uint32_t wmax[NW];
     __shared__ int sh_item;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+    // entries per transposing sum, gradient terms per entry, entries staged
+    // per batch (a whole number of groups), and this lane's (entry, term)
+    // after the sum (lane 63 holds the pad)
+    constexpr int kTerms = 7, EPG = kWave / kTerms;
+    constexpr int BATCH = (NT / EPG) * EPG;
+    static_assert(EPG * kTerms < kWave, "one pad value");
+    const int l_entry = lane / kTerms, l_term = lane - l_entry * kTerms;
     const float k2s = __fmul_rn(a.o.kappa2, kExpScale), tmin = a.o.t_min;
     const float smax = a.o.sigma_max;
     float *slotf = reinterpret_cast<float *>(a.slot);
@@ -339,11 +344,11 @@ void raster_bwd_kernel(RasterArgs a)
         // the cut-off test with the lane's state folded in (kLaneOff once
         // stopped or outside the image): a hit is one compare, its ballot is free
         float k2e = inside ? k2s : kLaneOff;
-        for (uint32_t b0 = I.b; b0 < I.e; b0 += NT) {
-            const int cnt = (int)min((uint32_t)NT, I.e - b0);
+        for (uint32_t b0 = I.b; b0 < I.e; b0 += BATCH) {
+            const int cnt = (int)min((uint32_t)BATCH, I.e - b0);
             __syncthreads();
             const uint32_t j = b0 + tid;
-            if (j < I.e) {
+            if (tid < BATCH && j < I.e) {
                 const uint32_t gid = min(a.tval[j], (uint32_t)a.n - 1u);
                 const size_t idx = vbase + gid;
                 // one 64-byte line per pair: record, place in the slot
@@ -361,20 +366,20 @@ void raster_bwd_kernel(RasterArgs a)
             }
             __syncthreads();
             if (b0 < end) {
-                // groups of 8 entries: 7 gradient terms + a zero pad each, one
-                // transposing wave sum per group; lane l ends with term l & 7
-                // of entry l >> 3
-                for (int q0 = 0; q0 < cnt; q0 += 8) {
+                // groups of EPG = 9 entries: their 7 gradient terms fill 63 of
+                // the 64 values of one transposing wave sum (the last is a
+                // zero pad); lane l ends with term l % 7 of entry l / 7
+                for (int q0 = 0; q0 < cnt; q0 += EPG) {
                     float gb[64];
                     bool any = false;
                     // the group's first entry index, held in one vector
-                    // register (an empty asm makes it opaque) so that the 8
+                    // register (an empty asm makes it opaque) so that the
                     // entries' LDS reads use it with immediate offsets instead
                     // of rebuilding an address for each entry
                     int qv = q0;
                     asm volatile("" : "+v"(qv));
 #pragma unroll
-                    for (int qq = 0; qq < 8; ++qq) {
+                    for (int qq = 0; qq < EPG; ++qq) {
                         float gv[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                         const int q = q0 + qq;
                         if (q < cnt) {
@@ -430,21 +435,21 @@ void raster_bwd_kernel(RasterArgs a)
                             }
                         }
 #pragma unroll
-                        for (int c = 0; c < 7; ++c) gb[qq * 8 + c] = gv[c];
-                        gb[qq * 8 + 7] = 0.0f;
+                        for (int c = 0; c < kTerms; ++c) gb[qq * kTerms + c] = gv[c];
                     }
+                    gb[63] = 0.0f;
                     float res = 0.0f;
                     if (wave_any_mask(any) != 0ull) {
                         wave_transpose_sum64(gb);
                         res = gb[0];
                     }
-                    const int q = q0 + (lane >> 3);
-                    if (q < cnt) {
+                    const int q = q0 + l_entry;
+                    if (l_entry < EPG && q < cnt) {
                         if constexpr (NW == 1) {
                             const size_t e = se[q];
-                            if (e < a.slot_cap) slotf[8 * e + (lane & 7)] = res;
+                            if (e < a.slot_cap) slotf[8 * e + l_term] = res;
                         } else {
-                            acc[w][q][lane & 7] = res;
+                            acc[w][q][l_term] = res;
                         }
                     }
                 }
