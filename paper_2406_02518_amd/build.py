@@ -30,7 +30,7 @@ def hipcc():
 def flags():
     return ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-Wall", "-Wno-unused-function", "-Wno-unused-result",
+            "-Wall", "-Wshadow", "-Wno-unused-function", "-Wno-unused-result",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 

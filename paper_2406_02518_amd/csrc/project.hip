@@ -400,14 +400,14 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
         for (; e + 4u <= c; e += 4u) {
             float4 s0[4], s1[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                s0[u] = a.slot[2 * ((size_t)off + e + u)];
-                s1[u] = a.slot[2 * ((size_t)off + e + u) + 1];
+            for (int t = 0; t < 4; ++t) {
+                s0[t] = a.slot[2 * ((size_t)off + e + t)];
+                s1[t] = a.slot[2 * ((size_t)off + e + t) + 1];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                g7[0] += s0[u].x; g7[1] += s0[u].y; g7[2] += s0[u].z; g7[3] += s0[u].w;
-                g7[4] += s1[u].x; g7[5] += s1[u].y; g7[6] += s1[u].z;
+            for (int t = 0; t < 4; ++t) {
+                g7[0] += s0[t].x; g7[1] += s0[t].y; g7[2] += s0[t].z; g7[3] += s0[t].w;
+                g7[4] += s1[t].x; g7[5] += s1[t].y; g7[6] += s1[t].z;
             }
         }
         if (e < c) {
@@ -416,16 +416,16 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
             const uint32_t rem = c - e;
             float4 s0[3], s1[3];
 #pragma unroll
-            for (int u = 0; u < 3; ++u) {
-                const size_t q = (size_t)off + e + min((uint32_t)u, rem - 1u);
-                s0[u] = a.slot[2 * q];
-                s1[u] = a.slot[2 * q + 1];
+            for (int t = 0; t < 3; ++t) {
+                const size_t q = (size_t)off + e + min((uint32_t)t, rem - 1u);
+                s0[t] = a.slot[2 * q];
+                s1[t] = a.slot[2 * q + 1];
             }
 #pragma unroll
-            for (int u = 0; u < 3; ++u) {
-                if ((uint32_t)u < rem) {
-                    g7[0] += s0[u].x; g7[1] += s0[u].y; g7[2] += s0[u].z; g7[3] += s0[u].w;
-                    g7[4] += s1[u].x; g7[5] += s1[u].y; g7[6] += s1[u].z;
+            for (int t = 0; t < 3; ++t) {
+                if ((uint32_t)t < rem) {
+                    g7[0] += s0[t].x; g7[1] += s0[t].y; g7[2] += s0[t].z; g7[3] += s0[t].w;
+                    g7[4] += s1[t].x; g7[5] += s1[t].y; g7[6] += s1[t].z;
                 }
             }
         }
@@ -535,14 +535,14 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
                 const float cd = 1.0f / (1.0f + expf(-zl));
                 const float gz = g7[6] * cd * (1.0f - cd);
                 if (a.m.entangled) zsum += gz;
-                float w[KL];
+                float wy[KL];
 #pragma unroll
                 for (int r = 0; r < KL; ++r) {
                     u[r] += gz * Y[r];
-                    w[r] = gz * h[r];
+                    wy[r] = gz * h[r];
                 }
                 float gdx, gdy, gdz;
-                sh_basis_grad<L>(dx, dy, dz, w, gdx, gdy, gdz);
+                sh_basis_grad<L>(dx, dy, dz, wy, gdx, gdy, gdz);
                 const float dd = gdx * dx + gdy * dy + gdz * dz;
                 const float grx = (gdx - dx * dd) * il, gry = (gdy - dy * dd) * il, grz = (gdz - dz * dd) * il;
                 gmu[0] += grx; gmu[1] += gry; gmu[2] += grz;
