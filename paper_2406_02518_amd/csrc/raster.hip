@@ -330,6 +330,9 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
             Cacc = pre.x;
             T = pre.y;
         }
+        // g times the tail S (the saved pixel value minus the colour
+        // composited so far), kept up to date entry by entry
+        float Sg = g * (Cf - Cacc);
         // end of the longest contributing prefix in the item
         uint32_t m = lastp;
 #pragma unroll
@@ -413,11 +416,13 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                                         om = stop ? 1.0f : om;
                                     }
                                 }
+                                // dL/ds = g (c T - S / (1 - s)) with S the tail
+                                // after this entry: g S is updated by -g c s T
                                 const float c = r1.z;
                                 const float sT = __fmul_rn(s, T);
-                                Cacc = __fmaf_rn(c, sT, Cacc);
-                                const float S = Cf - Cacc;
-                                const float ds = g * (c * T - S * __builtin_amdgcn_rcpf(om));
+                                const float gc = g * c;
+                                Sg = __fmaf_rn(-gc, sT, Sg);
+                                const float ds = __fmaf_rn(gc, T, -(Sg * __builtin_amdgcn_rcpf(om)));
                                 // moments of dL/ds G about the mean; the conic and
                                 // alpha factors are applied once per (view,
                                 // Gaussian) in the projection backward
