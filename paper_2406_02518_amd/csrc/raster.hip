@@ -182,7 +182,7 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
                         om = stop ? 1.0f : om;
                     }
                 }
-                // C += c (s T), the same rounded operations as the backward
+                // C += c (s T); T *= 1 - s exactly as the backward recomputes it
                 C = __fmaf_rn(r1.z, __fmul_rn(s, T), C);
                 T = __fmul_rn(T, om);
                 if constexpr (!SPLIT) last = hit ? pos + 1u : last;
