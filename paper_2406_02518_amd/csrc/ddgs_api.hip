@@ -496,8 +496,7 @@ ddgs_status enqueue_front(ddgs_ctx *c)
                buf<uint32_t>(c, "slot_lp"), buf<uint32_t>(c, "slot_btot")};
     const RenderOpts ro = render_opts(c->opt);
     stage_begin(c, DDGS_T_PROJECT);
-    HIP_TRY(c, launch_prep(m, gc, s));
-    HIP_TRY(c, launch_project(m, gc, buf<ViewDev>(c, "views"), V, ro, po, s));
+    HIP_TRY(c, launch_prep_project(m, gc, buf<ViewDev>(c, "views"), V, ro, po, s));
     stage_end(c, DDGS_T_PROJECT);
     stage_begin(c, DDGS_T_SORT);
     bool in_k1 = false;

@@ -209,9 +209,10 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
 // (each returns hipGetLastError() of its launches)
 
 // project.hip
-hipError_t launch_prep(const ModelDev &m, const GaussCache &gc, hipStream_t s);
-hipError_t launch_project(const ModelDev &m, const GaussCache &gc, const ViewDev *views, int V,
-                          const RenderOpts &o, const ProjOut &po, hipStream_t s);
+// The view-independent cache (gc) and the projection into V views (po); one
+// launch when V == 1, else the cache then one block row per view.
+hipError_t launch_prep_project(const ModelDev &m, const GaussCache &gc, const ViewDev *views, int V,
+                               const RenderOpts &o, const ProjOut &po, hipStream_t s);
 
 // Backward of the projection: sums each (view, Gaussian)'s gradient slots,
 // applies the chain rule to the parameters, and writes per-wave pose partials

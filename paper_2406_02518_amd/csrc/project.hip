@@ -146,22 +146,30 @@ __device__ __forceinline__ bool project_geom(const ViewDev &V, float mx, float m
 
 // ------------------------------------------------------------------ prepare
 
+// Bases staged in LDS by every block of the preparing kernels.
 template <int KMAX, int L>
-__global__ __launch_bounds__(kBlock) void prep_kernel(ModelDev m, GaussCache gc)
+__device__ __forceinline__ void stage_bases(const ModelDev &m, float *sb, float *sB)
 {
     constexpr int KL = L * (L + 2);
-    __shared__ float sb[KMAX];
-    __shared__ float sB[KL * KMAX];
     const int k = m.k;
     for (int q = threadIdx.x; q < KMAX; q += kBlock) sb[q] = q < k ? m.b_iso[q] : 0.0f;
     for (int q = threadIdx.x; q < KL * KMAX; q += kBlock) {
         const int r = q / KMAX, j = q % KMAX;
         sB[q] = j < k ? m.B_dir[r * k + j] : 0.0f;
     }
-    __syncthreads();
-    const int n = m.n;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
+}
+
+// The view-independent cache of Gaussian i: world covariance, opacity, the
+// isotropic radiosity (its logit for entangled models) and the directional
+// h = B f; written to gc and returned in registers (h only for directional
+// Gaussians).
+template <int KMAX, int L>
+__device__ __forceinline__ void prep_one(const ModelDev &m, const GaussCache &gc, int i, const float *sb,
+                                         const float *sB, float (&cw)[6], float &alpha, float &ciso,
+                                         float (&h)[L * (L + 2)])
+{
+    constexpr int KL = L * (L + 2);
+    const int n = m.n, k = m.k;
     float qw = m.quat[i], qx = m.quat[n + i], qy = m.quat[2 * n + i], qz = m.quat[3 * n + i];
     const float inv = 1.0f / sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
     qw *= inv; qx *= inv; qy *= inv; qz *= inv;
@@ -174,7 +182,6 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(ModelDev m, GaussCache gc)
         s2[a] = s * s;
     }
     // Sigma = Rq diag(s^2) Rq^T
-    float cw[6];
     cw[0] = Rq[0] * Rq[0] * s2[0] + Rq[1] * Rq[1] * s2[1] + Rq[2] * Rq[2] * s2[2];
     cw[1] = Rq[0] * Rq[3] * s2[0] + Rq[1] * Rq[4] * s2[1] + Rq[2] * Rq[5] * s2[2];
     cw[2] = Rq[0] * Rq[6] * s2[0] + Rq[1] * Rq[7] * s2[1] + Rq[2] * Rq[8] * s2[2];
@@ -183,48 +190,67 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(ModelDev m, GaussCache gc)
     cw[5] = Rq[6] * Rq[6] * s2[0] + Rq[7] * Rq[7] * s2[1] + Rq[8] * Rq[8] * s2[2];
 #pragma unroll
     for (int a = 0; a < 6; ++a) gc.cov[a * n + i] = cw[a];
-    gc.alpha[i] = sigmoidf(m.opacity_logit[i]);
+    alpha = sigmoidf(m.opacity_logit[i]);
+    gc.alpha[i] = alpha;
     float f[KMAX];
 #pragma unroll
     for (int j = 0; j < KMAX; ++j) f[j] = j < k ? m.feat[(size_t)j * n + i] : 0.0f;
+    ciso = 0.0f;
     if (i < m.n_iso || m.entangled) {
         float zl = 0.0f;
 #pragma unroll
         for (int j = 0; j < KMAX; ++j) zl += sb[j] * f[j];
-        gc.ciso[i] = m.entangled ? zl : sigmoidf(zl);
+        ciso = m.entangled ? zl : sigmoidf(zl);
+        gc.ciso[i] = ciso;
     }
+#pragma unroll
+    for (int r = 0; r < KL; ++r) h[r] = 0.0f;
     if (i >= m.n_iso) {
         const int nd = n - m.n_iso, id = i - m.n_iso;
 #pragma unroll
         for (int r = 0; r < KL; ++r) {
-            float h = 0.0f;
+            float hr = 0.0f;
 #pragma unroll
-            for (int j = 0; j < KMAX; ++j) h += sB[r * KMAX + j] * f[j];
-            gc.hdir[(size_t)r * nd + id] = h;
+            for (int j = 0; j < KMAX; ++j) hr += sB[r * KMAX + j] * f[j];
+            h[r] = hr;
+            gc.hdir[(size_t)r * nd + id] = hr;
         }
     }
 }
 
+template <int KMAX, int L>
+__global__ __launch_bounds__(kBlock) void prep_kernel(ModelDev m, GaussCache gc)
+{
+    constexpr int KL = L * (L + 2);
+    __shared__ float sb[KMAX];
+    __shared__ float sB[KL * KMAX];
+    stage_bases<KMAX, L>(m, sb, sB);
+    __syncthreads();
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= m.n) return;
+    float cw[6], alpha, ciso, h[KL];
+    prep_one<KMAX, L>(m, gc, i, sb, sB, cw, alpha, ciso, h);
+}
+
 // ------------------------------------------------------------------ project
 
-template <int L>
-__global__ __launch_bounds__(kBlock) void project_kernel(ModelDev m, GaussCache gc, const ViewDev *views,
-                                                         RenderOpts o, ProjOut po)
+// Projection of Gaussian i into view v from its cache values (cw, alpha,
+// ciso; hd(r) gives h_r of a directional Gaussian), then this block's scan of
+// the tile counts for the slot numbering (every thread of the block calls it).
+template <int L, class HD>
+__device__ __forceinline__ void project_one(const ModelDev &m, const ViewDev *views, const RenderOpts &o,
+                                            const ProjOut &po, int v, int i, const float (&cw)[6], float alpha,
+                                            float ciso, HD hd)
 {
     static_assert(kBlock == kSlotBlock, "one projection block per block of the slot numbering");
     constexpr int KL = L * (L + 2);
     const int n = m.n;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    const int v = blockIdx.y;
     const size_t vi = (size_t)v * n + i;
     uint32_t count = 0;
     float4 r1 = make_float4(0.f, 0.f, 0.f, 0.f);
     if (i < n) {
         const ViewDev V = views[v];
         const float mx = m.mean[i], my = m.mean[n + i], mz = m.mean[2 * n + i];
-        float cw[6];
-#pragma unroll
-        for (int a = 0; a < 6; ++a) cw[a] = gc.cov[a * n + i];
         Geom g;
         const bool ok = project_geom(V, mx, my, mz, cw, o, g);
         if (!ok) {
@@ -240,16 +266,15 @@ __global__ __launch_bounds__(kBlock) void project_kernel(ModelDev m, GaussCache 
             if (m.c_override) {
                 c = m.c_override[vi];
             } else if (i < m.n_iso) {
-                c = gc.ciso[i];
+                c = ciso;
             } else {
-                const int nd = n - m.n_iso, id = i - m.n_iso;
                 float rx = mx - V.so[0], ry = my - V.so[1], rz = mz - V.so[2];
                 const float il = 1.0f / sqrtf(rx * rx + ry * ry + rz * rz);
                 float Y[KL];
                 sh_basis<L>(rx * il, ry * il, rz * il, Y);
-                float zl = m.entangled ? gc.ciso[i] : 0.0f;
+                float zl = m.entangled ? ciso : 0.0f;
 #pragma unroll
-                for (int r = 0; r < KL; ++r) zl += Y[r] * gc.hdir[(size_t)r * nd + id];
+                for (int r = 0; r < KL; ++r) zl += Y[r] * hd(r);
                 c = sigmoidf(zl);
             }
             // conservative pixel box of the kappa ellipse: half-widths kappa sqrt(S00),
@@ -273,7 +298,7 @@ __global__ __launch_bounds__(kBlock) void project_kernel(ModelDev m, GaussCache 
             po.cnt[vi] = count;
             po.rect[vi] = rc;
             po.rec[4 * vi] = make_float4(g.mux, g.muy, g.A00, g.A01);
-            r1 = make_float4(g.A11, gc.alpha[i], c, 0.0f);
+            r1 = make_float4(g.A11, alpha, c, 0.0f);
             po.rec[4 * vi + 2] = make_float4(__uint_as_float(rc.x), __uint_as_float(rc.y), 0.0f, 0.0f);
         }
     }
@@ -298,6 +323,46 @@ __global__ __launch_bounds__(kBlock) void project_kernel(ModelDev m, GaussCache 
         po.slot_lp[vi] = lp;
     }
     if (threadIdx.x == 0) po.slot_btot[(size_t)v * gridDim.x + blockIdx.x] = total;
+    __syncthreads();  // (wsum is reused by the next call)
+}
+
+// One block per kSlotBlock Gaussians and view (grid.y): the cache is read
+// back from gc.
+template <int L>
+__global__ __launch_bounds__(kBlock) void project_kernel(ModelDev m, GaussCache gc, const ViewDev *views,
+                                                         RenderOpts o, ProjOut po)
+{
+    constexpr int KL = L * (L + 2);
+    const int n = m.n;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int ii = i < n ? i : 0;
+    float cw[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) cw[a] = i < n ? gc.cov[a * n + ii] : 0.0f;
+    const float alpha = i < n ? gc.alpha[ii] : 0.0f;
+    const bool iso_c = i < m.n_iso || m.entangled;
+    const float ciso = (i < n && iso_c) ? gc.ciso[ii] : 0.0f;
+    const int nd = n - m.n_iso, id = ii - m.n_iso;
+    project_one<L>(m, views, o, po, blockIdx.y, i, cw, alpha, ciso,
+                   [&](int r) { return gc.hdir[(size_t)r * nd + id]; });
+    (void)KL;
+}
+
+// One view: the cache is computed, written for the backward, and used for
+// the projection straight from registers (one launch, no read-back).
+template <int KMAX, int L>
+__global__ __launch_bounds__(kBlock) void prep_project_kernel(ModelDev m, GaussCache gc, const ViewDev *views,
+                                                              RenderOpts o, ProjOut po)
+{
+    constexpr int KL = L * (L + 2);
+    __shared__ float sb[KMAX];
+    __shared__ float sB[KL * KMAX];
+    stage_bases<KMAX, L>(m, sb, sB);
+    __syncthreads();
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    float cw[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, alpha = 0.0f, ciso = 0.0f, h[KL];
+    if (i < m.n) prep_one<KMAX, L>(m, gc, i, sb, sB, cw, alpha, ciso, h);
+    project_one<L>(m, views, o, po, 0, i, cw, alpha, ciso, [&](int r) { return h[r]; });
 }
 
 // ------------------------------------------------------------ backward chain
@@ -810,28 +875,21 @@ hipError_t dispatch_kl(int k, int L, F &&f)
 
 }  // namespace
 
-hipError_t launch_prep(const ModelDev &m, const GaussCache &gc, hipStream_t s)
-{
-    if (m.n == 0) return hipSuccess;
-    return dispatch_kl(m.k, m.L, [&](auto K, auto L) {
-        constexpr int KK = decltype(K)::value, LL = decltype(L)::value;
-        prep_kernel<KK, LL><<<(m.n + kBlock - 1) / kBlock, kBlock, 0, s>>>(m, gc);
-        return hipGetLastError();
-    });
-}
-
-hipError_t launch_project(const ModelDev &m, const GaussCache &gc, const ViewDev *views, int V,
-                          const RenderOpts &o, const ProjOut &po, hipStream_t s)
+hipError_t launch_prep_project(const ModelDev &m, const GaussCache &gc, const ViewDev *views, int V,
+                               const RenderOpts &o, const ProjOut &po, hipStream_t s)
 {
     if (m.n == 0 || V == 0) return hipSuccess;
-    dim3 grid((m.n + kBlock - 1) / kBlock, V);
-    switch (m.L) {
-    case 1: project_kernel<1><<<grid, kBlock, 0, s>>>(m, gc, views, o, po); break;
-    case 2: project_kernel<2><<<grid, kBlock, 0, s>>>(m, gc, views, o, po); break;
-    case 3: project_kernel<3><<<grid, kBlock, 0, s>>>(m, gc, views, o, po); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    const int nb = (m.n + kBlock - 1) / kBlock;
+    return dispatch_kl(m.k, m.L, [&](auto K, auto L) {
+        constexpr int KK = decltype(K)::value, LL = decltype(L)::value;
+        if (V == 1) {
+            prep_project_kernel<KK, LL><<<nb, kBlock, 0, s>>>(m, gc, views, o, po);
+        } else {
+            prep_kernel<KK, LL><<<nb, kBlock, 0, s>>>(m, gc);
+            project_kernel<LL><<<dim3(nb, V), kBlock, 0, s>>>(m, gc, views, o, po);
+        }
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_project_bwd(const ProjBwdArgs &a, hipStream_t s)
