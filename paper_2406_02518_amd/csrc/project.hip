@@ -332,7 +332,6 @@ template <int L>
 __global__ __launch_bounds__(kBlock) void project_kernel(ModelDev m, GaussCache gc, const ViewDev *views,
                                                          RenderOpts o, ProjOut po)
 {
-    constexpr int KL = L * (L + 2);
     const int n = m.n;
     const int i = blockIdx.x * kBlock + threadIdx.x;
     const int ii = i < n ? i : 0;
@@ -345,7 +344,6 @@ __global__ __launch_bounds__(kBlock) void project_kernel(ModelDev m, GaussCache 
     const int nd = n - m.n_iso, id = ii - m.n_iso;
     project_one<L>(m, views, o, po, blockIdx.y, i, cw, alpha, ciso,
                    [&](int r) { return gc.hdir[(size_t)r * nd + id]; });
-    (void)KL;
 }
 
 // One view: the cache is computed, written for the backward, and used for
