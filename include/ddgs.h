@@ -35,8 +35,19 @@
  *   - Every function returns a ddgs_status; on failure nothing is written to
  *     the outputs that the status code does not mention, and the message is
  *     kept in ddgs_last_error(ctx).  No C++ exception crosses the ABI.
- *   - The library allocates its internal workspace with hipMalloc, grows it
- *     on demand (outside a captured step) and frees it in ddgs_destroy.
+ *   - The library's internal workspace (records, tile lists, sort
+ *     temporaries, gradient slots, ...) comes from the caller's allocator
+ *     (ddgs_set_allocator; the Python binding hands it torch's caching
+ *     allocator), from a caller-owned region (ddgs_set_workspace), or, when
+ *     neither is set, from hipMalloc.  It grows on demand, never inside a
+ *     captured step, and is released by ddgs_destroy.
+ *   - Every result is deterministic: no floating-point atomics are used and
+ *     every reduction runs in a fixed order, so repeated calls on the same
+ *     inputs give bit-identical images and gradients.  There is therefore no
+ *     "deterministic" option.  Every call renders all views set with
+ *     ddgs_set_views in one batch (one launch per kernel for all views);
+ *     there is no separate batch-size option -- a caller wanting smaller
+ *     batches sets fewer views per call.
  *   - A context is not thread-safe; use one per host thread.
  */
 #ifndef DDGS_H
@@ -52,7 +63,7 @@ extern "C" {
 typedef enum {
     DDGS_OK = 0,
     DDGS_ERR_INVALID_ARG = 1, /* bad pointer, size, alignment or option        */
-    DDGS_ERR_OOM = 2,         /* hipMalloc failed                              */
+    DDGS_ERR_OOM = 2,         /* device allocation failed or workspace too small */
     DDGS_ERR_HIP = 3,         /* a HIP runtime call failed (message kept)      */
     DDGS_ERR_CAPACITY = 4,    /* tile entries exceeded the captured capacity   */
     DDGS_ERR_NONFINITE = 5,   /* non-finite value met in an input              */
@@ -111,10 +122,11 @@ typedef struct {
     float t_min;                 /* 0: early stop when T(1-s) < t_min (off)  */
     float z_near;                /* 1 mm: depth at or below which a Gaussian is culled */
     float sigma_max;             /* 0.99: clamp of s                          */
-    int32_t persistent;          /* 0: one workgroup per work item; 1:
-                                    persistent workgroups taking work items
-                                    from a counter (longest tiles first when
-                                    split is 0)                               */
+    int32_t persistent;          /* 0: one workgroup per work item; m in
+                                    1..8: persistent workgroups (m x 4 per CU
+                                    in the forward, m x 2 in the backward)
+                                    taking work items from a counter (longest
+                                    tiles first when split is 0)              */
     int32_t split;               /* 256: entries per work item -- a tile's
                                     depth-ordered list is cut into chunks of
                                     this many entries, composited in parallel
@@ -159,7 +171,7 @@ ddgs_status ddgs_get_options(const ddgs_ctx *ctx, ddgs_options *opt);
 /* Eq. 1/3 inputs. */
 ddgs_status ddgs_set_model(ddgs_ctx *ctx, const ddgs_model *model);
 ddgs_status ddgs_set_views(ddgs_ctx *ctx, const ddgs_view *views, int n_views);
-/* Pose registration (Sec. 4.4).  With an optimiser set, ddgs_step_capture
+/* Pose registration (Sec. 4.3).  With an optimiser set, ddgs_step_capture
  * appends one Adam step per view on the pose-tangent gradient the step just
  * computed (grads->dpose must be non-NULL; up to 256 views) and re-bases the
  * device view table with it: (rho, omega) = -lr * mhat / (sqrt(vhat) + eps)
@@ -177,7 +189,8 @@ ddgs_status ddgs_set_views(ddgs_ctx *ctx, const ddgs_view *views, int n_views);
  *     interchangeable for the optimiser; a pivot inside the object avoids it.
  * The moments restart from zero at the first replay after
  * ddgs_set_pose_optimizer or ddgs_set_views.  NULL turns the optimiser off.
- * Either call drops a captured step.  ddgs_get_views synchronises and
+ * Either call drops a captured step (a new capture keeps the moments).
+ * ddgs_get_views synchronises and
  * returns the current views, with the poses the optimiser has reached (they
  * also replace the host copy the library keeps).  The dpose output keeps the
  * left-tangent gradient in both modes. */
@@ -307,6 +320,13 @@ ddgs_status ddgs_rads_sample(ddgs_ctx *ctx, int64_t n1, const uint32_t *mc_keys,
  * chain (their gradients are zero).  Borrowed like the model arrays; the
  * caller keeps it sized for the current views.  Drops a captured step. */
 ddgs_status ddgs_set_radiosity_override(ddgs_ctx *ctx, const float *c);
+/* Pose composition used for a non-zero pose tangent: out = Exp(delta) pose,
+ * i.e. R' = Exp(omega) R and t' = Exp(omega) t + rho for delta = (rho,
+ * omega) (mm, rad; the left tangent the backward differentiates), evaluated
+ * in float64 from the float32 pose and rounded once to float32.  Exp is the
+ * rotation-vector exponential (Rodrigues' formula).  Host arrays; out may
+ * alias pose.  Needs no context. */
+ddgs_status ddgs_compose_pose(const float pose[12], const double delta[6], float out[12]);
 /* Number of floats of the concatenated images of the current views. */
 ddgs_status ddgs_image_size(const ddgs_ctx *ctx, int64_t *n_floats);
 
@@ -325,6 +345,22 @@ ddgs_status ddgs_image_size(const ddgs_ctx *ctx, int64_t *n_floats);
  * debug getters need more for their own trial buffers. */
 ddgs_status ddgs_set_workspace(ddgs_ctx *ctx, void *dev, size_t bytes);
 ddgs_status ddgs_workspace_size(ddgs_ctx *ctx, int64_t capacity, size_t *bytes);
+
+/* Caller allocator for the workspace buffers.  alloc(user, bytes) returns a
+ * device pointer on the context's device, at least 256-byte aligned, valid
+ * until free(user, ptr) (NULL: out of memory -> DDGS_ERR_OOM); it is called
+ * only from inside the library's entry points on the calling host thread,
+ * never while a stream capture is open.  A buffer is freed when it grows
+ * (after the context's stream has been synchronised), by
+ * ddgs_set_allocator / ddgs_set_workspace and by ddgs_destroy.  The caller's
+ * allocator may hand the memory of a freed buffer to later work on the same
+ * stream (a stream-ordered caching allocator such as torch's).  alloc NULL
+ * returns to hipMalloc.  Like ddgs_set_workspace, the call drops the previous
+ * workspace, any captured step and the last render; it takes precedence over
+ * a caller region set earlier (which it drops). */
+typedef void *(*ddgs_alloc_fn)(void *user, size_t bytes);
+typedef void (*ddgs_free_fn)(void *user, void *ptr);
+ddgs_status ddgs_set_allocator(ddgs_ctx *ctx, ddgs_alloc_fn alloc, ddgs_free_fn free_fn, void *user);
 
 /* ---------------------------------------------------------------- compute */
 
@@ -359,21 +395,41 @@ ddgs_status ddgs_loss(ddgs_ctx *ctx, int kind, const float *images, const float 
  * and no host synchronisation inside.  The pointers passed here are baked
  * into the graph and must stay valid.  ddgs_step_launch replays it;
  * ddgs_check synchronises and reports DDGS_ERR_CAPACITY if any replay (or
- * render) since the previous ddgs_check overflowed, and clears that flag
- * (outputs of an overflowed replay are invalid; capture again with a larger
- * capacity).  The model and views may change contents between
- * replays but not shapes (n, views' W/H); ddgs_set_model / ddgs_set_views
- * with a different shape drop the graph. */
+ * render) since the previous ddgs_check overflowed, and clears that flag.
+ * The images, loss values and gradients of an overflowed replay are invalid,
+ * and from the first overflowed replay until that ddgs_check every replay
+ * leaves the optimiser state alone: the appended pose and fitting Adam steps
+ * and the densification statistics are skipped (parameters, poses, moments
+ * and step counts unchanged), so an overflowed replay can be run again.
+ * The model and views may change contents between replays but not shapes
+ * (n, views' W/H); ddgs_set_model / ddgs_set_views with a different shape
+ * drop the graph.
+ *
+ * Retry after DDGS_ERR_CAPACITY: ddgs_step_report returns what the last
+ * ddgs_check found -- the number of replays whose updates were skipped
+ * (always the last ones launched before that check) and the largest number
+ * of tile entries any replay since the previous check needed.  The caller
+ * raises options.capacity above that need (ddgs_set_options), captures the
+ * step again (the optimiser moments and step counts are kept) and replays the
+ * skipped iterations again, in the same order. */
 ddgs_status ddgs_step_capture(ddgs_ctx *ctx, int loss_kind, const float *target, float lambda,
                               float *images, float *dL_dimages, float *loss_out,
                               const ddgs_grads *grads);
 ddgs_status ddgs_step_launch(ddgs_ctx *ctx);
 ddgs_status ddgs_check(ddgs_ctx *ctx, uint32_t *flags);
+ddgs_status ddgs_step_report(const ddgs_ctx *ctx, int64_t *skipped_replays, int64_t *entries_needed);
 
-/* Times forward + backward for each supported tile shape and scheduling mode
- * on the current model and views (the images are identical across
- * candidates), selects the fastest into the options and, if cache_path is
- * not NULL, reads/writes a JSON cache keyed by the workload signature.
+/* Times forward + backward (median of `repeats` after one warm-up call) on
+ * the current model and views and selects the fastest raster options: first
+ * every tile shape (16x16, 8x8, 16x8, 32x8; the waves per tile and the LDS
+ * batch follow from the shape: one pixel per lane, one staged record per
+ * pixel) with split 256, 1024 and 0, one workgroup per item; then, at the
+ * best shape, split 256, 1024, 2048, 4096 and 0 with persistent 0, 1, 2 and
+ * 4.  Images of candidates with split 0 are bit-identical; chunked ones
+ * differ only by rounding.  If cache_path is not NULL, a JSON cache keyed by
+ * the workload signature (device architecture, Gaussian-count bucket, k, L,
+ * footprint bucket -- tile entries per (view, Gaussian) at 16x16 tiles, in
+ * half octaves -- and the detector mix) is read first and written after.
  * best_ms (may be NULL) receives the chosen candidate's median time. */
 ddgs_status ddgs_autotune(ddgs_ctx *ctx, const char *cache_path, int repeats, float *best_ms);
 

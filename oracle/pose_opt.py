@@ -1,6 +1,6 @@
 """FP64 reference of one pose-optimiser step (test infrastructure, like the
 rest of oracle/): an Adam step on a view's pose-tangent gradient (rho, omega)
-followed by the re-basing the registration uses (Sec. 4.4): R <- Exp(omega) R,
+followed by the re-basing the registration uses (Sec. 4.3): R <- Exp(omega) R,
 t <- Exp(omega) t + rho, the left tangent at 0 that the backward
 differentiates.  Only tests import this module."""
 import numpy as np

@@ -32,7 +32,12 @@ EXPORTED = (
     "ddgs_debug_keep_unsorted", "ddgs_debug_sort_pairs", "ddgs_debug_exclusive_scan", "ddgs_debug_count_pairs",
     "ddgs_debug_pair_counts", "ddgs_enable_timing", "ddgs_stage_times", "ddgs_default_fit_options",
     "ddgs_set_fit_optimizer", "ddgs_set_densify_stats", "ddgs_densify_plan", "ddgs_densify_apply",
-    "ddgs_fit_reset_opacity", "ddgs_rads_prepare", "ddgs_rads_sample")
+    "ddgs_fit_reset_opacity", "ddgs_rads_prepare", "ddgs_rads_sample", "ddgs_step_report", "ddgs_set_allocator",
+    "ddgs_compose_pose")
+
+# allocator callbacks of ddgs_set_allocator: alloc(user, bytes) -> device pointer, free(user, ptr)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
 class ddgs_model(C.Structure):
@@ -151,6 +156,9 @@ def lib():
             "ddgs_rads_prepare": ([vp, C.POINTER(ddgs_volume), C.POINTER(C.c_float), C.POINTER(i64),
                                    C.POINTER(C.c_uint64)], st),
             "ddgs_rads_sample": ([vp, i64, vp, i64, vp, vp, vp, C.POINTER(i64)], st),
+            "ddgs_step_report": ([vp, C.POINTER(i64), C.POINTER(i64)], st),
+            "ddgs_set_allocator": ([vp, ALLOC_FN, FREE_FN, vp], st),
+            "ddgs_compose_pose": ([C.POINTER(C.c_float), C.POINTER(C.c_double), C.POINTER(C.c_float)], st),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -314,6 +322,30 @@ def ddgs_check(ctx, raise_on_error=True):
     return st, fl.value
 
 
+def ddgs_step_report(ctx):
+    """(skipped replays, largest entry need) found by the last ddgs_check."""
+    sk, need = C.c_int64(), C.c_int64()
+    _check(lib().ddgs_step_report(ctx, C.byref(sk), C.byref(need)), ctx)
+    return sk.value, need.value
+
+
+def ddgs_set_allocator(ctx, alloc_fn, free_fn):
+    """alloc_fn / free_fn: ALLOC_FN / FREE_FN objects (kept alive by the
+    caller), or None for hipMalloc."""
+    _check(lib().ddgs_set_allocator(ctx, alloc_fn or ALLOC_FN(), free_fn or FREE_FN(), None), ctx)
+
+
+def ddgs_compose_pose(pose, delta):
+    """Exp(delta) pose for a (3, 4) float32 pose and a 6-vector (rho, omega)
+    tangent: the library composes in float64 and rounds once."""
+    p = np.ascontiguousarray(np.asarray(pose, dtype=np.float32).reshape(12))
+    d = np.ascontiguousarray(np.asarray(delta, dtype=np.float64).reshape(6))
+    out = np.zeros(12, dtype=np.float32)
+    _check(lib().ddgs_compose_pose(p.ctypes.data_as(C.POINTER(C.c_float)), d.ctypes.data_as(C.POINTER(C.c_double)),
+                                   out.ctypes.data_as(C.POINTER(C.c_float))))
+    return out.reshape(3, 4)
+
+
 def ddgs_autotune(ctx, cache_path=None, repeats=5):
     ms = C.c_float()
     p = cache_path.encode() if cache_path else None
@@ -390,8 +422,37 @@ PARAM_NAMES = ("mean", "quat", "log_scale", "opacity_logit", "feat", "b_iso", "B
 GRAD_NAMES = ("dmean", "dquat", "dlog_scale", "dopacity_logit", "dfeat", "db_iso", "dB_dir", "dpose")
 
 
+class TorchAllocator:
+    """Workspace allocator of a context backed by torch's caching allocator:
+    every buffer the library asks for is a uint8 tensor allocated on the
+    context's stream and kept here until the library frees it."""
+
+    def __init__(self, torch, device, stream):
+        self.blocks = {}
+
+        def alloc(_user, nbytes):
+            try:
+                with torch.cuda.stream(stream):
+                    t = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+            except RuntimeError:  # out of memory: the library reports DDGS_ERR_OOM
+                return None
+            self.blocks[t.data_ptr()] = t
+            return t.data_ptr()
+
+        def free(_user, ptr):
+            self.blocks.pop(ptr, None)
+
+        self.alloc_fn = ALLOC_FN(alloc)
+        self.free_fn = FREE_FN(free)
+
+    def bytes_held(self):
+        return sum(t.numel() for t in self.blocks.values())
+
+
 class Renderer:
-    """Owns a ddgs context bound to a torch CUDA(HIP) device and stream."""
+    """Owns a ddgs context bound to a torch CUDA(HIP) device and stream.  The
+    library's workspace comes from torch's caching allocator (TorchAllocator),
+    so torch owns every byte of device memory the renderer uses."""
 
     def __init__(self, device=0, stream=None):
         import torch
@@ -404,6 +465,9 @@ class Renderer:
         self.n = 0
         self.k = 0
         self.L = 1
+        self.render_id = 0   # bumped by every render and state change (the autograd function checks it)
+        self.allocator = TorchAllocator(torch, self.device, self.stream)
+        ddgs_set_allocator(self.ctx, self.allocator.alloc_fn, self.allocator.free_fn)
 
     def close(self):
         if self.ctx is not None:
@@ -422,6 +486,7 @@ class Renderer:
         for k, v in kw.items():
             setattr(o, k, v)
         ddgs_set_options(self.ctx, o)
+        self.render_id += 1
 
     def options(self):
         o = ddgs_get_options(self.ctx)
@@ -445,6 +510,7 @@ class Renderer:
         for name in PARAM_NAMES:
             setattr(m, name, t[name].data_ptr())
         ddgs_set_model(self.ctx, m)
+        self.render_id += 1
         self._keep["model"] = t
         self.n, self.k, self.L = m.n, m.k, m.L
 
@@ -457,6 +523,7 @@ class Renderer:
     def set_views(self, views):
         self.views = list(views)
         ddgs_set_views(self.ctx, _views_struct(self.views), len(self.views))
+        self.render_id += 1
 
     def set_radiosity_override(self, c):
         """c: float32 device tensor [n_views][n] used as the radiosity instead of
@@ -553,15 +620,32 @@ class Renderer:
 
     def set_workspace(self, ws):
         """ws: a uint8 device tensor the library carves its workspace from
-        (kept alive here), or None for library-owned allocation."""
+        (kept alive here), or None to return to the torch allocator."""
         if ws is None:
             self._ws = None
             ddgs_set_workspace(self.ctx, None, 0)
+            ddgs_set_allocator(self.ctx, self.allocator.alloc_fn, self.allocator.free_fn)
             return
         if ws.dtype != self.torch.uint8 or ws.device != self.device or not ws.is_contiguous():
             raise ValueError(f"workspace must be a contiguous uint8 tensor on {self.device}")
         self._ws = ws
         ddgs_set_workspace(self.ctx, ws.data_ptr(), ws.numel())
+
+    def check_step(self):
+        """ddgs_check for a captured step.  Returns 0 when every replay since
+        the previous check fitted its tile-entry capacity.  After an overflow
+        it raises options.capacity to twice the largest need and returns the
+        number of replays whose updates were skipped (the last ones launched
+        before this check): the caller captures the step again and replays
+        those iterations, in order.  Other errors raise."""
+        st, _ = ddgs_check(self.ctx, raise_on_error=False)
+        if st == OK:
+            return 0
+        if st != ERR_CAPACITY:
+            _check(st, self.ctx)
+        skipped, need = ddgs_step_report(self.ctx)
+        self.set_options(capacity=int(min(max(2 * need, 1024), 0xFFFFFFF0)))
+        return skipped
 
     def image_size(self):
         return ddgs_image_size(self.ctx)
@@ -596,6 +680,7 @@ class Renderer:
         if out is None:
             out = self.torch.empty(self.image_size(), device=self.device, dtype=self.torch.float32)
         ddgs_render(self.ctx, out.data_ptr())
+        self.render_id += 1
         self._end(cur, out)
         return out
 

@@ -78,10 +78,14 @@ struct ddgs_ctx {
     int64_t total_pix = 0, max_view_pix = 0;
     bool views_dirty = true;
 
-    // workspace: library-owned buffers, or carved from a caller region
+    // workspace: buffers from the caller's allocator, carved from a caller
+    // region, or (neither set) from hipMalloc
     std::map<std::string, DevBuf> bufs;
-    char *ws_base = nullptr;      // caller workspace (NULL: hipMalloc per buffer)
+    char *ws_base = nullptr;      // caller workspace (NULL: an allocator per buffer)
     size_t ws_size = 0, ws_used = 0;
+    ddgs_alloc_fn alloc_fn = nullptr;  // caller allocator (NULL: hipMalloc)
+    ddgs_free_fn free_fn = nullptr;
+    void *alloc_user = nullptr;
     bool dry_run = false;         // ensure() only adds up sizes (ddgs_workspace_size)
     size_t dry_total = 0;
 
@@ -101,6 +105,7 @@ struct ddgs_ctx {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     int64_t step_cap = 0;
+    int64_t last_skipped = 0, last_need = 0;  // found by the last ddgs_check
     int max_items = 0;         // work items the raster grids are sized for
 
     // pinned staging of the view table uploads
@@ -169,15 +174,28 @@ ddgs_status ensure(ddgs_ctx *c, const char *name, size_t bytes, void **out)
         } else {
             if (b.p) {
                 HIP_TRY(c, hipStreamSynchronize(c->stream));
-                HIP_TRY(c, hipFree(b.p));
+                if (c->alloc_fn) c->free_fn(c->alloc_user, b.p);
+                else HIP_TRY(c, hipFree(b.p));
                 b.p = nullptr;
                 b.bytes = 0;
             }
-            hipError_t e = hipMalloc(&b.p, nb);
-            if (e != hipSuccess) {
-                b.p = nullptr;
-                return fail(c, DDGS_ERR_OOM, std::string("hipMalloc of ") + name + " (" + std::to_string(nb) +
-                                                 " bytes) failed: " + hipGetErrorString(e));
+            if (c->alloc_fn) {
+                b.p = c->alloc_fn(c->alloc_user, nb);
+                if (!b.p)
+                    return fail(c, DDGS_ERR_OOM, std::string("the caller's allocator returned NULL for ") + name +
+                                                     " (" + std::to_string(nb) + " bytes)");
+                if (((uintptr_t)b.p) % kWsAlign != 0) {
+                    c->free_fn(c->alloc_user, b.p);
+                    b.p = nullptr;
+                    return fail(c, DDGS_ERR_INVALID_ARG, "the caller's allocator returned memory not 256-byte aligned");
+                }
+            } else {
+                hipError_t e = hipMalloc(&b.p, nb);
+                if (e != hipSuccess) {
+                    b.p = nullptr;
+                    return fail(c, DDGS_ERR_OOM, std::string("hipMalloc of ") + name + " (" + std::to_string(nb) +
+                                                     " bytes) failed: " + hipGetErrorString(e));
+                }
             }
         }
         b.bytes = nb;
@@ -191,8 +209,11 @@ void release_buffers(ddgs_ctx *c)
 {
     (void)hipStreamSynchronize(c->stream);
     if (!c->ws_base)
-        for (auto &kv : c->bufs)
-            if (kv.second.p) (void)hipFree(kv.second.p);
+        for (auto &kv : c->bufs) {
+            if (!kv.second.p) continue;
+            if (c->alloc_fn) c->free_fn(c->alloc_user, kv.second.p);
+            else (void)hipFree(kv.second.p);
+        }
     c->bufs.clear();
     c->ws_used = 0;
 }
@@ -440,10 +461,14 @@ void stage_end(ddgs_ctx *c, int i)
 // device scalars: [0..1] u64 entry total, [2] entries kept (min(total, cap)),
 // [3] flags (bit 0: capacity overflow in some step since the last
 // ddgs_check, which clears them), [4], [5] work-queue counters,
-// [6] work items, [8..9] u64 scratch total
+// [6] work items, [7] captured replays whose updates were skipped since the
+// last ddgs_check, [8..9] u64 scratch total, [10..11] u64 largest entry total
+// of a captured replay since the last ddgs_check
 uint64_t *total_ptr(ddgs_ctx *c) { return (uint64_t *)buf<uint32_t>(c, "scalars"); }
 uint32_t *mdev_ptr(ddgs_ctx *c) { return buf<uint32_t>(c, "scalars") + 2; }
 uint32_t *flags_ptr(ddgs_ctx *c) { return buf<uint32_t>(c, "scalars") + 3; }
+uint32_t *skipped_ptr(ddgs_ctx *c) { return buf<uint32_t>(c, "scalars") + 7; }
+unsigned long long *need_ptr(ddgs_ctx *c) { return (unsigned long long *)(buf<uint32_t>(c, "scalars") + 10); }
 uint32_t *counter_ptr(ddgs_ctx *c) { return buf<uint32_t>(c, "scalars") + 4; }
 uint64_t *sort_total_ptr(ddgs_ctx *c) { return (uint64_t *)(buf<uint32_t>(c, "scalars") + 8); }
 uint32_t *n_items_ptr(ddgs_ctx *c) { return buf<uint32_t>(c, "scalars") + 6; }
@@ -510,7 +535,8 @@ ddgs_status enqueue_front(ddgs_ctx *c)
 }
 
 // Emission, tile sort, ranges, optional work queue and the forward raster.
-ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, int64_t sort_n, float *images)
+// captured: the step counters (skipped replays, largest need) are kept
+ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, int64_t sort_n, float *images, bool captured)
 {
     hipStream_t s = c->stream;
     const int V = (int)c->views_h.size();
@@ -523,7 +549,8 @@ ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, int64_t sort_n, float *images
     HIP_TRY(c, launch_emit(VN, n, order, buf<uint32_t>(c, "off_sorted"), buf<uint32_t>(c, "cnt_sorted"),
                            buf<uint2>(c, "rect"), buf<ViewDev>(c, "views"), tkey, tval, buf<uint32_t>(c, "slot_btot"),
                            (int64_t)c->views_h.size() * slot_blocks(n), (uint32_t)cap, total_ptr(c), mdev_ptr(c),
-                           flags_ptr(c), buf<uint2>(c, "ranges"), c->n_tiles, s));
+                           flags_ptr(c), captured ? skipped_ptr(c) : nullptr, captured ? need_ptr(c) : nullptr,
+                           buf<uint2>(c, "ranges"), c->n_tiles, s));
     if (c->keep_unsorted) {
         HIP_TRY(c, launch_copy_u32(buf<uint32_t>(c, "ukey"), tkey, mdev_ptr(c), sort_n, s));
         HIP_TRY(c, launch_copy_u32(buf<uint32_t>(c, "uval"), tval, mdev_ptr(c), sort_n, s));
@@ -571,7 +598,7 @@ ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, int64_t sort_n, float *images
         ra.pair_counts = pc;
         HIP_TRY(c, launch_fill_u32((uint32_t *)pc, 0u, 256, s));
     }
-    HIP_TRY(c, launch_raster_fwd(ra, c->num_cu * 8, s));
+    HIP_TRY(c, launch_raster_fwd(ra, c->num_cu * 4 * std::max(1, (int)c->opt.persistent), s));
     stage_end(c, DDGS_T_RASTER_FWD);
     return DDGS_OK;
 }
@@ -591,7 +618,8 @@ bool any_param_grad(const ddgs_grads *g)
     return g->dmean || g->dquat || g->dlog_scale || g->dopacity_logit || g->dfeat || g->db_iso || g->dB_dir;
 }
 
-ddgs_status enqueue_backward(ddgs_ctx *c, const float *dL, const ddgs_grads *g, int64_t slot_cap)
+// captured: the densification statistics skip overflowed replays
+ddgs_status enqueue_backward(ddgs_ctx *c, const float *dL, const ddgs_grads *g, int64_t slot_cap, bool captured)
 {
     hipStream_t s = c->stream;
     const int V = (int)c->views_h.size();
@@ -616,7 +644,7 @@ ddgs_status enqueue_backward(ddgs_ctx *c, const float *dL, const ddgs_grads *g, 
     ra.slot_cap = (uint32_t)std::min<int64_t>(slot_cap, 0xFFFFFFFFll);
     stage_begin(c, DDGS_T_RASTER_BWD);
     if (c->opt.persistent) HIP_TRY(c, launch_fill_u32(counter_ptr(c) + 1, 0u, 1, s));
-    HIP_TRY(c, launch_raster_bwd(ra, c->num_cu * 4, s));
+    HIP_TRY(c, launch_raster_bwd(ra, c->num_cu * 2 * std::max(1, (int)c->opt.persistent), s));
     stage_end(c, DDGS_T_RASTER_BWD);
     stage_begin(c, DDGS_T_PROJECT_BWD);
 
@@ -644,6 +672,7 @@ ddgs_status enqueue_backward(ddgs_ctx *c, const float *dL, const ddgs_grads *g, 
     pa.st_grad = c->st_grad;
     pa.st_cnt = c->st_cnt;
     pa.st_rad = c->st_rad;
+    pa.skip = captured ? flags_ptr(c) : nullptr;
     HIP_TRY(c, launch_project_bwd(pa, s));
     const int n_waves = ((n + 255) / 256) * 4;
     HIP_TRY(c, launch_grad_final(pa.m, buf<float>(c, "basis_part"), g->db_iso, g->dB_dir, buf<ViewDev>(c, "views"), V,
@@ -694,7 +723,7 @@ ddgs_status validate_options(ddgs_ctx *c, const ddgs_options &o)
     if (!(o.sigma_max > 0.0f) || !(o.sigma_max < 1.0f)) return fail(c, DDGS_ERR_INVALID_ARG, "sigma_max must be in (0, 1)");
     if (o.capacity < 0 || o.capacity > 0xFFFFFFFFll) return fail(c, DDGS_ERR_INVALID_ARG, "capacity out of range");
     if (o.split < 0 || o.split > (1 << 24)) return fail(c, DDGS_ERR_INVALID_ARG, "split must be in 0..2^24");
-    if (o.persistent != 0 && o.persistent != 1) return fail(c, DDGS_ERR_INVALID_ARG, "persistent must be 0 or 1");
+    if (o.persistent < 0 || o.persistent > 8) return fail(c, DDGS_ERR_INVALID_ARG, "persistent must be in 0..8");
     return DDGS_OK;
 }
 
@@ -1313,7 +1342,7 @@ ddgs_status ddgs_render(ddgs_ctx *c, float *images)
         HIP_TRY(c, launch_zero_u64(total_ptr(c), c->stream));
     }
     if (VN > 0) {
-        DDGS_TRY(enqueue_back(c, c->entry_cap, c->M, images));
+        DDGS_TRY(enqueue_back(c, c->entry_cap, c->M, images, false));
     } else {
         // no Gaussians: empty lists everywhere
         HIP_TRY(c, launch_fill_u32(mdev_ptr(c), 0u, 1, c->stream));
@@ -1356,7 +1385,7 @@ ddgs_status ddgs_backward(ddgs_ctx *c, const float *dL, const ddgs_grads *g)
         if (g->dpose) HIP_TRY(c, launch_fill_u32((uint32_t *)g->dpose, 0u, 6 * (int64_t)c->views_h.size(), c->stream));
         return DDGS_OK;
     }
-    DDGS_TRY(enqueue_backward(c, dL, g, c->entry_cap));
+    DDGS_TRY(enqueue_backward(c, dL, g, c->entry_cap, false));
     return DDGS_OK;
 }
 
@@ -1393,9 +1422,12 @@ ddgs_status ddgs_step_capture(ddgs_ctx *c, int kind, const float *target, float 
     if (c->adam_on) {
         float *st_;
         uint32_t *sp_;
+        // (moments restart only after ddgs_set_pose_optimizer / ddgs_set_views,
+        // so a capture repeated with a larger capacity continues the run)
+        const float *prev = buf<float>(c, "adam_state");
         DDGS_TRY(ensure_t(c, "adam_state", (size_t)12 * c->views_h.size(), &st_));
         DDGS_TRY(ensure_t(c, "adam_step", 1, &sp_));
-        c->adam_reset = true;
+        if (st_ != prev) c->adam_reset = true;
     }
     if (c->fit_on) {
         float *mv_;
@@ -1421,12 +1453,13 @@ ddgs_status ddgs_step_capture(ddgs_ctx *c, int kind, const float *target, float 
     c->timing = false;
     HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     ddgs_status st = enqueue_front(c);
-    if (st == DDGS_OK) st = enqueue_back(c, c->step_cap, c->step_cap, images);
+    if (st == DDGS_OK) st = enqueue_back(c, c->step_cap, c->step_cap, images, true);
     if (st == DDGS_OK) st = enqueue_loss(c, kind, images, target, lambda, loss_out, dL);
-    if (st == DDGS_OK) st = enqueue_backward(c, dL, g, c->step_cap);
+    if (st == DDGS_OK) st = enqueue_backward(c, dL, g, c->step_cap, true);
     if (st == DDGS_OK && c->adam_on) {
         hipError_t ea = launch_pose_adam(buf<ViewDev>(c, "views"), (int)c->views_h.size(), g->dpose,
-                                         buf<float>(c, "adam_state"), buf<uint32_t>(c, "adam_step"), c->adam, c->stream);
+                                         buf<float>(c, "adam_state"), buf<uint32_t>(c, "adam_step"), c->adam,
+                                         flags_ptr(c), c->stream);
         if (ea != hipSuccess) st = fail(c, DDGS_ERR_HIP, std::string("pose optimiser: ") + hipGetErrorString(ea));
     }
     if (st == DDGS_OK && c->fit_on) {
@@ -1438,6 +1471,7 @@ ddgs_status ddgs_step_capture(ddgs_ctx *c, int kind, const float *target, float 
         fa.m = buf<float>(c, "fit_mv");
         fa.v = fa.m + fa.off[kGroups];
         fa.step = buf<uint32_t>(c, "fit_step");
+        fa.skip = flags_ptr(c);
         fa.cfg = c->fit;
         hipError_t ea = launch_fit_adam(fa, c->num_cu, c->stream);
         if (ea != hipSuccess) st = fail(c, DDGS_ERR_HIP, std::string("fitting optimiser: ") + hipGetErrorString(ea));
@@ -1492,17 +1526,86 @@ ddgs_status ddgs_check(ddgs_ctx *c, uint32_t *flags)
     if (!c) return DDGS_ERR_INVALID_ARG;
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    uint32_t sc[4] = {0, 0, 0, 0};
+    uint32_t sc[12] = {};
     if (buf<uint32_t>(c, "scalars"))
         HIP_TRY(c, hipMemcpy(sc, buf<uint32_t>(c, "scalars"), sizeof(sc), hipMemcpyDeviceToHost));
     if (flags) *flags = sc[3];
-    // the flags accumulate over steps until read here
-    if (sc[3]) HIP_TRY(c, hipMemsetAsync(flags_ptr(c), 0, sizeof(uint32_t), c->stream));
     const uint64_t total = (uint64_t)sc[0] | ((uint64_t)sc[1] << 32);
+    const uint64_t need = (uint64_t)sc[10] | ((uint64_t)sc[11] << 32);
+    c->last_skipped = (int64_t)sc[7];
+    c->last_need = (int64_t)std::max(need, total);
+    // the flags and step counters accumulate over replays until read here
+    if (sc[3] || sc[7] || need) {
+        HIP_TRY(c, hipMemsetAsync(flags_ptr(c), 0, sizeof(uint32_t), c->stream));
+        HIP_TRY(c, hipMemsetAsync(skipped_ptr(c), 0, sizeof(uint32_t), c->stream));
+        HIP_TRY(c, hipMemsetAsync(need_ptr(c), 0, sizeof(uint64_t), c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
     if (c->M < 0) c->M = (int64_t)std::min<uint64_t>(total, (uint64_t)c->step_cap);
     if (sc[3] & 1u)
         return fail(c, DDGS_ERR_CAPACITY, "tile entries (" + std::to_string(total) + ") exceeded the capacity (" +
                                               std::to_string(c->step_cap) + ")");
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_step_report(const ddgs_ctx *c, int64_t *skipped, int64_t *need)
+{
+    if (!c) return DDGS_ERR_INVALID_ARG;
+    if (skipped) *skipped = c->last_skipped;
+    if (need) *need = c->last_need;
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_set_allocator(ddgs_ctx *c, ddgs_alloc_fn alloc, ddgs_free_fn free_fn, void *user)
+{
+    if (!c) return DDGS_ERR_INVALID_ARG;
+    if ((alloc == nullptr) != (free_fn == nullptr))
+        return fail(c, DDGS_ERR_INVALID_ARG, "pass both allocator functions or neither");
+    HIP_TRY(c, hipSetDevice(c->device));
+    drop_graph(c);
+    release_buffers(c);  // with the functions they came from
+    c->alloc_fn = alloc;
+    c->free_fn = free_fn;
+    c->alloc_user = alloc ? user : nullptr;
+    c->ws_base = nullptr;
+    c->ws_size = c->ws_used = 0;
+    c->views_dirty = true;
+    c->entry_cap = 0;
+    c->rendered = false;
+    c->tkey_sorted = c->tval_sorted = nullptr;
+    c->queue = nullptr;
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_compose_pose(const float pose[12], const double delta[6], float out[12])
+{
+    if (!pose || !delta || !out) return DDGS_ERR_INVALID_ARG;
+    for (int q = 0; q < 6; ++q)
+        if (!std::isfinite(delta[q])) return DDGS_ERR_NONFINITE;
+    // Exp(omega) by Rodrigues' formula, E = I + a [w]x + b [w]x^2 with
+    // a = sin(th) / th, b = (1 - cos(th)) / th^2 (series below th = 1e-4)
+    const double x = delta[3], y = delta[4], z = delta[5];
+    const double th2 = x * x + y * y + z * z, th = std::sqrt(th2);
+    double a, b;
+    if (th < 1e-4) {
+        a = 1.0 - th2 / 6.0;
+        b = 0.5 - th2 / 24.0;
+    } else {
+        a = std::sin(th) / th;
+        b = (1.0 - std::cos(th)) / th2;
+    }
+    const double E[9] = {1.0 - b * (y * y + z * z), -a * z + b * x * y, a * y + b * x * z,
+                         a * z + b * x * y, 1.0 - b * (x * x + z * z), -a * x + b * y * z,
+                         -a * y + b * x * z, a * x + b * y * z, 1.0 - b * (x * x + y * y)};
+    double P[12];
+    for (int q = 0; q < 12; ++q) P[q] = (double)pose[q];
+    for (int r = 0; r < 3; ++r) {
+        double row[4];
+        for (int col = 0; col < 4; ++col)
+            row[col] = E[3 * r] * P[col] + E[3 * r + 1] * P[4 + col] + E[3 * r + 2] * P[8 + col];
+        row[3] += delta[r];
+        for (int col = 0; col < 4; ++col) out[4 * r + col] = (float)row[col];
+    }
     return DDGS_OK;
 }
 
@@ -1665,16 +1768,28 @@ struct TuneEntry {
     double ms = 0.0;
 };
 
-std::string tune_signature(const ddgs_ctx *c)
+std::string device_arch(const ddgs_ctx *c)
 {
-    // workload signature: Gaussian-count bucket (power of two), the detector
-    // mix (sizes with multiplicity), the feature size and the degree
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, c->device) != hipSuccess) return "unknown";
+    std::string a = p.gcnArchName;
+    const size_t colon = a.find(':');  // drop the target features (e.g. ":sramecc+:xnack-")
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+std::string tune_signature(const ddgs_ctx *c, double entries_per_pair)
+{
+    // workload signature: device architecture, Gaussian-count bucket (power
+    // of two), the feature size and the degree, the footprint bucket (tile
+    // entries per (view, Gaussian) pair at 16x16 tiles, in half octaves) and
+    // the detector mix (sizes with multiplicity)
     std::map<std::pair<int, int>, int> mix;
     for (const auto &v : c->views_h) mix[{v.W, v.H}]++;
     int b = 0;
     while (((int64_t)1 << b) < c->model.n) ++b;
+    const int fb = entries_per_pair > 0.0 ? (int)std::floor(2.0 * std::log2(entries_per_pair)) : -99;
     std::ostringstream s;
-    s << "gfx950|n2^" << b << "|k" << c->model.k << "|L" << c->model.L << "|";
+    s << device_arch(c) << "|n2^" << b << "|k" << c->model.k << "|L" << c->model.L << "|fp" << fb << "|";
     for (const auto &kv : mix) s << kv.first.first << "x" << kv.first.second << "*" << kv.second << ";";
     return s.str();
 }
@@ -1717,7 +1832,7 @@ std::map<std::string, TuneEntry> read_cache(const char *path)
         double tw, th, pe, sp, ms;
         if (parse_num(obj, "tile_w", &tw) && parse_num(obj, "tile_h", &th) && parse_num(obj, "persistent", &pe) &&
             parse_num(obj, "split", &sp) && parse_num(obj, "ms", &ms) && raster_tile_supported((int)tw, (int)th) &&
-            (pe == 0.0 || pe == 1.0) && sp >= 0.0 && sp <= (double)(1 << 24)) {
+            pe >= 0.0 && pe <= 8.0 && pe == std::floor(pe) && sp >= 0.0 && sp <= (double)(1 << 24)) {
             TuneEntry e;
             e.tile_w = (int)tw;
             e.tile_h = (int)th;
@@ -1761,7 +1876,24 @@ ddgs_status ddgs_autotune(ddgs_ctx *c, const char *cache_path, int repeats, floa
     if (repeats < 1) repeats = 5;
     HIP_TRY(c, hipSetDevice(c->device));
     DDGS_TRY(check_ready(c));
-    const std::string sig = tune_signature(c);
+    const int64_t n = c->model.n, k = c->model.k, KL = kl_of(c->model.L), V = (int64_t)c->views_h.size();
+    const ddgs_options base = c->opt;
+    float *img, *dL, *gm, *gq, *gs, *go, *gf, *gb, *gB, *gp;
+    DDGS_TRY(prepare_views(c));
+    DDGS_TRY(ensure_t(c, "tune_img", c->total_pix, &img));
+    // the footprint bucket of the cache key: entries per pair at 16x16 tiles
+    double epp = 0.0;
+    {
+        ddgs_options o = base;
+        o.tile_w = o.tile_h = 16;
+        DDGS_TRY(ddgs_set_options(c, &o));
+        const ddgs_status st0 = ddgs_render(c, img);
+        const ddgs_status st1 = ddgs_set_options(c, &base);
+        if (st0 != DDGS_OK) return st0;
+        if (st1 != DDGS_OK) return st1;
+        if (n > 0 && V > 0) epp = (double)c->M / (double)(n * V);
+    }
+    const std::string sig = tune_signature(c, epp);
     std::map<std::string, TuneEntry> cache;
     if (cache_path) {
         cache = read_cache(cache_path);
@@ -1777,10 +1909,7 @@ ddgs_status ddgs_autotune(ddgs_ctx *c, const char *cache_path, int repeats, floa
             return DDGS_OK;
         }
     }
-    const int64_t n = c->model.n, k = c->model.k, KL = kl_of(c->model.L), V = (int64_t)c->views_h.size();
-    float *img, *dL, *gm, *gq, *gs, *go, *gf, *gb, *gB, *gp;
     DDGS_TRY(prepare_views(c));
-    DDGS_TRY(ensure_t(c, "tune_img", c->total_pix, &img));
     DDGS_TRY(ensure_t(c, "tune_dl", c->total_pix, &dL));
     DDGS_TRY(ensure_t(c, "tune_gm", 3 * n, &gm));
     DDGS_TRY(ensure_t(c, "tune_gq", 4 * n, &gq));
@@ -1795,47 +1924,57 @@ ddgs_status ddgs_autotune(ddgs_ctx *c, const char *cache_path, int repeats, floa
     hipEvent_t e0, e1;
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
-    const ddgs_options base = c->opt;
-    const int shapes[4][2] = {{16, 16}, {8, 8}, {16, 8}, {32, 8}};
     TuneEntry best;
     double best_t = 1e300;
     ddgs_status st = DDGS_OK;
-    const int splits[3] = {256, 1024, 0};
-    for (int si = 0; si < 4 && st == DDGS_OK; ++si) {
-        for (int ci = 0; ci < 6 && st == DDGS_OK; ++ci) {
-            const int pe = ci & 1, sp = splits[ci >> 1];
-            ddgs_options o = base;
-            o.tile_w = shapes[si][0];
-            o.tile_h = shapes[si][1];
-            o.persistent = pe;
-            o.split = sp;
-            st = ddgs_set_options(c, &o);
-            if (st == DDGS_OK) st = ddgs_render(c, img);
+    // median forward + backward time of one candidate (warm-up call first)
+    auto trial = [&](int tw, int th, int pe, int sp) {
+        ddgs_options o = base;
+        o.tile_w = tw;
+        o.tile_h = th;
+        o.persistent = pe;
+        o.split = sp;
+        st = ddgs_set_options(c, &o);
+        if (st == DDGS_OK) st = ddgs_render(c, img);
+        if (st == DDGS_OK) st = ddgs_backward(c, dL, &g);
+        std::vector<float> ts;
+        for (int r = 0; r < repeats && st == DDGS_OK; ++r) {
+            (void)hipEventRecord(e0, c->stream);
+            st = ddgs_render(c, img);
             if (st == DDGS_OK) st = ddgs_backward(c, dL, &g);
-            std::vector<float> ts;
-            for (int r = 0; r < repeats && st == DDGS_OK; ++r) {
-                (void)hipEventRecord(e0, c->stream);
-                st = ddgs_render(c, img);
-                if (st == DDGS_OK) st = ddgs_backward(c, dL, &g);
-                (void)hipEventRecord(e1, c->stream);
-                if (hipEventSynchronize(e1) != hipSuccess) st = fail(c, DDGS_ERR_HIP, "event sync failed");
-                float t = 0.0f;
-                (void)hipEventElapsedTime(&t, e0, e1);
-                ts.push_back(t);
-            }
-            if (st != DDGS_OK) break;
-            std::sort(ts.begin(), ts.end());
-            const double med = ts[ts.size() / 2];
-            if (med < best_t) {
-                best_t = med;
-                best.tile_w = o.tile_w;
-                best.tile_h = o.tile_h;
-                best.persistent = pe;
-                best.split = sp;
-                best.ms = med;
-            }
+            (void)hipEventRecord(e1, c->stream);
+            if (hipEventSynchronize(e1) != hipSuccess) st = fail(c, DDGS_ERR_HIP, "event sync failed");
+            float t = 0.0f;
+            (void)hipEventElapsedTime(&t, e0, e1);
+            ts.push_back(t);
         }
-    }
+        if (st != DDGS_OK) return;
+        std::sort(ts.begin(), ts.end());
+        const double med = ts[ts.size() / 2];
+        if (med < best_t) {
+            best_t = med;
+            best.tile_w = tw;
+            best.tile_h = th;
+            best.persistent = pe;
+            best.split = sp;
+            best.ms = med;
+        }
+    };
+    // stage 1: tile shape x a coarse chunking, one workgroup per item; stage
+    // 2: at the best shape, every chunk size x the persistent grid (0: off,
+    // else m x 4 (forward) and m x 2 (backward) workgroups per CU)
+    const int shapes[4][2] = {{16, 16}, {8, 8}, {16, 8}, {32, 8}};
+    const int coarse[3] = {256, 1024, 0};
+    for (int si = 0; si < 4 && st == DDGS_OK; ++si)
+        for (int ci = 0; ci < 3 && st == DDGS_OK; ++ci) trial(shapes[si][0], shapes[si][1], 0, coarse[ci]);
+    const int splits[5] = {256, 1024, 2048, 4096, 0};
+    const int mults[4] = {0, 1, 2, 4};
+    const int tw = best.tile_w, th = best.tile_h;
+    for (int sj = 0; sj < 5 && st == DDGS_OK; ++sj)
+        for (int mj = 0; mj < 4 && st == DDGS_OK; ++mj) {
+            const bool done = mults[mj] == 0 && (splits[sj] == 256 || splits[sj] == 1024 || splits[sj] == 0);
+            if (!done) trial(tw, th, mults[mj], splits[sj]);
+        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     ddgs_options o = base;

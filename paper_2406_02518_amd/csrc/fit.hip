@@ -29,6 +29,8 @@ constexpr int kFitBlock = 256;
 // so the kernel streams parameters, gradients and both moments once.
 __global__ __launch_bounds__(kFitBlock) void fit_adam_kernel(FitArgs a)
 {
+    // an overflowed step leaves parameters and moments alone
+    if (a.skip && (*a.skip & 1u)) return;
     const uint32_t t = *a.step + 1u;
     const double bc1 = 1.0 - pow((double)a.cfg.beta1, (double)t);
     const double bc2 = 1.0 - pow((double)a.cfg.beta2, (double)t);
@@ -54,9 +56,9 @@ __global__ __launch_bounds__(kFitBlock) void fit_adam_kernel(FitArgs a)
     }
 }
 
-__global__ void fit_step_kernel(uint32_t *step)
+__global__ void fit_step_kernel(uint32_t *step, const uint32_t *skip)
 {
-    if (threadIdx.x == 0) *step = *step + 1u;
+    if (threadIdx.x == 0 && !(skip && (*skip & 1u))) *step = *step + 1u;
 }
 
 __global__ __launch_bounds__(kFitBlock) void densify_plan_kernel(int n, const float *ls, const float *op,
@@ -167,7 +169,7 @@ hipError_t launch_fit_adam(const FitArgs &a, int num_cu, hipStream_t s)
     fit_adam_kernel<<<grid, kFitBlock, 0, s>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    fit_step_kernel<<<1, 64, 0, s>>>(a.step);
+    fit_step_kernel<<<1, 64, 0, s>>>(a.step, a.skip);
     return hipGetLastError();
 }
 

@@ -238,6 +238,9 @@ struct ProjBwdArgs {
     // densification statistics, [n] each (NULL: off): norm of the 2D-mean
     // gradient in normalised device units, visible views, largest radius (px)
     float *st_grad, *st_cnt, *st_rad;
+    // step flags of a captured step (NULL: plain call): while bit 0 (a tile
+    // list overflowed its capacity) is set the statistics are not updated
+    const uint32_t *skip;
 };
 hipError_t launch_project_bwd(const ProjBwdArgs &a, hipStream_t s);
 // floats of the basis tiles of the projection backward (one per block)
@@ -274,11 +277,14 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
 // (also clears the n_tiles tile ranges and turns the slot_nb block totals of
 // the slot numbering into the blocks' first slots, in place; cnt_sorted: tile
 // counts in depth order)
+// (captured steps also pass skipped / need: the count of replays whose
+// optimiser updates are skipped -- every replay from the first overflow on,
+// until the flags are cleared -- and the largest entry total; NULL: plain call)
 hipError_t launch_emit(int64_t VN, int n, const uint32_t *order, const uint32_t *off_sorted,
                        const uint32_t *cnt_sorted, const uint2 *rect, const ViewDev *views, uint32_t *tkey,
                        uint32_t *tval, uint32_t *slot_btot, int64_t slot_nb, uint32_t capacity,
-                       const uint64_t *total, uint32_t *m_out, uint32_t *flags, uint2 *ranges, int n_tiles,
-                       hipStream_t s);
+                       const uint64_t *total, uint32_t *m_out, uint32_t *flags, uint32_t *skipped,
+                       unsigned long long *need, uint2 *ranges, int n_tiles, hipStream_t s);
 // zero: clear the ranges first (else they must already be clear)
 hipError_t launch_ranges(const uint32_t *keys, const uint32_t *m_dev, int64_t m_cap, uint2 *ranges,
                          int n_tiles, bool zero, hipStream_t s);
@@ -336,8 +342,9 @@ struct AdamCfg {
     int pivot_mode;  // 0: rotate about the source, 1: about the world point pivot
     float pivot[3];
 };
+// (skip: step flags; nothing changes while bit 0, a capacity overflow, is set)
 hipError_t launch_pose_adam(ViewDev *views, int V, const float *dpose, float *state, uint32_t *step,
-                            const AdamCfg &cfg, hipStream_t s);
+                            const AdamCfg &cfg, const uint32_t *skip, hipStream_t s);
 
 // fit.hip -- the fitting loop: fused Adam over every parameter group,
 // densification and the opacity reset.  The flat parameter index runs over
@@ -356,6 +363,7 @@ struct FitArgs {
     int64_t off[kGroups + 1];  // flat offsets of the groups
     float *m, *v;              // moments [off[7]] each
     uint32_t *step;            // completed steps
+    const uint32_t *skip;      // step flags: no update while bit 0 (overflow) is set
     FitCfg cfg;
 };
 int64_t fit_param_count(int64_t n, int k, int kl);

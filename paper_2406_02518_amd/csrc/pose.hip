@@ -1,4 +1,4 @@
-// pose.hip -- on-device pose optimisation for registration (Sec. 4.4): one
+// pose.hip -- on-device pose optimisation for registration (Sec. 4.3): one
 // Adam step on every view's pose tangent (rho, omega) from the gradient of
 // the step just computed, then the view is re-based so that the next replay
 // of a captured step renders from the new poses.  The rotation turns about
@@ -38,8 +38,10 @@ __device__ void exp_so3(const double w[3], double E[9])
 // One thread per view.  state: [V][12] (first moments of (rho, omega), then
 // second moments); *step: completed Adam steps (shared by all views).
 __global__ __launch_bounds__(256) void pose_adam_kernel(ViewDev *views, int V, const float *dpose, float *state,
-                                                        uint32_t *step, AdamCfg cfg)
+                                                        uint32_t *step, AdamCfg cfg, const uint32_t *skip)
 {
+    // an overflowed step leaves poses, moments and the step count alone
+    if (skip && (*skip & 1u)) return;
     const int v = threadIdx.x;
     const uint32_t t = *step + 1u;
     __syncthreads();  // every thread has read the step count
@@ -99,11 +101,11 @@ __global__ __launch_bounds__(256) void pose_adam_kernel(ViewDev *views, int V, c
 }  // namespace
 
 hipError_t launch_pose_adam(ViewDev *views, int V, const float *dpose, float *state, uint32_t *step,
-                            const AdamCfg &cfg, hipStream_t s)
+                            const AdamCfg &cfg, const uint32_t *skip, hipStream_t s)
 {
     if (V <= 0) return hipSuccess;
     if (V > 256) return hipErrorInvalidValue;
-    pose_adam_kernel<<<1, 256, 0, s>>>(views, V, dpose, state, step, cfg);
+    pose_adam_kernel<<<1, 256, 0, s>>>(views, V, dpose, state, step, cfg, skip);
     return hipGetLastError();
 }
 

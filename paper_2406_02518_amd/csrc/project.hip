@@ -622,7 +622,7 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
             for (int q = 0; q < 9; ++q) a.pose_part[((size_t)v * n_waves + wave) * 9 + q] = pose[q];
         }
     }
-    if (valid && a.st_grad) {
+    if (valid && a.st_grad && !(a.skip && (*a.skip & 1u))) {
         a.st_grad[i] += st_grad;
         a.st_cnt[i] += st_cnt;
         a.st_rad[i] = fmaxf(a.st_rad[i], st_rad);

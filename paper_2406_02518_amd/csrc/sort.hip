@@ -446,7 +446,8 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(int64_t VN, int n, const u
                                                       const uint2 *rect, const ViewDev *views, uint32_t *tkey,
                                                       uint32_t *tval, uint32_t *slot_btot, int64_t slot_nb,
                                                       uint32_t capacity, const uint64_t *total, uint32_t *m_out,
-                                                      uint32_t *flags, uint2 *ranges, int n_tiles)
+                                                      uint32_t *flags, uint32_t *skipped, unsigned long long *need,
+                                                      uint2 *ranges, int n_tiles)
 {
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & (kWave - 1);
@@ -480,7 +481,14 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(int64_t VN, int n, const u
         const uint64_t t = *total;
         const bool over = t > (uint64_t)capacity;
         *m_out = over ? capacity : (uint32_t)t;
-        if (over) atomicOr(flags, 1u);
+        const uint32_t f = *flags | (over ? 1u : 0u);
+        *flags = f;
+        if (skipped) {
+            // captured step: from the first overflow on, every replay until
+            // the flags are cleared skips its optimiser updates
+            if (f & 1u) *skipped = *skipped + 1u;
+            if ((unsigned long long)t > *need) *need = (unsigned long long)t;
+        }
     }
     const bool valid = r < VN;
     uint32_t c = 0, off = 0xFFFFFFFFu, i = 0, x0y0 = 0, span = 1, rowbase = 0, ntx = 0;
@@ -734,12 +742,13 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
 hipError_t launch_emit(int64_t VN, int n, const uint32_t *order, const uint32_t *off_sorted,
                        const uint32_t *cnt_sorted, const uint2 *rect, const ViewDev *views, uint32_t *tkey,
                        uint32_t *tval, uint32_t *slot_btot, int64_t slot_nb, uint32_t capacity,
-                       const uint64_t *total, uint32_t *m_out, uint32_t *flags, uint2 *ranges, int n_tiles,
-                       hipStream_t s)
+                       const uint64_t *total, uint32_t *m_out, uint32_t *flags, uint32_t *skipped,
+                       unsigned long long *need, uint2 *ranges, int n_tiles, hipStream_t s)
 {
     const int64_t nb = std::max<int64_t>(1, blocks_for(VN, kBlock));
     emit_kernel<<<(unsigned)nb, kBlock, 0, s>>>(VN, n, order, off_sorted, cnt_sorted, rect, views, tkey, tval,
-                                                slot_btot, slot_nb, capacity, total, m_out, flags, ranges, n_tiles);
+                                                slot_btot, slot_nb, capacity, total, m_out, flags, skipped, need,
+                                                ranges, n_tiles);
     return hipGetLastError();
 }
 

@@ -11,7 +11,12 @@ again for the new size); the optimiser moments are carried across.  The
 schedule follows the 3D Gaussian splatting defaults the paper adopts for
 everything but the bases and features: densify every 100 iterations from
 500 to 15000, reset opacities to 0.01 every 3000, drop oversized Gaussians
-(world bound 0.1 x extent, screen bound 20 px) after the first reset."""
+(world bound 0.1 x extent, screen bound 20 px) after the first reset.
+
+The captured step has a fixed tile-entry capacity.  A replay that needs more
+changes nothing (its updates are skipped on the device); at the next check the
+loop raises the capacity, captures the step again and replays the skipped
+iterations, so the run is the same as one with ample capacity."""
 from dataclasses import dataclass
 
 import numpy as np
@@ -57,16 +62,41 @@ def fit(R, params, n_iso, L, views, targets, iters, extent, lam=0.2, schedule=No
 
     state = {}
 
+    def capture():
+        with torch.cuda.stream(R.stream):
+            binding.ddgs_step_capture(R.ctx, binding.LOSS_L1_DSSIM, tgt.data_ptr(), lam, img.data_ptr(),
+                                      dl.data_ptr(), loss.data_ptr(), R.grads_struct(state["grads"]))
+
     def setup(p, ni):
         R.set_model(p, ni, L, entangled)
         stats = R.new_densify_stats()
         R.set_densify_stats(stats)
         R.set_views([views[0]])
-        grads = R.alloc_grads()
+        state.update(params=p, n_iso=ni, stats=stats, grads=R.alloc_grads())
+        capture()
+
+    window = []   # (iteration, view) of the replays launched since the last check
+
+    def launch(it, j):
         with torch.cuda.stream(R.stream):
-            binding.ddgs_step_capture(R.ctx, binding.LOSS_L1_DSSIM, tgt.data_ptr(), lam, img.data_ptr(),
-                                      dl.data_ptr(), loss.data_ptr(), R.grads_struct(grads))
-        state.update(params=p, n_iso=ni, stats=stats, grads=grads)
+            tgt.copy_(targets[j], non_blocking=True)
+            R.set_views([views[j]])
+            binding.ddgs_step_launch(R.ctx)
+            losses[(it - 1) % len(losses)].copy_(loss[0], non_blocking=True)
+        window.append((it, j))
+
+    def check():
+        # an overflowed replay changed nothing: grow, capture again, replay it
+        while True:
+            skipped = R.check_step()
+            if skipped == 0:
+                break
+            redo = window[len(window) - skipped:]
+            window.clear()
+            capture()
+            for it_j in redo:
+                launch(*it_j)
+        window.clear()
 
     R.set_model(params, n_iso, L, entangled)
     R.set_fit_optimizer(extent, **(rates or {}))
@@ -77,19 +107,14 @@ def fit(R, params, n_iso, L, views, targets, iters, extent, lam=0.2, schedule=No
         for it in range(1, iters + 1):
             if not order:
                 order = list(rng.permutation(len(views)))
-            j = int(order.pop())
-            with torch.cuda.stream(R.stream):
-                tgt.copy_(targets[j], non_blocking=True)
-                R.set_views([views[j]])
-                binding.ddgs_step_launch(R.ctx)
-                losses[(it - 1) % len(losses)].copy_(loss[0], non_blocking=True)
+            launch(it, int(order.pop()))
             if log_every and it % log_every == 0:
-                binding.ddgs_check(R.ctx)
+                check()
                 history.append((it, R.n, float(losses.mean().item())))
                 if on_log:
                     on_log(history[-1])
             if sch.densify_from <= it <= sch.densify_until and it % sch.densify_every == 0:
-                binding.ddgs_check(R.ctx)
+                check()
                 late = sch.opacity_reset_every > 0 and it > sch.opacity_reset_every
                 with torch.cuda.stream(R.stream):
                     noise = torch.randn((R.n, 2, 3), generator=gen, device=R.device)
@@ -99,8 +124,9 @@ def fit(R, params, n_iso, L, views, targets, iters, extent, lam=0.2, schedule=No
                                         max_screen_radius=sch.max_screen_radius if late else 0.0)
                 setup(new, ni)
             if sch.opacity_reset_every and it % sch.opacity_reset_every == 0:
+                check()
                 R.reset_opacity(sch.reset_alpha)
-        binding.ddgs_check(R.ctx)
+        check()
         return state["params"], state["n_iso"], history
     finally:
         R.set_fit_optimizer(None)

@@ -1,4 +1,4 @@
-"""2D/3D pose registration on the GPU (Sec. 4.4): every view's pose is
+"""2D/3D pose registration on the GPU (Sec. 4.3): every view's pose is
 refined by gradient descent on an image loss against its target, through the
 renderer's pose-tangent gradient.
 
@@ -10,7 +10,9 @@ world origin): R <- Exp(omega) R, t <- t + rho.  Turning about the source
 instead (``pivot=None``) moves the image almost as a sideways shift does, so
 rotation and translation become nearly interchangeable and descent stalls in
 the resulting valley.  The loss is read back every ``check_every``
-iterations to test convergence."""
+iterations to test convergence.  A replay whose tile entries exceed the
+captured capacity changes no pose; at the next check the capacity is raised,
+the step captured again and the skipped iterations replayed."""
 import numpy as np
 
 from . import binding
@@ -35,16 +37,26 @@ def register(R, targets, iters=200, lr_trans=1.0, lr_rot=0.008, beta1=0.9, beta2
     loss_out = torch.empty(V, device=R.device)
     grads = R.alloc_grads(("dpose",))
     R.set_pose_optimizer(lr_trans, lr_rot, beta1, beta2, eps, pivot=pivot)
-    try:
+
+    def capture():
         with torch.cuda.stream(R.stream):
             binding.ddgs_step_capture(R.ctx, loss, targets.data_ptr(), lam, images.data_ptr(), dl.data_ptr(),
                                       loss_out.data_ptr(), R.grads_struct(grads))
+
+    try:
+        capture()
         history = []
         prev = None
         for it in range(1, iters + 1):
             binding.ddgs_step_launch(R.ctx)
             if it % check_every == 0 or it == iters:
-                binding.ddgs_check(R.ctx)
+                # replays skipped by an overflow are the last ones: run them again
+                skipped = R.check_step()
+                while skipped:
+                    capture()
+                    for _ in range(skipped):
+                        binding.ddgs_step_launch(R.ctx)
+                    skipped = R.check_step()
                 cur = loss_out.cpu().numpy().astype(np.float64)
                 history.append((it, cur))
                 if prev is not None and np.all(np.abs(prev - cur) <= np.maximum(rel_tol * np.abs(prev), abs_tol)):

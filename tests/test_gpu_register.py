@@ -1,4 +1,4 @@
-"""Pose registration (Sec. 4.4) on the GPU: the optimiser step inside the
+"""Pose registration (Sec. 4.3) on the GPU: the optimiser step inside the
 captured graph against its FP64 reference, and registration from perturbed
 poses towards targets rendered by the oracle."""
 import numpy as np

@@ -97,3 +97,33 @@ def test_registration_metrics():
     Rz[:, :3] = P[:, :3] @ Rotation.from_rotvec([0.0, 0.0, 0.3]).as_matrix()
     r = np.linalg.norm(pts[:, :2], axis=1)
     assert register.target_registration_error(Rz, P, pts) == pytest.approx(np.mean(2 * r * np.sin(0.15)), rel=1e-12)
+
+
+def test_compose_pose_is_the_left_exponential(L):
+    """ddgs_compose_pose: Exp(delta) pose with Exp from scipy's rotation-vector
+    map (an independent implementation), evaluated in float64 and rounded once;
+    zero tangent returns the pose, a translation tangent shifts t only, and
+    the small-angle series branch agrees with the closed form."""
+    import numpy as np
+    from scipy.spatial.transform import Rotation
+
+    from paper_2406_02518_amd import synth
+
+    rng = np.random.default_rng(33)
+    P = synth.azimuth_pose(25.0, 600.0).astype(np.float32)
+    np.testing.assert_array_equal(binding.ddgs_compose_pose(P, np.zeros(6)), P)
+    T = binding.ddgs_compose_pose(P, [1.5, -2.0, 3.25, 0.0, 0.0, 0.0])
+    np.testing.assert_array_equal(T[:, :3], P[:, :3])
+    np.testing.assert_allclose(T[:, 3], P[:, 3].astype(np.float64) + [1.5, -2.0, 3.25], rtol=0, atol=1e-4)
+    for scale in (0.3, 1e-3, 3e-5):
+        for _ in range(4):
+            d = np.concatenate([rng.normal(size=3) * 10.0, rng.normal(size=3) * scale])
+            E = Rotation.from_rotvec(d[3:]).as_matrix()
+            P64 = P.astype(np.float64)
+            want = np.concatenate([E @ P64[:, :3], (E @ P64[:, 3] + d[:3])[:, None]], axis=1)
+            got = binding.ddgs_compose_pose(P, d).astype(np.float64)
+            # one rounding to float32 on each side
+            tol = 2.0 ** -23 * np.maximum(1.0, np.abs(want))
+            assert np.all(np.abs(got - want) <= tol), (scale, np.abs(got - want).max())
+    with pytest.raises(binding.DDGSError):
+        binding.ddgs_compose_pose(P, [0, 0, 0, np.nan, 0, 0])

@@ -142,3 +142,95 @@ def test_densify_stats_from_the_oracle_gradient():
         exp_acc += vis * np.hypot(o["g2d"][vi, :, 0] * v.W / 2, o["g2d"][vi, :, 1] * v.H / 2)
     np.testing.assert_allclose(acc, exp_acc, rtol=1e-12)
     assert den.max() == 2 and acc.max() > 0 and rad.max() > 0
+
+
+def _iso_scene(means, std_mm, alpha=0.5, c=0.7):
+    """Isotropic Gaussians at world means (3, n) with std std_mm and one
+    radiosity c (features encode logit(c) along b_iso)."""
+    means = np.asarray(means, np.float64)
+    n = means.shape[1]
+    b = np.array([1.0, 0.5, -0.25, 0.125])
+    f = np.log(c / (1.0 - c)) * b / (b @ b)
+    return synth.Scene(mean=means, quat=np.tile([[1.0], [0.0], [0.0], [0.0]], (1, n)),
+                       log_scale=np.full((3, n), np.log(std_mm)),
+                       opacity_logit=np.full(n, np.log(alpha / (1.0 - alpha))), feat=np.tile(f[:, None], (1, n)),
+                       b_iso=b, B_dir=np.zeros((3, 4)), n_iso=n, L=1)
+
+
+def test_densify_statistic_against_finite_differences_of_the_mean():
+    """Independent pin of the densification statistic.  One isotropic Gaussian
+    on the principal ray (source-frame mean (0, 0, z)): shifting it by x along
+    the source-frame x axis moves its projected mean by f x / z pixels, while
+    the projected covariance s^2 J J^T + dI changes only at order x^2 (J J^T
+    = (f/z)^2 (I + (x, y)(x, y)^T / z^2)), so a central difference of the
+    loss under that shift gives dL/du exactly up to O(h^2); likewise for y.
+    Normalised device units are u_ndc = (2 u + 1) / W - 1, so the statistic is
+    the norm of (dL/du W/2, dL/dv H/2).  The upstream weights vanish near the
+    cut-off, so no pixel changes its contributor set under the shifts."""
+    W, H, pitch, sdd, sid, std = 48, 40, 0.8, 1000.0, 600.0, 2.0
+    v = synth.view(W, H, pitch, sdd, sid, 0.0)
+    f = np.float64(np.float32(sdd)) / np.float64(np.float32(pitch))
+    sig2 = (std * f / sid) ** 2 + 0.3
+    vv, uu = np.meshgrid(np.arange(H) + 0.5, np.arange(W) + 0.5, indexing="ij")
+    d2 = ((uu - W / 2) ** 2 + (vv - H / 2) ** 2) / sig2
+    g = np.random.default_rng(17).normal(size=(H, W)) * (d2 < 8.0)
+    R = np.asarray(v.pose, np.float64)[:, :3]
+
+    def loss(shift):
+        sc = _iso_scene(np.asarray(shift, np.float64)[:, None], std)
+        return float((ref.render(sc, [v])[0] * g).sum())
+
+    h = 1e-3
+    du = (loss(h * R[0]) - loss(-h * R[0])) / (2 * h) * sid / f
+    dv = (loss(h * R[1]) - loss(-h * R[1])) / (2 * h) * sid / f
+    expected = np.hypot(du * W / 2, dv * H / 2)
+    sc = _iso_scene(np.zeros((3, 1)), std)
+    o = ref.backward(sc, [v], ref.all_pixels([v]), g.ravel(), want_g2d=True)
+    acc, den, rad, stable = fit_ref.densify_stats(sc, [v], o["g2d"])
+    assert den[0] == 1 and stable[0]
+    assert expected > 1e-3
+    np.testing.assert_allclose(acc[0], expected, rtol=1e-6)
+    # the tracked radius: kappa sqrt(lambda_max), isotropic here
+    np.testing.assert_allclose(rad[0], 3.0 * np.sqrt(sig2), rtol=1e-12)
+
+
+def test_visibility_rule_at_the_image_edges():
+    """visible_boxes against boxes placed in closed form.  An isotropic
+    Gaussian at source-frame (x, 0, z) projects to u = f x / z + W/2 with
+    variance s^2 (f/z)^2 (1 + x^2 / z^2) + 0.3 along u (the pinhole Jacobian
+    at y = 0), and likewise along v at (0, y, z).  A Gaussian counts as
+    visible when its kappa box reaches a pixel centre u' + 0.5, u' = 0..W-1,
+    on both axes.  Boxes whose inner edge lies 0.02 px inside the outermost
+    centre on each of the four sides are visible, 0.02 px outside invisible."""
+    from scipy.optimize import brentq
+
+    W, H, pitch, sdd, sid, std, kappa = 50, 36, 1.0, 1000.0, 600.0, 1.5, 3.0
+    v = synth.view(W, H, pitch, sdd, sid, 0.0)
+    f = np.float64(np.float32(sdd)) / np.float64(np.float32(pitch))
+    P = np.asarray(v.pose, np.float64)
+    Rm, t = P[:, :3], P[:, 3]
+
+    def half(off):
+        return kappa * np.sqrt(std ** 2 * (f / sid) ** 2 * (1.0 + (off / sid) ** 2) + 0.3)
+
+    cams, want = [], []
+    for axis, size in ((0, W), (1, H)):
+        for side in (-1, 1):
+            for inside in (True, False):
+                e = -0.02 if inside else 0.02
+                if side > 0:   # left end of the box past the last centre, size - 0.5
+                    target = lambda off: f * off / sid + size / 2 - half(off) - (size - 0.5 + e)  # noqa: E731
+                else:          # right end of the box before the first centre, 0.5
+                    target = lambda off: f * off / sid + size / 2 + half(off) - (0.5 - e)  # noqa: E731
+                off = brentq(target, -sid, sid, xtol=1e-12)
+                cam = np.array([0.0, 0.0, sid])
+                cam[axis] = off
+                cams.append(cam)
+                want.append(inside)
+    means = np.stack([Rm.T @ (cm - t) for cm in cams], axis=1)
+    sc = _iso_scene(means, std)
+    vis, stable, _ = fit_ref.visible_boxes(sc, v, kappa=kappa)
+    np.testing.assert_array_equal(vis, np.array(want))
+    # the projected means confirm the placement (box edges 0.02 px from the centres)
+    pr = ref.project(sc, v)
+    assert np.all(pr[:, 0] > 0)
