@@ -177,10 +177,21 @@ def test_autograd_interleaved_forwards(R):
 
 # --------------------------------------------------------- overflow retry
 
-def test_overflowed_replay_changes_nothing(R):
+@pytest.fixture(scope="module")
+def RS():
+    """A renderer on a stream of its own (a captured step needs one)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    r = binding.Renderer(0, stream=torch.cuda.Stream())
+    yield r
+    r.close()
+
+
+def test_overflowed_replay_changes_nothing(RS):
     """A captured step whose tile entries exceed its capacity leaves the
     poses, the optimiser state and the model untouched, reports the overflow
     and the need, and the replays it skipped."""
+    R = RS
     c = synth.config("C4", scale=0.03)
     views = c.views[:3]
     R.set_scene(c.scene)
@@ -213,9 +224,10 @@ def test_overflowed_replay_changes_nothing(R):
         R.set_options(capacity=0)
 
 
-def test_registration_retries_overflow_exactly(R):
+def test_registration_retries_overflow_exactly(RS):
     """register() from a too-small capacity ends bit-identical to a run with
     ample capacity: the overflowed iterations are replayed after growing."""
+    R = RS
     from paper_2406_02518_amd import register
     c = synth.config("C4", scale=0.03)
     views = c.views[:4]
@@ -236,10 +248,11 @@ def test_registration_retries_overflow_exactly(R):
     np.testing.assert_array_equal(runs[0][1][-1][1], runs[1][1][-1][1])
 
 
-def test_fitting_retries_overflow_exactly(R):
+def test_fitting_retries_overflow_exactly(RS):
     """fit() from a too-small capacity ends bit-identical to a run with ample
     capacity (the fused Adam of an overflowed replay is skipped, the replay
     is run again after the capacity grows)."""
+    R = RS
     from paper_2406_02518_amd import fit
     c = synth.config("C3", scale=0.02)
     views = c.views[:6]
