@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build", "hip")
 LIB = os.path.join(HERE, "libddgs.so")
-SOURCES = ["ddgs_api.hip", "project.hip", "sort.hip", "raster.hip", "loss.hip", "pose.hip", "fit.hip", "rads.hip"]
+SOURCES = ["ddgs_api.hip", "project.hip", "bin.hip", "sort.hip", "raster.hip", "loss.hip", "pose.hip", "fit.hip", "rads.hip"]
 ARCH = "gfx950"
 
 

@@ -94,11 +94,9 @@ struct ddgs_ctx {
     uint64_t model_gen = 0, views_gen = 0, opt_gen = 0;
     uint64_t r_model_gen = ~0ull, r_views_gen = ~0ull, r_opt_gen = ~0ull;
     int64_t M = 0;             // entries of the last render
-    uint32_t *tkey_sorted = nullptr, *tval_sorted = nullptr;
     uint32_t *queue = nullptr;
     int64_t entry_cap = 0;     // capacity of the entry buffers
     bool keep_unsorted = false;
-    bool depth_in_k1 = false;  // the depth order ended in (skey2, sval2)
     bool count_pairs = false;
 
     // captured step
@@ -377,8 +375,20 @@ ddgs_status ensure_static(ddgs_ctx *c)
     DDGS_TRY(ensure_t(c, "rec", 4 * VN, &f4));
     uint2 *u2;
     DDGS_TRY(ensure_t(c, "rect", VN, &u2));
-    const char *u32s[] = {"zkey", "cnt", "skey", "sval", "skey2", "sval2", "off_sorted", "cnt_sorted", "slot_lp"};
+    const char *u32s[] = {"zkey", "cnt", "slot_lp"};
     for (const char *nm : u32s) DDGS_TRY(ensure_t(c, nm, VN, &u));
+    {
+        // per-tile entry counts: zero on allocation, then cleared by every
+        // scatter after the scan has read them
+        uint32_t *prev = buf<uint32_t>(c, "tile_cnt");
+        const size_t prev_bytes = c->bufs.count("tile_cnt") ? c->bufs["tile_cnt"].bytes : 0;
+        DDGS_TRY(ensure_t(c, "tile_cnt", std::max(1, c->n_tiles), &u));
+        if (u && u != prev) HIP_TRY(c, launch_fill_u32(u, 0u, (int64_t)(c->bufs["tile_cnt"].bytes / 4), c->stream));
+        (void)prev_bytes;
+    }
+    DDGS_TRY(ensure_t(c, "cursor", std::max(1, c->n_tiles), &u));
+    uint64_t *tb;
+    DDGS_TRY(ensure_t(c, "tile_bsum", std::max(1, (c->n_tiles + 255) / 256), &tb));
     DDGS_TRY(ensure_t(c, "slot_btot", std::max<int64_t>(1, (int64_t)c->views_h.size() * slot_blocks(n)), &u));
     DDGS_TRY(ensure_t(c, "ranges", std::max(1, c->n_tiles), &u2));
     DDGS_TRY(ensure_t(c, "qkey", std::max(1, c->n_tiles), &u));
@@ -419,15 +429,12 @@ ddgs_status ensure_entries(ddgs_ctx *c, int64_t cap)
     const int64_t VN = c->model.n * (int64_t)c->views_h.size();
     uint32_t *u;
     float4 *f4;
-    DDGS_TRY(ensure_t(c, "tkey", cap, &u));
+    uint2 *e2;
+    DDGS_TRY(ensure_t(c, "bin_ent", cap, &e2));
+    DDGS_TRY(ensure_t(c, "bin_tmp", cap, &e2));
     DDGS_TRY(ensure_t(c, "tval", cap, &u));
-    DDGS_TRY(ensure_t(c, "tkey2", cap, &u));
-    DDGS_TRY(ensure_t(c, "tval2", cap, &u));
     DDGS_TRY(ensure_t(c, "slot", 2 * cap, &f4));
-    if (c->keep_unsorted) {
-        DDGS_TRY(ensure_t(c, "ukey", cap, &u));
-        DDGS_TRY(ensure_t(c, "uval", cap, &u));
-    }
+    if (c->keep_unsorted) DDGS_TRY(ensure_t(c, "ubin", cap, &e2));
     // work items of the chunked raster and their per-pixel (C, T) partials
     const int split = effective_split(c);
     const int64_t max_items = split > 0 ? cap / split + c->n_tiles + 1 : 1;
@@ -437,7 +444,7 @@ ddgs_status ensure_entries(ddgs_ctx *c, int64_t cap)
     DDGS_TRY(ensure_t(c, "item_cnt", std::max(1, c->n_tiles), &u));
     DDGS_TRY(ensure_t(c, "item_base", std::max(1, c->n_tiles), &u));
     DDGS_TRY(ensure_t(c, "part", (size_t)(split > 0 ? max_items : 1) * c->opt.tile_w * c->opt.tile_h, &f2));
-    const int64_t big = std::max<int64_t>({VN, cap, (int64_t)c->n_tiles, 1});
+    const int64_t big = std::max<int64_t>({VN, (int64_t)c->n_tiles, 1});
     DDGS_TRY(ensure_t(c, "sort_counts", sort_counts_words(big), &u));
     DDGS_TRY(ensure_t(c, "sort_tot", kSortTotWords, &u));
     uint64_t *bs;
@@ -507,60 +514,49 @@ void set_items(ddgs_ctx *c, RasterArgs &ra, bool backward)
     ra.queue_counter = c->opt.persistent ? counter_ptr(c) + (backward ? 1 : 0) : nullptr;
 }
 
-// Projection, depth sort and scan of the tile counts (stages shared by the
-// plain and the captured paths).
-ddgs_status enqueue_front(ddgs_ctx *c)
+// Projection (which also counts every tile's entries) and the scan of the
+// tile counts into the tile ranges (stages shared by the plain and the
+// captured paths).  capacity: entries the tile lists may hold (the plain path
+// passes 2^32 - 1 and sizes its buffers from the total afterwards); captured:
+// the step counters (skipped replays, largest need) are kept.
+ddgs_status enqueue_front(ddgs_ctx *c, uint32_t capacity, bool captured)
 {
     hipStream_t s = c->stream;
     const ModelDev m = model_dev(c->model, c->c_override);
     const int V = (int)c->views_h.size();
-    const int64_t VN = (int64_t)m.n * V;
     GaussCache gc{buf<float>(c, "cov"), buf<float>(c, "alpha"), buf<float>(c, "ciso"), buf<float>(c, "hdir")};
     ProjOut po{buf<float4>(c, "rec"),      buf<uint2>(c, "rect"),     buf<uint32_t>(c, "zkey"),
-               buf<uint32_t>(c, "cnt"),    buf<uint32_t>(c, "skey"),  buf<uint32_t>(c, "sval"),
-               buf<uint32_t>(c, "slot_lp"), buf<uint32_t>(c, "slot_btot")};
+               buf<uint32_t>(c, "cnt"),    buf<uint32_t>(c, "tile_cnt"), buf<uint32_t>(c, "slot_lp"),
+               buf<uint32_t>(c, "slot_btot")};
     const RenderOpts ro = render_opts(c->opt);
     stage_begin(c, DDGS_T_PROJECT);
     HIP_TRY(c, launch_prep_project(m, gc, buf<ViewDev>(c, "views"), V, ro, po, s));
     stage_end(c, DDGS_T_PROJECT);
     stage_begin(c, DDGS_T_SORT);
-    bool in_k1 = false;
-    HIP_TRY(c, radix_sort_pairs(po.sort_key, po.sort_val, buf<uint32_t>(c, "skey2"), buf<uint32_t>(c, "sval2"), VN,
-                                nullptr, 32, sort_ws(c), &in_k1, s, po.cnt, buf<uint32_t>(c, "cnt_sorted")));
-    c->depth_in_k1 = in_k1;
-    // (the last depth pass also wrote the tile counts in depth order)
-    HIP_TRY(c, launch_exclusive_scan(buf<uint32_t>(c, "cnt_sorted"), nullptr, buf<uint32_t>(c, "off_sorted"), VN,
-                                     sort_ws(c), total_ptr(c), s));
+    HIP_TRY(c, launch_tile_scan(buf<uint32_t>(c, "tile_cnt"), c->n_tiles, buf<uint2>(c, "ranges"),
+                                buf<uint32_t>(c, "cursor"), capacity, total_ptr(c), mdev_ptr(c), flags_ptr(c),
+                                captured ? skipped_ptr(c) : nullptr, captured ? need_ptr(c) : nullptr,
+                                buf<uint32_t>(c, "slot_btot"), (int64_t)V * slot_blocks(m.n), buf<uint64_t>(c, "tile_bsum"),
+                                c->bufs["tile_bsum"].bytes / sizeof(uint64_t), s));
     return DDGS_OK;
 }
 
-// Emission, tile sort, ranges, optional work queue and the forward raster.
-// captured: the step counters (skipped replays, largest need) are kept
-ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, int64_t sort_n, float *images, bool captured)
+// Scatter of the entries into their tile ranges, the per-tile sort, the
+// optional work items or queue, and the forward raster.
+ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, float *images)
 {
     hipStream_t s = c->stream;
     const int V = (int)c->views_h.size();
     const int n = (int)c->model.n;
     const int64_t VN = (int64_t)n * V;
-    // the depth order: the values of the depth sort, in whichever buffer its
-    // last pass wrote
-    const uint32_t *order = c->depth_in_k1 ? buf<uint32_t>(c, "sval2") : buf<uint32_t>(c, "sval");
-    uint32_t *tkey = buf<uint32_t>(c, "tkey"), *tval = buf<uint32_t>(c, "tval");
-    HIP_TRY(c, launch_emit(VN, n, order, buf<uint32_t>(c, "off_sorted"), buf<uint32_t>(c, "cnt_sorted"),
-                           buf<uint2>(c, "rect"), buf<ViewDev>(c, "views"), tkey, tval, buf<uint32_t>(c, "slot_btot"),
-                           (int64_t)c->views_h.size() * slot_blocks(n), (uint32_t)cap, total_ptr(c), mdev_ptr(c),
-                           flags_ptr(c), captured ? skipped_ptr(c) : nullptr, captured ? need_ptr(c) : nullptr,
-                           buf<uint2>(c, "ranges"), c->n_tiles, s));
-    if (c->keep_unsorted) {
-        HIP_TRY(c, launch_copy_u32(buf<uint32_t>(c, "ukey"), tkey, mdev_ptr(c), sort_n, s));
-        HIP_TRY(c, launch_copy_u32(buf<uint32_t>(c, "uval"), tval, mdev_ptr(c), sort_n, s));
-    }
-    bool in_k1 = false;
-    HIP_TRY(c, radix_sort_pairs(tkey, tval, buf<uint32_t>(c, "tkey2"), buf<uint32_t>(c, "tval2"), sort_n, mdev_ptr(c),
-                                bits_for(c->n_tiles), sort_ws(c), &in_k1, s));
-    c->tkey_sorted = in_k1 ? buf<uint32_t>(c, "tkey2") : tkey;
-    c->tval_sorted = in_k1 ? buf<uint32_t>(c, "tval2") : tval;
-    HIP_TRY(c, launch_ranges(c->tkey_sorted, mdev_ptr(c), sort_n, buf<uint2>(c, "ranges"), c->n_tiles, false, s));
+    uint2 *ent = buf<uint2>(c, "bin_ent");
+    HIP_TRY(c, launch_bin_scatter(VN, n, buf<uint32_t>(c, "cnt"), buf<uint2>(c, "rect"), buf<uint32_t>(c, "zkey"),
+                                  buf<ViewDev>(c, "views"), buf<uint32_t>(c, "cursor"), (uint32_t)cap, ent,
+                                  buf<uint32_t>(c, "tile_cnt"), c->n_tiles, s));
+    if (c->keep_unsorted)
+        HIP_TRY(c, launch_copy_u32((uint32_t *)buf<uint2>(c, "ubin"), (const uint32_t *)ent, nullptr, 2 * cap, s));
+    HIP_TRY(c, launch_tile_sort(buf<uint2>(c, "ranges"), c->n_tiles, ent, buf<uint2>(c, "bin_tmp"),
+                                buf<uint32_t>(c, "tval"), s));
     c->queue = nullptr;
     const int split = effective_split(c);
     c->max_items = (int)max_items_for(c, cap);
@@ -584,7 +580,7 @@ ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, int64_t sort_n, float *images
     ra.n = n;
     ra.o = render_opts(c->opt);
     ra.ranges = buf<uint2>(c, "ranges");
-    ra.tval = c->tval_sorted;
+    ra.tval = buf<uint32_t>(c, "tval");
     ra.rec = buf<float4>(c, "rec");
     ra.n_tiles = c->n_tiles;
     set_items(c, ra, false);
@@ -630,7 +626,7 @@ ddgs_status enqueue_backward(ddgs_ctx *c, const float *dL, const ddgs_grads *g, 
     ra.n = n;
     ra.o = render_opts(c->opt);
     ra.ranges = buf<uint2>(c, "ranges");
-    ra.tval = c->tval_sorted;
+    ra.tval = buf<uint32_t>(c, "tval");
     ra.rec = buf<float4>(c, "rec");
     ra.n_tiles = c->n_tiles;
     set_items(c, ra, true);
@@ -897,7 +893,6 @@ ddgs_status ddgs_set_workspace(ddgs_ctx *c, void *dev, size_t bytes)
     c->views_dirty = true;
     c->entry_cap = 0;
     c->rendered = false;
-    c->tkey_sorted = c->tval_sorted = nullptr;
     c->queue = nullptr;
     return DDGS_OK;
 }
@@ -1329,27 +1324,27 @@ ddgs_status ddgs_render(ddgs_ctx *c, float *images)
     DDGS_TRY(ensure_entries(c, std::max<int64_t>(c->entry_cap, 1)));
     const int64_t VN = c->model.n * (int64_t)c->views_h.size();
     if (VN > 0) {
-        DDGS_TRY(enqueue_front(c));
+        DDGS_TRY(enqueue_front(c, 0xFFFFFFFFu, false));
         uint32_t sc[4] = {0, 0, 0, 0};
         HIP_TRY(c, hipMemcpyAsync(sc, total_ptr(c), sizeof(sc), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         const uint64_t total = (uint64_t)sc[0] | ((uint64_t)sc[1] << 32);
-        if (total >= 0xFFFFFFFFull) return fail(c, DDGS_ERR_CAPACITY, "more than 2^32-1 tile entries");
+        ddgs_status st = DDGS_OK;
+        if (total >= 0xFFFFFFFFull) st = fail(c, DDGS_ERR_CAPACITY, "more than 2^32-1 tile entries");
         c->M = (int64_t)total;
-        if (c->M > c->entry_cap) DDGS_TRY(ensure_entries(c, c->M));
-    } else {
-        c->M = 0;
-        HIP_TRY(c, launch_zero_u64(total_ptr(c), c->stream));
-    }
-    if (VN > 0) {
-        DDGS_TRY(enqueue_back(c, c->entry_cap, c->M, images, false));
+        if (st == DDGS_OK && c->M > c->entry_cap) st = ensure_entries(c, c->M);
+        if (st != DDGS_OK) {
+            // the scatter that clears the per-tile counts will not run
+            (void)launch_fill_u32(buf<uint32_t>(c, "tile_cnt"), 0u, c->n_tiles, c->stream);
+            return st;
+        }
+        DDGS_TRY(enqueue_back(c, c->entry_cap, images));
     } else {
         // no Gaussians: empty lists everywhere
+        c->M = 0;
+        HIP_TRY(c, launch_zero_u64(total_ptr(c), c->stream));
         HIP_TRY(c, launch_fill_u32(mdev_ptr(c), 0u, 1, c->stream));
-        HIP_TRY(c, launch_ranges(buf<uint32_t>(c, "tkey"), mdev_ptr(c), 0, buf<uint2>(c, "ranges"), c->n_tiles,
-                                 true, c->stream));
-        c->tkey_sorted = buf<uint32_t>(c, "tkey");
-        c->tval_sorted = buf<uint32_t>(c, "tval");
+        HIP_TRY(c, launch_ranges(nullptr, mdev_ptr(c), 0, buf<uint2>(c, "ranges"), c->n_tiles, true, c->stream));
         c->queue = nullptr;
         RasterArgs ra{};
         ra.views = buf<ViewDev>(c, "views");
@@ -1357,7 +1352,7 @@ ddgs_status ddgs_render(ddgs_ctx *c, float *images)
         ra.n = 1;
         ra.o = render_opts(c->opt);
         ra.ranges = buf<uint2>(c, "ranges");
-        ra.tval = c->tval_sorted;
+        ra.tval = buf<uint32_t>(c, "tval");
         ra.rec = buf<float4>(c, "rec");
         ra.n_tiles = c->n_tiles;
         ra.img = images;
@@ -1452,8 +1447,8 @@ ddgs_status ddgs_step_capture(ddgs_ctx *c, int kind, const float *target, float 
     const bool saved_timing = c->timing;
     c->timing = false;
     HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    ddgs_status st = enqueue_front(c);
-    if (st == DDGS_OK) st = enqueue_back(c, c->step_cap, c->step_cap, images, true);
+    ddgs_status st = enqueue_front(c, (uint32_t)c->step_cap, true);
+    if (st == DDGS_OK) st = enqueue_back(c, c->step_cap, images);
     if (st == DDGS_OK) st = enqueue_loss(c, kind, images, target, lambda, loss_out, dL);
     if (st == DDGS_OK) st = enqueue_backward(c, dL, g, c->step_cap, true);
     if (st == DDGS_OK && c->adam_on) {
@@ -1572,7 +1567,6 @@ ddgs_status ddgs_set_allocator(ddgs_ctx *c, ddgs_alloc_fn alloc, ddgs_free_fn fr
     c->views_dirty = true;
     c->entry_cap = 0;
     c->rendered = false;
-    c->tkey_sorted = c->tval_sorted = nullptr;
     c->queue = nullptr;
     return DDGS_OK;
 }
@@ -1695,14 +1689,30 @@ ddgs_status ddgs_debug_copy(ddgs_ctx *c, int what, void *host, size_t bytes)
     case DDGS_DBG_DEPTH_KEYS: src = buf<void>(c, "zkey"); need = (size_t)VN * 4; break;
     case DDGS_DBG_COUNTS: src = buf<void>(c, "cnt"); need = (size_t)VN * 4; break;
     case DDGS_DBG_RECTS: src = buf<void>(c, "rect"); need = (size_t)VN * 8; break;
-    case DDGS_DBG_TILE_KEYS_UNSORTED:
-    case DDGS_DBG_TILE_VALS_UNSORTED:
-        if (!c->keep_unsorted) return fail(c, DDGS_ERR_STATE, "unsorted entries were not kept");
-        src = buf<void>(c, what == DDGS_DBG_TILE_KEYS_UNSORTED ? "ukey" : "uval");
+    case DDGS_DBG_TILE_KEYS:
+    case DDGS_DBG_TILE_KEYS_UNSORTED: {
+        // the entries are binned by tile: every place of tile t's range holds t
+        if (what == DDGS_DBG_TILE_KEYS_UNSORTED && !c->keep_unsorted)
+            return fail(c, DDGS_ERR_STATE, "unsorted entries were not kept");
         need = (size_t)M * 4;
-        break;
-    case DDGS_DBG_TILE_KEYS: src = c->tkey_sorted; need = (size_t)M * 4; break;
-    case DDGS_DBG_TILE_VALS: src = c->tval_sorted; need = (size_t)M * 4; break;
+        if (bytes < need) return fail(c, DDGS_ERR_INVALID_ARG, "buffer too small: need " + std::to_string(need));
+        std::vector<uint2> rg(std::max(1, c->n_tiles));
+        if (c->n_tiles > 0)
+            HIP_TRY(c, hipMemcpy(rg.data(), buf<void>(c, "ranges"), sizeof(uint2) * c->n_tiles, hipMemcpyDeviceToHost));
+        uint32_t *o = (uint32_t *)host;
+        for (int t = 0; t < c->n_tiles; ++t)
+            for (uint32_t j = rg[t].x; j < rg[t].y && j < (uint32_t)M; ++j) o[j] = (uint32_t)t;
+        return DDGS_OK;
+    }
+    case DDGS_DBG_TILE_VALS_UNSORTED: {
+        if (!c->keep_unsorted) return fail(c, DDGS_ERR_STATE, "unsorted entries were not kept");
+        need = (size_t)M * 4;
+        if (bytes < need) return fail(c, DDGS_ERR_INVALID_ARG, "buffer too small: need " + std::to_string(need));
+        if (M > 0)
+            HIP_TRY(c, hipMemcpy2D(host, 4, (const char *)buf<void>(c, "ubin") + 4, 8, 4, (size_t)M, hipMemcpyDeviceToHost));
+        return DDGS_OK;
+    }
+    case DDGS_DBG_TILE_VALS: src = buf<void>(c, "tval"); need = (size_t)M * 4; break;
     case DDGS_DBG_RANGES: src = buf<void>(c, "ranges"); need = (size_t)c->n_tiles * 8; break;
     case DDGS_DBG_NLAST: src = buf<void>(c, "nlast"); need = (size_t)c->total_pix * 4; break;
     case DDGS_DBG_TILE_BASE: {

@@ -255,8 +255,6 @@ __device__ __forceinline__ void project_one(const ModelDev &m, const ViewDev *vi
         const bool ok = project_geom(V, mx, my, mz, cw, o, g);
         if (!ok) {
             po.zkey[vi] = 0xFFFFFFFFu;
-            po.sort_key[vi] = 0xFFFFFFFFu;
-            po.sort_val[vi] = (uint32_t)vi;
             po.cnt[vi] = 0;
             po.rect[vi] = make_uint2(0, 0);
             po.rec[4 * vi] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -291,10 +289,11 @@ __device__ __forceinline__ void project_one(const ModelDev &m, const ViewDev *vi
                 const int ty0 = (int)fv0 / o.tile_h, ty1 = (int)fv1 / o.tile_h;
                 count = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
                 rc = make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16));
+                // one entry per touched tile, counted per tile for the binning
+                for (int ty = ty0; ty <= ty1; ++ty)
+                    for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&po.tile_cnt[V.tile_base + ty * V.ntx + tx], 1u);
             }
             po.zkey[vi] = g.zbits;
-            po.sort_key[vi] = g.zbits;
-            po.sort_val[vi] = (uint32_t)vi;
             po.cnt[vi] = count;
             po.rect[vi] = rc;
             po.rec[4 * vi] = make_float4(g.mux, g.muy, g.A00, g.A01);

@@ -1,17 +1,10 @@
-// sort.hip -- tile binning of the projected footprints on gfx950: exclusive
-// scan of the per-(view, Gaussian) tile counts, emission of one
-// (tile, Gaussian) entry per touched tile, a stable LSD radix sort of
-// (key, value) u32 pairs, and the per-tile [start, end) ranges.
-//
-// Ordering scheme.  The tile lists must be ordered by (tile, depth, index)
-// (Eq. 1 composites front to back; ties by Gaussian index).  Instead of one
-// 64-bit (tile | depth) sort over all entries, the (view, Gaussian) pairs are
-// first sorted by their 32-bit depth key (stable, input in index order), the
-// entries are then emitted in that depth order, and a stable sort on the
-// tile id alone (1-2 passes) groups them by tile without disturbing the
-// depth order inside a tile.  The result is identical to the 64-bit sort and
-// moves far fewer bytes, since the depth pass runs over V*n pairs instead of
-// the several-times larger entry count.
+// sort.hip -- scans and the hand-written stable LSD radix sort on gfx950:
+// exclusive scans of u32 arrays (with 64-bit totals), the work items of the
+// chunked raster, a stable LSD radix sort of (key, value) u32 pairs (the
+// persistent raster's tile queue, the dual-sampling subsample, and an entry
+// point of its own), and per-tile [start, end) ranges of a sorted key array.
+// The tile lists of the render path are built by binning (bin.hip), which
+// needs no global sort.
 #include "internal.h"
 
 namespace ddgs {
@@ -433,110 +426,6 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *k
     }
 }
 
-// ------------------------------------------------------------------ emit
-
-// Entries of the (view, Gaussian) pairs in depth order.  The 64 pairs of a
-// wave own one contiguous output range [off(r0), off(r0 + 63) + cnt), so the
-// lanes walk that range together, consecutive lanes on consecutive entries,
-// and each finds the pair an entry belongs to by a binary search over the
-// wave's 64 offsets (read from the owning lanes by shuffles).  Within a pair
-// the entries run row-major over its tile rectangle.
-__global__ __launch_bounds__(kBlock) void emit_kernel(int64_t VN, int n, const uint32_t *order,
-                                                      const uint32_t *off_sorted, const uint32_t *cnt_sorted,
-                                                      const uint2 *rect, const ViewDev *views, uint32_t *tkey,
-                                                      uint32_t *tval, uint32_t *slot_btot, int64_t slot_nb,
-                                                      uint32_t capacity, const uint64_t *total, uint32_t *m_out,
-                                                      uint32_t *flags, uint32_t *skipped, unsigned long long *need,
-                                                      uint2 *ranges, int n_tiles)
-{
-    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int lane = threadIdx.x & (kWave - 1);
-    if (blockIdx.x == 0) {
-        // block 0 also turns the slot numbering's block totals into the
-        // blocks' first slots (in-place exclusive scan, wrapping at 2^32
-        // like the slot indices)
-        __shared__ uint32_t wl[kWaves];
-        uint32_t carry = 0;
-        for (int64_t c0 = 0; c0 < slot_nb; c0 += 4 * kBlock) {
-            const int64_t b = c0 + 4 * (int64_t)threadIdx.x;
-            uint32_t x[4], s = 0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                x[q] = b + q < slot_nb ? slot_btot[b + q] : 0u;
-                s += x[q];
-            }
-            uint32_t tot;
-            uint32_t pre = carry + block_excl_scan(s, wl, tot);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (b + q < slot_nb) slot_btot[b + q] = pre;
-                pre += x[q];
-            }
-            carry += tot;
-        }
-    }
-    // clear the tile ranges for the ranges kernel after the sort
-    for (int64_t t = r; t < n_tiles; t += (int64_t)gridDim.x * kBlock) ranges[t] = make_uint2(0u, 0u);
-    if (r == 0) {
-        const uint64_t t = *total;
-        const bool over = t > (uint64_t)capacity;
-        *m_out = over ? capacity : (uint32_t)t;
-        const uint32_t f = *flags | (over ? 1u : 0u);
-        *flags = f;
-        if (skipped) {
-            // captured step: from the first overflow on, every replay until
-            // the flags are cleared skips its optimiser updates
-            if (f & 1u) *skipped = *skipped + 1u;
-            if ((unsigned long long)t > *need) *need = (unsigned long long)t;
-        }
-    }
-    const bool valid = r < VN;
-    uint32_t c = 0, off = 0xFFFFFFFFu, i = 0, x0y0 = 0, span = 1, rowbase = 0, ntx = 0;
-    if (valid) {
-        const uint32_t vi = order[r];
-        c = cnt_sorted[r];
-        off = off_sorted[r];
-        if (c) {
-            const uint32_t v = vi / (uint32_t)n;
-            i = vi - v * (uint32_t)n;
-            const uint2 rc = rect[vi];
-            x0y0 = rc.x;
-            span = (rc.y & 0xFFFF) - (rc.x & 0xFFFF) + 1u;
-            rowbase = (uint32_t)views[v].tile_base;
-            ntx = (uint32_t)views[v].ntx;
-        }
-    }
-    // the wave's range; lanes past VN hold off = ~0 and never match
-    const uint64_t my_end = valid ? (uint64_t)off + c : 0ull;
-    uint64_t wend = my_end;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) wend = max(wend, (uint64_t)__shfl_xor((unsigned long long)wend, o, kWave));
-    if (wend > (uint64_t)capacity) wend = capacity;
-    const uint32_t wbeg = (uint32_t)__shfl((int)off, 0, kWave);
-    // (uniform loop: every lane takes part in the shuffles, since a shuffle
-    // from an inactive lane does not return that lane's value)
-    for (uint64_t e0 = (uint64_t)wbeg; e0 < wend; e0 += kWave) {
-        const uint64_t e = e0 + (uint64_t)lane;
-        int L = 0;
-#pragma unroll
-        for (int step = 32; step > 0; step >>= 1) {
-            const uint32_t o = (uint32_t)__shfl((int)off, L + step, kWave);
-            if (o != 0xFFFFFFFFu && (uint64_t)o <= e) L += step;
-        }
-        const uint32_t k = (uint32_t)(e - (uint64_t)(uint32_t)__shfl((int)off, L, kWave));
-        const uint32_t sp = (uint32_t)__shfl((int)span, L, kWave);
-        const uint32_t xy = (uint32_t)__shfl((int)x0y0, L, kWave);
-        const uint32_t rb = (uint32_t)__shfl((int)rowbase, L, kWave);
-        const uint32_t nt = (uint32_t)__shfl((int)ntx, L, kWave);
-        const uint32_t gi = (uint32_t)__shfl((int)i, L, kWave);
-        if (e < wend) {
-            const uint32_t dy = k / sp, dx = k - dy * sp;
-            tkey[e] = rb + ((xy >> 16) + dy) * nt + (xy & 0xFFFF) + dx;
-            tval[e] = gi;
-        }
-    }
-}
-
 __global__ void zero_u64_kernel(uint64_t *p) { *p = 0; }
 
 __global__ __launch_bounds__(kBlock) void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n)
@@ -736,19 +625,6 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
         std::swap(va, vb);
         *in_k1 = !*in_k1;
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_emit(int64_t VN, int n, const uint32_t *order, const uint32_t *off_sorted,
-                       const uint32_t *cnt_sorted, const uint2 *rect, const ViewDev *views, uint32_t *tkey,
-                       uint32_t *tval, uint32_t *slot_btot, int64_t slot_nb, uint32_t capacity,
-                       const uint64_t *total, uint32_t *m_out, uint32_t *flags, uint32_t *skipped,
-                       unsigned long long *need, uint2 *ranges, int n_tiles, hipStream_t s)
-{
-    const int64_t nb = std::max<int64_t>(1, blocks_for(VN, kBlock));
-    emit_kernel<<<(unsigned)nb, kBlock, 0, s>>>(VN, n, order, off_sorted, cnt_sorted, rect, views, tkey, tval,
-                                                slot_btot, slot_nb, capacity, total, m_out, flags, skipped, need,
-                                                ranges, n_tiles);
     return hipGetLastError();
 }
 

@@ -129,9 +129,11 @@ def test_tile_lists_bit_exact(R):
         ranges = R.debug(binding.DBG_RANGES, np.uint32, int(base[-1]) * 2).reshape(-1, 2)
     finally:
         binding.ddgs_debug_keep_unsorted(R.ctx, 0)
-    s = np.argsort(uk, kind="stable")
-    np.testing.assert_array_equal(sk, uk[s])
-    np.testing.assert_array_equal(sv, uv[s])
+    # the scatter bins the entries by tile (every place of a tile's range
+    # holds that tile) with an arbitrary order inside the range: the same
+    # entries as the sorted lists, tile by tile
+    np.testing.assert_array_equal(uk, sk)
+    np.testing.assert_array_equal(uv[np.lexsort((uv, uk))], sv[np.lexsort((sv, sk))])
     # same lists from the per-(view, Gaussian) keys and rectangles on the host
     n = c.scene.n
     _, zk, cnt, rects = _records(R, len(views), n)
@@ -150,6 +152,40 @@ def test_tile_lists_bit_exact(R):
     for v, view in enumerate(views):
         P = ref.project(c.scene, view)
         np.testing.assert_array_equal(zk[v][P[:, 0] > 0], P[P[:, 0] > 0, 8].astype(np.float32).view(np.uint32))
+
+
+def test_tile_lists_long_ranges_and_depth_ties(R):
+    """Tile ranges longer than the per-tile sort holds in LDS (sorted from
+    global memory in chunks) and runs of Gaussians with identical depth keys
+    (ordered by index): the sorted lists equal the host construction, for
+    both tile shapes that reach such lengths, and the image the oracle's."""
+    n = 7000
+    sc = synth.random_scene(31, n, k=8, L=1, extent=6.0, std_range=(1.5, 3.0), alpha_range=(0.01, 0.03))
+    # groups of four Gaussians share one mean (equal depth keys, index order decides)
+    sc.mean[:, 1:2000:4] = sc.mean[:, 0:2000:4]
+    sc.mean[:, 2:2000:4] = sc.mean[:, 0:2000:4]
+    sc.mean[:, 3:2000:4] = sc.mean[:, 0:2000:4]
+    v = synth.view(96, 80, 0.5, 1000.0, 600.0, 10.0)
+    R.set_scene(sc)
+    R.set_views([v])
+    try:
+        for tw, th in ((16, 16), (32, 8)):
+            R.set_options(tile_w=tw, tile_h=th, split=256)
+            img = R.render().cpu().numpy()
+            M = R.num_rendered()
+            sk = R.debug(binding.DBG_TILE_KEYS, np.uint32, M)
+            sv = R.debug(binding.DBG_TILE_VALS, np.uint32, M)
+            base = R.debug(binding.DBG_TILE_BASE, np.int32, 2)
+            ranges = R.debug(binding.DBG_RANGES, np.uint32, int(base[-1]) * 2).reshape(-1, 2)
+            assert (ranges[:, 1] - ranges[:, 0]).max() > 4096
+            _, zk, cnt, rects = _records(R, 1, n)
+            ek, ev = expected_tile_lists(zk.ravel(), cnt.ravel(), rects.reshape(-1, 4), base,
+                                         [(v.W + tw - 1) // tw], n)
+            np.testing.assert_array_equal(sk, ek)
+            np.testing.assert_array_equal(sv, ev)
+            assert rel_l2(img, ref.render(sc, [v])[0]) < 1e-4
+    finally:
+        R.set_options(tile_w=16, tile_h=16, split=256)
 
 
 # ---------------------------------------------------- radiosity override
