@@ -107,7 +107,7 @@ __device__ __forceinline__ void write_range(const ScanArgs &a, int t, uint64_t s
 {
     const uint64_t end = start + c, cap = a.capacity;
     const uint32_t s = (uint32_t)(start < cap ? start : cap), e = (uint32_t)(end < cap ? end : cap);
-    a.ranges[t] = make_uint2(s, e);
+    a.ranges[t] = e > s ? make_uint2(s, e) : make_uint2(0u, 0u);  // empty tiles: [0, 0)
     a.cursor[t] = s;
 }
 

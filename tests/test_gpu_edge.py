@@ -258,7 +258,7 @@ def test_fitting_retries_overflow_exactly(RS):
     views = c.views[:6]
     R.set_scene(c.scene)
     R.set_views(views)
-    targets = [t.clone() for t in R.split(R.render())]
+    targets = [t.reshape(-1).clone() for t in R.split(R.render())]
     results = []
     for cap in (0, 64):
         p = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in c.scene.arrays().items()}
