@@ -5,19 +5,17 @@
 //
 // Ordering scheme.  Eq. 1 composites a pixel's Gaussians front to back, so
 // each tile's list must be ordered by (depth key, Gaussian index).  Instead of
-// sorting every entry globally, the entries are binned by tile first: the
-// projection counts the entries of every tile with one atomic increment per
-// entry, one scan turns the counts into the tile ranges, and the scatter
-// claims a place inside its tile's range with an atomic cursor (so the order
-// inside a range is arbitrary).  One workgroup per tile then sorts its range
-// in LDS: a stable LSD radix sort on the depth key relative to the tile's
-// smallest key (only the bits that differ inside the tile), after which runs
-// of equal keys -- rare, FP32 depths of different Gaussians -- are put in
-// index order.  The result is bit-identical to a global stable sort on
-// (tile, depth, index), since that order is total.  The whole stage is three
-// launches (scan, scatter, sort) after the projection, against the dozen
-// of a global multi-pass radix sort, which on this path ran at the launch
-// floor.
+// sorting every entry globally, the entries are binned by tile first: per-
+// tile counts from LDS histograms of groups of Gaussians, one scan of the
+// counts into the tile ranges, and a scatter that places each entry inside
+// its tile's range (the order inside a range is arbitrary).  One workgroup
+// per tile then orders its range: entries are bucketed by the leading bits
+// of their (depth, index) code relative to the tile's smallest depth and
+// index, and ranked inside their bucket.  The result is bit-identical to a
+// global stable sort on (tile, depth, index), since that order is total.
+// The stage takes five launches after the projection (count, column scan,
+// tile scan, scatter, sort), against the dozen of a global multi-pass radix
+// sort, which on this path ran at the launch floor.
 #include "internal.h"
 
 namespace ddgs {
@@ -190,126 +188,177 @@ __global__ __launch_bounds__(kBlock) void tile_apply_kernel(const uint64_t *bsum
     if (t < a.n_tiles) write_range(a, t, bsum[blockIdx.x] + pre, v);
 }
 
-// ---------------------------------------------------------------- scatter
-// One thread per (view, Gaussian) pair: every tile of its rectangle claims
-// the next free place of that tile's range and stores (depth key, index).
-// Places at or beyond the capacity are dropped (an overflowed step, which the
-// flags report).  The grid also clears the tile counters for the next
-// projection.
-__global__ __launch_bounds__(kBlock) void bin_scatter_kernel(int64_t VN, int n, const uint32_t *cnt,
-                                                             const uint2 *rect, const uint32_t *zkey,
-                                                             const ViewDev *views, uint32_t *cursor,
-                                                             uint32_t capacity, uint2 *out, uint32_t *tile_cnt,
-                                                             int n_tiles)
+// ------------------------------------------------------- count and scatter
+// Global atomics on a few thousand tile counters serialise per address on
+// this part (a probe measured ~0.3 us per increment of one counter, 0.23 ms
+// for 3.3M entries over 4096 tiles), so no global atomic is used.  Instead
+// the pairs of each view are cut into groups of `per` Gaussians, and one
+// workgroup per (group, view, window of kWin tiles) counts its group's
+// entries per tile in LDS and writes the counts as one row of a count matrix
+// (per view: [groups][tiles of the view]).  A column scan turns every
+// column into the group's offset inside its tile and yields the tile
+// totals, the tile scan turns the totals into ranges, and the scatter
+// re-walks the same groups: an entry's place is its tile's start + its
+// group's offset + a place claimed from an LDS cursor (the order inside a
+// group is arbitrary; the per-tile sort fixes it).
+constexpr int kWin = 16384;  // tiles of one view held in LDS at a time
+
+struct BinArgs {
+    int n, V, groups, per;        // per: Gaussians per group
+    const uint32_t *cnt;          // [V*n] tiles touched per pair
+    const uint2 *rect;            // [V*n] tile rectangles
+    const uint32_t *zkey;         // [V*n]
+    const ViewDev *views;
+    uint32_t *mat;                // [groups * n_tiles]: view v at groups * tile_base[v]
+};
+
+// Calls f(local tile) for every tile of pair r's rectangle inside [t0, t1).
+template <class F>
+__device__ __forceinline__ void for_tiles(const BinArgs &a, int64_t r, int ntx, int t0, int t1, F f)
 {
-    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    for (int64_t t = r; t < n_tiles; t += (int64_t)gridDim.x * kBlock) tile_cnt[t] = 0u;
-    if (r >= VN) return;
-    if (cnt[r] == 0u) return;
-    const uint32_t v = (uint32_t)(r / n), i = (uint32_t)(r - (int64_t)v * n);
-    const uint2 rc = rect[r];
-    const uint32_t key = zkey[r];
+    const uint2 rc = a.rect[r];
     const int tx0 = rc.x & 0xFFFF, ty0 = rc.x >> 16, tx1 = rc.y & 0xFFFF, ty1 = rc.y >> 16;
-    const int base = views[v].tile_base, ntx = views[v].ntx;
+    if ((ty1 + 1) * ntx <= t0 || ty0 * ntx >= t1) return;  // no row of the rectangle in the window
     for (int ty = ty0; ty <= ty1; ++ty)
         for (int tx = tx0; tx <= tx1; ++tx) {
-            const uint32_t p = atomicAdd(&cursor[base + ty * ntx + tx], 1u);
-            if (p < capacity) out[p] = make_uint2(key, i);
+            const int lt = ty * ntx + tx;
+            if (lt >= t0 && lt < t1) f(lt);
         }
+}
+
+__global__ __launch_bounds__(kBlock) void bin_count_kernel(BinArgs a)
+{
+    extern __shared__ uint32_t hist[];
+    const int g = blockIdx.x, v = blockIdx.y, w = blockIdx.z;
+    const ViewDev &V = a.views[v];
+    const int Tv = V.ntx * V.nty, t0 = w * kWin;
+    if (t0 >= Tv) return;
+    const int t1 = min(Tv, t0 + kWin), nt = t1 - t0;
+    for (int j = threadIdx.x; j < nt; j += kBlock) hist[j] = 0u;
+    __syncthreads();
+    const int i0 = g * a.per, i1 = min(a.n, i0 + a.per);
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += kBlock) {
+        const int64_t r = (int64_t)v * a.n + i;
+        if (a.cnt[r] == 0u) continue;
+        for_tiles(a, r, V.ntx, t0, t1, [&](int lt) { atomicAdd(&hist[lt - t0], 1u); });
+    }
+    __syncthreads();
+    uint32_t *row = a.mat + (size_t)a.groups * V.tile_base + (size_t)g * Tv + t0;
+    for (int j = threadIdx.x; j < nt; j += kBlock) row[j] = hist[j];
+}
+
+// 64 tiles per workgroup, the groups split among kColParts waves: every wave
+// sums its share of the 64 columns (consecutive lanes on consecutive
+// columns), the shares are combined in LDS, and every wave writes its rows'
+// exclusive offsets.  tile_cnt[t] receives the column total.
+constexpr int kColParts = 8;
+__global__ __launch_bounds__(kWave *kColParts) void bin_colscan_kernel(BinArgs a, int n_tiles, uint32_t *tile_cnt)
+{
+    __shared__ uint32_t part[kColParts][kWave];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int t = blockIdx.x * kWave + lane;
+    const bool ok = t < n_tiles;
+    int v = 0;
+    if (ok) {
+        int lo = 0, hi = a.V - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.views[mid].tile_base <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        v = lo;
+    }
+    const ViewDev &V = a.views[v];
+    const int Tv = V.ntx * V.nty, lt = t - V.tile_base;
+    uint32_t *col = a.mat + (size_t)a.groups * V.tile_base + lt;
+    const int rows = (a.groups + kColParts - 1) / kColParts;
+    const int g0 = w * rows, g1 = min(a.groups, g0 + rows);
+    // the wave's rows, sixteen loads in flight
+    uint32_t sum = 0;
+    for (int g = g0; g < g1; g += 16) {
+        uint32_t x[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) x[q] = (ok && g + q < g1) ? col[(size_t)(g + q) * Tv] : 0u;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) sum += x[q];
+    }
+    part[w][lane] = sum;
+    __syncthreads();
+    uint32_t run = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < kColParts; ++q) {
+        const uint32_t c = part[q][lane];
+        if (q < w) run += c;
+        tot += c;
+    }
+    if (ok && w == 0) tile_cnt[t] = tot;
+    for (int g = g0; g < g1; g += 16) {
+        uint32_t x[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) x[q] = (ok && g + q < g1) ? col[(size_t)(g + q) * Tv] : 0u;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if (ok && g + q < g1) col[(size_t)(g + q) * Tv] = run;
+            run += x[q];
+        }
+    }
+}
+
+// Places: start[tile] (the tile's range start, clamped to the capacity) +
+// the group's offset + an LDS cursor; places at or beyond the capacity are
+// dropped (an overflowed step, which the flags report).
+__global__ __launch_bounds__(kBlock) void bin_scatter_kernel(BinArgs a, const uint32_t *start, uint32_t capacity,
+                                                             uint2 *out)
+{
+    extern __shared__ uint32_t cur[];
+    const int g = blockIdx.x, v = blockIdx.y, w = blockIdx.z;
+    const ViewDev &V = a.views[v];
+    const int Tv = V.ntx * V.nty, t0 = w * kWin;
+    if (t0 >= Tv) return;
+    const int t1 = min(Tv, t0 + kWin), nt = t1 - t0;
+    for (int j = threadIdx.x; j < nt; j += kBlock) cur[j] = 0u;
+    __syncthreads();
+    const uint32_t *row = a.mat + (size_t)a.groups * V.tile_base + (size_t)g * Tv;
+    const uint32_t *st = start + V.tile_base;
+    const int i0 = g * a.per, i1 = min(a.n, i0 + a.per);
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += kBlock) {
+        const int64_t r = (int64_t)v * a.n + i;
+        if (a.cnt[r] == 0u) continue;
+        const uint32_t key = a.zkey[r];
+        for_tiles(a, r, V.ntx, t0, t1, [&](int lt) {
+            const uint32_t p = st[lt] + row[lt] + atomicAdd(&cur[lt - t0], 1u);
+            if (p < capacity) out[p] = make_uint2(key, (uint32_t)i);
+        });
+    }
 }
 
 // ------------------------------------------------------------ tile sort
-// One workgroup per tile.  Entries (depth key, index) of the tile's range
-// are sorted by key - (smallest key of the tile), 8 bits per pass, with a
-// stable ranking: each wave ranks its rounds of 64 consecutive entries with
-// ballots (the lanes sharing the digit), the block adds the four waves'
-// histograms, and entries move to digit start + earlier waves + rank.  A
-// range of up to kSortLds entries stays in LDS across the passes; a longer
-// one is processed kSortLds entries at a time from global memory (each chunk
-// ranked in LDS, placed after the earlier chunks' entries of its digit), in
-// the range itself and a second buffer of the same layout.  Finally every
-// run of equal keys is put in index order and the indices are written out.
-constexpr int kSortLds = 4096;                       // entries held in LDS
-constexpr int kSortRounds = kSortLds / kBlock;       // rounds of 64 per wave
-constexpr int kDigits = 256;
+// One workgroup per tile puts its range in (depth key, index) order.  With
+// k = key - (smallest key of the tile) and i = index - (smallest index), the
+// order is that of the integer C = k 2^bi + i (bi = bits of the index span),
+// which is unique per entry.  The entries are bucketed by the top kBinBits
+// bits of C (a counting pass with LDS atomics; the order inside a bucket
+// does not matter), and each entry's final place is its bucket's start plus
+// the number of entries of its bucket with a smaller C.  Buckets hold a few
+// entries on average, so the ranking costs a few comparisons per entry (and
+// stays correct, if quadratic, for any distribution).  Ranges of up to
+// kSortLds entries are bucketed in LDS, longer ones in the same range of a
+// second global buffer.
+constexpr int kSortLds = 2048;     // entries bucketed in LDS
+constexpr int kBinBits = 11;
+constexpr int kBins = 1 << kBinBits;
 
 struct SortLds {
-    uint2 a[kSortLds];        // (relative key, index)
-    uint2 b[kSortLds];
-    uint32_t wh[kWaves][kDigits];  // per-wave digit counts, then offsets
-    uint32_t dstart[kDigits];      // digit start inside the chunk
-    uint32_t dcount[kDigits];      // entries of each digit in the chunk
-    uint32_t run[kDigits];         // global path: next place of each digit in the range
+    uint2 e[kSortLds];          // (relative key, index) in bucket order
+    uint32_t start[kBins];      // bucket starts
+    uint32_t cur[kBins];        // counts, then cursors
     uint32_t wl[kWaves];
-    uint32_t red[2 * kWaves];
+    uint32_t red[4 * kWaves];
 };
-
-// Stable ranking of the cnt (<= kSortLds) entries of src by the digit
-// (key >> shift) & 255: put(entry, digit, place) receives every entry with
-// its place in the chunk's digit-sorted order.  Leaves the chunk's digit
-// counts in dcount and their exclusive scan in dstart.
-template <class Put>
-__device__ __forceinline__ void rank_chunk(SortLds &S, const uint2 *src, int cnt, int shift, Put put)
-{
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    for (int d = threadIdx.x; d < kWaves * kDigits; d += kBlock) (&S.wh[0][0])[d] = 0u;
-    __syncthreads();
-    // wave w takes the consecutive entries [w q, (w + 1) q), q a multiple of 64
-    const int q = ((cnt + kWaves * kWave - 1) / (kWaves * kWave)) * kWave;
-    const int wb = w * q;
-    const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
-    uint32_t rank[kSortRounds];
-    uint2 e[kSortRounds];
-#pragma unroll
-    for (int rr = 0; rr < kSortRounds; ++rr) {
-        const int j = wb + rr * kWave + lane;
-        const bool ok = rr * kWave < q && j < cnt;
-        e[rr] = ok ? src[j] : make_uint2(0u, 0u);
-        rank[rr] = 0u;
-        if (rr * kWave >= q) continue;  // uniform over the wave
-        const uint32_t dg = (e[rr].x >> shift) & 255u;
-        uint64_t peers = __ballot(ok);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (dg >> b) & 1u;
-            const uint64_t bal = __ballot(bit);
-            peers &= bit ? bal : ~bal;
-        }
-        const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
-        uint32_t prev = 0;
-        if (ok) prev = S.wh[w][dg];
-        __builtin_amdgcn_wave_barrier();
-        if (ok && below == 0) S.wh[w][dg] = prev + (uint32_t)__popcll(peers);
-        __builtin_amdgcn_wave_barrier();
-        rank[rr] = prev + below;
-    }
-    __syncthreads();
-    {
-        // thread d owns digit d: offsets of the waves, then the digit starts
-        const int d = threadIdx.x;
-        const uint32_t c0 = S.wh[0][d], c1 = S.wh[1][d], c2 = S.wh[2][d], c3 = S.wh[3][d];
-        S.wh[0][d] = 0u;
-        S.wh[1][d] = c0;
-        S.wh[2][d] = c0 + c1;
-        S.wh[3][d] = c0 + c1 + c2;
-        uint32_t tot;
-        S.dstart[d] = block_scan(c0 + c1 + c2 + c3, S.wl, tot);
-        S.dcount[d] = c0 + c1 + c2 + c3;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int rr = 0; rr < kSortRounds; ++rr) {
-        const int j = wb + rr * kWave + lane;
-        if (rr * kWave < q && j < cnt) {
-            const uint32_t dg = (e[rr].x >> shift) & 255u;
-            put(e[rr], dg, S.dstart[dg] + S.wh[w][dg] + rank[rr]);
-        }
-    }
-}
 
 __device__ __forceinline__ int bit_length(uint32_t x) { return x ? 32 - __clz((int)x) : 0; }
 
-__global__ __launch_bounds__(kBlock) void tile_sort_kernel(const uint2 *ranges, int n_tiles, uint2 *ent,
+__global__ __launch_bounds__(kBlock) void tile_sort_kernel(const uint2 *ranges, int n_tiles, const uint2 *ent,
                                                            uint2 *tmp, uint32_t *tval)
 {
     __shared__ SortLds S;
@@ -318,105 +367,88 @@ __global__ __launch_bounds__(kBlock) void tile_sort_kernel(const uint2 *ranges, 
     const uint2 rg = ranges[tile];
     const int len = (int)(rg.y - rg.x);
     if (len <= 0) return;
-    uint2 *g = ent + rg.x;
-    uint2 *g2 = tmp + rg.x;
+    const uint2 *g = ent + rg.x;
     const int tid = threadIdx.x;
     if (len == 1) {
         if (tid == 0) tval[rg.x] = g[0].y;
         return;
     }
-    // smallest and largest key of the tile
-    uint32_t kmin = 0xFFFFFFFFu, kmax = 0u;
+    // key and index spans of the tile
+    uint32_t kmin = 0xFFFFFFFFu, kmax = 0u, imin = 0xFFFFFFFFu, imax = 0u;
     for (int j = tid; j < len; j += kBlock) {
-        const uint32_t k = g[j].x;
-        kmin = min(kmin, k);
-        kmax = max(kmax, k);
+        const uint2 x = g[j];
+        kmin = min(kmin, x.x);
+        kmax = max(kmax, x.x);
+        imin = min(imin, x.y);
+        imax = max(imax, x.y);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, o, kWave));
         kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, o, kWave));
+        imin = min(imin, (uint32_t)__shfl_xor((int)imin, o, kWave));
+        imax = max(imax, (uint32_t)__shfl_xor((int)imax, o, kWave));
     }
     const int lane = tid & (kWave - 1), w = tid / kWave;
     if (lane == 0) {
         S.red[w] = kmin;
         S.red[kWaves + w] = kmax;
+        S.red[2 * kWaves + w] = imin;
+        S.red[3 * kWaves + w] = imax;
+    }
+    for (int b = tid; b < kBins; b += kBlock) S.cur[b] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) {
+        kmin = min(kmin, S.red[q]);
+        kmax = max(kmax, S.red[kWaves + q]);
+        imin = min(imin, S.red[2 * kWaves + q]);
+        imax = max(imax, S.red[3 * kWaves + q]);
+    }
+    const int bi = bit_length(imax - imin);
+    const int total_bits = bit_length(kmax - kmin) + bi;
+    const int sh = total_bits > kBinBits ? total_bits - kBinBits : 0;
+    auto code = [&](uint2 x) -> uint64_t {
+        return ((uint64_t)(x.x - kmin) << bi) | (uint64_t)(x.y - imin);
+    };
+    // bucket counts
+    for (int j = tid; j < len; j += kBlock) atomicAdd(&S.cur[(uint32_t)(code(g[j]) >> sh)], 1u);
+    __syncthreads();
+    // bucket starts: thread t owns buckets t B .. t B + B - 1
+    {
+        constexpr int B = kBins / kBlock;
+        uint32_t c[B], sum = 0;
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            c[q] = S.cur[tid * B + q];
+            sum += c[q];
+        }
+        uint32_t tot;
+        uint32_t pre = block_scan(sum, S.wl, tot);
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            S.start[tid * B + q] = pre;
+            S.cur[tid * B + q] = pre;
+            pre += c[q];
+        }
     }
     __syncthreads();
-    kmin = min(min(S.red[0], S.red[1]), min(S.red[2], S.red[3]));
-    kmax = max(max(S.red[4], S.red[5]), max(S.red[6], S.red[7]));
-    const int passes = (bit_length(kmax - kmin) + 7) / 8;
-    __syncthreads();
-
-    uint2 *out;  // LDS or global buffer holding the key-sorted range
-    if (len <= kSortLds) {
-        // the whole range in LDS, keys relative to the minimum
-        for (int j = tid; j < len; j += kBlock) {
-            const uint2 x = g[j];
-            S.a[j] = make_uint2(x.x - kmin, x.y);
-        }
-        __syncthreads();
-        uint2 *src = S.a, *dst = S.b;
-        for (int p = 0; p < passes; ++p) {
-            rank_chunk(S, src, len, 8 * p, [&](uint2 x, uint32_t, uint32_t pos) { dst[pos] = x; });
-            __syncthreads();
-            uint2 *t = src;
-            src = dst;
-            dst = t;
-        }
-        out = src;
-    } else {
-        // chunks of kSortLds from global memory, ping-pong between the range
-        // and the same range of tmp
-        for (int j = tid; j < len; j += kBlock) {
-            const uint2 x = g[j];
-            g[j] = make_uint2(x.x - kmin, x.y);
-        }
-        __syncthreads();
-        uint2 *src = g, *dst = g2;
-        for (int p = 0; p < passes; ++p) {
-            const int shift = 8 * p;
-            // digit totals of the whole range, then their starts
-            S.run[tid] = 0u;
-            __syncthreads();
-            for (int j = tid; j < len; j += kBlock) atomicAdd(&S.run[(src[j].x >> shift) & 255u], 1u);
-            __syncthreads();
-            {
-                uint32_t tot;
-                const uint32_t c = S.run[tid];
-                __syncthreads();
-                const uint32_t st = block_scan(c, S.wl, tot);
-                S.run[tid] = st;  // running start of digit tid in the range
-            }
-            __syncthreads();
-            for (int c0 = 0; c0 < len; c0 += kSortLds) {
-                const int cnt = min(kSortLds, len - c0);
-                for (int j = tid; j < cnt; j += kBlock) S.a[j] = src[c0 + j];
-                __syncthreads();
-                rank_chunk(S, S.a, cnt, shift, [&](uint2 x, uint32_t dg, uint32_t pos) {
-                    dst[S.run[dg] + (pos - S.dstart[dg])] = x;
-                });
-                __syncthreads();
-                S.run[tid] += S.dcount[tid];
-                __syncthreads();
-            }
-            uint2 *t = src;
-            src = dst;
-            dst = t;
-        }
-        out = src;
-    }
-    __syncthreads();
-    // runs of equal keys in index order: entry j of a run [s, e) goes to
-    // s + (entries of the run with a smaller index)
+    // bucketing (in LDS, or in the range's place in tmp for long ranges)
+    uint2 *buf = len <= kSortLds ? S.e : tmp + rg.x;
     for (int j = tid; j < len; j += kBlock) {
-        const uint2 x = out[j];
-        int s = j, e = j + 1;
-        while (s > 0 && out[s - 1].x == x.x) --s;
-        while (e < len && out[e].x == x.x) ++e;
-        int r = s;
-        if (e - s > 1)
-            for (int m = s; m < e; ++m) r += out[m].y < x.y ? 1 : 0;
+        const uint2 x = g[j];
+        const uint32_t b = (uint32_t)(code(x) >> sh);
+        buf[atomicAdd(&S.cur[b], 1u)] = x;
+    }
+    __syncthreads();
+    // rank inside the bucket (after the bucketing the cursor is the bucket's end)
+    for (int p = tid; p < len; p += kBlock) {
+        const uint2 x = buf[p];
+        const uint64_t cx = code(x);
+        const uint32_t b = (uint32_t)(cx >> sh);
+        const uint32_t s0 = S.start[b], e0 = S.cur[b];
+        uint32_t r = s0;
+        for (uint32_t q = s0; q < e0; ++q) r += code(buf[q]) < cx ? 1u : 0u;
         tval[rg.x + r] = x.y;
     }
 }
@@ -441,18 +473,52 @@ hipError_t launch_tile_scan(const uint32_t *tile_cnt, int n_tiles, uint2 *ranges
     return hipGetLastError();
 }
 
-hipError_t launch_bin_scatter(int64_t VN, int n, const uint32_t *cnt, const uint2 *rect, const uint32_t *zkey,
-                              const ViewDev *views, uint32_t *cursor, uint32_t capacity, uint2 *out,
-                              uint32_t *tile_cnt, int n_tiles, hipStream_t s)
+// Gaussians per group: at least 2048, and few enough groups that the count
+// matrix stays within kMatWords words.
+constexpr int64_t kMatWords = (int64_t)8 << 20;
+int bin_per_group(int64_t n, int64_t n_tiles)
 {
-    const int64_t nb = std::max<int64_t>((VN + kBlock - 1) / kBlock, (n_tiles + kBlock - 1) / kBlock);
-    if (nb <= 0) return hipSuccess;
-    bin_scatter_kernel<<<(unsigned)nb, kBlock, 0, s>>>(VN, n, cnt, rect, zkey, views, cursor, capacity, out,
-                                                       tile_cnt, n_tiles);
+    int64_t per = 2048;
+    while (per < n && ((n + per - 1) / per) * std::max<int64_t>(n_tiles, 1) > kMatWords) per *= 2;
+    return (int)per;
+}
+
+size_t bin_matrix_words(int64_t n, int64_t n_tiles)
+{
+    const int64_t per = bin_per_group(n, n_tiles);
+    return (size_t)std::max<int64_t>(1, ((n + per - 1) / per) * std::max<int64_t>(n_tiles, 1));
+}
+
+hipError_t launch_bin_count(int n, int V, const uint32_t *cnt, const uint2 *rect, const ViewDev *views, int n_tiles,
+                            int max_view_tiles, uint32_t *mat, uint32_t *tile_cnt, hipStream_t s)
+{
+    if (n <= 0 || V <= 0 || n_tiles <= 0) return hipSuccess;
+    if (V > 65535 || max_view_tiles <= 0) return hipErrorInvalidValue;
+    const int per = bin_per_group(n, n_tiles);
+    BinArgs a{n, V, (n + per - 1) / per, per, cnt, rect, nullptr, views, mat};
+    const int wins = (max_view_tiles + kWin - 1) / kWin;
+    const size_t lds = sizeof(uint32_t) * std::min(max_view_tiles, kWin);
+    bin_count_kernel<<<dim3(a.groups, V, wins), kBlock, lds, s>>>(a);
+    bin_colscan_kernel<<<(n_tiles + kWave - 1) / kWave, kWave * kColParts, 0, s>>>(a, n_tiles, tile_cnt);
     return hipGetLastError();
 }
 
-hipError_t launch_tile_sort(const uint2 *ranges, int n_tiles, uint2 *ent, uint2 *tmp, uint32_t *tval, hipStream_t s)
+hipError_t launch_bin_scatter(int n, int V, const uint32_t *cnt, const uint2 *rect, const uint32_t *zkey,
+                              const ViewDev *views, int n_tiles, int max_view_tiles, const uint32_t *mat,
+                              const uint32_t *start, uint32_t capacity, uint2 *out, hipStream_t s)
+{
+    if (n <= 0 || V <= 0 || n_tiles <= 0) return hipSuccess;
+    if (V > 65535 || max_view_tiles <= 0) return hipErrorInvalidValue;
+    const int per = bin_per_group(n, n_tiles);
+    BinArgs a{n, V, (n + per - 1) / per, per, cnt, rect, zkey, views, const_cast<uint32_t *>(mat)};
+    const int wins = (max_view_tiles + kWin - 1) / kWin;
+    const size_t lds = sizeof(uint32_t) * std::min(max_view_tiles, kWin);
+    bin_scatter_kernel<<<dim3(a.groups, V, wins), kBlock, lds, s>>>(a, start, capacity, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_sort(const uint2 *ranges, int n_tiles, const uint2 *ent, uint2 *tmp, uint32_t *tval,
+                            hipStream_t s)
 {
     if (n_tiles <= 0) return hipSuccess;
     tile_sort_kernel<<<n_tiles, kBlock, 0, s>>>(ranges, n_tiles, ent, tmp, tval);

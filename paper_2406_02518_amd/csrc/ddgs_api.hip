@@ -74,7 +74,7 @@ struct ddgs_ctx {
     // derived view table for the current options
     std::vector<ViewDev> vdev_h;
     std::vector<int32_t> loss_tile_base_h;
-    int n_tiles = 0, loss_tiles = 0;
+    int n_tiles = 0, loss_tiles = 0, max_view_tiles = 0;
     int64_t total_pix = 0, max_view_pix = 0;
     bool views_dirty = true;
 
@@ -292,6 +292,7 @@ ddgs_status prepare_views(ddgs_ctx *c)
     c->vdev_h.assign(V, ViewDev{});
     c->loss_tile_base_h.assign(V + 1, 0);
     int64_t tiles = 0, pix = 0, ltiles = 0, maxp = 0;
+    c->max_view_tiles = 0;
     for (int v = 0; v < V; ++v) {
         const ddgs_view &h = c->views_h[v];
         ViewDev &d = c->vdev_h[v];
@@ -314,6 +315,7 @@ ddgs_status prepare_views(ddgs_ctx *c)
         d.tile_base = (int32_t)tiles;
         d.pix_base = pix;
         tiles += (int64_t)d.ntx * d.nty;
+        c->max_view_tiles = std::max(c->max_view_tiles, d.ntx * d.nty);
         pix += (int64_t)h.W * h.H;
         maxp = std::max<int64_t>(maxp, (int64_t)h.W * h.H);
         c->loss_tile_base_h[v] = (int32_t)ltiles;
@@ -377,15 +379,8 @@ ddgs_status ensure_static(ddgs_ctx *c)
     DDGS_TRY(ensure_t(c, "rect", VN, &u2));
     const char *u32s[] = {"zkey", "cnt", "slot_lp"};
     for (const char *nm : u32s) DDGS_TRY(ensure_t(c, nm, VN, &u));
-    {
-        // per-tile entry counts: zero on allocation, then cleared by every
-        // scatter after the scan has read them
-        uint32_t *prev = buf<uint32_t>(c, "tile_cnt");
-        const size_t prev_bytes = c->bufs.count("tile_cnt") ? c->bufs["tile_cnt"].bytes : 0;
-        DDGS_TRY(ensure_t(c, "tile_cnt", std::max(1, c->n_tiles), &u));
-        if (u && u != prev) HIP_TRY(c, launch_fill_u32(u, 0u, (int64_t)(c->bufs["tile_cnt"].bytes / 4), c->stream));
-        (void)prev_bytes;
-    }
+    DDGS_TRY(ensure_t(c, "tile_cnt", std::max(1, c->n_tiles), &u));
+    DDGS_TRY(ensure_t(c, "bin_mat", bin_matrix_words(n, c->n_tiles), &u));
     DDGS_TRY(ensure_t(c, "cursor", std::max(1, c->n_tiles), &u));
     uint64_t *tb;
     DDGS_TRY(ensure_t(c, "tile_bsum", std::max(1, (c->n_tiles + 255) / 256), &tb));
@@ -526,13 +521,15 @@ ddgs_status enqueue_front(ddgs_ctx *c, uint32_t capacity, bool captured)
     const int V = (int)c->views_h.size();
     GaussCache gc{buf<float>(c, "cov"), buf<float>(c, "alpha"), buf<float>(c, "ciso"), buf<float>(c, "hdir")};
     ProjOut po{buf<float4>(c, "rec"),      buf<uint2>(c, "rect"),     buf<uint32_t>(c, "zkey"),
-               buf<uint32_t>(c, "cnt"),    buf<uint32_t>(c, "tile_cnt"), buf<uint32_t>(c, "slot_lp"),
-               buf<uint32_t>(c, "slot_btot")};
+               buf<uint32_t>(c, "cnt"),    buf<uint32_t>(c, "slot_lp"), buf<uint32_t>(c, "slot_btot")};
     const RenderOpts ro = render_opts(c->opt);
     stage_begin(c, DDGS_T_PROJECT);
     HIP_TRY(c, launch_prep_project(m, gc, buf<ViewDev>(c, "views"), V, ro, po, s));
     stage_end(c, DDGS_T_PROJECT);
     stage_begin(c, DDGS_T_SORT);
+    HIP_TRY(c, launch_bin_count(m.n, V, buf<uint32_t>(c, "cnt"), buf<uint2>(c, "rect"), buf<ViewDev>(c, "views"),
+                                c->n_tiles, c->max_view_tiles, buf<uint32_t>(c, "bin_mat"), buf<uint32_t>(c, "tile_cnt"),
+                                s));
     HIP_TRY(c, launch_tile_scan(buf<uint32_t>(c, "tile_cnt"), c->n_tiles, buf<uint2>(c, "ranges"),
                                 buf<uint32_t>(c, "cursor"), capacity, total_ptr(c), mdev_ptr(c), flags_ptr(c),
                                 captured ? skipped_ptr(c) : nullptr, captured ? need_ptr(c) : nullptr,
@@ -550,9 +547,9 @@ ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, float *images)
     const int n = (int)c->model.n;
     const int64_t VN = (int64_t)n * V;
     uint2 *ent = buf<uint2>(c, "bin_ent");
-    HIP_TRY(c, launch_bin_scatter(VN, n, buf<uint32_t>(c, "cnt"), buf<uint2>(c, "rect"), buf<uint32_t>(c, "zkey"),
-                                  buf<ViewDev>(c, "views"), buf<uint32_t>(c, "cursor"), (uint32_t)cap, ent,
-                                  buf<uint32_t>(c, "tile_cnt"), c->n_tiles, s));
+    HIP_TRY(c, launch_bin_scatter(n, V, buf<uint32_t>(c, "cnt"), buf<uint2>(c, "rect"), buf<uint32_t>(c, "zkey"),
+                                  buf<ViewDev>(c, "views"), c->n_tiles, c->max_view_tiles, buf<uint32_t>(c, "bin_mat"),
+                                  buf<uint32_t>(c, "cursor"), (uint32_t)cap, ent, s));
     if (c->keep_unsorted)
         HIP_TRY(c, launch_copy_u32((uint32_t *)buf<uint2>(c, "ubin"), (const uint32_t *)ent, nullptr, 2 * cap, s));
     HIP_TRY(c, launch_tile_sort(buf<uint2>(c, "ranges"), c->n_tiles, ent, buf<uint2>(c, "bin_tmp"),
@@ -1333,11 +1330,7 @@ ddgs_status ddgs_render(ddgs_ctx *c, float *images)
         if (total >= 0xFFFFFFFFull) st = fail(c, DDGS_ERR_CAPACITY, "more than 2^32-1 tile entries");
         c->M = (int64_t)total;
         if (st == DDGS_OK && c->M > c->entry_cap) st = ensure_entries(c, c->M);
-        if (st != DDGS_OK) {
-            // the scatter that clears the per-tile counts will not run
-            (void)launch_fill_u32(buf<uint32_t>(c, "tile_cnt"), 0u, c->n_tiles, c->stream);
-            return st;
-        }
+        if (st != DDGS_OK) return st;
         DDGS_TRY(enqueue_back(c, c->entry_cap, images));
     } else {
         // no Gaussians: empty lists everywhere

@@ -67,8 +67,6 @@ struct ProjOut {
     uint2 *rect;     // [V*n]: (tx0 | ty0 << 16, tx1 | ty1 << 16), inclusive
     uint32_t *zkey;  // [V*n]: float bits of the source-frame depth, ~0u if culled
     uint32_t *cnt;   // [V*n]: number of tiles touched
-    uint32_t *tile_cnt;  // [n_tiles]: entries per tile, incremented once per
-                         // (pair, tile) (zero on entry; the scatter clears it)
     // gradient-slot numbering in (view, Gaussian) order: each block of
     // kSlotBlock Gaussians of a view stores its exclusive scan of the tile
     // counts (slot_lp, [V*n]) and its total (slot_btot, [V * slot_blocks(n)]),
@@ -284,7 +282,8 @@ hipError_t launch_ranges(const uint32_t *keys, const uint32_t *m_dev, int64_t m_
 
 // bin.hip -- tile binning and the per-tile sort of the tile lists.
 // Exclusive scan of the per-tile entry counts: ranges[t] = [start, end)
-// clamped to capacity, cursor[t] = start; *total (u64) = all entries,
+// clamped to capacity ([0, 0) if empty), cursor[t] = start clamped to
+// capacity; *total (u64) = all entries,
 // *m_out = min(total, capacity), flags bit 0 set when total > capacity
 // (captured steps also pass skipped / need: the count of replays whose
 // optimiser updates are skipped -- every replay from the first overflow on,
@@ -297,16 +296,25 @@ hipError_t launch_tile_scan(const uint32_t *tile_cnt, int n_tiles, uint2 *ranges
                             uint32_t capacity, uint64_t *total, uint32_t *m_out, uint32_t *flags,
                             uint32_t *skipped, unsigned long long *need, uint32_t *slot_btot, int64_t slot_nb,
                             uint64_t *bsum, size_t bsum_words, hipStream_t s);
-// Every (pair, tile) entry claims the next place of its tile's range (atomic
-// cursor) and stores (depth key, Gaussian index) there; places at or beyond
-// capacity are dropped.  Clears tile_cnt[0, n_tiles).
-hipError_t launch_bin_scatter(int64_t VN, int n, const uint32_t *cnt, const uint2 *rect, const uint32_t *zkey,
-                              const ViewDev *views, uint32_t *cursor, uint32_t capacity, uint2 *out,
-                              uint32_t *tile_cnt, int n_tiles, hipStream_t s);
+// Per-tile entry counts without global atomics: groups of Gaussians of each
+// view count their entries per tile in LDS into a count matrix mat
+// ([bin_matrix_words] u32), whose columns are then scanned into every
+// group's offset inside its tile; tile_cnt[t] receives the tile's total.
+// max_view_tiles: the largest tile count of one view.
+size_t bin_matrix_words(int64_t n, int64_t n_tiles);
+hipError_t launch_bin_count(int n, int V, const uint32_t *cnt, const uint2 *rect, const ViewDev *views, int n_tiles,
+                            int max_view_tiles, uint32_t *mat, uint32_t *tile_cnt, hipStream_t s);
+// Every (pair, tile) entry goes to start[tile] + its group's offset + a place
+// claimed inside the group, as (depth key, Gaussian index); places at or
+// beyond capacity are dropped.
+hipError_t launch_bin_scatter(int n, int V, const uint32_t *cnt, const uint2 *rect, const uint32_t *zkey,
+                              const ViewDev *views, int n_tiles, int max_view_tiles, const uint32_t *mat,
+                              const uint32_t *start, uint32_t capacity, uint2 *out, hipStream_t s);
 // One workgroup per tile sorts its range of ent by (depth key, index) and
 // writes the indices to tval; tmp (same layout as ent) is scratch for ranges
-// longer than the LDS holds.  ent is overwritten.
-hipError_t launch_tile_sort(const uint2 *ranges, int n_tiles, uint2 *ent, uint2 *tmp, uint32_t *tval, hipStream_t s);
+// longer than the LDS holds.
+hipError_t launch_tile_sort(const uint2 *ranges, int n_tiles, const uint2 *ent, uint2 *tmp, uint32_t *tval,
+                            hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_zero_u64(uint64_t *p, hipStream_t s);
 hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, const uint32_t *n_dev, int64_t n_cap,

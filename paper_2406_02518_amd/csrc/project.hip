@@ -289,9 +289,6 @@ __device__ __forceinline__ void project_one(const ModelDev &m, const ViewDev *vi
                 const int ty0 = (int)fv0 / o.tile_h, ty1 = (int)fv1 / o.tile_h;
                 count = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
                 rc = make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16));
-                // one entry per touched tile, counted per tile for the binning
-                for (int ty = ty0; ty <= ty1; ++ty)
-                    for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&po.tile_cnt[V.tile_base + ty * V.ntx + tx], 1u);
             }
             po.zkey[vi] = g.zbits;
             po.cnt[vi] = count;
