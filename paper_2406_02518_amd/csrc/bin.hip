@@ -226,7 +226,11 @@ __device__ __forceinline__ void for_tiles(const BinArgs &a, int64_t r, int ntx, 
         }
 }
 
-__global__ __launch_bounds__(kBlock) void bin_count_kernel(BinArgs a)
+// (1024 threads per workgroup: the groups are few, so each needs many waves
+// in flight to hide the latency of its reads and LDS atomics)
+constexpr int kBinBlock = 1024;
+
+__global__ __launch_bounds__(kBinBlock) void bin_count_kernel(BinArgs a)
 {
     extern __shared__ uint32_t hist[];
     const int g = blockIdx.x, v = blockIdx.y, w = blockIdx.z;
@@ -234,17 +238,17 @@ __global__ __launch_bounds__(kBlock) void bin_count_kernel(BinArgs a)
     const int Tv = V.ntx * V.nty, t0 = w * kWin;
     if (t0 >= Tv) return;
     const int t1 = min(Tv, t0 + kWin), nt = t1 - t0;
-    for (int j = threadIdx.x; j < nt; j += kBlock) hist[j] = 0u;
+    for (int j = threadIdx.x; j < nt; j += kBinBlock) hist[j] = 0u;
     __syncthreads();
     const int i0 = g * a.per, i1 = min(a.n, i0 + a.per);
-    for (int i = i0 + (int)threadIdx.x; i < i1; i += kBlock) {
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += kBinBlock) {
         const int64_t r = (int64_t)v * a.n + i;
         if (a.cnt[r] == 0u) continue;
         for_tiles(a, r, V.ntx, t0, t1, [&](int lt) { atomicAdd(&hist[lt - t0], 1u); });
     }
     __syncthreads();
     uint32_t *row = a.mat + (size_t)a.groups * V.tile_base + (size_t)g * Tv + t0;
-    for (int j = threadIdx.x; j < nt; j += kBlock) row[j] = hist[j];
+    for (int j = threadIdx.x; j < nt; j += kBinBlock) row[j] = hist[j];
 }
 
 // 64 tiles per workgroup, the groups split among kColParts waves: every wave
@@ -304,11 +308,12 @@ __global__ __launch_bounds__(kWave *kColParts) void bin_colscan_kernel(BinArgs a
     }
 }
 
-// Places: start[tile] (the tile's range start, clamped to the capacity) +
-// the group's offset + an LDS cursor; places at or beyond the capacity are
-// dropped (an overflowed step, which the flags report).
-__global__ __launch_bounds__(kBlock) void bin_scatter_kernel(BinArgs a, const uint32_t *start, uint32_t capacity,
-                                                             uint2 *out)
+// Places: every tile's cursor starts at the tile's range start (clamped to
+// the capacity) + the group's offset, and each entry claims the next place
+// from it (an LDS atomic); places at or beyond the capacity are dropped (an
+// overflowed step, which the flags report).
+__global__ __launch_bounds__(kBinBlock) void bin_scatter_kernel(BinArgs a, const uint32_t *start, uint32_t capacity,
+                                                                uint2 *out)
 {
     extern __shared__ uint32_t cur[];
     const int g = blockIdx.x, v = blockIdx.y, w = blockIdx.z;
@@ -316,17 +321,17 @@ __global__ __launch_bounds__(kBlock) void bin_scatter_kernel(BinArgs a, const ui
     const int Tv = V.ntx * V.nty, t0 = w * kWin;
     if (t0 >= Tv) return;
     const int t1 = min(Tv, t0 + kWin), nt = t1 - t0;
-    for (int j = threadIdx.x; j < nt; j += kBlock) cur[j] = 0u;
+    const uint32_t *row = a.mat + (size_t)a.groups * V.tile_base + (size_t)g * Tv + t0;
+    const uint32_t *st = start + V.tile_base + t0;
+    for (int j = threadIdx.x; j < nt; j += kBinBlock) cur[j] = st[j] + row[j];
     __syncthreads();
-    const uint32_t *row = a.mat + (size_t)a.groups * V.tile_base + (size_t)g * Tv;
-    const uint32_t *st = start + V.tile_base;
     const int i0 = g * a.per, i1 = min(a.n, i0 + a.per);
-    for (int i = i0 + (int)threadIdx.x; i < i1; i += kBlock) {
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += kBinBlock) {
         const int64_t r = (int64_t)v * a.n + i;
         if (a.cnt[r] == 0u) continue;
         const uint32_t key = a.zkey[r];
         for_tiles(a, r, V.ntx, t0, t1, [&](int lt) {
-            const uint32_t p = st[lt] + row[lt] + atomicAdd(&cur[lt - t0], 1u);
+            const uint32_t p = atomicAdd(&cur[lt - t0], 1u);
             if (p < capacity) out[p] = make_uint2(key, (uint32_t)i);
         });
     }
@@ -345,19 +350,21 @@ __global__ __launch_bounds__(kBlock) void bin_scatter_kernel(BinArgs a, const ui
 // kSortLds entries are bucketed in LDS, longer ones in the same range of a
 // second global buffer.
 constexpr int kSortLds = 2048;     // entries bucketed in LDS
+constexpr int kSortRegs = kSortLds / kBlock;  // entries per thread held in registers
 constexpr int kBinBits = 11;
 constexpr int kBins = 1 << kBinBits;
 
 struct SortLds {
-    uint2 e[kSortLds];          // (relative key, index) in bucket order
+    uint2 e[kSortLds];          // (key, index) in bucket order
     uint32_t start[kBins];      // bucket starts
-    uint32_t cur[kBins];        // counts, then cursors
+    uint32_t cur[kBins];        // counts, then cursors (bucket ends at the last step)
     uint32_t wl[kWaves];
     uint32_t red[4 * kWaves];
 };
 
 __device__ __forceinline__ int bit_length(uint32_t x) { return x ? 32 - __clz((int)x) : 0; }
 
+// Entry j of the range for a thread's slot q: j = tid + q * kBlock.
 __global__ __launch_bounds__(kBlock) void tile_sort_kernel(const uint2 *ranges, int n_tiles, const uint2 *ent,
                                                            uint2 *tmp, uint32_t *tval)
 {
@@ -373,14 +380,33 @@ __global__ __launch_bounds__(kBlock) void tile_sort_kernel(const uint2 *ranges, 
         if (tid == 0) tval[rg.x] = g[0].y;
         return;
     }
-    // key and index spans of the tile
+    const bool in_regs = len <= kSortLds;  // uniform over the block
+    // the range (in registers when it fits), and the key and index spans
+    uint2 x[kSortRegs];
     uint32_t kmin = 0xFFFFFFFFu, kmax = 0u, imin = 0xFFFFFFFFu, imax = 0u;
-    for (int j = tid; j < len; j += kBlock) {
-        const uint2 x = g[j];
-        kmin = min(kmin, x.x);
-        kmax = max(kmax, x.x);
-        imin = min(imin, x.y);
-        imax = max(imax, x.y);
+    if (in_regs) {
+#pragma unroll
+        for (int q = 0; q < kSortRegs; ++q) {
+            const int j = tid + q * kBlock;
+            x[q] = j < len ? g[j] : make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
+        }
+#pragma unroll
+        for (int q = 0; q < kSortRegs; ++q) {
+            if (tid + q * kBlock < len) {
+                kmin = min(kmin, x[q].x);
+                kmax = max(kmax, x[q].x);
+                imin = min(imin, x[q].y);
+                imax = max(imax, x[q].y);
+            }
+        }
+    } else {
+        for (int j = tid; j < len; j += kBlock) {
+            const uint2 y = g[j];
+            kmin = min(kmin, y.x);
+            kmax = max(kmax, y.x);
+            imin = min(imin, y.y);
+            imax = max(imax, y.y);
+        }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -408,11 +434,17 @@ __global__ __launch_bounds__(kBlock) void tile_sort_kernel(const uint2 *ranges, 
     const int bi = bit_length(imax - imin);
     const int total_bits = bit_length(kmax - kmin) + bi;
     const int sh = total_bits > kBinBits ? total_bits - kBinBits : 0;
-    auto code = [&](uint2 x) -> uint64_t {
-        return ((uint64_t)(x.x - kmin) << bi) | (uint64_t)(x.y - imin);
+    auto code = [&](uint2 y) -> uint64_t {
+        return ((uint64_t)(y.x - kmin) << bi) | (uint64_t)(y.y - imin);
     };
     // bucket counts
-    for (int j = tid; j < len; j += kBlock) atomicAdd(&S.cur[(uint32_t)(code(g[j]) >> sh)], 1u);
+    if (in_regs) {
+#pragma unroll
+        for (int q = 0; q < kSortRegs; ++q)
+            if (tid + q * kBlock < len) atomicAdd(&S.cur[(uint32_t)(code(x[q]) >> sh)], 1u);
+    } else {
+        for (int j = tid; j < len; j += kBlock) atomicAdd(&S.cur[(uint32_t)(code(g[j]) >> sh)], 1u);
+    }
     __syncthreads();
     // bucket starts: thread t owns buckets t B .. t B + B - 1
     {
@@ -433,23 +465,40 @@ __global__ __launch_bounds__(kBlock) void tile_sort_kernel(const uint2 *ranges, 
         }
     }
     __syncthreads();
-    // bucketing (in LDS, or in the range's place in tmp for long ranges)
-    uint2 *buf = len <= kSortLds ? S.e : tmp + rg.x;
-    for (int j = tid; j < len; j += kBlock) {
-        const uint2 x = g[j];
-        const uint32_t b = (uint32_t)(code(x) >> sh);
-        buf[atomicAdd(&S.cur[b], 1u)] = x;
-    }
-    __syncthreads();
-    // rank inside the bucket (after the bucketing the cursor is the bucket's end)
-    for (int p = tid; p < len; p += kBlock) {
-        const uint2 x = buf[p];
-        const uint64_t cx = code(x);
-        const uint32_t b = (uint32_t)(cx >> sh);
-        const uint32_t s0 = S.start[b], e0 = S.cur[b];
-        uint32_t r = s0;
-        for (uint32_t q = s0; q < e0; ++q) r += code(buf[q]) < cx ? 1u : 0u;
-        tval[rg.x + r] = x.y;
+    if (in_regs) {
+        // bucketing in LDS, then each entry (still in registers) is ranked
+        // against the other entries of its bucket
+#pragma unroll
+        for (int q = 0; q < kSortRegs; ++q)
+            if (tid + q * kBlock < len) S.e[atomicAdd(&S.cur[(uint32_t)(code(x[q]) >> sh)], 1u)] = x[q];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kSortRegs; ++q) {
+            if (tid + q * kBlock >= len) continue;
+            const uint64_t cx = code(x[q]);
+            const uint32_t b = (uint32_t)(cx >> sh);
+            const uint32_t s0 = S.start[b], e0 = S.cur[b];
+            uint32_t r = s0;
+            for (uint32_t p = s0; p < e0; ++p) r += code(S.e[p]) < cx ? 1u : 0u;
+            tval[rg.x + r] = x[q].y;
+        }
+    } else {
+        // long range: bucketed in the range's place in tmp
+        uint2 *buf = tmp + rg.x;
+        for (int j = tid; j < len; j += kBlock) {
+            const uint2 y = g[j];
+            buf[atomicAdd(&S.cur[(uint32_t)(code(y) >> sh)], 1u)] = y;
+        }
+        __syncthreads();
+        for (int p = tid; p < len; p += kBlock) {
+            const uint2 y = buf[p];
+            const uint64_t cy = code(y);
+            const uint32_t b = (uint32_t)(cy >> sh);
+            const uint32_t s0 = S.start[b], e0 = S.cur[b];
+            uint32_t r = s0;
+            for (uint32_t q = s0; q < e0; ++q) r += code(buf[q]) < cy ? 1u : 0u;
+            tval[rg.x + r] = y.y;
+        }
     }
 }
 
@@ -498,7 +547,7 @@ hipError_t launch_bin_count(int n, int V, const uint32_t *cnt, const uint2 *rect
     BinArgs a{n, V, (n + per - 1) / per, per, cnt, rect, nullptr, views, mat};
     const int wins = (max_view_tiles + kWin - 1) / kWin;
     const size_t lds = sizeof(uint32_t) * std::min(max_view_tiles, kWin);
-    bin_count_kernel<<<dim3(a.groups, V, wins), kBlock, lds, s>>>(a);
+    bin_count_kernel<<<dim3(a.groups, V, wins), kBinBlock, lds, s>>>(a);
     bin_colscan_kernel<<<(n_tiles + kWave - 1) / kWave, kWave * kColParts, 0, s>>>(a, n_tiles, tile_cnt);
     return hipGetLastError();
 }
@@ -513,7 +562,7 @@ hipError_t launch_bin_scatter(int n, int V, const uint32_t *cnt, const uint2 *re
     BinArgs a{n, V, (n + per - 1) / per, per, cnt, rect, zkey, views, const_cast<uint32_t *>(mat)};
     const int wins = (max_view_tiles + kWin - 1) / kWin;
     const size_t lds = sizeof(uint32_t) * std::min(max_view_tiles, kWin);
-    bin_scatter_kernel<<<dim3(a.groups, V, wins), kBlock, lds, s>>>(a, start, capacity, out);
+    bin_scatter_kernel<<<dim3(a.groups, V, wins), kBinBlock, lds, s>>>(a, start, capacity, out);
     return hipGetLastError();
 }
 
