@@ -469,6 +469,19 @@ ddgs_status ddgs_debug_keep_unsorted(ddgs_ctx *ctx, int keep);
  * tile lists. */
 ddgs_status ddgs_debug_sort_pairs(ddgs_ctx *ctx, uint32_t *keys, uint32_t *vals, int64_t n, int bits);
 
+/* The radix sort of ddgs_debug_sort_pairs without any allocation, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid it): its temporaries (the ping-pong
+ * halves and the digit counts) live in a static device array of 12 MiB that
+ * each GPU holds for the life of the process, so n is limited to 2^20 pairs
+ * (larger n: DDGS_ERR_INVALID_ARG, nothing enqueued).  Same result as
+ * ddgs_debug_sort_pairs (stable by key bits [0, bits), in place); the work is
+ * enqueued on the context's stream without synchronising.  Every call on one
+ * GPU shares that array, so calls that overlap on a GPU (other streams, other
+ * threads or contexts) race; the array holds the last call's temporaries and
+ * needs no clearing between calls. */
+ddgs_status ddgs_sort_pairs_noalloc(ddgs_ctx *ctx, uint32_t *keys, uint32_t *vals, int64_t n, int bits);
+
 /* Exclusive prefix sum of n u32 values on the device; *total receives the
  * 64-bit sum (host).  Exposes the scan that places the tile entries. */
 ddgs_status ddgs_debug_exclusive_scan(ddgs_ctx *ctx, const uint32_t *in, uint32_t *out, int64_t n,

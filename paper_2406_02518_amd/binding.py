@@ -33,7 +33,7 @@ EXPORTED = (
     "ddgs_debug_pair_counts", "ddgs_enable_timing", "ddgs_stage_times", "ddgs_default_fit_options",
     "ddgs_set_fit_optimizer", "ddgs_set_densify_stats", "ddgs_densify_plan", "ddgs_densify_apply",
     "ddgs_fit_reset_opacity", "ddgs_rads_prepare", "ddgs_rads_sample", "ddgs_step_report", "ddgs_set_allocator",
-    "ddgs_compose_pose")
+    "ddgs_compose_pose", "ddgs_sort_pairs_noalloc")
 
 # allocator callbacks of ddgs_set_allocator: alloc(user, bytes) -> device pointer, free(user, ptr)
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t)
@@ -159,6 +159,7 @@ def lib():
             "ddgs_step_report": ([vp, C.POINTER(i64), C.POINTER(i64)], st),
             "ddgs_set_allocator": ([vp, ALLOC_FN, FREE_FN, vp], st),
             "ddgs_compose_pose": ([C.POINTER(C.c_float), C.POINTER(C.c_double), C.POINTER(C.c_float)], st),
+            "ddgs_sort_pairs_noalloc": ([vp, vp, vp, i64, C.c_int], st),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -377,6 +378,10 @@ def ddgs_debug_copy(ctx, what, dtype, count):
 
 def ddgs_debug_sort_pairs(ctx, keys_ptr, vals_ptr, n, bits):
     _check(lib().ddgs_debug_sort_pairs(ctx, C.c_void_p(keys_ptr), C.c_void_p(vals_ptr), int(n), int(bits)), ctx)
+
+
+def ddgs_sort_pairs_noalloc(ctx, keys_ptr, vals_ptr, n, bits):
+    _check(lib().ddgs_sort_pairs_noalloc(ctx, C.c_void_p(keys_ptr), C.c_void_p(vals_ptr), int(n), int(bits)), ctx)
 
 
 def ddgs_debug_exclusive_scan(ctx, in_ptr, out_ptr, n):

@@ -12,6 +12,7 @@
 #include <fstream>
 #include <limits>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -20,6 +21,12 @@
 #include "internal.h"
 
 using namespace ddgs;
+
+// The static scratch of ddgs_sort_pairs_noalloc (the one entry point that
+// allocates nothing): one copy per GPU, alive until the process ends.
+constexpr int64_t kNoallocSortMax = (int64_t)1 << 20;         // pairs
+constexpr size_t kNoallocScratchBytes = (size_t)12 << 20;    // 12 MiB
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
 
 namespace {
 
@@ -726,6 +733,39 @@ bool is_state_current(const ddgs_ctx *c)
            c->r_opt_gen == c->opt_gen;
 }
 
+// ----------------------------------------------- static scratch (no allocation)
+// ddgs_sort_pairs_noalloc takes its temporaries from this file-scope device
+// array instead of the workspace: every GPU the library runs on holds its own
+// copy until the process ends.  Host code never passes the array's name to
+// a kernel (on the host it is only a stand-in for the symbol); it uses the
+// device address hipGetSymbolAddress returns, looked up once per device (at
+// ddgs_create, or at the entry point's first call on a device) and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Looks up the scratch address of the current device (c->device) once.
+ddgs_status scratch_lookup(ddgs_ctx *c)
+{
+    if (c->device < 0 || c->device >= kMaxDevices) return fail(c, DDGS_ERR_UNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[c->device]) return DDGS_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(c, DDGS_ERR_HIP, std::string("hipGetSymbolAddress of the static scratch: ") + hipGetErrorString(e));
+    g_scratch_ptr[c->device] = p;
+    return DDGS_OK;
+}
+
+ddgs_status scratch_base(ddgs_ctx *c, char **out)
+{
+    DDGS_TRY(scratch_lookup(c));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    *out = (char *)g_scratch_ptr[c->device];
+    return DDGS_OK;
+}
+
 }  // namespace
 
 // ======================================================================= ABI
@@ -791,6 +831,9 @@ ddgs_status ddgs_create(ddgs_ctx **out, int device, void *hip_stream)
         ddgs_destroy(c);
         return DDGS_ERR_HIP;
     }
+    // the static scratch of ddgs_sort_pairs_noalloc: looked up once per device
+    // (a failure is reported by that entry point, which tries again)
+    (void)scratch_lookup(c);
     *out = c;
     return DDGS_OK;
 }
@@ -1741,6 +1784,42 @@ ddgs_status ddgs_debug_sort_pairs(ddgs_ctx *c, uint32_t *keys, uint32_t *vals, i
         HIP_TRY(c, launch_copy_u32(vals, v1, nullptr, n, c->stream));
     }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_sort_pairs_noalloc(ddgs_ctx *c, uint32_t *keys, uint32_t *vals, int64_t n, int bits)
+{
+    if (!c || n < 0 || bits < 1 || bits > 32 || (n > 0 && (!keys || !vals)))
+        return fail(c, DDGS_ERR_INVALID_ARG, "bad sort arguments");
+    if (n > kNoallocSortMax)
+        return fail(c, DDGS_ERR_INVALID_ARG,
+                    "n = " + std::to_string(n) + " exceeds the static scratch limit of " +
+                        std::to_string(kNoallocSortMax) + " pairs of ddgs_sort_pairs_noalloc");
+    if (n == 0) return DDGS_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    char *base = nullptr;
+    DDGS_TRY(scratch_base(c, &base));
+    // carve the ping-pong halves and the radix temporaries for this n
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base + off;
+        off += ws_round(bytes);
+        return p;
+    };
+    uint32_t *k1 = (uint32_t *)take(sizeof(uint32_t) * (size_t)n);
+    uint32_t *v1 = (uint32_t *)take(sizeof(uint32_t) * (size_t)n);
+    const size_t cw = sort_counts_words(n), bw = sort_blocksum_words(n);
+    uint32_t *counts = (uint32_t *)take(sizeof(uint32_t) * cw);
+    uint32_t *tot = (uint32_t *)take(sizeof(uint32_t) * kSortTotWords);
+    uint64_t *bsum = (uint64_t *)take(sizeof(uint64_t) * bw);
+    if (off > kNoallocScratchBytes) return fail(c, DDGS_ERR_INVALID_ARG, "static scratch too small for this sort");
+    const SortWs ws{counts, tot, bsum, cw, bw};
+    bool in_k1 = false;
+    HIP_TRY(c, radix_sort_pairs(keys, vals, k1, v1, n, nullptr, bits, ws, &in_k1, c->stream));
+    if (in_k1) {
+        HIP_TRY(c, launch_copy_u32(keys, k1, nullptr, n, c->stream));
+        HIP_TRY(c, launch_copy_u32(vals, v1, nullptr, n, c->stream));
+    }
     return DDGS_OK;
 }
 
