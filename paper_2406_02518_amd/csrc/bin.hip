@@ -61,6 +61,14 @@ struct ScanArgs {
     unsigned long long *need;
     uint32_t *slot_btot;
     int64_t slot_nb;
+    // work items of `split` entries (split > 0, one-launch scan only): per
+    // tile the item count and first item, the (tile, chunk) list, the item
+    // count (clamped to max_items) and the two work-queue counters cleared
+    uint32_t split;
+    uint32_t *item_cnt, *item_base;
+    uint2 *items;
+    uint32_t max_items;
+    uint32_t *n_items, *counter;
 };
 
 __device__ void slot_block_scan(uint32_t *slot_btot, int64_t slot_nb, uint32_t *wl)
@@ -113,24 +121,63 @@ __global__ __launch_bounds__(kBlock) void tile_scan_self_kernel(ScanArgs a)
 {
     __shared__ uint32_t wl[kWaves];
     __shared__ uint64_t red[kWaves];
+    __shared__ uint32_t ired[kWaves];
     if (blockIdx.x == 0) slot_block_scan(a.slot_btot, a.slot_nb, wl);
     const int base = blockIdx.x * kBlock;
+    const uint32_t sp = a.split;
+    // entries and (with chunks) work items of the tiles before this block's
     uint64_t c = 0;
+    uint32_t ci = 0;
 #pragma unroll 4
-    for (int t = threadIdx.x; t < base; t += kBlock) c += a.tile_cnt[t];
+    for (int t = threadIdx.x; t < base; t += kBlock) {
+        const uint32_t x = a.tile_cnt[t];
+        c += x;
+        if (sp) ci += (x + sp - 1u) / sp;
+    }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
-    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = c;
+    for (int o = 32; o > 0; o >>= 1) {
+        c += __shfl_xor(c, o, kWave);
+        ci += __shfl_xor(ci, o, kWave);
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        red[threadIdx.x / kWave] = c;
+        ired[threadIdx.x / kWave] = ci;
+    }
     __syncthreads();
     uint64_t carry = 0;
+    uint32_t icarry = 0;
 #pragma unroll
-    for (int q = 0; q < kWaves; ++q) carry += red[q];
+    for (int q = 0; q < kWaves; ++q) {
+        carry += red[q];
+        icarry += ired[q];
+    }
     const int t = base + threadIdx.x;
     const uint32_t v = t < a.n_tiles ? a.tile_cnt[t] : 0u;
     uint32_t tot;
     const uint32_t pre = block_scan(v, wl, tot);
     if (t < a.n_tiles) write_range(a, t, carry + pre, v);
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) finish_scan(a, carry + tot);
+    uint32_t itot = 0;
+    if (sp) {
+        // (chunks of the unclamped count: past a clamped range end an item is
+        // empty, and only an overflowed step, whose results are discarded,
+        // clamps)
+        const uint32_t nv = (v + sp - 1u) / sp;
+        const uint32_t ipre = icarry + block_scan(nv, wl, itot);
+        if (t < a.n_tiles) {
+            a.item_cnt[t] = nv;
+            a.item_base[t] = ipre;
+            for (uint32_t k = 0; k < nv && ipre + k < a.max_items; ++k) a.items[ipre + k] = make_uint2((uint32_t)t, k);
+        }
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        finish_scan(a, carry + tot);
+        if (sp) {
+            const uint32_t ni = icarry + itot;
+            *a.n_items = ni > a.max_items ? a.max_items : ni;
+            a.counter[0] = 0u;
+            a.counter[1] = 0u;
+        }
+    }
 }
 
 // More tiles: block sums, one block scanning them, then the blocks' scans.
@@ -350,7 +397,11 @@ __global__ __launch_bounds__(kBinBlock) void bin_scatter_kernel(BinArgs a, const
 // kSortLds entries are bucketed in LDS, longer ones in the same range of a
 // second global buffer.
 constexpr int kSortLds = 2048;     // entries bucketed in LDS
-constexpr int kSortRegs = kSortLds / kBlock;  // entries per thread held in registers
+constexpr int kSortBlock = 512;    // threads per tile (the per-tile phases are latency-bound:
+                                   // 512 measured 0.037 ms at 500k / 8x8 tiles, 256 0.045,
+                                   // 1024 0.053)
+constexpr int kSortWaves = kSortBlock / kWave;
+constexpr int kSortRegs = kSortLds / kSortBlock;  // entries per thread held in registers
 constexpr int kBinBits = 11;
 constexpr int kBins = 1 << kBinBits;
 
@@ -358,14 +409,33 @@ struct SortLds {
     uint2 e[kSortLds];          // (key, index) in bucket order
     uint32_t start[kBins];      // bucket starts
     uint32_t cur[kBins];        // counts, then cursors (bucket ends at the last step)
-    uint32_t wl[kWaves];
-    uint32_t red[4 * kWaves];
+    uint32_t wl[kSortWaves];
+    uint32_t red[4 * kSortWaves];
 };
+
+// exclusive scan over a block of kSortBlock threads; returns the block total
+__device__ __forceinline__ uint32_t sort_block_scan(uint32_t x, uint32_t *lds, uint32_t &total)
+{
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const uint32_t inc = wave_incl_scan(x);
+    if (lane == kWave - 1) lds[w] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    total = 0;
+#pragma unroll
+    for (int q = 0; q < kSortWaves; ++q) {
+        const uint32_t t = lds[q];
+        if (q < w) before += t;
+        total += t;
+    }
+    __syncthreads();
+    return before + inc - x;
+}
 
 __device__ __forceinline__ int bit_length(uint32_t x) { return x ? 32 - __clz((int)x) : 0; }
 
 // Entry j of the range for a thread's slot q: j = tid + q * kBlock.
-__global__ __launch_bounds__(kBlock) void tile_sort_kernel(const uint2 *ranges, int n_tiles, const uint2 *ent,
+__global__ __launch_bounds__(kSortBlock) void tile_sort_kernel(const uint2 *ranges, int n_tiles, const uint2 *ent,
                                                            uint2 *tmp, uint32_t *tval)
 {
     __shared__ SortLds S;
@@ -387,12 +457,12 @@ __global__ __launch_bounds__(kBlock) void tile_sort_kernel(const uint2 *ranges, 
     if (in_regs) {
 #pragma unroll
         for (int q = 0; q < kSortRegs; ++q) {
-            const int j = tid + q * kBlock;
+            const int j = tid + q * kSortBlock;
             x[q] = j < len ? g[j] : make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
         }
 #pragma unroll
         for (int q = 0; q < kSortRegs; ++q) {
-            if (tid + q * kBlock < len) {
+            if (tid + q * kSortBlock < len) {
                 kmin = min(kmin, x[q].x);
                 kmax = max(kmax, x[q].x);
                 imin = min(imin, x[q].y);
@@ -400,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void tile_sort_kernel(const uint2 *ranges, 
             }
         }
     } else {
-        for (int j = tid; j < len; j += kBlock) {
+        for (int j = tid; j < len; j += kSortBlock) {
             const uint2 y = g[j];
             kmin = min(kmin, y.x);
             kmax = max(kmax, y.x);
@@ -418,18 +488,18 @@ __global__ __launch_bounds__(kBlock) void tile_sort_kernel(const uint2 *ranges, 
     const int lane = tid & (kWave - 1), w = tid / kWave;
     if (lane == 0) {
         S.red[w] = kmin;
-        S.red[kWaves + w] = kmax;
-        S.red[2 * kWaves + w] = imin;
-        S.red[3 * kWaves + w] = imax;
+        S.red[kSortWaves + w] = kmax;
+        S.red[2 * kSortWaves + w] = imin;
+        S.red[3 * kSortWaves + w] = imax;
     }
-    for (int b = tid; b < kBins; b += kBlock) S.cur[b] = 0u;
+    for (int b = tid; b < kBins; b += kSortBlock) S.cur[b] = 0u;
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < kWaves; ++q) {
+    for (int q = 0; q < kSortWaves; ++q) {
         kmin = min(kmin, S.red[q]);
-        kmax = max(kmax, S.red[kWaves + q]);
-        imin = min(imin, S.red[2 * kWaves + q]);
-        imax = max(imax, S.red[3 * kWaves + q]);
+        kmax = max(kmax, S.red[kSortWaves + q]);
+        imin = min(imin, S.red[2 * kSortWaves + q]);
+        imax = max(imax, S.red[3 * kSortWaves + q]);
     }
     const int bi = bit_length(imax - imin);
     const int total_bits = bit_length(kmax - kmin) + bi;
@@ -441,14 +511,14 @@ __global__ __launch_bounds__(kBlock) void tile_sort_kernel(const uint2 *ranges, 
     if (in_regs) {
 #pragma unroll
         for (int q = 0; q < kSortRegs; ++q)
-            if (tid + q * kBlock < len) atomicAdd(&S.cur[(uint32_t)(code(x[q]) >> sh)], 1u);
+            if (tid + q * kSortBlock < len) atomicAdd(&S.cur[(uint32_t)(code(x[q]) >> sh)], 1u);
     } else {
-        for (int j = tid; j < len; j += kBlock) atomicAdd(&S.cur[(uint32_t)(code(g[j]) >> sh)], 1u);
+        for (int j = tid; j < len; j += kSortBlock) atomicAdd(&S.cur[(uint32_t)(code(g[j]) >> sh)], 1u);
     }
     __syncthreads();
     // bucket starts: thread t owns buckets t B .. t B + B - 1
     {
-        constexpr int B = kBins / kBlock;
+        constexpr int B = kBins / kSortBlock;
         uint32_t c[B], sum = 0;
 #pragma unroll
         for (int q = 0; q < B; ++q) {
@@ -456,7 +526,7 @@ __global__ __launch_bounds__(kBlock) void tile_sort_kernel(const uint2 *ranges, 
             sum += c[q];
         }
         uint32_t tot;
-        uint32_t pre = block_scan(sum, S.wl, tot);
+        uint32_t pre = sort_block_scan(sum, S.wl, tot);
 #pragma unroll
         for (int q = 0; q < B; ++q) {
             S.start[tid * B + q] = pre;
@@ -470,11 +540,11 @@ __global__ __launch_bounds__(kBlock) void tile_sort_kernel(const uint2 *ranges, 
         // against the other entries of its bucket
 #pragma unroll
         for (int q = 0; q < kSortRegs; ++q)
-            if (tid + q * kBlock < len) S.e[atomicAdd(&S.cur[(uint32_t)(code(x[q]) >> sh)], 1u)] = x[q];
+            if (tid + q * kSortBlock < len) S.e[atomicAdd(&S.cur[(uint32_t)(code(x[q]) >> sh)], 1u)] = x[q];
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < kSortRegs; ++q) {
-            if (tid + q * kBlock >= len) continue;
+            if (tid + q * kSortBlock >= len) continue;
             const uint64_t cx = code(x[q]);
             const uint32_t b = (uint32_t)(cx >> sh);
             const uint32_t s0 = S.start[b], e0 = S.cur[b];
@@ -485,12 +555,12 @@ __global__ __launch_bounds__(kBlock) void tile_sort_kernel(const uint2 *ranges, 
     } else {
         // long range: bucketed in the range's place in tmp
         uint2 *buf = tmp + rg.x;
-        for (int j = tid; j < len; j += kBlock) {
+        for (int j = tid; j < len; j += kSortBlock) {
             const uint2 y = g[j];
             buf[atomicAdd(&S.cur[(uint32_t)(code(y) >> sh)], 1u)] = y;
         }
         __syncthreads();
-        for (int p = tid; p < len; p += kBlock) {
+        for (int p = tid; p < len; p += kSortBlock) {
             const uint2 y = buf[p];
             const uint64_t cy = code(y);
             const uint32_t b = (uint32_t)(cy >> sh);
@@ -504,17 +574,30 @@ __global__ __launch_bounds__(kBlock) void tile_sort_kernel(const uint2 *ranges, 
 
 }  // namespace
 
+bool tile_scan_makes_items(int n_tiles) { return n_tiles <= kTileScanSelfMax; }
+
 hipError_t launch_tile_scan(const uint32_t *tile_cnt, int n_tiles, uint2 *ranges, uint32_t *cursor,
                             uint32_t capacity, uint64_t *total, uint32_t *m_out, uint32_t *flags,
                             uint32_t *skipped, unsigned long long *need, uint32_t *slot_btot, int64_t slot_nb,
-                            uint64_t *bsum, size_t bsum_words, hipStream_t s)
+                            uint64_t *bsum, size_t bsum_words, const TileItems *it, hipStream_t s)
 {
-    ScanArgs a{tile_cnt, n_tiles, ranges, cursor, capacity, total, m_out, flags, skipped, need, slot_btot, slot_nb};
+    ScanArgs a{tile_cnt, n_tiles, ranges, cursor, capacity, total, m_out, flags, skipped, need, slot_btot, slot_nb,
+               0u, nullptr, nullptr, nullptr, 0u, nullptr, nullptr};
     const int nb = (n_tiles + kBlock - 1) / kBlock;
     if (n_tiles <= kTileScanSelfMax) {
+        if (it && it->split > 0) {
+            a.split = (uint32_t)it->split;
+            a.item_cnt = it->cnt;
+            a.item_base = it->base;
+            a.items = it->items;
+            a.max_items = it->max_items;
+            a.n_items = it->n_items;
+            a.counter = it->counter;
+        }
         tile_scan_self_kernel<<<std::max(1, nb), kBlock, 0, s>>>(a);
         return hipGetLastError();
     }
+    if (it) return hipErrorInvalidValue;  // the three-launch scan makes no items
     if (!bsum || (size_t)nb > bsum_words) return hipErrorInvalidValue;
     tile_sum_kernel<<<nb, kBlock, 0, s>>>(tile_cnt, n_tiles, bsum);
     tile_top_kernel<<<1, 1024, 0, s>>>(bsum, nb, a);
@@ -570,7 +653,7 @@ hipError_t launch_tile_sort(const uint2 *ranges, int n_tiles, const uint2 *ent, 
                             hipStream_t s)
 {
     if (n_tiles <= 0) return hipSuccess;
-    tile_sort_kernel<<<n_tiles, kBlock, 0, s>>>(ranges, n_tiles, ent, tmp, tval);
+    tile_sort_kernel<<<n_tiles, kSortBlock, 0, s>>>(ranges, n_tiles, ent, tmp, tval);
     return hipGetLastError();
 }
 

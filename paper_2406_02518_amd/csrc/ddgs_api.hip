@@ -112,6 +112,7 @@ struct ddgs_ctx {
     int64_t step_cap = 0;
     int64_t last_skipped = 0, last_need = 0;  // found by the last ddgs_check
     int max_items = 0;         // work items the raster grids are sized for
+    bool items_folded = false; // the tile scan wrote the work items (captured step)
 
     // pinned staging of the view table uploads
     void *stage_host = nullptr;
@@ -537,11 +538,21 @@ ddgs_status enqueue_front(ddgs_ctx *c, uint32_t capacity, bool captured)
     HIP_TRY(c, launch_bin_count(m.n, V, buf<uint32_t>(c, "cnt"), buf<uint2>(c, "rect"), buf<ViewDev>(c, "views"),
                                 c->n_tiles, c->max_view_tiles, buf<uint32_t>(c, "bin_mat"), buf<uint32_t>(c, "tile_cnt"),
                                 s));
+    // a captured step (its buffers are sized already) has the scan write the
+    // chunked raster's work items too
+    TileItems ti{};
+    const bool fold = captured && effective_split(c) > 0 && tile_scan_makes_items(c->n_tiles);
+    if (fold) {
+        c->max_items = (int)max_items_for(c, capacity);
+        ti = TileItems{effective_split(c), buf<uint32_t>(c, "item_cnt"), buf<uint32_t>(c, "item_base"),
+                       buf<uint2>(c, "items"), (uint32_t)c->max_items, n_items_ptr(c), counter_ptr(c)};
+    }
+    c->items_folded = fold;
     HIP_TRY(c, launch_tile_scan(buf<uint32_t>(c, "tile_cnt"), c->n_tiles, buf<uint2>(c, "ranges"),
                                 buf<uint32_t>(c, "cursor"), capacity, total_ptr(c), mdev_ptr(c), flags_ptr(c),
                                 captured ? skipped_ptr(c) : nullptr, captured ? need_ptr(c) : nullptr,
                                 buf<uint32_t>(c, "slot_btot"), (int64_t)V * slot_blocks(m.n), buf<uint64_t>(c, "tile_bsum"),
-                                c->bufs["tile_bsum"].bytes / sizeof(uint64_t), s));
+                                c->bufs["tile_bsum"].bytes / sizeof(uint64_t), fold ? &ti : nullptr, s));
     return DDGS_OK;
 }
 
@@ -564,7 +575,9 @@ ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, float *images)
     c->queue = nullptr;
     const int split = effective_split(c);
     c->max_items = (int)max_items_for(c, cap);
-    if (split > 0) {
+    if (split > 0 && c->items_folded) {
+        // (written by the tile scan)
+    } else if (split > 0) {
         HIP_TRY(c, launch_items(buf<uint2>(c, "ranges"), c->n_tiles, split, buf<uint32_t>(c, "item_cnt"),
                                 buf<uint32_t>(c, "item_base"), buf<uint2>(c, "items"), (uint32_t)c->max_items,
                                 sort_ws(c), sort_total_ptr(c), n_items_ptr(c), counter_ptr(c), s));

@@ -291,11 +291,22 @@ hipError_t launch_ranges(const uint32_t *keys, const uint32_t *m_dev, int64_t m_
 // call).  Also turns the slot numbering's block totals (slot_btot, slot_nb
 // of them) into the blocks' first slots.  One launch up to kTileScanSelfMax
 // tiles, else three (bsum: [tiles / 256] u64 scratch).
+// With `items` (only where tile_scan_makes_items: the one-launch scan), the
+// same launch also writes the work items of `split` entries per tile (what
+// launch_items writes).
 constexpr int kTileScanSelfMax = 16384;
+struct TileItems {
+    int split;
+    uint32_t *cnt, *base;
+    uint2 *items;
+    uint32_t max_items;
+    uint32_t *n_items, *counter;
+};
+bool tile_scan_makes_items(int n_tiles);
 hipError_t launch_tile_scan(const uint32_t *tile_cnt, int n_tiles, uint2 *ranges, uint32_t *cursor,
                             uint32_t capacity, uint64_t *total, uint32_t *m_out, uint32_t *flags,
                             uint32_t *skipped, unsigned long long *need, uint32_t *slot_btot, int64_t slot_nb,
-                            uint64_t *bsum, size_t bsum_words, hipStream_t s);
+                            uint64_t *bsum, size_t bsum_words, const TileItems *items, hipStream_t s);
 // Per-tile entry counts without global atomics: groups of Gaussians of each
 // view count their entries per tile in LDS into a count matrix mat
 // ([bin_matrix_words] u32), whose columns are then scanned into every
