@@ -193,6 +193,33 @@ __device__ __forceinline__ void wave_transpose_sum64(float (&v)[64])
     }
 }
 
+// Sums 16 per-lane values over the wave at once: afterwards every lane l
+// holds the wave total of v[(l >> 2) & 15].  The transposing butterfly of
+// wave_transpose_sum64 over lane bits 5, 4, 3 and 2 (value index bits 3..0),
+// then plain butterflies over bits 1 and 0, which leave the four lanes of a
+// quad with the same total.
+__device__ __forceinline__ float wave_transpose_sum16(float (&v)[16])
+{
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 8]),
+                                                        false, false);
+        v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 4]),
+                                                        false, false);
+        v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) v[i] = pair_sum_bit3(v[i], v[i + 2]);
+    float x = pair_sum_bit2(v[0], v[1]);
+    x += dpp_move<0xB1>(x);   // quad_perm [1,0,3,2]
+    x += dpp_move<0x4E>(x);   // quad_perm [2,3,0,1]
+    return x;
+}
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
 {
     const int lane = (int)__lane_id();

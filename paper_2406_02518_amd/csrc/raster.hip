@@ -58,6 +58,9 @@ constexpr float kLaneOff = __builtin_huge_valf();
 // min(s, sigma_max) for s = alpha G >= 0 as one v_med3_f32 (median of s,
 // 0 and sigma_max), without the NaN canonicalisation fminf brings.
 __device__ __forceinline__ float clamp_opacity(float s, float smax) { return __builtin_amdgcn_fmed3f(s, 0.0f, smax); }
+// 1 - s for an unclamped s = alpha G, in one rounding (the same in the
+// forward and every backward)
+__device__ __forceinline__ float one_minus_alpha_g(float alpha, float G) { return __fmaf_rn(-alpha, G, 1.0f); }
 
 // Wave-wide OR of a predicate as a lane mask (the compare mask itself).
 __device__ __forceinline__ uint64_t wave_any_mask(bool p) { return __builtin_amdgcn_ballot_w64(p); }
@@ -108,12 +111,25 @@ __device__ __forceinline__ Item resolve_item(const RasterArgs &a, int it)
                 (uint32_t)__builtin_amdgcn_readfirstlane((int)e), __builtin_amdgcn_readfirstlane(chunk)};
 }
 
-// Next work item of this workgroup: its block index once, or (persistent
-// mode) items taken from a shared counter until none are left.
+// Item of block b when blocks map to items directly.  Workgroups are dealt
+// to the eight XCDs in turn (block b to XCD b mod 8), and each XCD has its
+// own L2: XCD x gets the x-th contiguous eighth of the n items, so that
+// neighbouring tiles, which share most of their Gaussians, read those
+// records through the same L2.  The grid is a multiple of 8 and at least n.
+__device__ __forceinline__ int xcd_item(int b, int n)
+{
+    const int per = (n + 7) >> 3;
+    const int k = b >> 3;
+    return k < per ? (b & 7) * per + k : 0x7FFFFFFF;
+}
+
+// Next work item of this workgroup: the item of its block once, or
+// (persistent mode) items taken from a shared counter until none are left.
 __device__ __forceinline__ int next_item(const RasterArgs &a, int &iter, int *sh)
 {
     if (!a.queue_counter) {
-        const int t = iter == 0 ? (int)blockIdx.x : 0x7FFFFFFF;
+        const int n = a.split ? (int)*a.n_items : a.n_tiles;
+        const int t = iter == 0 ? xcd_item((int)blockIdx.x, n) : 0x7FFFFFFF;
         ++iter;
         return t;
     }
@@ -160,8 +176,12 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
         // compare and its wave ballot costs no vector instruction
         float k2e = inside ? k2s : kLaneOff;
         // one entry: when any lane hits, the whole wave runs it without
-        // branches; lanes that miss keep their state
-        auto entry = [&](const float4 r0, const float4 r1, uint32_t pos) {
+        // branches; lanes that miss keep their state.  CLAMP: some entry of
+        // the batch has alpha > sigma_max / 2.  Otherwise alpha G stays below
+        // sigma_max with a factor-two margin (G <= 1, up to the rounding of
+        // its exponent) and the clamp min(alpha G, sigma_max) is the identity
+        auto entry = [&](const float4 r0, const float4 r1, uint32_t pos, auto clamp_c) {
+            constexpr bool CLAMP = decltype(clamp_c)::value;
             const float dx = __fsub_rn(fpx, r0.x), dy = __fsub_rn(fpy, r0.y);
             const float ex = falloff_exponent(dx, dy, r0.z, r0.w, r1.x);
             bool hit = ex >= k2e;
@@ -169,8 +189,13 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
                 // lanes that miss run the same arithmetic with G = 0: s = 0,
                 // 1 - s = 1, so C and T stay exactly as they are
                 float G = hit ? __builtin_amdgcn_exp2f(ex) : 0.0f;
-                float s = clamp_opacity(__fmul_rn(r1.y, G), smax);
-                float om = __fsub_rn(1.0f, s);
+                float s = __fmul_rn(r1.y, G), om;
+                if constexpr (CLAMP) {
+                    s = clamp_opacity(s, smax);
+                    om = __fsub_rn(1.0f, s);
+                } else {
+                    om = one_minus_alpha_g(r1.y, G);
+                }
                 if constexpr (!SPLIT) {
                     // early termination (t_min > 0 runs unsplit): the lane
                     // stops before this entry
@@ -189,22 +214,9 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
                 if constexpr (COUNT) n_contrib += hit ? 1u : 0u;
             }
         };
-        for (uint32_t b0 = I.b; b0 < I.e; b0 += NT) {
-            __syncthreads();
-            const uint32_t j = b0 + tid;
-            if (j < I.e) {
-                const uint32_t gid = min(a.tval[j], (uint32_t)a.n - 1u);
-                const size_t idx = vbase + gid;
-                float4 r0 = a.rec[4 * idx], r1 = a.rec[4 * idx + 1];
-                scale_conic(r0, r1);
-                s0[tid] = r0;
-                s1[tid] = r1;
-            }
-            __syncthreads();
-            const int cnt = (int)min((uint32_t)NT, I.e - b0);
-            if (COUNT && k2e < 0.0f) n_eval += (uint32_t)cnt;
-            // four entries' records read together (one LDS address, immediate
-            // offsets), then run in order
+        // the batch's entries in order, four records read together (one LDS
+        // address, immediate offsets)
+        auto run_batch = [&](uint32_t b0, int cnt, auto clamp_c) {
             int q = 0;
             for (; q + 4 <= cnt; q += 4) {
                 float4 r0[4], r1[4];
@@ -214,9 +226,28 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
                     r1[u] = s1[q + u];
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) entry(r0[u], r1[u], b0 + (uint32_t)(q + u));
+                for (int u = 0; u < 4; ++u) entry(r0[u], r1[u], b0 + (uint32_t)(q + u), clamp_c);
             }
-            for (; q < cnt; ++q) entry(s0[q], s1[q], b0 + (uint32_t)q);
+            for (; q < cnt; ++q) entry(s0[q], s1[q], b0 + (uint32_t)q, clamp_c);
+        };
+        for (uint32_t b0 = I.b; b0 < I.e; b0 += NT) {
+            __syncthreads();
+            const uint32_t j = b0 + tid;
+            bool over = false;  // an opacity above sigma_max / 2 in this batch
+            if (j < I.e) {
+                const uint32_t gid = min(a.tval[j], (uint32_t)a.n - 1u);
+                const size_t idx = vbase + gid;
+                float4 r0 = a.rec[4 * idx], r1 = a.rec[4 * idx + 1];
+                over = r1.y > 0.5f * smax;
+                scale_conic(r0, r1);
+                s0[tid] = r0;
+                s1[tid] = r1;
+            }
+            const bool clamp = __syncthreads_or(over);
+            const int cnt = (int)min((uint32_t)NT, I.e - b0);
+            if (COUNT && k2e < 0.0f) n_eval += (uint32_t)cnt;
+            if (clamp) run_batch(b0, cnt, std::true_type{});
+            else run_batch(b0, cnt, std::false_type{});
             if (tmin > 0.0f && __syncthreads_and(k2e == kLaneOff)) break;
         }
         if constexpr (COUNT) {
@@ -347,10 +378,112 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
         // the cut-off test with the lane's state folded in (kLaneOff once
         // stopped or outside the image): a hit is one compare, its ballot is free
         float k2e = inside ? k2s : kLaneOff;
+        // the staged batch's entries in groups of EPG, CLAMP as in the forward
+        // (without it every alpha of the batch is at most sigma_max / 2: s =
+        // alpha G and no step is clamped)
+        auto run_groups = [&](uint32_t b0, int cnt, auto clamp_c) {
+            constexpr bool CLAMP = decltype(clamp_c)::value;
+            // groups of EPG = 9 entries: their 7 gradient terms fill 63 of
+            // the 64 values of one transposing wave sum (the last is a
+            // zero pad); lane l ends with term l % 7 of entry l / 7
+            for (int q0 = 0; q0 < cnt; q0 += EPG) {
+                float gb[64];
+                bool any = false;
+                // the group's first entry index, held in one vector
+                // register (an empty asm makes it opaque) so that the
+                // entries' LDS reads use it with immediate offsets instead
+                // of rebuilding an address for each entry
+                int qv = q0;
+                asm volatile("" : "+v"(qv));
+#pragma unroll
+                for (int qq = 0; qq < EPG; ++qq) {
+                    float gv[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                    const int q = q0 + qq;
+                    if (q < cnt) {
+                        const float4 r0 = s0[qv + qq];
+                        const float4 r1 = s1[qv + qq];
+                        const float dx = __fsub_rn(fpx, r0.x), dy = __fsub_rn(fpy, r0.y);
+                        const float ex = falloff_exponent(dx, dy, r0.z, r0.w, r1.x);
+                        bool hit = ex >= k2e;
+                        if constexpr (!SPLIT) hit = hit && (b0 + (uint32_t)q) < lastp;
+                        // when any lane hits, the whole wave runs the entry:
+                        // computed without branches, lanes that miss keep
+                        // their state and contribute zeros
+                        if (wave_any_mask(hit) != 0ull) {
+                            // lanes that miss run the same arithmetic with
+                            // G = 0: s = 0, 1 - s = 1, so the running colour
+                            // and T stay exactly as they are and every term
+                            // below is zero
+                            float G = hit ? __builtin_amdgcn_exp2f(ex) : 0.0f;
+                            float sraw = __fmul_rn(r1.y, G);
+                            float s = sraw, om;
+                            if constexpr (CLAMP) {
+                                s = clamp_opacity(sraw, smax);
+                                om = __fsub_rn(1.0f, s);
+                            } else {
+                                om = one_minus_alpha_g(r1.y, G);
+                            }
+                            if constexpr (!SPLIT) {
+                                // t_min > 0 runs unsplit
+                                if (tmin > 0.0f) {
+                                    const bool stop = hit & (__fmul_rn(T, om) < tmin);
+                                    k2e = stop ? kLaneOff : k2e;
+                                    hit = hit & !stop;
+                                    G = stop ? 0.0f : G;
+                                    sraw = stop ? 0.0f : sraw;
+                                    s = stop ? 0.0f : s;
+                                    om = stop ? 1.0f : om;
+                                }
+                            }
+                            // dL/ds = g (c T - S / (1 - s)) with S the tail
+                            // after this entry: g S is updated by -g c s T
+                            const float c = r1.z;
+                            const float sT = __fmul_rn(s, T);
+                            const float gc = g * c;
+                            Sg = __fmaf_rn(-gc, sT, Sg);
+                            const float ds = __fmaf_rn(gc, T, -(Sg * __builtin_amdgcn_rcpf(om)));
+                            // moments of dL/ds G about the mean; the conic and
+                            // alpha factors are applied once per (view,
+                            // Gaussian) in the projection backward
+                            float gds = ds * G;
+                            if constexpr (CLAMP) gds = (sraw > smax) ? 0.0f : gds;
+                            const float m1x = gds * dx, m1y = gds * dy;
+                            gv[0] = m1x;
+                            gv[1] = m1y;
+                            gv[2] = m1x * dx;
+                            gv[3] = m1x * dy;
+                            gv[4] = m1y * dy;
+                            gv[5] = gds;
+                            gv[6] = g * sT;
+                            T = __fmul_rn(T, om);
+                            any = true;
+                        }
+                    }
+#pragma unroll
+                    for (int c = 0; c < kTerms; ++c) gb[qq * kTerms + c] = gv[c];
+                }
+                gb[63] = 0.0f;
+                float res = 0.0f;
+                if (wave_any_mask(any) != 0ull) {
+                    wave_transpose_sum64(gb);
+                    res = gb[0];
+                }
+                const int q = q0 + l_entry;
+                if (l_entry < EPG && q < cnt) {
+                    if constexpr (NW == 1) {
+                        const size_t e = se[q];
+                        if (e < a.slot_cap) slotf[8 * e + l_term] = res;
+                    } else {
+                        acc[w][q][l_term] = res;
+                    }
+                }
+            }
+        };
         for (uint32_t b0 = I.b; b0 < I.e; b0 += BATCH) {
             const int cnt = (int)min((uint32_t)BATCH, I.e - b0);
             __syncthreads();
             const uint32_t j = b0 + tid;
+            bool over = false;  // an opacity above sigma_max / 2 in this batch
             if (tid < BATCH && j < I.e) {
                 const uint32_t gid = min(a.tval[j], (uint32_t)a.n - 1u);
                 const size_t idx = vbase + gid;
@@ -359,6 +492,7 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                 float4 r0 = a.rec[4 * idx], r1 = a.rec[4 * idx + 1];
                 const float4 r2 = a.rec[4 * idx + 2];
                 const uint32_t place = __float_as_uint(r1.w);
+                over = r1.y > 0.5f * smax;
                 scale_conic(r0, r1);
                 s0[tid] = r0;
                 s1[tid] = r1;
@@ -367,98 +501,9 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                 se[tid] = first_slot(a.slot_bofs, a.slot_nblk, v, (int)gid, place) +
                           (uint32_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
             }
-            __syncthreads();
-            if (b0 < end) {
-                // groups of EPG = 9 entries: their 7 gradient terms fill 63 of
-                // the 64 values of one transposing wave sum (the last is a
-                // zero pad); lane l ends with term l % 7 of entry l / 7
-                for (int q0 = 0; q0 < cnt; q0 += EPG) {
-                    float gb[64];
-                    bool any = false;
-                    // the group's first entry index, held in one vector
-                    // register (an empty asm makes it opaque) so that the
-                    // entries' LDS reads use it with immediate offsets instead
-                    // of rebuilding an address for each entry
-                    int qv = q0;
-                    asm volatile("" : "+v"(qv));
-#pragma unroll
-                    for (int qq = 0; qq < EPG; ++qq) {
-                        float gv[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                        const int q = q0 + qq;
-                        if (q < cnt) {
-                            const float4 r0 = s0[qv + qq];
-                            const float4 r1 = s1[qv + qq];
-                            const float dx = __fsub_rn(fpx, r0.x), dy = __fsub_rn(fpy, r0.y);
-                            const float ex = falloff_exponent(dx, dy, r0.z, r0.w, r1.x);
-                            bool hit = ex >= k2e;
-                            if constexpr (!SPLIT) hit = hit && (b0 + (uint32_t)q) < lastp;
-                            // when any lane hits, the whole wave runs the entry:
-                            // computed without branches, lanes that miss keep
-                            // their state and contribute zeros
-                            if (wave_any_mask(hit) != 0ull) {
-                                // lanes that miss run the same arithmetic with
-                                // G = 0: s = 0, 1 - s = 1, so the running colour
-                                // and T stay exactly as they are and every term
-                                // below is zero
-                                float G = hit ? __builtin_amdgcn_exp2f(ex) : 0.0f;
-                                float sraw = __fmul_rn(r1.y, G);
-                                float s = clamp_opacity(sraw, smax);
-                                float om = __fsub_rn(1.0f, s);
-                                if constexpr (!SPLIT) {
-                                    // t_min > 0 runs unsplit
-                                    if (tmin > 0.0f) {
-                                        const bool stop = hit & (__fmul_rn(T, om) < tmin);
-                                        k2e = stop ? kLaneOff : k2e;
-                                        hit = hit & !stop;
-                                        G = stop ? 0.0f : G;
-                                        sraw = stop ? 0.0f : sraw;
-                                        s = stop ? 0.0f : s;
-                                        om = stop ? 1.0f : om;
-                                    }
-                                }
-                                // dL/ds = g (c T - S / (1 - s)) with S the tail
-                                // after this entry: g S is updated by -g c s T
-                                const float c = r1.z;
-                                const float sT = __fmul_rn(s, T);
-                                const float gc = g * c;
-                                Sg = __fmaf_rn(-gc, sT, Sg);
-                                const float ds = __fmaf_rn(gc, T, -(Sg * __builtin_amdgcn_rcpf(om)));
-                                // moments of dL/ds G about the mean; the conic and
-                                // alpha factors are applied once per (view,
-                                // Gaussian) in the projection backward
-                                const float gds = (sraw > smax) ? 0.0f : ds * G;
-                                const float m1x = gds * dx, m1y = gds * dy;
-                                gv[0] = m1x;
-                                gv[1] = m1y;
-                                gv[2] = m1x * dx;
-                                gv[3] = m1x * dy;
-                                gv[4] = m1y * dy;
-                                gv[5] = gds;
-                                gv[6] = g * sT;
-                                T = __fmul_rn(T, om);
-                                any = true;
-                            }
-                        }
-#pragma unroll
-                        for (int c = 0; c < kTerms; ++c) gb[qq * kTerms + c] = gv[c];
-                    }
-                    gb[63] = 0.0f;
-                    float res = 0.0f;
-                    if (wave_any_mask(any) != 0ull) {
-                        wave_transpose_sum64(gb);
-                        res = gb[0];
-                    }
-                    const int q = q0 + l_entry;
-                    if (l_entry < EPG && q < cnt) {
-                        if constexpr (NW == 1) {
-                            const size_t e = se[q];
-                            if (e < a.slot_cap) slotf[8 * e + l_term] = res;
-                        } else {
-                            acc[w][q][l_term] = res;
-                        }
-                    }
-                }
-            }
+            const bool clamp = __syncthreads_or(over);
+            if (b0 < end && clamp) run_groups(b0, cnt, std::true_type{});
+            else if (b0 < end) run_groups(b0, cnt, std::false_type{});
             if constexpr (NW > 1) {
                 __syncthreads();
                 if (tid < cnt) {
@@ -491,6 +536,184 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
     }
 }
 
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Backward of 8 x 8 tiles in chunks (the tuned shape).  The seven per-entry
+// sums are formed in two parts instead of by a seven-term butterfly per
+// entry.  The per-pair factor q = dL/ds G (zero where a pixel misses the
+// entry) goes to LDS for sixteen entries at a time, and its moments about the
+// mean come from one dense contraction over the 64 pixels on the matrix
+// cores: raw moments M_n = sum_p q(p) P_n(p) of the pixel monomials
+// P = (1, x, y, x^2, x y, y^2) about the tile centre, sixteen steps of
+// v_mfma_f32_16x16x4_f32 with the entries as rows and the monomials as
+// columns, then shifted to each entry's mean.  The colour term g s T is
+// summed by a transposing butterfly over the wave.  The vector ALU keeps the
+// per-pair compositing arithmetic; the matrix cores, which run beside it,
+// take the reductions.
+__global__ __launch_bounds__(kWave) void raster_bwd_mm_kernel(RasterArgs a)
+{
+    constexpr int TW = 8, TH = 8, NT = TW * TH, GRP = 16;
+    static_assert(NT == kWave, "one wave per tile");
+    // s1 first, as in the general kernel (paired reads of alpha and c)
+    __shared__ float4 s10[2 * NT];
+    float4 *const s1 = s10;
+    float4 *const s0 = s10 + NT;
+    __shared__ uint32_t se[NT];
+    __shared__ float aq[GRP][NT + 1];  // q by (entry, pixel); padded rows keep the operand reads off shared banks
+    __shared__ float dm[GRP][17];      // by entry: raw moments in columns 0..5, the colour term in 16
+    __shared__ int sh_item;
+    const int tid = threadIdx.x;
+    const float k2s = __fmul_rn(a.o.kappa2, kExpScale);
+    const float smax = a.o.sigma_max;
+    // matrix operands: lane l supplies A[l % 16][l / 16] = q of entry l % 16 at
+    // pixel p = st + 16 (l / 16) in step st, and B[l / 16][l % 16] = monomial
+    // l % 16 of that pixel (zero past the sixth); D[r][j] comes back in lane
+    // j + 16 (r / 4), item r % 4
+    float bm[GRP];
+    {
+        const int nn = tid & 15, kq = tid >> 4;
+#pragma unroll
+        for (int st = 0; st < GRP; ++st) {
+            const int p = st + 16 * kq;
+            const float x = (float)(p & 7) - 3.5f, y = (float)(p >> 3) - 3.5f;
+            float b = 0.0f;
+            b = nn == 0 ? 1.0f : b;
+            b = nn == 1 ? x : b;
+            b = nn == 2 ? y : b;
+            b = nn == 3 ? x * x : b;
+            b = nn == 4 ? x * y : b;
+            b = nn == 5 ? y * y : b;
+            bm[st] = b;
+        }
+    }
+    int iter = 0;
+    for (;;) {
+        const int it = next_item(a, iter, &sh_item);
+        const Item I = resolve_item(a, it);
+        if (I.tile < 0) break;
+        const int v = view_of_tile(a.views, a.V, I.tile);
+        const ViewDev &V = a.views[v];
+        const int lt = I.tile - V.tile_base;
+        const int ty = lt / V.ntx, tx = lt - ty * V.ntx;
+        const int px = tx * TW + tid % TW, py = ty * TH + tid / TW;
+        const bool inside = px < V.W && py < V.H;
+        const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+        // the monomials' origin
+        const float cx = (float)(tx * TW) + 0.5f * TW, cy = (float)(ty * TH) + 0.5f * TH;
+        const size_t vbase = (size_t)v * a.n;
+        float g = 0.0f, Cf = 0.0f;
+        if (inside) {
+            const size_t p = (size_t)V.pix_base + (size_t)py * V.W + px;
+            g = a.dL_dimg[p];
+            Cf = a.img_saved[p];
+        }
+        // (C, T) in front of the chunk, and g times the tail S
+        const float2 pre = a.part[(size_t)it * NT + tid];
+        float T = pre.y;
+        float Sg = g * (Cf - pre.x);
+        float k2e = inside ? k2s : kLaneOff;
+        auto run_groups = [&](int cnt, auto clamp_c) {
+            constexpr bool CLAMP = decltype(clamp_c)::value;
+            for (int q0 = 0; q0 < cnt; q0 += GRP) {
+                float tv[GRP];
+                // the group's first entry in one vector register (opaque to
+                // the compiler), so that the record reads take immediate offsets
+                int qv = q0;
+                asm volatile("" : "+v"(qv));
+#pragma unroll
+                for (int e = 0; e < GRP; ++e) {
+                    float qq = 0.0f, t = 0.0f;
+                    if (q0 + e < cnt) {
+                        const float4 r0 = s0[qv + e];
+                        const float4 r1 = s1[qv + e];
+                        const float dx = __fsub_rn(fpx, r0.x), dy = __fsub_rn(fpy, r0.y);
+                        const float ex = falloff_exponent(dx, dy, r0.z, r0.w, r1.x);
+                        const bool hit = ex >= k2e;
+                        // lanes that miss run the same arithmetic with G = 0:
+                        // T and the tail stay as they are, q and g s T are 0
+                        if (wave_any_mask(hit) != 0ull) {
+                            const float G = hit ? __builtin_amdgcn_exp2f(ex) : 0.0f;
+                            const float sraw = __fmul_rn(r1.y, G);
+                            float s = sraw, om;
+                            if constexpr (CLAMP) {
+                                s = clamp_opacity(sraw, smax);
+                                om = __fsub_rn(1.0f, s);
+                            } else {
+                                om = one_minus_alpha_g(r1.y, G);
+                            }
+                            // dL/ds = g (c T - S / (1 - s)), S the tail after this entry
+                            const float gc = g * r1.z;
+                            const float sT = __fmul_rn(s, T);
+                            Sg = __fmaf_rn(-gc, sT, Sg);
+                            const float ds = __fmaf_rn(gc, T, -(Sg * __builtin_amdgcn_rcpf(om)));
+                            qq = ds * G;
+                            if constexpr (CLAMP) qq = (sraw > smax) ? 0.0f : qq;
+                            t = g * sT;
+                            T = __fmul_rn(T, om);
+                        }
+                    }
+                    aq[e][tid] = qq;
+                    tv[e] = t;
+                }
+                const float tsum = wave_transpose_sum16(tv);
+                if ((tid & 3) == 0) dm[tid >> 2][16] = tsum;
+                __syncthreads();
+                floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int st = 0; st < GRP; ++st)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(aq[tid & 15][st + 16 * (tid >> 4)], bm[st], acc, 0, 0, 0);
+                if ((tid & 15) < 6) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) dm[4 * (tid >> 4) + i][tid & 15] = acc[i];
+                }
+                __syncthreads();
+                if (tid < GRP && q0 + tid < cnt) {
+                    // moments about the mean: with x = u + (x - u), u the
+                    // mean's offset from the tile centre
+                    const float M0 = dm[tid][0], M1 = dm[tid][1], M2 = dm[tid][2];
+                    const float M3 = dm[tid][3], M4 = dm[tid][4], M5 = dm[tid][5];
+                    const float4 r0 = s0[q0 + tid];
+                    const float ux = r0.x - cx, uy = r0.y - cy;
+                    const float m1x = M1 - ux * M0, m1y = M2 - uy * M0;
+                    const float mxx = M3 - ux * (2.0f * M1 - ux * M0);
+                    const float mxy = M4 - ux * M2 - uy * M1 + ux * uy * M0;
+                    const float myy = M5 - uy * (2.0f * M2 - uy * M0);
+                    const size_t e = se[q0 + tid];
+                    if (e < a.slot_cap) {
+                        a.slot[2 * e] = make_float4(m1x, m1y, mxx, mxy);
+                        a.slot[2 * e + 1] = make_float4(myy, M0, dm[tid][16], 0.0f);
+                    }
+                }
+                __syncthreads();
+            }
+        };
+        for (uint32_t b0 = I.b; b0 < I.e; b0 += NT) {
+            const int cnt = (int)min((uint32_t)NT, I.e - b0);
+            __syncthreads();
+            const uint32_t j = b0 + tid;
+            bool over = false;  // an opacity above sigma_max / 2 in this batch
+            if (j < I.e) {
+                const uint32_t gid = min(a.tval[j], (uint32_t)a.n - 1u);
+                const size_t idx = vbase + gid;
+                float4 r0 = a.rec[4 * idx], r1 = a.rec[4 * idx + 1];
+                const float4 r2 = a.rec[4 * idx + 2];
+                const uint32_t place = __float_as_uint(r1.w);
+                over = r1.y > 0.5f * smax;
+                scale_conic(r0, r1);
+                s0[tid] = r0;
+                s1[tid] = r1;
+                const uint32_t rx = __float_as_uint(r2.x), ry = __float_as_uint(r2.y);
+                const int tx0 = rx & 0xFFFF, ty0 = rx >> 16, tx1 = ry & 0xFFFF;
+                se[tid] = first_slot(a.slot_bofs, a.slot_nblk, v, (int)gid, place) +
+                          (uint32_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
+            }
+            const bool clamp = __syncthreads_or(over);
+            if (clamp) run_groups(cnt, std::true_type{});
+            else run_groups(cnt, std::false_type{});
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void tile_cost_kernel(const uint2 *ranges, int n_tiles, uint32_t *keys,
                                                         uint32_t *vals, uint32_t *counter)
 {
@@ -503,10 +726,13 @@ __global__ __launch_bounds__(256) void tile_cost_kernel(const uint2 *ranges, int
     vals[t] = (uint32_t)t;
 }
 
+// grids of blocks mapped by xcd_item
+inline int round_up8(int n) { return (n + 7) / 8 * 8; }
+
 template <int TW, int TH>
 hipError_t fwd_inst(const RasterArgs &a, int pb, hipStream_t s)
 {
-    const int grid = a.queue_counter ? pb : (a.split ? a.max_items : a.n_tiles);
+    const int grid = a.queue_counter ? pb : round_up8(a.split ? a.max_items : a.n_tiles);
     if (grid > 0) {
         const bool cnt = a.pair_counts != nullptr;
         if (a.split && cnt) raster_fwd_kernel<TW, TH, true, true><<<grid, TW * TH, 0, s>>>(a);
@@ -521,9 +747,11 @@ hipError_t fwd_inst(const RasterArgs &a, int pb, hipStream_t s)
 template <int TW, int TH>
 hipError_t bwd_inst(const RasterArgs &a, int pb, hipStream_t s)
 {
-    const int grid = a.queue_counter ? pb : (a.split ? a.max_items : a.n_tiles);
+    const int grid = a.queue_counter ? pb : round_up8(a.split ? a.max_items : a.n_tiles);
     if (grid > 0) {
-        if (a.split)
+        if (a.split && TW == 8 && TH == 8)
+            raster_bwd_mm_kernel<<<grid, TW * TH, 0, s>>>(a);
+        else if (a.split)
             raster_bwd_kernel<TW, TH, true><<<grid, TW * TH, 0, s>>>(a);
         else
             raster_bwd_kernel<TW, TH, false><<<grid, TW * TH, 0, s>>>(a);
