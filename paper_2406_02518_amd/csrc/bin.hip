@@ -298,16 +298,18 @@ __global__ __launch_bounds__(kBinBlock) void bin_count_kernel(BinArgs a)
     for (int j = threadIdx.x; j < nt; j += kBinBlock) row[j] = hist[j];
 }
 
-// 64 tiles per workgroup, the groups split among kColParts waves: every wave
-// sums its share of the 64 columns (consecutive lanes on consecutive
-// columns), the shares are combined in LDS, and every wave writes its rows'
-// exclusive offsets.  tile_cnt[t] receives the column total.
-constexpr int kColParts = 8;
-__global__ __launch_bounds__(kWave *kColParts) void bin_colscan_kernel(BinArgs a, int n_tiles, uint32_t *tile_cnt)
+// 16 tiles per workgroup (256 workgroups at 4096 tiles), the groups cut into
+// kColBlocks contiguous blocks: thread (b, c) sums column c over row block b
+// (16 consecutive tiles of a row are one 64-byte read), the block sums are
+// combined in LDS, and every thread writes its rows' exclusive offsets.
+// tile_cnt[t] receives the column total.
+constexpr int kColTiles = 16, kColBlocks = 32;
+__global__ __launch_bounds__(kColTiles *kColBlocks) void bin_colscan_kernel(BinArgs a, int n_tiles,
+                                                                          uint32_t *tile_cnt)
 {
-    __shared__ uint32_t part[kColParts][kWave];
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    const int t = blockIdx.x * kWave + lane;
+    __shared__ uint32_t part[kColBlocks][kColTiles];
+    const int c = threadIdx.x % kColTiles, rb = threadIdx.x / kColTiles;
+    const int t = blockIdx.x * kColTiles + c;
     const bool ok = t < n_tiles;
     int v = 0;
     if (ok) {
@@ -322,9 +324,9 @@ __global__ __launch_bounds__(kWave *kColParts) void bin_colscan_kernel(BinArgs a
     const ViewDev &V = a.views[v];
     const int Tv = V.ntx * V.nty, lt = t - V.tile_base;
     uint32_t *col = a.mat + (size_t)a.groups * V.tile_base + lt;
-    const int rows = (a.groups + kColParts - 1) / kColParts;
-    const int g0 = w * rows, g1 = min(a.groups, g0 + rows);
-    // the wave's rows, sixteen loads in flight
+    const int rows = (a.groups + kColBlocks - 1) / kColBlocks;
+    const int g0 = rb * rows, g1 = min(a.groups, g0 + rows);
+    // the block's rows, sixteen loads in flight
     uint32_t sum = 0;
     for (int g = g0; g < g1; g += 16) {
         uint32_t x[16];
@@ -333,16 +335,16 @@ __global__ __launch_bounds__(kWave *kColParts) void bin_colscan_kernel(BinArgs a
 #pragma unroll
         for (int q = 0; q < 16; ++q) sum += x[q];
     }
-    part[w][lane] = sum;
+    part[rb][c] = sum;
     __syncthreads();
     uint32_t run = 0, tot = 0;
 #pragma unroll
-    for (int q = 0; q < kColParts; ++q) {
-        const uint32_t c = part[q][lane];
-        if (q < w) run += c;
-        tot += c;
+    for (int q = 0; q < kColBlocks; ++q) {
+        const uint32_t x = part[q][c];
+        if (q < rb) run += x;
+        tot += x;
     }
-    if (ok && w == 0) tile_cnt[t] = tot;
+    if (ok && rb == 0) tile_cnt[t] = tot;
     for (int g = g0; g < g1; g += 16) {
         uint32_t x[16];
 #pragma unroll
@@ -642,7 +644,7 @@ hipError_t launch_bin_count(int n, int V, const uint32_t *cnt, const uint2 *rect
     const int wins = (max_view_tiles + kWin - 1) / kWin;
     const size_t lds = sizeof(uint32_t) * std::min(max_view_tiles, kWin);
     bin_count_kernel<<<dim3(a.groups, V, wins), kBinBlock, lds, s>>>(a);
-    bin_colscan_kernel<<<(n_tiles + kWave - 1) / kWave, kWave * kColParts, 0, s>>>(a, n_tiles, tile_cnt);
+    bin_colscan_kernel<<<(n_tiles + kColTiles - 1) / kColTiles, kColTiles * kColBlocks, 0, s>>>(a, n_tiles, tile_cnt);
     return hipGetLastError();
 }
 

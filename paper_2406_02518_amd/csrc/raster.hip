@@ -186,6 +186,10 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
             const float ex = falloff_exponent(dx, dy, r0.z, r0.w, r1.x);
             bool hit = ex >= k2e;
             if (wave_any_mask(hit) != 0ull) {
+                // (an empty volatile asm keeps this a branch: the compiler would
+                // otherwise turn the entry into selects, which run it, and
+                // two more selects, even when no lane hits)
+                asm volatile("");
                 // lanes that miss run the same arithmetic with G = 0: s = 0,
                 // 1 - s = 1, so C and T stay exactly as they are
                 float G = hit ? __builtin_amdgcn_exp2f(ex) : 0.0f;
@@ -552,15 +556,22 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // take the reductions.
 __global__ __launch_bounds__(kWave) void raster_bwd_mm_kernel(RasterArgs a)
 {
-    constexpr int TW = 8, TH = 8, NT = TW * TH, GRP = 16;
+    // entries per contraction, and entries whose records are read together
+    // (two: 0.2235 ms against 0.2242 for one and 0.2242 for four, at 500k /
+    // 512^2; reading the next batch's records during the current one was
+    // slower, 0.2443 ms, through the registers it holds)
+    constexpr int TW = 8, TH = 8, NT = TW * TH, GRP = 16, PF = 2;
     static_assert(NT == kWave, "one wave per tile");
     // s1 first, as in the general kernel (paired reads of alpha and c)
     __shared__ float4 s10[2 * NT];
     float4 *const s1 = s10;
     float4 *const s0 = s10 + NT;
     __shared__ uint32_t se[NT];
-    __shared__ float aq[GRP][NT + 1];  // q by (entry, pixel); padded rows keep the operand reads off shared banks
-    __shared__ float dm[GRP][17];      // by entry: raw moments in columns 0..5, the colour term in 16
+    // q by (entry, pixel), the rows padded so that the operand reads of one
+    // step fall in distinct banks
+    __shared__ float aq[GRP][NT + 1];
+    __shared__ float dm[GRP][8];  // raw moments by (entry, monomial)
+    __shared__ float tsm[GRP];    // the colour term by entry
     __shared__ int sh_item;
     const int tid = threadIdx.x;
     const float k2s = __fmul_rn(a.o.kappa2, kExpScale);
@@ -612,80 +623,102 @@ __global__ __launch_bounds__(kWave) void raster_bwd_mm_kernel(RasterArgs a)
         float T = pre.y;
         float Sg = g * (Cf - pre.x);
         float k2e = inside ? k2s : kLaneOff;
+        // slots of group qp (its raw moments in acc, its colour terms in tsm):
+        // the moments go through LDS by (entry, monomial), then lane e < 16
+        // shifts entry qp + e's moments to the mean and stores its slot
+        auto finalize = [&](int qp, int cnt, const floatx4 &acc) {
+            if ((tid & 15) < 6) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) dm[4 * (tid >> 4) + i][tid & 15] = acc[i];
+            }
+            __syncthreads();
+            if (tid < GRP && qp + tid < cnt) {
+                // moments about the mean: with x = u + (x - u), u the mean's
+                // offset from the tile centre
+                const float M0 = dm[tid][0], M1 = dm[tid][1], M2 = dm[tid][2];
+                const float M3 = dm[tid][3], M4 = dm[tid][4], M5 = dm[tid][5];
+                const float4 r0 = s0[qp + tid];
+                const float ux = r0.x - cx, uy = r0.y - cy;
+                const float m1x = M1 - ux * M0, m1y = M2 - uy * M0;
+                const float mxx = M3 - ux * (2.0f * M1 - ux * M0);
+                const float mxy = M4 - ux * M2 - uy * M1 + ux * uy * M0;
+                const float myy = M5 - uy * (2.0f * M2 - uy * M0);
+                const size_t e = se[qp + tid];
+                if (e < a.slot_cap) {
+                    a.slot[2 * e] = make_float4(m1x, m1y, mxx, mxy);
+                    a.slot[2 * e + 1] = make_float4(myy, M0, tsm[tid], 0.0f);
+                }
+            }
+            __syncthreads();
+        };
+        // The batch's groups of 16 entries.  Software-pipelined: group k's
+        // contraction is issued after its entries, and its slots are
+        // finalised after group k + 1's entries, so the matrix cores' latency
+        // is covered by the next group's arithmetic.
         auto run_groups = [&](int cnt, auto clamp_c) {
             constexpr bool CLAMP = decltype(clamp_c)::value;
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
             for (int q0 = 0; q0 < cnt; q0 += GRP) {
                 float tv[GRP];
                 // the group's first entry in one vector register (opaque to
                 // the compiler), so that the record reads take immediate offsets
                 int qv = q0;
                 asm volatile("" : "+v"(qv));
+                // PF entries' records read together, then run in order
 #pragma unroll
-                for (int e = 0; e < GRP; ++e) {
-                    float qq = 0.0f, t = 0.0f;
-                    if (q0 + e < cnt) {
-                        const float4 r0 = s0[qv + e];
-                        const float4 r1 = s1[qv + e];
-                        const float dx = __fsub_rn(fpx, r0.x), dy = __fsub_rn(fpy, r0.y);
-                        const float ex = falloff_exponent(dx, dy, r0.z, r0.w, r1.x);
-                        const bool hit = ex >= k2e;
-                        // lanes that miss run the same arithmetic with G = 0:
-                        // T and the tail stay as they are, q and g s T are 0
-                        if (wave_any_mask(hit) != 0ull) {
-                            const float G = hit ? __builtin_amdgcn_exp2f(ex) : 0.0f;
-                            const float sraw = __fmul_rn(r1.y, G);
-                            float s = sraw, om;
-                            if constexpr (CLAMP) {
-                                s = clamp_opacity(sraw, smax);
-                                om = __fsub_rn(1.0f, s);
-                            } else {
-                                om = one_minus_alpha_g(r1.y, G);
-                            }
-                            // dL/ds = g (c T - S / (1 - s)), S the tail after this entry
-                            const float gc = g * r1.z;
-                            const float sT = __fmul_rn(s, T);
-                            Sg = __fmaf_rn(-gc, sT, Sg);
-                            const float ds = __fmaf_rn(gc, T, -(Sg * __builtin_amdgcn_rcpf(om)));
-                            qq = ds * G;
-                            if constexpr (CLAMP) qq = (sraw > smax) ? 0.0f : qq;
-                            t = g * sT;
-                            T = __fmul_rn(T, om);
-                        }
+                for (int e4 = 0; e4 < GRP; e4 += PF) {
+                    float4 R0[PF], R1[PF];
+#pragma unroll
+                    for (int u = 0; u < PF; ++u) {
+                        R0[u] = s0[qv + e4 + u];
+                        R1[u] = s1[qv + e4 + u];
                     }
-                    aq[e][tid] = qq;
-                    tv[e] = t;
+#pragma unroll
+                    for (int u = 0; u < PF; ++u) {
+                        const int e = e4 + u;
+                        const float4 r0 = R0[u], r1 = R1[u];
+                        float qq = 0.0f, t = 0.0f;
+                        if (q0 + e < cnt) {
+                            const float dx = __fsub_rn(fpx, r0.x), dy = __fsub_rn(fpy, r0.y);
+                            const float ex = falloff_exponent(dx, dy, r0.z, r0.w, r1.x);
+                            const bool hit = ex >= k2e;
+                            // lanes that miss run the same arithmetic with G = 0:
+                            // T and the tail stay as they are, q and g s T are 0
+                            if (wave_any_mask(hit) != 0ull) {
+                                const float G = hit ? __builtin_amdgcn_exp2f(ex) : 0.0f;
+                                const float sraw = __fmul_rn(r1.y, G);
+                                float s = sraw, om;
+                                if constexpr (CLAMP) {
+                                    s = clamp_opacity(sraw, smax);
+                                    om = __fsub_rn(1.0f, s);
+                                } else {
+                                    om = one_minus_alpha_g(r1.y, G);
+                                }
+                                // dL/ds = g (c T - S / (1 - s)), S the tail after this entry
+                                const float gc = g * r1.z;
+                                const float sT = __fmul_rn(s, T);
+                                Sg = __fmaf_rn(-gc, sT, Sg);
+                                const float ds = __fmaf_rn(gc, T, -(Sg * __builtin_amdgcn_rcpf(om)));
+                                qq = ds * G;
+                                if constexpr (CLAMP) qq = (sraw > smax) ? 0.0f : qq;
+                                t = g * sT;
+                                T = __fmul_rn(T, om);
+                            }
+                        }
+                        aq[e][tid] = qq;
+                        tv[e] = t;
+                    }
                 }
                 const float tsum = wave_transpose_sum16(tv);
-                if ((tid & 3) == 0) dm[tid >> 2][16] = tsum;
+                if (q0 > 0) finalize(q0 - GRP, cnt, acc);
+                if ((tid & 3) == 0) tsm[tid >> 2] = tsum;
                 __syncthreads();
-                floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                acc = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
                 for (int st = 0; st < GRP; ++st)
                     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(aq[tid & 15][st + 16 * (tid >> 4)], bm[st], acc, 0, 0, 0);
-                if ((tid & 15) < 6) {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) dm[4 * (tid >> 4) + i][tid & 15] = acc[i];
-                }
-                __syncthreads();
-                if (tid < GRP && q0 + tid < cnt) {
-                    // moments about the mean: with x = u + (x - u), u the
-                    // mean's offset from the tile centre
-                    const float M0 = dm[tid][0], M1 = dm[tid][1], M2 = dm[tid][2];
-                    const float M3 = dm[tid][3], M4 = dm[tid][4], M5 = dm[tid][5];
-                    const float4 r0 = s0[q0 + tid];
-                    const float ux = r0.x - cx, uy = r0.y - cy;
-                    const float m1x = M1 - ux * M0, m1y = M2 - uy * M0;
-                    const float mxx = M3 - ux * (2.0f * M1 - ux * M0);
-                    const float mxy = M4 - ux * M2 - uy * M1 + ux * uy * M0;
-                    const float myy = M5 - uy * (2.0f * M2 - uy * M0);
-                    const size_t e = se[q0 + tid];
-                    if (e < a.slot_cap) {
-                        a.slot[2 * e] = make_float4(m1x, m1y, mxx, mxy);
-                        a.slot[2 * e + 1] = make_float4(myy, M0, dm[tid][16], 0.0f);
-                    }
-                }
-                __syncthreads();
             }
+            finalize((cnt - 1) / GRP * GRP, cnt, acc);
         };
         for (uint32_t b0 = I.b; b0 < I.e; b0 += NT) {
             const int cnt = (int)min((uint32_t)NT, I.e - b0);
