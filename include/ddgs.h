@@ -446,7 +446,7 @@ ddgs_status ddgs_num_rendered(const ddgs_ctx *ctx, int64_t *n);
 enum {
     DDGS_DBG_RECORDS = 0,     /* [n_views*n][8] f32: mu^x, mu^y, A00, A01, A11, alpha, c, 0 */
     DDGS_DBG_DEPTH_KEYS = 1,  /* [n_views*n] u32: float bits of z, 0xFFFFFFFF if culled */
-    DDGS_DBG_COUNTS = 2,      /* [n_views*n] u32: tiles touched                  */
+    DDGS_DBG_COUNTS = 2,      /* [n_views*n] u32: tiles kept (see TILE_MASKS)    */
     DDGS_DBG_RECTS = 3,       /* [n_views*n][4] u16: tile x0, y0, x1, y1 (incl.)   */
     DDGS_DBG_TILE_KEYS_UNSORTED = 4, /* [M] u32 global tile id, emission order  */
     DDGS_DBG_TILE_VALS_UNSORTED = 5, /* [M] u32 Gaussian index, emission order  */
@@ -455,8 +455,15 @@ enum {
     DDGS_DBG_RANGES = 8,      /* [n_tiles][2] u32 [start, end)                   */
     DDGS_DBG_NLAST = 9,       /* [pixels] u32: end of the contributing prefix    */
     DDGS_DBG_TILE_BASE = 10,  /* [n_views+1] i32: first global tile id per view  */
-    DDGS_DBG_FIT_MOMENTS = 11 /* [2][n(11+k) + k + k_L k] f32: Adam first, then
-                                 second moments, groups in model order       */
+    DDGS_DBG_FIT_MOMENTS = 11, /* [2][n(11+k) + k + k_L k] f32: Adam first, then
+                                  second moments, groups in model order      */
+    DDGS_DBG_TILE_MASKS = 12  /* [n_views*n] u32: tiles of the rectangle the
+                                 cut-off ellipse reaches, bit b = row-major
+                                 place b, for rectangles of at most 32 tiles
+                                 (larger ones keep every tile: 0xFFFFFFFF);
+                                 a tile is kept when the least d^T A d over
+                                 its pixel centres (the centres' box) is at
+                                 most 1.001 kappa^2 */
 };
 /* Copies an internal array of the last render to host memory (synchronises).
  * The *_UNSORTED arrays are kept only when options are set with

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libddgs.so")
 OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_CAPACITY, ERR_NONFINITE, ERR_STATE, ERR_UNSUPPORTED = range(8)
 LOSS_L1_DSSIM, LOSS_NCC, LOSS_LINEAR = 0, 1, 2
 (DBG_RECORDS, DBG_DEPTH_KEYS, DBG_COUNTS, DBG_RECTS, DBG_TILE_KEYS_UNSORTED, DBG_TILE_VALS_UNSORTED,
- DBG_TILE_KEYS, DBG_TILE_VALS, DBG_RANGES, DBG_NLAST, DBG_TILE_BASE, DBG_FIT_MOMENTS) = range(12)
+ DBG_TILE_KEYS, DBG_TILE_VALS, DBG_RANGES, DBG_NLAST, DBG_TILE_BASE, DBG_FIT_MOMENTS, DBG_TILE_MASKS) = range(13)
 T_PROJECT, T_SORT, T_RASTER_FWD, T_LOSS, T_RASTER_BWD, T_PROJECT_BWD, T_COUNT = range(7)
 STAGES = ("project", "sort", "raster_fwd", "loss", "raster_bwd", "project_bwd")
 

@@ -252,24 +252,27 @@ constexpr int kWin = 16384;  // tiles of one view held in LDS at a time
 
 struct BinArgs {
     int n, V, groups, per;        // per: Gaussians per group
-    const uint32_t *cnt;          // [V*n] tiles touched per pair
+    const uint32_t *cnt;          // [V*n] tiles kept per pair
     const uint2 *rect;            // [V*n] tile rectangles
+    const uint32_t *tmask;        // [V*n] kept tiles of the rectangles (tile_kept)
     const uint32_t *zkey;         // [V*n]
     const ViewDev *views;
     uint32_t *mat;                // [groups * n_tiles]: view v at groups * tile_base[v]
 };
 
-// Calls f(local tile) for every tile of pair r's rectangle inside [t0, t1).
+// Calls f(local tile) for every kept tile of pair r's rectangle inside [t0, t1).
 template <class F>
 __device__ __forceinline__ void for_tiles(const BinArgs &a, int64_t r, int ntx, int t0, int t1, F f)
 {
     const uint2 rc = a.rect[r];
     const int tx0 = rc.x & 0xFFFF, ty0 = rc.x >> 16, tx1 = rc.y & 0xFFFF, ty1 = rc.y >> 16;
     if ((ty1 + 1) * ntx <= t0 || ty0 * ntx >= t1) return;  // no row of the rectangle in the window
+    const uint32_t mask = a.tmask[r], area = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+    uint32_t place = 0;
     for (int ty = ty0; ty <= ty1; ++ty)
-        for (int tx = tx0; tx <= tx1; ++tx) {
+        for (int tx = tx0; tx <= tx1; ++tx, ++place) {
             const int lt = ty * ntx + tx;
-            if (lt >= t0 && lt < t1) f(lt);
+            if (lt >= t0 && lt < t1 && tile_kept(mask, area, place)) f(lt);
         }
 }
 
@@ -634,13 +637,14 @@ size_t bin_matrix_words(int64_t n, int64_t n_tiles)
     return (size_t)std::max<int64_t>(1, ((n + per - 1) / per) * std::max<int64_t>(n_tiles, 1));
 }
 
-hipError_t launch_bin_count(int n, int V, const uint32_t *cnt, const uint2 *rect, const ViewDev *views, int n_tiles,
-                            int max_view_tiles, uint32_t *mat, uint32_t *tile_cnt, hipStream_t s)
+hipError_t launch_bin_count(int n, int V, const uint32_t *cnt, const uint2 *rect, const uint32_t *tmask,
+                            const ViewDev *views, int n_tiles, int max_view_tiles, uint32_t *mat, uint32_t *tile_cnt,
+                            hipStream_t s)
 {
     if (n <= 0 || V <= 0 || n_tiles <= 0) return hipSuccess;
     if (V > 65535 || max_view_tiles <= 0) return hipErrorInvalidValue;
     const int per = bin_per_group(n, n_tiles);
-    BinArgs a{n, V, (n + per - 1) / per, per, cnt, rect, nullptr, views, mat};
+    BinArgs a{n, V, (n + per - 1) / per, per, cnt, rect, tmask, nullptr, views, mat};
     const int wins = (max_view_tiles + kWin - 1) / kWin;
     const size_t lds = sizeof(uint32_t) * std::min(max_view_tiles, kWin);
     bin_count_kernel<<<dim3(a.groups, V, wins), kBinBlock, lds, s>>>(a);
@@ -648,14 +652,15 @@ hipError_t launch_bin_count(int n, int V, const uint32_t *cnt, const uint2 *rect
     return hipGetLastError();
 }
 
-hipError_t launch_bin_scatter(int n, int V, const uint32_t *cnt, const uint2 *rect, const uint32_t *zkey,
-                              const ViewDev *views, int n_tiles, int max_view_tiles, const uint32_t *mat,
+hipError_t launch_bin_scatter(int n, int V, const uint32_t *cnt, const uint2 *rect, const uint32_t *tmask,
+                              const uint32_t *zkey, const ViewDev *views, int n_tiles, int max_view_tiles,
+                              const uint32_t *mat,
                               const uint32_t *start, uint32_t capacity, uint2 *out, hipStream_t s)
 {
     if (n <= 0 || V <= 0 || n_tiles <= 0) return hipSuccess;
     if (V > 65535 || max_view_tiles <= 0) return hipErrorInvalidValue;
     const int per = bin_per_group(n, n_tiles);
-    BinArgs a{n, V, (n + per - 1) / per, per, cnt, rect, zkey, views, const_cast<uint32_t *>(mat)};
+    BinArgs a{n, V, (n + per - 1) / per, per, cnt, rect, tmask, zkey, views, const_cast<uint32_t *>(mat)};
     const int wins = (max_view_tiles + kWin - 1) / kWin;
     const size_t lds = sizeof(uint32_t) * std::min(max_view_tiles, kWin);
     bin_scatter_kernel<<<dim3((a.groups + 7) / 8 * 8, V, wins), kBinBlock, lds, s>>>(a, start, capacity, out);

@@ -385,7 +385,7 @@ ddgs_status ensure_static(ddgs_ctx *c)
     DDGS_TRY(ensure_t(c, "rec", 4 * VN, &f4));
     uint2 *u2;
     DDGS_TRY(ensure_t(c, "rect", VN, &u2));
-    const char *u32s[] = {"zkey", "cnt", "slot_lp"};
+    const char *u32s[] = {"zkey", "cnt", "slot_lp", "tmask"};
     for (const char *nm : u32s) DDGS_TRY(ensure_t(c, nm, VN, &u));
     DDGS_TRY(ensure_t(c, "tile_cnt", std::max(1, c->n_tiles), &u));
     DDGS_TRY(ensure_t(c, "bin_mat", bin_matrix_words(n, c->n_tiles), &u));
@@ -528,16 +528,17 @@ ddgs_status enqueue_front(ddgs_ctx *c, uint32_t capacity, bool captured)
     const ModelDev m = model_dev(c->model, c->c_override);
     const int V = (int)c->views_h.size();
     GaussCache gc{buf<float>(c, "cov"), buf<float>(c, "alpha"), buf<float>(c, "ciso"), buf<float>(c, "hdir")};
-    ProjOut po{buf<float4>(c, "rec"),      buf<uint2>(c, "rect"),     buf<uint32_t>(c, "zkey"),
-               buf<uint32_t>(c, "cnt"),    buf<uint32_t>(c, "slot_lp"), buf<uint32_t>(c, "slot_btot")};
+    ProjOut po{buf<float4>(c, "rec"),   buf<uint2>(c, "rect"),        buf<uint32_t>(c, "tmask"),
+               buf<uint32_t>(c, "zkey"), buf<uint32_t>(c, "cnt"),       buf<uint32_t>(c, "slot_lp"),
+               buf<uint32_t>(c, "slot_btot")};
     const RenderOpts ro = render_opts(c->opt);
     stage_begin(c, DDGS_T_PROJECT);
     HIP_TRY(c, launch_prep_project(m, gc, buf<ViewDev>(c, "views"), V, ro, po, s));
     stage_end(c, DDGS_T_PROJECT);
     stage_begin(c, DDGS_T_SORT);
-    HIP_TRY(c, launch_bin_count(m.n, V, buf<uint32_t>(c, "cnt"), buf<uint2>(c, "rect"), buf<ViewDev>(c, "views"),
-                                c->n_tiles, c->max_view_tiles, buf<uint32_t>(c, "bin_mat"), buf<uint32_t>(c, "tile_cnt"),
-                                s));
+    HIP_TRY(c, launch_bin_count(m.n, V, buf<uint32_t>(c, "cnt"), buf<uint2>(c, "rect"), buf<uint32_t>(c, "tmask"),
+                                buf<ViewDev>(c, "views"), c->n_tiles, c->max_view_tiles, buf<uint32_t>(c, "bin_mat"),
+                                buf<uint32_t>(c, "tile_cnt"), s));
     // a captured step (its buffers are sized already) has the scan write the
     // chunked raster's work items too
     TileItems ti{};
@@ -565,9 +566,9 @@ ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, float *images)
     const int n = (int)c->model.n;
     const int64_t VN = (int64_t)n * V;
     uint2 *ent = buf<uint2>(c, "bin_ent");
-    HIP_TRY(c, launch_bin_scatter(n, V, buf<uint32_t>(c, "cnt"), buf<uint2>(c, "rect"), buf<uint32_t>(c, "zkey"),
-                                  buf<ViewDev>(c, "views"), c->n_tiles, c->max_view_tiles, buf<uint32_t>(c, "bin_mat"),
-                                  buf<uint32_t>(c, "cursor"), (uint32_t)cap, ent, s));
+    HIP_TRY(c, launch_bin_scatter(n, V, buf<uint32_t>(c, "cnt"), buf<uint2>(c, "rect"), buf<uint32_t>(c, "tmask"),
+                                  buf<uint32_t>(c, "zkey"), buf<ViewDev>(c, "views"), c->n_tiles, c->max_view_tiles,
+                                  buf<uint32_t>(c, "bin_mat"), buf<uint32_t>(c, "cursor"), (uint32_t)cap, ent, s));
     if (c->keep_unsorted)
         HIP_TRY(c, launch_copy_u32((uint32_t *)buf<uint2>(c, "ubin"), (const uint32_t *)ent, nullptr, 2 * cap, s));
     HIP_TRY(c, launch_tile_sort(buf<uint2>(c, "ranges"), c->n_tiles, ent, buf<uint2>(c, "bin_tmp"),
@@ -1738,6 +1739,7 @@ ddgs_status ddgs_debug_copy(ddgs_ctx *c, int what, void *host, size_t bytes)
     case DDGS_DBG_DEPTH_KEYS: src = buf<void>(c, "zkey"); need = (size_t)VN * 4; break;
     case DDGS_DBG_COUNTS: src = buf<void>(c, "cnt"); need = (size_t)VN * 4; break;
     case DDGS_DBG_RECTS: src = buf<void>(c, "rect"); need = (size_t)VN * 8; break;
+    case DDGS_DBG_TILE_MASKS: src = buf<void>(c, "tmask"); need = (size_t)VN * 4; break;
     case DDGS_DBG_TILE_KEYS:
     case DDGS_DBG_TILE_KEYS_UNSORTED: {
         // the entries are binned by tile: every place of tile t's range holds t

@@ -59,14 +59,31 @@ struct GaussCache {
 constexpr int kSlotBlock = 256;
 inline int64_t slot_blocks(int64_t n) { return (n + kSlotBlock - 1) / kSlotBlock; }
 
+// Tile selection of a pair: its rectangle [tx0, tx1] x [ty0, ty1] and, when
+// the rectangle has at most kMaskTiles tiles, a mask of the tiles the cut-off
+// ellipse reaches (bit b = row-major place b in the rectangle); larger
+// rectangles keep every tile (mask kAllTiles).
+constexpr uint32_t kMaskTiles = 32;
+constexpr uint32_t kAllTiles = 0xFFFFFFFFu;
+__device__ __forceinline__ bool tile_kept(uint32_t mask, uint32_t area, uint32_t place)
+{
+    return area > kMaskTiles || ((mask >> place) & 1u);
+}
+// place of a kept tile among the pair's kept tiles (its gradient slot)
+__device__ __forceinline__ uint32_t kept_rank(uint32_t mask, uint32_t area, uint32_t place)
+{
+    return area > kMaskTiles ? place : (uint32_t)__popc(mask & ((1u << place) - 1u));
+}
+
 // Per (view, Gaussian) projection output.
 struct ProjOut {
     float4 *rec;     // [V*n][4], 64 B (one cache line) per pair: (mx, my, A00, A01),
                      // (A11, alpha, c, bits of the pair's place in its block's
-                     // slot numbering), (bits of rect.x, rect.y, 0, 0), unused
+                     // slot numbering), (bits of rect.x, rect.y, tile mask, 0), unused
     uint2 *rect;     // [V*n]: (tx0 | ty0 << 16, tx1 | ty1 << 16), inclusive
+    uint32_t *tmask; // [V*n]: kept tiles of the rectangle (tile_kept)
     uint32_t *zkey;  // [V*n]: float bits of the source-frame depth, ~0u if culled
-    uint32_t *cnt;   // [V*n]: number of tiles touched
+    uint32_t *cnt;   // [V*n]: number of tiles kept
     // gradient-slot numbering in (view, Gaussian) order: each block of
     // kSlotBlock Gaussians of a view stores its exclusive scan of the tile
     // counts (slot_lp, [V*n]) and its total (slot_btot, [V * slot_blocks(n)]),
@@ -340,14 +357,16 @@ hipError_t launch_tile_scan(const uint32_t *tile_cnt, int n_tiles, uint2 *ranges
 // group's offset inside its tile; tile_cnt[t] receives the tile's total.
 // max_view_tiles: the largest tile count of one view.
 size_t bin_matrix_words(int64_t n, int64_t n_tiles);
-hipError_t launch_bin_count(int n, int V, const uint32_t *cnt, const uint2 *rect, const ViewDev *views, int n_tiles,
-                            int max_view_tiles, uint32_t *mat, uint32_t *tile_cnt, hipStream_t s);
+hipError_t launch_bin_count(int n, int V, const uint32_t *cnt, const uint2 *rect, const uint32_t *tmask,
+                            const ViewDev *views, int n_tiles, int max_view_tiles, uint32_t *mat, uint32_t *tile_cnt,
+                            hipStream_t s);
 // Every (pair, tile) entry goes to start[tile] + its group's offset + a place
 // claimed inside the group, as (depth key, Gaussian index); places at or
 // beyond capacity are dropped.
-hipError_t launch_bin_scatter(int n, int V, const uint32_t *cnt, const uint2 *rect, const uint32_t *zkey,
-                              const ViewDev *views, int n_tiles, int max_view_tiles, const uint32_t *mat,
-                              const uint32_t *start, uint32_t capacity, uint2 *out, hipStream_t s);
+hipError_t launch_bin_scatter(int n, int V, const uint32_t *cnt, const uint2 *rect, const uint32_t *tmask,
+                              const uint32_t *zkey, const ViewDev *views, int n_tiles, int max_view_tiles,
+                              const uint32_t *mat, const uint32_t *start, uint32_t capacity, uint2 *out,
+                              hipStream_t s);
 // One workgroup per tile sorts its range of ent by (depth key, index) and
 // writes the indices to tval; tmp (same layout as ent) is scratch for ranges
 // longer than the LDS holds.

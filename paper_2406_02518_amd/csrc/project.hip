@@ -234,6 +234,46 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(ModelDev m, GaussCache gc)
 
 // ------------------------------------------------------------------ project
 
+// Minimum of d^T A d over the box [xl, xh] x [yl, yh] of offsets from the
+// mean (A positive definite, iA00 = 1 / A00, iA11 = 1 / A11): zero when the
+// mean lies in the box, else the least of the four edges' minima (on an edge
+// the quadratic is a parabola in the free coordinate, minimised at
+// -A01 x / A11 or -A01 y / A00 and clamped to the edge).
+__device__ __forceinline__ float box_min_d2(float A00, float A01, float A11, float iA00, float iA11, float xl,
+                                            float xh, float yl, float yh)
+{
+    if (xl <= 0.0f && 0.0f <= xh && yl <= 0.0f && 0.0f <= yh) return 0.0f;
+    auto q = [&](float x, float y) { return x * (A00 * x + 2.0f * A01 * y) + A11 * y * y; };
+    auto on_x = [&](float x) { return q(x, fminf(fmaxf(-A01 * x * iA11, yl), yh)); };
+    auto on_y = [&](float y) { return q(fminf(fmaxf(-A01 * y * iA00, xl), xh), y); };
+    return fminf(fminf(on_x(xl), on_x(xh)), fminf(on_y(yl), on_y(yh)));
+}
+
+// Tiles of the rectangle [tx0, tx1] x [ty0, ty1] (at most 32, bit b =
+// row-major place in the rectangle) whose pixel centres come within the
+// cut-off ellipse d^T A d <= kappa^2, widened by 0.1 % (far above the
+// rounding of these FP32 evaluations and of the per-pixel test) so that no
+// pixel the exact definition puts inside is dropped.  The rectangle is the
+// ellipse's bounding box, so its corner tiles are often outside.
+__device__ __forceinline__ uint32_t tile_mask(const Geom &g, const RenderOpts &o, const ViewDev &V, int tx0, int ty0,
+                                              int tx1, int ty1)
+{
+    const float lim = o.kappa * o.kappa * 1.001f;
+    const float iA00 = 1.0f / g.A00, iA11 = 1.0f / g.A11;
+    uint32_t m = 0u;
+    int b = 0;
+    for (int ty = ty0; ty <= ty1; ++ty) {
+        const float yl = (float)(ty * o.tile_h) + 0.5f - g.muy;
+        const float yh = (float)min((ty + 1) * o.tile_h, V.H) - 0.5f - g.muy;
+        for (int tx = tx0; tx <= tx1; ++tx, ++b) {
+            const float xl = (float)(tx * o.tile_w) + 0.5f - g.mux;
+            const float xh = (float)min((tx + 1) * o.tile_w, V.W) - 0.5f - g.mux;
+            if (box_min_d2(g.A00, g.A01, g.A11, iA00, iA11, xl, xh, yl, yh) <= lim) m |= 1u << b;
+        }
+    }
+    return m;
+}
+
 // Projection of Gaussian i into view v from its cache values (cw, alpha,
 // ciso; hd(r) gives h_r of a directional Gaussian), then this block's scan of
 // the tile counts for the slot numbering (every thread of the block calls it).
@@ -257,6 +297,7 @@ __device__ __forceinline__ void project_one(const ModelDev &m, const ViewDev *vi
             po.zkey[vi] = 0xFFFFFFFFu;
             po.cnt[vi] = 0;
             po.rect[vi] = make_uint2(0, 0);
+            po.tmask[vi] = 0u;
             po.rec[4 * vi] = make_float4(0.f, 0.f, 0.f, 0.f);
             po.rec[4 * vi + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
         } else {
@@ -284,18 +325,26 @@ __device__ __forceinline__ void project_one(const ModelDev &m, const ViewDev *vi
             const float fv0 = fmaxf(ceilf(g.muy - ryp - 0.5f), 0.0f);
             const float fv1 = fminf(floorf(g.muy + ryp - 0.5f), (float)(V.H - 1));
             uint2 rc = make_uint2(0, 0);
+            uint32_t mask = kAllTiles;
             if (fu0 <= fu1 && fv0 <= fv1) {
                 const int tx0 = (int)fu0 / o.tile_w, tx1 = (int)fu1 / o.tile_w;
                 const int ty0 = (int)fv0 / o.tile_h, ty1 = (int)fv1 / o.tile_h;
                 count = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+                // rectangles of up to 32 tiles keep only the tiles the
+                // ellipse reaches (larger ones keep every tile)
+                if (count <= kMaskTiles) {
+                    mask = tile_mask(g, o, V, tx0, ty0, tx1, ty1);
+                    count = (uint32_t)__popc(mask);
+                }
                 rc = make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16));
             }
             po.zkey[vi] = g.zbits;
             po.cnt[vi] = count;
             po.rect[vi] = rc;
+            po.tmask[vi] = mask;
             po.rec[4 * vi] = make_float4(g.mux, g.muy, g.A00, g.A01);
             r1 = make_float4(g.A11, alpha, c, 0.0f);
-            po.rec[4 * vi + 2] = make_float4(__uint_as_float(rc.x), __uint_as_float(rc.y), 0.0f, 0.0f);
+            po.rec[4 * vi + 2] = make_float4(__uint_as_float(rc.x), __uint_as_float(rc.y), __uint_as_float(mask), 0.0f);
         }
     }
     // the pair's place in its block's slot numbering (exclusive scan of the
@@ -803,21 +852,23 @@ __device__ void pose_final_block(int v, const ViewDev *views, int n_waves, const
     double s[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) s[q] = 0.0;
-    // two partials' loads in flight per thread
+    // four partials' loads in flight per thread (one block reduces a view:
+    // the block's time is its chain of load round trips), then the rest
+    constexpr int U = 4;
     int w = threadIdx.x;
-    for (; w + kFinalBlock < n_waves; w += 2 * kFinalBlock) {
+    for (; w + (U - 1) * kFinalBlock < n_waves; w += U * kFinalBlock) {
         const float *p0 = part + ((size_t)v * n_waves + w) * 9;
-        const float *p1 = p0 + (size_t)kFinalBlock * 9;
-        float x0[9], x1[9];
+        float x[U][9];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            x0[q] = p0[q];
-            x1[q] = p1[q];
-        }
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int q = 0; q < 9; ++q) s[q] += (double)x0[q] + (double)x1[q];
+            for (int q = 0; q < 9; ++q) x[u][q] = p0[(size_t)u * kFinalBlock * 9 + q];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < 9; ++q) s[q] += (double)x[u][q];
     }
-    if (w < n_waves) {
+    for (; w < n_waves; w += kFinalBlock) {
         const float *p = part + ((size_t)v * n_waves + w) * 9;
 #pragma unroll
         for (int q = 0; q < 9; ++q) s[q] += (double)p[q];

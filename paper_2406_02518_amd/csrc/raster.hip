@@ -492,7 +492,7 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                 const uint32_t gid = min(a.tval[j], (uint32_t)a.n - 1u);
                 const size_t idx = vbase + gid;
                 // one 64-byte line per pair: record, place in the slot
-                // numbering, rectangle
+                // numbering, rectangle and tile mask
                 float4 r0 = a.rec[4 * idx], r1 = a.rec[4 * idx + 1];
                 const float4 r2 = a.rec[4 * idx + 2];
                 const uint32_t place = __float_as_uint(r1.w);
@@ -500,10 +500,14 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                 scale_conic(r0, r1);
                 s0[tid] = r0;
                 s1[tid] = r1;
+                // the slot: the pair's first slot plus this tile's rank among
+                // the pair's kept tiles (row-major in its rectangle)
                 const uint32_t rx = __float_as_uint(r2.x), ry = __float_as_uint(r2.y);
-                const int tx0 = rx & 0xFFFF, ty0 = rx >> 16, tx1 = ry & 0xFFFF;
+                const int tx0 = rx & 0xFFFF, ty0 = rx >> 16, tx1 = ry & 0xFFFF, ty1 = ry >> 16;
+                const uint32_t area = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+                const uint32_t at = (uint32_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
                 se[tid] = first_slot(a.slot_bofs, a.slot_nblk, v, (int)gid, place) +
-                          (uint32_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
+                          kept_rank(__float_as_uint(r2.z), area, at);
             }
             const bool clamp = __syncthreads_or(over);
             if (b0 < end && clamp) run_groups(b0, cnt, std::true_type{});
@@ -735,10 +739,14 @@ __global__ __launch_bounds__(kWave) void raster_bwd_mm_kernel(RasterArgs a)
                 scale_conic(r0, r1);
                 s0[tid] = r0;
                 s1[tid] = r1;
+                // the slot: the pair's first slot plus this tile's rank among
+                // the pair's kept tiles (row-major in its rectangle)
                 const uint32_t rx = __float_as_uint(r2.x), ry = __float_as_uint(r2.y);
-                const int tx0 = rx & 0xFFFF, ty0 = rx >> 16, tx1 = ry & 0xFFFF;
+                const int tx0 = rx & 0xFFFF, ty0 = rx >> 16, tx1 = ry & 0xFFFF, ty1 = ry >> 16;
+                const uint32_t area = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+                const uint32_t at = (uint32_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
                 se[tid] = first_slot(a.slot_bofs, a.slot_nblk, v, (int)gid, place) +
-                          (uint32_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
+                          kept_rank(__float_as_uint(r2.z), area, at);
             }
             const bool clamp = __syncthreads_or(over);
             if (clamp) run_groups(cnt, std::true_type{});

@@ -43,9 +43,43 @@ def small_scene(seed=5, n=600, k=16, L=3, extent=20.0, iso_fraction=0.8, std_ran
                               std_range=std_range, alpha_range=alpha_range)
 
 
-def expected_tile_lists(zkeys, counts, rects, tile_base, ntx_per_view, n):
+def kept_tiles(rect, mask):
+    """The kept tiles of a rectangle (tx0, ty0, tx1, ty1) in row-major order:
+    bit b of the mask is place b when the rectangle has at most 32 tiles,
+    larger rectangles keep every tile."""
+    tx0, ty0, tx1, ty1 = (int(x) for x in rect)
+    area = (tx1 - tx0 + 1) * (ty1 - ty0 + 1)
+    out, b = [], 0
+    for ty in range(ty0, ty1 + 1):
+        for tx in range(tx0, tx1 + 1):
+            if area > 32 or (int(mask) >> b) & 1:
+                out.append((tx, ty))
+            b += 1
+    return out
+
+
+def box_min_d2(A00, A01, A11, xl, xh, yl, yh):
+    """min of d^T A d over the box [xl, xh] x [yl, yh] of offsets (FP64): the
+    vertices and the interior critical points of the four edges."""
+    if xl <= 0 <= xh and yl <= 0 <= yh:
+        return 0.0
+    q = lambda x, y: A00 * x * x + 2 * A01 * x * y + A11 * y * y  # noqa: E731
+    c = [q(x, y) for x in (xl, xh) for y in (yl, yh)]
+    for x in (xl, xh):
+        y = -A01 * x / A11
+        if yl <= y <= yh:
+            c.append(q(x, y))
+    for y in (yl, yh):
+        x = -A01 * y / A00
+        if xl <= x <= xh:
+            c.append(q(x, y))
+    return min(c)
+
+
+def expected_tile_lists(zkeys, counts, rects, tile_base, ntx_per_view, n, masks):
     """Host construction of the sorted tile lists: emit every (view, Gaussian)
-    rectangle in (depth key, index) order, then stable-sort by tile id."""
+    entry of its kept tiles in (depth key, index) order, then stable-sort by
+    tile id."""
     VN = zkeys.size
     order = np.lexsort((np.arange(VN), zkeys))  # by zkey, ties by index
     keys, vals = [], []
@@ -54,11 +88,11 @@ def expected_tile_lists(zkeys, counts, rects, tile_base, ntx_per_view, n):
         if c == 0:
             continue
         v, i = divmod(int(vi), n)
-        tx0, ty0, tx1, ty1 = (int(x) for x in rects[vi])
-        for ty in range(ty0, ty1 + 1):
-            for tx in range(tx0, tx1 + 1):
-                keys.append(tile_base[v] + ty * ntx_per_view[v] + tx)
-                vals.append(i)
+        tiles = kept_tiles(rects[vi], masks[vi])
+        assert len(tiles) == c
+        for tx, ty in tiles:
+            keys.append(tile_base[v] + ty * ntx_per_view[v] + tx)
+            vals.append(i)
     keys = np.asarray(keys, dtype=np.uint32)
     vals = np.asarray(vals, dtype=np.uint32)
     s = np.argsort(keys, kind="stable")

@@ -3,7 +3,7 @@ oracle and plain library routines (numpy stable sort, cumulative sum)."""
 import numpy as np
 import pytest
 
-from gpu_common import expected_tile_lists, make_renderer, rel_l2, small_scene
+from gpu_common import box_min_d2, expected_tile_lists, kept_tiles, make_renderer, rel_l2, small_scene
 from oracle import ref
 from paper_2406_02518_amd import binding, synth
 
@@ -72,6 +72,10 @@ def _records(R, V, n):
     return rec, zk, cnt, rects
 
 
+def _masks(R, V, n):
+    return R.debug(binding.DBG_TILE_MASKS, np.uint32, V * n).reshape(V, n)
+
+
 @pytest.mark.parametrize("cfg", ["C1", "C2s"])
 def test_projection_records_match_oracle(R, cfg):
     if cfg == "C1":
@@ -83,6 +87,7 @@ def test_projection_records_match_oracle(R, cfg):
     R.render()
     n = c.scene.n
     rec, zk, cnt, rects = _records(R, len(c.views), n)
+    masks = _masks(R, len(c.views), n)
     for v, view in enumerate(c.views):
         P = ref.project(c.scene, view)
         valid = P[:, 0] > 0
@@ -106,10 +111,25 @@ def test_projection_records_match_oracle(R, cfg):
             v0, v1 = max(v0, 0), min(v1, view.H - 1)
             if u0 > u1 or v0 > v1:
                 continue
-            assert cnt[v, i] > 0
-            tx0, ty0, tx1, ty1 = rects[v, i]
+            # (a bounding box with pixel centres may still have none inside the
+            # ellipse: then no tile is kept and the count is zero)
+            tx0, ty0, tx1, ty1 = (int(x) for x in rects[v, i])
             assert tx0 <= u0 // tw and tx1 >= u1 // tw and ty0 <= v0 // th and ty1 >= v1 // th
-            assert cnt[v, i] == (tx1 - tx0 + 1) * (ty1 - ty0 + 1)
+            # the kept tiles: exactly those whose pixel centres come within the
+            # cut-off ellipse (FP64 geometry of the oracle's conic; tiles at the
+            # 0.1 % margin are not decided here)
+            kept = set(kept_tiles(rects[v, i], masks[v, i]))
+            assert cnt[v, i] == len(kept)
+            A00, A01, A11 = P[i, 3], P[i, 4], P[i, 5]
+            for ty in range(ty0, ty1 + 1):
+                for tx in range(tx0, tx1 + 1):
+                    xl, xh = tx * tw + 0.5 - P[i, 1], min((tx + 1) * tw, view.W) - 0.5 - P[i, 1]
+                    yl, yh = ty * th + 0.5 - P[i, 2], min((ty + 1) * th, view.H) - 0.5 - P[i, 2]
+                    d2 = box_min_d2(A00, A01, A11, xl, xh, yl, yh)
+                    if d2 <= 9.0 * (1 - 1e-4):
+                        assert (tx, ty) in kept, (v, i, tx, ty, d2)
+                    elif d2 > 9.0 * (1 + 2e-3) and (tx1 - tx0 + 1) * (ty1 - ty0 + 1) <= 32:
+                        assert (tx, ty) not in kept, (v, i, tx, ty, d2)
 
 
 def test_tile_lists_bit_exact(R):
@@ -137,8 +157,9 @@ def test_tile_lists_bit_exact(R):
     # same lists from the per-(view, Gaussian) keys and rectangles on the host
     n = c.scene.n
     _, zk, cnt, rects = _records(R, len(views), n)
+    masks = _masks(R, len(views), n)
     ntx = [(v.W + 15) // 16 for v in views]
-    ek, ev = expected_tile_lists(zk.ravel(), cnt.ravel(), rects.reshape(-1, 4), base, ntx, n)
+    ek, ev = expected_tile_lists(zk.ravel(), cnt.ravel(), rects.reshape(-1, 4), base, ntx, n, masks.ravel())
     np.testing.assert_array_equal(sk, ek)
     np.testing.assert_array_equal(sv, ev)
     # ranges by a linear scan
@@ -180,7 +201,7 @@ def test_tile_lists_long_ranges_and_depth_ties(R):
             assert (ranges[:, 1] - ranges[:, 0]).max() > 4096
             _, zk, cnt, rects = _records(R, 1, n)
             ek, ev = expected_tile_lists(zk.ravel(), cnt.ravel(), rects.reshape(-1, 4), base,
-                                         [(v.W + tw - 1) // tw], n)
+                                         [(v.W + tw - 1) // tw], n, _masks(R, 1, n).ravel())
             np.testing.assert_array_equal(sk, ek)
             np.testing.assert_array_equal(sv, ev)
             assert rel_l2(img, ref.render(sc, [v])[0]) < 1e-4
