@@ -501,8 +501,10 @@ ddgs_status ddgs_debug_exclusive_scan(ddgs_ctx *ctx, const uint32_t *in, uint32_
 ddgs_status ddgs_debug_count_pairs(ddgs_ctx *ctx, int enable);
 ddgs_status ddgs_debug_pair_counts(ddgs_ctx *ctx, int64_t *evaluated, int64_t *contributing);
 
-/* Accumulated device time of the last render/backward/step per stage, ms
- * (filled when timing is enabled with ddgs_enable_timing). */
+/* Device time of the last render/backward per stage, ms (filled when timing
+ * is enabled with ddgs_enable_timing; captured steps are not timed).  The
+ * sort stage is the sum of its two parts: between them a render reads the
+ * entry total back to the host, which is not device work. */
 enum { DDGS_T_PROJECT = 0, DDGS_T_SORT = 1, DDGS_T_RASTER_FWD = 2, DDGS_T_LOSS = 3,
        DDGS_T_RASTER_BWD = 4, DDGS_T_PROJECT_BWD = 5, DDGS_T_COUNT = 6 };
 ddgs_status ddgs_enable_timing(ddgs_ctx *ctx, int enable);

@@ -852,23 +852,21 @@ __device__ void pose_final_block(int v, const ViewDev *views, int n_waves, const
     double s[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) s[q] = 0.0;
-    // four partials' loads in flight per thread (one block reduces a view:
-    // the block's time is its chain of load round trips), then the rest
-    constexpr int U = 4;
+    // two partials' loads in flight per thread
     int w = threadIdx.x;
-    for (; w + (U - 1) * kFinalBlock < n_waves; w += U * kFinalBlock) {
+    for (; w + kFinalBlock < n_waves; w += 2 * kFinalBlock) {
         const float *p0 = part + ((size_t)v * n_waves + w) * 9;
-        float x[U][9];
+        const float *p1 = p0 + (size_t)kFinalBlock * 9;
+        float x0[9], x1[9];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int q = 0; q < 9; ++q) {
+            x0[q] = p0[q];
+            x1[q] = p1[q];
+        }
 #pragma unroll
-            for (int q = 0; q < 9; ++q) x[u][q] = p0[(size_t)u * kFinalBlock * 9 + q];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int q = 0; q < 9; ++q) s[q] += (double)x[u][q];
+        for (int q = 0; q < 9; ++q) s[q] += (double)x0[q] + (double)x1[q];
     }
-    for (; w < n_waves; w += kFinalBlock) {
+    if (w < n_waves) {
         const float *p = part + ((size_t)v * n_waves + w) * 9;
 #pragma unroll
         for (int q = 0; q < 9; ++q) s[q] += (double)p[q];
