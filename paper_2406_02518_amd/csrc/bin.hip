@@ -49,7 +49,11 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t x, uint32_t *lds /* >= 4
 // its own, then scans its own.  Writes the ranges (clamped to the capacity)
 // and the scatter cursors (= range starts); the last block stores the total,
 // the kept count and the step flags.  Block 0 also turns the slot
-// numbering's block totals into the blocks' first slots (in place).
+// numbering's block totals into the blocks' first slots (in place).  The
+// same scan lists, in tile order, the tiles of more than kSortShort entries
+// for the tile sort's long-range launch (a list built with a global atomic
+// per tile would serialise on its counter).
+constexpr int kSortShort = 2560;  // longest range the per-tile sort's first launch takes
 struct ScanArgs {
     const uint32_t *tile_cnt;
     int n_tiles;
@@ -69,7 +73,12 @@ struct ScanArgs {
     uint2 *items;
     uint32_t max_items;
     uint32_t *n_items, *counter;
+    // long tiles (count > kSortShort): the list, its length, and per-block
+    // counts of the three-launch scan
+    uint32_t *long_list, *long_n, *long_bsum;
 };
+
+__device__ __forceinline__ uint32_t is_long(uint32_t cnt) { return cnt > (uint32_t)kSortShort ? 1u : 0u; }
 
 __device__ void slot_block_scan(uint32_t *slot_btot, int64_t slot_nb, uint32_t *wl)
 {
@@ -121,41 +130,50 @@ __global__ __launch_bounds__(kBlock) void tile_scan_self_kernel(ScanArgs a)
 {
     __shared__ uint32_t wl[kWaves];
     __shared__ uint64_t red[kWaves];
-    __shared__ uint32_t ired[kWaves];
+    __shared__ uint32_t ired[kWaves], lred[kWaves];
     if (blockIdx.x == 0) slot_block_scan(a.slot_btot, a.slot_nb, wl);
     const int base = blockIdx.x * kBlock;
     const uint32_t sp = a.split;
-    // entries and (with chunks) work items of the tiles before this block's
+    // entries, long tiles and (with chunks) work items of the tiles before
+    // this block's
     uint64_t c = 0;
-    uint32_t ci = 0;
+    uint32_t ci = 0, cl = 0;
 #pragma unroll 4
     for (int t = threadIdx.x; t < base; t += kBlock) {
         const uint32_t x = a.tile_cnt[t];
         c += x;
+        cl += is_long(x);
         if (sp) ci += (x + sp - 1u) / sp;
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         c += __shfl_xor(c, o, kWave);
         ci += __shfl_xor(ci, o, kWave);
+        cl += __shfl_xor(cl, o, kWave);
     }
     if ((threadIdx.x & (kWave - 1)) == 0) {
         red[threadIdx.x / kWave] = c;
         ired[threadIdx.x / kWave] = ci;
+        lred[threadIdx.x / kWave] = cl;
     }
     __syncthreads();
     uint64_t carry = 0;
-    uint32_t icarry = 0;
+    uint32_t icarry = 0, lcarry = 0;
 #pragma unroll
     for (int q = 0; q < kWaves; ++q) {
         carry += red[q];
         icarry += ired[q];
+        lcarry += lred[q];
     }
     const int t = base + threadIdx.x;
     const uint32_t v = t < a.n_tiles ? a.tile_cnt[t] : 0u;
     uint32_t tot;
     const uint32_t pre = block_scan(v, wl, tot);
     if (t < a.n_tiles) write_range(a, t, carry + pre, v);
+    uint32_t ltot;
+    const uint32_t lf = is_long(v);
+    const uint32_t lpre = lcarry + block_scan(lf, wl, ltot);
+    if (lf) a.long_list[lpre] = (uint32_t)t;
     uint32_t itot = 0;
     if (sp) {
         // (chunks of the unclamped count: past a clamped range end an item is
@@ -171,6 +189,7 @@ __global__ __launch_bounds__(kBlock) void tile_scan_self_kernel(ScanArgs a)
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
         finish_scan(a, carry + tot);
+        *a.long_n = lcarry + ltot;
         if (sp) {
             const uint32_t ni = icarry + itot;
             *a.n_items = ni > a.max_items ? a.max_items : ni;
@@ -181,50 +200,86 @@ __global__ __launch_bounds__(kBlock) void tile_scan_self_kernel(ScanArgs a)
 }
 
 // More tiles: block sums, one block scanning them, then the blocks' scans.
-__global__ __launch_bounds__(kBlock) void tile_sum_kernel(const uint32_t *cnt, int n, uint64_t *bsum)
+__global__ __launch_bounds__(kBlock) void tile_sum_kernel(const uint32_t *cnt, int n, uint64_t *bsum, uint32_t *lsum)
 {
     const int t = blockIdx.x * kBlock + threadIdx.x;
-    uint64_t c = t < n ? cnt[t] : 0u;
+    const uint32_t x = t < n ? cnt[t] : 0u;
+    uint64_t c = x;
+    uint32_t l = is_long(x);
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
+    for (int o = 32; o > 0; o >>= 1) {
+        c += __shfl_xor(c, o, kWave);
+        l += __shfl_xor(l, o, kWave);
+    }
     __shared__ uint64_t red[kWaves];
-    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = c;
+    __shared__ uint32_t lred[kWaves];
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        red[threadIdx.x / kWave] = c;
+        lred[threadIdx.x / kWave] = l;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) bsum[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x == 0) {
+        bsum[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+        lsum[blockIdx.x] = lred[0] + lred[1] + lred[2] + lred[3];
+    }
 }
 
-__global__ __launch_bounds__(1024) void tile_top_kernel(uint64_t *bsum, int nb, ScanArgs a)
+__global__ __launch_bounds__(1024) void tile_top_kernel(uint64_t *bsum, uint32_t *lsum, int nb, ScanArgs a)
 {
     __shared__ uint64_t wt[16];
+    __shared__ uint32_t lwt[16];
     __shared__ uint64_t carry_s;
+    __shared__ uint32_t lcarry_s;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    if (threadIdx.x == 0) carry_s = 0;
+    if (threadIdx.x == 0) {
+        carry_s = 0;
+        lcarry_s = 0;
+    }
     __syncthreads();
     for (int c0 = 0; c0 < nb; c0 += 1024) {
         const int idx = c0 + threadIdx.x;
         const uint64_t x = idx < nb ? bsum[idx] : 0;
+        const uint32_t lx = idx < nb ? lsum[idx] : 0u;
         uint64_t inc = x;
 #pragma unroll
         for (int o = 1; o < kWave; o <<= 1) {
             const uint64_t y = __shfl_up(inc, o, kWave);
             if (lane >= o) inc += y;
         }
-        if (lane == kWave - 1) wt[w] = inc;
+        const uint32_t linc = wave_incl_scan(lx);
+        if (lane == kWave - 1) {
+            wt[w] = inc;
+            lwt[w] = linc;
+        }
         __syncthreads();
         uint64_t before = carry_s, tot = 0;
+        uint32_t lbefore = lcarry_s, ltot = 0;
         for (int q = 0; q < 16; ++q) {
-            if (q < w) before += wt[q];
+            if (q < w) {
+                before += wt[q];
+                lbefore += lwt[q];
+            }
             tot += wt[q];
+            ltot += lwt[q];
         }
-        if (idx < nb) bsum[idx] = before + inc - x;
+        if (idx < nb) {
+            bsum[idx] = before + inc - x;
+            lsum[idx] = lbefore + linc - lx;
+        }
         __syncthreads();
-        if (threadIdx.x == 0) carry_s += tot;
+        if (threadIdx.x == 0) {
+            carry_s += tot;
+            lcarry_s += ltot;
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) finish_scan(a, carry_s);
+    if (threadIdx.x == 0) {
+        finish_scan(a, carry_s);
+        *a.long_n = lcarry_s;
+    }
 }
 
-__global__ __launch_bounds__(kBlock) void tile_apply_kernel(const uint64_t *bsum, ScanArgs a)
+__global__ __launch_bounds__(kBlock) void tile_apply_kernel(const uint64_t *bsum, const uint32_t *lsum, ScanArgs a)
 {
     __shared__ uint32_t wl[kWaves];
     if (blockIdx.x == gridDim.x - 1) slot_block_scan(a.slot_btot, a.slot_nb, wl);
@@ -233,6 +288,9 @@ __global__ __launch_bounds__(kBlock) void tile_apply_kernel(const uint64_t *bsum
     uint32_t tot;
     const uint32_t pre = block_scan(v, wl, tot);
     if (t < a.n_tiles) write_range(a, t, bsum[blockIdx.x] + pre, v);
+    const uint32_t lf = is_long(v);
+    const uint32_t lpre = lsum[blockIdx.x] + block_scan(lf, wl, tot);
+    if (lf) a.long_list[lpre] = (uint32_t)t;
 }
 
 // ------------------------------------------------------- count and scatter
@@ -407,29 +465,34 @@ __global__ __launch_bounds__(kBinBlock) void bin_scatter_kernel(BinArgs a, const
 // does not matter), and each entry's final place is its bucket's start plus
 // the number of entries of its bucket with a smaller C.  Buckets hold a few
 // entries on average, so the ranking costs a few comparisons per entry (and
-// stays correct, if quadratic, for any distribution).  Ranges of up to
-// kSortLds entries are bucketed in LDS, longer ones in the same range of a
+// stays correct, if quadratic, for any distribution).  Ranges that fit the
+// LDS capacity CAP are bucketed in LDS, longer ones in the same range of a
 // second global buffer.
-constexpr int kSortLds = 2048;     // entries bucketed in LDS
-constexpr int kSortBlock = 512;    // threads per tile (the per-tile phases are latency-bound:
-                                   // 512 measured 0.037 ms at 500k / 8x8 tiles, 256 0.045,
-                                   // 1024 0.053)
-constexpr int kSortWaves = kSortBlock / kWave;
-constexpr int kSortRegs = kSortLds / kSortBlock;  // entries per thread held in registers
+// Two instances: ranges of up to 2560 entries with 512 threads per tile (the
+// per-tile phases are latency-bound: 512 measured 0.037 ms at 500k / 8x8
+// tiles, 256 0.045, 1024 0.053; four workgroups of 37 KB LDS per CU), and
+// longer ranges, up to 7168 in LDS (two workgroups of 74 KB per CU), with
+// 1024 threads in a second launch.  Each launch leaves the other's tiles.
+constexpr int kSortShortBlock = 512;
+constexpr int kSortLong = 7168, kSortLongBlock = 1024;
+constexpr int kSortLongGrid = 512;  // two workgroups per CU
 constexpr int kBinBits = 11;
 constexpr int kBins = 1 << kBinBits;
 
+template <int CAP, int BLOCK>
 struct SortLds {
-    uint2 e[kSortLds];          // (key, index) in bucket order
+    uint2 e[CAP];               // (key, index) in bucket order
     uint32_t start[kBins];      // bucket starts
     uint32_t cur[kBins];        // counts, then cursors (bucket ends at the last step)
-    uint32_t wl[kSortWaves];
-    uint32_t red[4 * kSortWaves];
+    uint32_t wl[BLOCK / kWave];
+    uint32_t red[4 * (BLOCK / kWave)];
 };
 
-// exclusive scan over a block of kSortBlock threads; returns the block total
+// exclusive scan over a block of BLOCK threads; returns the block total
+template <int BLOCK>
 __device__ __forceinline__ uint32_t sort_block_scan(uint32_t x, uint32_t *lds, uint32_t &total)
 {
+    constexpr int kSortWaves = BLOCK / kWave;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const uint32_t inc = wave_incl_scan(x);
     if (lane == kWave - 1) lds[w] = inc;
@@ -448,16 +511,17 @@ __device__ __forceinline__ uint32_t sort_block_scan(uint32_t x, uint32_t *lds, u
 
 __device__ __forceinline__ int bit_length(uint32_t x) { return x ? 32 - __clz((int)x) : 0; }
 
-// Entry j of the range for a thread's slot q: j = tid + q * kBlock.
-__global__ __launch_bounds__(kSortBlock) void tile_sort_kernel(const uint2 *ranges, int n_tiles, const uint2 *ent,
-                                                           uint2 *tmp, uint32_t *tval)
+// Sorts one tile's range rg (len >= 1) with the whole block; entry j of the
+// range sits in a thread's slot q, j = tid + q * BLOCK.  Writes S from its
+// first steps on: a caller that sorts several tiles puts a barrier between
+// them.
+template <int CAP, int BLOCK>
+__device__ __forceinline__ void sort_tile(SortLds<CAP, BLOCK> &S, uint2 rg, const uint2 *ent, uint2 *tmp,
+                                          uint32_t *tval)
 {
-    __shared__ SortLds S;
-    const int tile = blockIdx.x;
-    if (tile >= n_tiles) return;
-    const uint2 rg = ranges[tile];
+    constexpr int kSortLds = CAP, kSortBlock = BLOCK, kSortWaves = BLOCK / kWave;
+    constexpr int kSortRegs = CAP / BLOCK;  // entries per thread held in registers
     const int len = (int)(rg.y - rg.x);
-    if (len <= 0) return;
     const uint2 *g = ent + rg.x;
     const int tid = threadIdx.x;
     if (len == 1) {
@@ -540,7 +604,7 @@ __global__ __launch_bounds__(kSortBlock) void tile_sort_kernel(const uint2 *rang
             sum += c[q];
         }
         uint32_t tot;
-        uint32_t pre = sort_block_scan(sum, S.wl, tot);
+        uint32_t pre = sort_block_scan<BLOCK>(sum, S.wl, tot);
 #pragma unroll
         for (int q = 0; q < B; ++q) {
             S.start[tid * B + q] = pre;
@@ -586,6 +650,40 @@ __global__ __launch_bounds__(kSortBlock) void tile_sort_kernel(const uint2 *rang
     }
 }
 
+// One workgroup per tile, leaving the long tiles (is_long of the tile's
+// count, the tile scan's rule for its list) to the second launch.
+template <int CAP, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void tile_sort_kernel(const uint2 *ranges, const uint32_t *tile_cnt, int n_tiles,
+                                                          const uint2 *ent, uint2 *tmp, uint32_t *tval)
+{
+    static_assert(CAP >= kSortShort, "short ranges are sorted in LDS");
+    __shared__ SortLds<CAP, BLOCK> S;
+    const int tile = blockIdx.x;
+    if (tile >= n_tiles) return;
+    const uint32_t cnt = tile_cnt[tile];  // (both loads in flight together)
+    const uint2 rg = ranges[tile];
+    if (is_long(cnt) || rg.y <= rg.x) return;
+    sort_tile<CAP, BLOCK>(S, rg, ent, tmp, tval);
+}
+
+// The tile scan's list of long tiles.  Few tiles are that long and they
+// cluster in the image, so a fixed grid takes them round-robin from the list
+// (a workgroup per tile, with this much LDS each, would spend more on being
+// dispatched for every short or empty tile than on the long ones).
+template <int CAP, int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8, 8))) void tile_sort_long_kernel(
+    const uint2 *ranges, const uint2 *ent, uint2 *tmp, uint32_t *tval, const uint32_t *list, const uint32_t *n_list)
+{
+    __shared__ SortLds<CAP, BLOCK> S;
+    const uint32_t n_long = *n_list;
+    for (uint32_t i = blockIdx.x; i < n_long; i += gridDim.x) {
+        const uint2 rg = ranges[list[i]];
+        if (rg.y <= rg.x) continue;  // (a range clamped away by an overflowed step)
+        sort_tile<CAP, BLOCK>(S, rg, ent, tmp, tval);
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 bool tile_scan_makes_items(int n_tiles) { return n_tiles <= kTileScanSelfMax; }
@@ -593,10 +691,12 @@ bool tile_scan_makes_items(int n_tiles) { return n_tiles <= kTileScanSelfMax; }
 hipError_t launch_tile_scan(const uint32_t *tile_cnt, int n_tiles, uint2 *ranges, uint32_t *cursor,
                             uint32_t capacity, uint64_t *total, uint32_t *m_out, uint32_t *flags,
                             uint32_t *skipped, unsigned long long *need, uint32_t *slot_btot, int64_t slot_nb,
-                            uint64_t *bsum, size_t bsum_words, const TileItems *it, hipStream_t s)
+                            uint64_t *bsum, size_t bsum_words, const TileItems *it, const LongTiles &lt,
+                            hipStream_t s)
 {
     ScanArgs a{tile_cnt, n_tiles, ranges, cursor, capacity, total, m_out, flags, skipped, need, slot_btot, slot_nb,
-               0u, nullptr, nullptr, nullptr, 0u, nullptr, nullptr};
+               0u, nullptr, nullptr, nullptr, 0u, nullptr, nullptr, lt.list, lt.n, lt.bsum};
+    if (!lt.list || !lt.n) return hipErrorInvalidValue;
     const int nb = (n_tiles + kBlock - 1) / kBlock;
     if (n_tiles <= kTileScanSelfMax) {
         if (it && it->split > 0) {
@@ -612,10 +712,10 @@ hipError_t launch_tile_scan(const uint32_t *tile_cnt, int n_tiles, uint2 *ranges
         return hipGetLastError();
     }
     if (it) return hipErrorInvalidValue;  // the three-launch scan makes no items
-    if (!bsum || (size_t)nb > bsum_words) return hipErrorInvalidValue;
-    tile_sum_kernel<<<nb, kBlock, 0, s>>>(tile_cnt, n_tiles, bsum);
-    tile_top_kernel<<<1, 1024, 0, s>>>(bsum, nb, a);
-    tile_apply_kernel<<<nb, kBlock, 0, s>>>(bsum, a);
+    if (!bsum || (size_t)nb > bsum_words || !lt.bsum || (size_t)nb > lt.bsum_words) return hipErrorInvalidValue;
+    tile_sum_kernel<<<nb, kBlock, 0, s>>>(tile_cnt, n_tiles, bsum, lt.bsum);
+    tile_top_kernel<<<1, 1024, 0, s>>>(bsum, lt.bsum, nb, a);
+    tile_apply_kernel<<<nb, kBlock, 0, s>>>(bsum, lt.bsum, a);
     return hipGetLastError();
 }
 
@@ -667,11 +767,15 @@ hipError_t launch_bin_scatter(int n, int V, const uint32_t *cnt, const uint2 *re
     return hipGetLastError();
 }
 
-hipError_t launch_tile_sort(const uint2 *ranges, int n_tiles, const uint2 *ent, uint2 *tmp, uint32_t *tval,
-                            hipStream_t s)
+hipError_t launch_tile_sort(const uint2 *ranges, const uint32_t *tile_cnt, int n_tiles, const uint2 *ent, uint2 *tmp,
+                            uint32_t *tval, const LongTiles &lt, hipStream_t s)
 {
     if (n_tiles <= 0) return hipSuccess;
-    tile_sort_kernel<<<n_tiles, kSortBlock, 0, s>>>(ranges, n_tiles, ent, tmp, tval);
+    tile_sort_kernel<kSortShort, kSortShortBlock><<<n_tiles, kSortShortBlock, 0, s>>>(ranges, tile_cnt, n_tiles, ent,
+                                                                                       tmp, tval);
+    const int g = std::min(n_tiles, kSortLongGrid);
+    tile_sort_long_kernel<kSortLong, kSortLongBlock><<<g, kSortLongBlock, 0, s>>>(ranges, ent, tmp, tval, lt.list,
+                                                                                   lt.n);
     return hipGetLastError();
 }
 

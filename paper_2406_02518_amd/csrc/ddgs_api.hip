@@ -397,6 +397,8 @@ ddgs_status ensure_static(ddgs_ctx *c)
     DDGS_TRY(ensure_t(c, "tile_bsum", std::max(1, (c->n_tiles + 255) / 256), &tb));
     DDGS_TRY(ensure_t(c, "slot_btot", std::max<int64_t>(1, (int64_t)c->views_h.size() * slot_blocks(n)), &u));
     DDGS_TRY(ensure_t(c, "ranges", std::max(1, c->n_tiles), &u2));
+    DDGS_TRY(ensure_t(c, "long_tiles", std::max(1, c->n_tiles), &u));
+    DDGS_TRY(ensure_t(c, "long_bsum", std::max(1, (c->n_tiles + 255) / 256), &u));
     DDGS_TRY(ensure_t(c, "qkey", std::max(1, c->n_tiles), &u));
     DDGS_TRY(ensure_t(c, "qval", std::max(1, c->n_tiles), &u));
     DDGS_TRY(ensure_t(c, "qkey2", std::max(1, c->n_tiles), &u));
@@ -477,7 +479,8 @@ void stage_end(ddgs_ctx *c, int i)
 // ddgs_check, which clears them), [4], [5] work-queue counters,
 // [6] work items, [7] captured replays whose updates were skipped since the
 // last ddgs_check, [8..9] u64 scratch total, [10..11] u64 largest entry total
-// of a captured replay since the last ddgs_check
+// of a captured replay since the last ddgs_check, [12] the number of tiles
+// the tile scan listed for the tile sort's long-range launch
 uint64_t *total_ptr(ddgs_ctx *c) { return (uint64_t *)buf<uint32_t>(c, "scalars"); }
 uint32_t *mdev_ptr(ddgs_ctx *c) { return buf<uint32_t>(c, "scalars") + 2; }
 uint32_t *flags_ptr(ddgs_ctx *c) { return buf<uint32_t>(c, "scalars") + 3; }
@@ -486,6 +489,11 @@ unsigned long long *need_ptr(ddgs_ctx *c) { return (unsigned long long *)(buf<ui
 uint32_t *counter_ptr(ddgs_ctx *c) { return buf<uint32_t>(c, "scalars") + 4; }
 uint64_t *sort_total_ptr(ddgs_ctx *c) { return (uint64_t *)(buf<uint32_t>(c, "scalars") + 8); }
 uint32_t *n_items_ptr(ddgs_ctx *c) { return buf<uint32_t>(c, "scalars") + 6; }
+LongTiles long_tiles(ddgs_ctx *c)
+{
+    return LongTiles{buf<uint32_t>(c, "long_tiles"), buf<uint32_t>(c, "scalars") + 12, buf<uint32_t>(c, "long_bsum"),
+                     c->bufs["long_bsum"].bytes / sizeof(uint32_t)};
+}
 SortWs sort_ws(ddgs_ctx *c)
 {
     return SortWs{buf<uint32_t>(c, "sort_counts"), buf<uint32_t>(c, "sort_tot"), buf<uint64_t>(c, "sort_bsum"),
@@ -557,7 +565,7 @@ ddgs_status enqueue_front(ddgs_ctx *c, uint32_t capacity, bool captured)
                                 buf<uint32_t>(c, "cursor"), capacity, total_ptr(c), mdev_ptr(c), flags_ptr(c),
                                 captured ? skipped_ptr(c) : nullptr, captured ? need_ptr(c) : nullptr,
                                 buf<uint32_t>(c, "slot_btot"), (int64_t)V * slot_blocks(m.n), buf<uint64_t>(c, "tile_bsum"),
-                                c->bufs["tile_bsum"].bytes / sizeof(uint64_t), fold ? &ti : nullptr, s));
+                                c->bufs["tile_bsum"].bytes / sizeof(uint64_t), fold ? &ti : nullptr, long_tiles(c), s));
     // the sort stage is timed in two parts: a plain render reads the entry
     // total back to the host between them, and that round trip is not device work
     stage_end(c, DDGS_T_SORT);
@@ -579,8 +587,8 @@ ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, float *images)
                                   buf<uint32_t>(c, "bin_mat"), buf<uint32_t>(c, "cursor"), (uint32_t)cap, ent, s));
     if (c->keep_unsorted)
         HIP_TRY(c, launch_copy_u32((uint32_t *)buf<uint2>(c, "ubin"), (const uint32_t *)ent, nullptr, 2 * cap, s));
-    HIP_TRY(c, launch_tile_sort(buf<uint2>(c, "ranges"), c->n_tiles, ent, buf<uint2>(c, "bin_tmp"),
-                                buf<uint32_t>(c, "tval"), s));
+    HIP_TRY(c, launch_tile_sort(buf<uint2>(c, "ranges"), buf<uint32_t>(c, "tile_cnt"), c->n_tiles, ent,
+                                buf<uint2>(c, "bin_tmp"), buf<uint32_t>(c, "tval"), long_tiles(c), s));
     c->queue = nullptr;
     const int split = effective_split(c);
     c->max_items = (int)max_items_for(c, cap);

@@ -346,11 +346,20 @@ struct TileItems {
     uint32_t max_items;
     uint32_t *n_items, *counter;
 };
+// The tiles too long for the per-tile sort's first launch, listed by the
+// tile scan for its second: list [n_tiles], n (one word: the list's length),
+// bsum [bsum_words >= ceil(n_tiles / 256)] per-block counts of the
+// three-launch scan.
+struct LongTiles {
+    uint32_t *list, *n, *bsum;
+    size_t bsum_words;
+};
 bool tile_scan_makes_items(int n_tiles);
 hipError_t launch_tile_scan(const uint32_t *tile_cnt, int n_tiles, uint2 *ranges, uint32_t *cursor,
                             uint32_t capacity, uint64_t *total, uint32_t *m_out, uint32_t *flags,
                             uint32_t *skipped, unsigned long long *need, uint32_t *slot_btot, int64_t slot_nb,
-                            uint64_t *bsum, size_t bsum_words, const TileItems *items, hipStream_t s);
+                            uint64_t *bsum, size_t bsum_words, const TileItems *items, const LongTiles &lt,
+                            hipStream_t s);
 // Per-tile entry counts without global atomics: groups of Gaussians of each
 // view count their entries per tile in LDS into a count matrix mat
 // ([bin_matrix_words] u32), whose columns are then scanned into every
@@ -367,11 +376,12 @@ hipError_t launch_bin_scatter(int n, int V, const uint32_t *cnt, const uint2 *re
                               const uint32_t *zkey, const ViewDev *views, int n_tiles, int max_view_tiles,
                               const uint32_t *mat, const uint32_t *start, uint32_t capacity, uint2 *out,
                               hipStream_t s);
-// One workgroup per tile sorts its range of ent by (depth key, index) and
-// writes the indices to tval; tmp (same layout as ent) is scratch for ranges
-// longer than the LDS holds.
-hipError_t launch_tile_sort(const uint2 *ranges, int n_tiles, const uint2 *ent, uint2 *tmp, uint32_t *tval,
-                            hipStream_t s);
+// Sorts every tile's range of ent by (depth key, index) and writes the
+// indices to tval; tmp (same layout as ent) is scratch for ranges longer than
+// the LDS holds.  tile_cnt and lt are those the tile scan of the same step
+// used (the long tiles go to a second launch).
+hipError_t launch_tile_sort(const uint2 *ranges, const uint32_t *tile_cnt, int n_tiles, const uint2 *ent, uint2 *tmp,
+                            uint32_t *tval, const LongTiles &lt, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_zero_u64(uint64_t *p, hipStream_t s);
 hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, const uint32_t *n_dev, int64_t n_cap,

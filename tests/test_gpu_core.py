@@ -176,11 +176,13 @@ def test_tile_lists_bit_exact(R):
 
 
 def test_tile_lists_long_ranges_and_depth_ties(R):
-    """Tile ranges longer than the per-tile sort holds in LDS (sorted from
-    global memory in chunks) and runs of Gaussians with identical depth keys
-    (ordered by index): the sorted lists equal the host construction, for
-    both tile shapes that reach such lengths, and the image the oracle's."""
-    n = 7000
+    """Tile ranges of every length class of the per-tile sort (up to 2560
+    entries, 2560 to 7168 bucketed in LDS by the long-range launch, beyond
+    7168 bucketed in global memory) and runs of Gaussians with identical
+    depth keys (ordered by index): the sorted lists equal the host
+    construction, for both tile shapes that reach such lengths, and the image
+    the oracle's."""
+    n = 10000
     sc = synth.random_scene(31, n, k=8, L=1, extent=6.0, std_range=(1.5, 3.0), alpha_range=(0.01, 0.03))
     # groups of four Gaussians share one mean (equal depth keys, index order decides)
     sc.mean[:, 1:2000:4] = sc.mean[:, 0:2000:4]
@@ -198,7 +200,8 @@ def test_tile_lists_long_ranges_and_depth_ties(R):
             sv = R.debug(binding.DBG_TILE_VALS, np.uint32, M)
             base = R.debug(binding.DBG_TILE_BASE, np.int32, 2)
             ranges = R.debug(binding.DBG_RANGES, np.uint32, int(base[-1]) * 2).reshape(-1, 2)
-            assert (ranges[:, 1] - ranges[:, 0]).max() > 4096
+            lens = ranges[:, 1].astype(np.int64) - ranges[:, 0]
+            assert lens.max() > 7168 and ((lens > 2560) & (lens <= 7168)).any()
             _, zk, cnt, rects = _records(R, 1, n)
             ek, ev = expected_tile_lists(zk.ravel(), cnt.ravel(), rects.reshape(-1, 4), base,
                                          [(v.W + tw - 1) // tw], n, _masks(R, 1, n).ravel())
