@@ -411,7 +411,7 @@ __global__ __launch_bounds__(kBlock) void prep_project_kernel(ModelDev m, GaussC
 // ------------------------------------------------------------ backward chain
 
 template <int KMAX, int L>
-__global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void project_bwd_kernel(ProjBwdArgs a)
 {
     constexpr int KL = L * (L + 2);
     const int n = a.m.n, k = a.m.k;
@@ -439,34 +439,50 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
     float cw[6];
 #pragma unroll
     for (int q = 0; q < 6; ++q) cw[q] = a.gc.cov[q * n + ii];
-    // basis-gradient operands staged in LDS (used at the end): the features
-    // are read here, with the other parameters, so that their latency overlaps
-    // (the B operands of the basis contraction -- features in the matrix
-    // cores' layout, lane l holding feature t 16 + l % 16 of the wave's
-    // Gaussian 4 s + l / 16 for step s -- are read here, with the other
-    // parameters, and used at the end; sU holds each wave's U rows and then
-    // its tile, s_done counts the block's finished waves)
+    // values used after the view loop, read here so that their latency
+    // overlaps the slot reads (stores in the loop keep the compiler from
+    // moving them up)
+    const float al = a.gc.alpha[ii];
+    float quat0[4] = {1.f, 0.f, 0.f, 0.f}, lsc0[3] = {0.f, 0.f, 0.f}, st0[3] = {0.f, 0.f, 0.f};
+    if (a.per_gaussian) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) quat0[q] = a.m.quat[q * n + ii];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) lsc0[q] = a.m.log_scale[q * n + ii];
+    }
+    if (a.st_grad) {
+        st0[0] = a.st_grad[ii];
+        st0[1] = a.st_cnt[ii];
+        st0[2] = a.st_rad[ii];
+    }
+    // The basis contraction's B operands (the features) are read here, with
+    // the other parameters, so that their latency overlaps: one coalesced row
+    // per feature (lane = Gaussian), moved into the matrix cores' layout
+    // through the wave's LDS rows at the end.  sU holds each wave's U rows and
+    // then its tile, sF its features, s_done counts the block's finished
+    // waves; sbi and sBd hold the bases for the feature gradients.
     constexpr int NTILE = (KMAX + 15) / 16, NCOL = NTILE * 16;
     constexpr int NW = kBlock / kWave;
     static_assert(16 * NCOL <= kWave * 17, "a wave tile fits in the wave's U rows");
     __shared__ float sU[NW][kWave][17];
+    __shared__ float sF[NW][kWave][NCOL + 1];
+    __shared__ float sbi[KMAX], sBd[KL * KMAX];
     __shared__ uint32_t s_done;
     const int w = threadIdx.x / kWave;
     const int ri = lane & 15, kk = lane >> 4;
-    float fb[kWave / 4][NTILE];
+    if (threadIdx.x == 0) s_done = 0;
+    stage_bases<KMAX, L>(a.m, sbi, sBd);
+    __syncthreads();
+    float fc[NCOL];
+#pragma unroll
+    for (int j = 0; j < NCOL; ++j) fc[j] = 0.0f;
     if (a.bpart) {
-        if (threadIdx.x == 0) s_done = 0;
-        __syncthreads();
-        const int g0 = blockIdx.x * kBlock + w * kWave;  // the wave's first Gaussian
 #pragma unroll
-        for (int st = 0; st < kWave / 4; ++st)
-#pragma unroll
-            for (int t = 0; t < NTILE; ++t) {
-                const int g = g0 + 4 * st + kk, j = t * 16 + ri;
-                // (a clamped index for lanes past the end or past k; masked below)
-                const float x = a.m.feat[(size_t)min(j, k - 1) * n + min(g, n - 1)];
-                fb[st][t] = (g < n && j < k && a.per_gaussian) ? x : 0.0f;
-            }
+        for (int j = 0; j < NCOL; ++j) {
+            // (a clamped row past k; masked below)
+            const float x = a.m.feat[(size_t)min(j, k - 1) * n + ii];
+            fc[j] = (valid && j < k && a.per_gaussian) ? x : 0.0f;
+        }
     }
     float h[KL];
 #pragma unroll
@@ -546,7 +562,6 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
             // dL/dA00 = -alpha/2 sum q dx^2, dL/dA01 (both off-diagonal
             // entries together) = -alpha sum q dx dy, dL/dA11 = -alpha/2 sum q dy^2.
             {
-                const float al = a.gc.alpha[ii];
                 const float m1x = g7[0], m1y = g7[1];
                 g7[0] = al * (g.A00 * m1x + g.A01 * m1y);
                 g7[1] = al * (g.A01 * m1x + g.A11 * m1y);
@@ -668,13 +683,13 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
         }
     }
     if (valid && a.st_grad && !(a.skip && (*a.skip & 1u))) {
-        a.st_grad[i] += st_grad;
-        a.st_cnt[i] += st_cnt;
-        a.st_rad[i] = fmaxf(a.st_rad[i], st_rad);
+        a.st_grad[i] = st0[0] + st_grad;
+        a.st_cnt[i] = st0[1] + st_cnt;
+        a.st_rad[i] = fmaxf(st0[2], st_rad);
     }
     if (valid && a.per_gaussian) {
         // Sigma = M M^T, M = Rq diag(s): dL/dM = 2 GSw M
-        float qw = a.m.quat[i], qx = a.m.quat[n + i], qy = a.m.quat[2 * n + i], qz = a.m.quat[3 * n + i];
+        float qw = quat0[0], qx = quat0[1], qy = quat0[2], qz = quat0[3];
         const float qnorm = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
         const float iq = 1.0f / qnorm;
         qw *= iq; qx *= iq; qy *= iq; qz *= iq;
@@ -682,7 +697,7 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
         quat_rot(qw, qx, qy, qz, Rq);
         float s[3];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) s[q] = expf(a.m.log_scale[q * n + i]);
+        for (int q = 0; q < 3; ++q) s[q] = expf(lsc0[q]);
         const float Gs[9] = {GSw[0], GSw[1], GSw[2], GSw[1], GSw[3], GSw[4], GSw[2], GSw[4], GSw[5]};
         float GR[9];
         float gls[3];
@@ -722,17 +737,19 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
             for (int q = 0; q < 3; ++q) a.dlog_scale[q * n + i] = gls[q];
         }
         if (a.dopacity) {
-            const float al = a.gc.alpha[i];
             a.dopacity[i] = galpha * al * (1.0f - al);
         }
         if (a.dfeat) {
-            if (!is_dir) {
-                for (int j = 0; j < k; ++j) a.dfeat[(size_t)j * n + i] = zsum * a.m.b_iso[j];
-            } else {
-                for (int j = 0; j < k; ++j) {
-                    float acc = a.m.entangled ? zsum * a.m.b_iso[j] : 0.0f;
+            // (bases from LDS: sbi[j] = b_iso[j], sBd[r KMAX + j] = B_dir[r][j])
+            const bool iso_term = !is_dir || a.m.entangled;
 #pragma unroll
-                    for (int r = 0; r < KL; ++r) acc += a.m.B_dir[r * k + j] * u[r];
+            for (int j = 0; j < KMAX; ++j) {
+                if (j < k) {
+                    float acc = iso_term ? zsum * sbi[j] : 0.0f;
+                    if (is_dir) {
+#pragma unroll
+                        for (int r = 0; r < KL; ++r) acc += sBd[r * KMAX + j] * u[r];
+                    }
                     a.dfeat[(size_t)j * n + i] = acc;
                 }
             }
@@ -760,6 +777,8 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
         }
 #pragma unroll
         for (int r = 0; r < 16; ++r) sU[w][lane][r] = row[r];
+#pragma unroll
+        for (int j = 0; j < NCOL; ++j) sF[w][lane][j] = fc[j];
         // (other lanes of this wave read these rows next)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -775,7 +794,7 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(ProjBwdArgs a)
             const float av = sU[w][g][ri];
 #pragma unroll
             for (int t = 0; t < NTILE; ++t)
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, fb[st][t], acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, sF[w][g][t * 16 + ri], acc[t], 0, 0, 0);
         }
         // the wave's tile replaces its U rows (all its operand reads are done)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
