@@ -138,7 +138,8 @@ __global__ __launch_bounds__(kBlock) void tile_scan_self_kernel(ScanArgs a)
     // this block's
     uint64_t c = 0;
     uint32_t ci = 0, cl = 0;
-#pragma unroll 4
+    // (unrolled so that the loads of up to 16 rounds are in flight together)
+#pragma unroll 16
     for (int t = threadIdx.x; t < base; t += kBlock) {
         const uint32_t x = a.tile_cnt[t];
         c += x;

@@ -412,8 +412,7 @@ ddgs_status ensure_static(ddgs_ctx *c)
         DDGS_TRY(ensure_t(c, "scalars", 16, &u));
         if (u && u != prev) HIP_TRY(c, hipMemsetAsync(u, 0, sizeof(uint32_t) * 16, c->stream));
     }
-    const int64_t n_waves = ((n + 255) / 256) * 4;
-    DDGS_TRY(ensure_t(c, "pose_part", (size_t)std::max<int64_t>(1, V * n_waves * 9), &f));
+    DDGS_TRY(ensure_t(c, "pose_part", (size_t)std::max<int64_t>(1, V * slot_blocks(n) * 9), &f));
     DDGS_TRY(ensure_t(c, "basis_part", basis_part_floats((int)std::max<int64_t>(1, n)), &f));
     double *d;
     DDGS_TRY(ensure_t(c, "loss_part", loss_part_doubles((int)V, c->max_view_pix, c->loss_tiles), &d));
@@ -707,9 +706,9 @@ ddgs_status enqueue_backward(ddgs_ctx *c, const float *dL, const ddgs_grads *g, 
     pa.st_rad = c->st_rad;
     pa.skip = captured ? flags_ptr(c) : nullptr;
     HIP_TRY(c, launch_project_bwd(pa, s));
-    const int n_waves = ((n + 255) / 256) * 4;
+    // (one pose partial per projection block)
     HIP_TRY(c, launch_grad_final(pa.m, buf<float>(c, "basis_part"), g->db_iso, g->dB_dir, buf<ViewDev>(c, "views"), V,
-                                 n_waves, buf<float>(c, "pose_part"), g->dpose, s));
+                                 (int)slot_blocks(n), buf<float>(c, "pose_part"), g->dpose, s));
     stage_end(c, DDGS_T_PROJECT_BWD);
     return DDGS_OK;
 }

@@ -258,8 +258,8 @@ hipError_t launch_prep_project(const ModelDev &m, const GaussCache &gc, const Vi
                                const RenderOpts &o, const ProjOut &po, hipStream_t s);
 
 // Backward of the projection: sums each (view, Gaussian)'s gradient slots,
-// applies the chain rule to the parameters, and writes per-wave pose partials
-// [V][n_waves][9] and, per block of kSlotBlock Gaussians, its share of the
+// applies the chain rule to the parameters, and writes, per block of
+// kSlotBlock Gaussians, pose partials [V][9][blocks] and its share of the
 // basis gradients: the 16 x NCOL tile U F^T over the block's Gaussians, with
 // row r < k_L of U the direction terms of a directional Gaussian and row 15
 // the isotropic logit's gradient (NCOL = 16 or 32 columns of features).
@@ -275,7 +275,7 @@ struct ProjBwdArgs {
     const float4 *slot;
     float *dmean, *dquat, *dlog_scale, *dopacity, *dfeat;  // NULL: skip
     float *bpart;       // [blocks][16][NCOL] basis tiles (NULL: skip)
-    float *pose_part;   // [V][n_waves][9]
+    float *pose_part;   // [V][9][blocks]
     int per_gaussian;   // 0: pose only
     uint32_t slot_cap;  // number of gradient slots (entries beyond are ignored)
     // densification statistics, [n] each (NULL: off): norm of the 2D-mean
@@ -291,7 +291,7 @@ size_t basis_part_floats(int n);
 // FP64 sums of the basis tiles (when db or dB) and of the pose partials (when
 // dpose), in one launch
 hipError_t launch_grad_final(const ModelDev &m, const float *bpart, float *db, float *dB, const ViewDev *views,
-                             int V, int n_waves, const float *ppart, float *dpose, hipStream_t s);
+                             int V, int n_parts, const float *ppart, float *dpose, hipStream_t s);
 
 // sort.hip
 constexpr int kScanTile = 4096;

@@ -13,6 +13,7 @@ namespace ddgs {
 namespace {
 
 constexpr int kBlock = 256;
+static_assert(kBlock == kSlotBlock, "one projection block per block of the slot numbering");
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
@@ -419,8 +420,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     const bool valid = i < n;
     const int ii = valid ? i : 0;
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    const int n_waves = gridDim.x * (kBlock / kWave);
     const bool is_dir = ii >= a.m.n_iso;
     const int nd = n - a.m.n_iso, id = ii - a.m.n_iso;
     // the next view's slot count and first slot, read one view ahead (the
@@ -467,6 +466,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     __shared__ float sU[NW][kWave][17];
     __shared__ float sF[NW][kWave][NCOL + 1];
     __shared__ float sbi[KMAX], sBd[KL * KMAX];
+    __shared__ float sP[2][NW][9];
     __shared__ uint32_t s_done;
     const int w = threadIdx.x / kWave;
     const int ri = lane & 15, kk = lane >> 4;
@@ -674,12 +674,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                 pose[8] = R[6] * grx + R[7] * gry + R[8] * grz;
             }
         }
-        // per-wave pose partials (deterministic, reduced in FP64 later)
+        // per-block pose partials, component-major (deterministic: the
+        // waves' sums added in a fixed order; reduced in FP64 later).  Two
+        // buffers: no wave gets two views ahead of the barrier.
 #pragma unroll
         for (int q = 0; q < 9; ++q) pose[q] = wave_sum_to_lane63(pose[q]);
         if (lane == kWave - 1) {
 #pragma unroll
-            for (int q = 0; q < 9; ++q) a.pose_part[((size_t)v * n_waves + wave) * 9 + q] = pose[q];
+            for (int q = 0; q < 9; ++q) sP[v & 1][w][q] = pose[q];
+        }
+        __syncthreads();
+        if (threadIdx.x < 9) {
+            const int q = threadIdx.x;
+            float t = sP[v & 1][0][q];
+#pragma unroll
+            for (int u = 1; u < NW; ++u) t += sP[v & 1][u][q];
+            a.pose_part[((size_t)v * 9 + q) * gridDim.x + blockIdx.x] = t;
         }
     }
     if (valid && a.st_grad && !(a.skip && (*a.skip & 1u))) {
@@ -822,7 +832,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
 // kFinalBlock-thread blocks: blocks [0, 16 NCOL) each sum one element of the
 // per-wave basis tiles (when basis gradients are wanted), the next V blocks
 // each turn one view's per-wave pose partials into (rho, omega).
-constexpr int kFinalBlock = 512;
+constexpr int kFinalBlock = 256;
 
 template <int N>
 __device__ __forceinline__ void block_sum_f64(double (&x)[N], double (*red)[N])
@@ -866,29 +876,29 @@ __device__ void basis_final_block(int o, int k, const float *part, int nwaves, f
 
 // dpose[v] = (rho, omega) from the per-wave partials: rho = sum d mu_c +
 // sum R d r; omega = sum (R mu) x d mu_c + covariance term + t x sum d mu_c.
-__device__ void pose_final_block(int v, const ViewDev *views, int n_waves, const float *part, float *dpose)
+__device__ void pose_final_block(int v, const ViewDev *views, int n_parts, const float *part, float *dpose)
 {
     double s[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) s[q] = 0.0;
-    // two partials' loads in flight per thread
+    // component-major partials ([9][n_parts] per view): coalesced rows, the
+    // loads of two partials in flight per thread
+    const float *p = part + (size_t)v * 9 * n_parts;
     int w = threadIdx.x;
-    for (; w + kFinalBlock < n_waves; w += 2 * kFinalBlock) {
-        const float *p0 = part + ((size_t)v * n_waves + w) * 9;
-        const float *p1 = p0 + (size_t)kFinalBlock * 9;
-        float x0[9], x1[9];
+    for (; w + kFinalBlock < n_parts; w += 2 * kFinalBlock) {
+        float x[2][9];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            x0[q] = p0[q];
-            x1[q] = p1[q];
-        }
+        for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int q = 0; q < 9; ++q) s[q] += (double)x0[q] + (double)x1[q];
+            for (int q = 0; q < 9; ++q) x[u][q] = p[(size_t)q * n_parts + w + u * kFinalBlock];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int q = 0; q < 9; ++q) s[q] += (double)x[u][q];
     }
-    if (w < n_waves) {
-        const float *p = part + ((size_t)v * n_waves + w) * 9;
+    if (w < n_parts) {
 #pragma unroll
-        for (int q = 0; q < 9; ++q) s[q] += (double)p[q];
+        for (int q = 0; q < 9; ++q) s[q] += (double)p[(size_t)q * n_parts + w];
     }
     __shared__ double red[kFinalBlock / kWave][9];
     block_sum_f64<9>(s, red);
@@ -908,11 +918,11 @@ __device__ void pose_final_block(int v, const ViewDev *views, int n_waves, const
 template <int KMAX, int L>
 __global__ __launch_bounds__(kFinalBlock) void grad_final_kernel(int k, const float *bpart, int bwaves, int nbasis,
                                                                  float *db, float *dB, const ViewDev *views,
-                                                                 int n_waves, const float *ppart, float *dpose)
+                                                                 int n_parts, const float *ppart, float *dpose)
 {
     const int o = blockIdx.x;
     if (o < nbasis) basis_final_block<KMAX, L>(o, k, bpart, bwaves, db, dB);
-    else pose_final_block(o - nbasis, views, n_waves, ppart, dpose);
+    else pose_final_block(o - nbasis, views, n_parts, ppart, dpose);
 }
 
 template <typename F>
@@ -967,7 +977,7 @@ hipError_t launch_project_bwd(const ProjBwdArgs &a, hipStream_t s)
 size_t basis_part_floats(int n) { return (size_t)std::max<int64_t>(1, slot_blocks(n)) * 16 * 32; }
 
 hipError_t launch_grad_final(const ModelDev &m, const float *bpart, float *db, float *dB, const ViewDev *views,
-                             int V, int n_waves, const float *ppart, float *dpose, hipStream_t s)
+                             int V, int n_parts, const float *ppart, float *dpose, hipStream_t s)
 {
     const bool basis = (db || dB) && m.n > 0;
     const int nview = dpose ? V : 0;
@@ -978,7 +988,7 @@ hipError_t launch_grad_final(const ModelDev &m, const float *bpart, float *db, f
         const int nbasis = basis ? 16 * NCOL : 0;
         if (nbasis + nview > 0)
             grad_final_kernel<KK, LL><<<nbasis + nview, kFinalBlock, 0, s>>>(m.k, bpart, bwaves, nbasis, db, dB,
-                                                                            views, n_waves, ppart, dpose);
+                                                                            views, n_parts, ppart, dpose);
         return hipGetLastError();
     });
 }

@@ -294,11 +294,29 @@ __global__ __launch_bounds__(TW *TH) void merge_kernel(RasterArgs a)
     const int ty = lt / V.ntx, tx = lt - ty * V.ntx;
     const int px = tx * TW + tid % TW, py = ty * TH + tid / TW;
     const uint32_t base = a.item_base[tile], cnt = a.item_cnt[tile];
+    const uint32_t last = a.ranges[tile].y;
+    // items past the item capacity do not exist (overflowed step)
+    const uint32_t mi = (uint32_t)a.max_items;
+    const uint32_t kend = base < mi ? min(cnt, mi - base) : 0u;
+    float2 *const pp = a.part + (size_t)base * NT + tid;
     float C = 0.0f, T = 1.0f;
-    for (uint32_t k = 0; k < cnt && base + k < (uint32_t)a.max_items; ++k) {
-        float2 *slot = a.part + (size_t)(base + k) * NT + tid;
-        const float2 ck = *slot;
-        *slot = make_float2(C, T);
+    // four items' partials read together (each item's place then receives
+    // the (C, T) in front of it)
+    uint32_t k = 0;
+    for (; k + 4u <= kend; k += 4u) {
+        float2 ck[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ck[u] = pp[(size_t)(k + u) * NT];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            pp[(size_t)(k + u) * NT] = make_float2(C, T);
+            C = __fmaf_rn(T, ck[u].x, C);
+            T = __fmul_rn(T, ck[u].y);
+        }
+    }
+    for (; k < kend; ++k) {
+        const float2 ck = pp[(size_t)k * NT];
+        pp[(size_t)k * NT] = make_float2(C, T);
         C = __fmaf_rn(T, ck.x, C);
         T = __fmul_rn(T, ck.y);
     }
@@ -306,7 +324,7 @@ __global__ __launch_bounds__(TW *TH) void merge_kernel(RasterArgs a)
         const size_t p = (size_t)V.pix_base + (size_t)py * V.W + px;
         a.img[p] = C;
         a.img_saved[p] = C;
-        a.nlast[p] = a.ranges[tile].y;
+        a.nlast[p] = last;
     }
 }
 
