@@ -279,6 +279,147 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
     }
 }
 
+// Forward of 8 x 8 tiles in chunks (the tuned shape) with an entry list per
+// 4 x 4 quadrant.  An entry's cut-off ellipse usually covers a part of the
+// tile, and a wave that runs it on all 64 pixels spends most lanes on misses.
+// Here lane l covers pixel (4 (q % 2) + r % 4, 4 (q / 2) + r / 4) of the tile
+// (q = l / 16, r = l % 16); each batch of entries is listed per quadrant
+// whose pixel centres the ellipse's bounding box reaches (half-widths
+// kappa sqrt(Sigma_xx), kappa sqrt(Sigma_yy) of Sigma = A^-1, widened by
+// 0.1 %, far above the rounding of the per-pixel test), and the wave runs the
+// longest list, the lanes of each quadrant taking their own list's entries
+// in depth order (shorter lists are padded with a record that no pixel
+// reaches).  An entry left out of a quadrant's list misses all its pixels,
+// where the update is an exact no-op, so the images and chunk results equal
+// the unculled kernel's bit for bit.  The chunk results are stored by pixel
+// (row-major in the tile), as the other kernels index them.
+__global__ __launch_bounds__(kWave) void raster_fwd_quad_kernel(RasterArgs a)
+{
+    constexpr int TW = 8, TH = 8, NT = TW * TH, NUL = NT;
+    static_assert(NT == kWave, "one wave per tile");
+    // records by entry, s1 first: entry e's pair sits at byte 16 e (s1) and
+    // 16 e + S0OFF (s0), so that one register with two immediate offsets
+    // reads it; the lists hold these byte places
+    constexpr uint32_t S0OFF = 16u * (NT + 1);
+    __shared__ float4 s10[2 * (NT + 1)];
+    float4 *const s1 = s10;
+    float4 *const s0 = s10 + (NT + 1);
+    // per quadrant: the byte places of its entries (rows four words apart in
+    // bank, so that the four quadrants' reads of one step do not collide)
+    __shared__ __align__(16) uint32_t ql[4][NT + 4];
+    __shared__ int sh_item;
+    const int tid = threadIdx.x;
+    const int qd = tid >> 4, qr = tid & 15;
+    const int lx = 4 * (qd & 1) + (qr & 3), ly = 4 * (qd >> 1) + (qr >> 2);
+    const float k2s = __fmul_rn(a.o.kappa2, kExpScale);
+    const float smax = a.o.sigma_max;
+    const float kw = a.o.kappa * 1.001f;
+    if (tid == 0) {
+        // the padding record: d^T A d = -(dx^2 + dy^2) ~ -2e36 < any cut-off
+        s0[NUL] = make_float4(1e18f, 1e18f, -1.0f, 0.0f);
+        s1[NUL] = make_float4(-1.0f, 0.0f, 0.0f, 0.0f);
+    }
+    const char *const srec = reinterpret_cast<const char *>(s10);
+    int iter = 0;
+    for (;;) {
+        const int it = next_item(a, iter, &sh_item);
+        const Item I = resolve_item(a, it);
+        if (I.tile < 0) break;
+        const int v = view_of_tile(a.views, a.V, I.tile);
+        const ViewDev &V = a.views[v];
+        const int lt = I.tile - V.tile_base;
+        const int ty = lt / V.ntx, tx = lt - ty * V.ntx;
+        const int px = tx * TW + lx, py = ty * TH + ly;
+        const bool inside = px < V.W && py < V.H;
+        const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+        const float tx0 = (float)(tx * TW), ty0 = (float)(ty * TH);
+        const size_t vbase = (size_t)v * a.n;
+        float T = 1.0f, C = 0.0f;
+        const float k2e = inside ? k2s : kLaneOff;
+        auto entry = [&](const float4 r0, const float4 r1, auto clamp_c) {
+            constexpr bool CLAMP = decltype(clamp_c)::value;
+            const float dx = __fsub_rn(fpx, r0.x), dy = __fsub_rn(fpy, r0.y);
+            const float ex = falloff_exponent(dx, dy, r0.z, r0.w, r1.x);
+            const bool hit = ex >= k2e;
+            if (wave_any_mask(hit) != 0ull) {
+                asm volatile("");
+                const float G = hit ? __builtin_amdgcn_exp2f(ex) : 0.0f;
+                float s = __fmul_rn(r1.y, G), om;
+                if constexpr (CLAMP) {
+                    s = clamp_opacity(s, smax);
+                    om = __fsub_rn(1.0f, s);
+                } else {
+                    om = one_minus_alpha_g(r1.y, G);
+                }
+                C = __fmaf_rn(r1.z, __fmul_rn(s, T), C);
+                T = __fmul_rn(T, om);
+            }
+        };
+        // the longest list in steps of four: four places of the lane's list,
+        // then their records
+        const uint32_t *const myl = &ql[qd][0];
+        auto run_lists = [&](int nmax, auto clamp_c) {
+            for (int i0 = 0; i0 < nmax; i0 += 4) {
+                const uint4 ev = *reinterpret_cast<const uint4 *>(myl + i0);
+                const uint32_t e[4] = {ev.x, ev.y, ev.z, ev.w};
+                float4 r0[4], r1[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    r1[u] = *reinterpret_cast<const float4 *>(srec + e[u]);
+                    r0[u] = *reinterpret_cast<const float4 *>(srec + e[u] + S0OFF);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) entry(r0[u], r1[u], clamp_c);
+            }
+        };
+        for (uint32_t b0 = I.b; b0 < I.e; b0 += NT) {
+            __syncthreads();
+            const uint32_t j = b0 + tid;
+            bool over = false;  // an opacity above sigma_max / 2 in this batch
+            uint32_t qm = 0u;   // quadrants this lane's entry reaches
+            if (j < I.e) {
+                const uint32_t gid = min(a.tval[j], (uint32_t)a.n - 1u);
+                const size_t idx = vbase + gid;
+                float4 r0 = a.rec[4 * idx], r1 = a.rec[4 * idx + 1];
+                over = r1.y > 0.5f * smax;
+                // bounding box of the cut-off ellipse against the quadrants'
+                // pixel-centre ranges [0.5, 3.5] and [4.5, 7.5] of the tile
+                const float idet = 1.0f / (r0.z * r1.x - r0.w * r0.w);
+                const float hx = kw * sqrtf(r1.x * idet), hy = kw * sqrtf(r0.z * idet);
+                const float ux = r0.x - tx0, uy = r0.y - ty0;
+                const bool xa = ux - hx <= 3.5f && ux + hx >= 0.5f, xb = ux - hx <= 7.5f && ux + hx >= 4.5f;
+                const bool ya = uy - hy <= 3.5f && uy + hy >= 0.5f, yb = uy - hy <= 7.5f && uy + hy >= 4.5f;
+                qm = (xa && ya ? 1u : 0u) | (xb && ya ? 2u : 0u) | (xa && yb ? 4u : 0u) | (xb && yb ? 8u : 0u);
+                scale_conic(r0, r1);
+                s0[tid] = r0;
+                s1[tid] = r1;
+            }
+            // lists: every place first holds the padding record, then each
+            // quadrant's entries in batch order
+            reinterpret_cast<uint4 *>(&ql[qd][4 * qr])[0] = make_uint4(16u * NUL, 16u * NUL, 16u * NUL, 16u * NUL);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            int nmax = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool in = (qm >> q) & 1u;
+                const uint64_t b = wave_any_mask(in);
+                if (in) {
+                    const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
+                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+                    ql[q][pos] = 16u * (uint32_t)tid;
+                }
+                nmax = max(nmax, (int)__popcll(b));
+            }
+            const bool clamp = __syncthreads_or(over);
+            if (clamp) run_lists(nmax, std::true_type{});
+            else run_lists(nmax, std::false_type{});
+        }
+        a.part[(size_t)it * NT + ly * TW + lx] = make_float2(C, T);
+    }
+}
+
 // Split mode: folds each tile's chunk results in depth order with the over
 // operator, writes the images, and replaces every chunk's (C, T) by the
 // (C, T) accumulated in front of it (what the chunk's backward starts from).
@@ -795,6 +936,7 @@ hipError_t fwd_inst(const RasterArgs &a, int pb, hipStream_t s)
     if (grid > 0) {
         const bool cnt = a.pair_counts != nullptr;
         if (a.split && cnt) raster_fwd_kernel<TW, TH, true, true><<<grid, TW * TH, 0, s>>>(a);
+        else if (a.split && TW == 8 && TH == 8) raster_fwd_quad_kernel<<<grid, TW * TH, 0, s>>>(a);
         else if (a.split) raster_fwd_kernel<TW, TH, true, false><<<grid, TW * TH, 0, s>>>(a);
         else if (cnt) raster_fwd_kernel<TW, TH, false, true><<<grid, TW * TH, 0, s>>>(a);
         else raster_fwd_kernel<TW, TH, false, false><<<grid, TW * TH, 0, s>>>(a);
