@@ -319,6 +319,32 @@ def test_forward_is_tile_and_schedule_invariant(R):
         R.set_options(tile_w=16, tile_h=16, persistent=0, split=256)
 
 
+def test_quadrant_forward_equals_the_unculled_forward(R):
+    """8 x 8 tiles in chunks run the forward with an entry list per 4 x 4
+    quadrant; the pair-counting build of the same render runs every entry on
+    every pixel.  An entry left out of a quadrant's list misses all its pixels
+    (an exact no-op), so the images are bit-identical: views whose sizes are
+    not multiples of 8, opacities on both sides of sigma_max / 2 (both
+    compositing paths), several chunk sizes."""
+    sc = synth.random_scene(41, 3000, k=8, L=1, extent=5.0, std_range=(0.2, 1.5), alpha_range=(0.05, 0.99))
+    views = [synth.view(90, 70, 0.3, 1000.0, 600.0, 20.0), synth.view(37, 53, 0.5, 1000.0, 550.0, 200.0)]
+    R.set_scene(sc)
+    R.set_views(views)
+    try:
+        for sp in (7, 64, 256):
+            R.set_options(tile_w=8, tile_h=8, split=sp)
+            img = R.render().cpu().numpy()
+            binding.ddgs_debug_count_pairs(R.ctx, 1)
+            try:
+                full = R.render().cpu().numpy()
+            finally:
+                binding.ddgs_debug_count_pairs(R.ctx, 0)
+            np.testing.assert_array_equal(img, full)
+            assert np.abs(img).max() > 0
+    finally:
+        R.set_options(tile_w=16, tile_h=16, split=256)
+
+
 def test_batched_views_equal_single_views(R):
     c = synth.config("C4", scale=0.05)
     views = c.views[:5]
