@@ -330,7 +330,7 @@ ddgs_status prepare_views(ddgs_ctx *c)
         pix += (int64_t)h.W * h.H;
         maxp = std::max<int64_t>(maxp, (int64_t)h.W * h.H);
         c->loss_tile_base_h[v] = (int32_t)ltiles;
-        ltiles += (int64_t)((h.W + 15) / 16) * ((h.H + 15) / 16);
+        ltiles += (int64_t)((h.W + kLossTileW - 1) / kLossTileW) * ((h.H + kLossTileH - 1) / kLossTileH);
     }
     c->loss_tile_base_h[V] = (int32_t)ltiles;
     if (tiles >= (int64_t)1 << 30 || ltiles >= (int64_t)1 << 30)

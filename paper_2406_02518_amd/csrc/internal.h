@@ -512,6 +512,8 @@ hipError_t launch_rads_draws(const RadsVol &v, const uint64_t *cdf, const uint64
 hipError_t launch_knn3(const float *pts, int64_t N, float *ls, hipStream_t s);
 
 // loss.hip
+// SSIM output tile (pixels): one workgroup of kLossTileW x kLossTileH threads
+constexpr int kLossTileW = 32, kLossTileH = 32;
 struct LossArgs {
     const ViewDev *views;
     int V;
@@ -522,7 +524,7 @@ struct LossArgs {
     float *grad;       // image layout (may be NULL)
     double *part;      // scratch
     float *maps;       // scratch, 3 * total_pix floats (SSIM)
-    int loss_tiles;    // SSIM: total 16x16 tiles
+    int loss_tiles;    // SSIM: total output tiles
     const int32_t *loss_tile_base; // [V+1]
     int64_t max_view_pix;          // largest W*H among the views
 };

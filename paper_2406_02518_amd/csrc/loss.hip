@@ -4,8 +4,9 @@
 // zero padding), 1 - NCC for pose scoring, and a linear loss whose gradient
 // is a fixed weight image.  Scalar reductions accumulate in FP64.
 //
-// SSIM: each 16x16 output tile stages its 26x26 input halo in LDS and
-// filters separably (rows, then columns).  The gradient needs the adjoint of
+// SSIM: each output tile (kLossTileW x kLossTileH) stages its input halo
+// (5 pixels wider on every side) in LDS and filters separably (rows, then
+// columns).  The gradient needs the adjoint of
 // the windowed means, which for a symmetric window with zero padding is the
 // same windowed sum applied to the per-pixel partial derivatives; a second
 // kernel filters those three maps the same way.
@@ -15,10 +16,11 @@ namespace ddgs {
 
 namespace {
 
-constexpr int kTS = 16;            // output tile edge
-constexpr int kR = 5;              // window radius
-constexpr int kHalo = kTS + 2 * kR;  // 26
-constexpr int kBlock = kTS * kTS;
+constexpr int kTW = kLossTileW, kTH = kLossTileH;  // output tile
+constexpr int kR = 5;                               // window radius
+constexpr int kHaloW = kTW + 2 * kR, kHaloH = kTH + 2 * kR;
+constexpr int kBlock = kTW * kTH;
+constexpr int kBlockWaves = kBlock / kWave;
 
 struct Window { float w[11]; };
 
@@ -33,8 +35,9 @@ __device__ __forceinline__ int tile_view(const int32_t *base, int V, int t)
     return lo;
 }
 
-template <int NQ>
-__device__ __forceinline__ void block_sum_d(double (&x)[NQ], double *red /* [4][NQ] */)
+// (NW waves; red holds NW x NQ doubles)
+template <int NQ, int NW>
+__device__ __forceinline__ void block_sum_d(double (&x)[NQ], double *red)
 {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
@@ -50,33 +53,38 @@ __device__ __forceinline__ void block_sum_d(double (&x)[NQ], double *red /* [4][
     __syncthreads();
     if (threadIdx.x == 0)
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) x[q] = red[q] + red[NQ + q] + red[2 * NQ + q] + red[3 * NQ + q];
+        for (int q = 0; q < NQ; ++q) {
+            double t = red[q];
+#pragma unroll
+            for (int u = 1; u < NW; ++u) t += red[u * NQ + q];
+            x[q] = t;
+        }
 }
 
 // 5 windowed moments per pixel: mean x, mean y, mean x^2, mean y^2, mean xy
 __global__ __launch_bounds__(kBlock) void ssim_fwd_kernel(LossArgs a, Window win)
 {
-    __shared__ float sx[kHalo][kHalo + 1], sy[kHalo][kHalo + 1];
-    __shared__ float hs[5][kHalo][kTS + 1];
-    __shared__ double red[4 * 2];
+    __shared__ float sx[kHaloH][kHaloW + 1], sy[kHaloH][kHaloW + 1];
+    __shared__ float hs[5][kHaloH][kTW + 1];
+    __shared__ double red[kBlockWaves * 2];
     const int t = blockIdx.x;
     const int v = tile_view(a.loss_tile_base, a.V, t);
     const ViewDev &V = a.views[v];
-    const int ntx = (V.W + kTS - 1) / kTS;
+    const int ntx = (V.W + kTW - 1) / kTW;
     const int lt = t - a.loss_tile_base[v];
     const int ty = lt / ntx, tx = lt - ty * ntx;
-    const int ox = tx * kTS - kR, oy = ty * kTS - kR;
+    const int ox = tx * kTW - kR, oy = ty * kTH - kR;
     const float *x = a.img + V.pix_base, *y = a.target + V.pix_base;
-    for (int q = threadIdx.x; q < kHalo * kHalo; q += kBlock) {
-        const int r = q / kHalo, c = q % kHalo;
+    for (int q = threadIdx.x; q < kHaloH * kHaloW; q += kBlock) {
+        const int r = q / kHaloW, c = q % kHaloW;
         const int gx = ox + c, gy = oy + r;
         const bool in = gx >= 0 && gx < V.W && gy >= 0 && gy < V.H;
         sx[r][c] = in ? x[(size_t)gy * V.W + gx] : 0.0f;
         sy[r][c] = in ? y[(size_t)gy * V.W + gx] : 0.0f;
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < kHalo * kTS; q += kBlock) {
-        const int r = q / kTS, c = q % kTS;
+    for (int q = threadIdx.x; q < kHaloH * kTW; q += kBlock) {
+        const int r = q / kTW, c = q % kTW;
         float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f;
 #pragma unroll
         for (int d = 0; d < 11; ++d) {
@@ -86,8 +94,8 @@ __global__ __launch_bounds__(kBlock) void ssim_fwd_kernel(LossArgs a, Window win
         hs[0][r][c] = m0; hs[1][r][c] = m1; hs[2][r][c] = m2; hs[3][r][c] = m3; hs[4][r][c] = m4;
     }
     __syncthreads();
-    const int lx = threadIdx.x % kTS, ly = threadIdx.x / kTS;
-    const int gx = tx * kTS + lx, gy = ty * kTS + ly;
+    const int lx = threadIdx.x % kTW, ly = threadIdx.x / kTW;
+    const int gx = tx * kTW + lx, gy = ty * kTH + ly;
     double part[2] = {0.0, 0.0};
     if (gx < V.W && gy < V.H) {
         float mo[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
@@ -110,7 +118,7 @@ __global__ __launch_bounds__(kBlock) void ssim_fwd_kernel(LossArgs a, Window win
         a.maps[a.total_pix + p] = -s * B1 * iD;                                 // d s / d mean x^2
         a.maps[2 * a.total_pix + p] = 2.0f * A1 * iD;                           // d s / d mean xy
     }
-    block_sum_d<2>(part, red);
+    block_sum_d<2, kBlockWaves>(part, red);
     if (threadIdx.x == 0) {
         a.part[2 * (size_t)t] = part[0];
         a.part[2 * (size_t)t + 1] = part[1];
@@ -118,17 +126,17 @@ __global__ __launch_bounds__(kBlock) void ssim_fwd_kernel(LossArgs a, Window win
 }
 
 // Loss of view v from the per-tile partial sums of the forward (one block of
-// 256 threads; FP64 sums in a fixed order).
+// kBlock threads; FP64 sums in a fixed order).
 __device__ void ssim_final_view(const LossArgs &a, int v)
 {
     const int t0 = a.loss_tile_base[v], t1 = a.loss_tile_base[v + 1];
     double x[2] = {0.0, 0.0};
-    for (int t = t0 + threadIdx.x; t < t1; t += 256) {
+    for (int t = t0 + threadIdx.x; t < t1; t += kBlock) {
         x[0] += a.part[2 * (size_t)t];
         x[1] += a.part[2 * (size_t)t + 1];
     }
-    __shared__ double red[4 * 2];
-    block_sum_d<2>(x, red);
+    __shared__ double red[kBlockWaves * 2];
+    block_sum_d<2, kBlockWaves>(x, red);
     if (threadIdx.x == 0 && a.loss_out) {
         const ViewDev &V = a.views[v];
         const double P = (double)V.W * (double)V.H;
@@ -138,20 +146,20 @@ __device__ void ssim_final_view(const LossArgs &a, int v)
 
 __global__ __launch_bounds__(kBlock) void ssim_bwd_kernel(LossArgs a, Window win)
 {
-    __shared__ float sm[3][kHalo][kHalo + 1];
-    __shared__ float hs[3][kHalo][kTS + 1];
+    __shared__ float sm[3][kHaloH][kHaloW + 1];
+    __shared__ float hs[3][kHaloH][kTW + 1];
     const int t = blockIdx.x;
     // the forward's partial sums are complete: the first V blocks also
     // finish the views' loss values (every view has at least one tile)
     if (t < a.V) ssim_final_view(a, t);
     const int v = tile_view(a.loss_tile_base, a.V, t);
     const ViewDev &V = a.views[v];
-    const int ntx = (V.W + kTS - 1) / kTS;
+    const int ntx = (V.W + kTW - 1) / kTW;
     const int lt = t - a.loss_tile_base[v];
     const int ty = lt / ntx, tx = lt - ty * ntx;
-    const int ox = tx * kTS - kR, oy = ty * kTS - kR;
-    for (int q = threadIdx.x; q < kHalo * kHalo; q += kBlock) {
-        const int r = q / kHalo, c = q % kHalo;
+    const int ox = tx * kTW - kR, oy = ty * kTH - kR;
+    for (int q = threadIdx.x; q < kHaloH * kHaloW; q += kBlock) {
+        const int r = q / kHaloW, c = q % kHaloW;
         const int gx = ox + c, gy = oy + r;
         const bool in = gx >= 0 && gx < V.W && gy >= 0 && gy < V.H;
         const size_t p = (size_t)V.pix_base + (size_t)gy * V.W + gx;
@@ -159,8 +167,8 @@ __global__ __launch_bounds__(kBlock) void ssim_bwd_kernel(LossArgs a, Window win
         for (int m = 0; m < 3; ++m) sm[m][r][c] = in ? a.maps[m * a.total_pix + p] : 0.0f;
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < kHalo * kTS; q += kBlock) {
-        const int r = q / kTS, c = q % kTS;
+    for (int q = threadIdx.x; q < kHaloH * kTW; q += kBlock) {
+        const int r = q / kTW, c = q % kTW;
         float m0 = 0.f, m1 = 0.f, m2 = 0.f;
 #pragma unroll
         for (int d = 0; d < 11; ++d) {
@@ -171,8 +179,8 @@ __global__ __launch_bounds__(kBlock) void ssim_bwd_kernel(LossArgs a, Window win
         hs[0][r][c] = m0; hs[1][r][c] = m1; hs[2][r][c] = m2;
     }
     __syncthreads();
-    const int lx = threadIdx.x % kTS, ly = threadIdx.x / kTS;
-    const int gx = tx * kTS + lx, gy = ty * kTS + ly;
+    const int lx = threadIdx.x % kTW, ly = threadIdx.x / kTW;
+    const int gx = tx * kTW + lx, gy = ty * kTH + ly;
     if (gx >= V.W || gy >= V.H) return;
     float f0 = 0.f, f1 = 0.f, f2 = 0.f;
 #pragma unroll
@@ -189,7 +197,7 @@ __global__ __launch_bounds__(kBlock) void ssim_bwd_kernel(LossArgs a, Window win
     a.grad[p] = ((1.0f - a.lambda) * sg - a.lambda * (f0 + 2.0f * xv * f1 + yv * f2)) / P;
 }
 
-__global__ __launch_bounds__(256) void ssim_final_kernel(LossArgs a) { ssim_final_view(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void ssim_final_kernel(LossArgs a) { ssim_final_view(a, blockIdx.x); }
 
 // ------------------------------------------------------------------- NCC
 
@@ -207,7 +215,7 @@ __global__ __launch_bounds__(256) void ncc_stats_kernel(LossArgs a, int nchunks)
         s[0] += x; s[1] += y; s[2] += x * x; s[3] += y * y; s[4] += x * y;
     }
     __shared__ double red[4 * 5];
-    block_sum_d<5>(s, red);
+    block_sum_d<5, 4>(s, red);
     if (threadIdx.x == 0)
 #pragma unroll
         for (int q = 0; q < 5; ++q) a.part[((size_t)v * nchunks + blockIdx.x) * 5 + q] = s[q];
@@ -224,7 +232,7 @@ __global__ __launch_bounds__(256) void ncc_final_kernel(LossArgs a, int nchunks,
 #pragma unroll
         for (int q = 0; q < 5; ++q) s[q] += a.part[((size_t)v * nchunks + c) * 5 + q];
     __shared__ double red[4 * 5];
-    block_sum_d<5>(s, red);
+    block_sum_d<5, 4>(s, red);
     if (threadIdx.x == 0) {
         const double mx = s[0] / P, my = s[1] / P;
         const double vx = fmax(s[2] / P - mx * mx, 0.0), vy = fmax(s[3] / P - my * my, 0.0);
@@ -266,7 +274,7 @@ __global__ __launch_bounds__(256) void linear_kernel(LossArgs a, int nchunks)
         if (a.grad) a.grad[V.pix_base + p] = w;
     }
     __shared__ double red[4];
-    block_sum_d<1>(s, red);
+    block_sum_d<1, 4>(s, red);
     if (threadIdx.x == 0) a.part[(size_t)v * nchunks + blockIdx.x] = s[0];
 }
 
@@ -276,7 +284,7 @@ __global__ __launch_bounds__(256) void linear_final_kernel(LossArgs a, int nchun
     double s[1] = {0.0};
     for (int c = threadIdx.x; c < nchunks; c += 256) s[0] += a.part[(size_t)v * nchunks + c];
     __shared__ double red[4];
-    block_sum_d<1>(s, red);
+    block_sum_d<1, 4>(s, red);
     if (threadIdx.x == 0 && a.loss_out) a.loss_out[v] = (float)s[0];
 }
 
@@ -309,7 +317,7 @@ hipError_t launch_loss(int kind, const LossArgs &a, hipStream_t s)
         const Window w = make_window();
         ssim_fwd_kernel<<<a.loss_tiles, kBlock, 0, s>>>(a, w);
         if (a.grad) ssim_bwd_kernel<<<a.loss_tiles, kBlock, 0, s>>>(a, w);
-        else ssim_final_kernel<<<a.V, 256, 0, s>>>(a);
+        else ssim_final_kernel<<<a.V, kBlock, 0, s>>>(a);
         return hipGetLastError();
     }
     const int nchunks = (int)((maxP + kChunk - 1) / kChunk);
