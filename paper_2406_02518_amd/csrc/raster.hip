@@ -423,12 +423,18 @@ __global__ __launch_bounds__(kWave) void raster_fwd_quad_kernel(RasterArgs a)
 // Split mode: folds each tile's chunk results in depth order with the over
 // operator, writes the images, and replaces every chunk's (C, T) by the
 // (C, T) accumulated in front of it (what the chunk's backward starts from).
+// (several tiles per workgroup for the one-wave tiles, one per wave:
+// fewer, larger workgroups)
 template <int TW, int TH>
-__global__ __launch_bounds__(TW *TH) void merge_kernel(RasterArgs a)
+constexpr int merge_tiles_per_block() { return TW * TH >= 256 ? 1 : 256 / (TW * TH); }
+
+template <int TW, int TH>
+__global__ __launch_bounds__((TW * TH * merge_tiles_per_block<TW, TH>())) void merge_kernel(RasterArgs a)
 {
     constexpr int NT = TW * TH;
-    const int tile = blockIdx.x;
-    const int tid = threadIdx.x;
+    const int tile = blockIdx.x * merge_tiles_per_block<TW, TH>() + (int)threadIdx.x / NT;
+    if (tile >= a.n_tiles) return;
+    const int tid = threadIdx.x % NT;
     const int v = view_of_tile(a.views, a.V, tile);
     const ViewDev &V = a.views[v];
     const int lt = tile - V.tile_base;
@@ -941,7 +947,10 @@ hipError_t fwd_inst(const RasterArgs &a, int pb, hipStream_t s)
         else if (cnt) raster_fwd_kernel<TW, TH, false, true><<<grid, TW * TH, 0, s>>>(a);
         else raster_fwd_kernel<TW, TH, false, false><<<grid, TW * TH, 0, s>>>(a);
     }
-    if (a.split && a.n_tiles > 0) merge_kernel<TW, TH><<<a.n_tiles, TW * TH, 0, s>>>(a);
+    if (a.split && a.n_tiles > 0) {
+        constexpr int MTB = merge_tiles_per_block<TW, TH>();
+        merge_kernel<TW, TH><<<(a.n_tiles + MTB - 1) / MTB, TW * TH * MTB, 0, s>>>(a);
+    }
     return hipGetLastError();
 }
 
