@@ -395,7 +395,7 @@ __global__ __launch_bounds__(kBlock) void project_kernel(ModelDev m, GaussCache 
 // One view: the cache is computed, written for the backward, and used for
 // the projection straight from registers (one launch, no read-back).
 template <int KMAX, int L>
-__global__ __launch_bounds__(kBlock) void prep_project_kernel(ModelDev m, GaussCache gc, const ViewDev *views,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void prep_project_kernel(ModelDev m, GaussCache gc, const ViewDev *views,
                                                               RenderOpts o, ProjOut po)
 {
     constexpr int KL = L * (L + 2);
