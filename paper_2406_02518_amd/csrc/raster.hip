@@ -723,7 +723,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // summed by a transposing butterfly over the wave.  The vector ALU keeps the
 // per-pair compositing arithmetic; the matrix cores, which run beside it,
 // take the reductions.
-__global__ __launch_bounds__(kWave) void raster_bwd_mm_kernel(RasterArgs a)
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(5))) void raster_bwd_mm_kernel(RasterArgs a)
 {
     // entries per contraction, and entries whose records are read together
     // (two: 0.2235 ms against 0.2242 for one and 0.2242 for four, at 500k /
@@ -846,36 +846,32 @@ __global__ __launch_bounds__(kWave) void raster_bwd_mm_kernel(RasterArgs a)
                     for (int u = 0; u < PF; ++u) {
                         const int e = e4 + u;
                         const float4 r0 = R0[u], r1 = R1[u];
-                        float qq = 0.0f, t = 0.0f;
-                        if (q0 + e < cnt) {
-                            const float dx = __fsub_rn(fpx, r0.x), dy = __fsub_rn(fpy, r0.y);
-                            const float ex = falloff_exponent(dx, dy, r0.z, r0.w, r1.x);
-                            const bool hit = ex >= k2e;
-                            // lanes that miss run the same arithmetic with G = 0:
-                            // T and the tail stay as they are, q and g s T are 0
-                            if (wave_any_mask(hit) != 0ull) {
-                                const float G = hit ? __builtin_amdgcn_exp2f(ex) : 0.0f;
-                                const float sraw = __fmul_rn(r1.y, G);
-                                float s = sraw, om;
-                                if constexpr (CLAMP) {
-                                    s = clamp_opacity(sraw, smax);
-                                    om = __fsub_rn(1.0f, s);
-                                } else {
-                                    om = one_minus_alpha_g(r1.y, G);
-                                }
-                                // dL/ds = g (c T - S / (1 - s)), S the tail after this entry
-                                const float gc = g * r1.z;
-                                const float sT = __fmul_rn(s, T);
-                                Sg = __fmaf_rn(-gc, sT, Sg);
-                                const float ds = __fmaf_rn(gc, T, -(Sg * __builtin_amdgcn_rcpf(om)));
-                                qq = ds * G;
-                                if constexpr (CLAMP) qq = (sraw > smax) ? 0.0f : qq;
-                                t = g * sT;
-                                T = __fmul_rn(T, om);
-                            }
+                        // branch-free: lanes that miss (and the padding record)
+                        // run the same arithmetic with G = 0, which leaves T and
+                        // the tail as they are and makes q and g s T zero, so
+                        // the compiler may interleave the entries of the group
+                        const float dx = __fsub_rn(fpx, r0.x), dy = __fsub_rn(fpy, r0.y);
+                        const float ex = falloff_exponent(dx, dy, r0.z, r0.w, r1.x);
+                        const bool hit = ex >= k2e;
+                        const float G = hit ? __builtin_amdgcn_exp2f(ex) : 0.0f;
+                        const float sraw = __fmul_rn(r1.y, G);
+                        float s = sraw, om;
+                        if constexpr (CLAMP) {
+                            s = clamp_opacity(sraw, smax);
+                            om = __fsub_rn(1.0f, s);
+                        } else {
+                            om = one_minus_alpha_g(r1.y, G);
                         }
+                        // dL/ds = g (c T - S / (1 - s)), S the tail after this entry
+                        const float gc = g * r1.z;
+                        const float sT = __fmul_rn(s, T);
+                        Sg = __fmaf_rn(-gc, sT, Sg);
+                        const float ds = __fmaf_rn(gc, T, -(Sg * __builtin_amdgcn_rcpf(om)));
+                        float qq = ds * G;
+                        if constexpr (CLAMP) qq = (sraw > smax) ? 0.0f : qq;
+                        T = __fmul_rn(T, om);
                         aq[e][tid] = qq;
-                        tv[e] = t;
+                        tv[e] = g * sT;
                     }
                 }
                 const float tsum = wave_transpose_sum16(tv);
@@ -912,6 +908,13 @@ __global__ __launch_bounds__(kWave) void raster_bwd_mm_kernel(RasterArgs a)
                 const uint32_t at = (uint32_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
                 se[tid] = first_slot(a.slot_bofs, a.slot_nblk, v, (int)gid, place) +
                           kept_rank(__float_as_uint(r2.z), area, at);
+            } else {
+                // places past the batch's entries hold a record that no pixel
+                // reaches (d^T A d = -(dx^2 + dy^2) ~ -2e36, alpha = c = 0):
+                // every group runs all its entries without a bound check, and
+                // these contribute exact zeros
+                s0[tid] = make_float4(1e18f, 1e18f, -1.0f, 0.0f);
+                s1[tid] = make_float4(-1.0f, 0.0f, 0.0f, 0.0f);
             }
             const bool clamp = __syncthreads_or(over);
             if (clamp) run_groups(cnt, std::true_type{});
