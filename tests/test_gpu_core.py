@@ -212,6 +212,56 @@ def test_tile_lists_long_ranges_and_depth_ties(R):
         R.set_options(tile_w=16, tile_h=16, split=256)
 
 
+def test_tile_lists_many_tiles_and_long_ranges(R):
+    """More tiles than the one-launch tile scan takes (16900 tiles of 8 x 8 on
+    a 1040 x 1040 view: the three-launch scan then lists the long tiles), with
+    a cluster of large Gaussians whose tiles fall in every length class of the
+    per-tile sort (above 7168 entries, 2560 to 7168, below): the sorted lists
+    equal the host construction bit for bit and the image the oracle's."""
+    n = 7600
+    sc = synth.random_scene(37, n, k=8, L=1, extent=2.0, std_range=(2.0, 2.6), alpha_range=(0.002, 0.006))
+    v = synth.view(1040, 1040, 0.3, 1000.0, 600.0, 0.0)
+    R.set_scene(sc)
+    R.set_views([v])
+    try:
+        R.set_options(tile_w=8, tile_h=8, split=256)
+        img = R.render().cpu().numpy()
+        M = R.num_rendered()
+        sk = R.debug(binding.DBG_TILE_KEYS, np.uint32, M)
+        sv = R.debug(binding.DBG_TILE_VALS, np.uint32, M)
+        base = R.debug(binding.DBG_TILE_BASE, np.int32, 2)
+        assert int(base[-1]) == 130 * 130
+        ranges = R.debug(binding.DBG_RANGES, np.uint32, int(base[-1]) * 2).reshape(-1, 2)
+        lens = ranges[:, 1].astype(np.int64) - ranges[:, 0]
+        assert lens.max() > 7168 and ((lens > 2560) & (lens <= 7168)).any() and ((lens > 0) & (lens <= 2560)).any()
+        _, zk, cnt, rects = _records(R, 1, n)
+        masks = _masks(R, 1, n)
+        # host lists: every entry of a Gaussian's kept tiles in (depth key,
+        # index) order, then a stable sort by tile (rectangles above 32 tiles
+        # keep every tile)
+        zk, cnt, rects, masks = zk[0], cnt[0], rects[0].astype(np.int64), masks[0]
+        keys, vals = [], []
+        for i in np.lexsort((np.arange(n), zk)):
+            if cnt[i] == 0:
+                continue
+            tx0, ty0, tx1, ty1 = rects[i]
+            if (tx1 - tx0 + 1) * (ty1 - ty0 + 1) <= 32:
+                t = np.array([ty * 130 + tx for tx, ty in kept_tiles(rects[i], masks[i])], dtype=np.int64)
+            else:
+                yy, xx = np.mgrid[ty0:ty1 + 1, tx0:tx1 + 1]
+                t = (yy * 130 + xx).ravel()
+            assert len(t) == cnt[i]
+            keys.append(t)
+            vals.append(np.full(len(t), i, dtype=np.int64))
+        keys, vals = np.concatenate(keys), np.concatenate(vals)
+        o = np.argsort(keys, kind="stable")
+        np.testing.assert_array_equal(sk, keys[o].astype(np.uint32))
+        np.testing.assert_array_equal(sv, vals[o].astype(np.uint32))
+        assert rel_l2(img, ref.render(sc, [v])[0]) < 1e-4
+    finally:
+        R.set_options(tile_w=16, tile_h=16, split=256)
+
+
 # ---------------------------------------------------- radiosity override
 
 def test_radiosity_override_is_linear_and_matches_oracle(R):
