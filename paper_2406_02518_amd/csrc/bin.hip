@@ -723,8 +723,11 @@ hipError_t launch_tile_scan(const uint32_t *tile_cnt, int n_tiles, uint2 *ranges
 // Gaussians per group: at least 1024 (one per thread of the count and
 // scatter workgroups; with the XCD-ordered groups 1024 measured 0.024 ms for
 // the scatter at 500k Gaussians / 8x8 tiles against 0.036 ms for 2048), and
-// few enough groups that the count matrix stays within kMatWords words.
-constexpr int64_t kMatWords = (int64_t)8 << 20;
+// few enough groups that the count matrix stays within kMatWords words
+// (256 MB; with many views the cap sets the group size: at 1M Gaussians and
+// 96256 tiles a cap of 8M words made groups of 16k and the scatter took
+// 1.21 ms, 64M words 0.96 ms, the 64-pose batch 8.33 -> 8.10 ms per step).
+constexpr int64_t kMatWords = (int64_t)64 << 20;
 int bin_per_group(int64_t n, int64_t n_tiles)
 {
     int64_t per = 1024;
