@@ -420,12 +420,18 @@ ddgs_status ddgs_check(ddgs_ctx *ctx, uint32_t *flags);
 ddgs_status ddgs_step_report(const ddgs_ctx *ctx, int64_t *skipped_replays, int64_t *entries_needed);
 
 /* Times forward + backward (median of `repeats` after one warm-up call) on
- * the current model and views and selects the fastest raster options: first
+ * the current model and views and selects the fastest raster options.  Each
+ * candidate's kernels (projection to projection backward, as a captured step
+ * runs them) are captured into a graph of the tuner's own and replayed, so
+ * that the plain render's host round trip is not timed (on the default
+ * stream, which cannot be captured, plain render + backward calls are timed
+ * instead).  Like any ddgs_set_options call it drops a captured step;
+ * the step counters that ddgs_check reads are kept.  First
  * every tile shape (16x16, 8x8, 16x8, 32x8; the waves per tile and the LDS
  * batch follow from the shape: one pixel per lane, one staged record per
- * pixel) with split 256, 1024 and 0, one workgroup per item; then, at the
- * best shape, split 256, 1024, 2048, 4096 and 0 with persistent 0, 1, 2 and
- * 4.  Images of candidates with split 0 are bit-identical; chunked ones
+ * pixel) with split 128, 256, 1024 and 0, one workgroup per item; then, at
+ * the best shape, split 64, 128, 256, 512, 1024, 2048, 4096 and 0 with
+ * persistent 0, 1, 2 and 4.  Images of candidates with split 0 are bit-identical; chunked ones
  * differ only by rounding.  If cache_path is not NULL, a JSON cache keyed by
  * the workload signature (device architecture, Gaussian-count bucket, k, L,
  * footprint bucket -- tile entries per (view, Gaussian) at 16x16 tiles, in

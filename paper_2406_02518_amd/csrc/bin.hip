@@ -772,12 +772,13 @@ hipError_t launch_bin_scatter(int n, int V, const uint32_t *cnt, const uint2 *re
 }
 
 hipError_t launch_tile_sort(const uint2 *ranges, const uint32_t *tile_cnt, int n_tiles, const uint2 *ent, uint2 *tmp,
-                            uint32_t *tval, const LongTiles &lt, hipStream_t s)
+                            uint32_t *tval, const LongTiles &lt, int long_grid, hipStream_t s)
 {
     if (n_tiles <= 0) return hipSuccess;
     tile_sort_kernel<kSortShort, kSortShortBlock><<<n_tiles, kSortShortBlock, 0, s>>>(ranges, tile_cnt, n_tiles, ent,
                                                                                        tmp, tval);
-    const int g = std::min(n_tiles, kSortLongGrid);
+    const int g = std::min(std::min(n_tiles, kSortLongGrid), long_grid);
+    if (g <= 0) return hipGetLastError();
     tile_sort_long_kernel<kSortLong, kSortLongBlock><<<g, kSortLongBlock, 0, s>>>(ranges, ent, tmp, tval, lt.list,
                                                                                    lt.n);
     return hipGetLastError();

@@ -113,6 +113,15 @@ struct ddgs_ctx {
     int64_t last_skipped = 0, last_need = 0;  // found by the last ddgs_check
     int max_items = 0;         // work items the raster grids are sized for
     bool items_folded = false; // the tile scan wrote the work items (captured step)
+    // workgroups of the long-range tile sort: a plain render reads the number
+    // of long tiles with the entry total and launches one per long tile (none
+    // if there are none); a captured step takes twice the most that plain
+    // renders of the same Gaussian count and tile layout saw (at least 16),
+    // or the full grid when none has been seen.  Fewer workgroups than long
+    // tiles only take several each (the lists are the same).
+    int long_grid = 0;
+    int64_t long_seen = -1, long_seen_n = -1;
+    int long_seen_tiles = -1;
 
     // pinned staging of the view table uploads
     void *stage_host = nullptr;
@@ -587,7 +596,7 @@ ddgs_status enqueue_back(ddgs_ctx *c, int64_t cap, float *images)
     if (c->keep_unsorted)
         HIP_TRY(c, launch_copy_u32((uint32_t *)buf<uint2>(c, "ubin"), (const uint32_t *)ent, nullptr, 2 * cap, s));
     HIP_TRY(c, launch_tile_sort(buf<uint2>(c, "ranges"), buf<uint32_t>(c, "tile_cnt"), c->n_tiles, ent,
-                                buf<uint2>(c, "bin_tmp"), buf<uint32_t>(c, "tval"), long_tiles(c), s));
+                                buf<uint2>(c, "bin_tmp"), buf<uint32_t>(c, "tval"), long_tiles(c), c->long_grid, s));
     c->queue = nullptr;
     const int split = effective_split(c);
     c->max_items = (int)max_items_for(c, cap);
@@ -1403,16 +1412,26 @@ ddgs_status ddgs_render(ddgs_ctx *c, float *images)
     const int64_t VN = c->model.n * (int64_t)c->views_h.size();
     if (VN > 0) {
         DDGS_TRY(enqueue_front(c, 0xFFFFFFFFu, false));
-        uint32_t sc[4] = {0, 0, 0, 0};
+        // entry total ([0..1]) and number of long tiles ([12])
+        uint32_t sc[13] = {};
         HIP_TRY(c, hipMemcpyAsync(sc, total_ptr(c), sizeof(sc), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         const uint64_t total = (uint64_t)sc[0] | ((uint64_t)sc[1] << 32);
+        const int64_t n_long = sc[12];
+        if (c->long_seen_n != c->model.n || c->long_seen_tiles != c->n_tiles) c->long_seen = -1;
+        c->long_seen = std::max(c->long_seen, n_long);
+        c->long_seen_n = c->model.n;
+        c->long_seen_tiles = c->n_tiles;
+        c->long_grid = (int)std::min<int64_t>(n_long, 1 << 30);
         ddgs_status st = DDGS_OK;
         if (total >= 0xFFFFFFFFull) st = fail(c, DDGS_ERR_CAPACITY, "more than 2^32-1 tile entries");
         c->M = (int64_t)total;
         if (st == DDGS_OK && c->M > c->entry_cap) st = ensure_entries(c, c->M);
         if (st != DDGS_OK) return st;
-        DDGS_TRY(enqueue_back(c, c->entry_cap, images));
+        // (the exact total bounds the work items, so the raster grids take
+        // no more workgroups than this render can fill; the buffers keep
+        // entry_cap)
+        DDGS_TRY(enqueue_back(c, std::max<int64_t>(c->M, 1), images));
     } else {
         // no Gaussians: empty lists everywhere
         c->M = 0;
@@ -1521,6 +1540,8 @@ ddgs_status ddgs_step_capture(ddgs_ctx *c, int kind, const float *target, float 
     const bool saved_timing = c->timing;
     c->timing = false;
     HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    const bool seen = c->long_seen >= 0 && c->long_seen_n == c->model.n && c->long_seen_tiles == c->n_tiles;
+    c->long_grid = seen ? (int)std::max<int64_t>(16, std::min<int64_t>(2 * c->long_seen, 1 << 30)) : (1 << 30);
     ddgs_status st = enqueue_front(c, (uint32_t)c->step_cap, true);
     if (st == DDGS_OK) st = enqueue_back(c, c->step_cap, images);
     if (st == DDGS_OK) st = enqueue_loss(c, kind, images, target, lambda, loss_out, dL);
@@ -2048,56 +2069,126 @@ ddgs_status ddgs_autotune(ddgs_ctx *c, const char *cache_path, int repeats, floa
     TuneEntry best;
     double best_t = 1e300;
     ddgs_status st = DDGS_OK;
-    // median forward + backward time of one candidate (warm-up call first)
+    // median forward + backward time of one candidate: the kernels a captured
+    // step of these options runs (projection, binning, sort, raster, merge,
+    // backward), captured into a graph of the tuner's own and replayed, so
+    // that the host round trip of a plain render (which reads the entry total
+    // back between the scan and the scatter) does not enter the timing.  One
+    // plain render sizes the graph's capacity (twice its entries) and the
+    // long-range sort grid; one replay warms up.
+    const bool saved_timing = c->timing;
+    ddgs_options cand = base;
+    auto record = [&](std::vector<float> &ts) {
+        std::sort(ts.begin(), ts.end());
+        const double med = ts[ts.size() / 2];
+        if (med < best_t) {
+            best_t = med;
+            best.tile_w = cand.tile_w;
+            best.tile_h = cand.tile_h;
+            best.persistent = cand.persistent;
+            best.split = cand.split;
+            best.ms = med;
+        }
+    };
+    // the trial graphs update the step counters of the scalars block (flags,
+    // skipped replays, largest need) as a captured step does; what the
+    // caller's replays left there for ddgs_check is restored afterwards
+    uint32_t saved_sc[16] = {};
+    HIP_TRY(c, hipMemcpyAsync(saved_sc, buf<uint32_t>(c, "scalars"), sizeof(saved_sc), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
     auto trial = [&](int tw, int th, int pe, int sp) {
         ddgs_options o = base;
         o.tile_w = tw;
         o.tile_h = th;
         o.persistent = pe;
         o.split = sp;
+        cand = o;
         st = ddgs_set_options(c, &o);
         if (st == DDGS_OK) st = ddgs_render(c, img);
-        if (st == DDGS_OK) st = ddgs_backward(c, dL, &g);
+        if (st != DDGS_OK) return;
         std::vector<float> ts;
+        if (!c->stream) {
+            // (the default stream cannot be captured: plain render + backward)
+            st = ddgs_backward(c, dL, &g);
+            for (int r = 0; r < repeats && st == DDGS_OK; ++r) {
+                (void)hipEventRecord(e0, c->stream);
+                st = ddgs_render(c, img);
+                if (st == DDGS_OK) st = ddgs_backward(c, dL, &g);
+                (void)hipEventRecord(e1, c->stream);
+                if (hipEventSynchronize(e1) != hipSuccess) st = fail(c, DDGS_ERR_HIP, "event sync failed");
+                float t = 0.0f;
+                (void)hipEventElapsedTime(&t, e0, e1);
+                ts.push_back(t);
+            }
+        }
+        const int64_t cap = std::min<int64_t>(std::max<int64_t>(2 * c->M, 1024), 0xFFFFFFF0ll);
+        if (c->stream) st = ensure_entries(c, cap);
+        if (st != DDGS_OK || !c->stream) {
+            if (st == DDGS_OK) record(ts);
+            return;
+        }
+        c->long_grid = (int)std::max<int64_t>(16, std::min<int64_t>(2 * c->long_seen, 1 << 30));
+        c->timing = false;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            c->timing = saved_timing;
+            st = fail(c, DDGS_ERR_HIP, "tuner: hipStreamBeginCapture failed");
+            return;
+        }
+        st = enqueue_front(c, (uint32_t)cap, true);
+        if (st == DDGS_OK) st = enqueue_back(c, cap, img);
+        if (st == DDGS_OK) st = enqueue_backward(c, dL, &g, cap, true);
+        const hipError_t ec = hipStreamEndCapture(c->stream, &graph);
+        c->timing = saved_timing;
+        if (st == DDGS_OK && ec != hipSuccess)
+            st = fail(c, DDGS_ERR_HIP, std::string("tuner: hipStreamEndCapture: ") + hipGetErrorString(ec));
+        if (st == DDGS_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+            st = fail(c, DDGS_ERR_HIP, "tuner: hipGraphInstantiate failed");
+        if (st == DDGS_OK && hipGraphLaunch(exec, c->stream) != hipSuccess)
+            st = fail(c, DDGS_ERR_HIP, "tuner: hipGraphLaunch failed");
         for (int r = 0; r < repeats && st == DDGS_OK; ++r) {
             (void)hipEventRecord(e0, c->stream);
-            st = ddgs_render(c, img);
-            if (st == DDGS_OK) st = ddgs_backward(c, dL, &g);
+            if (hipGraphLaunch(exec, c->stream) != hipSuccess) st = fail(c, DDGS_ERR_HIP, "tuner: hipGraphLaunch failed");
             (void)hipEventRecord(e1, c->stream);
             if (hipEventSynchronize(e1) != hipSuccess) st = fail(c, DDGS_ERR_HIP, "event sync failed");
             float t = 0.0f;
             (void)hipEventElapsedTime(&t, e0, e1);
             ts.push_back(t);
         }
-        if (st != DDGS_OK) return;
-        std::sort(ts.begin(), ts.end());
-        const double med = ts[ts.size() / 2];
-        if (med < best_t) {
-            best_t = med;
-            best.tile_w = tw;
-            best.tile_h = th;
-            best.persistent = pe;
-            best.split = sp;
-            best.ms = med;
-        }
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (st == DDGS_OK) record(ts);
     };
     // stage 1: tile shape x a coarse chunking, one workgroup per item; stage
     // 2: at the best shape, every chunk size x the persistent grid (0: off,
     // else m x 4 (forward) and m x 2 (backward) workgroups per CU)
     const int shapes[4][2] = {{16, 16}, {8, 8}, {16, 8}, {32, 8}};
-    const int coarse[3] = {256, 1024, 0};
+    // (at 500k Gaussians, 512^2 and 8x8 tiles the captured step took 0.457,
+    // 0.453, 0.471, 0.520 ms at chunks of 64, 128, 256, 512; the 64-view
+    // 256^2 batch is fastest at 512 and above, the uneven batch at 256)
+    const int coarse[4] = {128, 256, 1024, 0};
     for (int si = 0; si < 4 && st == DDGS_OK; ++si)
-        for (int ci = 0; ci < 3 && st == DDGS_OK; ++ci) trial(shapes[si][0], shapes[si][1], 0, coarse[ci]);
-    const int splits[5] = {256, 1024, 2048, 4096, 0};
+        for (int ci = 0; ci < 4 && st == DDGS_OK; ++ci) trial(shapes[si][0], shapes[si][1], 0, coarse[ci]);
+    const int splits[8] = {64, 128, 256, 512, 1024, 2048, 4096, 0};
     const int mults[4] = {0, 1, 2, 4};
     const int tw = best.tile_w, th = best.tile_h;
-    for (int sj = 0; sj < 5 && st == DDGS_OK; ++sj)
+    for (int sj = 0; sj < 8 && st == DDGS_OK; ++sj)
         for (int mj = 0; mj < 4 && st == DDGS_OK; ++mj) {
-            const bool done = mults[mj] == 0 && (splits[sj] == 256 || splits[sj] == 1024 || splits[sj] == 0);
+            bool done = false;
+            for (int ci = 0; ci < 4; ++ci) done = done || (mults[mj] == 0 && splits[sj] == coarse[ci]);
             if (!done) trial(tw, th, mults[mj], splits[sj]);
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    {
+        uint32_t sc[16] = {};
+        HIP_TRY(c, hipMemcpyAsync(sc, buf<uint32_t>(c, "scalars"), sizeof(sc), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        for (int w : {3, 7, 10, 11}) sc[w] = saved_sc[w];
+        HIP_TRY(c, hipMemcpyAsync(buf<uint32_t>(c, "scalars"), sc, sizeof(sc), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
     ddgs_options o = base;
     if (st == DDGS_OK) {
         o.tile_w = best.tile_w;

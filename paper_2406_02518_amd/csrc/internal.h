@@ -379,9 +379,11 @@ hipError_t launch_bin_scatter(int n, int V, const uint32_t *cnt, const uint2 *re
 // Sorts every tile's range of ent by (depth key, index) and writes the
 // indices to tval; tmp (same layout as ent) is scratch for ranges longer than
 // the LDS holds.  tile_cnt and lt are those the tile scan of the same step
-// used (the long tiles go to a second launch).
+// used (the long tiles go to a second launch of at most long_grid
+// workgroups, each taking the listed tiles round-robin; none if long_grid
+// is 0, which only a caller that knows the list is empty passes).
 hipError_t launch_tile_sort(const uint2 *ranges, const uint32_t *tile_cnt, int n_tiles, const uint2 *ent, uint2 *tmp,
-                            uint32_t *tval, const LongTiles &lt, hipStream_t s);
+                            uint32_t *tval, const LongTiles &lt, int long_grid, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_zero_u64(uint64_t *p, hipStream_t s);
 hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, const uint32_t *n_dev, int64_t n_cap,

@@ -161,6 +161,33 @@ def test_capacity_overflow_flag_persists_until_checked(R):
     R.set_options(capacity=0)
 
 
+def test_autotune_keeps_unchecked_overflow(R):
+    """The tuner times each candidate as a captured graph of its own, which
+    updates the step counters as a captured step does; an overflow of the
+    caller's replays that no ddgs_check has read yet is still reported after
+    tuning, and the tuner's own replays add none."""
+    c = synth.config("C4", scale=0.05)
+    R.set_scene(c.scene)
+    R.set_views(c.views[:4])
+    target = torch.zeros(R.image_size(), device="cuda")
+    R.set_options(capacity=1000)
+    _capture(R, binding.LOSS_LINEAR, target, 0.0, binding.GRAD_NAMES)
+    binding.ddgs_step_launch(R.ctx)
+    assert binding.ddgs_autotune(R.ctx, None, 1) > 0
+    st, flags = binding.ddgs_check(R.ctx, raise_on_error=False)
+    assert st == binding.ERR_CAPACITY and flags & 1
+    assert binding.ddgs_autotune(R.ctx, None, 1) > 0
+    assert binding.ddgs_check(R.ctx, raise_on_error=False) == (binding.OK, 0)
+    # the tuned options capture and replay like any others
+    o = R.options()
+    R.set_options(capacity=0)
+    assert R.options()["split"] == o["split"]
+    plain = _plain(R, binding.LOSS_LINEAR, target, 0.0, binding.GRAD_NAMES)
+    bufs = _capture(R, binding.LOSS_LINEAR, target, 0.0, binding.GRAD_NAMES)
+    _same(_launch(R, bufs), plain)
+    R.set_options(tile_w=16, tile_h=16, persistent=0, split=256)
+
+
 def test_backward_before_render_is_a_state_error(R):
     c = synth.config("C1")
     R.set_scene(c.scene)
@@ -200,7 +227,7 @@ def test_autotune_picks_a_candidate_and_caches_it(R, tmp_path):
     assert ms > 0
     o = R.options()
     assert (o["tile_w"], o["tile_h"]) in ((16, 16), (8, 8), (16, 8), (32, 8))
-    assert o["split"] in (0, 256, 1024, 2048, 4096) and o["persistent"] in (0, 1, 2, 4)
+    assert o["split"] in (0, 64, 128, 256, 512, 1024, 2048, 4096) and o["persistent"] in (0, 1, 2, 4)
     # a different chunking changes the image only by rounding
     assert rel_l2(R.render().cpu().numpy(), before) < 1e-6
     import json
