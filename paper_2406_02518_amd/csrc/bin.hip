@@ -652,10 +652,12 @@ __device__ __forceinline__ void sort_tile(SortLds<CAP, BLOCK> &S, uint2 rg, cons
 }
 
 // One workgroup per tile, leaving the long tiles (is_long of the tile's
-// count, the tile scan's rule for its list) to the second launch.
+// count, the tile scan's rule for its list) to the second launch unless
+// take_long is set (then there is no second launch, and a long tile is
+// bucketed in global memory by this launch's workgroup).
 template <int CAP, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void tile_sort_kernel(const uint2 *ranges, const uint32_t *tile_cnt, int n_tiles,
-                                                          const uint2 *ent, uint2 *tmp, uint32_t *tval)
+                                                          const uint2 *ent, uint2 *tmp, uint32_t *tval, int take_long)
 {
     static_assert(CAP >= kSortShort, "short ranges are sorted in LDS");
     __shared__ SortLds<CAP, BLOCK> S;
@@ -663,7 +665,7 @@ __global__ __launch_bounds__(BLOCK) void tile_sort_kernel(const uint2 *ranges, c
     if (tile >= n_tiles) return;
     const uint32_t cnt = tile_cnt[tile];  // (both loads in flight together)
     const uint2 rg = ranges[tile];
-    if (is_long(cnt) || rg.y <= rg.x) return;
+    if ((is_long(cnt) && !take_long) || rg.y <= rg.x) return;
     sort_tile<CAP, BLOCK>(S, rg, ent, tmp, tval);
 }
 
@@ -775,9 +777,9 @@ hipError_t launch_tile_sort(const uint2 *ranges, const uint32_t *tile_cnt, int n
                             uint32_t *tval, const LongTiles &lt, int long_grid, hipStream_t s)
 {
     if (n_tiles <= 0) return hipSuccess;
-    tile_sort_kernel<kSortShort, kSortShortBlock><<<n_tiles, kSortShortBlock, 0, s>>>(ranges, tile_cnt, n_tiles, ent,
-                                                                                       tmp, tval);
     const int g = std::min(std::min(n_tiles, kSortLongGrid), long_grid);
+    tile_sort_kernel<kSortShort, kSortShortBlock><<<n_tiles, kSortShortBlock, 0, s>>>(ranges, tile_cnt, n_tiles, ent,
+                                                                                       tmp, tval, g <= 0 ? 1 : 0);
     if (g <= 0) return hipGetLastError();
     tile_sort_long_kernel<kSortLong, kSortLongBlock><<<g, kSortLongBlock, 0, s>>>(ranges, ent, tmp, tval, lt.list,
                                                                                    lt.n);

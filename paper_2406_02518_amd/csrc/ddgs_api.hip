@@ -114,11 +114,13 @@ struct ddgs_ctx {
     int max_items = 0;         // work items the raster grids are sized for
     bool items_folded = false; // the tile scan wrote the work items (captured step)
     // workgroups of the long-range tile sort: a plain render reads the number
-    // of long tiles with the entry total and launches one per long tile (none
-    // if there are none); a captured step takes twice the most that plain
-    // renders of the same Gaussian count and tile layout saw (at least 16),
-    // or the full grid when none has been seen.  Fewer workgroups than long
-    // tiles only take several each (the lists are the same).
+    // of long tiles with the entry total and launches one per long tile (no
+    // launch if there are none); a captured step takes twice the most that
+    // plain renders of the same Gaussian count and tile layout saw (at least
+    // 16), the full grid when none has been seen, and no second launch when
+    // they saw none (the first launch then sorts any long tile a replay
+    // has, through global memory).  Fewer workgroups than long tiles only
+    // take several each; the lists are the same either way.
     int long_grid = 0;
     int64_t long_seen = -1, long_seen_n = -1;
     int long_seen_tiles = -1;
@@ -432,6 +434,15 @@ ddgs_status ensure_static(ddgs_ctx *c)
 // Chunked work items are exact for Eq. 1 without early termination; with
 // t_min > 0 each tile is walked by one workgroup.
 int effective_split(const ddgs_ctx *c) { return c->opt.t_min > 0.0f ? 0 : std::max(0, (int)c->opt.split); }
+
+// long-range sort grid of a captured step (see ddgs_ctx::long_grid)
+int captured_long_grid(const ddgs_ctx *c)
+{
+    const bool seen = c->long_seen >= 0 && c->long_seen_n == c->model.n && c->long_seen_tiles == c->n_tiles;
+    if (!seen) return 1 << 30;
+    if (c->long_seen == 0) return 0;
+    return (int)std::max<int64_t>(16, std::min<int64_t>(2 * c->long_seen, 1 << 30));
+}
 
 int64_t max_items_for(const ddgs_ctx *c, int64_t cap)
 {
@@ -1540,8 +1551,7 @@ ddgs_status ddgs_step_capture(ddgs_ctx *c, int kind, const float *target, float 
     const bool saved_timing = c->timing;
     c->timing = false;
     HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    const bool seen = c->long_seen >= 0 && c->long_seen_n == c->model.n && c->long_seen_tiles == c->n_tiles;
-    c->long_grid = seen ? (int)std::max<int64_t>(16, std::min<int64_t>(2 * c->long_seen, 1 << 30)) : (1 << 30);
+    c->long_grid = captured_long_grid(c);
     ddgs_status st = enqueue_front(c, (uint32_t)c->step_cap, true);
     if (st == DDGS_OK) st = enqueue_back(c, c->step_cap, images);
     if (st == DDGS_OK) st = enqueue_loss(c, kind, images, target, lambda, loss_out, dL);
@@ -2127,7 +2137,7 @@ ddgs_status ddgs_autotune(ddgs_ctx *c, const char *cache_path, int repeats, floa
             if (st == DDGS_OK) record(ts);
             return;
         }
-        c->long_grid = (int)std::max<int64_t>(16, std::min<int64_t>(2 * c->long_seen, 1 << 30));
+        c->long_grid = captured_long_grid(c);
         c->timing = false;
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;

@@ -380,8 +380,9 @@ hipError_t launch_bin_scatter(int n, int V, const uint32_t *cnt, const uint2 *re
 // indices to tval; tmp (same layout as ent) is scratch for ranges longer than
 // the LDS holds.  tile_cnt and lt are those the tile scan of the same step
 // used (the long tiles go to a second launch of at most long_grid
-// workgroups, each taking the listed tiles round-robin; none if long_grid
-// is 0, which only a caller that knows the list is empty passes).
+// workgroups, each taking the listed tiles round-robin; with long_grid 0
+// there is no second launch and the first one sorts the long tiles too,
+// through global memory: meant for steps that rarely or never have any).
 hipError_t launch_tile_sort(const uint2 *ranges, const uint32_t *tile_cnt, int n_tiles, const uint2 *ent, uint2 *tmp,
                             uint32_t *tval, const LongTiles &lt, int long_grid, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);

@@ -188,6 +188,47 @@ def test_autotune_keeps_unchecked_overflow(R):
     R.set_options(tile_w=16, tile_h=16, persistent=0, split=256)
 
 
+def test_captured_step_sorts_long_tiles_it_has_not_seen(R):
+    """The per-tile sort runs in two launches (ranges up to 2560 entries, then
+    the longer ones); a captured step whose plain renders saw no long range
+    has only the first, which then sorts any long range a replay brings
+    through global memory.  Captured on a view with the Gaussians out of the
+    frame, replayed on one with ranges beyond 7168 entries: image, loss and
+    every gradient equal the plain path's bit for bit."""
+    n = 10000
+    sc = synth.random_scene(31, n, k=8, L=1, extent=6.0, std_range=(1.5, 3.0), alpha_range=(0.01, 0.03))
+    dense = synth.view(96, 80, 0.5, 1000.0, 600.0, 10.0)
+    away = synth.view(96, 80, 0.5, 1000.0, 600.0, 10.0,
+                      pose=synth.perturbed_pose(synth.azimuth_pose(10.0, 600.0), [0.0, 0.0, 0.0], [200.0, 0.0, 0.0]))
+    w = torch.from_numpy(np.random.default_rng(3).normal(size=96 * 80).astype(np.float32)).cuda()
+    R2 = binding.Renderer(0, stream=R.stream)
+    try:
+        R2.set_options(tile_w=16, tile_h=16, split=256)
+        R2.set_scene(sc)
+        R2.set_views([dense])
+        plain = _plain(R2, binding.LOSS_LINEAR, w, 0.0, binding.GRAD_NAMES)
+        M = R2.num_rendered()
+        base = R2.debug(binding.DBG_TILE_BASE, np.int32, 2)
+        ranges = R2.debug(binding.DBG_RANGES, np.uint32, int(base[-1]) * 2).reshape(-1, 2)
+        assert (ranges[:, 1].astype(np.int64) - ranges[:, 0]).max() > 7168
+    finally:
+        R2.close()
+    R.set_options(tile_w=16, tile_h=16, split=256, capacity=2 * M)
+    try:
+        R.set_scene(sc)
+        R.set_views([away])
+        with torch.cuda.stream(R.stream):
+            R.render()
+        R.stream.synchronize()
+        rg = R.debug(binding.DBG_RANGES, np.uint32, int(base[-1]) * 2).reshape(-1, 2)
+        assert (rg[:, 1].astype(np.int64) - rg[:, 0]).max() <= 2560
+        bufs = _capture(R, binding.LOSS_LINEAR, w, 0.0, binding.GRAD_NAMES)
+        R.set_views([dense])
+        _same(_launch(R, bufs), plain)
+    finally:
+        R.set_options(tile_w=16, tile_h=16, split=256, capacity=0)
+
+
 def test_backward_before_render_is_a_state_error(R):
     c = synth.config("C1")
     R.set_scene(c.scene)
