@@ -74,6 +74,8 @@ def parse():
                     help="iterations of the registration run on the 64 pose candidates (0: skip)")
     ap.add_argument("--tile", default="auto", help="WxH, or auto: the built-in autotuner picks tile shape, "
                     "scheduling and chunk size on the live inputs")
+    ap.add_argument("--split", type=int, default=None,
+                    help="chunk size with a fixed --tile (default: the library's default)")
     ap.add_argument("--workload", default="all", choices=("all", "fitting", "batched", "uneven"),
                     help="run one workload only (for per-workload profiler runs); the JSON line then carries "
                          "the fitting step only when it ran")
@@ -189,6 +191,8 @@ def main():
         copy_calibration()
         return
     fixed = None if args.tile == "auto" else tuple(int(x) for x in args.tile.split("x"))
+    fixed_opts = {} if not fixed else dict(tile_w=fixed[0], tile_h=fixed[1],
+                                           **({} if args.split is None else {"split": args.split}))
     stream = torch.cuda.Stream()
 
     run_fit = args.workload in ("all", "fitting")
@@ -202,7 +206,7 @@ def main():
         views = cfg.views
         R = binding.Renderer(0, stream=stream)
         if fixed:
-            R.set_options(tile_w=fixed[0], tile_h=fixed[1])
+            R.set_options(**fixed_opts)
         with torch.cuda.stream(stream):
             R.set_scene(cfg.extra["true_scene"])
             R.set_views(views)
@@ -434,7 +438,7 @@ def main():
         c4 = synth.config("C4")
         R4 = binding.Renderer(0, stream=stream)
         if fixed:
-            R4.set_options(tile_w=fixed[0], tile_h=fixed[1])
+            R4.set_options(**fixed_opts)
         with torch.cuda.stream(stream):
             R4.set_scene(c4.scene)
             R4.set_views([c4.extra["gt_view"]])
@@ -580,7 +584,7 @@ def main():
             R5.set_scene(c5.scene)
             R5.set_views(c5.views)
             if fixed:
-                R5.set_options(tile_w=fixed[0], tile_h=fixed[1])
+                R5.set_options(**fixed_opts)
             else:
                 binding.ddgs_autotune(R5.ctx, None, 3)
             tuned5 = R5.options()
