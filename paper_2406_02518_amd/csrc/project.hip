@@ -777,44 +777,61 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         // four tiles in a fixed order (no workgroup barrier: waves do not
         // wait for each other)
         const bool own = valid && a.per_gaussian;
-        float row[16];
+        float *tile = &sU[w][0][0];
+        if (!a.m.entangled && __builtin_amdgcn_ballot_w64(own && is_dir) == 0ull) {
+            // a wave of isotropic Gaussians only contributes z f_j to row 15
+            // (d b_iso): sixteen products per lane summed over the wave by a
+            // transposing butterfly, no operand staging (the other rows of
+            // its tile are zero)
+            const float z = own ? zsum : 0.0f;
+            for (int e = lane; e < 15 * NCOL; e += kWave) tile[e] = 0.0f;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) row[r] = 0.0f;
-        if (own && (!is_dir || a.m.entangled)) row[15] = zsum;
-        if (own && is_dir) {
+            for (int t = 0; t < NTILE; ++t) {
+                float v[16];
 #pragma unroll
-            for (int r = 0; r < KL; ++r) row[r] = u[r];
-        }
+                for (int j = 0; j < 16; ++j) v[j] = z * fc[t * 16 + j];
+                const float sum = wave_transpose_sum16(v);
+                if ((lane & 3) == 0) tile[15 * NCOL + t * 16 + (lane >> 2)] = sum;
+            }
+        } else {
+            float row[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) sU[w][lane][r] = row[r];
+            for (int r = 0; r < 16; ++r) row[r] = 0.0f;
+            if (own && (!is_dir || a.m.entangled)) row[15] = zsum;
+            if (own && is_dir) {
 #pragma unroll
-        for (int j = 0; j < NCOL; ++j) sF[w][lane][j] = fc[j];
-        // (other lanes of this wave read these rows next)
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // operand layout: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
-        // D[r][j] comes back in lane j + 16 (r / 4), item r % 4
-        floatx4 acc[NTILE];
+                for (int r = 0; r < KL; ++r) row[r] = u[r];
+            }
 #pragma unroll
-        for (int t = 0; t < NTILE; ++t) acc[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int r = 0; r < 16; ++r) sU[w][lane][r] = row[r];
 #pragma unroll
-        for (int st = 0; st < kWave / 4; ++st) {
-            const int g = 4 * st + kk;
-            const float av = sU[w][g][ri];
+            for (int j = 0; j < NCOL; ++j) sF[w][lane][j] = fc[j];
+            // (other lanes of this wave read these rows next)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // operand layout: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
+            // D[r][j] comes back in lane j + 16 (r / 4), item r % 4
+            floatx4 acc[NTILE];
+#pragma unroll
+            for (int t = 0; t < NTILE; ++t) acc[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int st = 0; st < kWave / 4; ++st) {
+                const int g = 4 * st + kk;
+                const float av = sU[w][g][ri];
+#pragma unroll
+                for (int t = 0; t < NTILE; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, sF[w][g][t * 16 + ri], acc[t], 0, 0, 0);
+            }
+            // the wave's tile replaces its U rows (all its operand reads are done)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
             for (int t = 0; t < NTILE; ++t)
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, sF[w][g][t * 16 + ri], acc[t], 0, 0, 0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) tile[(4 * kk + q) * NCOL + t * 16 + ri] = acc[t][q];
         }
-        // the wave's tile replaces its U rows (all its operand reads are done)
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        float *tile = &sU[w][0][0];
-#pragma unroll
-        for (int t = 0; t < NTILE; ++t)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) tile[(4 * kk + q) * NCOL + t * 16 + ri] = acc[t][q];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         uint32_t before = 0;
         if (lane == 0) before = atomicAdd(&s_done, 1u);
