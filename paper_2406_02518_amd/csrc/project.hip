@@ -421,6 +421,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     const int ii = valid ? i : 0;
     const int lane = threadIdx.x & (kWave - 1);
     const bool is_dir = ii >= a.m.n_iso;
+    // (block-uniform) features, feature gradients and basis tile of this
+    // block are the isotropic launch's
+    const bool iso_blk = (int)blockIdx.x < a.iso_blocks;
     const int nd = n - a.m.n_iso, id = ii - a.m.n_iso;
     // the next view's slot count and first slot, read one view ahead (the
     // first view's before the parameters, since its slot reads wait on them)
@@ -476,7 +479,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     float fc[NCOL];
 #pragma unroll
     for (int j = 0; j < NCOL; ++j) fc[j] = 0.0f;
-    if (a.bpart) {
+    if (a.bpart && !iso_blk) {
 #pragma unroll
         for (int j = 0; j < NCOL; ++j) {
             // (a clamped row past k; masked below)
@@ -688,7 +691,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
             const int q = threadIdx.x;
             float t = sP[v & 1][0][q];
 #pragma unroll
-            for (int u = 1; u < NW; ++u) t += sP[v & 1][u][q];
+            for (int wv = 1; wv < NW; ++wv) t += sP[v & 1][wv][q];
             a.pose_part[((size_t)v * 9 + q) * gridDim.x + blockIdx.x] = t;
         }
     }
@@ -749,7 +752,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         if (a.dopacity) {
             a.dopacity[i] = galpha * al * (1.0f - al);
         }
-        if (a.dfeat) {
+        if (iso_blk) a.zbuf[i] = zsum;
+        if (a.dfeat && !iso_blk) {
             // (bases from LDS: sbi[j] = b_iso[j], sBd[r KMAX + j] = B_dir[r][j])
             const bool iso_term = !is_dir || a.m.entangled;
 #pragma unroll
@@ -766,7 +770,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         }
     }
 
-    if (a.bpart) {
+    if (a.bpart && !iso_blk) {
         // the shared bases (Eq. 3): d B_dir[r][j] = sum over directional
         // Gaussians of u_r f_j, d b_iso[j] = sum over isotropic ones (and
         // every Gaussian of an entangled model) of z f_j -- this block's share
@@ -842,6 +846,55 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
             for (int e = lane; e < 16 * NCOL; e += kWave)
                 a.bpart[(size_t)blockIdx.x * 16 * NCOL + e] = ((t0[e] + t1[e]) + t2[e]) + t3[e];
         }
+    }
+}
+
+// Isotropic blocks of the projection backward (one per block of kBlock
+// Gaussians, all of index < n_iso): the feature gradients z b_iso and the
+// block's basis tile, whose only non-zero row is 15, d b_iso = sum z f (per
+// wave a transposing butterfly over its 64 Gaussians, the four waves added in
+// a fixed order).  The features are read here, with few registers per thread,
+// instead of being held through the projection backward.
+template <int KMAX>
+__global__ __launch_bounds__(kBlock) void iso_feat_kernel(int n, int k, const float *zbuf, const float *feat,
+                                                          const float *b_iso, float *dfeat, float *bpart)
+{
+    constexpr int NTILE = (KMAX + 15) / 16, NCOL = NTILE * 16, NW = kBlock / kWave;
+    __shared__ float sbi[KMAX];
+    __shared__ float srow[NW][NCOL];
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = i < n;
+    const int ii = valid ? i : 0;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (threadIdx.x < KMAX) sbi[threadIdx.x] = (int)threadIdx.x < k ? b_iso[threadIdx.x] : 0.0f;
+    const float z = valid ? zbuf[ii] : 0.0f;
+    float f[NCOL];
+#pragma unroll
+    for (int j = 0; j < NCOL; ++j) {
+        // (a clamped row past k; masked)
+        const float x = bpart ? feat[(size_t)min(j, k - 1) * n + ii] : 0.0f;
+        f[j] = (valid && j < k) ? x : 0.0f;
+    }
+    __syncthreads();
+    if (dfeat && valid) {
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j)
+            if (j < k) dfeat[(size_t)j * n + i] = z * sbi[j];
+    }
+    if (!bpart) return;
+#pragma unroll
+    for (int t = 0; t < NTILE; ++t) {
+        float v[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = z * f[t * 16 + j];
+        const float sum = wave_transpose_sum16(v);
+        if ((lane & 3) == 0) srow[w][t * 16 + (lane >> 2)] = sum;
+    }
+    __syncthreads();
+    float *out = bpart + (size_t)blockIdx.x * 16 * NCOL;
+    for (int e = threadIdx.x; e < 16 * NCOL; e += kBlock) {
+        const int col = e % NCOL;
+        out[e] = e >= 15 * NCOL ? ((srow[0][col] + srow[1][col]) + srow[2][col]) + srow[3][col] : 0.0f;
     }
 }
 
@@ -987,6 +1040,9 @@ hipError_t launch_project_bwd(const ProjBwdArgs &a, hipStream_t s)
     return dispatch_kl(a.m.k, a.m.L, [&](auto K, auto L) {
         constexpr int KK = decltype(K)::value, LL = decltype(L)::value;
         project_bwd_kernel<KK, LL><<<(a.m.n + kBlock - 1) / kBlock, kBlock, 0, s>>>(a);
+        if (a.iso_blocks > 0)
+            iso_feat_kernel<KK><<<a.iso_blocks, kBlock, 0, s>>>(a.m.n, a.m.k, a.zbuf, a.m.feat, a.m.b_iso, a.dfeat,
+                                                                a.bpart);
         return hipGetLastError();
     });
 }
