@@ -426,6 +426,7 @@ ddgs_status ensure_static(ddgs_ctx *c)
     DDGS_TRY(ensure_t(c, "pose_part", (size_t)std::max<int64_t>(1, V * slot_blocks(n) * 9), &f));
     DDGS_TRY(ensure_t(c, "basis_part", basis_part_floats((int)std::max<int64_t>(1, n)), &f));
     DDGS_TRY(ensure_t(c, "zbuf", (size_t)std::max<int64_t>(1, n), &f));
+    DDGS_TRY(ensure_t(c, "ubuf", (size_t)KL * std::max<int64_t>(1, n - c->model.n_iso), &f));
     double *d;
     DDGS_TRY(ensure_t(c, "loss_part", loss_part_doubles((int)V, c->max_view_pix, c->loss_tiles), &d));
     DDGS_TRY(ensure_t(c, "loss_maps", (size_t)3 * c->total_pix, &f));
@@ -725,14 +726,11 @@ ddgs_status enqueue_backward(ddgs_ctx *c, const float *dL, const ddgs_grads *g, 
     pa.st_cnt = c->st_cnt;
     pa.st_rad = c->st_rad;
     pa.skip = captured ? flags_ptr(c) : nullptr;
-    // leading blocks of isotropic Gaussians only: their feature gradients
-    // and basis tiles come from the isotropic launch
-    pa.zbuf = buf<float>(c, "zbuf");
-    pa.iso_blocks = 0;
-    if (per_g && (pa.dfeat || pa.bpart) && !pa.m.entangled) {
-        const int64_t nb = slot_blocks(n);
-        pa.iso_blocks = (int)(c->model.n_iso >= n ? nb : c->model.n_iso / kSlotBlock);
-    }
+    // feature and basis gradients in a second launch, from the radiosity
+    // logits' gradients
+    const bool feat_g = per_g && (pa.dfeat || pa.bpart);
+    pa.zbuf = feat_g ? buf<float>(c, "zbuf") : nullptr;
+    pa.ubuf = feat_g ? buf<float>(c, "ubuf") : nullptr;
     HIP_TRY(c, launch_project_bwd(pa, s));
     // (one pose partial per projection block)
     HIP_TRY(c, launch_grad_final(pa.m, buf<float>(c, "basis_part"), g->db_iso, g->dB_dir, buf<ViewDev>(c, "views"), V,

@@ -284,15 +284,15 @@ struct ProjBwdArgs {
     // step flags of a captured step (NULL: plain call): while bit 0 (a tile
     // list overflowed its capacity) is set the statistics are not updated
     const uint32_t *skip;
-    // blocks [0, iso_blocks) hold isotropic Gaussians only (none when the
-    // model is entangled): there the kernel leaves the feature gradients and
-    // the basis tiles to a second launch and writes each Gaussian's
-    // radiosity-logit gradient z = dL/dc c (1 - c) to zbuf [n]
-    int iso_blocks;
-    float *zbuf;
+    // the radiosity logits' gradients handed to the feature-gradient launch
+    // (NULL: neither feature nor basis gradients are wanted): zbuf [n], the
+    // isotropic term's z = dL/dc c (1 - c) (every Gaussian of an entangled
+    // model; 0 for the directional ones of a disentangled one), ubuf
+    // [k_L][n - n_iso], the directional coefficients' u = z Y(d)
+    float *zbuf, *ubuf;
 };
-// The projection backward, then (iso_blocks > 0) the isotropic blocks'
-// feature gradients z b_iso and basis tiles (row 15: sum z f) from zbuf.
+// The projection backward, then (zbuf set and dfeat or bpart wanted) the
+// feature gradients and the basis tiles from zbuf and ubuf.
 hipError_t launch_project_bwd(const ProjBwdArgs &a, hipStream_t s);
 // floats of the basis tiles of the projection backward (one per block)
 size_t basis_part_floats(int n);

@@ -415,15 +415,12 @@ template <int KMAX, int L>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void project_bwd_kernel(ProjBwdArgs a)
 {
     constexpr int KL = L * (L + 2);
-    const int n = a.m.n, k = a.m.k;
+    const int n = a.m.n;
     const int i = blockIdx.x * kBlock + threadIdx.x;
     const bool valid = i < n;
     const int ii = valid ? i : 0;
     const int lane = threadIdx.x & (kWave - 1);
     const bool is_dir = ii >= a.m.n_iso;
-    // (block-uniform) features, feature gradients and basis tile of this
-    // block are the isotropic launch's
-    const bool iso_blk = (int)blockIdx.x < a.iso_blocks;
     const int nd = n - a.m.n_iso, id = ii - a.m.n_iso;
     // the next view's slot count and first slot, read one view ahead (the
     // first view's before the parameters, since its slot reads wait on them)
@@ -457,36 +454,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         st0[1] = a.st_cnt[ii];
         st0[2] = a.st_rad[ii];
     }
-    // The basis contraction's B operands (the features) are read here, with
-    // the other parameters, so that their latency overlaps: one coalesced row
-    // per feature (lane = Gaussian), moved into the matrix cores' layout
-    // through the wave's LDS rows at the end.  sU holds each wave's U rows and
-    // then its tile, sF its features, s_done counts the block's finished
-    // waves; sbi and sBd hold the bases for the feature gradients.
-    constexpr int NTILE = (KMAX + 15) / 16, NCOL = NTILE * 16;
     constexpr int NW = kBlock / kWave;
-    static_assert(16 * NCOL <= kWave * 17, "a wave tile fits in the wave's U rows");
-    __shared__ float sU[NW][kWave][17];
-    __shared__ float sF[NW][kWave][NCOL + 1];
-    __shared__ float sbi[KMAX], sBd[KL * KMAX];
     __shared__ float sP[2][NW][9];
-    __shared__ uint32_t s_done;
     const int w = threadIdx.x / kWave;
-    const int ri = lane & 15, kk = lane >> 4;
-    if (threadIdx.x == 0) s_done = 0;
-    stage_bases<KMAX, L>(a.m, sbi, sBd);
-    __syncthreads();
-    float fc[NCOL];
-#pragma unroll
-    for (int j = 0; j < NCOL; ++j) fc[j] = 0.0f;
-    if (a.bpart && !iso_blk) {
-#pragma unroll
-        for (int j = 0; j < NCOL; ++j) {
-            // (a clamped row past k; masked below)
-            const float x = a.m.feat[(size_t)min(j, k - 1) * n + ii];
-            fc[j] = (valid && j < k && a.per_gaussian) ? x : 0.0f;
-        }
-    }
     float h[KL];
 #pragma unroll
     for (int r = 0; r < KL; ++r) h[r] = 0.0f;
@@ -752,149 +722,149 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         if (a.dopacity) {
             a.dopacity[i] = galpha * al * (1.0f - al);
         }
-        if (iso_blk) a.zbuf[i] = zsum;
-        if (a.dfeat && !iso_blk) {
-            // (bases from LDS: sbi[j] = b_iso[j], sBd[r KMAX + j] = B_dir[r][j])
-            const bool iso_term = !is_dir || a.m.entangled;
+        // the radiosity logits' gradients, for the feature and basis
+        // gradients of the second launch: z (isotropic term) and u (the
+        // directional coefficients)
+        if (a.zbuf) {
+            a.zbuf[i] = zsum;
+            if (is_dir) {
 #pragma unroll
-            for (int j = 0; j < KMAX; ++j) {
-                if (j < k) {
-                    float acc = iso_term ? zsum * sbi[j] : 0.0f;
-                    if (is_dir) {
-#pragma unroll
-                        for (int r = 0; r < KL; ++r) acc += sBd[r * KMAX + j] * u[r];
-                    }
-                    a.dfeat[(size_t)j * n + i] = acc;
-                }
+                for (int r = 0; r < KL; ++r) a.ubuf[(size_t)r * nd + id] = u[r];
             }
-        }
-    }
-
-    if (a.bpart && !iso_blk) {
-        // the shared bases (Eq. 3): d B_dir[r][j] = sum over directional
-        // Gaussians of u_r f_j, d b_iso[j] = sum over isotropic ones (and
-        // every Gaussian of an entangled model) of z f_j -- this block's share
-        // of the dense contraction U F^T, on the matrix cores with
-        // v_mfma_f32_16x16x4_f32: each wave stages its 64 Gaussians' U rows
-        // in its own LDS rows, runs 16 steps of four Gaussians
-        // and leaves its tile there; the block's last wave to finish adds the
-        // four tiles in a fixed order (no workgroup barrier: waves do not
-        // wait for each other)
-        const bool own = valid && a.per_gaussian;
-        float *tile = &sU[w][0][0];
-        if (!a.m.entangled && __builtin_amdgcn_ballot_w64(own && is_dir) == 0ull) {
-            // a wave of isotropic Gaussians only contributes z f_j to row 15
-            // (d b_iso): sixteen products per lane summed over the wave by a
-            // transposing butterfly, no operand staging (the other rows of
-            // its tile are zero)
-            const float z = own ? zsum : 0.0f;
-            for (int e = lane; e < 15 * NCOL; e += kWave) tile[e] = 0.0f;
-#pragma unroll
-            for (int t = 0; t < NTILE; ++t) {
-                float v[16];
-#pragma unroll
-                for (int j = 0; j < 16; ++j) v[j] = z * fc[t * 16 + j];
-                const float sum = wave_transpose_sum16(v);
-                if ((lane & 3) == 0) tile[15 * NCOL + t * 16 + (lane >> 2)] = sum;
-            }
-        } else {
-            float row[16];
-#pragma unroll
-            for (int r = 0; r < 16; ++r) row[r] = 0.0f;
-            if (own && (!is_dir || a.m.entangled)) row[15] = zsum;
-            if (own && is_dir) {
-#pragma unroll
-                for (int r = 0; r < KL; ++r) row[r] = u[r];
-            }
-#pragma unroll
-            for (int r = 0; r < 16; ++r) sU[w][lane][r] = row[r];
-#pragma unroll
-            for (int j = 0; j < NCOL; ++j) sF[w][lane][j] = fc[j];
-            // (other lanes of this wave read these rows next)
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            // operand layout: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
-            // D[r][j] comes back in lane j + 16 (r / 4), item r % 4
-            floatx4 acc[NTILE];
-#pragma unroll
-            for (int t = 0; t < NTILE; ++t) acc[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int st = 0; st < kWave / 4; ++st) {
-                const int g = 4 * st + kk;
-                const float av = sU[w][g][ri];
-#pragma unroll
-                for (int t = 0; t < NTILE; ++t)
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, sF[w][g][t * 16 + ri], acc[t], 0, 0, 0);
-            }
-            // the wave's tile replaces its U rows (all its operand reads are done)
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-            for (int t = 0; t < NTILE; ++t)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) tile[(4 * kk + q) * NCOL + t * 16 + ri] = acc[t][q];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        uint32_t before = 0;
-        if (lane == 0) before = atomicAdd(&s_done, 1u);
-        before = (uint32_t)__shfl((int)before, 0, kWave);
-        if (before == NW - 1) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            const float *t0 = &sU[0][0][0], *t1 = &sU[1][0][0], *t2 = &sU[2][0][0], *t3 = &sU[3][0][0];
-            for (int e = lane; e < 16 * NCOL; e += kWave)
-                a.bpart[(size_t)blockIdx.x * 16 * NCOL + e] = ((t0[e] + t1[e]) + t2[e]) + t3[e];
         }
     }
 }
 
-// Isotropic blocks of the projection backward (one per block of kBlock
-// Gaussians, all of index < n_iso): the feature gradients z b_iso and the
-// block's basis tile, whose only non-zero row is 15, d b_iso = sum z f (per
-// wave a transposing butterfly over its 64 Gaussians, the four waves added in
-// a fixed order).  The features are read here, with few registers per thread,
-// instead of being held through the projection backward.
-template <int KMAX>
-__global__ __launch_bounds__(kBlock) void iso_feat_kernel(int n, int k, const float *zbuf, const float *feat,
-                                                          const float *b_iso, float *dfeat, float *bpart)
+// Feature and basis gradients from the radiosity logits' gradients the
+// projection backward leaves (z = dL/dc_iso c (1 - c) in zbuf, the
+// directional coefficients' u = dL/dc c (1 - c) Y(d) in ubuf), one thread per
+// Gaussian: d f = z b_iso (isotropic term) + B_dir^T u (directional term),
+// and this block's share of the shared bases' gradients (Eq. 3), d B_dir[r][j]
+// = sum over directional Gaussians of u_r f_j, d b_iso[j] = sum over
+// isotropic ones (and every Gaussian of an entangled model) of z f_j.  Kept
+// apart from the projection backward so that neither the features nor the
+// matrix-core operands are held through its chain rule.
+//
+// The contraction U F^T: a wave of isotropic Gaussians only has row 15 (z f:
+// sixteen products per lane summed over the wave by a transposing
+// butterfly); any other wave stages its 64 U rows and features in its LDS
+// rows and runs 16 steps of v_mfma_f32_16x16x4_f32 (four Gaussians each).
+// Each wave leaves its tile in LDS; the block's last wave to finish adds the
+// four tiles in a fixed order (no workgroup barrier: waves do not wait for
+// each other).
+template <int KMAX, int L>
+__global__ __launch_bounds__(kBlock) void feat_grad_kernel(ProjBwdArgs a)
 {
-    constexpr int NTILE = (KMAX + 15) / 16, NCOL = NTILE * 16, NW = kBlock / kWave;
-    __shared__ float sbi[KMAX];
-    __shared__ float srow[NW][NCOL];
+    constexpr int KL = L * (L + 2);
+    constexpr int NTILE = (KMAX + 15) / 16, NCOL = NTILE * 16;
+    constexpr int NW = kBlock / kWave;
+    static_assert(16 * NCOL <= kWave * 17, "a wave tile fits in the wave's U rows");
+    __shared__ float sU[NW][kWave][17];
+    __shared__ float sF[NW][kWave][NCOL + 1];
+    __shared__ float sbi[KMAX], sBd[KL * KMAX];
+    __shared__ uint32_t s_done;
+    const int n = a.m.n, k = a.m.k;
     const int i = blockIdx.x * kBlock + threadIdx.x;
     const bool valid = i < n;
     const int ii = valid ? i : 0;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    if (threadIdx.x < KMAX) sbi[threadIdx.x] = (int)threadIdx.x < k ? b_iso[threadIdx.x] : 0.0f;
-    const float z = valid ? zbuf[ii] : 0.0f;
-    float f[NCOL];
+    const int ri = lane & 15, kk = lane >> 4;
+    const bool is_dir = ii >= a.m.n_iso;
+    const int nd = n - a.m.n_iso, id = ii - a.m.n_iso;
+    if (threadIdx.x == 0) s_done = 0;
+    stage_bases<KMAX, L>(a.m, sbi, sBd);
+    const float z = valid ? a.zbuf[ii] : 0.0f;
+    float u[KL];
+#pragma unroll
+    for (int r = 0; r < KL; ++r) u[r] = 0.0f;
+    if (valid && is_dir) {
+#pragma unroll
+        for (int r = 0; r < KL; ++r) u[r] = a.ubuf[(size_t)r * nd + id];
+    }
+    float fc[NCOL];
 #pragma unroll
     for (int j = 0; j < NCOL; ++j) {
         // (a clamped row past k; masked)
-        const float x = bpart ? feat[(size_t)min(j, k - 1) * n + ii] : 0.0f;
-        f[j] = (valid && j < k) ? x : 0.0f;
+        const float x = a.bpart ? a.m.feat[(size_t)min(j, k - 1) * n + ii] : 0.0f;
+        fc[j] = (valid && j < k) ? x : 0.0f;
     }
     __syncthreads();
-    if (dfeat && valid) {
+    const bool iso_term = !is_dir || a.m.entangled;
+    if (a.dfeat && valid) {
+        // (bases from LDS: sbi[j] = b_iso[j], sBd[r KMAX + j] = B_dir[r][j])
 #pragma unroll
-        for (int j = 0; j < KMAX; ++j)
-            if (j < k) dfeat[(size_t)j * n + i] = z * sbi[j];
+        for (int j = 0; j < KMAX; ++j) {
+            if (j < k) {
+                float acc = iso_term ? z * sbi[j] : 0.0f;
+                if (is_dir) {
+#pragma unroll
+                    for (int r = 0; r < KL; ++r) acc += sBd[r * KMAX + j] * u[r];
+                }
+                a.dfeat[(size_t)j * n + i] = acc;
+            }
+        }
     }
-    if (!bpart) return;
+    if (!a.bpart) return;
+    float *tile = &sU[w][0][0];
+    if (!a.m.entangled && __builtin_amdgcn_ballot_w64(valid && is_dir) == 0ull) {
+        // isotropic Gaussians only: row 15, the other rows of the tile zero
+        for (int e = lane; e < 15 * NCOL; e += kWave) tile[e] = 0.0f;
 #pragma unroll
-    for (int t = 0; t < NTILE; ++t) {
-        float v[16];
+        for (int t = 0; t < NTILE; ++t) {
+            float v[16];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) v[j] = z * f[t * 16 + j];
-        const float sum = wave_transpose_sum16(v);
-        if ((lane & 3) == 0) srow[w][t * 16 + (lane >> 2)] = sum;
+            for (int j = 0; j < 16; ++j) v[j] = z * fc[t * 16 + j];
+            const float sum = wave_transpose_sum16(v);
+            if ((lane & 3) == 0) tile[15 * NCOL + t * 16 + (lane >> 2)] = sum;
+        }
+    } else {
+        float row[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) row[r] = 0.0f;
+        if (valid && iso_term) row[15] = z;
+        if (valid && is_dir) {
+#pragma unroll
+            for (int r = 0; r < KL; ++r) row[r] = u[r];
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) sU[w][lane][r] = row[r];
+#pragma unroll
+        for (int j = 0; j < NCOL; ++j) sF[w][lane][j] = fc[j];
+        // (other lanes of this wave read these rows next)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // operand layout: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
+        // D[r][j] comes back in lane j + 16 (r / 4), item r % 4
+        floatx4 acc[NTILE];
+#pragma unroll
+        for (int t = 0; t < NTILE; ++t) acc[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int st = 0; st < kWave / 4; ++st) {
+            const int g = 4 * st + kk;
+            const float av = sU[w][g][ri];
+#pragma unroll
+            for (int t = 0; t < NTILE; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, sF[w][g][t * 16 + ri], acc[t], 0, 0, 0);
+        }
+        // the wave's tile replaces its U rows (all its operand reads are done)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) tile[(4 * kk + q) * NCOL + t * 16 + ri] = acc[t][q];
     }
-    __syncthreads();
-    float *out = bpart + (size_t)blockIdx.x * 16 * NCOL;
-    for (int e = threadIdx.x; e < 16 * NCOL; e += kBlock) {
-        const int col = e % NCOL;
-        out[e] = e >= 15 * NCOL ? ((srow[0][col] + srow[1][col]) + srow[2][col]) + srow[3][col] : 0.0f;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    uint32_t before = 0;
+    if (lane == 0) before = atomicAdd(&s_done, 1u);
+    before = (uint32_t)__shfl((int)before, 0, kWave);
+    if (before == NW - 1) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        const float *t0 = &sU[0][0][0], *t1 = &sU[1][0][0], *t2 = &sU[2][0][0], *t3 = &sU[3][0][0];
+        for (int e = lane; e < 16 * NCOL; e += kWave)
+            a.bpart[(size_t)blockIdx.x * 16 * NCOL + e] = ((t0[e] + t1[e]) + t2[e]) + t3[e];
     }
 }
 
@@ -1039,10 +1009,9 @@ hipError_t launch_project_bwd(const ProjBwdArgs &a, hipStream_t s)
     if (a.m.n == 0 || a.V == 0) return hipSuccess;
     return dispatch_kl(a.m.k, a.m.L, [&](auto K, auto L) {
         constexpr int KK = decltype(K)::value, LL = decltype(L)::value;
-        project_bwd_kernel<KK, LL><<<(a.m.n + kBlock - 1) / kBlock, kBlock, 0, s>>>(a);
-        if (a.iso_blocks > 0)
-            iso_feat_kernel<KK><<<a.iso_blocks, kBlock, 0, s>>>(a.m.n, a.m.k, a.zbuf, a.m.feat, a.m.b_iso, a.dfeat,
-                                                                a.bpart);
+        const int nb = (a.m.n + kBlock - 1) / kBlock;
+        project_bwd_kernel<KK, LL><<<nb, kBlock, 0, s>>>(a);
+        if (a.zbuf && (a.dfeat || a.bpart)) feat_grad_kernel<KK, LL><<<nb, kBlock, 0, s>>>(a);
         return hipGetLastError();
     });
 }
