@@ -15,8 +15,6 @@ namespace {
 constexpr int kBlock = 256;
 static_assert(kBlock == kSlotBlock, "one projection block per block of the slot numbering");
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
 // Real orthonormal spherical basis of degrees 1..L at the unit direction
 // (x, y, z): order l = 1..L, m = -l..l, no Condon-Shortley phase.  The
 // normalisations are sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!) times the factor
@@ -742,25 +740,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
 // and this block's share of the shared bases' gradients (Eq. 3), d B_dir[r][j]
 // = sum over directional Gaussians of u_r f_j, d b_iso[j] = sum over
 // isotropic ones (and every Gaussian of an entangled model) of z f_j.  Kept
-// apart from the projection backward so that neither the features nor the
-// matrix-core operands are held through its chain rule.
+// apart from the projection backward so that the features are not held
+// through its chain rule.
 //
-// The contraction U F^T: a wave of isotropic Gaussians only has row 15 (z f:
-// sixteen products per lane summed over the wave by a transposing
-// butterfly); any other wave stages its 64 U rows and features in its LDS
-// rows and runs 16 steps of v_mfma_f32_16x16x4_f32 (four Gaussians each).
-// Each wave leaves its tile in LDS; the block's last wave to finish adds the
-// four tiles in a fixed order (no workgroup barrier: waves do not wait for
-// each other).
+// The contraction U F^T, a wave's 64 Gaussians at a time: row r of the
+// wave's tile is sum u_r f over the wave, the sixteen products per lane and
+// 16 columns summed by a transposing butterfly (lane 4 j ends with column
+// j); a wave of isotropic Gaussians only has row 15 (z f).  The contraction
+// is small beside the feature traffic (k_L + 1 rows of 16 products per
+// Gaussian), so it stays on the vector ALU without operand staging.  Each
+// wave leaves its tile in LDS; the block's last wave to finish adds the four
+// tiles in a fixed order (no workgroup barrier: waves do not wait for each
+// other).
 template <int KMAX, int L>
 __global__ __launch_bounds__(kBlock) void feat_grad_kernel(ProjBwdArgs a)
 {
     constexpr int KL = L * (L + 2);
     constexpr int NTILE = (KMAX + 15) / 16, NCOL = NTILE * 16;
     constexpr int NW = kBlock / kWave;
-    static_assert(16 * NCOL <= kWave * 17, "a wave tile fits in the wave's U rows");
-    __shared__ float sU[NW][kWave][17];
-    __shared__ float sF[NW][kWave][NCOL + 1];
+    __shared__ float sT[NW][16 * NCOL];
     __shared__ float sbi[KMAX], sBd[KL * KMAX];
     __shared__ uint32_t s_done;
     const int n = a.m.n, k = a.m.k;
@@ -768,7 +766,6 @@ __global__ __launch_bounds__(kBlock) void feat_grad_kernel(ProjBwdArgs a)
     const bool valid = i < n;
     const int ii = valid ? i : 0;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    const int ri = lane & 15, kk = lane >> 4;
     const bool is_dir = ii >= a.m.n_iso;
     const int nd = n - a.m.n_iso, id = ii - a.m.n_iso;
     if (threadIdx.x == 0) s_done = 0;
@@ -805,66 +802,34 @@ __global__ __launch_bounds__(kBlock) void feat_grad_kernel(ProjBwdArgs a)
         }
     }
     if (!a.bpart) return;
-    float *tile = &sU[w][0][0];
-    if (!a.m.entangled && __builtin_amdgcn_ballot_w64(valid && is_dir) == 0ull) {
-        // isotropic Gaussians only: row 15, the other rows of the tile zero
-        for (int e = lane; e < 15 * NCOL; e += kWave) tile[e] = 0.0f;
+    float *tile = &sT[w][0];
+    // row r of the tile: sum over the wave of wr f
+    auto tile_row = [&](int r, float wr) {
 #pragma unroll
         for (int t = 0; t < NTILE; ++t) {
             float v[16];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) v[j] = z * fc[t * 16 + j];
+            for (int j = 0; j < 16; ++j) v[j] = wr * fc[t * 16 + j];
             const float sum = wave_transpose_sum16(v);
-            if ((lane & 3) == 0) tile[15 * NCOL + t * 16 + (lane >> 2)] = sum;
+            if ((lane & 3) == 0) tile[r * NCOL + t * 16 + (lane >> 2)] = sum;
         }
-    } else {
-        float row[16];
+    };
+    const bool dir_wave = __builtin_amdgcn_ballot_w64(valid && is_dir) != 0ull;
+    for (int e = lane; e < 15 * NCOL; e += kWave)
+        if (!dir_wave || e >= KL * NCOL) tile[e] = 0.0f;
+    if (dir_wave) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) row[r] = 0.0f;
-        if (valid && iso_term) row[15] = z;
-        if (valid && is_dir) {
-#pragma unroll
-            for (int r = 0; r < KL; ++r) row[r] = u[r];
-        }
-#pragma unroll
-        for (int r = 0; r < 16; ++r) sU[w][lane][r] = row[r];
-#pragma unroll
-        for (int j = 0; j < NCOL; ++j) sF[w][lane][j] = fc[j];
-        // (other lanes of this wave read these rows next)
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // operand layout: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
-        // D[r][j] comes back in lane j + 16 (r / 4), item r % 4
-        floatx4 acc[NTILE];
-#pragma unroll
-        for (int t = 0; t < NTILE; ++t) acc[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int st = 0; st < kWave / 4; ++st) {
-            const int g = 4 * st + kk;
-            const float av = sU[w][g][ri];
-#pragma unroll
-            for (int t = 0; t < NTILE; ++t)
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, sF[w][g][t * 16 + ri], acc[t], 0, 0, 0);
-        }
-        // the wave's tile replaces its U rows (all its operand reads are done)
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-        for (int t = 0; t < NTILE; ++t)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) tile[(4 * kk + q) * NCOL + t * 16 + ri] = acc[t][q];
+        for (int r = 0; r < KL; ++r) tile_row(r, u[r]);
     }
+    tile_row(15, iso_term ? z : 0.0f);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     uint32_t before = 0;
     if (lane == 0) before = atomicAdd(&s_done, 1u);
     before = (uint32_t)__shfl((int)before, 0, kWave);
     if (before == NW - 1) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        const float *t0 = &sU[0][0][0], *t1 = &sU[1][0][0], *t2 = &sU[2][0][0], *t3 = &sU[3][0][0];
         for (int e = lane; e < 16 * NCOL; e += kWave)
-            a.bpart[(size_t)blockIdx.x * 16 * NCOL + e] = ((t0[e] + t1[e]) + t2[e]) + t3[e];
+            a.bpart[(size_t)blockIdx.x * 16 * NCOL + e] = ((sT[0][e] + sT[1][e]) + sT[2][e]) + sT[3][e];
     }
 }
 
