@@ -161,6 +161,27 @@ def test_capacity_overflow_flag_persists_until_checked(R):
     R.set_options(capacity=0)
 
 
+def test_autotune_on_the_default_stream():
+    """On the default stream, which cannot be captured, the tuner times plain
+    render + backward calls instead of trial graphs; it still picks one of its
+    candidates and the image changes by rounding only."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    r = make_renderer()
+    try:
+        c = synth.config("C2", scale=0.05)
+        r.set_scene(c.scene)
+        r.set_views(c.views)
+        before = r.render().cpu().numpy()
+        assert binding.ddgs_autotune(r.ctx, None, 1) > 0
+        o = r.options()
+        assert (o["tile_w"], o["tile_h"]) in ((16, 16), (8, 8), (16, 8), (32, 8))
+        assert o["split"] in (0, 64, 128, 256, 512, 1024, 2048, 4096) and o["persistent"] in (0, 1, 2, 4)
+        assert rel_l2(r.render().cpu().numpy(), before) < 1e-6
+    finally:
+        r.close()
+
+
 def test_autotune_keeps_unchecked_overflow(R):
     """The tuner times each candidate as a captured graph of its own, which
     updates the step counters as a captured step does; an overflow of the
