@@ -416,6 +416,16 @@ ddgs_status ddgs_step_capture(ddgs_ctx *ctx, int loss_kind, const float *target,
                               float *images, float *dL_dimages, float *loss_out,
                               const ddgs_grads *grads);
 ddgs_status ddgs_step_launch(ddgs_ctx *ctx);
+/* Sets the target image the captured step's loss reads from the next replay
+ * on (Eq. 2 fitting target, NCC reference or linear-loss weights; device
+ * memory in the image layout of the current views, caller-owned, 4-byte
+ * aligned, and left unchanged until the replays that read it have run).  A
+ * fitting loop over many poses keeps every target resident and passes the
+ * current one here instead of copying it into the captured buffer; the
+ * pointer travels with the view table's upload (no copy of the image).
+ * DDGS_ERR_STATE without a captured step, DDGS_ERR_INVALID_ARG for NULL or
+ * misaligned pointers. */
+ddgs_status ddgs_step_set_target(ddgs_ctx *ctx, const float *target);
 ddgs_status ddgs_check(ddgs_ctx *ctx, uint32_t *flags);
 ddgs_status ddgs_step_report(const ddgs_ctx *ctx, int64_t *skipped_replays, int64_t *entries_needed);
 

@@ -27,7 +27,7 @@ EXPORTED = (
     "ddgs_default_options", "ddgs_set_options", "ddgs_get_options", "ddgs_set_model", "ddgs_set_views",
     "ddgs_set_radiosity_override", "ddgs_set_workspace", "ddgs_workspace_size", "ddgs_set_pose_optimizer",
     "ddgs_get_views",
-    "ddgs_image_size", "ddgs_render", "ddgs_backward", "ddgs_loss", "ddgs_step_capture", "ddgs_step_launch",
+    "ddgs_image_size", "ddgs_render", "ddgs_backward", "ddgs_loss", "ddgs_step_capture", "ddgs_step_launch", "ddgs_step_set_target",
     "ddgs_check", "ddgs_autotune", "ddgs_param_count", "ddgs_num_rendered", "ddgs_debug_copy",
     "ddgs_debug_keep_unsorted", "ddgs_debug_sort_pairs", "ddgs_debug_exclusive_scan", "ddgs_debug_count_pairs",
     "ddgs_debug_pair_counts", "ddgs_enable_timing", "ddgs_stage_times", "ddgs_default_fit_options",
@@ -135,6 +135,7 @@ def lib():
             "ddgs_loss": ([vp, C.c_int, vp, vp, C.c_float, vp, vp], st),
             "ddgs_step_capture": ([vp, C.c_int, vp, C.c_float, vp, vp, vp, C.POINTER(ddgs_grads)], st),
             "ddgs_step_launch": ([vp], st),
+            "ddgs_step_set_target": ([vp, vp], st),
             "ddgs_check": ([vp, C.POINTER(C.c_uint32)], st),
             "ddgs_autotune": ([vp, C.c_char_p, C.c_int, C.POINTER(C.c_float)], st),
             "ddgs_param_count": ([C.c_int, C.c_int, i64, C.POINTER(i64), C.POINTER(i64)], st),
@@ -313,6 +314,10 @@ def ddgs_step_capture(ctx, kind, target_ptr, lam, images_ptr, dl_ptr, loss_ptr, 
 
 def ddgs_step_launch(ctx):
     _check(lib().ddgs_step_launch(ctx), ctx)
+
+
+def ddgs_step_set_target(ctx, target_ptr):
+    _check(lib().ddgs_step_set_target(ctx, C.c_void_p(int(target_ptr))), ctx)
 
 
 def ddgs_check(ctx, raise_on_error=True):

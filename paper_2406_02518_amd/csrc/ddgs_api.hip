@@ -125,6 +125,9 @@ struct ddgs_ctx {
     int64_t long_seen = -1, long_seen_n = -1;
     int long_seen_tiles = -1;
 
+    // target image of the captured step's loss (uploaded with the view table)
+    const float *step_target = nullptr;
+
     // pinned staging of the view table uploads
     void *stage_host = nullptr;
     size_t stage_bytes = 0;
@@ -296,10 +299,16 @@ int bits_for(int64_t n)
     return b;
 }
 
-// The "views" buffer holds the device views (at least one slot) followed by
-// the V + 1 first loss tiles per view.
+// The "views" buffer holds the device views (at least one slot), the V + 1
+// first loss tiles per view, and the captured step's target image pointer.
 size_t loss_base_offset(int V) { return sizeof(ViewDev) * (size_t)std::max(1, V); }
-size_t views_bytes(int V) { return loss_base_offset(V) + sizeof(int32_t) * (size_t)(V + 1); }
+size_t target_slot_offset(int V) { return (loss_base_offset(V) + sizeof(int32_t) * (size_t)(V + 1) + 7) & ~(size_t)7; }
+size_t views_bytes(int V) { return target_slot_offset(V) + sizeof(void *); }
+const float *const *target_slot_ptr(ddgs_ctx *c)
+{
+    char *p = buf<char>(c, "views");
+    return p ? reinterpret_cast<const float *const *>(p + target_slot_offset((int)c->views_h.size())) : nullptr;
+}
 int32_t *loss_tile_base_ptr(ddgs_ctx *c)
 {
     char *p = buf<char>(c, "views");
@@ -370,6 +379,7 @@ ddgs_status prepare_views(ddgs_ctx *c)
     char *h = (char *)c->stage_host;
     if (V > 0) std::memcpy(h, c->vdev_h.data(), sizeof(ViewDev) * V);
     std::memcpy(h + loss_base_offset(V), c->loss_tile_base_h.data(), sizeof(int32_t) * (V + 1));
+    std::memcpy(h + target_slot_offset(V), &c->step_target, sizeof(void *));
     HIP_TRY(c, hipMemcpyAsync(vp, h, need, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipEventRecord(c->stage_event, c->stream));
     c->stage_pending = true;
@@ -739,8 +749,9 @@ ddgs_status enqueue_backward(ddgs_ctx *c, const float *dL, const ddgs_grads *g, 
     return DDGS_OK;
 }
 
+// (captured: the target is read from the view table's target slot)
 ddgs_status enqueue_loss(ddgs_ctx *c, int kind, const float *images, const float *target, float lambda,
-                         float *loss_out, float *dL)
+                         float *loss_out, float *dL, bool captured = false)
 {
     LossArgs la{};
     la.views = buf<ViewDev>(c, "views");
@@ -748,6 +759,7 @@ ddgs_status enqueue_loss(ddgs_ctx *c, int kind, const float *images, const float
     la.total_pix = c->total_pix;
     la.img = images;
     la.target = target;
+    la.target_ref = captured ? target_slot_ptr(c) : nullptr;
     la.lambda = lambda;
     la.loss_out = loss_out;
     la.grad = dL;
@@ -1524,6 +1536,9 @@ ddgs_status ddgs_step_capture(ddgs_ctx *c, int kind, const float *target, float 
         return fail(c, DDGS_ERR_INVALID_ARG, "the fitting optimiser needs every parameter gradient");
     drop_graph(c);
     DDGS_TRY(ensure_static(c));
+    c->step_target = target;
+    c->views_dirty = true;
+    DDGS_TRY(prepare_views(c));
     if (c->adam_on) {
         float *st_;
         uint32_t *sp_;
@@ -1560,7 +1575,7 @@ ddgs_status ddgs_step_capture(ddgs_ctx *c, int kind, const float *target, float 
     c->long_grid = captured_long_grid(c);
     ddgs_status st = enqueue_front(c, (uint32_t)c->step_cap, true);
     if (st == DDGS_OK) st = enqueue_back(c, c->step_cap, images);
-    if (st == DDGS_OK) st = enqueue_loss(c, kind, images, target, lambda, loss_out, dL);
+    if (st == DDGS_OK) st = enqueue_loss(c, kind, images, target, lambda, loss_out, dL, true);
     if (st == DDGS_OK) st = enqueue_backward(c, dL, g, c->step_cap, true);
     if (st == DDGS_OK && c->adam_on) {
         hipError_t ea = launch_pose_adam(buf<ViewDev>(c, "views"), (int)c->views_h.size(), g->dpose,
@@ -1618,12 +1633,27 @@ ddgs_status ddgs_step_launch(ddgs_ctx *c)
         c->fit_reset = false;
         c->fit_live = true;
     }
+    // (a target set by ddgs_step_set_target since the last upload)
+    DDGS_TRY(prepare_views(c));
     HIP_TRY(c, hipGraphLaunch(c->exec, c->stream));
     c->M = -1;  // unknown until ddgs_check
     c->rendered = true;
     c->r_model_gen = c->model_gen;
     c->r_views_gen = c->views_gen;
     c->r_opt_gen = c->opt_gen;
+    return DDGS_OK;
+}
+
+ddgs_status ddgs_step_set_target(ddgs_ctx *c, const float *target)
+{
+    if (!c) return DDGS_ERR_INVALID_ARG;
+    if (!target) return fail(c, DDGS_ERR_INVALID_ARG, "null target");
+    if (((uintptr_t)target) % 4 != 0) return fail(c, DDGS_ERR_INVALID_ARG, "arrays must be 4-byte aligned");
+    if (!c->exec) return fail(c, DDGS_ERR_STATE, "no captured step");
+    if (target != c->step_target) {
+        c->step_target = target;
+        c->views_dirty = true;  // uploaded with the view table, at the latest by the next launch
+    }
     return DDGS_OK;
 }
 

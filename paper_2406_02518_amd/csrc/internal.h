@@ -530,6 +530,9 @@ struct LossArgs {
     int V;
     int64_t total_pix;
     const float *img, *target;
+    // (captured steps) the target is read from this device slot, so that a
+    // replay can take another target image without a copy; NULL: target
+    const float *const *target_ref;
     float lambda;
     float *loss_out;   // [V] (may be NULL)
     float *grad;       // image layout (may be NULL)

@@ -35,6 +35,9 @@ __device__ __forceinline__ int tile_view(const int32_t *base, int V, int t)
     return lo;
 }
 
+// the target image: through the captured step's device slot when set
+__device__ __forceinline__ const float *loss_target(const LossArgs &a) { return a.target_ref ? *a.target_ref : a.target; }
+
 // (NW waves; red holds NW x NQ doubles)
 template <int NQ, int NW>
 __device__ __forceinline__ void block_sum_d(double (&x)[NQ], double *red)
@@ -74,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void ssim_fwd_kernel(LossArgs a, Window win
     const int lt = t - a.loss_tile_base[v];
     const int ty = lt / ntx, tx = lt - ty * ntx;
     const int ox = tx * kTW - kR, oy = ty * kTH - kR;
-    const float *x = a.img + V.pix_base, *y = a.target + V.pix_base;
+    const float *x = a.img + V.pix_base, *y = loss_target(a) + V.pix_base;
     for (int q = threadIdx.x; q < kHaloH * kHaloW; q += kBlock) {
         const int r = q / kHaloW, c = q % kHaloW;
         const int gx = ox + c, gy = oy + r;
@@ -190,7 +193,7 @@ __global__ __launch_bounds__(kBlock) void ssim_bwd_kernel(LossArgs a, Window win
         f2 += win.w[d] * hs[2][ly + d][lx];
     }
     const size_t p = (size_t)V.pix_base + (size_t)gy * V.W + gx;
-    const float xv = a.img[p], yv = a.target[p];
+    const float xv = a.img[p], yv = loss_target(a)[p];
     const float P = (float)V.W * (float)V.H;
     const float d = xv - yv;
     const float sg = (d > 0.0f) ? 1.0f : ((d < 0.0f) ? -1.0f : 0.0f);
@@ -209,9 +212,10 @@ __global__ __launch_bounds__(256) void ncc_stats_kernel(LossArgs a, int nchunks)
     const ViewDev &V = a.views[v];
     const int64_t P = (int64_t)V.W * V.H;
     const int64_t p0 = (int64_t)blockIdx.x * kChunk;
+    const float *tg = loss_target(a);
     double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int64_t p = p0 + threadIdx.x; p < min(P, p0 + kChunk); p += 256) {
-        const double x = a.img[V.pix_base + p], y = a.target[V.pix_base + p];
+        const double x = a.img[V.pix_base + p], y = tg[V.pix_base + p];
         s[0] += x; s[1] += y; s[2] += x * x; s[3] += y * y; s[4] += x * y;
     }
     __shared__ double red[4 * 5];
@@ -255,7 +259,7 @@ __global__ __launch_bounds__(256) void ncc_grad_kernel(LossArgs a, const double 
     const float mx = (float)stats[4 * v], my = (float)stats[4 * v + 1], sx = (float)stats[4 * v + 2];
     const float ncc = (float)stats[4 * v + 3], sy = (float)stats[4 * (size_t)a.V + v];
     const float xh = (a.img[V.pix_base + p] - mx) / sx;
-    const float yh = (a.target[V.pix_base + p] - my) / sy;
+    const float yh = (loss_target(a)[V.pix_base + p] - my) / sy;
     a.grad[V.pix_base + p] = -(yh - ncc * xh) / ((float)P * sx);
 }
 
@@ -267,9 +271,10 @@ __global__ __launch_bounds__(256) void linear_kernel(LossArgs a, int nchunks)
     const ViewDev &V = a.views[v];
     const int64_t P = (int64_t)V.W * V.H;
     const int64_t p0 = (int64_t)blockIdx.x * kChunk;
+    const float *tg = loss_target(a);
     double s[1] = {0.0};
     for (int64_t p = p0 + threadIdx.x; p < min(P, p0 + kChunk); p += 256) {
-        const float w = a.target[V.pix_base + p];
+        const float w = tg[V.pix_base + p];
         s[0] += (double)w * a.img[V.pix_base + p];
         if (a.grad) a.grad[V.pix_base + p] = w;
     }

@@ -57,6 +57,7 @@ def fit(R, params, n_iso, L, views, targets, iters, extent, lam=0.2, schedule=No
     tgt = torch.empty(P, device=R.device)
     img = torch.empty(P, device=R.device)
     dl = torch.empty(P, device=R.device)
+    tgts = [t.contiguous() for t in targets]
     loss = torch.empty(1, device=R.device)
     losses = torch.zeros(max(1, log_every), device=R.device)
 
@@ -79,7 +80,8 @@ def fit(R, params, n_iso, L, views, targets, iters, extent, lam=0.2, schedule=No
 
     def launch(it, j):
         with torch.cuda.stream(R.stream):
-            tgt.copy_(targets[j], non_blocking=True)
+            # (the step reads this view's target in place: no copy)
+            binding.ddgs_step_set_target(R.ctx, tgts[j].data_ptr())
             R.set_views([views[j]])
             binding.ddgs_step_launch(R.ctx)
             losses[(it - 1) % len(losses)].copy_(loss[0], non_blocking=True)

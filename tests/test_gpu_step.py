@@ -115,6 +115,34 @@ def test_pose_update_without_recapture(R):
         R2.close()
 
 
+@pytest.mark.parametrize("kind,lam", [(binding.LOSS_L1_DSSIM, 0.2), (binding.LOSS_NCC, 0.0), (binding.LOSS_LINEAR, 0.0)])
+def test_step_target_switches_without_copy(R, kind, lam):
+    """Replays that take their loss target from ddgs_step_set_target (the
+    captured buffer untouched) equal the plain path with that target, bit for
+    bit, for each loss; the pointer travels with a pose change too."""
+    c = synth.config("C4", scale=0.05)
+    R.set_scene(c.scene)
+    R.set_views(c.views[:2])
+    P = R.image_size()
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    targets = [torch.rand(P, device="cuda", generator=gen) for _ in range(3)]
+    bufs = _capture(R, kind, targets[0], lam, binding.GRAD_NAMES)
+    for j, (views, t) in enumerate([(c.views[:2], targets[1]), (c.views[2:4], targets[2]), (c.views[2:4], targets[0])]):
+        binding.ddgs_step_set_target(R.ctx, t.data_ptr())
+        if j == 1:
+            R.set_views(views)
+        step = _launch(R, bufs)
+        R2 = binding.Renderer(0, stream=R.stream)
+        try:
+            R2.set_scene(c.scene)
+            R2.set_views(views)
+            _same(step, _plain(R2, kind, t, lam, binding.GRAD_NAMES))
+        finally:
+            R2.close()
+    with pytest.raises(binding.DDGSError):
+        binding.ddgs_step_set_target(R.ctx, 0)
+
+
 def test_capacity_overflow_is_reported_not_faulted(R):
     c = synth.config("C4", scale=0.05)
     R.set_scene(c.scene)
