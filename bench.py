@@ -113,6 +113,12 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 4}), flush=True)
 
 
+def ordinal(k):
+    """1st, 2nd, 3rd, 4th, ..., 11th, 12th, 13th, ..., 21st, 32nd."""
+    suffix = "th" if 10 <= k % 100 <= 20 else {1: "st", 2: "nd", 3: "rd"}.get(k % 10, "th")
+    return f"{k}{suffix}"
+
+
 def traffic_from_profiles(kernel, workload):
     """HBM bytes per launch from a committed rocprofv3 counter summary, valid
     only while the kernel sources are unchanged."""
@@ -634,7 +640,7 @@ def main():
         dt = time.perf_counter() - a
         scale = v.H / len(rows)
         cpu = {"value": round(dt * scale * 1e3, 1), "unit": "ms", "cores": threads, "kind": "oracle", "host": host_cpu(),
-               "sample": f"view 0 of the fitting workload, every {args.cpu_row_stride}th detector row "
+               "sample": f"view 0 of the fitting workload, every {ordinal(args.cpu_row_stride)} detector row "
                          f"({len(rows)} of {v.H} rows = {len(pix)} pixels x 500k Gaussians), forward at those "
                          f"pixels + analytic FP64 backward of a linear loss on them; {dt:.1f} s measured, "
                          f"scaled by {scale:g} to one full 512x512 fwd+bwd"}
@@ -669,7 +675,7 @@ def main():
                 ref.backward(cs.scene, cs.views, pix_x, np.ones(len(pix_x)), threads=threads)
                 dt_x = time.perf_counter() - a
                 cpu[f"{label}_fwd_bwd_ms_extrapolated"] = round(dt_x * full / len(pix_x) * 1e3, 1)
-                cpu[f"{label}_sample"] = (f"every {args.cpu_extra_stride}th detector row of all {len(cs.views)} views "
+                cpu[f"{label}_sample"] = (f"every {ordinal(args.cpu_extra_stride)} detector row of all {len(cs.views)} views "
                                           f"({len(pix_x)} of {full} pixels x {cs.scene.n} Gaussians), "
                                           f"{dt_x:.1f} s measured, scaled by {full / len(pix_x):.2f}")
         for name in ("C1", "C2"):
